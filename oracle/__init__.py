@@ -1,0 +1,169 @@
+"""CPU oracle for D2Q9 BGK + NSBC (Euser & Vuik, arXiv 2005.08674).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` are the only users.  The product path
+(the HIP library and its Python binding) never imports anything from here, and
+this package imports nothing from the product package.
+
+``lbm_oracle.c`` holds the lattice arithmetic (plain C, fp64, or x87 extended
+precision when built with ``-DORC_LONG_DOUBLE``); this module builds it with
+gcc and wraps it with ctypes.  ``mlp.py`` is the numpy fp64 oracle of the
+boundary-closure network and ``reflection.py`` the fp64 reflection-energy norm.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+BUILD_DIR = os.path.join(HERE, "_build")
+SRC = os.path.join(HERE, "lbm_oracle.c")
+LIBS = {"double": os.path.join(BUILD_DIR, "liblbm_oracle.so"),
+        "longdouble": os.path.join(BUILD_DIR, "liblbm_oracle_ld.so")}
+
+BC_PERIODIC = 0
+BC_NSBC = 1
+
+
+def build(verbose: bool = False) -> None:
+    """Compile both precisions of the oracle with gcc (always recompiles)."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    base = ["gcc", "-O2", "-std=c11", "-fno-fast-math", "-ffp-contract=off",
+            "-fopenmp", "-shared", "-fPIC", SRC, "-lm"]
+    for kind, out in LIBS.items():
+        cmd = list(base) + ["-o", out + ".tmp"]
+        if kind == "longdouble":
+            cmd.insert(1, "-DORC_LONG_DOUBLE")
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        os.replace(out + ".tmp", out)
+
+
+class OrcParams(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("tau", ctypes.c_double), ("rho0", ctypes.c_double),
+                ("bc", ctypes.c_int * 4),
+                ("gamma", ctypes.c_double), ("beta", ctypes.c_double),
+                ("m0_rho", ctypes.c_double), ("m0_ux", ctypes.c_double), ("m0_uy", ctypes.c_double),
+                ("corr_mode", ctypes.c_int), ("grad_order", ctypes.c_int),
+                ("corner_mode", ctypes.c_int)]
+
+
+_handles: dict = {}
+
+
+def _lib(kind: str = "double"):
+    if kind in _handles:
+        return _handles[kind]
+    path = LIBS[kind]
+    if not os.path.exists(path):
+        build()
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    for name, args in [("orc_feq", [ctypes.c_double] * 4 + [P]),
+                       ("orc_collide_node", [ctypes.c_double, ctypes.c_double, P, P]),
+                       ("orc_moments_node", [ctypes.c_double, P, P]),
+                       ("orc_lattice_c", [P, P, P, P]),
+                       ("orc_init", [P, P, P, P, P]),
+                       ("orc_moments", [P, P, P, P, P]),
+                       ("orc_step", [P, P, ctypes.c_int]),
+                       ("orc_num_threads", []),
+                       ("orc_real_bytes", [])]:
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    _handles[kind] = lib
+    return lib
+
+
+def _dtype(kind: str):
+    return np.float64 if kind == "double" else np.longdouble
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def lattice_constants(kind: str = "double"):
+    """(cx, cy, w, opp) as the oracle defines them."""
+    lib = _lib(kind)
+    cx = np.zeros(9, np.int32)
+    cy = np.zeros(9, np.int32)
+    w = np.zeros(9, _dtype(kind))
+    opp = np.zeros(9, np.int32)
+    lib.orc_lattice_c(_ptr(cx), _ptr(cy), _ptr(w), _ptr(opp))
+    return cx, cy, w, opp
+
+
+def feq(rho0, drho, ux, uy, kind: str = "double") -> np.ndarray:
+    out = np.zeros(9, _dtype(kind))
+    _lib(kind).orc_feq(float(rho0), float(drho), float(ux), float(uy), _ptr(out))
+    return out
+
+
+def collide_node(tau, rho0, g9, kind: str = "double") -> np.ndarray:
+    g9 = np.ascontiguousarray(g9, dtype=_dtype(kind))
+    out = np.zeros(9, _dtype(kind))
+    _lib(kind).orc_collide_node(float(tau), float(rho0), _ptr(g9), _ptr(out))
+    return out
+
+
+def moments_node(rho0, g9, kind: str = "double") -> np.ndarray:
+    g9 = np.ascontiguousarray(g9, dtype=_dtype(kind))
+    out = np.zeros(3, _dtype(kind))
+    _lib(kind).orc_moments_node(float(rho0), _ptr(g9), _ptr(out))
+    return out
+
+
+class Lattice:
+    """One D2Q9 lattice advanced by the oracle.
+
+    ``bc`` is (left, right, bottom, top), each BC_PERIODIC or BC_NSBC.
+    Fields are [ny][nx] arrays; ``drho`` is rho - rho0.
+    """
+
+    def __init__(self, nx, ny, tau, drho, ux, uy, rho0=1.0, bc=(1, 1, 1, 1),
+                 gamma=0.6, beta=0.0, m0=(1.0, 0.0, 0.0), corr_mode=0,
+                 grad_order=1, corner_mode=0, kind: str = "double"):
+        self.kind = kind
+        self.lib = _lib(kind)
+        p = OrcParams()
+        p.nx, p.ny, p.tau, p.rho0 = int(nx), int(ny), float(tau), float(rho0)
+        for e in range(4):
+            p.bc[e] = int(bc[e])
+        p.gamma, p.beta = float(gamma), float(beta)
+        p.m0_rho, p.m0_ux, p.m0_uy = (float(v) for v in m0)
+        p.corr_mode, p.grad_order, p.corner_mode = int(corr_mode), int(grad_order), int(corner_mode)
+        self.p = p
+        self.nx, self.ny, self.rho0 = int(nx), int(ny), float(rho0)
+        self.t = 0
+        self.g = np.zeros((9, ny, nx), _dtype(kind))
+        f = [np.ascontiguousarray(a, dtype=np.float64).reshape(ny, nx) for a in (drho, ux, uy)]
+        rc = self.lib.orc_init(ctypes.byref(p), _ptr(f[0]), _ptr(f[1]), _ptr(f[2]), _ptr(self.g))
+        if rc != 0:
+            raise ValueError("oracle rejected the lattice parameters")
+
+    def set_farfield(self, beta, rho, ux, uy):
+        self.p.beta = float(beta)
+        self.p.m0_rho, self.p.m0_ux, self.p.m0_uy = float(rho), float(ux), float(uy)
+
+    def step(self, n: int = 1):
+        rc = self.lib.orc_step(ctypes.byref(self.p), _ptr(self.g), int(n))
+        if rc != 0:
+            raise RuntimeError(f"orc_step failed ({rc})")
+        self.t += int(n)
+        return self
+
+    def moments(self):
+        """(rho - rho0, ux, uy), each [ny][nx] float64."""
+        out = [np.zeros((self.ny, self.nx), np.float64) for _ in range(3)]
+        self.lib.orc_moments(ctypes.byref(self.p), _ptr(self.g), _ptr(out[0]), _ptr(out[1]), _ptr(out[2]))
+        return tuple(out)
+
+
+def num_threads() -> int:
+    return int(_lib("double").orc_num_threads())
