@@ -1,0 +1,161 @@
+#!/usr/bin/env python3
+"""Throughput of the D2Q9 BGK + NSBC sweep on one MI355X.
+
+One step = one lbm_step(1): the bulk collide-stream kernel over the interior
+plus the NSBC edge/corner kernel over the perimeter.  Workload: 4096 x 4096
+lattice, tau 0.51, 8 seeded Gaussian pulses (amplitude U[1e-4, 1e-3],
+half-width U[4, 16]), NSBC on all four edges, populations stored as FP32
+deviations f_i - w_i rho0 (the headline), plus FP16/BF16-deviation and FP64
+variants.  Inputs are resident in HBM before timing starts.
+
+Prints ONE JSON line (rank 0): metric/value (MLUPS), ms_per_step, the bulk
+kernel's roofline fraction from HIP-event durations measured in the timed
+region, and the CPU fp64 oracle timed on a bounded sample of the same
+workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS D2Q9+NSBC (FP32 vs FP16 store, MLP closure); % HBM peak; reflection"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_store(torch, W, store, steps, warmup, tune_reps=5, size=4096):
+    from paper_2005_08674_amd import lbm
+    from paper_2005_08674_amd.lattice import Lattice
+
+    w = W.pulses_4096(n=size)
+    lat = Lattice(w.nx, w.ny, w.tau, w.fields, store=store)
+    best, times = lat.autotune(reps=tune_reps)
+    tile_name = lbm.lbm_tile_describe(best)
+    log(f"[{store}] autotune -> {tile_name} ({min(times):.4f} ms); "
+        + ", ".join(f"{lbm.lbm_tile_describe(i)}={t:.4f}" for i, t in enumerate(times)))
+    lat.step(warmup)
+    stream = lat.stream
+    torch.cuda.synchronize()
+    lbm.lbm_enable_timing(lat.ctx, True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    e0.record(stream)
+    lat.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms = e0.elapsed_time(e1)
+    bulk_ms, bulk_n, edge_ms, edge_n = lbm.lbm_kernel_times(lat.ctx)
+    lbm.lbm_enable_timing(lat.ctx, False)
+    bpn, nodes_launch = lbm.lbm_bulk_traffic(lat.ctx)
+    ok = lat.check_finite()
+    nodes = w.nx * w.ny
+    out = {
+        "store": store,
+        "tile": tile_name,
+        "ms_per_step": ms / steps,
+        "wall_s": t_wall,
+        "mlups": nodes * steps / (ms * 1e-3) / 1e6,
+        "bulk_avg_ms": bulk_ms / max(bulk_n, 1),
+        "edge_avg_ms": edge_ms / max(edge_n, 1),
+        "bytes_per_node": bpn,
+        "bulk_nodes": nodes_launch,
+        "finite": bool(ok),
+        "workload": w,
+    }
+    achieved = bpn * nodes_launch / (out["bulk_avg_ms"] * 1e-3) / 1e9
+    out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+    lat.close()
+    return out
+
+
+def cpu_baseline(W, w, budget_s=12.0):
+    import oracle
+    o = oracle.Lattice(w.nx, w.ny, w.tau, *w.fields)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        o.step(1)
+        steps += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": round(w.nx * w.ny * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{w.nx}x{w.ny} pulse workload, {steps} fp64 oracle steps ({dt:.1f} s, init excluded)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--size", type=int, default=4096)
+    ap.add_argument("--variants", default="f16,bf16,f64", help="extra storage variants ('' for none)")
+    ap.add_argument("--variant-steps", type=int, default=500)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2005_08674_amd import lbm, workloads as W
+    lbm.load()
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+
+    main_run = run_store(torch, W, "f32", args.steps, args.warmup, size=args.size)
+    variants = {}
+    for st in [s for s in args.variants.split(",") if s]:
+        r = run_store(torch, W, st, args.variant_steps, min(args.warmup, 20), size=args.size)
+        variants[st] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 5),
+                        "bulk_avg_ms": round(r["bulk_avg_ms"], 5), "tile": r["tile"],
+                        "roofline_frac": r["roofline"]["frac"], "achieved_GBs": r["roofline"]["achieved"],
+                        "steps": args.variant_steps, "finite": r["finite"]}
+    w = main_run["workload"]
+    line = {
+        "metric": METRIC,
+        "value": round(main_run["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_run["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.nx}x{w.ny} D2Q9 BGK tau {w.tau}, 8 seeded Gaussian pulses, "
+                               "NSBC (gamma 0.6, beta 0) on 4 edges, FP32 deviation storage, FP32 compute",
+                   "nx": w.nx, "ny": w.ny, "store": "f32", "tile": main_run["tile"],
+                   "bulk_avg_ms": round(main_run["bulk_avg_ms"], 5),
+                   "edge_avg_ms": round(main_run["edge_avg_ms"], 5),
+                   "bytes_per_node": main_run["bytes_per_node"]},
+        "roofline": main_run["roofline"],
+        "variants": variants,
+        "finite": main_run["finite"],
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(W, w)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

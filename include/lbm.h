@@ -1,0 +1,198 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) D2Q9 lattice-Boltzmann library with
+ * the Non-equilibrium Symmetry Boundary Condition (NSBC) of Euser & Vuik,
+ * "A non-reflective boundary condition for LBM based on the assumption of
+ * non-equilibrium symmetry" (arXiv 2005.08674).
+ *
+ * The problem the calls solve (paper Secs. 3 and 5): a D2Q9 lattice (Fig. 1)
+ * evolves by the lattice Boltzmann equation (eq. lbe_0) with the BGK
+ * collision (eqs. lbe_1, feq_1) and relaxation time tau; on the edges marked
+ * NSBC the incoming populations are rebuilt from a predicted macroscopic vector
+ * (eqs. nes_0..nes_4) with relaxation parameter gamma, far-field factor beta
+ * and reference vector m0; the observable is (rho, u) (eqs. cf_0, cf_1).
+ *
+ * Conventions shared by every call
+ *  - Lattice directions are numbered as in Fig. 1: c_0 = (0,0), c_1 = (1,0),
+ *    c_2 = (-1,0), c_3 = (0,1), c_4 = (0,-1), c_5 = (1,1), c_6 = (-1,-1),
+ *    c_7 = (-1,1), c_8 = (1,-1).  Node (x, y): x in [0, nx), y in [0, ny), y up.
+ *  - Fields exchanged with the caller are row-major [ny][nx] arrays in DEVICE
+ *    memory (x fastest).  Densities are exchanged as the deviation rho - rho0.
+ *  - Stored populations are deviations g_i = f_i - f^eq_i(rho0, u_b) from the
+ *    discrete equilibrium of a base state (rho0, u_b); u_b = 0 (the default)
+ *    gives g_i = f_i - w_i rho0.  A base velocity equal to the mean flow keeps
+ *    the stored values, and their rounding errors, proportional to the
+ *    disturbance instead of to the mean flow.
+ *  - All device memory is owned by the caller; the library never allocates
+ *    device memory.  Contexts are host objects owned by the library.
+ *  - Every call returns LBM_OK (0) or a negative LBM_ERR_* code and never
+ *    aborts.  Argument errors are reported before anything is enqueued.
+ *    lbm_last_error() returns a message for the calling thread's last error.
+ *  - Work is enqueued asynchronously on the HIP stream given to lbm_init; a
+ *    call that returns data to the host says so and synchronizes that stream.
+ *  - One context may be used from one thread at a time.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LBM_OK = 0,
+    LBM_ERR_ARG = -1,         /* invalid argument or parameter combination */
+    LBM_ERR_HIP = -2,         /* a HIP runtime call or kernel launch failed */
+    LBM_ERR_STATE = -3,       /* call not valid in the context's current state */
+    LBM_ERR_NONFINITE = -4,   /* the populations hold a NaN or infinity */
+    LBM_ERR_UNSUPPORTED = -5  /* valid request the library does not implement */
+};
+
+/* Edge index in lbm_params.bc: 0 = left (x = 0), 1 = right (x = nx-1),
+ * 2 = bottom (y = 0), 3 = top (y = ny-1). */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_NSBC = 1 };
+
+/* Storage of the populations.  Arithmetic is fp64 for LBM_STORE_F64 and fp32
+ * for the three others.  The 16-bit codecs store s_i = g_i / w_i * 2^k with
+ * round-to-nearest-even: k = lbm_params.f16_exp for FP16 (a per-lattice power
+ * of two that keeps s_i in FP16's normal range), k = 0 for BF16. */
+enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16DEV = 2, LBM_STORE_BF16DEV = 3 };
+
+/* lbm_params.f16_exp value asking lbm_init to choose k from the initial
+ * fields so that max |g_i / w_i| * 2^k is close to 2^12. */
+#define LBM_F16_EXP_AUTO (-1000)
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef struct {
+    int32_t nx, ny;       /* lattice size, each >= 3 */
+    double tau;           /* BGK relaxation time, eq. lbe_1 with dt = 1; must be > 0.5 */
+    double rho0;          /* base density of the deviation form, > 0 */
+    int32_t bc[4];        /* LBM_BC_* per edge; periodic edges come in pairs (left+right, bottom+top) */
+    double gamma;         /* NSBC relaxation parameter, eq. nes_2 (the paper uses 0.6) */
+    int32_t store;        /* LBM_STORE_* */
+    int32_t corr_mode;    /* eq. nes_4: 0 = shift w_i (drho + c_i.dj / c_s^2) (exact moments),
+                             1 = literal w_i (drho + c_i.dj) */
+    int32_t grad_order;   /* eq. nes_2 normal derivative: 1 = two-point, 2 = three-point one-sided */
+    int32_t corner_mode;  /* corner nodes of two NSBC edges: 0 = diagonal normal (gamma/sqrt 2),
+                             1 = gamma/2 */
+    int32_t f16_exp;      /* k of the FP16 codec, or LBM_F16_EXP_AUTO; ignored by other stores */
+    int32_t reserved0;    /* set to 0 */
+    double ubase[2];      /* base velocity u_b of the deviation form, |u_b| <= 0.5 (default 0) */
+} lbm_params;
+
+/* Fill *p with defaults: 3x3 lattice, tau 0.6, rho0 1, NSBC on all edges,
+ * gamma 0.6, FP32 storage, corr_mode 0, grad_order 1, corner_mode 0,
+ * f16_exp auto, u_b = 0.  Always succeeds for a non-null p. */
+int lbm_params_default(lbm_params* p);
+
+/* Device workspace, in bytes, that lbm_init needs for these parameters: two
+ * population buffers (9 planes each) and a scratch area for reductions. */
+int lbm_workspace_bytes(const lbm_params* p, size_t* bytes);
+
+/* Create a context on `workspace` (device memory of at least
+ * lbm_workspace_bytes bytes, 256-byte aligned, borrowed until lbm_destroy)
+ * and set every node to the discrete equilibrium of the initial fields
+ * (f = f^eq(rho, u), eq. feq_1).  drho, ux, uy are device float64 [ny][nx]
+ * arrays (rho - rho0 and the velocity).  `hip_stream` is the hipStream_t all
+ * later work of this context is enqueued on (NULL = the null stream).
+ * Synchronizes the stream (it reads a reduction back when f16_exp is auto).
+ * The far-field factor starts at beta = 0 with m0 = (rho0, 0, 0).
+ * The 16-bit stores hold s_i = g_i / w_i * 2^k (see LBM_STORE_*). */
+int lbm_init(lbm_ctx** out, const lbm_params* p, void* workspace, size_t bytes,
+             const double* drho, const double* ux, const double* uy, void* hip_stream);
+
+/* Far-field criterion, eq. nes_3: m_c = (1 - beta) m_p + beta m0 with
+ * m0 = (rho_ref, ux_ref, uy_ref) (absolute density).  beta in [0, 1].
+ * Takes effect from the next step. */
+int lbm_set_farfield(lbm_ctx* ctx, double beta, double rho_ref, double ux_ref, double uy_ref);
+
+/* Advance n >= 0 time steps (stream, NSBC, collide; eqs. lbe_0, nes_0..nes_4,
+ * lbe_1).  Asynchronous; the context's time advances by n. */
+int lbm_step(lbm_ctx* ctx, int32_t n);
+
+/* Moments of every node at the current time (eqs. cf_0, cf_1): writes
+ * rho - rho0 (deviation = 1) or rho (deviation = 0) to drho_out and the
+ * velocity to ux_out, uy_out, each a device [ny][nx] array of float64
+ * (out_f64 = 1) or float32 (out_f64 = 0).  Any output pointer may be NULL
+ * to skip it.  Asynchronous. */
+int lbm_moments(lbm_ctx* ctx, void* drho_out, void* ux_out, void* uy_out, int out_f64, int deviation);
+
+/* Current time step count. */
+int lbm_time(const lbm_ctx* ctx, int64_t* t);
+
+/* Message of the calling thread's last failed call ("" if none).  The
+ * pointer stays valid until the next library call on the same thread. */
+const char* lbm_last_error(void);
+
+/* Release the context.  The workspace is the caller's and is not freed.
+ * Waits for the context's stream. */
+void lbm_destroy(lbm_ctx* ctx);
+
+/* ---------------------------------------------------------------- extras */
+
+/* Decoded populations as f_i - w_i rho0 (whatever the base velocity) in a
+ * device float64 [9][ny][nx] array.  Asynchronous. */
+int lbm_get_populations(lbm_ctx* ctx, double* g_out);
+
+/* Overwrite the state with the device float64 [9][ny][nx] values
+ * g_i = f_i - w_i rho0 (converted to the base state and encoded to the
+ * context's storage).  The state is the post-collision
+ * population set, the quantity lbm_get_populations returns.  Asynchronous. */
+int lbm_set_populations(lbm_ctx* ctx, const double* g);
+
+/* *ok = 1 if every stored population is finite, else 0 (and the call returns
+ * LBM_ERR_NONFINITE).  Synchronizes the stream. */
+int lbm_check_finite(lbm_ctx* ctx, int* ok);
+
+/* FP16 codec exponent k in use (0 for the other stores). */
+int lbm_f16_exp(const lbm_ctx* ctx, int32_t* k);
+
+/* Acoustic energy of a perturbation, in fp64 with a fixed-order reduction:
+ *   E = sum over the nodes of `test` of 1/2 [c_s^2 d_rho^2 / rho0 + rho0 |d_u|^2]
+ * where (d_rho, d_u) is the difference between `test` at node (x, y) and
+ *  - `ref` at node (x + x_off, y + y_off) when ref is not NULL (a larger
+ *    reference lattice containing test's window; both must share rho0 and
+ *    the window must fit inside ref), or
+ *  - the uniform state (rho0, ux_ref, uy_ref) when ref is NULL.
+ * The result is written to *out_dev, one float64 in device memory.
+ * Asynchronous on test's stream; when ref is given its stream must be the same
+ * stream or the caller orders the two. */
+int lbm_energy(lbm_ctx* test, const lbm_ctx* ref, int32_t x_off, int32_t y_off,
+               double ux_ref, double uy_ref, double* out_dev);
+
+/* Bulk-kernel tile shapes.  lbm_tile_count gives the number of candidate
+ * shapes; lbm_tile_describe writes a short text name of candidate `id` into
+ * buf; lbm_set_tile selects one for this context (the default is chosen from
+ * the lattice and storage).  lbm_autotune times every candidate on the
+ * context's own lattice (`reps` timed launches each, median of those, after
+ * one warm-up; the state is saved and restored around the timing) and selects
+ * the fastest; it writes the chosen id to *best and, if times_ms is not NULL,
+ * the per-candidate median launch time in milliseconds (length
+ * lbm_tile_count).  Synchronizes the stream. */
+int lbm_tile_count(void);
+int lbm_tile_describe(int32_t id, char* buf, size_t len);
+int lbm_set_tile(lbm_ctx* ctx, int32_t id);
+int lbm_get_tile(const lbm_ctx* ctx, int32_t* id);
+int lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* best, float* times_ms);
+
+/* Per-kernel timing with HIP events on the context's stream.  While enabled,
+ * every lbm_step launch of the bulk kernel and of the edge kernel is
+ * bracketed by events; lbm_kernel_times synchronizes the stream and returns
+ * the summed elapsed milliseconds and launch counts since the last reset. */
+int lbm_enable_timing(lbm_ctx* ctx, int on);
+int lbm_kernel_times(lbm_ctx* ctx, double* bulk_ms, int64_t* bulk_launches,
+                     double* edge_ms, int64_t* edge_launches);
+
+/* Bytes the bulk kernel must move per interior node and step
+ * (2 x 9 x bytes per stored population) and the interior node count
+ * (nx-2)(ny-2) it updates per launch. */
+int lbm_bulk_traffic(const lbm_ctx* ctx, int64_t* bytes_per_node, int64_t* nodes_per_launch);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,477 @@
+// lbm_api.hip -- the C ABI declared in include/lbm.h: context lifetime,
+// workspace layout, parameter checking, step loop, timing and autotuning.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_device.h"
+#include "lbm_launch.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail(LBM_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kScratchBytes = 1 << 20;
+constexpr size_t kOffEnergy = 0;            // energy partials (double)
+constexpr size_t kOffAbsmax = 64 << 10;     // absmax partials (float)
+constexpr size_t kOffFlag = 128 << 10;      // finiteness flag (int)
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t elem_bytes(int store) {
+  switch (store) {
+    case LBM_STORE_F64: return 8;
+    case LBM_STORE_F32: return 4;
+    default: return 2;
+  }
+}
+
+struct Layout {
+  size_t esize;
+  int32_t pitch;
+  int64_t plane;     // elements
+  size_t buf_bytes;  // one population buffer (9 planes)
+  size_t total;
+};
+
+Layout layout(const lbm_params* p) {
+  Layout l;
+  l.esize = elem_bytes(p->store);
+  const size_t row = round_up((size_t)p->nx * l.esize, 256);
+  l.pitch = (int32_t)(row / l.esize);
+  const size_t plane_bytes = round_up(row * (size_t)p->ny, 4096);
+  l.plane = (int64_t)(plane_bytes / l.esize);
+  l.buf_bytes = round_up(9 * plane_bytes, (size_t)2 << 20);
+  l.total = 2 * l.buf_bytes + kScratchBytes;
+  return l;
+}
+
+int check_params(const lbm_params* p) {
+  if (!p) return fail(LBM_ERR_ARG, "params is NULL");
+  if (p->nx < 3 || p->ny < 3) return fail(LBM_ERR_ARG, "lattice %dx%d: each side must be >= 3", p->nx, p->ny);
+  if ((int64_t)p->nx * p->ny > (int64_t)1 << 28)
+    return fail(LBM_ERR_ARG, "lattice %dx%d exceeds 2^28 nodes", p->nx, p->ny);
+  if (!(p->tau > 0.5) || !std::isfinite(p->tau))
+    return fail(LBM_ERR_ARG, "tau = %g: BGK needs tau > 0.5", p->tau);
+  if (!(p->rho0 > 0) || !std::isfinite(p->rho0)) return fail(LBM_ERR_ARG, "rho0 = %g must be > 0", p->rho0);
+  for (int e = 0; e < 4; ++e)
+    if (p->bc[e] != LBM_BC_PERIODIC && p->bc[e] != LBM_BC_NSBC)
+      return fail(LBM_ERR_ARG, "bc[%d] = %d is not LBM_BC_PERIODIC or LBM_BC_NSBC", e, p->bc[e]);
+  if ((p->bc[0] == LBM_BC_PERIODIC) != (p->bc[1] == LBM_BC_PERIODIC) ||
+      (p->bc[2] == LBM_BC_PERIODIC) != (p->bc[3] == LBM_BC_PERIODIC))
+    return fail(LBM_ERR_ARG, "periodic edges must come in pairs (left+right, bottom+top)");
+  if (!std::isfinite(p->gamma)) return fail(LBM_ERR_ARG, "gamma must be finite");
+  if (!std::isfinite(p->ubase[0]) || !std::isfinite(p->ubase[1]) ||
+      p->ubase[0] * p->ubase[0] + p->ubase[1] * p->ubase[1] > 0.25)
+    return fail(LBM_ERR_ARG, "base velocity (%g, %g) must be finite with |u_b| <= 0.5", p->ubase[0], p->ubase[1]);
+  if (p->store < LBM_STORE_F64 || p->store > LBM_STORE_BF16DEV) return fail(LBM_ERR_ARG, "store = %d", p->store);
+  if (p->corr_mode != 0 && p->corr_mode != 1) return fail(LBM_ERR_ARG, "corr_mode = %d", p->corr_mode);
+  if (p->grad_order != 1 && p->grad_order != 2) return fail(LBM_ERR_ARG, "grad_order = %d", p->grad_order);
+  if (p->corner_mode != 0 && p->corner_mode != 1) return fail(LBM_ERR_ARG, "corner_mode = %d", p->corner_mode);
+  if (p->store == LBM_STORE_F16DEV && p->f16_exp != LBM_F16_EXP_AUTO && (p->f16_exp < -30 || p->f16_exp > 60))
+    return fail(LBM_ERR_ARG, "f16_exp = %d outside [-30, 60]", p->f16_exp);
+  return LBM_OK;
+}
+
+void set_scales(lbm::LatDesc& L, int store, int k) {
+  for (int i = 0; i < 9; ++i) {
+    if (store == LBM_STORE_F64 || store == LBM_STORE_F32) {
+      L.ds[i] = 1.0f;
+      L.es[i] = 1.0f;
+    } else {
+      const double w = lbm::wgt<double>(i);
+      L.ds[i] = (float)std::ldexp(w, -k);
+      L.es[i] = (float)std::ldexp(1.0 / w, k);  // 2.25, 9, 36 times 2^k: exact
+    }
+  }
+}
+
+int default_tile(const lbm_params*) { return 5; }
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_params p;
+  lbm::LatDesc L;
+  Layout lay;
+  int parity = 0;
+  hipStream_t stream = nullptr;
+  int64_t t = 0;
+  char* ws = nullptr;
+  char* scratch = nullptr;
+  int tile = 0;
+  int f16_exp = 0;
+  // per-kernel timing
+  bool timing = false;
+  std::vector<hipEvent_t> events;
+  size_t ev_used = 0;
+  double bulk_ms = 0, edge_ms = 0;
+  int64_t bulk_n = 0, edge_n = 0;
+};
+
+namespace {
+
+int flush_timing(lbm_ctx* c) {
+  if (c->ev_used == 0) return LBM_OK;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (size_t k = 0; k + 2 < c->ev_used; k += 3) {
+    float a = 0, b = 0;
+    HIPCHK(hipEventElapsedTime(&a, c->events[k], c->events[k + 1]));
+    HIPCHK(hipEventElapsedTime(&b, c->events[k + 1], c->events[k + 2]));
+    c->bulk_ms += a;
+    c->edge_ms += b;
+    c->bulk_n += 1;
+    c->edge_n += 1;
+  }
+  c->ev_used = 0;
+  return LBM_OK;
+}
+
+int next_event(lbm_ctx* c, hipEvent_t* ev) {
+  if (c->ev_used == c->events.size()) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    c->events.push_back(e);
+  }
+  *ev = c->events[c->ev_used++];
+  return LBM_OK;
+}
+
+int step_once(lbm_ctx* c) {
+  if (c->timing) {
+    if (c->ev_used + 3 > 3 * 4096) {
+      int rc = flush_timing(c);
+      if (rc) return rc;
+    }
+    hipEvent_t e0, e1, e2;
+    int rc;
+    if ((rc = next_event(c, &e0)) || (rc = next_event(c, &e1)) || (rc = next_event(c, &e2))) return rc;
+    HIPCHK(hipEventRecord(e0, c->stream));
+    HIPCHK(lbm::launch_bulk(c->L, c->parity, c->tile, c->stream));
+    HIPCHK(hipEventRecord(e1, c->stream));
+    HIPCHK(lbm::launch_edge(c->L, c->parity, c->stream));
+    HIPCHK(hipEventRecord(e2, c->stream));
+  } else {
+    HIPCHK(lbm::launch_bulk(c->L, c->parity, c->tile, c->stream));
+    HIPCHK(lbm::launch_edge(c->L, c->parity, c->stream));
+  }
+  c->parity ^= 1;
+  c->t += 1;
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_params_default(lbm_params* p) {
+  if (!p) return fail(LBM_ERR_ARG, "params is NULL");
+  std::memset(p, 0, sizeof(*p));
+  p->nx = 3;
+  p->ny = 3;
+  p->tau = 0.6;
+  p->rho0 = 1.0;
+  for (int e = 0; e < 4; ++e) p->bc[e] = LBM_BC_NSBC;
+  p->gamma = 0.6;
+  p->store = LBM_STORE_F32;
+  p->corr_mode = 0;
+  p->grad_order = 1;
+  p->corner_mode = 0;
+  p->f16_exp = LBM_F16_EXP_AUTO;
+  return LBM_OK;
+}
+
+int lbm_workspace_bytes(const lbm_params* p, size_t* bytes) {
+  int rc = check_params(p);
+  if (rc) return rc;
+  if (!bytes) return fail(LBM_ERR_ARG, "bytes is NULL");
+  *bytes = layout(p).total;
+  return LBM_OK;
+}
+
+int lbm_init(lbm_ctx** out, const lbm_params* p, void* workspace, size_t bytes, const double* drho,
+             const double* ux, const double* uy, void* hip_stream) {
+  if (!out) return fail(LBM_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = check_params(p);
+  if (rc) return rc;
+  if (!workspace || ((uintptr_t)workspace & 255)) return fail(LBM_ERR_ARG, "workspace NULL or not 256-byte aligned");
+  if (!drho || !ux || !uy) return fail(LBM_ERR_ARG, "initial fields must not be NULL");
+  Layout lay = layout(p);
+  if (bytes < lay.total) return fail(LBM_ERR_ARG, "workspace of %zu bytes < %zu required", bytes, lay.total);
+
+  lbm_ctx* c = new lbm_ctx();
+  c->p = *p;
+  c->lay = lay;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->ws = static_cast<char*>(workspace);
+  c->scratch = c->ws + 2 * lay.buf_bytes;
+  lbm::LatDesc& L = c->L;
+  std::memset(&L, 0, sizeof(L));
+  L.buf[0] = c->ws;
+  L.buf[1] = c->ws + lay.buf_bytes;
+  L.nx = p->nx;
+  L.ny = p->ny;
+  L.pitch = lay.pitch;
+  L.store = p->store;
+  L.plane = lay.plane;
+  for (int e = 0; e < 4; ++e) L.bc[e] = p->bc[e];
+  L.corr_mode = p->corr_mode;
+  L.grad_order = p->grad_order;
+  L.corner_mode = p->corner_mode;
+  L.omega = 1.0 / p->tau;
+  L.rho0 = p->rho0;
+  L.gamma = p->gamma;
+  L.beta = 0.0;
+  L.ub[0] = p->ubase[0];
+  L.ub[1] = p->ubase[1];
+  for (int i = 0; i < 9; ++i) {
+    const double cu = lbm::kCx[i] * p->ubase[0] + lbm::kCy[i] * p->ubase[1];
+    L.pb[i] = 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * (p->ubase[0] * p->ubase[0] + p->ubase[1] * p->ubase[1]);
+  }
+  L.m0[0] = 0.0;
+  L.m0[1] = -p->ubase[0];
+  L.m0[2] = -p->ubase[1];
+  c->tile = default_tile(p);
+
+  int k = 0;
+  if (p->store == LBM_STORE_F16DEV) {
+    if (p->f16_exp == LBM_F16_EXP_AUTO) {
+      float* part = reinterpret_cast<float*>(c->scratch + kOffAbsmax);
+      std::vector<float> host(lbm::absmax_blocks());
+      hipError_t e = lbm::launch_absmax_init(L, drho, ux, uy, part, c->stream);
+      if (e == hipSuccess) e = hipMemcpyAsync(host.data(), part, host.size() * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+      if (e != hipSuccess) {
+        delete c;
+        return fail(LBM_ERR_HIP, "f16 exponent reduction: %s", hipGetErrorString(e));
+      }
+      float mx = 0.f;
+      for (float v : host) mx = std::max(mx, v);
+      if (!std::isfinite(mx)) {
+        delete c;
+        return fail(LBM_ERR_ARG, "initial fields are not finite");
+      }
+      k = mx > 1e-30f ? (int)std::floor(std::log2(4096.0 / (double)mx)) : 12;
+      k = std::min(60, std::max(-30, k));
+    } else {
+      k = p->f16_exp;
+    }
+  }
+  c->f16_exp = k;
+  set_scales(L, p->store, k);
+
+  hipError_t e = lbm::launch_init(L, 0, drho, ux, uy, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(LBM_ERR_HIP, "init kernel: %s", hipGetErrorString(e));
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+int lbm_set_farfield(lbm_ctx* c, double beta, double rho_ref, double ux_ref, double uy_ref) {
+  if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
+  if (!(beta >= 0.0 && beta <= 1.0)) return fail(LBM_ERR_ARG, "beta = %g outside [0, 1]", beta);
+  if (!std::isfinite(rho_ref) || !std::isfinite(ux_ref) || !std::isfinite(uy_ref))
+    return fail(LBM_ERR_ARG, "reference vector must be finite");
+  c->L.beta = beta;
+  c->L.m0[0] = rho_ref - c->p.rho0;
+  c->L.m0[1] = ux_ref - c->L.ub[0];
+  c->L.m0[2] = uy_ref - c->L.ub[1];
+  return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* c, int32_t n) {
+  if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
+  if (n < 0) return fail(LBM_ERR_ARG, "n = %d < 0", n);
+  for (int32_t s = 0; s < n; ++s) {
+    int rc = step_once(c);
+    if (rc) return rc;
+  }
+  return LBM_OK;
+}
+
+int lbm_moments(lbm_ctx* c, void* r, void* u, void* v, int out_f64, int deviation) {
+  if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
+  HIPCHK(lbm::launch_moments(c->L, c->parity, r, u, v, out_f64 ? 1 : 0, deviation ? 1 : 0, c->stream));
+  return LBM_OK;
+}
+
+int lbm_time(const lbm_ctx* c, int64_t* t) {
+  if (!c || !t) return fail(LBM_ERR_ARG, "NULL argument");
+  *t = c->t;
+  return LBM_OK;
+}
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+void lbm_destroy(lbm_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+  delete c;
+}
+
+int lbm_get_populations(lbm_ctx* c, double* g_out) {
+  if (!c || !g_out) return fail(LBM_ERR_ARG, "NULL argument");
+  HIPCHK(lbm::launch_get_pops(c->L, c->parity, g_out, c->stream));
+  return LBM_OK;
+}
+
+int lbm_set_populations(lbm_ctx* c, const double* g) {
+  if (!c || !g) return fail(LBM_ERR_ARG, "NULL argument");
+  HIPCHK(lbm::launch_set_pops(c->L, c->parity, g, c->stream));
+  return LBM_OK;
+}
+
+int lbm_check_finite(lbm_ctx* c, int* ok) {
+  if (!c || !ok) return fail(LBM_ERR_ARG, "NULL argument");
+  int* flag = reinterpret_cast<int*>(c->scratch + kOffFlag);
+  int host = 0;
+  HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), c->stream));
+  HIPCHK(lbm::launch_finite(c->L, c->parity, flag, c->stream));
+  HIPCHK(hipMemcpyAsync(&host, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  *ok = host ? 0 : 1;
+  return host ? fail(LBM_ERR_NONFINITE, "populations hold a non-finite value at t = %lld", (long long)c->t) : LBM_OK;
+}
+
+int lbm_f16_exp(const lbm_ctx* c, int32_t* k) {
+  if (!c || !k) return fail(LBM_ERR_ARG, "NULL argument");
+  *k = c->p.store == LBM_STORE_F16DEV ? c->f16_exp : 0;
+  return LBM_OK;
+}
+
+int lbm_energy(lbm_ctx* test, const lbm_ctx* ref, int32_t x_off, int32_t y_off, double ux_ref, double uy_ref,
+               double* out_dev) {
+  if (!test || !out_dev) return fail(LBM_ERR_ARG, "NULL argument");
+  if (ref) {
+    if (ref->p.rho0 != test->p.rho0) return fail(LBM_ERR_ARG, "test and reference rho0 differ");
+    if (x_off < 0 || y_off < 0 || x_off + test->p.nx > ref->p.nx || y_off + test->p.ny > ref->p.ny)
+      return fail(LBM_ERR_ARG, "window %dx%d at (%d, %d) does not fit in the %dx%d reference", test->p.nx,
+                  test->p.ny, x_off, y_off, ref->p.nx, ref->p.ny);
+  }
+  double* part = reinterpret_cast<double*>(test->scratch + kOffEnergy);
+  HIPCHK(lbm::launch_energy(test->L, test->parity, ref ? &ref->L : nullptr, ref ? ref->parity : 0, x_off, y_off,
+                            ux_ref, uy_ref, part, out_dev, test->stream));
+  return LBM_OK;
+}
+
+int lbm_tile_count(void) { return lbm::num_tiles(); }
+
+int lbm_tile_describe(int32_t id, char* buf, size_t len) {
+  if (!buf || len == 0) return fail(LBM_ERR_ARG, "NULL buffer");
+  if (id < 0 || id >= lbm::num_tiles()) return fail(LBM_ERR_ARG, "tile id %d out of range", id);
+  lbm::tile_name(id, buf, len);
+  return LBM_OK;
+}
+
+int lbm_set_tile(lbm_ctx* c, int32_t id) {
+  if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
+  if (id < 0 || id >= lbm::num_tiles()) return fail(LBM_ERR_ARG, "tile id %d out of range", id);
+  c->tile = id;
+  return LBM_OK;
+}
+
+int lbm_get_tile(const lbm_ctx* c, int32_t* id) {
+  if (!c || !id) return fail(LBM_ERR_ARG, "NULL argument");
+  *id = c->tile;
+  return LBM_OK;
+}
+
+int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* best, float* times_ms) {
+  if (!c || !best) return fail(LBM_ERR_ARG, "NULL argument");
+  if (reps < 1 || reps > 1000) return fail(LBM_ERR_ARG, "reps = %d outside [1, 1000]", reps);
+  // The bulk kernel reads buffer `parity` and writes only the other one, so
+  // relaunching it leaves the state untouched.
+  const int nt = lbm::num_tiles();
+  std::vector<hipEvent_t> ev(2 * reps);
+  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+  float best_t = 1e30f;
+  int best_id = c->tile;
+  int rc = LBM_OK;
+  for (int id = 0; id < nt && rc == LBM_OK; ++id) {
+    hipError_t e = lbm::launch_bulk(c->L, c->parity, id, c->stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+      e = hipEventRecord(ev[2 * r], c->stream);
+      if (e == hipSuccess) e = lbm::launch_bulk(c->L, c->parity, id, c->stream);
+      if (e == hipSuccess) e = hipEventRecord(ev[2 * r + 1], c->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    std::vector<float> ts(reps);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = hipEventElapsedTime(&ts[r], ev[2 * r], ev[2 * r + 1]);
+    if (e != hipSuccess) {
+      rc = fail(LBM_ERR_HIP, "autotune candidate %d: %s", id, hipGetErrorString(e));
+      break;
+    }
+    std::sort(ts.begin(), ts.end());
+    const float med = ts[reps / 2];
+    if (times_ms) times_ms[id] = med;
+    if (med < best_t) {
+      best_t = med;
+      best_id = id;
+    }
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (rc) return rc;
+  c->tile = best_id;
+  *best = best_id;
+  return LBM_OK;
+}
+
+int lbm_enable_timing(lbm_ctx* c, int on) {
+  if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
+  int rc = flush_timing(c);
+  if (rc) return rc;
+  c->timing = on != 0;
+  c->bulk_ms = c->edge_ms = 0;
+  c->bulk_n = c->edge_n = 0;
+  return LBM_OK;
+}
+
+int lbm_kernel_times(lbm_ctx* c, double* bulk_ms, int64_t* bulk_launches, double* edge_ms, int64_t* edge_launches) {
+  if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
+  int rc = flush_timing(c);
+  if (rc) return rc;
+  if (bulk_ms) *bulk_ms = c->bulk_ms;
+  if (bulk_launches) *bulk_launches = c->bulk_n;
+  if (edge_ms) *edge_ms = c->edge_ms;
+  if (edge_launches) *edge_launches = c->edge_n;
+  c->bulk_ms = c->edge_ms = 0;
+  c->bulk_n = c->edge_n = 0;
+  return LBM_OK;
+}
+
+int lbm_bulk_traffic(const lbm_ctx* c, int64_t* bytes_per_node, int64_t* nodes_per_launch) {
+  if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
+  if (bytes_per_node) *bytes_per_node = 18 * (int64_t)c->lay.esize;
+  if (nodes_per_launch) *nodes_per_launch = (int64_t)(c->p.nx - 2) * (c->p.ny - 2);
+  return LBM_OK;
+}
+
+}  // extern "C"

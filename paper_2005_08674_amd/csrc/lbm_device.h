@@ -1,0 +1,207 @@
+// lbm_device.h -- device-side building blocks of the D2Q9 BGK + NSBC sweep
+// for gfx950: lattice constants, storage codecs, the per-node BGK update, the
+// NSBC boundary-node update, and the lattice descriptor every kernel takes.
+//
+// Method: Euser & Vuik (arXiv 2005.08674), Sec. 3 (eqs. lbe_0, lbe_1, feq_1,
+// moments eqs. cf_0/cf_1) and Sec. 5 (eqs. nes_0..nes_4).
+//
+// State convention: a population buffer holds the POST-collision deviations
+// g*_i = f*_i - f^eq_i(rho0, u_b) of time t, the distance from the discrete
+// equilibrium of a base state (rho0, u_b); with u_b = 0 this is
+// f_i - w_i rho0.  All node arithmetic runs on (drho, du) = (rho - rho0,
+// u - u_b), which keeps every operand proportional to the deviation from the
+// base state and so keeps rounding errors proportional to it too.  One step pulls g*_i(x - c_i) into node x
+// (streaming, eq. lbe_0), rebuilds the populations that no neighbour supplies
+// on NSBC edges (eqs. nes_0..nes_4), collides (eq. lbe_1) and writes the
+// post-collision set of time t+1 to the other buffer.  Collision conserves
+// mass and momentum, so the moments of the stored set are the moments of the
+// pre-collision state at the same time.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// ------------------------------------------------------------------ lattice
+// Directions as numbered in the paper's Fig. 1 (y up).
+constexpr int kCx[9] = {0, 1, -1, 0, 0, 1, -1, -1, 1};
+constexpr int kCy[9] = {0, 0, 0, 1, -1, 1, -1, 1, -1};
+constexpr int kOpp[9] = {0, 2, 1, 4, 3, 6, 5, 8, 7};
+
+template <class R>
+__host__ __device__ constexpr R wgt(int i) {
+  return i == 0 ? R(4) / R(9) : (i <= 4 ? R(1) / R(9) : R(1) / R(36));
+}
+
+enum Store : int { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3 };
+enum Edge : int { E_LEFT = 0, E_RIGHT = 1, E_BOTTOM = 2, E_TOP = 3 };
+enum Bc : int { BC_PERIODIC = 0, BC_NSBC = 1 };
+
+// ------------------------------------------------------------------ codecs
+// Stored type T, arithmetic type R.  The 16-bit codecs keep s = g / w_i * 2^k;
+// dec multiplies by ds_i = w_i 2^-k, enc by es_i = 2^k / w_i, then rounds to
+// nearest even.
+template <int S> struct Codec;
+
+template <> struct Codec<ST_F64> {
+  using T = double;
+  using R = double;
+  __device__ static inline R dec(T v, float) { return v; }
+  __device__ static inline T enc(R v, float) { return v; }
+};
+
+template <> struct Codec<ST_F32> {
+  using T = float;
+  using R = float;
+  __device__ static inline R dec(T v, float) { return v; }
+  __device__ static inline T enc(R v, float) { return v; }
+};
+
+template <> struct Codec<ST_F16> {
+  using T = _Float16;
+  using R = float;
+  __device__ static inline R dec(T v, float s) { return static_cast<float>(v) * s; }
+  __device__ static inline T enc(R v, float s) { return static_cast<_Float16>(v * s); }
+};
+
+template <> struct Codec<ST_BF16> {
+  using T = uint16_t;
+  using R = float;
+  __device__ static inline R dec(T v, float s) {
+    return __uint_as_float(static_cast<uint32_t>(v) << 16) * s;
+  }
+  __device__ static inline T enc(R v, float s) {
+    // round to nearest, ties to even, on the top 16 bits of the fp32 pattern
+    uint32_t u = __float_as_uint(v * s);
+    if ((u & 0x7f800000u) == 0x7f800000u) return static_cast<T>((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return static_cast<T>(u >> 16);
+  }
+};
+
+// ------------------------------------------------------------------ lattice descriptor
+// Everything a kernel needs to update one lattice.  Buffers buf[0], buf[1]
+// hold 9 planes each: population i of node (x, y) is at
+// buf[b] + i * plane + y * pitch + x (elements of the stored type).
+struct LatDesc {
+  void* buf[2];
+  int32_t nx, ny, pitch, store;
+  int64_t plane;
+  int32_t bc[4];
+  int32_t corr_mode, grad_order, corner_mode, _pad1;
+  double omega;     // 1 / tau
+  double rho0;
+  double gamma;
+  double beta;
+  double m0[3];     // far-field vector (rho - rho0, ux - ubx, uy - uby)
+  double ub[2];     // base velocity u_b of the deviation form
+  double pb[9];     // P_i(u_b) = 1 + 3 c_i.u_b + 9/2 (c_i.u_b)^2 - 3/2 |u_b|^2
+  float ds[9];      // decode scale per population
+  float es[9];      // encode scale per population
+};
+
+// Base state of the deviation form in the arithmetic type.
+template <class R> struct Base {
+  R ubx, uby;
+  R pb[9];
+  __device__ inline explicit Base(const LatDesc& L) : ubx(R(L.ub[0])), uby(R(L.ub[1])) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) pb[i] = R(L.pb[i]);
+  }
+};
+
+// ------------------------------------------------------------------ per-node arithmetic
+// Moments of one node (eqs. cf_0/cf_1) from the deviations: with
+// sum_i f^eq_i(rho0, u_b) = rho0 and sum_i c_i f^eq_i(rho0, u_b) = rho0 u_b,
+//   drho = sum g_i,  rho u = rho0 u_b + sum c_i g_i,
+//   du = u - u_b = (sum c_i g_i - drho u_b) / (rho0 + drho).
+template <class R>
+__device__ inline void moments(const R g[9], R rho0, const Base<R>& b, R& drho, R& dux, R& duy) {
+  drho = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
+  const R jx = (g[1] - g[2]) + (g[5] - g[6]) + (g[8] - g[7]);
+  const R jy = (g[3] - g[4]) + (g[5] - g[6]) + (g[7] - g[8]);
+  const R ir = R(1) / (rho0 + drho);
+  dux = (jx - drho * b.ubx) * ir;
+  duy = (jy - drho * b.uby) * ir;
+}
+
+// Discrete equilibrium (eq. feq_1, c_s^2 = 1/3) minus the base equilibrium:
+//   f^eq_i(rho, u) - f^eq_i(rho0, u_b) = w_i [ drho P_i(u_b) + rho (P_i(u) - P_i(u_b)) ],
+//   P_i(u) - P_i(u_b) = a (3 + 9/2 (a + 2 b_i)) - 3/2 du.(du + 2 u_b),
+// with a = c_i.du and b_i = c_i.u_b.  For u_b = 0 this is
+//   w_i [ drho + rho (3 c.u + 9/2 (c.u)^2 - 3/2 u.u) ].
+template <class R>
+__device__ inline void equilibrium(R rho0, const Base<R>& b, R drho, R dux, R duy, R geq[9]) {
+  const R rho = rho0 + drho;
+  const R q = R(1.5) * (dux * (dux + R(2) * b.ubx) + duy * (duy + R(2) * b.uby));
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const R a = R(kCx[i]) * dux + R(kCy[i]) * duy;
+    const R bi2 = R(2) * (R(kCx[i]) * b.ubx + R(kCy[i]) * b.uby);
+    geq[i] = wgt<R>(i) * fma(drho, b.pb[i], rho * fma(a, fma(R(4.5), a + bi2, R(3)), -q));
+  }
+}
+
+// BGK collision in place (eq. lbe_1, dt = 1): g <- g + omega (g^eq - g).
+template <class R>
+__device__ inline void bgk(R g[9], R rho0, const Base<R>& b, R omega) {
+  R drho, dux, duy, geq[9];
+  moments(g, rho0, b, drho, dux, duy);
+  equilibrium(rho0, b, drho, dux, duy, geq);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) g[i] = fma(omega, geq[i] - g[i], g[i]);
+}
+
+template <int S>
+__device__ inline typename Codec<S>::R load_pop(const LatDesc& L, const typename Codec<S>::T* base, int i,
+                                                int64_t idx) {
+  return Codec<S>::dec(base[i * L.plane + idx], L.ds[i]);
+}
+
+// ------------------------------------------------------------------ NSBC
+// Moment triple (drho, ux - ubx, uy - uby).
+template <class R> struct M3 {
+  R v[3];
+};
+
+// Rebuild the unknown populations of one boundary node and correct it
+// (eqs. nes_0..nes_4).  `unknown` has bit i set for every population whose
+// pull source lies outside the domain; g holds the streamed (known) values.
+// mc is the corrected macroscopic vector (drho, du_x, du_y).
+template <class R>
+__device__ inline void nsbc_assign_correct(R g[9], uint32_t unknown, const M3<R>& mc, R rho0, const Base<R>& b,
+                                           int corr_mode) {
+  R geq[9];
+  equilibrium(rho0, b, mc.v[0], mc.v[1], mc.v[2], geq);
+  // eqs. nes_0/nes_1: f_in = f_in^eq + (f_out - f_out^eq); a population whose
+  // opposite is unknown too (corner "buried" pair) takes its equilibrium.
+  // The base equilibrium cancels, so the same formula holds for deviations.
+  R gn[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int o = kOpp[i];
+    if (unknown & (1u << i)) {
+      gn[i] = (unknown & (1u << o)) ? geq[i] : geq[i] + (g[o] - geq[o]);
+    } else {
+      gn[i] = g[i];
+    }
+  }
+  // eq. nes_4: rescale (mass) and shift (momentum) so the node carries m_c:
+  //   drho_err = sum f - rho_c = sum g - drho_c,
+  //   dj = sum c f - rho_c u_c = sum c g - rho_c du_c - drho_c u_b.
+  const R s = ((gn[0] + gn[1]) + (gn[2] + gn[3])) + ((gn[4] + gn[5]) + (gn[6] + gn[7])) + gn[8];
+  const R jx = (gn[1] - gn[2]) + (gn[5] - gn[6]) + (gn[8] - gn[7]);
+  const R jy = (gn[3] - gn[4]) + (gn[5] - gn[6]) + (gn[7] - gn[8]);
+  const R rhoc = rho0 + mc.v[0];
+  const R ddr = s - mc.v[0];
+  const R k = corr_mode == 0 ? R(3) : R(1);
+  const R djx = k * (jx - rhoc * mc.v[1] - mc.v[0] * b.ubx);
+  const R djy = k * (jy - rhoc * mc.v[2] - mc.v[0] * b.uby);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    g[i] = gn[i] - wgt<R>(i) * (ddr + (R(kCx[i]) * djx + R(kCy[i]) * djy));
+  }
+}
+
+}  // namespace lbm

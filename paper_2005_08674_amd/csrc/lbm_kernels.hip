@@ -1,0 +1,574 @@
+// lbm_kernels.hip -- gfx950 kernels of the D2Q9 BGK + NSBC sweep and its
+// helpers (initialisation, moments, population export/import, finiteness,
+// fp64 energy reduction) plus their host-side launchers.
+//
+// Bulk kernel: fused pull-streaming + BGK collision (eqs. lbe_0, lbe_1,
+// feq_1) over the interior nodes 1 <= x <= nx-2, 1 <= y <= ny-2.  Pure
+// streaming work: 9 loads and 9 stores per node, no data reuse except the
+// +-1 shifted cache lines of neighbouring wavefronts, so it is bound by HBM
+// bandwidth.  Threads map to consecutive x (coalesced, 64-wide wavefronts);
+// stores are aligned, the x-shifted loads straddle one extra line per
+// wavefront which the same CU / XCD L2 serves.  An optional block remap
+// gives every XCD a contiguous band of tiles so that those shared lines stay
+// in one L2.
+//
+// Edge kernel: the perimeter nodes.  One 64-lane block per segment of an
+// edge stages the moments of a 3-deep, (64 + 4)-wide strip of the previous
+// step in LDS, then each lane pulls its known populations (wrapping across
+// periodic edges), rebuilds the unknown ones with NSBC (Sec. 5) and collides.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "lbm_device.h"
+#include "lbm_launch.h"
+
+namespace lbm {
+
+// ------------------------------------------------------------------ bulk kernel
+template <int S, int BX, int BY, int NYT, bool REMAP>
+__global__ __launch_bounds__(BX* BY) void k_bulk(LatDesc L, int parity, int tiles_x, int ntiles) {
+  using C = Codec<S>;
+  using T = typename C::T;
+  using R = typename C::R;
+  int tile = blockIdx.x;
+  if (REMAP) {
+    const int per = (ntiles + 7) >> 3;
+    tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  }
+  if (tile >= ntiles) return;
+  const int tyi = tile / tiles_x;
+  const int txi = tile - tyi * tiles_x;
+  const int x = txi * BX + threadIdx.x;
+  if (x < 1 || x > L.nx - 2) return;
+  const int y0 = 1 + tyi * (BY * NYT) + threadIdx.y;
+  const int pitch = L.pitch;
+  const T* __restrict__ A = static_cast<const T*>(L.buf[parity]);
+  T* __restrict__ B = static_cast<T*>(L.buf[parity ^ 1]);
+  const int64_t plane = L.plane;
+  const R rho0 = R(L.rho0), omega = R(L.omega);
+  const Base<R> base(L);
+
+  R g[NYT][9];
+#pragma unroll
+  for (int j = 0; j < NYT; ++j) {
+    const int y = y0 + j * BY;
+    if (y <= L.ny - 2) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        const int idx = (y - kCy[i]) * pitch + (x - kCx[i]);
+        g[j][i] = C::dec(A[i * plane + idx], L.ds[i]);
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NYT; ++j) {
+    const int y = y0 + j * BY;
+    if (y <= L.ny - 2) {
+      bgk<R>(g[j], rho0, base, omega);
+      const int idx = y * pitch + x;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) B[i * plane + idx] = C::enc(g[j][i], L.es[i]);
+    }
+  }
+}
+
+struct TileShape {
+  int bx, by, nyt;
+  bool remap;
+};
+
+#define LBM_TILES(X)         \
+  X(64, 4, 1, false)         \
+  X(64, 4, 2, false)         \
+  X(64, 4, 4, false)         \
+  X(128, 2, 1, false)        \
+  X(128, 2, 2, false)        \
+  X(256, 1, 1, false)        \
+  X(256, 1, 2, false)        \
+  X(256, 1, 4, false)        \
+  X(64, 8, 1, false)         \
+  X(128, 4, 1, false)        \
+  X(64, 4, 1, true)          \
+  X(64, 4, 2, true)          \
+  X(64, 4, 4, true)          \
+  X(128, 2, 1, true)         \
+  X(128, 2, 2, true)         \
+  X(256, 1, 1, true)         \
+  X(256, 1, 2, true)         \
+  X(256, 1, 4, true)         \
+  X(64, 8, 1, true)          \
+  X(128, 4, 1, true)
+
+static const TileShape kTiles[] = {
+#define X(a, b, c, d) {a, b, c, d},
+    LBM_TILES(X)
+#undef X
+};
+static constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
+
+int num_tiles() { return kNumTiles; }
+
+void tile_name(int id, char* buf, size_t len) {
+  if (id < 0 || id >= kNumTiles) {
+    snprintf(buf, len, "invalid");
+    return;
+  }
+  const TileShape& t = kTiles[id];
+  snprintf(buf, len, "%dx%dx%d%s", t.bx, t.by, t.nyt, t.remap ? "+xcd" : "");
+}
+
+template <int S, int BX, int BY, int NYT, bool REMAP>
+static hipError_t launch_bulk_t(const LatDesc& L, int parity, hipStream_t s) {
+  const int tiles_x = (L.nx + BX - 1) / BX;
+  const int tiles_y = (L.ny - 2 + BY * NYT - 1) / (BY * NYT);
+  const int ntiles = tiles_x * tiles_y;
+  if (ntiles <= 0) return hipSuccess;
+  const int grid = REMAP ? ((ntiles + 7) >> 3) * 8 : ntiles;
+  k_bulk<S, BX, BY, NYT, REMAP><<<dim3(grid), dim3(BX, BY), 0, s>>>(L, parity, tiles_x, ntiles);
+  return hipGetLastError();
+}
+
+template <int S>
+static hipError_t launch_bulk_s(const LatDesc& L, int parity, int tile, hipStream_t s) {
+  int id = 0;
+#define X(a, b, c, d)                                          \
+  if (tile == id) return launch_bulk_t<S, a, b, c, d>(L, parity, s); \
+  ++id;
+  LBM_TILES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_bulk(const LatDesc& L, int parity, int tile, hipStream_t s) {
+  switch (L.store) {
+    case ST_F64: return launch_bulk_s<ST_F64>(L, parity, tile, s);
+    case ST_F32: return launch_bulk_s<ST_F32>(L, parity, tile, s);
+    case ST_F16: return launch_bulk_s<ST_F16>(L, parity, tile, s);
+    case ST_BF16: return launch_bulk_s<ST_BF16>(L, parity, tile, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------ edge kernel
+constexpr int SEG = 64;    // boundary nodes per block (one wavefront)
+constexpr int HALO = 2;    // tangential halo of the staged strip
+constexpr int DEPTH = 3;   // staged depths 0..2 along the inward normal
+constexpr int STRIP = SEG + 2 * HALO;
+
+__host__ __device__ inline int edge_segments_v(int ny) { return (ny + SEG - 1) / SEG; }
+__host__ __device__ inline int edge_segments_h(int nx) { return (nx - 2 + SEG - 1) / SEG; }
+
+// Node of edge `edge` at depth d (along the inward normal) and tangential
+// coordinate t (y for left/right, x for bottom/top).
+__device__ inline void edge_node(const LatDesc& L, int edge, int d, int t, int& x, int& y) {
+  switch (edge) {
+    case E_LEFT: x = d; y = t; break;
+    case E_RIGHT: x = L.nx - 1 - d; y = t; break;
+    case E_BOTTOM: x = t; y = d; break;
+    default: x = t; y = L.ny - 1 - d; break;
+  }
+}
+
+template <class R>
+__device__ inline R normal_diff(R mb, R m1, R m2, int order) {
+  return order == 1 ? mb - m1 : (R(3) * mb - R(4) * m1 + m2) * R(0.5);
+}
+
+template <int S>
+__global__ __launch_bounds__(SEG) void k_edge(LatDesc L, int parity) {
+  using C = Codec<S>;
+  using T = typename C::T;
+  using R = typename C::R;
+  __shared__ R mom[3][DEPTH][STRIP];
+
+  const int nx = L.nx, ny = L.ny;
+  const int nsv = edge_segments_v(ny), nsh = edge_segments_h(nx);
+  int b = blockIdx.x, edge;
+  if (b < nsv) {
+    edge = E_LEFT;
+  } else if (b < 2 * nsv) {
+    edge = E_RIGHT;
+    b -= nsv;
+  } else if (b < 2 * nsv + nsh) {
+    edge = E_BOTTOM;
+    b -= 2 * nsv;
+  } else {
+    edge = E_TOP;
+    b -= 2 * nsv + nsh;
+  }
+  const bool vertical = edge == E_LEFT || edge == E_RIGHT;
+  const int ntan = vertical ? ny : nx;
+  const int t0 = vertical ? b * SEG : 1 + b * SEG;
+  const int tend = vertical ? ny : nx - 1;
+  const bool xper = L.bc[E_LEFT] == BC_PERIODIC;
+  const bool yper = L.bc[E_BOTTOM] == BC_PERIODIC;
+  const bool tan_per = vertical ? yper : xper;
+  const bool any_nsbc = !(xper && yper);
+
+  const T* __restrict__ A = static_cast<const T*>(L.buf[parity]);
+  T* __restrict__ B = static_cast<T*>(L.buf[parity ^ 1]);
+  const int pitch = L.pitch;
+  const int64_t plane = L.plane;
+  const R rho0 = R(L.rho0);
+  const Base<R> base(L);
+
+  // Stage the time-t moments of the strip (depth 0..2, tangential halo 2).
+  if (any_nsbc) {
+    for (int k = threadIdx.x; k < DEPTH * STRIP; k += SEG) {
+      const int d = k / STRIP, tt = k - d * STRIP;
+      int t = t0 - HALO + tt;
+      bool inside = true;
+      if (t < 0 || t >= ntan) {
+        if (tan_per) t = t < 0 ? t + ntan : t - ntan;
+        else inside = false;
+      }
+      R m[3] = {R(0), R(0), R(0)};
+      if (inside) {
+        int x, y;
+        edge_node(L, edge, d, t, x, y);
+        R g[9];
+        const int idx = y * pitch + x;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) g[i] = C::dec(A[i * plane + idx], L.ds[i]);
+        moments<R>(g, rho0, base, m[0], m[1], m[2]);
+      }
+      mom[0][d][tt] = m[0];
+      mom[1][d][tt] = m[1];
+      mom[2][d][tt] = m[2];
+    }
+  }
+  __syncthreads();
+
+  const int t = t0 + threadIdx.x;
+  if (t >= tend) return;
+  int x, y;
+  edge_node(L, edge, 0, t, x, y);
+
+  // Pull the known populations; mark those whose source is outside the domain.
+  R g[9];
+  uint32_t unknown = 0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    int sx = x - kCx[i], sy = y - kCy[i];
+    const bool outx = sx < 0 || sx >= nx;
+    const bool outy = sy < 0 || sy >= ny;
+    if ((outx && !xper) || (outy && !yper)) {
+      unknown |= 1u << i;
+      g[i] = R(0);
+    } else {
+      if (outx) sx = sx < 0 ? sx + nx : sx - nx;
+      if (outy) sy = sy < 0 ? sy + ny : sy - ny;
+      g[i] = C::dec(A[i * plane + (sy * pitch + sx)], L.ds[i]);
+    }
+  }
+
+  const bool onL = x == 0 && L.bc[E_LEFT] == BC_NSBC;
+  const bool onR = x == nx - 1 && L.bc[E_RIGHT] == BC_NSBC;
+  const bool onB = y == 0 && L.bc[E_BOTTOM] == BC_NSBC;
+  const bool onT = y == ny - 1 && L.bc[E_TOP] == BC_NSBC;
+  if (onL || onR || onB || onT) {
+    const int tt = threadIdx.x + HALO;
+    const bool own = (edge == E_LEFT && onL) || (edge == E_RIGHT && onR) || (edge == E_BOTTOM && onB) ||
+                     (edge == E_TOP && onT);
+    int nn = 0;
+    R dsum[3] = {R(0), R(0), R(0)};
+    // eq. nes_2: outward normal derivative by a one-sided difference, time t
+    if (own) {
+      ++nn;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) dsum[c] += normal_diff(mom[c][0][tt], mom[c][1][tt], mom[c][2][tt], L.grad_order);
+    }
+    if (vertical && (onB || onT)) {  // corner node: second normal runs along this strip
+      const int s = onB ? 1 : -1;
+      ++nn;
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        dsum[c] += normal_diff(mom[c][0][tt], mom[c][0][tt + s], mom[c][0][tt + 2 * s], L.grad_order);
+    }
+    R fac = R(L.gamma);
+    if (nn == 2) fac *= L.corner_mode == 0 ? R(0.70710678118654752440) : R(0.5);
+    const R beta = R(L.beta);
+    M3<R> mc;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const R mp = mom[c][0][tt] - fac * dsum[c];
+      mc.v[c] = (R(1) - beta) * mp + beta * R(L.m0[c]);  // eq. nes_3
+    }
+    nsbc_assign_correct<R>(g, unknown, mc, rho0, base, L.corr_mode);
+  }
+  bgk<R>(g, rho0, base, R(L.omega));
+  const int idx = y * pitch + x;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) B[i * plane + idx] = C::enc(g[i], L.es[i]);
+}
+
+int edge_blocks(int nx, int ny) { return 2 * edge_segments_v(ny) + 2 * edge_segments_h(nx); }
+
+hipError_t launch_edge(const LatDesc& L, int parity, hipStream_t s) {
+  const dim3 grid(edge_blocks(L.nx, L.ny)), block(SEG);
+  switch (L.store) {
+    case ST_F64: k_edge<ST_F64><<<grid, block, 0, s>>>(L, parity); break;
+    case ST_F32: k_edge<ST_F32><<<grid, block, 0, s>>>(L, parity); break;
+    case ST_F16: k_edge<ST_F16><<<grid, block, 0, s>>>(L, parity); break;
+    case ST_BF16: k_edge<ST_BF16><<<grid, block, 0, s>>>(L, parity); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ helpers
+// Equilibrium deviations in fp64 for the initial state, encoded to the store.
+template <int S>
+__global__ void k_init(LatDesc L, int parity, const double* __restrict__ drho, const double* __restrict__ ux,
+                       const double* __restrict__ uy) {
+  using C = Codec<S>;
+  using T = typename C::T;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= L.nx) return;
+  const int64_t k = (int64_t)y * L.nx + x;
+  double geq[9];
+  const Base<double> base(L);
+  equilibrium<double>(L.rho0, base, drho[k], ux[k] - L.ub[0], uy[k] - L.ub[1], geq);
+  T* B = static_cast<T*>(L.buf[parity]);
+  const int idx = y * L.pitch + x;
+  // scale in fp64 (the encode scales are exact powers of two over w_i), then
+  // round once to the stored type
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+    B[i * L.plane + idx] = C::enc(typename C::R(geq[i] * (double)L.es[i]), 1.0f);
+}
+
+// Per-block maximum of |geq_i / w_i| over the initial fields (FP16 exponent choice).
+__global__ void k_absmax_init(LatDesc L, const double* __restrict__ drho, const double* __restrict__ ux,
+                              const double* __restrict__ uy, float* partial) {
+  __shared__ float red[256];
+  float mx = 0.f;
+  const int64_t n = (int64_t)L.nx * L.ny;
+  const Base<double> base(L);
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    double geq[9];
+    equilibrium<double>(L.rho0, base, drho[k], ux[k] - L.ub[0], uy[k] - L.ub[1], geq);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) mx = fmaxf(mx, (float)fabs(geq[i] / wgt<double>(i)));
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// Decoded populations of node (x, y) in fp64, for any store (runtime switch).
+__device__ inline void load_node_f64(const LatDesc& L, int parity, int x, int y, double g[9]) {
+  const int idx = y * L.pitch + x;
+  switch (L.store) {
+    case ST_F64: {
+      const double* A = static_cast<const double*>(L.buf[parity]);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) g[i] = A[i * L.plane + idx];
+      break;
+    }
+    case ST_F32: {
+      const float* A = static_cast<const float*>(L.buf[parity]);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) g[i] = A[i * L.plane + idx];
+      break;
+    }
+    case ST_F16: {
+      const _Float16* A = static_cast<const _Float16*>(L.buf[parity]);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) g[i] = (double)Codec<ST_F16>::dec(A[i * L.plane + idx], L.ds[i]);
+      break;
+    }
+    default: {
+      const uint16_t* A = static_cast<const uint16_t*>(L.buf[parity]);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) g[i] = (double)Codec<ST_BF16>::dec(A[i * L.plane + idx], L.ds[i]);
+      break;
+    }
+  }
+}
+
+// rho - rho0 and the absolute velocity of node (x, y), in fp64.
+__device__ inline void node_moments_f64(const LatDesc& L, int parity, int x, int y, double& dr, double& ux,
+                                        double& uy) {
+  double g[9];
+  load_node_f64(L, parity, x, y, g);
+  const Base<double> base(L);
+  moments<double>(g, L.rho0, base, dr, ux, uy);
+  ux += L.ub[0];
+  uy += L.ub[1];
+}
+
+__global__ void k_moments(LatDesc L, int parity, void* out_r, void* out_u, void* out_v, int f64, int deviation) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= L.nx) return;
+  double dr, ux, uy;
+  node_moments_f64(L, parity, x, y, dr, ux, uy);
+  const double r = deviation ? dr : L.rho0 + dr;
+  const int64_t k = (int64_t)y * L.nx + x;
+  if (f64) {
+    if (out_r) static_cast<double*>(out_r)[k] = r;
+    if (out_u) static_cast<double*>(out_u)[k] = ux;
+    if (out_v) static_cast<double*>(out_v)[k] = uy;
+  } else {
+    if (out_r) static_cast<float*>(out_r)[k] = (float)r;
+    if (out_u) static_cast<float*>(out_u)[k] = (float)ux;
+    if (out_v) static_cast<float*>(out_v)[k] = (float)uy;
+  }
+}
+
+__global__ void k_get_pops(LatDesc L, int parity, double* out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= L.nx) return;
+  double g[9];
+  load_node_f64(L, parity, x, y, g);
+  const int64_t n = (int64_t)L.nx * L.ny, k = (int64_t)y * L.nx + x;
+  // f_i - w_i rho0 = g_i + w_i rho0 (P_i(u_b) - 1)
+#pragma unroll
+  for (int i = 0; i < 9; ++i) out[i * n + k] = g[i] + wgt<double>(i) * L.rho0 * (L.pb[i] - 1.0);
+}
+
+template <int S>
+__global__ void k_set_pops(LatDesc L, int parity, const double* __restrict__ in) {
+  using C = Codec<S>;
+  using T = typename C::T;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= L.nx) return;
+  const int64_t n = (int64_t)L.nx * L.ny, k = (int64_t)y * L.nx + x;
+  T* B = static_cast<T*>(L.buf[parity]);
+  const int idx = y * L.pitch + x;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const double g = in[i * n + k] - wgt<double>(i) * L.rho0 * (L.pb[i] - 1.0);
+    B[i * L.plane + idx] = C::enc(typename C::R(g * (double)L.es[i]), 1.0f);
+  }
+}
+
+__global__ void k_finite(LatDesc L, int parity, int* bad) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= L.nx) return;
+  double g[9];
+  load_node_f64(L, parity, x, y, g);
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) ok = ok && isfinite(g[i]);
+  if (!ok) *bad = 1;
+}
+
+// Acoustic-energy reduction in fp64, fixed order: a fixed grid strides over
+// the test nodes, every block reduces in a fixed tree and writes one partial;
+// k_sum_partials adds the partials in a fixed tree.
+constexpr int EN_BLOCK = 256;
+constexpr int EN_GRID = 1024;
+
+__global__ __launch_bounds__(EN_BLOCK) void k_energy(LatDesc T_, int pt, LatDesc R_, int pr, int has_ref, int xo,
+                                                    int yo, double ux_ref, double uy_ref, double* partial) {
+  __shared__ double red[EN_BLOCK];
+  double acc = 0.0;
+  const int64_t n = (int64_t)T_.nx * T_.ny;
+  const double cs2 = 1.0 / 3.0, rho0 = T_.rho0;
+  for (int64_t k = (int64_t)blockIdx.x * EN_BLOCK + threadIdx.x; k < n; k += (int64_t)EN_GRID * EN_BLOCK) {
+    const int y = (int)(k / T_.nx), x = (int)(k - (int64_t)y * T_.nx);
+    double dr, ux, uy;
+    node_moments_f64(T_, pt, x, y, dr, ux, uy);
+    double rr = 0.0, ru = ux_ref, rv = uy_ref;
+    if (has_ref) node_moments_f64(R_, pr, x + xo, y + yo, rr, ru, rv);
+    const double a = dr - rr, b = ux - ru, c = uy - rv;
+    acc += 0.5 * (cs2 * a * a / rho0 + rho0 * (b * b + c * c));
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = EN_BLOCK / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(EN_BLOCK) void k_sum_partials(const double* partial, int n, double* out) {
+  __shared__ double red[EN_BLOCK];
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < n; k += EN_BLOCK) acc += partial[k];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = EN_BLOCK / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+// ------------------------------------------------------------------ launchers
+static inline dim3 node_grid(const LatDesc& L, int bs) { return dim3((L.nx + bs - 1) / bs, L.ny); }
+
+hipError_t launch_init(const LatDesc& L, int parity, const double* drho, const double* ux, const double* uy,
+                       hipStream_t s) {
+  const dim3 grid = node_grid(L, 256), block(256);
+  switch (L.store) {
+    case ST_F64: k_init<ST_F64><<<grid, block, 0, s>>>(L, parity, drho, ux, uy); break;
+    case ST_F32: k_init<ST_F32><<<grid, block, 0, s>>>(L, parity, drho, ux, uy); break;
+    case ST_F16: k_init<ST_F16><<<grid, block, 0, s>>>(L, parity, drho, ux, uy); break;
+    case ST_BF16: k_init<ST_BF16><<<grid, block, 0, s>>>(L, parity, drho, ux, uy); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+int absmax_blocks() { return 256; }
+
+hipError_t launch_absmax_init(const LatDesc& L, const double* drho, const double* ux, const double* uy,
+                              float* partial, hipStream_t s) {
+  k_absmax_init<<<dim3(absmax_blocks()), dim3(256), 0, s>>>(L, drho, ux, uy, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(const LatDesc& L, int parity, void* r, void* u, void* v, int f64, int deviation,
+                          hipStream_t s) {
+  k_moments<<<node_grid(L, 256), dim3(256), 0, s>>>(L, parity, r, u, v, f64, deviation);
+  return hipGetLastError();
+}
+
+hipError_t launch_get_pops(const LatDesc& L, int parity, double* out, hipStream_t s) {
+  k_get_pops<<<node_grid(L, 256), dim3(256), 0, s>>>(L, parity, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_pops(const LatDesc& L, int parity, const double* in, hipStream_t s) {
+  const dim3 grid = node_grid(L, 256), block(256);
+  switch (L.store) {
+    case ST_F64: k_set_pops<ST_F64><<<grid, block, 0, s>>>(L, parity, in); break;
+    case ST_F32: k_set_pops<ST_F32><<<grid, block, 0, s>>>(L, parity, in); break;
+    case ST_F16: k_set_pops<ST_F16><<<grid, block, 0, s>>>(L, parity, in); break;
+    case ST_BF16: k_set_pops<ST_BF16><<<grid, block, 0, s>>>(L, parity, in); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_finite(const LatDesc& L, int parity, int* bad, hipStream_t s) {
+  k_finite<<<node_grid(L, 256), dim3(256), 0, s>>>(L, parity, bad);
+  return hipGetLastError();
+}
+
+int energy_partials() { return EN_GRID; }
+
+hipError_t launch_energy(const LatDesc& T_, int pt, const LatDesc* R_, int pr, int xo, int yo, double ux_ref,
+                         double uy_ref, double* partial, double* out, hipStream_t s) {
+  k_energy<<<dim3(EN_GRID), dim3(EN_BLOCK), 0, s>>>(T_, pt, R_ ? *R_ : T_, pr, R_ != nullptr, xo, yo, ux_ref,
+                                                     uy_ref, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_sum_partials<<<dim3(1), dim3(EN_BLOCK), 0, s>>>(partial, EN_GRID, out);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

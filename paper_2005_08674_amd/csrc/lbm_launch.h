@@ -1,0 +1,31 @@
+// lbm_launch.h -- host-side launchers of the kernels in lbm_kernels.hip
+// (internal to the library; the public interface is include/lbm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+#include "lbm_device.h"
+
+namespace lbm {
+
+int num_tiles();
+void tile_name(int id, char* buf, size_t len);
+hipError_t launch_bulk(const LatDesc& L, int parity, int tile, hipStream_t s);
+int edge_blocks(int nx, int ny);
+hipError_t launch_edge(const LatDesc& L, int parity, hipStream_t s);
+hipError_t launch_init(const LatDesc& L, int parity, const double* drho, const double* ux, const double* uy,
+                       hipStream_t s);
+int absmax_blocks();
+hipError_t launch_absmax_init(const LatDesc& L, const double* drho, const double* ux, const double* uy,
+                              float* partial, hipStream_t s);
+hipError_t launch_moments(const LatDesc& L, int parity, void* r, void* u, void* v, int f64, int deviation,
+                          hipStream_t s);
+hipError_t launch_get_pops(const LatDesc& L, int parity, double* out, hipStream_t s);
+hipError_t launch_set_pops(const LatDesc& L, int parity, const double* in, hipStream_t s);
+hipError_t launch_finite(const LatDesc& L, int parity, int* bad, hipStream_t s);
+int energy_partials();
+hipError_t launch_energy(const LatDesc& T_, int pt, const LatDesc* R_, int pr, int xo, int yo, double ux_ref,
+                         double uy_ref, double* partial, double* out, hipStream_t s);
+
+}  // namespace lbm

@@ -1,0 +1,227 @@
+"""Python binding of the C ABI in include/lbm.h (argument marshalling only).
+
+Every function here has the name of the C entry point it calls and does no
+arithmetic of the method: all of it runs in the HIP library.  PyTorch provides
+device memory (tensors whose data pointers are handed over) and the stream.
+The library must have been built (``paper_2005_08674_amd.build.build()``);
+loading fails loudly if it is missing -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "_lib", "liblbm.so")
+
+LBM_OK = 0
+LBM_ERR_ARG = -1
+LBM_ERR_HIP = -2
+LBM_ERR_STATE = -3
+LBM_ERR_NONFINITE = -4
+LBM_ERR_UNSUPPORTED = -5
+
+LBM_BC_PERIODIC = 0
+LBM_BC_NSBC = 1
+
+LBM_STORE_F64 = 0
+LBM_STORE_F32 = 1
+LBM_STORE_F16DEV = 2
+LBM_STORE_BF16DEV = 3
+LBM_F16_EXP_AUTO = -1000
+
+STORE_NAMES = {"f64": LBM_STORE_F64, "f32": LBM_STORE_F32, "f16": LBM_STORE_F16DEV, "bf16": LBM_STORE_BF16DEV}
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where} failed ({code}): {msg}")
+        self.code = code
+
+
+class lbm_params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("tau", ctypes.c_double), ("rho0", ctypes.c_double),
+                ("bc", ctypes.c_int32 * 4),
+                ("gamma", ctypes.c_double),
+                ("store", ctypes.c_int32), ("corr_mode", ctypes.c_int32),
+                ("grad_order", ctypes.c_int32), ("corner_mode", ctypes.c_int32),
+                ("f16_exp", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("ubase", ctypes.c_double * 2)]
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_SIGS = {
+    "lbm_params_default": [_P],
+    "lbm_workspace_bytes": [_P, _P],
+    "lbm_init": [_P, _P, _P, ctypes.c_size_t, _P, _P, _P, _P],
+    "lbm_set_farfield": [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double],
+    "lbm_step": [_P, ctypes.c_int32],
+    "lbm_moments": [_P, _P, _P, _P, ctypes.c_int, ctypes.c_int],
+    "lbm_time": [_P, _P],
+    "lbm_get_populations": [_P, _P],
+    "lbm_set_populations": [_P, _P],
+    "lbm_check_finite": [_P, _P],
+    "lbm_f16_exp": [_P, _P],
+    "lbm_energy": [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double, _P],
+    "lbm_tile_count": [],
+    "lbm_tile_describe": [ctypes.c_int32, _P, ctypes.c_size_t],
+    "lbm_set_tile": [_P, ctypes.c_int32],
+    "lbm_get_tile": [_P, _P],
+    "lbm_autotune": [_P, ctypes.c_int32, _P, _P],
+    "lbm_enable_timing": [_P, ctypes.c_int],
+    "lbm_kernel_times": [_P, _P, _P, _P, _P],
+    "lbm_bulk_traffic": [_P, _P, _P],
+}
+
+
+def load():
+    """Load liblbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                           "(run paper_2005_08674_amd.build.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, args in _SIGS.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.lbm_last_error.argtypes = []
+    lib.lbm_last_error.restype = ctypes.c_char_p
+    lib.lbm_destroy.argtypes = [_P]
+    lib.lbm_destroy.restype = None
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return list(_SIGS) + ["lbm_last_error", "lbm_destroy"]
+
+
+def _check(rc: int, where: str):
+    if rc != LBM_OK:
+        raise LbmError(rc, where, lbm_last_error())
+    return rc
+
+
+def lbm_last_error() -> str:
+    return load().lbm_last_error().decode()
+
+
+def lbm_params_default() -> lbm_params:
+    p = lbm_params()
+    _check(load().lbm_params_default(ctypes.byref(p)), "lbm_params_default")
+    return p
+
+
+def lbm_workspace_bytes(p: lbm_params) -> int:
+    n = ctypes.c_size_t()
+    _check(load().lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(n)), "lbm_workspace_bytes")
+    return n.value
+
+
+def lbm_init(p: lbm_params, workspace_ptr: int, nbytes: int, drho_ptr: int, ux_ptr: int, uy_ptr: int,
+             stream_ptr: int):
+    ctx = ctypes.c_void_p()
+    _check(load().lbm_init(ctypes.byref(ctx), ctypes.byref(p), workspace_ptr, nbytes, drho_ptr, ux_ptr, uy_ptr,
+                           stream_ptr), "lbm_init")
+    return ctx
+
+
+def lbm_set_farfield(ctx, beta, rho_ref, ux_ref, uy_ref):
+    _check(load().lbm_set_farfield(ctx, beta, rho_ref, ux_ref, uy_ref), "lbm_set_farfield")
+
+
+def lbm_step(ctx, n: int):
+    _check(load().lbm_step(ctx, int(n)), "lbm_step")
+
+
+def lbm_moments(ctx, drho_ptr, ux_ptr, uy_ptr, out_f64: bool = True, deviation: bool = True):
+    _check(load().lbm_moments(ctx, drho_ptr, ux_ptr, uy_ptr, int(out_f64), int(deviation)), "lbm_moments")
+
+
+def lbm_time(ctx) -> int:
+    t = ctypes.c_int64()
+    _check(load().lbm_time(ctx, ctypes.byref(t)), "lbm_time")
+    return t.value
+
+
+def lbm_destroy(ctx):
+    load().lbm_destroy(ctx)
+
+
+def lbm_get_populations(ctx, g_ptr):
+    _check(load().lbm_get_populations(ctx, g_ptr), "lbm_get_populations")
+
+
+def lbm_set_populations(ctx, g_ptr):
+    _check(load().lbm_set_populations(ctx, g_ptr), "lbm_set_populations")
+
+
+def lbm_check_finite(ctx) -> bool:
+    ok = ctypes.c_int()
+    rc = load().lbm_check_finite(ctx, ctypes.byref(ok))
+    if rc not in (LBM_OK, LBM_ERR_NONFINITE):
+        _check(rc, "lbm_check_finite")
+    return bool(ok.value)
+
+
+def lbm_f16_exp(ctx) -> int:
+    k = ctypes.c_int32()
+    _check(load().lbm_f16_exp(ctx, ctypes.byref(k)), "lbm_f16_exp")
+    return k.value
+
+
+def lbm_energy(test_ctx, ref_ctx, x_off, y_off, ux_ref, uy_ref, out_ptr):
+    _check(load().lbm_energy(test_ctx, ref_ctx, int(x_off), int(y_off), float(ux_ref), float(uy_ref), out_ptr),
+           "lbm_energy")
+
+
+def lbm_tile_count() -> int:
+    return int(load().lbm_tile_count())
+
+
+def lbm_tile_describe(tile_id: int) -> str:
+    buf = ctypes.create_string_buffer(64)
+    _check(load().lbm_tile_describe(int(tile_id), buf, 64), "lbm_tile_describe")
+    return buf.value.decode()
+
+
+def lbm_set_tile(ctx, tile_id: int):
+    _check(load().lbm_set_tile(ctx, int(tile_id)), "lbm_set_tile")
+
+
+def lbm_get_tile(ctx) -> int:
+    t = ctypes.c_int32()
+    _check(load().lbm_get_tile(ctx, ctypes.byref(t)), "lbm_get_tile")
+    return t.value
+
+
+def lbm_autotune(ctx, reps: int = 5):
+    best = ctypes.c_int32()
+    n = lbm_tile_count()
+    times = (ctypes.c_float * n)()
+    _check(load().lbm_autotune(ctx, int(reps), ctypes.byref(best), times), "lbm_autotune")
+    return best.value, list(times)
+
+
+def lbm_enable_timing(ctx, on: bool):
+    _check(load().lbm_enable_timing(ctx, int(on)), "lbm_enable_timing")
+
+
+def lbm_kernel_times(ctx):
+    bm, em = ctypes.c_double(), ctypes.c_double()
+    bn, en = ctypes.c_int64(), ctypes.c_int64()
+    _check(load().lbm_kernel_times(ctx, ctypes.byref(bm), ctypes.byref(bn), ctypes.byref(em), ctypes.byref(en)),
+           "lbm_kernel_times")
+    return bm.value, bn.value, em.value, en.value
+
+
+def lbm_bulk_traffic(ctx):
+    b, n = ctypes.c_int64(), ctypes.c_int64()
+    _check(load().lbm_bulk_traffic(ctx, ctypes.byref(b), ctypes.byref(n)), "lbm_bulk_traffic")
+    return b.value, n.value

@@ -1,0 +1,99 @@
+"""Host-side checks of the C-ABI library (no GPU needed): the built
+liblbm.so loads, exports every entry point include/lbm.h declares, and its
+argument validation and workspace arithmetic behave as documented."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2005_08674_amd import lbm as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", f) for f in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if f.endswith(".h")]
+
+
+def _declared():
+    names = set()
+    for h in HEADERS:
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(lbm_\w+)\s*\(", src, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        from paper_2005_08674_amd import build
+        build.build()
+    return L.load()
+
+
+def test_header_declares_the_core_calls():
+    names = _declared()
+    for n in ["lbm_init", "lbm_step", "lbm_set_farfield", "lbm_moments"]:
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    cdll = ctypes.CDLL(L.LIB_PATH)
+    missing = [n for n in _declared() if not hasattr(cdll, n)]
+    assert not missing, missing
+    for n in _declared():
+        assert n in L.exported_symbols(), f"binding lacks {n}"
+
+
+def test_defaults_and_workspace(lib):
+    p = L.lbm_params_default()
+    assert (p.nx, p.ny, p.tau, p.rho0, p.gamma) == (3, 3, 0.6, 1.0, 0.6)
+    assert list(p.bc) == [1, 1, 1, 1] and p.store == L.LBM_STORE_F32
+    p.nx, p.ny = 4096, 4096
+    n32 = L.lbm_workspace_bytes(p)
+    assert n32 >= 2 * 9 * 4096 * 4096 * 4
+    p.store = L.LBM_STORE_F16DEV
+    n16 = L.lbm_workspace_bytes(p)
+    assert 2 * 9 * 4096 * 4096 * 2 <= n16 < n32
+    p.store = L.LBM_STORE_F64
+    assert L.lbm_workspace_bytes(p) >= 2 * 9 * 4096 * 4096 * 8
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("nx", 2, "each side"), ("tau", 0.5, "tau"), ("store", 7, "store"), ("grad_order", 3, "grad_order"),
+    ("corr_mode", 2, "corr_mode"), ("corner_mode", -1, "corner_mode"), ("rho0", 0.0, "rho0"),
+])
+def test_invalid_params_rejected(lib, field, value, msg):
+    p = L.lbm_params_default()
+    p.nx = p.ny = 16
+    setattr(p, field, value)
+    with pytest.raises(L.LbmError) as e:
+        L.lbm_workspace_bytes(p)
+    assert e.value.code == L.LBM_ERR_ARG and msg in str(e.value)
+
+
+def test_unpaired_periodic_edges_rejected(lib):
+    p = L.lbm_params_default()
+    p.nx = p.ny = 16
+    p.bc[0] = L.LBM_BC_PERIODIC
+    with pytest.raises(L.LbmError, match="pairs"):
+        L.lbm_workspace_bytes(p)
+
+
+def test_init_rejects_bad_workspace_before_any_gpu_work(lib):
+    p = L.lbm_params_default()
+    p.nx = p.ny = 16
+    with pytest.raises(L.LbmError, match="aligned"):
+        L.lbm_init(p, 0, 1 << 20, 8, 8, 8, 0)
+    with pytest.raises(L.LbmError, match="required"):
+        L.lbm_init(p, 1 << 12, 16, 8, 8, 8, 0)
+
+
+def test_tile_table(lib):
+    n = L.lbm_tile_count()
+    assert n >= 8
+    names = [L.lbm_tile_describe(i) for i in range(n)]
+    assert len(set(names)) == n
+    with pytest.raises(L.LbmError):
+        L.lbm_tile_describe(n)
