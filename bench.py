@@ -32,7 +32,28 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_store(torch, W, store, steps, warmup, tune_reps=5, size=4096):
+def copy_ceiling(torch, nbytes, reps=20):
+    """GB/s of the library's plain copy kernel moving nbytes in + nbytes out (median of reps)."""
+    from paper_2005_08674_amd import lbm
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    lbm.lbm_stream_copy(src.data_ptr(), dst.data_ptr(), nbytes, stream.cuda_stream)
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        lbm.lbm_stream_copy(src.data_ptr(), dst.data_ptr(), nbytes, stream.cuda_stream)
+        b.record(stream)
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    ts.sort()
+    ms = ts[len(ts) // 2]
+    del src, dst
+    return 2 * nbytes / (ms * 1e-3) / 1e9, ms
+
+
+def run_store(torch, W, store, steps, warmup, tune_reps=5, size=4096, serial_check=False):
     from paper_2005_08674_amd import lbm
     from paper_2005_08674_amd.lattice import Lattice
 
@@ -45,9 +66,19 @@ def run_store(torch, W, store, steps, warmup, tune_reps=5, size=4096):
     lat.step(warmup)
     stream = lat.stream
     torch.cuda.synchronize()
-    lbm.lbm_enable_timing(lat.ctx, True)
+    if serial_check:
+        for ov in (True, False):
+            lbm.lbm_set_overlap(lat.ctx, ov)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            lat.step(100)
+            b.record(stream)
+            torch.cuda.synchronize()
+            log(f"[{store}] overlap={ov}: {a.elapsed_time(b) / 100:.5f} ms/step")
+    # Timed region: K steps, bracketed by synchronisation, no instrumentation.
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
     t_wall = time.perf_counter()
     e0.record(stream)
     lat.step(steps)
@@ -55,6 +86,10 @@ def run_store(torch, W, store, steps, warmup, tune_reps=5, size=4096):
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
     ms = e0.elapsed_time(e1)
+    # The same K steps again with every kernel launch bracketed by HIP events
+    # on the stream it runs on: per-kernel durations for the roofline.
+    lbm.lbm_enable_timing(lat.ctx, True)
+    lat.step(steps)
     bulk_ms, bulk_n, edge_ms, edge_n = lbm.lbm_kernel_times(lat.ctx)
     lbm.lbm_enable_timing(lat.ctx, False)
     bpn, nodes_launch = lbm.lbm_bulk_traffic(lat.ctx)
@@ -105,6 +140,8 @@ def main():
     ap.add_argument("--variants", default="f16,bf16,f64", help="extra storage variants ('' for none)")
     ap.add_argument("--variant-steps", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune-reps", type=int, default=5)
+    ap.add_argument("--no-copy-ref", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -120,10 +157,12 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
 
-    main_run = run_store(torch, W, "f32", args.steps, args.warmup, size=args.size)
+    main_run = run_store(torch, W, "f32", args.steps, args.warmup, tune_reps=args.tune_reps, size=args.size,
+                         serial_check=True)
     variants = {}
     for st in [s for s in args.variants.split(",") if s]:
-        r = run_store(torch, W, st, args.variant_steps, min(args.warmup, 20), size=args.size)
+        r = run_store(torch, W, st, args.variant_steps, min(args.warmup, 20), tune_reps=args.tune_reps,
+                      size=args.size)
         variants[st] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 5),
                         "bulk_avg_ms": round(r["bulk_avg_ms"], 5), "tile": r["tile"],
                         "roofline_frac": r["roofline"]["frac"], "achieved_GBs": r["roofline"]["achieved"],
@@ -152,6 +191,10 @@ def main():
         "variants": variants,
         "finite": main_run["finite"],
     }
+    if not args.no_copy_ref:
+        gbs, ms = copy_ceiling(torch, 9 * w.nx * w.ny * 4)
+        line["copy_reference"] = {"GBs": round(gbs, 1), "ms": round(ms, 5), "bytes_each_way": 9 * w.nx * w.ny * 4,
+                                  "bulk_frac_of_copy": round(main_run["roofline"]["achieved"] / gbs, 4)}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(W, w)
     print(json.dumps(line), flush=True)

@@ -186,10 +186,26 @@ int lbm_enable_timing(lbm_ctx* ctx, int on);
 int lbm_kernel_times(lbm_ctx* ctx, double* bulk_ms, int64_t* bulk_launches,
                      double* edge_ms, int64_t* edge_launches);
 
+/* Run the edge/corner kernel on a second stream of the library's own,
+ * concurrently with the bulk kernel of the same step (on = 1), or after it on
+ * the context's stream (on = 0, the default: on gfx950 the extra event
+ * traffic of the overlapped form costs more than the edge kernel it hides).  Both orders give identical
+ * results: within a step the two kernels read the same buffer and write
+ * disjoint nodes; every step waits for both kernels of the previous one, and
+ * lbm_step returns with the context's stream ordered after all its work. */
+int lbm_set_overlap(lbm_ctx* ctx, int on);
+
 /* Bytes the bulk kernel must move per interior node and step
  * (2 x 9 x bytes per stored population) and the interior node count
  * (nx-2)(ny-2) it updates per launch. */
 int lbm_bulk_traffic(const lbm_ctx* ctx, int64_t* bytes_per_node, int64_t* nodes_per_launch);
+
+/* Plain device-to-device copy of `bytes` bytes (16-byte loads, non-temporal
+ * stores) on `hip_stream`: the streaming-bandwidth reference the bulk kernel
+ * is measured against, and the known-size kernel used to calibrate hardware
+ * byte counters.  src and dst are 16-byte aligned, non-overlapping device
+ * buffers owned by the caller.  Asynchronous. */
+int lbm_stream_copy(const void* src, void* dst, size_t bytes, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -62,7 +62,10 @@ Layout layout(const lbm_params* p) {
   l.esize = elem_bytes(p->store);
   const size_t row = round_up((size_t)p->nx * l.esize, 256);
   l.pitch = (int32_t)(row / l.esize);
-  const size_t plane_bytes = round_up(row * (size_t)p->ny, 4096);
+  size_t plane_bytes = round_up(row * (size_t)p->ny, 4096);
+  // keep the nine planes from sitting a large power of two apart, so the 18
+  // concurrent streams of one step do not start on the same HBM channel
+  if (plane_bytes % 65536 == 0) plane_bytes += 4096;
   l.plane = (int64_t)(plane_bytes / l.esize);
   l.buf_bytes = round_up(9 * plane_bytes, (size_t)2 << 20);
   l.total = 2 * l.buf_bytes + kScratchBytes;
@@ -109,7 +112,7 @@ void set_scales(lbm::LatDesc& L, int store, int k) {
   }
 }
 
-int default_tile(const lbm_params*) { return 5; }
+int default_tile(const lbm_params*) { return 0; }
 
 }  // namespace
 
@@ -124,6 +127,10 @@ struct lbm_ctx {
   char* scratch = nullptr;
   int tile = 0;
   int f16_exp = 0;
+  // edge kernel on a second stream, overlapped with the bulk kernel
+  bool overlap = false;
+  hipStream_t side = nullptr;
+  hipEvent_t ev_bulk = nullptr, ev_edge = nullptr;
   // per-kernel timing
   bool timing = false;
   std::vector<hipEvent_t> events;
@@ -137,10 +144,11 @@ namespace {
 int flush_timing(lbm_ctx* c) {
   if (c->ev_used == 0) return LBM_OK;
   HIPCHK(hipStreamSynchronize(c->stream));
-  for (size_t k = 0; k + 2 < c->ev_used; k += 3) {
+  HIPCHK(hipStreamSynchronize(c->side));
+  for (size_t k = 0; k + 3 < c->ev_used; k += 4) {
     float a = 0, b = 0;
     HIPCHK(hipEventElapsedTime(&a, c->events[k], c->events[k + 1]));
-    HIPCHK(hipEventElapsedTime(&b, c->events[k + 1], c->events[k + 2]));
+    HIPCHK(hipEventElapsedTime(&b, c->events[k + 2], c->events[k + 3]));
     c->bulk_ms += a;
     c->edge_ms += b;
     c->bulk_n += 1;
@@ -160,24 +168,36 @@ int next_event(lbm_ctx* c, hipEvent_t* ev) {
   return LBM_OK;
 }
 
+// Launch one step.  The bulk kernel goes on the context's stream; the edge
+// kernel goes on the side stream when overlapping (else on the same stream).
+// Both read buffer `parity` and write disjoint node sets of the other one, so
+// within a step they are independent; across steps each waits for both
+// kernels of the previous step (events ev_bulk / ev_edge).
 int step_once(lbm_ctx* c) {
+  hipStream_t es = c->overlap ? c->side : c->stream;
+  hipEvent_t t[4] = {nullptr, nullptr, nullptr, nullptr};
   if (c->timing) {
-    if (c->ev_used + 3 > 3 * 4096) {
+    if (c->ev_used + 4 > 4 * 4096) {
       int rc = flush_timing(c);
       if (rc) return rc;
     }
-    hipEvent_t e0, e1, e2;
-    int rc;
-    if ((rc = next_event(c, &e0)) || (rc = next_event(c, &e1)) || (rc = next_event(c, &e2))) return rc;
-    HIPCHK(hipEventRecord(e0, c->stream));
-    HIPCHK(lbm::launch_bulk(c->L, c->parity, c->tile, c->stream));
-    HIPCHK(hipEventRecord(e1, c->stream));
-    HIPCHK(lbm::launch_edge(c->L, c->parity, c->stream));
-    HIPCHK(hipEventRecord(e2, c->stream));
-  } else {
-    HIPCHK(lbm::launch_bulk(c->L, c->parity, c->tile, c->stream));
-    HIPCHK(lbm::launch_edge(c->L, c->parity, c->stream));
+    for (int k = 0; k < 4; ++k) {
+      int rc = next_event(c, &t[k]);
+      if (rc) return rc;
+    }
   }
+  if (c->overlap) {
+    HIPCHK(hipStreamWaitEvent(c->side, c->ev_bulk, 0));    // bulk kernel of the previous step
+    HIPCHK(hipStreamWaitEvent(c->stream, c->ev_edge, 0));  // edge kernel of the previous step
+  }
+  if (t[2]) HIPCHK(hipEventRecord(t[2], es));
+  HIPCHK(lbm::launch_edge(c->L, c->parity, es));
+  if (t[3]) HIPCHK(hipEventRecord(t[3], es));
+  if (c->overlap) HIPCHK(hipEventRecord(c->ev_edge, es));
+  if (t[0]) HIPCHK(hipEventRecord(t[0], c->stream));
+  HIPCHK(lbm::launch_bulk(c->L, c->parity, c->tile, c->stream));
+  if (t[1]) HIPCHK(hipEventRecord(t[1], c->stream));
+  if (c->overlap) HIPCHK(hipEventRecord(c->ev_bulk, c->stream));
   c->parity ^= 1;
   c->t += 1;
   return LBM_OK;
@@ -224,6 +244,15 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* workspace, size_t bytes, 
   if (bytes < lay.total) return fail(LBM_ERR_ARG, "workspace of %zu bytes < %zu required", bytes, lay.total);
 
   lbm_ctx* c = new lbm_ctx();
+  {
+    hipError_t e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_bulk, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_edge, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      lbm_destroy(c);
+      return fail(LBM_ERR_HIP, "stream/event creation: %s", hipGetErrorString(e));
+    }
+  }
   c->p = *p;
   c->lay = lay;
   c->stream = static_cast<hipStream_t>(hip_stream);
@@ -266,13 +295,13 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* workspace, size_t bytes, 
       if (e == hipSuccess) e = hipMemcpyAsync(host.data(), part, host.size() * sizeof(float), hipMemcpyDeviceToHost, c->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
       if (e != hipSuccess) {
-        delete c;
+        lbm_destroy(c);
         return fail(LBM_ERR_HIP, "f16 exponent reduction: %s", hipGetErrorString(e));
       }
       float mx = 0.f;
       for (float v : host) mx = std::max(mx, v);
       if (!std::isfinite(mx)) {
-        delete c;
+        lbm_destroy(c);
         return fail(LBM_ERR_ARG, "initial fields are not finite");
       }
       k = mx > 1e-30f ? (int)std::floor(std::log2(4096.0 / (double)mx)) : 12;
@@ -287,7 +316,7 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* workspace, size_t bytes, 
   hipError_t e = lbm::launch_init(L, 0, drho, ux, uy, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
-    delete c;
+    lbm_destroy(c);
     return fail(LBM_ERR_HIP, "init kernel: %s", hipGetErrorString(e));
   }
   *out = c;
@@ -309,10 +338,24 @@ int lbm_set_farfield(lbm_ctx* c, double beta, double rho_ref, double ux_ref, dou
 int lbm_step(lbm_ctx* c, int32_t n) {
   if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
   if (n < 0) return fail(LBM_ERR_ARG, "n = %d < 0", n);
+  if (n == 0) return LBM_OK;
+  if (c->overlap) {
+    // fork: the side stream starts after everything already on the stream
+    HIPCHK(hipEventRecord(c->ev_bulk, c->stream));
+    HIPCHK(hipEventRecord(c->ev_edge, c->stream));
+  }
   for (int32_t s = 0; s < n; ++s) {
     int rc = step_once(c);
     if (rc) return rc;
   }
+  // join: later work on the stream sees the last edge kernel too
+  if (c->overlap) HIPCHK(hipStreamWaitEvent(c->stream, c->ev_edge, 0));
+  return LBM_OK;
+}
+
+int lbm_set_overlap(lbm_ctx* c, int on) {
+  if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
+  c->overlap = on != 0;
   return LBM_OK;
 }
 
@@ -333,6 +376,12 @@ const char* lbm_last_error(void) { return g_err.c_str(); }
 void lbm_destroy(lbm_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamDestroy(c->side);
+  }
+  if (c->ev_bulk) (void)hipEventDestroy(c->ev_bulk);
+  if (c->ev_edge) (void)hipEventDestroy(c->ev_edge);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   delete c;
 }
@@ -471,6 +520,16 @@ int lbm_bulk_traffic(const lbm_ctx* c, int64_t* bytes_per_node, int64_t* nodes_p
   if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
   if (bytes_per_node) *bytes_per_node = 18 * (int64_t)c->lay.esize;
   if (nodes_per_launch) *nodes_per_launch = (int64_t)(c->p.nx - 2) * (c->p.ny - 2);
+  return LBM_OK;
+}
+
+int lbm_stream_copy(const void* src, void* dst, size_t bytes, void* hip_stream) {
+  if (bytes == 0) return LBM_OK;
+  if (!src || !dst) return fail(LBM_ERR_ARG, "NULL pointer");
+  if (((uintptr_t)src & 15) || ((uintptr_t)dst & 15)) return fail(LBM_ERR_ARG, "src/dst not 16-byte aligned");
+  const uintptr_t a = (uintptr_t)src, b = (uintptr_t)dst;
+  if (a < b + bytes && b < a + bytes) return fail(LBM_ERR_ARG, "src and dst overlap");
+  HIPCHK(lbm::launch_copy(src, dst, bytes, static_cast<hipStream_t>(hip_stream)));
   return LBM_OK;
 }
 

@@ -26,19 +26,60 @@
 namespace lbm {
 
 // ------------------------------------------------------------------ bulk kernel
-template <int S, int BX, int BY, int NYT, bool REMAP>
-__global__ __launch_bounds__(BX* BY) void k_bulk(LatDesc L, int parity, int tiles_x, int ntiles) {
+// Store of one population; NTS selects a non-temporal store (the written
+// buffer is not read again before the next step streams it back in, so it
+// should not displace the lines the shifted loads share).
+template <bool NTS, class T>
+__device__ inline void put(T* p, T v) {
+  if (NTS) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+// Load of one population; NTL selects a non-temporal load, used only for the
+// populations with c_x = 0, whose cache lines no other wavefront reads.
+template <class T>
+__device__ inline T get(const T* p, bool nt) {
+  if (nt) return __builtin_nontemporal_load(p);
+  return *p;
+}
+
+// Block -> tile maps.  Workgroups are dispatched to the 8 XCDs round-robin
+// (workgroup b runs on XCD b mod 8), and each XCD has its own L2.
+//   REMAP 0: tile = b (row-major tiles, consecutive tiles on different XCDs).
+//   REMAP 1: XCD k takes the k-th contiguous eighth of the tiles.
+//   REMAP 2: XCD k takes the tile rows r = k (mod 8) and walks each row in x,
+//            so the x-neighbours that share the shifted loads' straddling
+//            cache lines run back to back on one XCD, while the eight XCDs
+//            still work on eight adjacent rows.
+template <int REMAP>
+__device__ inline bool bulk_tile(int tiles_x, int tiles_y, int& txi, int& tyi) {
+  const int b = blockIdx.x;
+  if (REMAP == 2) {
+    const int seq = b >> 3;
+    const int grp = seq / tiles_x;
+    txi = seq - grp * tiles_x;
+    tyi = grp * 8 + (b & 7);
+    return tyi < tiles_y;
+  }
+  const int ntiles = tiles_x * tiles_y;
+  int tile = b;
+  if (REMAP == 1) {
+    const int per = (ntiles + 7) >> 3;
+    tile = (b & 7) * per + (b >> 3);
+  }
+  if (tile >= ntiles) return false;
+  tyi = tile / tiles_x;
+  txi = tile - tyi * tiles_x;
+  return true;
+}
+
+template <int S, int BX, int BY, int NYT, int REMAP, bool NTS, bool NTL>
+__global__ __launch_bounds__(BX* BY) void k_bulk(LatDesc L, int parity, int tiles_x, int tiles_y) {
   using C = Codec<S>;
   using T = typename C::T;
   using R = typename C::R;
-  int tile = blockIdx.x;
-  if (REMAP) {
-    const int per = (ntiles + 7) >> 3;
-    tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  }
-  if (tile >= ntiles) return;
-  const int tyi = tile / tiles_x;
-  const int txi = tile - tyi * tiles_x;
+  int txi, tyi;
+  if (!bulk_tile<REMAP>(tiles_x, tiles_y, txi, tyi)) return;
   const int x = txi * BX + threadIdx.x;
   if (x < 1 || x > L.nx - 2) return;
   const int y0 = 1 + tyi * (BY * NYT) + threadIdx.y;
@@ -57,7 +98,7 @@ __global__ __launch_bounds__(BX* BY) void k_bulk(LatDesc L, int parity, int tile
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         const int idx = (y - kCy[i]) * pitch + (x - kCx[i]);
-        g[j][i] = C::dec(A[i * plane + idx], L.ds[i]);
+        g[j][i] = C::dec(get(A + i * plane + idx, NTL && kCx[i] == 0), L.ds[i]);
       }
     }
   }
@@ -68,40 +109,49 @@ __global__ __launch_bounds__(BX* BY) void k_bulk(LatDesc L, int parity, int tile
       bgk<R>(g[j], rho0, base, omega);
       const int idx = y * pitch + x;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) B[i * plane + idx] = C::enc(g[j][i], L.es[i]);
+      for (int i = 0; i < 9; ++i) put<NTS>(B + i * plane + idx, C::enc(g[j][i], L.es[i]));
     }
   }
 }
 
 struct TileShape {
-  int bx, by, nyt;
-  bool remap;
+  int bx, by, nyt, remap;
+  bool nts, ntl;
 };
 
-#define LBM_TILES(X)         \
-  X(64, 4, 1, false)         \
-  X(64, 4, 2, false)         \
-  X(64, 4, 4, false)         \
-  X(128, 2, 1, false)        \
-  X(128, 2, 2, false)        \
-  X(256, 1, 1, false)        \
-  X(256, 1, 2, false)        \
-  X(256, 1, 4, false)        \
-  X(64, 8, 1, false)         \
-  X(128, 4, 1, false)        \
-  X(64, 4, 1, true)          \
-  X(64, 4, 2, true)          \
-  X(64, 4, 4, true)          \
-  X(128, 2, 1, true)         \
-  X(128, 2, 2, true)         \
-  X(256, 1, 1, true)         \
-  X(256, 1, 2, true)         \
-  X(256, 1, 4, true)         \
-  X(64, 8, 1, true)          \
-  X(128, 4, 1, true)
+// Candidate launch shapes of the bulk kernel: block (BX x BY), nodes per
+// thread along y (NYT), block -> tile map (REMAP), non-temporal stores (NTS),
+// non-temporal loads of the unshifted populations (NTL).
+#define LBM_TILES(X)                   \
+  X(256, 1, 1, 0, true, false)         \
+  X(256, 1, 2, 0, true, false)         \
+  X(256, 1, 4, 0, true, false)         \
+  X(128, 2, 1, 0, true, false)         \
+  X(128, 2, 2, 0, true, false)         \
+  X(64, 4, 1, 0, true, false)          \
+  X(64, 4, 2, 0, true, false)          \
+  X(64, 8, 1, 0, true, false)          \
+  X(128, 4, 1, 0, true, false)         \
+  X(512, 1, 1, 0, true, false)         \
+  X(1024, 1, 1, 0, true, false)        \
+  X(256, 1, 1, 1, true, false)         \
+  X(128, 2, 1, 1, true, false)         \
+  X(256, 1, 1, 2, true, false)         \
+  X(256, 1, 2, 2, true, false)         \
+  X(512, 1, 1, 2, true, false)         \
+  X(128, 2, 1, 2, true, false)         \
+  X(64, 4, 1, 2, true, false)          \
+  X(256, 1, 1, 2, true, true)          \
+  X(512, 1, 1, 2, true, true)          \
+  X(256, 1, 1, 0, true, true)          \
+  X(512, 1, 1, 0, true, true)          \
+  X(256, 1, 1, 0, false, false)        \
+  X(256, 1, 2, 0, false, false)        \
+  X(128, 2, 1, 0, false, false)        \
+  X(64, 4, 1, 0, false, false)
 
 static const TileShape kTiles[] = {
-#define X(a, b, c, d) {a, b, c, d},
+#define X(a, b, c, d, e, f) {a, b, c, d, e, f},
     LBM_TILES(X)
 #undef X
 };
@@ -115,25 +165,28 @@ void tile_name(int id, char* buf, size_t len) {
     return;
   }
   const TileShape& t = kTiles[id];
-  snprintf(buf, len, "%dx%dx%d%s", t.bx, t.by, t.nyt, t.remap ? "+xcd" : "");
+  snprintf(buf, len, "%dx%dx%d%s%s%s", t.bx, t.by, t.nyt, t.remap == 1 ? "+xcdband" : (t.remap == 2 ? "+xcdrow" : ""),
+           t.nts ? "+nts" : "", t.ntl ? "+ntl" : "");
 }
 
-template <int S, int BX, int BY, int NYT, bool REMAP>
+template <int S, int BX, int BY, int NYT, int REMAP, bool NTS, bool NTL>
 static hipError_t launch_bulk_t(const LatDesc& L, int parity, hipStream_t s) {
   const int tiles_x = (L.nx + BX - 1) / BX;
   const int tiles_y = (L.ny - 2 + BY * NYT - 1) / (BY * NYT);
-  const int ntiles = tiles_x * tiles_y;
-  if (ntiles <= 0) return hipSuccess;
-  const int grid = REMAP ? ((ntiles + 7) >> 3) * 8 : ntiles;
-  k_bulk<S, BX, BY, NYT, REMAP><<<dim3(grid), dim3(BX, BY), 0, s>>>(L, parity, tiles_x, ntiles);
+  if (tiles_x <= 0 || tiles_y <= 0) return hipSuccess;
+  int grid;
+  if (REMAP == 0) grid = tiles_x * tiles_y;
+  else if (REMAP == 1) grid = ((tiles_x * tiles_y + 7) >> 3) * 8;
+  else grid = tiles_x * ((tiles_y + 7) >> 3) * 8;
+  k_bulk<S, BX, BY, NYT, REMAP, NTS, NTL><<<dim3(grid), dim3(BX, BY), 0, s>>>(L, parity, tiles_x, tiles_y);
   return hipGetLastError();
 }
 
 template <int S>
 static hipError_t launch_bulk_s(const LatDesc& L, int parity, int tile, hipStream_t s) {
   int id = 0;
-#define X(a, b, c, d)                                          \
-  if (tile == id) return launch_bulk_t<S, a, b, c, d>(L, parity, s); \
+#define X(a, b, c, d, e, f)                                                \
+  if (tile == id) return launch_bulk_t<S, a, b, c, d, e, f>(L, parity, s); \
   ++id;
   LBM_TILES(X)
 #undef X
@@ -175,8 +228,11 @@ __device__ inline R normal_diff(R mb, R m1, R m2, int order) {
   return order == 1 ? mb - m1 : (R(3) * mb - R(4) * m1 + m2) * R(0.5);
 }
 
+constexpr int EDGE_THREADS = 256;  // >= DEPTH * STRIP: one staged strip node per thread
+static_assert(EDGE_THREADS >= DEPTH * STRIP, "edge block must cover the staged strip");
+
 template <int S>
-__global__ __launch_bounds__(SEG) void k_edge(LatDesc L, int parity) {
+__global__ __launch_bounds__(EDGE_THREADS) void k_edge(LatDesc L, int parity) {
   using C = Codec<S>;
   using T = typename C::T;
   using R = typename C::R;
@@ -212,63 +268,68 @@ __global__ __launch_bounds__(SEG) void k_edge(LatDesc L, int parity) {
   const int64_t plane = L.plane;
   const R rho0 = R(L.rho0);
   const Base<R> base(L);
+  const int tid = threadIdx.x;
 
-  // Stage the time-t moments of the strip (depth 0..2, tangential halo 2).
-  if (any_nsbc) {
-    for (int k = threadIdx.x; k < DEPTH * STRIP; k += SEG) {
-      const int d = k / STRIP, tt = k - d * STRIP;
-      int t = t0 - HALO + tt;
-      bool inside = true;
-      if (t < 0 || t >= ntan) {
-        if (tan_per) t = t < 0 ? t + ntan : t - ntan;
-        else inside = false;
-      }
-      R m[3] = {R(0), R(0), R(0)};
-      if (inside) {
-        int x, y;
-        edge_node(L, edge, d, t, x, y);
-        R g[9];
-        const int idx = y * pitch + x;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = C::dec(A[i * plane + idx], L.ds[i]);
-        moments<R>(g, rho0, base, m[0], m[1], m[2]);
-      }
-      mom[0][d][tt] = m[0];
-      mom[1][d][tt] = m[1];
-      mom[2][d][tt] = m[2];
-    }
-  }
-  __syncthreads();
-
-  const int t = t0 + threadIdx.x;
-  if (t >= tend) return;
-  int x, y;
-  edge_node(L, edge, 0, t, x, y);
-
-  // Pull the known populations; mark those whose source is outside the domain.
+  // Lanes 0..SEG-1 own one boundary node each: pull its known populations
+  // (wrapping across periodic edges) and mark those whose source lies
+  // outside the domain.  Issued before the strip staging so both sets of
+  // loads are in flight together.
+  const int t = t0 + tid;
+  const bool owner = tid < SEG && t < tend;
+  int x = 0, y = 0;
   R g[9];
   uint32_t unknown = 0;
+  if (owner) {
+    edge_node(L, edge, 0, t, x, y);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    int sx = x - kCx[i], sy = y - kCy[i];
-    const bool outx = sx < 0 || sx >= nx;
-    const bool outy = sy < 0 || sy >= ny;
-    if ((outx && !xper) || (outy && !yper)) {
-      unknown |= 1u << i;
-      g[i] = R(0);
-    } else {
-      if (outx) sx = sx < 0 ? sx + nx : sx - nx;
-      if (outy) sy = sy < 0 ? sy + ny : sy - ny;
-      g[i] = C::dec(A[i * plane + (sy * pitch + sx)], L.ds[i]);
+    for (int i = 0; i < 9; ++i) {
+      int sx = x - kCx[i], sy = y - kCy[i];
+      const bool outx = sx < 0 || sx >= nx;
+      const bool outy = sy < 0 || sy >= ny;
+      if ((outx && !xper) || (outy && !yper)) {
+        unknown |= 1u << i;
+        g[i] = R(0);
+      } else {
+        if (outx) sx = sx < 0 ? sx + nx : sx - nx;
+        if (outy) sy = sy < 0 ? sy + ny : sy - ny;
+        g[i] = C::dec(A[i * plane + (sy * pitch + sx)], L.ds[i]);
+      }
     }
   }
+
+  // Stage the time-t moments of the strip (depth 0..2, tangential halo 2),
+  // one strip node per thread.
+  if (any_nsbc && tid < DEPTH * STRIP) {
+    const int d = tid / STRIP, tt = tid - d * STRIP;
+    int ts = t0 - HALO + tt;
+    bool inside = true;
+    if (ts < 0 || ts >= ntan) {
+      if (tan_per) ts = ts < 0 ? ts + ntan : ts - ntan;
+      else inside = false;
+    }
+    R m[3] = {R(0), R(0), R(0)};
+    if (inside) {
+      int sx, sy;
+      edge_node(L, edge, d, ts, sx, sy);
+      R gs[9];
+      const int idx = sy * pitch + sx;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) gs[i] = C::dec(A[i * plane + idx], L.ds[i]);
+      moments<R>(gs, rho0, base, m[0], m[1], m[2]);
+    }
+    mom[0][d][tt] = m[0];
+    mom[1][d][tt] = m[1];
+    mom[2][d][tt] = m[2];
+  }
+  __syncthreads();
+  if (!owner) return;
 
   const bool onL = x == 0 && L.bc[E_LEFT] == BC_NSBC;
   const bool onR = x == nx - 1 && L.bc[E_RIGHT] == BC_NSBC;
   const bool onB = y == 0 && L.bc[E_BOTTOM] == BC_NSBC;
   const bool onT = y == ny - 1 && L.bc[E_TOP] == BC_NSBC;
   if (onL || onR || onB || onT) {
-    const int tt = threadIdx.x + HALO;
+    const int tt = tid + HALO;
     const bool own = (edge == E_LEFT && onL) || (edge == E_RIGHT && onR) || (edge == E_BOTTOM && onB) ||
                      (edge == E_TOP && onT);
     int nn = 0;
@@ -280,11 +341,11 @@ __global__ __launch_bounds__(SEG) void k_edge(LatDesc L, int parity) {
       for (int c = 0; c < 3; ++c) dsum[c] += normal_diff(mom[c][0][tt], mom[c][1][tt], mom[c][2][tt], L.grad_order);
     }
     if (vertical && (onB || onT)) {  // corner node: second normal runs along this strip
-      const int s = onB ? 1 : -1;
+      const int sgn = onB ? 1 : -1;
       ++nn;
 #pragma unroll
       for (int c = 0; c < 3; ++c)
-        dsum[c] += normal_diff(mom[c][0][tt], mom[c][0][tt + s], mom[c][0][tt + 2 * s], L.grad_order);
+        dsum[c] += normal_diff(mom[c][0][tt], mom[c][0][tt + sgn], mom[c][0][tt + 2 * sgn], L.grad_order);
     }
     R fac = R(L.gamma);
     if (nn == 2) fac *= L.corner_mode == 0 ? R(0.70710678118654752440) : R(0.5);
@@ -300,13 +361,13 @@ __global__ __launch_bounds__(SEG) void k_edge(LatDesc L, int parity) {
   bgk<R>(g, rho0, base, R(L.omega));
   const int idx = y * pitch + x;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) B[i * plane + idx] = C::enc(g[i], L.es[i]);
+  for (int i = 0; i < 9; ++i) put<true>(B + i * plane + idx, C::enc(g[i], L.es[i]));
 }
 
 int edge_blocks(int nx, int ny) { return 2 * edge_segments_v(ny) + 2 * edge_segments_h(nx); }
 
 hipError_t launch_edge(const LatDesc& L, int parity, hipStream_t s) {
-  const dim3 grid(edge_blocks(L.nx, L.ny)), block(SEG);
+  const dim3 grid(edge_blocks(L.nx, L.ny)), block(EDGE_THREADS);
   switch (L.store) {
     case ST_F64: k_edge<ST_F64><<<grid, block, 0, s>>>(L, parity); break;
     case ST_F32: k_edge<ST_F32><<<grid, block, 0, s>>>(L, parity); break;
@@ -505,6 +566,41 @@ __global__ __launch_bounds__(EN_BLOCK) void k_sum_partials(const double* partial
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = red[0];
+}
+
+// Plain device copy: one 16-byte element per thread, non-temporal loads and
+// stores, one block per 4 KiB.  The bandwidth reference the bulk kernel is
+// compared with.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_copy16(const u32x4* __restrict__ a, u32x4* __restrict__ b, size_t n16) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n16) __builtin_nontemporal_store(__builtin_nontemporal_load(a + i), b + i);
+}
+
+__global__ void k_copy1(const unsigned char* __restrict__ a, unsigned char* __restrict__ b, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
+  const size_t n16 = bytes / 16;
+  for (size_t done = 0; done < n16;) {  // chunks keep a launch below 2^31 work-items
+    const size_t chunk = n16 - done < ((size_t)1 << 31) ? n16 - done : ((size_t)1 << 31);
+    const unsigned grid = (unsigned)((chunk + 255) / 256);
+    k_copy16<<<dim3(grid), dim3(256), 0, s>>>(static_cast<const u32x4*>(src) + done,
+                                               static_cast<u32x4*>(dst) + done, chunk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    done += chunk;
+  }
+  const size_t tail = bytes - n16 * 16;
+  if (tail) {
+    k_copy1<<<dim3(1), dim3(16), 0, s>>>(static_cast<const unsigned char*>(src) + n16 * 16,
+                                         static_cast<unsigned char*>(dst) + n16 * 16, tail);
+    return hipGetLastError();
+  }
+  return hipSuccess;
 }
 
 // ------------------------------------------------------------------ launchers

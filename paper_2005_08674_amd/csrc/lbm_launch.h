@@ -28,4 +28,6 @@ int energy_partials();
 hipError_t launch_energy(const LatDesc& T_, int pt, const LatDesc* R_, int pr, int xo, int yo, double ux_ref,
                          double uy_ref, double* partial, double* out, hipStream_t s);
 
+hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+
 }  // namespace lbm

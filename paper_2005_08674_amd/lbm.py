@@ -74,6 +74,8 @@ _SIGS = {
     "lbm_enable_timing": [_P, ctypes.c_int],
     "lbm_kernel_times": [_P, _P, _P, _P, _P],
     "lbm_bulk_traffic": [_P, _P, _P],
+    "lbm_set_overlap": [_P, ctypes.c_int],
+    "lbm_stream_copy": [_P, _P, ctypes.c_size_t, _P],
 }
 
 
@@ -219,6 +221,14 @@ def lbm_kernel_times(ctx):
     _check(load().lbm_kernel_times(ctx, ctypes.byref(bm), ctypes.byref(bn), ctypes.byref(em), ctypes.byref(en)),
            "lbm_kernel_times")
     return bm.value, bn.value, em.value, en.value
+
+
+def lbm_set_overlap(ctx, on: bool):
+    _check(load().lbm_set_overlap(ctx, int(on)), "lbm_set_overlap")
+
+
+def lbm_stream_copy(src_ptr, dst_ptr, nbytes, stream_ptr):
+    _check(load().lbm_stream_copy(src_ptr, dst_ptr, int(nbytes), stream_ptr), "lbm_stream_copy")
 
 
 def lbm_bulk_traffic(ctx):

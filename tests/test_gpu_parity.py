@@ -191,3 +191,40 @@ def test_nonfinite_detected():
     pops[3, 5, 5] = float("nan")
     g.set_populations(pops)
     assert not g.check_finite()
+
+
+def test_overlap_matches_serial():
+    """Edge kernel on the side stream (overlapped) or after the bulk kernel: identical bits."""
+    from paper_2005_08674_amd import lbm
+    w = W.vortex_512x256(nx=192, ny=96)
+    a = _lattice(nx=192, ny=96, tau=0.55, fields=w.fields, store="f32", m0=w.m0, ubase=(0.1, 0.0))
+    b = _lattice(nx=192, ny=96, tau=0.55, fields=w.fields, store="f32", m0=w.m0, ubase=(0.1, 0.0))
+    lbm.lbm_set_overlap(a.ctx, True)
+    lbm.lbm_set_overlap(b.ctx, False)
+    for n in (1, 5, 37):
+        a.step(n)
+        b.step(n)
+        assert np.array_equal(a.populations().cpu().numpy(), b.populations().cpu().numpy())
+
+
+def test_kernel_timing_counts_launches():
+    from paper_2005_08674_amd import lbm
+    w = W.pulse_128(256, 256)
+    g = _lattice(nx=256, ny=256, tau=0.6, fields=w.fields, store="f32")
+    lbm.lbm_enable_timing(g.ctx, True)
+    g.step(25)
+    bm, bn, em, en = lbm.lbm_kernel_times(g.ctx)
+    assert bn == 25 and en == 25 and bm > 0 and em > 0
+    lbm.lbm_enable_timing(g.ctx, False)
+    b, n = lbm.lbm_bulk_traffic(g.ctx)
+    assert b == 72 and n == 254 * 254
+
+
+@pytest.mark.parametrize("nbytes", [16, 4096 + 7, 3 * 1000003])
+def test_stream_copy(nbytes):
+    from paper_2005_08674_amd import lbm
+    src = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, device="cuda")
+    dst = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    lbm.lbm_stream_copy(src.data_ptr(), dst.data_ptr(), nbytes, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
