@@ -26,41 +26,48 @@ def _grid(nx: int, ny: int):
     return x, y
 
 
-def gaussian_pulses(nx: int, ny: int, pulses: Sequence[Tuple[float, float, float, float]],
-                    u0: Tuple[float, float] = (0.0, 0.0)):
-    """Superposed Gaussian density pulses on a uniform flow.
+def gaussian_pulses_xy(x, y, pulses: Sequence[Tuple[float, float, float, float]], u0=(0.0, 0.0)):
+    """Superposed Gaussian density pulses on a uniform flow, at coordinates (x, y).
 
     Each pulse is (amplitude A, half-width at half-maximum w, x_c, y_c):
     drho = sum A exp(-ln2 d^2 / w^2), u = u0 everywhere.
     """
-    x, y = _grid(nx, ny)
-    drho = np.zeros((ny, nx))
+    drho = np.zeros(np.shape(x))
     for a, w, xc, yc in pulses:
         d2 = (x - xc) ** 2 + (y - yc) ** 2
         drho += a * np.exp(-math.log(2.0) * d2 / (w * w))
-    return drho, np.full((ny, nx), float(u0[0])), np.full((ny, nx), float(u0[1]))
+    return drho, np.full(np.shape(x), float(u0[0])), np.full(np.shape(x), float(u0[1]))
 
 
-def lamb_oseen(nx: int, ny: int, x0: float, y0: float, rc: float, uv: float,
-               u0: Tuple[float, float] = (0.1, 0.0), rho0: float = 1.0, offset=(0.0, 0.0)):
-    """Lamb-Oseen vortex on a uniform flow (Sec. 7, eqs. cv_u, cv_v, cv_d).
+def gaussian_pulses(nx: int, ny: int, pulses: Sequence[Tuple[float, float, float, float]],
+                    u0: Tuple[float, float] = (0.0, 0.0)):
+    """gaussian_pulses_xy on the nx x ny lattice."""
+    x, y = _grid(nx, ny)
+    return gaussian_pulses_xy(x, y, pulses, u0)
+
+
+def lamb_oseen_xy(x, y, x0: float, y0: float, rc: float, uv: float, u0=(0.1, 0.0), rho0: float = 1.0):
+    """Lamb-Oseen vortex on a uniform flow (Sec. 7, eqs. cv_u, cv_v, cv_d), at coordinates (x, y).
 
     With d^2 = (x-x0)^2 + (y-y0)^2 and the swirl amplitude U_v = beta*u0:
       u = u0x - U_v (y-y0)/R_c exp(-d^2/(2 R_c^2))
       v = u0y + U_v (x-x0)/R_c exp(-d^2/(2 R_c^2))
       rho = rho0 (1 - U_v^2/(2 C_v) exp(-d^2/R_c^2)),  C_v = c_s^2 in 2-D, exponent 1/(gamma-1) = 1.
     The swirl speed peaks at d = R_c with value U_v e^{-1/2}.
-    ``offset`` shifts the lattice coordinates (used to place a window in a larger reference).
     """
-    x, y = _grid(nx, ny)
-    x = x + offset[0]
-    y = y + offset[1]
     d2 = (x - x0) ** 2 + (y - y0) ** 2
     e = np.exp(-d2 / (2.0 * rc * rc))
     ux = u0[0] - uv * (y - y0) / rc * e
     uy = u0[1] + uv * (x - x0) / rc * e
     drho = -rho0 * uv * uv / (2.0 * CS * CS) * e * e
     return drho, ux, uy
+
+
+def lamb_oseen(nx: int, ny: int, x0: float, y0: float, rc: float, uv: float,
+               u0: Tuple[float, float] = (0.1, 0.0), rho0: float = 1.0, offset=(0.0, 0.0)):
+    """lamb_oseen_xy on the nx x ny lattice; ``offset`` shifts the lattice coordinates."""
+    x, y = _grid(nx, ny)
+    return lamb_oseen_xy(x + offset[0], y + offset[1], x0, y0, rc, uv, u0, rho0)
 
 
 def swirl_amplitude(max_swirl: float) -> float:
