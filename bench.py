@@ -53,16 +53,27 @@ def copy_ceiling(torch, nbytes, reps=20):
     return 2 * nbytes / (ms * 1e-3) / 1e9, ms
 
 
-def run_store(torch, W, store, steps, warmup, tune_reps=5, size=4096, serial_check=False):
+def run_store(torch, W, store, steps, warmup, tune_reps=5, size=4096, serial_check=False, tile=None, retune=False):
     from paper_2005_08674_amd import lbm
     from paper_2005_08674_amd.lattice import Lattice
 
     w = W.pulses_4096(n=size)
     lat = Lattice(w.nx, w.ny, w.tau, w.fields, store=store)
-    best, times = lat.autotune(reps=tune_reps)
-    tile_name = lbm.lbm_tile_describe(best)
-    log(f"[{store}] autotune -> {tile_name} ({min(times):.4f} ms); "
-        + ", ".join(f"{lbm.lbm_tile_describe(i)}={t:.4f}" for i, t in enumerate(times)))
+    from paper_2005_08674_amd import autotune
+    if tile:
+        names = [lbm.lbm_tile_describe(i) for i in range(lbm.lbm_tile_count())]
+        lbm.lbm_set_tile(lat.ctx, names.index(tile))
+        tile_name = tile
+        log(f"[{store}] tile fixed to {tile}")
+    else:
+        tile_name = None if retune else autotune.apply(lat, store)
+        if tile_name:
+            log(f"[{store}] tile from the autotuner cache: {tile_name}")
+        else:
+            e = autotune.tune(lat, store, reps=tune_reps, path=None)
+            tile_name = e["tile"]
+            log(f"[{store}] autotune -> {tile_name} ({e['ms']:.4f} ms); "
+                + ", ".join(f"{n}={t:.4f}" for n, t in e["candidates"].items()))
     lat.step(warmup)
     stream = lat.stream
     torch.cuda.synchronize()
@@ -115,6 +126,38 @@ def run_store(torch, W, store, steps, warmup, tune_reps=5, size=4096, serial_che
     return out
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bulk_pulses4096_f32_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2005_08674_amd", "csrc", f) for f in ("lbm_kernels.hip", "lbm_device.h")]
+
+
+def kernel_source_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(tile: str):
+    """HBM bytes per bulk launch measured with rocprofv3 counters (profiles/), or None when the
+    record is missing, was taken with another tile, or the kernel sources changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
+    if rec.get("kernel_source_sha256") != kernel_source_sha() or rec.get("tile") != tile:
+        return None
+    try:
+        return float(rec["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(W, w, budget_s=12.0):
     import oracle
     o = oracle.Lattice(w.nx, w.ny, w.tau, *w.fields)
@@ -142,6 +185,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune-reps", type=int, default=5)
     ap.add_argument("--no-copy-ref", action="store_true")
+    ap.add_argument("--tile", default=None, help="fix the FP32 bulk tile by name instead of autotuning")
+    ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache and re-time all tiles")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -158,16 +203,19 @@ def main():
     torch.cuda.set_device(0)
 
     main_run = run_store(torch, W, "f32", args.steps, args.warmup, tune_reps=args.tune_reps, size=args.size,
-                         serial_check=True)
+                         serial_check=True, tile=args.tile, retune=args.retune)
     variants = {}
     for st in [s for s in args.variants.split(",") if s]:
         r = run_store(torch, W, st, args.variant_steps, min(args.warmup, 20), tune_reps=args.tune_reps,
-                      size=args.size)
+                      size=args.size, retune=args.retune)
         variants[st] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 5),
                         "bulk_avg_ms": round(r["bulk_avg_ms"], 5), "tile": r["tile"],
                         "roofline_frac": r["roofline"]["frac"], "achieved_GBs": r["roofline"]["achieved"],
                         "steps": args.variant_steps, "finite": r["finite"]}
     w = main_run["workload"]
+    traffic = recorded_traffic(main_run["tile"])
+    if traffic is not None:
+        main_run["roofline"]["traffic"] = traffic
     line = {
         "metric": METRIC,
         "value": round(main_run["mlups"], 1),
