@@ -158,6 +158,37 @@ def recorded_traffic(tile: str):
         return None
 
 
+def run_ensemble(torch, W, steps, count=256, seed=4):
+    """The batched-ensemble workload: `count` lattices with sides U{64..512}, tau U[0.52, 0.8], pulse or
+    vortex, FP32 storage; `steps` steps in ONE graph launch (captured beforehand)."""
+    from paper_2005_08674_amd import lbm
+    from paper_2005_08674_amd.ensemble import Ensemble, member_params
+    ms = W.ensemble_members(count, seed=seed)
+    members = [member_params(m.nx, m.ny, m.tau, store="f32",
+                             ubase=(m.params["u0"] if m.kind == "vortex" else (0.0, 0.0))) for m in ms]
+    ens = Ensemble(members, [W.member_fields(m) for m in ms])
+    for k, m in enumerate(ms):
+        ens.set_farfield(k, 0.0, *W.member_m0(m))
+    best, times = ens.autotune(reps=5)
+    shape = lbm.lbm_ens_shape_describe(best)
+    nodes, nb, ne = ens.info()
+    ens.step_graph(steps)  # capture, instantiate, first launch (untimed)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(ens.stream)
+    ens.step_graph(steps)
+    b.record(ens.stream)
+    torch.cuda.synchronize()
+    ms_ = a.elapsed_time(b)
+    ens.close()
+    bulk_nodes = sum((m.nx - 2) * (m.ny - 2) for m in ms)
+    return {"mlups": round(nodes * steps / (ms_ * 1e-3) / 1e6, 1), "ms_per_step": round(ms_ / steps, 5),
+            "members": count, "nodes": nodes, "steps_per_graph_launch": steps, "shape": shape,
+            "bulk_blocks": nb, "edge_blocks": ne, "bulk_ms_by_shape": {lbm.lbm_ens_shape_describe(i): round(t, 5)
+                                                                      for i, t in enumerate(times)},
+            "step_GBs_algorithmic": round(72 * bulk_nodes / (ms_ / steps * 1e-3) / 1e9, 1)}
+
+
 def cpu_baseline(W, w, budget_s=12.0):
     import oracle
     o = oracle.Lattice(w.nx, w.ny, w.tau, *w.fields)
@@ -187,6 +218,7 @@ def main():
     ap.add_argument("--no-copy-ref", action="store_true")
     ap.add_argument("--tile", default=None, help="fix the FP32 bulk tile by name instead of autotuning")
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache and re-time all tiles")
+    ap.add_argument("--ensemble-steps", type=int, default=2000, help="0 skips the ensemble variant")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -212,6 +244,8 @@ def main():
                         "bulk_avg_ms": round(r["bulk_avg_ms"], 5), "tile": r["tile"],
                         "roofline_frac": r["roofline"]["frac"], "achieved_GBs": r["roofline"]["achieved"],
                         "steps": args.variant_steps, "finite": r["finite"]}
+    if args.ensemble_steps > 0:
+        variants["ensemble256_f32"] = run_ensemble(torch, W, args.ensemble_steps)
     w = main_run["workload"]
     traffic = recorded_traffic(main_run["tile"])
     if traffic is not None:

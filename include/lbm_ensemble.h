@@ -1,0 +1,90 @@
+/*
+ * lbm_ensemble.h -- C ABI of the batched ensemble: many independent D2Q9
+ * BGK + NSBC lattices of different sizes and parameters advanced together.
+ *
+ * The method per lattice is the one of lbm.h (Euser & Vuik, arXiv 2005.08674,
+ * Secs. 3 and 5: eqs. lbe_0, lbe_1, feq_1, nes_0..nes_4).  The ensemble adds
+ * no arithmetic: one launch of the bulk kernel covers the interior tiles of
+ * every member (through a device table of {member, tile}), one launch of the
+ * edge kernel covers the edge segments of every member, and n such steps can
+ * be captured once into a HIP graph and replayed as a single graph launch.
+ * Every member's result is bit-identical to the same lattice run alone
+ * through lbm.h.
+ *
+ * Conventions are those of lbm.h: device memory belongs to the caller, the
+ * ensemble object is host memory owned by the library, calls return LBM_OK or
+ * a negative LBM_ERR_* code (message in lbm_last_error()), and work is
+ * asynchronous on the caller's stream.
+ */
+#ifndef LBM_ENSEMBLE_H
+#define LBM_ENSEMBLE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "lbm.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ens lbm_ens;
+
+/* Device workspace in bytes for `count` members described by members[0..count-1]
+ * (each a valid lbm_params; all must use the same `store`): descriptor and
+ * tile tables, a scratch area, and two population buffers per member. */
+int lbm_ens_workspace_bytes(const lbm_params* members, int32_t count, size_t* bytes);
+
+/* Create the ensemble on `workspace` (device memory, 256-byte aligned, at
+ * least lbm_ens_workspace_bytes, borrowed until lbm_ens_destroy) and set
+ * every member to the equilibrium of its initial fields (eq. feq_1).
+ * drho, ux, uy are device float64 arrays holding the members' [ny][nx]
+ * fields one after another (member m starts at element sum_{k<m} nx_k ny_k).
+ * All members start with beta = 0, m0 = (rho0, 0, 0).  Synchronizes
+ * `hip_stream` (the stream all later work goes to). */
+int lbm_ens_init(lbm_ens** out, const lbm_params* members, int32_t count, void* workspace, size_t bytes,
+                 const double* drho, const double* ux, const double* uy, void* hip_stream);
+
+/* Far-field criterion of one member (eq. nes_3), as lbm_set_farfield.  Takes
+ * effect from the next step, including steps of already captured graphs. */
+int lbm_ens_set_farfield(lbm_ens* e, int32_t member, double beta, double rho_ref, double ux_ref, double uy_ref);
+
+/* Advance every member n >= 0 steps with two kernel launches per step. */
+int lbm_ens_step(lbm_ens* e, int32_t n);
+
+/* Advance every member n >= 1 steps with one launch of a HIP graph holding
+ * the n steps' 2n kernel launches.  The graph is captured and instantiated
+ * on first use for this n (and step parity) and cached until lbm_ens_destroy. */
+int lbm_ens_step_graph(lbm_ens* e, int32_t n);
+
+/* Moments of one member, as lbm_moments. */
+int lbm_ens_moments(lbm_ens* e, int32_t member, void* drho_out, void* ux_out, void* uy_out, int out_f64,
+                    int deviation);
+
+/* Populations of one member as f_i - w_i rho0, device float64 [9][ny][nx]. */
+int lbm_ens_get_populations(lbm_ens* e, int32_t member, double* g_out);
+
+/* Steps taken so far (the same for every member). */
+int lbm_ens_time(const lbm_ens* e, int64_t* t);
+
+/* Total node count, and the block counts of one bulk launch and of one edge
+ * launch for the current tile shape. */
+int lbm_ens_info(const lbm_ens* e, int64_t* nodes, int32_t* bulk_blocks, int32_t* edge_blocks);
+
+/* Bulk tile shapes of the ensemble kernel (rebuilds the tile table; cached
+ * graphs are dropped).  lbm_ens_autotune times every shape (median of `reps`
+ * launches after one warm-up; the state is not advanced) and keeps the
+ * fastest; times_ms (optional) receives one median per shape. */
+int lbm_ens_shape_count(void);
+int lbm_ens_shape_describe(int32_t id, char* buf, size_t len);
+int lbm_ens_set_shape(lbm_ens* e, int32_t id);
+int lbm_ens_autotune(lbm_ens* e, int32_t reps, int32_t* best, float* times_ms);
+
+/* Release the ensemble (waits for its stream; destroys cached graphs). */
+void lbm_ens_destroy(lbm_ens* e);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_ENSEMBLE_H */

@@ -12,9 +12,11 @@
 
 #include "lbm.h"
 #include "lbm_device.h"
+#include "lbm_host.h"
 #include "lbm_launch.h"
 
-namespace {
+namespace lbm {
+namespace host {
 
 thread_local std::string g_err;
 
@@ -28,16 +30,7 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
-#define HIPCHK(expr)                                                                        \
-  do {                                                                                      \
-    hipError_t e_ = (expr);                                                                 \
-    if (e_ != hipSuccess) return fail(LBM_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
-  } while (0)
-
-constexpr size_t kScratchBytes = 1 << 20;
-constexpr size_t kOffEnergy = 0;            // energy partials (double)
-constexpr size_t kOffAbsmax = 64 << 10;     // absmax partials (float)
-constexpr size_t kOffFlag = 128 << 10;      // finiteness flag (int)
+const char* last_error() { return g_err.c_str(); }
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -48,14 +41,6 @@ size_t elem_bytes(int store) {
     default: return 2;
   }
 }
-
-struct Layout {
-  size_t esize;
-  int32_t pitch;
-  int64_t plane;     // elements
-  size_t buf_bytes;  // one population buffer (9 planes)
-  size_t total;
-};
 
 Layout layout(const lbm_params* p) {
   Layout l;
@@ -99,18 +84,85 @@ int check_params(const lbm_params* p) {
   return LBM_OK;
 }
 
-void set_scales(lbm::LatDesc& L, int store, int k) {
+void set_scales(LatDesc& L, int store, int k) {
   for (int i = 0; i < 9; ++i) {
     if (store == LBM_STORE_F64 || store == LBM_STORE_F32) {
       L.ds[i] = 1.0f;
       L.es[i] = 1.0f;
     } else {
-      const double w = lbm::wgt<double>(i);
+      const double w = wgt<double>(i);
       L.ds[i] = (float)std::ldexp(w, -k);
       L.es[i] = (float)std::ldexp(1.0 / w, k);  // 2.25, 9, 36 times 2^k: exact
     }
   }
 }
+
+void fill_desc(LatDesc& L, const lbm_params* p, const Layout& lay, void* buf0, void* buf1) {
+  std::memset(&L, 0, sizeof(L));
+  L.buf[0] = buf0;
+  L.buf[1] = buf1;
+  L.nx = p->nx;
+  L.ny = p->ny;
+  L.pitch = lay.pitch;
+  L.store = p->store;
+  L.plane = lay.plane;
+  for (int e = 0; e < 4; ++e) L.bc[e] = p->bc[e];
+  L.corr_mode = p->corr_mode;
+  L.grad_order = p->grad_order;
+  L.corner_mode = p->corner_mode;
+  L.omega = 1.0 / p->tau;
+  L.rho0 = p->rho0;
+  L.gamma = p->gamma;
+  L.beta = 0.0;
+  L.ub[0] = p->ubase[0];
+  L.ub[1] = p->ubase[1];
+  for (int i = 0; i < 9; ++i) {
+    const double cu = kCx[i] * p->ubase[0] + kCy[i] * p->ubase[1];
+    L.pb[i] = 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * (p->ubase[0] * p->ubase[0] + p->ubase[1] * p->ubase[1]);
+  }
+  // far field m0 = (rho0, 0, 0) until set
+  L.m0[0] = 0.0;
+  L.m0[1] = -p->ubase[0];
+  L.m0[2] = -p->ubase[1];
+  set_scales(L, p->store, 0);
+}
+
+int set_farfield(LatDesc& L, double beta, double rho_ref, double ux_ref, double uy_ref) {
+  if (!(beta >= 0.0 && beta <= 1.0)) return fail(LBM_ERR_ARG, "beta = %g outside [0, 1]", beta);
+  if (!std::isfinite(rho_ref) || !std::isfinite(ux_ref) || !std::isfinite(uy_ref))
+    return fail(LBM_ERR_ARG, "reference vector must be finite");
+  L.beta = beta;
+  L.m0[0] = rho_ref - L.rho0;
+  L.m0[1] = ux_ref - L.ub[0];
+  L.m0[2] = uy_ref - L.ub[1];
+  return LBM_OK;
+}
+
+int f16_exp_from_max(float mx) {
+  int k = mx > 1e-30f ? (int)std::floor(std::log2(4096.0 / (double)mx)) : 12;
+  return std::min(60, std::max(-30, k));
+}
+
+}  // namespace host
+}  // namespace lbm
+
+namespace {
+
+using lbm::host::fail;
+using lbm::host::Layout;
+using lbm::host::layout;
+using lbm::host::check_params;
+using lbm::host::kScratchBytes;
+
+#define HIPCHK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail(LBM_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kOffEnergy = 0;            // energy partials (double)
+constexpr size_t kOffAbsmax = 64 << 10;     // absmax partials (float)
+constexpr size_t kOffFlag = 128 << 10;      // finiteness flag (int)
 
 int default_tile(const lbm_params*) { return 0; }
 
@@ -259,31 +311,7 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* workspace, size_t bytes, 
   c->ws = static_cast<char*>(workspace);
   c->scratch = c->ws + 2 * lay.buf_bytes;
   lbm::LatDesc& L = c->L;
-  std::memset(&L, 0, sizeof(L));
-  L.buf[0] = c->ws;
-  L.buf[1] = c->ws + lay.buf_bytes;
-  L.nx = p->nx;
-  L.ny = p->ny;
-  L.pitch = lay.pitch;
-  L.store = p->store;
-  L.plane = lay.plane;
-  for (int e = 0; e < 4; ++e) L.bc[e] = p->bc[e];
-  L.corr_mode = p->corr_mode;
-  L.grad_order = p->grad_order;
-  L.corner_mode = p->corner_mode;
-  L.omega = 1.0 / p->tau;
-  L.rho0 = p->rho0;
-  L.gamma = p->gamma;
-  L.beta = 0.0;
-  L.ub[0] = p->ubase[0];
-  L.ub[1] = p->ubase[1];
-  for (int i = 0; i < 9; ++i) {
-    const double cu = lbm::kCx[i] * p->ubase[0] + lbm::kCy[i] * p->ubase[1];
-    L.pb[i] = 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * (p->ubase[0] * p->ubase[0] + p->ubase[1] * p->ubase[1]);
-  }
-  L.m0[0] = 0.0;
-  L.m0[1] = -p->ubase[0];
-  L.m0[2] = -p->ubase[1];
+  lbm::host::fill_desc(L, p, lay, c->ws, c->ws + lay.buf_bytes);
   c->tile = default_tile(p);
 
   int k = 0;
@@ -304,14 +332,13 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* workspace, size_t bytes, 
         lbm_destroy(c);
         return fail(LBM_ERR_ARG, "initial fields are not finite");
       }
-      k = mx > 1e-30f ? (int)std::floor(std::log2(4096.0 / (double)mx)) : 12;
-      k = std::min(60, std::max(-30, k));
+      k = lbm::host::f16_exp_from_max(mx);
     } else {
       k = p->f16_exp;
     }
   }
   c->f16_exp = k;
-  set_scales(L, p->store, k);
+  lbm::host::set_scales(L, p->store, k);
 
   hipError_t e = lbm::launch_init(L, 0, drho, ux, uy, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -325,14 +352,7 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* workspace, size_t bytes, 
 
 int lbm_set_farfield(lbm_ctx* c, double beta, double rho_ref, double ux_ref, double uy_ref) {
   if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
-  if (!(beta >= 0.0 && beta <= 1.0)) return fail(LBM_ERR_ARG, "beta = %g outside [0, 1]", beta);
-  if (!std::isfinite(rho_ref) || !std::isfinite(ux_ref) || !std::isfinite(uy_ref))
-    return fail(LBM_ERR_ARG, "reference vector must be finite");
-  c->L.beta = beta;
-  c->L.m0[0] = rho_ref - c->p.rho0;
-  c->L.m0[1] = ux_ref - c->L.ub[0];
-  c->L.m0[2] = uy_ref - c->L.ub[1];
-  return LBM_OK;
+  return lbm::host::set_farfield(c->L, beta, rho_ref, ux_ref, uy_ref);
 }
 
 int lbm_step(lbm_ctx* c, int32_t n) {
@@ -371,7 +391,7 @@ int lbm_time(const lbm_ctx* c, int64_t* t) {
   return LBM_OK;
 }
 
-const char* lbm_last_error(void) { return g_err.c_str(); }
+const char* lbm_last_error(void) { return lbm::host::last_error(); }
 
 void lbm_destroy(lbm_ctx* c) {
   if (!c) return;

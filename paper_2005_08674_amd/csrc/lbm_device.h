@@ -101,6 +101,10 @@ struct LatDesc {
   float es[9];      // encode scale per population
 };
 
+// Buffer `parity` (0 or 1) of a lattice.  A select rather than an indexed
+// access, so a descriptor copied into registers stays in registers.
+__host__ __device__ inline void* buf_of(const LatDesc& L, int parity) { return parity ? L.buf[1] : L.buf[0]; }
+
 // Base state of the deviation form in the arithmetic type.
 template <class R> struct Base {
   R ubx, uby;

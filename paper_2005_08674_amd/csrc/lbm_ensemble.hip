@@ -1,0 +1,493 @@
+// lbm_ensemble.hip -- batched ensemble of independent lattices (include/lbm_ensemble.h).
+//
+// Every member keeps the single-lattice layout (two 9-plane buffers) inside
+// one workspace arena.  A device table lists, for one launch of the bulk
+// kernel, the (member, tile) of every block, and another lists the (member,
+// edge, segment) of every block of the edge kernel, so a whole ensemble step
+// is two launches whatever the member count.  Each block copies its member's
+// descriptor from device memory and runs exactly the per-tile bodies of the
+// single-lattice kernels, so results are bit-identical to lattices run alone.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <utility>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_ensemble.h"
+#include "lbm_device.h"
+#include "lbm_host.h"
+#include "lbm_launch.h"
+#include "lbm_sweep.h"
+
+namespace lbm {
+
+struct EnsTile {
+  int32_t lat, txi, tyi, pad;
+};
+struct EnsSeg {
+  int32_t lat, edge, seg, pad;
+};
+
+template <int S, int BX, int BY, int NYT>
+__global__ __launch_bounds__(BX* BY) void k_ens_bulk(const LatDesc* __restrict__ descs,
+                                                     const EnsTile* __restrict__ tiles, int parity) {
+  const EnsTile t = tiles[blockIdx.x];
+  const LatDesc L = descs[t.lat];
+  bulk_tile_body<S, BX, BY, NYT, true, false>(L, parity, t.txi, t.tyi);
+}
+
+template <int S>
+__global__ __launch_bounds__(EDGE_THREADS) void k_ens_edge(const LatDesc* __restrict__ descs,
+                                                          const EnsSeg* __restrict__ segs, int parity) {
+  __shared__ typename Codec<S>::R mom[3][DEPTH][STRIP];
+  const EnsSeg sg = segs[blockIdx.x];
+  const LatDesc L = descs[sg.lat];
+  edge_segment_body<S>(L, parity, sg.edge, sg.seg, mom);
+}
+
+struct EnsShape {
+  int bx, by, nyt;
+};
+
+#define LBM_ENS_SHAPES(X) \
+  X(64, 4, 1)             \
+  X(128, 2, 1)            \
+  X(256, 1, 1)            \
+  X(64, 4, 2)             \
+  X(128, 2, 2)            \
+  X(64, 8, 1)             \
+  X(64, 4, 4)             \
+  X(128, 2, 4)            \
+  X(256, 1, 4)            \
+  X(64, 8, 2)             \
+  X(32, 8, 2)             \
+  X(128, 4, 2)
+
+static const EnsShape kEnsShapes[] = {
+#define X(a, b, c) {a, b, c},
+    LBM_ENS_SHAPES(X)
+#undef X
+};
+static constexpr int kNumEnsShapes = sizeof(kEnsShapes) / sizeof(kEnsShapes[0]);
+
+template <int S>
+static hipError_t launch_ens_bulk_s(int shape, const LatDesc* d, const EnsTile* t, int n, int parity,
+                                    hipStream_t s) {
+  int id = 0;
+#define X(a, b, c)                                                              \
+  if (shape == id) {                                                            \
+    k_ens_bulk<S, a, b, c><<<dim3(n), dim3(a, b), 0, s>>>(d, t, parity);        \
+    return hipGetLastError();                                                   \
+  }                                                                             \
+  ++id;
+  LBM_ENS_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+static hipError_t launch_ens_bulk(int store, int shape, const LatDesc* d, const EnsTile* t, int n, int parity,
+                                  hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  switch (store) {
+    case ST_F64: return launch_ens_bulk_s<ST_F64>(shape, d, t, n, parity, s);
+    case ST_F32: return launch_ens_bulk_s<ST_F32>(shape, d, t, n, parity, s);
+    case ST_F16: return launch_ens_bulk_s<ST_F16>(shape, d, t, n, parity, s);
+    case ST_BF16: return launch_ens_bulk_s<ST_BF16>(shape, d, t, n, parity, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+static hipError_t launch_ens_edge(int store, const LatDesc* d, const EnsSeg* sg, int n, int parity, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const dim3 grid(n), block(EDGE_THREADS);
+  switch (store) {
+    case ST_F64: k_ens_edge<ST_F64><<<grid, block, 0, s>>>(d, sg, parity); break;
+    case ST_F32: k_ens_edge<ST_F32><<<grid, block, 0, s>>>(d, sg, parity); break;
+    case ST_F16: k_ens_edge<ST_F16><<<grid, block, 0, s>>>(d, sg, parity); break;
+    case ST_BF16: k_ens_edge<ST_BF16><<<grid, block, 0, s>>>(d, sg, parity); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace lbm
+
+namespace {
+
+using lbm::host::fail;
+
+#define HIPCHK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail(LBM_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kAlign = 4096;
+
+struct EnsLayout {
+  size_t off_descs, off_tiles, off_segs, off_scratch, off_lattices, total;
+  size_t max_tiles, nsegs;
+  std::vector<size_t> lat_off;  // member buffers, relative to the workspace
+  std::vector<lbm::host::Layout> lat;
+};
+
+size_t tiles_for(const lbm_params& p, const lbm::EnsShape& s) {
+  const size_t tx = (p.nx + s.bx - 1) / s.bx;
+  const size_t ty = (p.ny - 2 + s.by * s.nyt - 1) / (s.by * s.nyt);
+  return tx * ty;
+}
+
+int ens_layout(const lbm_params* m, int32_t count, EnsLayout& L) {
+  if (!m || count < 1) return fail(LBM_ERR_ARG, "need at least one member");
+  for (int32_t k = 0; k < count; ++k) {
+    int rc = lbm::host::check_params(&m[k]);
+    if (rc) return fail(rc, "member %d: %s", k, lbm::host::last_error());
+    if (m[k].store != m[0].store) return fail(LBM_ERR_ARG, "member %d: all members must share one store", k);
+  }
+  using lbm::host::round_up;
+  L.max_tiles = 0;
+  L.nsegs = 0;
+  for (int s = 0; s < lbm::kNumEnsShapes; ++s) {
+    size_t n = 0;
+    for (int32_t k = 0; k < count; ++k) n += tiles_for(m[k], lbm::kEnsShapes[s]);
+    L.max_tiles = std::max(L.max_tiles, n);
+  }
+  for (int32_t k = 0; k < count; ++k) L.nsegs += lbm::edge_blocks(m[k].nx, m[k].ny);
+  if (L.max_tiles > (size_t)INT32_MAX || L.nsegs > (size_t)INT32_MAX) return fail(LBM_ERR_ARG, "ensemble too large");
+  size_t off = 0;
+  L.off_descs = off;
+  off = round_up(off + sizeof(lbm::LatDesc) * count, kAlign);
+  L.off_tiles = off;
+  off = round_up(off + sizeof(lbm::EnsTile) * L.max_tiles, kAlign);
+  L.off_segs = off;
+  off = round_up(off + sizeof(lbm::EnsSeg) * L.nsegs, kAlign);
+  L.off_scratch = off;
+  off = round_up(off + lbm::host::kScratchBytes, (size_t)2 << 20);
+  L.off_lattices = off;
+  L.lat.resize(count);
+  L.lat_off.resize(count);
+  for (int32_t k = 0; k < count; ++k) {
+    L.lat[k] = lbm::host::layout(&m[k]);
+    L.lat_off[k] = off;
+    off += 2 * L.lat[k].buf_bytes;
+  }
+  L.total = off;
+  return LBM_OK;
+}
+
+}  // namespace
+
+struct lbm_ens {
+  int32_t count = 0;
+  int store = 0;
+  std::vector<lbm_params> p;
+  std::vector<lbm::LatDesc> descs;
+  EnsLayout lay;
+  char* ws = nullptr;
+  lbm::LatDesc* d_descs = nullptr;
+  lbm::EnsTile* d_tiles = nullptr;
+  lbm::EnsSeg* d_segs = nullptr;
+  int32_t ntiles = 0, nsegs = 0;
+  int shape = 0;
+  int parity = 0;
+  int64_t t = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;  // private stream used for graph capture
+  std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+};
+
+namespace {
+
+void drop_graphs(lbm_ens* e) {
+  for (auto& kv : e->graphs) (void)hipGraphExecDestroy(kv.second);
+  e->graphs.clear();
+}
+
+int upload_descs(lbm_ens* e) {
+  HIPCHK(hipMemcpyAsync(e->d_descs, e->descs.data(), sizeof(lbm::LatDesc) * e->count, hipMemcpyHostToDevice,
+                        e->stream));
+  HIPCHK(hipStreamSynchronize(e->stream));
+  return LBM_OK;
+}
+
+int build_tiles(lbm_ens* e, int shape) {
+  const lbm::EnsShape& s = lbm::kEnsShapes[shape];
+  std::vector<lbm::EnsTile> tiles;
+  for (int32_t k = 0; k < e->count; ++k) {
+    const int tx = (e->p[k].nx + s.bx - 1) / s.bx;
+    const int ty = (e->p[k].ny - 2 + s.by * s.nyt - 1) / (s.by * s.nyt);
+    for (int j = 0; j < ty; ++j)
+      for (int i = 0; i < tx; ++i) tiles.push_back({k, i, j, 0});
+  }
+  if (tiles.size() > e->lay.max_tiles) return fail(LBM_ERR_STATE, "tile table overflow");
+  HIPCHK(hipMemcpyAsync(e->d_tiles, tiles.data(), sizeof(lbm::EnsTile) * tiles.size(), hipMemcpyHostToDevice,
+                        e->stream));
+  HIPCHK(hipStreamSynchronize(e->stream));
+  e->ntiles = (int32_t)tiles.size();
+  e->shape = shape;
+  drop_graphs(e);
+  return LBM_OK;
+}
+
+int ens_launch_step(lbm_ens* e, int parity, hipStream_t s) {
+  HIPCHK(lbm::launch_ens_bulk(e->store, e->shape, e->d_descs, e->d_tiles, e->ntiles, parity, s));
+  HIPCHK(lbm::launch_ens_edge(e->store, e->d_descs, e->d_segs, e->nsegs, parity, s));
+  return LBM_OK;
+}
+
+int check_member(const lbm_ens* e, int32_t m) {
+  if (!e) return fail(LBM_ERR_ARG, "ensemble is NULL");
+  if (m < 0 || m >= e->count) return fail(LBM_ERR_ARG, "member %d out of range [0, %d)", m, e->count);
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_ens_workspace_bytes(const lbm_params* members, int32_t count, size_t* bytes) {
+  if (!bytes) return fail(LBM_ERR_ARG, "bytes is NULL");
+  EnsLayout L;
+  int rc = ens_layout(members, count, L);
+  if (rc) return rc;
+  *bytes = L.total;
+  return LBM_OK;
+}
+
+void lbm_ens_destroy(lbm_ens* e) {
+  if (!e) return;
+  (void)hipStreamSynchronize(e->stream);
+  drop_graphs(e);
+  if (e->cap) (void)hipStreamDestroy(e->cap);
+  delete e;
+}
+
+int lbm_ens_init(lbm_ens** out, const lbm_params* members, int32_t count, void* workspace, size_t bytes,
+                 const double* drho, const double* ux, const double* uy, void* hip_stream) {
+  if (!out) return fail(LBM_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  EnsLayout lay;
+  int rc = ens_layout(members, count, lay);
+  if (rc) return rc;
+  if (!workspace || ((uintptr_t)workspace & 255)) return fail(LBM_ERR_ARG, "workspace NULL or not 256-byte aligned");
+  if (bytes < lay.total) return fail(LBM_ERR_ARG, "workspace of %zu bytes < %zu required", bytes, lay.total);
+  if (!drho || !ux || !uy) return fail(LBM_ERR_ARG, "initial fields must not be NULL");
+
+  lbm_ens* e = new lbm_ens();
+  e->count = count;
+  e->store = members[0].store;
+  e->p.assign(members, members + count);
+  e->lay = lay;
+  e->ws = static_cast<char*>(workspace);
+  e->stream = static_cast<hipStream_t>(hip_stream);
+  e->d_descs = reinterpret_cast<lbm::LatDesc*>(e->ws + lay.off_descs);
+  e->d_tiles = reinterpret_cast<lbm::EnsTile*>(e->ws + lay.off_tiles);
+  e->d_segs = reinterpret_cast<lbm::EnsSeg*>(e->ws + lay.off_segs);
+  if (hipStreamCreateWithFlags(&e->cap, hipStreamNonBlocking) != hipSuccess) {
+    lbm_ens_destroy(e);
+    return fail(LBM_ERR_HIP, "capture stream creation failed");
+  }
+  e->descs.resize(count);
+  float* part = reinterpret_cast<float*>(e->ws + lay.off_scratch);
+  std::vector<float> host(lbm::absmax_blocks());
+  size_t foff = 0;
+  for (int32_t k = 0; k < count; ++k) {
+    const lbm_params& p = members[k];
+    char* base = e->ws + lay.lat_off[k];
+    lbm::host::fill_desc(e->descs[k], &p, lay.lat[k], base, base + lay.lat[k].buf_bytes);
+    int kexp = 0;
+    if (p.store == LBM_STORE_F16DEV) {
+      if (p.f16_exp == LBM_F16_EXP_AUTO) {
+        hipError_t he = lbm::launch_absmax_init(e->descs[k], drho + foff, ux + foff, uy + foff, part, e->stream);
+        if (he == hipSuccess)
+          he = hipMemcpyAsync(host.data(), part, host.size() * sizeof(float), hipMemcpyDeviceToHost, e->stream);
+        if (he == hipSuccess) he = hipStreamSynchronize(e->stream);
+        if (he != hipSuccess) {
+          lbm_ens_destroy(e);
+          return fail(LBM_ERR_HIP, "member %d f16 exponent: %s", k, hipGetErrorString(he));
+        }
+        float mx = 0.f;
+        for (float v : host) mx = std::max(mx, v);
+        kexp = lbm::host::f16_exp_from_max(mx);
+      } else {
+        kexp = p.f16_exp;
+      }
+    }
+    lbm::host::set_scales(e->descs[k], p.store, kexp);
+    hipError_t he = lbm::launch_init(e->descs[k], 0, drho + foff, ux + foff, uy + foff, e->stream);
+    if (he != hipSuccess) {
+      lbm_ens_destroy(e);
+      return fail(LBM_ERR_HIP, "member %d init: %s", k, hipGetErrorString(he));
+    }
+    foff += (size_t)p.nx * p.ny;
+  }
+  std::vector<lbm::EnsSeg> segs;
+  for (int32_t k = 0; k < count; ++k) {
+    const int nb = lbm::edge_blocks(members[k].nx, members[k].ny);
+    for (int b = 0; b < nb; ++b) {
+      int bb = b, edge = 0;
+      lbm::edge_of_block(members[k].nx, members[k].ny, bb, edge);
+      segs.push_back({k, edge, bb, 0});
+    }
+  }
+  e->nsegs = (int32_t)segs.size();
+  hipError_t he = hipMemcpyAsync(e->d_segs, segs.data(), sizeof(lbm::EnsSeg) * segs.size(), hipMemcpyHostToDevice,
+                                 e->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(e->stream);
+  if (he != hipSuccess) {
+    lbm_ens_destroy(e);
+    return fail(LBM_ERR_HIP, "segment table: %s", hipGetErrorString(he));
+  }
+  if ((rc = upload_descs(e)) || (rc = build_tiles(e, 0))) {
+    lbm_ens_destroy(e);
+    return rc;
+  }
+  *out = e;
+  return LBM_OK;
+}
+
+int lbm_ens_set_farfield(lbm_ens* e, int32_t member, double beta, double rho_ref, double ux_ref, double uy_ref) {
+  int rc = check_member(e, member);
+  if (rc) return rc;
+  lbm::LatDesc L = e->descs[member];
+  rc = lbm::host::set_farfield(L, beta, rho_ref, ux_ref, uy_ref);
+  if (rc) return rc;
+  e->descs[member] = L;
+  return upload_descs(e);
+}
+
+int lbm_ens_step(lbm_ens* e, int32_t n) {
+  if (!e) return fail(LBM_ERR_ARG, "ensemble is NULL");
+  if (n < 0) return fail(LBM_ERR_ARG, "n = %d < 0", n);
+  for (int32_t s = 0; s < n; ++s) {
+    int rc = ens_launch_step(e, e->parity, e->stream);
+    if (rc) return rc;
+    e->parity ^= 1;
+    e->t += 1;
+  }
+  return LBM_OK;
+}
+
+int lbm_ens_step_graph(lbm_ens* e, int32_t n) {
+  if (!e) return fail(LBM_ERR_ARG, "ensemble is NULL");
+  if (n < 1 || n > 100000) return fail(LBM_ERR_ARG, "n = %d outside [1, 100000]", n);
+  const std::pair<int, int> key(n, e->parity);
+  auto it = e->graphs.find(key);
+  if (it == e->graphs.end()) {
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(e->cap, hipStreamCaptureModeThreadLocal));
+    int rc = LBM_OK;
+    for (int32_t s = 0; s < n && rc == LBM_OK; ++s) rc = ens_launch_step(e, e->parity ^ (s & 1), e->cap);
+    hipError_t he = hipStreamEndCapture(e->cap, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (he != hipSuccess) return fail(LBM_ERR_HIP, "graph capture: %s", hipGetErrorString(he));
+    hipGraphExec_t x = nullptr;
+    he = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (he != hipSuccess) return fail(LBM_ERR_HIP, "graph instantiate: %s", hipGetErrorString(he));
+    it = e->graphs.emplace(key, x).first;
+  }
+  HIPCHK(hipGraphLaunch(it->second, e->stream));
+  e->parity ^= (n & 1);
+  e->t += n;
+  return LBM_OK;
+}
+
+int lbm_ens_moments(lbm_ens* e, int32_t member, void* r, void* u, void* v, int out_f64, int deviation) {
+  int rc = check_member(e, member);
+  if (rc) return rc;
+  HIPCHK(lbm::launch_moments(e->descs[member], e->parity, r, u, v, out_f64 ? 1 : 0, deviation ? 1 : 0, e->stream));
+  return LBM_OK;
+}
+
+int lbm_ens_get_populations(lbm_ens* e, int32_t member, double* g_out) {
+  int rc = check_member(e, member);
+  if (rc) return rc;
+  if (!g_out) return fail(LBM_ERR_ARG, "g_out is NULL");
+  HIPCHK(lbm::launch_get_pops(e->descs[member], e->parity, g_out, e->stream));
+  return LBM_OK;
+}
+
+int lbm_ens_time(const lbm_ens* e, int64_t* t) {
+  if (!e || !t) return fail(LBM_ERR_ARG, "NULL argument");
+  *t = e->t;
+  return LBM_OK;
+}
+
+int lbm_ens_info(const lbm_ens* e, int64_t* nodes, int32_t* bulk_blocks, int32_t* edge_blocks) {
+  if (!e) return fail(LBM_ERR_ARG, "ensemble is NULL");
+  if (nodes) {
+    int64_t n = 0;
+    for (const auto& p : e->p) n += (int64_t)p.nx * p.ny;
+    *nodes = n;
+  }
+  if (bulk_blocks) *bulk_blocks = e->ntiles;
+  if (edge_blocks) *edge_blocks = e->nsegs;
+  return LBM_OK;
+}
+
+int lbm_ens_shape_count(void) { return lbm::kNumEnsShapes; }
+
+int lbm_ens_shape_describe(int32_t id, char* buf, size_t len) {
+  if (!buf || len == 0) return fail(LBM_ERR_ARG, "NULL buffer");
+  if (id < 0 || id >= lbm::kNumEnsShapes) return fail(LBM_ERR_ARG, "shape id %d out of range", id);
+  const lbm::EnsShape& s = lbm::kEnsShapes[id];
+  snprintf(buf, len, "%dx%dx%d", s.bx, s.by, s.nyt);
+  return LBM_OK;
+}
+
+int lbm_ens_set_shape(lbm_ens* e, int32_t id) {
+  if (!e) return fail(LBM_ERR_ARG, "ensemble is NULL");
+  if (id < 0 || id >= lbm::kNumEnsShapes) return fail(LBM_ERR_ARG, "shape id %d out of range", id);
+  return build_tiles(e, id);
+}
+
+int lbm_ens_autotune(lbm_ens* e, int32_t reps, int32_t* best, float* times_ms) {
+  if (!e || !best) return fail(LBM_ERR_ARG, "NULL argument");
+  if (reps < 1 || reps > 1000) return fail(LBM_ERR_ARG, "reps = %d outside [1, 1000]", reps);
+  std::vector<hipEvent_t> ev(2 * reps);
+  for (auto& x : ev) HIPCHK(hipEventCreate(&x));
+  float best_t = 1e30f;
+  int best_id = e->shape;
+  int rc = LBM_OK;
+  for (int id = 0; id < lbm::kNumEnsShapes && rc == LBM_OK; ++id) {
+    rc = build_tiles(e, id);
+    if (rc) break;
+    // the bulk kernel reads buffer `parity` and writes only the other one
+    hipError_t he =
+        lbm::launch_ens_bulk(e->store, id, e->d_descs, e->d_tiles, e->ntiles, e->parity, e->stream);
+    for (int r = 0; r < reps && he == hipSuccess; ++r) {
+      he = hipEventRecord(ev[2 * r], e->stream);
+      if (he == hipSuccess)
+        he = lbm::launch_ens_bulk(e->store, id, e->d_descs, e->d_tiles, e->ntiles, e->parity, e->stream);
+      if (he == hipSuccess) he = hipEventRecord(ev[2 * r + 1], e->stream);
+    }
+    if (he == hipSuccess) he = hipStreamSynchronize(e->stream);
+    std::vector<float> ts(reps);
+    for (int r = 0; r < reps && he == hipSuccess; ++r) he = hipEventElapsedTime(&ts[r], ev[2 * r], ev[2 * r + 1]);
+    if (he != hipSuccess) {
+      rc = fail(LBM_ERR_HIP, "ensemble autotune shape %d: %s", id, hipGetErrorString(he));
+      break;
+    }
+    std::sort(ts.begin(), ts.end());
+    if (times_ms) times_ms[id] = ts[reps / 2];
+    if (ts[reps / 2] < best_t) {
+      best_t = ts[reps / 2];
+      best_id = id;
+    }
+  }
+  for (auto& x : ev) (void)hipEventDestroy(x);
+  if (rc) return rc;
+  rc = build_tiles(e, best_id);
+  if (rc) return rc;
+  *best = best_id;
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,42 @@
+// lbm_host.h -- host-side helpers shared by the single-lattice and the
+// ensemble C-ABI implementations: error reporting, parameter checks, the
+// workspace layout and the lattice descriptor.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "lbm.h"
+#include "lbm_device.h"
+
+namespace lbm {
+namespace host {
+
+constexpr size_t kScratchBytes = 1 << 20;
+
+// Record a formatted message for lbm_last_error() and return `code`.
+int fail(int code, const char* fmt, ...);
+const char* last_error();
+
+size_t round_up(size_t v, size_t a);
+size_t elem_bytes(int store);
+
+// Population buffers of one lattice: pitch (elements per row, rows of 256
+// bytes), plane (elements per population plane), one buffer = 9 planes.
+struct Layout {
+  size_t esize;
+  int32_t pitch;
+  int64_t plane;
+  size_t buf_bytes;
+  size_t total;  // two buffers + scratch
+};
+
+Layout layout(const lbm_params* p);
+int check_params(const lbm_params* p);
+void set_scales(LatDesc& L, int store, int k);
+void fill_desc(LatDesc& L, const lbm_params* p, const Layout& lay, void* buf0, void* buf1);
+int set_farfield(LatDesc& L, double beta, double rho_ref, double ux_ref, double uy_ref);
+int f16_exp_from_max(float mx);
+
+}  // namespace host
+}  // namespace lbm

@@ -22,27 +22,11 @@
 
 #include "lbm_device.h"
 #include "lbm_launch.h"
+#include "lbm_sweep.h"
 
 namespace lbm {
 
 // ------------------------------------------------------------------ bulk kernel
-// Store of one population; NTS selects a non-temporal store (the written
-// buffer is not read again before the next step streams it back in, so it
-// should not displace the lines the shifted loads share).
-template <bool NTS, class T>
-__device__ inline void put(T* p, T v) {
-  if (NTS) __builtin_nontemporal_store(v, p);
-  else *p = v;
-}
-
-// Load of one population; NTL selects a non-temporal load, used only for the
-// populations with c_x = 0, whose cache lines no other wavefront reads.
-template <class T>
-__device__ inline T get(const T* p, bool nt) {
-  if (nt) return __builtin_nontemporal_load(p);
-  return *p;
-}
-
 // Block -> tile maps.  Workgroups are dispatched to the 8 XCDs round-robin
 // (workgroup b runs on XCD b mod 8), and each XCD has its own L2.
 //   REMAP 0: tile = b (row-major tiles, consecutive tiles on different XCDs).
@@ -75,43 +59,9 @@ __device__ inline bool bulk_tile(int tiles_x, int tiles_y, int& txi, int& tyi) {
 
 template <int S, int BX, int BY, int NYT, int REMAP, bool NTS, bool NTL>
 __global__ __launch_bounds__(BX* BY) void k_bulk(LatDesc L, int parity, int tiles_x, int tiles_y) {
-  using C = Codec<S>;
-  using T = typename C::T;
-  using R = typename C::R;
   int txi, tyi;
   if (!bulk_tile<REMAP>(tiles_x, tiles_y, txi, tyi)) return;
-  const int x = txi * BX + threadIdx.x;
-  if (x < 1 || x > L.nx - 2) return;
-  const int y0 = 1 + tyi * (BY * NYT) + threadIdx.y;
-  const int pitch = L.pitch;
-  const T* __restrict__ A = static_cast<const T*>(L.buf[parity]);
-  T* __restrict__ B = static_cast<T*>(L.buf[parity ^ 1]);
-  const int64_t plane = L.plane;
-  const R rho0 = R(L.rho0), omega = R(L.omega);
-  const Base<R> base(L);
-
-  R g[NYT][9];
-#pragma unroll
-  for (int j = 0; j < NYT; ++j) {
-    const int y = y0 + j * BY;
-    if (y <= L.ny - 2) {
-#pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        const int idx = (y - kCy[i]) * pitch + (x - kCx[i]);
-        g[j][i] = C::dec(get(A + i * plane + idx, NTL && kCx[i] == 0), L.ds[i]);
-      }
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < NYT; ++j) {
-    const int y = y0 + j * BY;
-    if (y <= L.ny - 2) {
-      bgk<R>(g[j], rho0, base, omega);
-      const int idx = y * pitch + x;
-#pragma unroll
-      for (int i = 0; i < 9; ++i) put<NTS>(B + i * plane + idx, C::enc(g[j][i], L.es[i]));
-    }
-  }
+  bulk_tile_body<S, BX, BY, NYT, NTS, NTL>(L, parity, txi, tyi);
 }
 
 struct TileShape {
@@ -204,164 +154,12 @@ hipError_t launch_bulk(const LatDesc& L, int parity, int tile, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ edge kernel
-constexpr int SEG = 64;    // boundary nodes per block (one wavefront)
-constexpr int HALO = 2;    // tangential halo of the staged strip
-constexpr int DEPTH = 3;   // staged depths 0..2 along the inward normal
-constexpr int STRIP = SEG + 2 * HALO;
-
-__host__ __device__ inline int edge_segments_v(int ny) { return (ny + SEG - 1) / SEG; }
-__host__ __device__ inline int edge_segments_h(int nx) { return (nx - 2 + SEG - 1) / SEG; }
-
-// Node of edge `edge` at depth d (along the inward normal) and tangential
-// coordinate t (y for left/right, x for bottom/top).
-__device__ inline void edge_node(const LatDesc& L, int edge, int d, int t, int& x, int& y) {
-  switch (edge) {
-    case E_LEFT: x = d; y = t; break;
-    case E_RIGHT: x = L.nx - 1 - d; y = t; break;
-    case E_BOTTOM: x = t; y = d; break;
-    default: x = t; y = L.ny - 1 - d; break;
-  }
-}
-
-template <class R>
-__device__ inline R normal_diff(R mb, R m1, R m2, int order) {
-  return order == 1 ? mb - m1 : (R(3) * mb - R(4) * m1 + m2) * R(0.5);
-}
-
-constexpr int EDGE_THREADS = 256;  // >= DEPTH * STRIP: one staged strip node per thread
-static_assert(EDGE_THREADS >= DEPTH * STRIP, "edge block must cover the staged strip");
-
 template <int S>
 __global__ __launch_bounds__(EDGE_THREADS) void k_edge(LatDesc L, int parity) {
-  using C = Codec<S>;
-  using T = typename C::T;
-  using R = typename C::R;
-  __shared__ R mom[3][DEPTH][STRIP];
-
-  const int nx = L.nx, ny = L.ny;
-  const int nsv = edge_segments_v(ny), nsh = edge_segments_h(nx);
+  __shared__ typename Codec<S>::R mom[3][DEPTH][STRIP];
   int b = blockIdx.x, edge;
-  if (b < nsv) {
-    edge = E_LEFT;
-  } else if (b < 2 * nsv) {
-    edge = E_RIGHT;
-    b -= nsv;
-  } else if (b < 2 * nsv + nsh) {
-    edge = E_BOTTOM;
-    b -= 2 * nsv;
-  } else {
-    edge = E_TOP;
-    b -= 2 * nsv + nsh;
-  }
-  const bool vertical = edge == E_LEFT || edge == E_RIGHT;
-  const int ntan = vertical ? ny : nx;
-  const int t0 = vertical ? b * SEG : 1 + b * SEG;
-  const int tend = vertical ? ny : nx - 1;
-  const bool xper = L.bc[E_LEFT] == BC_PERIODIC;
-  const bool yper = L.bc[E_BOTTOM] == BC_PERIODIC;
-  const bool tan_per = vertical ? yper : xper;
-  const bool any_nsbc = !(xper && yper);
-
-  const T* __restrict__ A = static_cast<const T*>(L.buf[parity]);
-  T* __restrict__ B = static_cast<T*>(L.buf[parity ^ 1]);
-  const int pitch = L.pitch;
-  const int64_t plane = L.plane;
-  const R rho0 = R(L.rho0);
-  const Base<R> base(L);
-  const int tid = threadIdx.x;
-
-  // Lanes 0..SEG-1 own one boundary node each: pull its known populations
-  // (wrapping across periodic edges) and mark those whose source lies
-  // outside the domain.  Issued before the strip staging so both sets of
-  // loads are in flight together.
-  const int t = t0 + tid;
-  const bool owner = tid < SEG && t < tend;
-  int x = 0, y = 0;
-  R g[9];
-  uint32_t unknown = 0;
-  if (owner) {
-    edge_node(L, edge, 0, t, x, y);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      int sx = x - kCx[i], sy = y - kCy[i];
-      const bool outx = sx < 0 || sx >= nx;
-      const bool outy = sy < 0 || sy >= ny;
-      if ((outx && !xper) || (outy && !yper)) {
-        unknown |= 1u << i;
-        g[i] = R(0);
-      } else {
-        if (outx) sx = sx < 0 ? sx + nx : sx - nx;
-        if (outy) sy = sy < 0 ? sy + ny : sy - ny;
-        g[i] = C::dec(A[i * plane + (sy * pitch + sx)], L.ds[i]);
-      }
-    }
-  }
-
-  // Stage the time-t moments of the strip (depth 0..2, tangential halo 2),
-  // one strip node per thread.
-  if (any_nsbc && tid < DEPTH * STRIP) {
-    const int d = tid / STRIP, tt = tid - d * STRIP;
-    int ts = t0 - HALO + tt;
-    bool inside = true;
-    if (ts < 0 || ts >= ntan) {
-      if (tan_per) ts = ts < 0 ? ts + ntan : ts - ntan;
-      else inside = false;
-    }
-    R m[3] = {R(0), R(0), R(0)};
-    if (inside) {
-      int sx, sy;
-      edge_node(L, edge, d, ts, sx, sy);
-      R gs[9];
-      const int idx = sy * pitch + sx;
-#pragma unroll
-      for (int i = 0; i < 9; ++i) gs[i] = C::dec(A[i * plane + idx], L.ds[i]);
-      moments<R>(gs, rho0, base, m[0], m[1], m[2]);
-    }
-    mom[0][d][tt] = m[0];
-    mom[1][d][tt] = m[1];
-    mom[2][d][tt] = m[2];
-  }
-  __syncthreads();
-  if (!owner) return;
-
-  const bool onL = x == 0 && L.bc[E_LEFT] == BC_NSBC;
-  const bool onR = x == nx - 1 && L.bc[E_RIGHT] == BC_NSBC;
-  const bool onB = y == 0 && L.bc[E_BOTTOM] == BC_NSBC;
-  const bool onT = y == ny - 1 && L.bc[E_TOP] == BC_NSBC;
-  if (onL || onR || onB || onT) {
-    const int tt = tid + HALO;
-    const bool own = (edge == E_LEFT && onL) || (edge == E_RIGHT && onR) || (edge == E_BOTTOM && onB) ||
-                     (edge == E_TOP && onT);
-    int nn = 0;
-    R dsum[3] = {R(0), R(0), R(0)};
-    // eq. nes_2: outward normal derivative by a one-sided difference, time t
-    if (own) {
-      ++nn;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) dsum[c] += normal_diff(mom[c][0][tt], mom[c][1][tt], mom[c][2][tt], L.grad_order);
-    }
-    if (vertical && (onB || onT)) {  // corner node: second normal runs along this strip
-      const int sgn = onB ? 1 : -1;
-      ++nn;
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-        dsum[c] += normal_diff(mom[c][0][tt], mom[c][0][tt + sgn], mom[c][0][tt + 2 * sgn], L.grad_order);
-    }
-    R fac = R(L.gamma);
-    if (nn == 2) fac *= L.corner_mode == 0 ? R(0.70710678118654752440) : R(0.5);
-    const R beta = R(L.beta);
-    M3<R> mc;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const R mp = mom[c][0][tt] - fac * dsum[c];
-      mc.v[c] = (R(1) - beta) * mp + beta * R(L.m0[c]);  // eq. nes_3
-    }
-    nsbc_assign_correct<R>(g, unknown, mc, rho0, base, L.corr_mode);
-  }
-  bgk<R>(g, rho0, base, R(L.omega));
-  const int idx = y * pitch + x;
-#pragma unroll
-  for (int i = 0; i < 9; ++i) put<true>(B + i * plane + idx, C::enc(g[i], L.es[i]));
+  edge_of_block(L.nx, L.ny, b, edge);
+  edge_segment_body<S>(L, parity, edge, b, mom);
 }
 
 int edge_blocks(int nx, int ny) { return 2 * edge_segments_v(ny) + 2 * edge_segments_h(nx); }
@@ -392,7 +190,7 @@ __global__ void k_init(LatDesc L, int parity, const double* __restrict__ drho, c
   double geq[9];
   const Base<double> base(L);
   equilibrium<double>(L.rho0, base, drho[k], ux[k] - L.ub[0], uy[k] - L.ub[1], geq);
-  T* B = static_cast<T*>(L.buf[parity]);
+  T* B = static_cast<T*>(buf_of(L, parity));
   const int idx = y * L.pitch + x;
   // scale in fp64 (the encode scales are exact powers of two over w_i), then
   // round once to the stored type
@@ -428,25 +226,25 @@ __device__ inline void load_node_f64(const LatDesc& L, int parity, int x, int y,
   const int idx = y * L.pitch + x;
   switch (L.store) {
     case ST_F64: {
-      const double* A = static_cast<const double*>(L.buf[parity]);
+      const double* A = static_cast<const double*>(buf_of(L, parity));
 #pragma unroll
       for (int i = 0; i < 9; ++i) g[i] = A[i * L.plane + idx];
       break;
     }
     case ST_F32: {
-      const float* A = static_cast<const float*>(L.buf[parity]);
+      const float* A = static_cast<const float*>(buf_of(L, parity));
 #pragma unroll
       for (int i = 0; i < 9; ++i) g[i] = A[i * L.plane + idx];
       break;
     }
     case ST_F16: {
-      const _Float16* A = static_cast<const _Float16*>(L.buf[parity]);
+      const _Float16* A = static_cast<const _Float16*>(buf_of(L, parity));
 #pragma unroll
       for (int i = 0; i < 9; ++i) g[i] = (double)Codec<ST_F16>::dec(A[i * L.plane + idx], L.ds[i]);
       break;
     }
     default: {
-      const uint16_t* A = static_cast<const uint16_t*>(L.buf[parity]);
+      const uint16_t* A = static_cast<const uint16_t*>(buf_of(L, parity));
 #pragma unroll
       for (int i = 0; i < 9; ++i) g[i] = (double)Codec<ST_BF16>::dec(A[i * L.plane + idx], L.ds[i]);
       break;
@@ -504,7 +302,7 @@ __global__ void k_set_pops(LatDesc L, int parity, const double* __restrict__ in)
   const int y = blockIdx.y;
   if (x >= L.nx) return;
   const int64_t n = (int64_t)L.nx * L.ny, k = (int64_t)y * L.nx + x;
-  T* B = static_cast<T*>(L.buf[parity]);
+  T* B = static_cast<T*>(buf_of(L, parity));
   const int idx = y * L.pitch + x;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {

@@ -1,0 +1,234 @@
+// lbm_sweep.h -- the per-tile bodies of the two sweep kernels, shared by
+// the single-lattice kernels (lbm_kernels.hip) and the ensemble kernels
+// (lbm_ensemble.hip): the bulk collide-stream tile and the NSBC edge segment.
+#pragma once
+
+#include "lbm_device.h"
+
+namespace lbm {
+
+// Store of one population; NTS selects a non-temporal store (the written
+// buffer is not read again before the next step streams it back in, so it
+// should not displace the lines the shifted loads share).
+template <bool NTS, class T>
+__device__ inline void put(T* p, T v) {
+  if (NTS) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+// Load of one population; NTL selects a non-temporal load, used only for the
+// populations with c_x = 0, whose cache lines no other wavefront reads.
+template <class T>
+__device__ inline T get(const T* p, bool nt) {
+  if (nt) return __builtin_nontemporal_load(p);
+  return *p;
+}
+
+// One bulk tile: BX x (BY * NYT) interior nodes starting at tile (txi, tyi)
+// of lattice L -- pull, BGK, store (eqs. lbe_0, lbe_1, feq_1).
+template <int S, int BX, int BY, int NYT, bool NTS, bool NTL>
+__device__ inline void bulk_tile_body(const LatDesc& L, int parity, int txi, int tyi) {
+  using C = Codec<S>;
+  using T = typename C::T;
+  using R = typename C::R;
+  const int x = txi * BX + threadIdx.x;
+  if (x < 1 || x > L.nx - 2) return;
+  const int y0 = 1 + tyi * (BY * NYT) + threadIdx.y;
+  const int pitch = L.pitch;
+  const T* __restrict__ A = static_cast<const T*>(buf_of(L, parity));
+  T* __restrict__ B = static_cast<T*>(buf_of(L, parity ^ 1));
+  const int64_t plane = L.plane;
+  const R rho0 = R(L.rho0), omega = R(L.omega);
+  const Base<R> base(L);
+
+  R g[NYT][9];
+#pragma unroll
+  for (int j = 0; j < NYT; ++j) {
+    const int y = y0 + j * BY;
+    if (y <= L.ny - 2) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        const int idx = (y - kCy[i]) * pitch + (x - kCx[i]);
+        g[j][i] = C::dec(get(A + i * plane + idx, NTL && kCx[i] == 0), L.ds[i]);
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NYT; ++j) {
+    const int y = y0 + j * BY;
+    if (y <= L.ny - 2) {
+      bgk<R>(g[j], rho0, base, omega);
+      const int idx = y * pitch + x;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) put<NTS>(B + i * plane + idx, C::enc(g[j][i], L.es[i]));
+    }
+  }
+}
+
+constexpr int SEG = 64;    // boundary nodes per block (one wavefront)
+constexpr int HALO = 2;    // tangential halo of the staged strip
+constexpr int DEPTH = 3;   // staged depths 0..2 along the inward normal
+constexpr int STRIP = SEG + 2 * HALO;
+
+__host__ __device__ inline int edge_segments_v(int ny) { return (ny + SEG - 1) / SEG; }
+__host__ __device__ inline int edge_segments_h(int nx) { return (nx - 2 + SEG - 1) / SEG; }
+
+// Node of edge `edge` at depth d (along the inward normal) and tangential
+// coordinate t (y for left/right, x for bottom/top).
+__device__ inline void edge_node(const LatDesc& L, int edge, int d, int t, int& x, int& y) {
+  switch (edge) {
+    case E_LEFT: x = d; y = t; break;
+    case E_RIGHT: x = L.nx - 1 - d; y = t; break;
+    case E_BOTTOM: x = t; y = d; break;
+    default: x = t; y = L.ny - 1 - d; break;
+  }
+}
+
+template <class R>
+__device__ inline R normal_diff(R mb, R m1, R m2, int order) {
+  return order == 1 ? mb - m1 : (R(3) * mb - R(4) * m1 + m2) * R(0.5);
+}
+
+constexpr int EDGE_THREADS = 256;  // >= DEPTH * STRIP: one staged strip node per thread
+static_assert(EDGE_THREADS >= DEPTH * STRIP, "edge block must cover the staged strip");
+
+// Block index -> (edge, segment) of a lattice: left segments first, then
+// right, bottom, top.  Left/right segments cover y = 0..ny-1 (corners
+// included), bottom/top segments cover x = 1..nx-2.
+__host__ __device__ inline void edge_of_block(int nx, int ny, int& b, int& edge) {
+  const int nsv = edge_segments_v(ny), nsh = edge_segments_h(nx);
+  if (b < nsv) {
+    edge = E_LEFT;
+  } else if (b < 2 * nsv) {
+    edge = E_RIGHT;
+    b -= nsv;
+  } else if (b < 2 * nsv + nsh) {
+    edge = E_BOTTOM;
+    b -= 2 * nsv;
+  } else {
+    edge = E_TOP;
+    b -= 2 * nsv + nsh;
+  }
+}
+
+// One 64-node segment `b` of edge `edge` of lattice L, computed by a block of
+// EDGE_THREADS threads: lanes 0..SEG-1 own one boundary node each.
+template <int S>
+__device__ inline void edge_segment_body(const LatDesc& L, int parity, int edge, int b,
+                                         typename Codec<S>::R (&mom)[3][DEPTH][STRIP]) {
+  using C = Codec<S>;
+  using T = typename C::T;
+  using R = typename C::R;
+  const int nx = L.nx, ny = L.ny;
+  const bool vertical = edge == E_LEFT || edge == E_RIGHT;
+  const int ntan = vertical ? ny : nx;
+  const int t0 = vertical ? b * SEG : 1 + b * SEG;
+  const int tend = vertical ? ny : nx - 1;
+  const bool xper = L.bc[E_LEFT] == BC_PERIODIC;
+  const bool yper = L.bc[E_BOTTOM] == BC_PERIODIC;
+  const bool tan_per = vertical ? yper : xper;
+  const bool any_nsbc = !(xper && yper);
+
+  const T* __restrict__ A = static_cast<const T*>(buf_of(L, parity));
+  T* __restrict__ B = static_cast<T*>(buf_of(L, parity ^ 1));
+  const int pitch = L.pitch;
+  const int64_t plane = L.plane;
+  const R rho0 = R(L.rho0);
+  const Base<R> base(L);
+  const int tid = threadIdx.x;
+
+  // Lanes 0..SEG-1 own one boundary node each: pull its known populations
+  // (wrapping across periodic edges) and mark those whose source lies
+  // outside the domain.  Issued before the strip staging so both sets of
+  // loads are in flight together.
+  const int t = t0 + tid;
+  const bool owner = tid < SEG && t < tend;
+  int x = 0, y = 0;
+  R g[9];
+  uint32_t unknown = 0;
+  if (owner) {
+    edge_node(L, edge, 0, t, x, y);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      int sx = x - kCx[i], sy = y - kCy[i];
+      const bool outx = sx < 0 || sx >= nx;
+      const bool outy = sy < 0 || sy >= ny;
+      if ((outx && !xper) || (outy && !yper)) {
+        unknown |= 1u << i;
+        g[i] = R(0);
+      } else {
+        if (outx) sx = sx < 0 ? sx + nx : sx - nx;
+        if (outy) sy = sy < 0 ? sy + ny : sy - ny;
+        g[i] = C::dec(A[i * plane + (sy * pitch + sx)], L.ds[i]);
+      }
+    }
+  }
+
+  // Stage the time-t moments of the strip (depth 0..2, tangential halo 2),
+  // one strip node per thread.
+  if (any_nsbc && tid < DEPTH * STRIP) {
+    const int d = tid / STRIP, tt = tid - d * STRIP;
+    int ts = t0 - HALO + tt;
+    bool inside = true;
+    if (ts < 0 || ts >= ntan) {
+      if (tan_per) ts = ts < 0 ? ts + ntan : ts - ntan;
+      else inside = false;
+    }
+    R m[3] = {R(0), R(0), R(0)};
+    if (inside) {
+      int sx, sy;
+      edge_node(L, edge, d, ts, sx, sy);
+      R gs[9];
+      const int idx = sy * pitch + sx;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) gs[i] = C::dec(A[i * plane + idx], L.ds[i]);
+      moments<R>(gs, rho0, base, m[0], m[1], m[2]);
+    }
+    mom[0][d][tt] = m[0];
+    mom[1][d][tt] = m[1];
+    mom[2][d][tt] = m[2];
+  }
+  __syncthreads();
+  if (!owner) return;
+
+  const bool onL = x == 0 && L.bc[E_LEFT] == BC_NSBC;
+  const bool onR = x == nx - 1 && L.bc[E_RIGHT] == BC_NSBC;
+  const bool onB = y == 0 && L.bc[E_BOTTOM] == BC_NSBC;
+  const bool onT = y == ny - 1 && L.bc[E_TOP] == BC_NSBC;
+  if (onL || onR || onB || onT) {
+    const int tt = tid + HALO;
+    const bool own = (edge == E_LEFT && onL) || (edge == E_RIGHT && onR) || (edge == E_BOTTOM && onB) ||
+                     (edge == E_TOP && onT);
+    int nn = 0;
+    R dsum[3] = {R(0), R(0), R(0)};
+    // eq. nes_2: outward normal derivative by a one-sided difference, time t
+    if (own) {
+      ++nn;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) dsum[c] += normal_diff(mom[c][0][tt], mom[c][1][tt], mom[c][2][tt], L.grad_order);
+    }
+    if (vertical && (onB || onT)) {  // corner node: second normal runs along this strip
+      const int sgn = onB ? 1 : -1;
+      ++nn;
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        dsum[c] += normal_diff(mom[c][0][tt], mom[c][0][tt + sgn], mom[c][0][tt + 2 * sgn], L.grad_order);
+    }
+    R fac = R(L.gamma);
+    if (nn == 2) fac *= L.corner_mode == 0 ? R(0.70710678118654752440) : R(0.5);
+    const R beta = R(L.beta);
+    M3<R> mc;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const R mp = mom[c][0][tt] - fac * dsum[c];
+      mc.v[c] = (R(1) - beta) * mp + beta * R(L.m0[c]);  // eq. nes_3
+    }
+    nsbc_assign_correct<R>(g, unknown, mc, rho0, base, L.corr_mode);
+  }
+  bgk<R>(g, rho0, base, R(L.omega));
+  const int idx = y * pitch + x;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) put<true>(B + i * plane + idx, C::enc(g[i], L.es[i]));
+}
+
+}  // namespace lbm

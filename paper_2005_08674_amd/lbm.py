@@ -76,6 +76,21 @@ _SIGS = {
     "lbm_bulk_traffic": [_P, _P, _P],
     "lbm_set_overlap": [_P, ctypes.c_int],
     "lbm_stream_copy": [_P, _P, ctypes.c_size_t, _P],
+    # ensemble (include/lbm_ensemble.h)
+    "lbm_ens_workspace_bytes": [_P, ctypes.c_int32, _P],
+    "lbm_ens_init": [_P, _P, ctypes.c_int32, _P, ctypes.c_size_t, _P, _P, _P, _P],
+    "lbm_ens_set_farfield": [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                             ctypes.c_double],
+    "lbm_ens_step": [_P, ctypes.c_int32],
+    "lbm_ens_step_graph": [_P, ctypes.c_int32],
+    "lbm_ens_moments": [_P, ctypes.c_int32, _P, _P, _P, ctypes.c_int, ctypes.c_int],
+    "lbm_ens_get_populations": [_P, ctypes.c_int32, _P],
+    "lbm_ens_time": [_P, _P],
+    "lbm_ens_info": [_P, _P, _P, _P],
+    "lbm_ens_shape_count": [],
+    "lbm_ens_shape_describe": [ctypes.c_int32, _P, ctypes.c_size_t],
+    "lbm_ens_set_shape": [_P, ctypes.c_int32],
+    "lbm_ens_autotune": [_P, ctypes.c_int32, _P, _P],
 }
 
 
@@ -96,12 +111,14 @@ def load():
     lib.lbm_last_error.restype = ctypes.c_char_p
     lib.lbm_destroy.argtypes = [_P]
     lib.lbm_destroy.restype = None
+    lib.lbm_ens_destroy.argtypes = [_P]
+    lib.lbm_ens_destroy.restype = None
     _lib = lib
     return lib
 
 
 def exported_symbols():
-    return list(_SIGS) + ["lbm_last_error", "lbm_destroy"]
+    return list(_SIGS) + ["lbm_last_error", "lbm_destroy", "lbm_ens_destroy"]
 
 
 def _check(rc: int, where: str):
@@ -235,3 +252,78 @@ def lbm_bulk_traffic(ctx):
     b, n = ctypes.c_int64(), ctypes.c_int64()
     _check(load().lbm_bulk_traffic(ctx, ctypes.byref(b), ctypes.byref(n)), "lbm_bulk_traffic")
     return b.value, n.value
+
+
+# ------------------------------------------------------------------ ensemble
+
+def lbm_ens_workspace_bytes(members) -> int:
+    arr = (lbm_params * len(members))(*members)
+    n = ctypes.c_size_t()
+    _check(load().lbm_ens_workspace_bytes(arr, len(members), ctypes.byref(n)), "lbm_ens_workspace_bytes")
+    return n.value
+
+
+def lbm_ens_init(members, workspace_ptr, nbytes, drho_ptr, ux_ptr, uy_ptr, stream_ptr):
+    arr = (lbm_params * len(members))(*members)
+    ens = ctypes.c_void_p()
+    _check(load().lbm_ens_init(ctypes.byref(ens), arr, len(members), workspace_ptr, nbytes, drho_ptr, ux_ptr,
+                               uy_ptr, stream_ptr), "lbm_ens_init")
+    return ens
+
+
+def lbm_ens_set_farfield(ens, member, beta, rho_ref, ux_ref, uy_ref):
+    _check(load().lbm_ens_set_farfield(ens, int(member), beta, rho_ref, ux_ref, uy_ref), "lbm_ens_set_farfield")
+
+
+def lbm_ens_step(ens, n: int):
+    _check(load().lbm_ens_step(ens, int(n)), "lbm_ens_step")
+
+
+def lbm_ens_step_graph(ens, n: int):
+    _check(load().lbm_ens_step_graph(ens, int(n)), "lbm_ens_step_graph")
+
+
+def lbm_ens_moments(ens, member, drho_ptr, ux_ptr, uy_ptr, out_f64=True, deviation=True):
+    _check(load().lbm_ens_moments(ens, int(member), drho_ptr, ux_ptr, uy_ptr, int(out_f64), int(deviation)),
+           "lbm_ens_moments")
+
+
+def lbm_ens_get_populations(ens, member, g_ptr):
+    _check(load().lbm_ens_get_populations(ens, int(member), g_ptr), "lbm_ens_get_populations")
+
+
+def lbm_ens_time(ens) -> int:
+    t = ctypes.c_int64()
+    _check(load().lbm_ens_time(ens, ctypes.byref(t)), "lbm_ens_time")
+    return t.value
+
+
+def lbm_ens_info(ens):
+    n, b, e = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load().lbm_ens_info(ens, ctypes.byref(n), ctypes.byref(b), ctypes.byref(e)), "lbm_ens_info")
+    return n.value, b.value, e.value
+
+
+def lbm_ens_shape_count() -> int:
+    return int(load().lbm_ens_shape_count())
+
+
+def lbm_ens_shape_describe(shape_id: int) -> str:
+    buf = ctypes.create_string_buffer(64)
+    _check(load().lbm_ens_shape_describe(int(shape_id), buf, 64), "lbm_ens_shape_describe")
+    return buf.value.decode()
+
+
+def lbm_ens_set_shape(ens, shape_id: int):
+    _check(load().lbm_ens_set_shape(ens, int(shape_id)), "lbm_ens_set_shape")
+
+
+def lbm_ens_autotune(ens, reps: int = 5):
+    best = ctypes.c_int32()
+    times = (ctypes.c_float * lbm_ens_shape_count())()
+    _check(load().lbm_ens_autotune(ens, int(reps), ctypes.byref(best), times), "lbm_ens_autotune")
+    return best.value, list(times)
+
+
+def lbm_ens_destroy(ens):
+    load().lbm_ens_destroy(ens)

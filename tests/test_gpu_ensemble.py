@@ -1,0 +1,152 @@
+"""GPU ensemble: every member of a batched ensemble is bit-identical to the
+same lattice stepped alone; graph replays equal eager steps; the 256-member
+workload runs in one graph launch."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2005_08674_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2005_08674_amd import lbm
+    lbm.load()
+
+
+def _mixed_members(store="f32"):
+    """Uneven small lattices with every edge mix and reading variant."""
+    from paper_2005_08674_amd.ensemble import member_params
+    rng = np.random.default_rng(21)
+    specs = [
+        dict(nx=67, ny=45), dict(nx=130, ny=70, bc=(1, 1, 0, 0)), dict(nx=70, ny=130, bc=(0, 0, 1, 1)),
+        dict(nx=65, ny=66, bc=(0, 0, 0, 0)), dict(nx=100, ny=90, grad_order=2), dict(nx=3, ny=3),
+        dict(nx=3, ny=150, corner_mode=1), dict(nx=257, ny=64, corr_mode=1), dict(nx=64, ny=257),
+        dict(nx=200, ny=3, bc=(1, 1, 0, 0)), dict(nx=333, ny=129, ubase=(0.05, -0.02)),
+    ]
+    members, fields, far = [], [], []
+    for sp in specs:
+        nx, ny = sp.pop("nx"), sp.pop("ny")
+        tau = float(rng.uniform(0.52, 0.8))
+        members.append(member_params(nx, ny, tau, store=store, **sp))
+        u0 = (float(rng.uniform(-0.05, 0.05)), float(rng.uniform(-0.05, 0.05)))
+        fields.append(W.gaussian_pulses(nx, ny, [(1e-3, 5.0, rng.uniform(0, nx), rng.uniform(0, ny))], u0=u0))
+        far.append((float(rng.uniform(0, 0.5)), 1.0 + 1e-4, u0[0], u0[1]))
+    return members, fields, far
+
+
+def _standalone(p, f, far):
+    from paper_2005_08674_amd.lattice import Lattice
+    from paper_2005_08674_amd import lbm
+    g = Lattice(p.nx, p.ny, p.tau, f, rho0=p.rho0, bc=tuple(p.bc), gamma=p.gamma, store=p.store,
+                corr_mode=p.corr_mode, grad_order=p.grad_order, corner_mode=p.corner_mode,
+                ubase=(p.ubase[0], p.ubase[1]))
+    g.set_farfield(*far)
+    return g
+
+
+@pytest.mark.parametrize("store", ["f32", "f16", "f64"])
+def test_members_bitwise_equal_standalone(store):
+    from paper_2005_08674_amd.ensemble import Ensemble
+    members, fields, far = _mixed_members(store)
+    ens = Ensemble(members, fields)
+    for m, fa in enumerate(far):
+        ens.set_farfield(m, *fa)
+    ens.step(13)
+    for m, (p, f) in enumerate(zip(members, fields)):
+        g = _standalone(p, f, far[m])
+        g.step(13)
+        assert np.array_equal(ens.populations(m), g.populations().cpu().numpy()), (store, m, p.nx, p.ny)
+        g.close()
+
+
+def test_fp64_members_match_oracle():
+    from paper_2005_08674_amd.ensemble import Ensemble
+    members, fields, far = _mixed_members("f64")
+    ens = Ensemble(members, fields)
+    for m, fa in enumerate(far):
+        ens.set_farfield(m, *fa)
+    ens.step_graph(40)
+    for m in (0, 4, 7, 10):
+        p = members[m]
+        o = oracle.Lattice(p.nx, p.ny, p.tau, *fields[m], bc=tuple(p.bc), gamma=p.gamma, beta=far[m][0],
+                           m0=far[m][1:], corr_mode=p.corr_mode, grad_order=p.grad_order, corner_mode=p.corner_mode)
+        o.step(40)
+        gm, om = ens.moments(m), o.moments()
+        assert np.abs(gm[0] - om[0]).max() < 1e-15
+        assert max(np.abs(gm[1] - om[1]).max(), np.abs(gm[2] - om[2]).max()) / 0.05 < 1e-12
+
+
+def test_graph_replays_equal_eager_steps():
+    """Replay a captured 7-step graph repeatedly, with eager work and synchronisation between the
+    replays and a far-field change, and check every replay against eager stepping."""
+    from paper_2005_08674_amd.ensemble import Ensemble
+    members, fields, far = _mixed_members("f32")
+    a = Ensemble(members, fields)
+    b = Ensemble(members, fields)
+    for m, fa in enumerate(far):
+        a.set_farfield(m, *fa)
+        b.set_farfield(m, *fa)
+    for rep in range(5):
+        if rep == 3:
+            a.set_farfield(2, 0.7, 1.0, 0.01, 0.0)
+            b.set_farfield(2, 0.7, 1.0, 0.01, 0.0)
+        a.step_graph(7)
+        b.step(7)
+        x = torch.randn(1000, device="cuda").sum().item()  # unrelated eager work between replays
+        assert np.isfinite(x)
+        for m in range(len(members)):
+            assert np.array_equal(a.populations(m), b.populations(m)), (rep, m)
+    assert a.t == b.t == 35
+
+
+def test_all_shapes_bitwise_identical():
+    from paper_2005_08674_amd import lbm
+    from paper_2005_08674_amd.ensemble import Ensemble
+    members, fields, far = _mixed_members("f32")
+    ref = None
+    for shape in range(lbm.lbm_ens_shape_count()):
+        e = Ensemble(members, fields)
+        lbm.lbm_ens_set_shape(e.ens, shape)
+        e.step_graph(6)
+        pops = [e.populations(m) for m in range(len(members))]
+        if ref is None:
+            ref = pops
+        else:
+            for m in range(len(members)):
+                assert np.array_equal(pops[m], ref[m]), (shape, m)
+        e.close()
+
+
+def test_ensemble_256_one_graph_launch():
+    """The 256-member workload (sizes U{64..512}^2, tau U[0.52, 0.8], pulse or vortex) in one graph
+    launch of 200 steps; spot-check members against standalone lattices."""
+    from paper_2005_08674_amd.ensemble import Ensemble, member_params
+    ms = W.ensemble_members(256, seed=4)
+    members = [member_params(m.nx, m.ny, m.tau, store="f32",
+                             ubase=(m.params["u0"] if m.kind == "vortex" else (0.0, 0.0))) for m in ms]
+    fields = [W.member_fields(m) for m in ms]
+    ens = Ensemble(members, fields)
+    for k, m in enumerate(ms):
+        ens.set_farfield(k, 0.0, *W.member_m0(m))
+    best, times = ens.autotune(reps=3)
+    nodes, nb, ne = ens.info()
+    ens.step_graph(200)  # capture + first launch
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ens.step_graph(200)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_ = e0.elapsed_time(e1)
+    print(f"\n[ensemble 256] nodes={nodes} bulk blocks={nb} edge blocks={ne} shape={best} "
+          f"{nodes * 200 / (ms_ * 1e-3) / 1e6:.0f} MLUPS ({ms_ / 200 * 1e3:.1f} us/step)", flush=True)
+    for k in (0, 17, 255):
+        g = _standalone(members[k], fields[k], (0.0, *W.member_m0(ms[k])))
+        g.step(400)
+        assert np.array_equal(ens.populations(k), g.populations().cpu().numpy()), k
