@@ -71,6 +71,7 @@ def _lib(kind: str = "double"):
                        ("orc_init", [P, P, P, P, P]),
                        ("orc_moments", [P, P, P, P, P]),
                        ("orc_step", [P, P, ctypes.c_int]),
+                       ("orc_post_collision", [P, P, P]),
                        ("orc_num_threads", []),
                        ("orc_real_bytes", [])]:
         f = getattr(lib, name)
@@ -157,6 +158,12 @@ class Lattice:
             raise RuntimeError(f"orc_step failed ({rc})")
         self.t += int(n)
         return self
+
+    def post_collision(self):
+        """Post-collision populations g* = f* - w rho0 of every node, [9][ny][nx]."""
+        out = np.zeros_like(self.g)
+        self.lib.orc_post_collision(ctypes.byref(self.p), _ptr(self.g), _ptr(out))
+        return out
 
     def moments(self):
         """(rho - rho0, ux, uy), each [ny][nx] float64."""

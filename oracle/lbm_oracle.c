@@ -191,6 +191,20 @@ int orc_moments(const orc_params *p, const real *g, double *drho, double *ux, do
     return 0;
 }
 
+/* The post-collision populations g* of every node (step 2 of the step
+ * alone): the quantity the GPU library keeps in its buffers. */
+int orc_post_collision(const orc_params *p, const real *g, real *out) {
+    if (check_params(p)) return -1;
+    const size_t n = (size_t)p->nx * p->ny;
+    for (size_t k = 0; k < n; ++k) {
+        real gn[Q], gs[Q];
+        for (int i = 0; i < Q; ++i) gn[i] = g[(size_t)i * n + k];
+        collide((real)p->tau, (real)p->rho0, gn, gs);
+        for (int i = 0; i < Q; ++i) out[(size_t)i * n + k] = gs[i];
+    }
+    return 0;
+}
+
 static int wrap(int v, int n) { return ((v % n) + n) % n; }
 
 /* Population i of node (x, y) is unknown after streaming when its source

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "lbm.h"
+#include "lbm_closure.h"
 #include "lbm_device.h"
 #include "lbm_host.h"
 #include "lbm_launch.h"
@@ -540,6 +541,30 @@ int lbm_bulk_traffic(const lbm_ctx* c, int64_t* bytes_per_node, int64_t* nodes_p
   if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
   if (bytes_per_node) *bytes_per_node = 18 * (int64_t)c->lay.esize;
   if (nodes_per_launch) *nodes_per_launch = (int64_t)(c->p.nx - 2) * (c->p.ny - 2);
+  return LBM_OK;
+}
+
+int lbm_set_closure(lbm_ctx* c, const void* net, int mode) {
+  if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
+  if (mode != 0 && mode != 1) return fail(LBM_ERR_ARG, "closure mode %d", mode);
+  if (mode == 1 && !net) return fail(LBM_ERR_ARG, "closure mode 1 needs a network");
+  if (net && ((uintptr_t)net & 15)) return fail(LBM_ERR_ARG, "network blob not 16-byte aligned");
+  c->L.net = mode ? net : nullptr;
+  c->L.closure = mode;
+  return LBM_OK;
+}
+
+int lbm_closure_features(lbm_ctx* c, const int32_t* sites, int32_t n, float* feat_out, float* mc_out) {
+  if (!c || (n > 0 && (!sites || !feat_out || !mc_out))) return fail(LBM_ERR_ARG, "NULL argument");
+  if (n < 0) return fail(LBM_ERR_ARG, "n < 0");
+  HIPCHK(lbm::host::closure_features(&c->L, nullptr, 1, c->parity, sites, n, feat_out, mc_out, c->stream));
+  return LBM_OK;
+}
+
+int lbm_closure_moments(lbm_ctx* c, const int32_t* sites, int32_t n, const float* sub, float* m_out) {
+  if (!c || (n > 0 && (!sites || !m_out))) return fail(LBM_ERR_ARG, "NULL argument");
+  if (n < 0) return fail(LBM_ERR_ARG, "n < 0");
+  HIPCHK(lbm::host::closure_moments(&c->L, nullptr, 1, c->parity, sites, n, sub, m_out, c->stream));
   return LBM_OK;
 }
 

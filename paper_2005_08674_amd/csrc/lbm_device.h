@@ -99,6 +99,9 @@ struct LatDesc {
   double pb[9];     // P_i(u_b) = 1 + 3 c_i.u_b + 9/2 (c_i.u_b)^2 - 3/2 |u_b|^2
   float ds[9];      // decode scale per population
   float es[9];      // encode scale per population
+  const void* net;  // closure network (lbm::mlp::Net) or null
+  int32_t closure;  // 1: the edge kernel replaces NSBC's m_c by the network's, NSBC as fallback
+  int32_t _pad2;
 };
 
 // Buffer `parity` (0 or 1) of a lattice.  A select rather than an indexed

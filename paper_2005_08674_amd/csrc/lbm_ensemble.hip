@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "lbm.h"
+#include "lbm_closure.h"
 #include "lbm_ensemble.h"
 #include "lbm_device.h"
 #include "lbm_host.h"
@@ -45,7 +46,7 @@ __global__ __launch_bounds__(EDGE_THREADS) void k_ens_edge(const LatDesc* __rest
   __shared__ typename Codec<S>::R mom[3][DEPTH][STRIP];
   const EnsSeg sg = segs[blockIdx.x];
   const LatDesc L = descs[sg.lat];
-  edge_segment_body<S>(L, parity, sg.edge, sg.seg, mom);
+  edge_segment_body<S, false>(L, parity, sg.edge, sg.seg, mom, nullptr);
 }
 
 struct EnsShape {
@@ -429,6 +430,20 @@ int lbm_ens_info(const lbm_ens* e, int64_t* nodes, int32_t* bulk_blocks, int32_t
   }
   if (bulk_blocks) *bulk_blocks = e->ntiles;
   if (edge_blocks) *edge_blocks = e->nsegs;
+  return LBM_OK;
+}
+
+int lbm_ens_closure_features(lbm_ens* e, const int32_t* sites, int32_t n, float* feat_out, float* mc_out) {
+  if (!e || (n > 0 && (!sites || !feat_out || !mc_out))) return fail(LBM_ERR_ARG, "NULL argument");
+  if (n < 0) return fail(LBM_ERR_ARG, "n < 0");
+  HIPCHK(lbm::host::closure_features(nullptr, e->d_descs, e->count, e->parity, sites, n, feat_out, mc_out, e->stream));
+  return LBM_OK;
+}
+
+int lbm_ens_closure_moments(lbm_ens* e, const int32_t* sites, int32_t n, const float* sub, float* m_out) {
+  if (!e || (n > 0 && (!sites || !m_out))) return fail(LBM_ERR_ARG, "NULL argument");
+  if (n < 0) return fail(LBM_ERR_ARG, "n < 0");
+  HIPCHK(lbm::host::closure_moments(nullptr, e->d_descs, e->count, e->parity, sites, n, sub, m_out, e->stream));
   return LBM_OK;
 }
 

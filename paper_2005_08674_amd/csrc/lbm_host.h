@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <hip/hip_runtime.h>
+
 #include "lbm.h"
 #include "lbm_device.h"
 
@@ -37,6 +39,13 @@ void set_scales(LatDesc& L, int store, int k);
 void fill_desc(LatDesc& L, const lbm_params* p, const Layout& lay, void* buf0, void* buf1);
 int set_farfield(LatDesc& L, double beta, double rho_ref, double ux_ref, double uy_ref);
 int f16_exp_from_max(float mx);
+
+// Closure sampling launchers (lbm_closure.hip).  Exactly one of `single`
+// (one lattice) or `descs` (device descriptors of an ensemble) is used.
+hipError_t closure_features(const LatDesc* single, const LatDesc* descs, int count, int parity, const int32_t* sites,
+                            int n, float* feat, float* mc, hipStream_t s);
+hipError_t closure_moments(const LatDesc* single, const LatDesc* descs, int count, int parity, const int32_t* sites,
+                           int n, const float* sub, float* out, hipStream_t s);
 
 }  // namespace host
 }  // namespace lbm

@@ -159,20 +159,35 @@ __global__ __launch_bounds__(EDGE_THREADS) void k_edge(LatDesc L, int parity) {
   __shared__ typename Codec<S>::R mom[3][DEPTH][STRIP];
   int b = blockIdx.x, edge;
   edge_of_block(L.nx, L.ny, b, edge);
-  edge_segment_body<S>(L, parity, edge, b, mom);
+  edge_segment_body<S, false>(L, parity, edge, b, mom, nullptr);
+}
+
+// The edge kernel with the learned closure (NSBC fallback).
+template <int S>
+__global__ __launch_bounds__(EDGE_THREADS) void k_edge_closure(LatDesc L, int parity) {
+  __shared__ typename Codec<S>::R mom[3][DEPTH][STRIP];
+  __shared__ ClosureLds cl;
+  int b = blockIdx.x, edge;
+  edge_of_block(L.nx, L.ny, b, edge);
+  edge_segment_body<S, true>(L, parity, edge, b, mom, &cl);
 }
 
 int edge_blocks(int nx, int ny) { return 2 * edge_segments_v(ny) + 2 * edge_segments_h(nx); }
 
 hipError_t launch_edge(const LatDesc& L, int parity, hipStream_t s) {
   const dim3 grid(edge_blocks(L.nx, L.ny)), block(EDGE_THREADS);
+  const bool cl = L.closure && L.net;
+#define LBM_EDGE(ST)                                                            \
+  if (cl) k_edge_closure<ST><<<grid, block, 0, s>>>(L, parity);                \
+  else k_edge<ST><<<grid, block, 0, s>>>(L, parity);
   switch (L.store) {
-    case ST_F64: k_edge<ST_F64><<<grid, block, 0, s>>>(L, parity); break;
-    case ST_F32: k_edge<ST_F32><<<grid, block, 0, s>>>(L, parity); break;
-    case ST_F16: k_edge<ST_F16><<<grid, block, 0, s>>>(L, parity); break;
-    case ST_BF16: k_edge<ST_BF16><<<grid, block, 0, s>>>(L, parity); break;
+    case ST_F64: LBM_EDGE(ST_F64) break;
+    case ST_F32: LBM_EDGE(ST_F32) break;
+    case ST_F16: LBM_EDGE(ST_F16) break;
+    case ST_BF16: LBM_EDGE(ST_BF16) break;
     default: return hipErrorInvalidValue;
   }
+#undef LBM_EDGE
   return hipGetLastError();
 }
 

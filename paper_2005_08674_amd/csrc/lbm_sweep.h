@@ -3,7 +3,9 @@
 // (lbm_ensemble.hip): the bulk collide-stream tile and the NSBC edge segment.
 #pragma once
 
+#include "lbm_closure.h"
 #include "lbm_device.h"
+#include "lbm_mlp.h"
 
 namespace lbm {
 
@@ -111,11 +113,24 @@ __host__ __device__ inline void edge_of_block(int nx, int ny, int& b, int& edge)
   }
 }
 
+// LDS of the closure path of the edge kernel: strip features, the 64 x 96
+// network input tile, the two hidden tiles and the outputs.
+struct ClosureLds {
+  float feat[NODE_FEAT][DEPTH][STRIP];
+  __attribute__((aligned(16))) mlp::bf16 X[SEG * mlp::XS];
+  __attribute__((aligned(16))) mlp::bf16 H1[SEG * mlp::HS];
+  __attribute__((aligned(16))) mlp::bf16 H2[SEG * mlp::HS];
+  float Y[SEG][4];
+};
+
 // One 64-node segment `b` of edge `edge` of lattice L, computed by a block of
-// EDGE_THREADS threads: lanes 0..SEG-1 own one boundary node each.
-template <int S>
+// EDGE_THREADS threads: lanes 0..SEG-1 own one boundary node each.  With
+// CLOSURE the NSBC vector m_c of every node with a single NSBC normal is
+// corrected by the closure network (NSBC stays the fallback when the output
+// is not finite or leaves the trust bound); corners keep NSBC.
+template <int S, bool CLOSURE>
 __device__ inline void edge_segment_body(const LatDesc& L, int parity, int edge, int b,
-                                         typename Codec<S>::R (&mom)[3][DEPTH][STRIP]) {
+                                         typename Codec<S>::R (&mom)[3][DEPTH][STRIP], ClosureLds* cl) {
   using C = Codec<S>;
   using T = typename C::T;
   using R = typename C::R;
@@ -128,6 +143,11 @@ __device__ inline void edge_segment_body(const LatDesc& L, int parity, int edge,
   const bool yper = L.bc[E_BOTTOM] == BC_PERIODIC;
   const bool tan_per = vertical ? yper : xper;
   const bool any_nsbc = !(xper && yper);
+  // outward normal of this edge and the sign taking the tangent t = (-n_y, n_x)
+  // to increasing tangential coordinate
+  const int enx = edge == E_LEFT ? -1 : (edge == E_RIGHT ? 1 : 0);
+  const int eny = edge == E_BOTTOM ? -1 : (edge == E_TOP ? 1 : 0);
+  const int tsign = (edge == E_RIGHT || edge == E_BOTTOM) ? 1 : -1;
 
   const T* __restrict__ A = static_cast<const T*>(buf_of(L, parity));
   T* __restrict__ B = static_cast<T*>(buf_of(L, parity ^ 1));
@@ -164,8 +184,8 @@ __device__ inline void edge_segment_body(const LatDesc& L, int parity, int edge,
     }
   }
 
-  // Stage the time-t moments of the strip (depth 0..2, tangential halo 2),
-  // one strip node per thread.
+  // Stage the time-t moments (and, with CLOSURE, the strip features) of the
+  // strip (depth 0..2, tangential halo 2), one strip node per thread.
   if (any_nsbc && tid < DEPTH * STRIP) {
     const int d = tid / STRIP, tt = tid - d * STRIP;
     int ts = t0 - HALO + tt;
@@ -175,6 +195,7 @@ __device__ inline void edge_segment_body(const LatDesc& L, int parity, int edge,
       else inside = false;
     }
     R m[3] = {R(0), R(0), R(0)};
+    float f[NODE_FEAT] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (inside) {
       int sx, sy;
       edge_node(L, edge, d, ts, sx, sy);
@@ -183,23 +204,29 @@ __device__ inline void edge_segment_body(const LatDesc& L, int parity, int edge,
 #pragma unroll
       for (int i = 0; i < 9; ++i) gs[i] = C::dec(A[i * plane + idx], L.ds[i]);
       moments<R>(gs, rho0, base, m[0], m[1], m[2]);
+      if (CLOSURE) strip_node_features<R>(gs, rho0, base, enx, eny, f);
     }
     mom[0][d][tt] = m[0];
     mom[1][d][tt] = m[1];
     mom[2][d][tt] = m[2];
+    if (CLOSURE) {
+#pragma unroll
+      for (int q = 0; q < NODE_FEAT; ++q) cl->feat[q][d][tt] = f[q];
+    }
   }
   __syncthreads();
-  if (!owner) return;
 
-  const bool onL = x == 0 && L.bc[E_LEFT] == BC_NSBC;
-  const bool onR = x == nx - 1 && L.bc[E_RIGHT] == BC_NSBC;
-  const bool onB = y == 0 && L.bc[E_BOTTOM] == BC_NSBC;
-  const bool onT = y == ny - 1 && L.bc[E_TOP] == BC_NSBC;
-  if (onL || onR || onB || onT) {
-    const int tt = tid + HALO;
-    const bool own = (edge == E_LEFT && onL) || (edge == E_RIGHT && onR) || (edge == E_BOTTOM && onB) ||
-                     (edge == E_TOP && onT);
-    int nn = 0;
+  const bool onL = owner && x == 0 && L.bc[E_LEFT] == BC_NSBC;
+  const bool onR = owner && x == nx - 1 && L.bc[E_RIGHT] == BC_NSBC;
+  const bool onB = owner && y == 0 && L.bc[E_BOTTOM] == BC_NSBC;
+  const bool onT = owner && y == ny - 1 && L.bc[E_TOP] == BC_NSBC;
+  const bool nsbc_node = onL || onR || onB || onT;
+  const int tt = tid + HALO;
+  const bool own = (edge == E_LEFT && onL) || (edge == E_RIGHT && onR) || (edge == E_BOTTOM && onB) ||
+                   (edge == E_TOP && onT);
+  int nn = 0;
+  M3<R> mc;
+  if (nsbc_node) {
     R dsum[3] = {R(0), R(0), R(0)};
     // eq. nes_2: outward normal derivative by a one-sided difference, time t
     if (own) {
@@ -217,14 +244,71 @@ __device__ inline void edge_segment_body(const LatDesc& L, int parity, int edge,
     R fac = R(L.gamma);
     if (nn == 2) fac *= L.corner_mode == 0 ? R(0.70710678118654752440) : R(0.5);
     const R beta = R(L.beta);
-    M3<R> mc;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const R mp = mom[c][0][tt] - fac * dsum[c];
       mc.v[c] = (R(1) - beta) * mp + beta * R(L.m0[c]);  // eq. nes_3
     }
-    nsbc_assign_correct<R>(g, unknown, mc, rho0, base, L.corr_mode);
   }
+
+  if (CLOSURE) {
+    const mlp::Net& net = *static_cast<const mlp::Net*>(L.net);
+    const bool eligible = nsbc_node && own && nn == 1;
+    float mcn[3] = {0.f, 0.f, 0.f};
+    if (tid < SEG) {
+      // network input row of this lane: strip features, omega, m_c in the (n, t) frame
+      float xin[mlp::NFEAT];
+      if (eligible) {
+#pragma unroll
+        for (int d = 0; d < DEPTH; ++d)
+#pragma unroll
+          for (int k = -1; k <= 1; ++k)
+#pragma unroll
+            for (int q = 0; q < NODE_FEAT; ++q) xin[(3 * d + k + 1) * NODE_FEAT + q] = cl->feat[q][d][tt + tsign * k];
+        xin[81] = float(L.omega);
+        R mcv[3] = {mc.v[0], mc.v[1], mc.v[2]};
+        to_normal_frame<R>(mcv, base, enx, eny, mcn);
+        xin[82] = mcn[0];
+        xin[83] = mcn[1];
+        xin[84] = mcn[2];
+      }
+      mlp::bf16* row = cl->X + tid * mlp::XS;
+#pragma unroll
+      for (int q = 0; q < mlp::IN; ++q) {
+        const float v = (eligible && q < mlp::NFEAT) ? (xin[q] - net.feat_mean[q]) * net.feat_inv_std[q] : 0.f;
+        row[q] = (mlp::bf16)v;
+      }
+    }
+    __syncthreads();
+    {
+      const int w = tid >> 6;  // wavefront w runs rows 16 w .. 16 w + 15
+      mlp::f32x4 yv;
+      mlp::forward16(net, cl->X + 16 * w * mlp::XS, cl->H1 + 16 * w * mlp::HS, cl->H2 + 16 * w * mlp::HS, yv);
+      const int l = tid & 63, col = l & 15;
+      if (col < 3) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cl->Y[16 * w + 4 * (l >> 4) + r][col] = yv[r];
+      }
+    }
+    __syncthreads();
+    if (eligible) {
+      const float o0 = cl->Y[tid][0], o1 = cl->Y[tid][1], o2 = cl->Y[tid][2];
+      // NSBC stays when an output is not finite or leaves the trust bound
+      // (fmaxf would drop a NaN operand, so finiteness is tested first)
+      const bool finite = isfinite(o0) && isfinite(o1) && isfinite(o2);
+      if (finite && fmaxf(fabsf(o0), fmaxf(fabsf(o1), fabsf(o2))) <= net.trust) {
+        const float drho = mcn[0] + o0 * net.out_scale[0];
+        const float un = mcn[1] + o1 * net.out_scale[1];
+        const float ut = mcn[2] + o2 * net.out_scale[2];
+        // back to (drho, u - u_b) in the lattice frame: u = u_n n + u_t t, t = (-n_y, n_x)
+        mc.v[0] = R(drho);
+        mc.v[1] = R(un * float(enx) - ut * float(eny)) - base.ubx;
+        mc.v[2] = R(un * float(eny) + ut * float(enx)) - base.uby;
+      }
+    }
+  }
+  if (!owner) return;
+  if (nsbc_node) nsbc_assign_correct<R>(g, unknown, mc, rho0, base, L.corr_mode);
   bgk<R>(g, rho0, base, R(L.omega));
   const int idx = y * pitch + x;
 #pragma unroll

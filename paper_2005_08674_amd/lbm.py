@@ -91,6 +91,23 @@ _SIGS = {
     "lbm_ens_shape_describe": [ctypes.c_int32, _P, ctypes.c_size_t],
     "lbm_ens_set_shape": [_P, ctypes.c_int32],
     "lbm_ens_autotune": [_P, ctypes.c_int32, _P, _P],
+    # learned closure (include/lbm_closure.h)
+    "lbm_closure_net_bytes": [_P],
+    "lbm_set_closure": [_P, _P, ctypes.c_int],
+    "lbm_closure_features": [_P, _P, ctypes.c_int32, _P, _P],
+    "lbm_closure_moments": [_P, _P, ctypes.c_int32, _P, _P],
+    "lbm_ens_closure_features": [_P, _P, ctypes.c_int32, _P, _P],
+    "lbm_ens_closure_moments": [_P, _P, ctypes.c_int32, _P, _P],
+    "lbm_mlp_workspace_bytes": [ctypes.c_int32, _P],
+    "lbm_mlp_init": [_P, ctypes.c_int32, _P, ctypes.c_size_t, _P, _P],
+    "lbm_mlp_fit_normalization": [_P, _P, _P, ctypes.c_int64],
+    "lbm_mlp_pack": [_P, _P, _P, ctypes.c_int64, _P, _P],
+    "lbm_mlp_train_step": [_P, _P, _P, ctypes.c_int64, _P, ctypes.c_int32, ctypes.c_float, _P],
+    "lbm_mlp_grads": [_P, _P, _P, ctypes.c_int64, _P, ctypes.c_int32, _P, _P],
+    "lbm_mlp_forward": [_P, _P, ctypes.c_int64, _P],
+    "lbm_mlp_params": [_P, _P],
+    "lbm_mlp_normalization": [_P, _P, _P, _P],
+    "lbm_mlp_export": [_P, ctypes.c_float, _P],
 }
 
 
@@ -113,12 +130,14 @@ def load():
     lib.lbm_destroy.restype = None
     lib.lbm_ens_destroy.argtypes = [_P]
     lib.lbm_ens_destroy.restype = None
+    lib.lbm_mlp_destroy.argtypes = [_P]
+    lib.lbm_mlp_destroy.restype = None
     _lib = lib
     return lib
 
 
 def exported_symbols():
-    return list(_SIGS) + ["lbm_last_error", "lbm_destroy", "lbm_ens_destroy"]
+    return list(_SIGS) + ["lbm_last_error", "lbm_destroy", "lbm_ens_destroy", "lbm_mlp_destroy"]
 
 
 def _check(rc: int, where: str):
@@ -327,3 +346,87 @@ def lbm_ens_autotune(ens, reps: int = 5):
 
 def lbm_ens_destroy(ens):
     load().lbm_ens_destroy(ens)
+
+
+# ------------------------------------------------------------------ closure
+
+LBM_MLP_INPUTS = 96
+LBM_MLP_FEATURES = 85
+LBM_MLP_NPARAM = 10563
+
+
+def lbm_closure_net_bytes() -> int:
+    n = ctypes.c_size_t()
+    _check(load().lbm_closure_net_bytes(ctypes.byref(n)), "lbm_closure_net_bytes")
+    return n.value
+
+
+def lbm_set_closure(ctx, net_ptr, mode: int):
+    _check(load().lbm_set_closure(ctx, net_ptr, int(mode)), "lbm_set_closure")
+
+
+def lbm_closure_features(ctx, sites_ptr, n, feat_ptr, mc_ptr):
+    _check(load().lbm_closure_features(ctx, sites_ptr, int(n), feat_ptr, mc_ptr), "lbm_closure_features")
+
+
+def lbm_closure_moments(ctx, sites_ptr, n, sub_ptr, m_ptr):
+    _check(load().lbm_closure_moments(ctx, sites_ptr, int(n), sub_ptr, m_ptr), "lbm_closure_moments")
+
+
+def lbm_ens_closure_features(ens, sites_ptr, n, feat_ptr, mc_ptr):
+    _check(load().lbm_ens_closure_features(ens, sites_ptr, int(n), feat_ptr, mc_ptr), "lbm_ens_closure_features")
+
+
+def lbm_ens_closure_moments(ens, sites_ptr, n, sub_ptr, m_ptr):
+    _check(load().lbm_ens_closure_moments(ens, sites_ptr, int(n), sub_ptr, m_ptr), "lbm_ens_closure_moments")
+
+
+def lbm_mlp_workspace_bytes(max_batch: int) -> int:
+    n = ctypes.c_size_t()
+    _check(load().lbm_mlp_workspace_bytes(int(max_batch), ctypes.byref(n)), "lbm_mlp_workspace_bytes")
+    return n.value
+
+
+def lbm_mlp_init(max_batch, workspace_ptr, nbytes, params_ptr, stream_ptr):
+    m = ctypes.c_void_p()
+    _check(load().lbm_mlp_init(ctypes.byref(m), int(max_batch), workspace_ptr, nbytes, params_ptr, stream_ptr),
+           "lbm_mlp_init")
+    return m
+
+
+def lbm_mlp_fit_normalization(m, feat_ptr, resid_ptr, n):
+    _check(load().lbm_mlp_fit_normalization(m, feat_ptr, resid_ptr, int(n)), "lbm_mlp_fit_normalization")
+
+
+def lbm_mlp_pack(m, feat_ptr, resid_ptr, n, x_ptr, t_ptr):
+    _check(load().lbm_mlp_pack(m, feat_ptr, resid_ptr, int(n), x_ptr, t_ptr), "lbm_mlp_pack")
+
+
+def lbm_mlp_train_step(m, x_ptr, t_ptr, nsamples, rows_ptr, batch, lr, loss_ptr):
+    _check(load().lbm_mlp_train_step(m, x_ptr, t_ptr, int(nsamples), rows_ptr, int(batch), float(lr), loss_ptr),
+           "lbm_mlp_train_step")
+
+
+def lbm_mlp_grads(m, x_ptr, t_ptr, nsamples, rows_ptr, batch, grads_ptr, loss_ptr):
+    _check(load().lbm_mlp_grads(m, x_ptr, t_ptr, int(nsamples), rows_ptr, int(batch), grads_ptr, loss_ptr),
+           "lbm_mlp_grads")
+
+
+def lbm_mlp_forward(m, x_ptr, n, y_ptr):
+    _check(load().lbm_mlp_forward(m, x_ptr, int(n), y_ptr), "lbm_mlp_forward")
+
+
+def lbm_mlp_params(m, out_ptr):
+    _check(load().lbm_mlp_params(m, out_ptr), "lbm_mlp_params")
+
+
+def lbm_mlp_normalization(m, mean_ptr, inv_std_ptr, scale_ptr):
+    _check(load().lbm_mlp_normalization(m, mean_ptr, inv_std_ptr, scale_ptr), "lbm_mlp_normalization")
+
+
+def lbm_mlp_export(m, trust, net_ptr):
+    _check(load().lbm_mlp_export(m, float(trust), net_ptr), "lbm_mlp_export")
+
+
+def lbm_mlp_destroy(m):
+    load().lbm_mlp_destroy(m)

@@ -1,0 +1,140 @@
+"""Pins of the closure network oracle (oracle/mlp.py) and of the closure-input
+oracle (oracle/closure.py) against independent references: central finite
+differences, PyTorch fp64 autograd and torch.optim.Adam (library routines
+implementing the published algorithms), torch's bfloat16 rounding, and
+invariants of the input definition."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import closure as OC
+from oracle import mlp as M
+from paper_2005_08674_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+
+
+def _data(n=37, seed=1):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((n, M.IN)), rng.standard_normal((n, M.OUT))
+
+
+def test_bf16_rounding_matches_torch():
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.standard_normal(10000) * 10.0 ** rng.integers(-8, 8, 10000),
+                        [0.0, -0.0, 1.0, 1.00390625, 1.01171875, 3.4e38]])
+    ref = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(M.bf16_round(x), ref)
+
+
+def test_gradients_match_finite_differences():
+    """Unrounded network: backward equals central differences of the loss."""
+    p = M.init_params(3)
+    for k in p:
+        p[k] = p[k] + 0.05 * np.random.default_rng(5).standard_normal(p[k].shape)
+    X, T = _data()
+    _, g = M.loss_and_grads(p, X, T, bf16=False)
+    rng = np.random.default_rng(7)
+    h = 1e-5
+    for k in p:
+        flat = p[k].reshape(-1)
+        for idx in rng.choice(flat.size, size=min(6, flat.size), replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp = M.loss(p, X, T, bf16=False)
+            flat[idx] = old - h
+            lm = M.loss(p, X, T, bf16=False)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            assert g[k].reshape(-1)[idx] == pytest.approx(fd, rel=1e-5, abs=1e-9), (k, idx)
+
+
+def test_gradients_match_torch_autograd():
+    p = M.init_params(4)
+    X, T = _data(53, 2)
+    L, g = M.loss_and_grads(p, X, T, bf16=False)
+    tp = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True) for k, v in p.items()}
+    Xt, Tt = torch.tensor(X), torch.tensor(T)
+    h1 = torch.tanh(Xt @ tp["W1"].T + tp["b1"])
+    h2 = torch.tanh(h1 @ tp["W2"].T + tp["b2"])
+    y = h2 @ tp["W3"].T + tp["b3"]
+    lt = ((y - Tt) ** 2).mean()
+    lt.backward()
+    assert float(lt.detach()) == pytest.approx(L, rel=1e-13)
+    for k in p:
+        assert np.allclose(g[k], tp[k].grad.numpy(), rtol=1e-11, atol=1e-15), k
+
+
+def test_adam_matches_torch():
+    p = M.init_params(5)
+    X, T = _data(20, 3)
+    m, v = M.adam_init(p)
+    tp = {k: torch.tensor(v_, dtype=torch.float64, requires_grad=True) for k, v_ in p.items()}
+    opt = torch.optim.Adam(list(tp.values()), lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
+    for step in range(1, 6):
+        _, g = M.loss_and_grads(p, X, T, bf16=False)
+        p, m, v = M.adam_step(p, g, m, v, step, 1e-3)
+        opt.zero_grad()
+        for k in tp:
+            tp[k].grad = torch.tensor(g[k])
+        opt.step()
+    for k in p:
+        assert np.allclose(p[k], tp[k].detach().numpy(), rtol=1e-12, atol=1e-15), k
+
+
+def test_bf16_network_is_close_to_exact_network():
+    """The BF16 operand rounding changes outputs and gradients at the 1e-2 level, not more."""
+    p = M.init_params(6)
+    X, T = _data(64, 4)
+    y16, _ = M.forward(p, X, bf16=True)
+    y64, _ = M.forward(p, X, bf16=False)
+    assert np.abs(y16 - y64).max() < 5e-2 * np.abs(y64).max()
+    _, g16 = M.loss_and_grads(p, X, T, bf16=True)
+    _, g64 = M.loss_and_grads(p, X, T, bf16=False)
+    for k in g16:
+        assert np.linalg.norm(g16[k] - g64[k]) < 5e-2 * np.linalg.norm(g64[k]), k
+
+
+def test_closure_inputs_at_equilibrium_and_symmetry():
+    """At t = 0 every node is at equilibrium: all non-equilibrium moments vanish and the velocity
+    components are the initial field in the edge frame; mirroring the lattice maps a left-edge
+    site onto the right edge with identical inputs."""
+    nx, ny = 24, 20
+    f = W.lamb_oseen(nx, ny, 9.3, 10.1, 4.0, 0.03, (0.04, -0.01))
+    lat = oracle.Lattice(nx, ny, 0.7, *f)
+    feat, mc = OC.site_features(lat, 0, 10, 0, gamma=0.6)
+    for j in range(9):
+        assert np.abs(feat[9 * j + 3:9 * j + 9]).max() < 1e-17
+    # node (0, 10) is strip node j = 1 (d = 0, k = 0); normal (-1, 0), tangent (0, -1)
+    assert feat[1 * 9 + 1] == pytest.approx(-f[1][10, 0], abs=1e-16)
+    assert feat[1 * 9 + 2] == pytest.approx(-f[2][10, 0], abs=1e-16)
+    # strip node d = 2, k = 1 sits at (2, 9)
+    assert feat[(3 * 2 + 2) * 9] == pytest.approx(f[0][9, 2], abs=1e-17)
+    assert feat[81] == pytest.approx(1 / 0.7)
+    lat.step(7)
+    fl, _ = OC.site_features(lat, 0, 10, 0, gamma=0.6)
+    mir = tuple(a[:, ::-1].copy() for a in f)
+    mir = (mir[0], -mir[1], mir[2])
+    lat2 = oracle.Lattice(nx, ny, 0.7, *mir)
+    lat2.step(7)
+    fr, _ = OC.site_features(lat2, nx - 1, 10, 1, gamma=0.6)
+    # mirror x -> -x maps the left frame (n, t) = ((-1,0), (0,-1)) onto the right frame ((1,0), (0,1)):
+    # normal components agree, tangential ones flip sign, and the strip's k order reverses
+    sign = np.array([1, 1, -1, 1, -1, 1, -1, 1, 1])
+    for d in range(3):
+        for k in (-1, 0, 1):
+            a = fl[9 * (3 * d + k + 1):9 * (3 * d + k + 2)]
+            b = fr[9 * (3 * d - k + 1):9 * (3 * d - k + 2)]
+            assert np.allclose(a, sign * b, atol=1e-15, rtol=1e-11), (d, k)
+
+
+def test_closure_mc_special_cases():
+    nx, ny = 16, 14
+    f = W.gaussian_pulses(nx, ny, [(1e-3, 3.0, 5.0, 6.0)], u0=(0.02, 0.01))
+    lat = oracle.Lattice(nx, ny, 0.6, *f)
+    lat.step(3)
+    m = OC.site_moments(lat, 5, ny - 1, 3)
+    _, mc0 = OC.site_features(lat, 5, ny - 1, 3, gamma=0.0)
+    assert np.allclose(mc0, m, atol=1e-17)
+    _, mc1 = OC.site_features(lat, 5, ny - 1, 3, gamma=0.6, beta=1.0, m0=(1.001, 0.03, -0.02))
+    assert np.allclose(mc1, [1e-3, -0.02, -0.03], atol=1e-16)
