@@ -6,16 +6,23 @@
  * (assignment and correction, eqs. nes_0, nes_1, nes_4) stays as is and is
  * also the fallback.
  *
- * Network: 96 inputs (85 used) -> 64 tanh -> 64 tanh -> 3 outputs, BF16
+ * Network: 96 inputs (87 used) -> 64 tanh -> 64 tanh -> 3 outputs, BF16
  * weights and layer inputs, FP32 accumulation on gfx950 matrix cores.
  * Inputs of a boundary node b with outward normal n and tangent
  * t = (-n_y, n_x): for the nine strip nodes b - d n + k t (d = 0..2,
  * k = -1..1, node j = 3 d + k + 1 -> inputs 9 j .. 9 j + 8) the values
- * [rho - rho0, u.n, u.t, P_nn, P_nt, P_tt, Q_nnt, Q_ntt, R_nntt] (the 2nd to
- * 4th moments of f - f^eq in the (n, t) frame); input 81 = 1/tau; inputs
- * 82..84 = NSBC's m_c as (rho - rho0, u.n, u.t); inputs 85..95 = 0.  Inputs
- * are normalised by per-input mean and 1/std.  The 3 outputs, times
- * per-output scales, are added to m_c in the (n, t) frame.
+ * [rho - rho_ref, (u - u_ref).n, (u - u_ref).t, P_nn, P_nt, P_tt, Q_nnt,
+ * Q_ntt, R_nntt], where (rho_ref, u_ref) is the far-field state m0 of
+ * lbm_set_farfield and P, Q, R are the 2nd to 4th moments of f - f^eq in the
+ * (n, t) frame; inputs 82..84 = NSBC's m_c - m0 as (drho, u.n, u.t).  These
+ * 84 values are divided by the strip amplitude
+ *   A = sqrt(mean over the 9 strip nodes of c_s^2 (rho - rho_ref)^2 / rho0^2
+ *            + |u - u_ref|^2);
+ * input 81 = 1/tau; inputs 85, 86 = u_ref.n, u_ref.t; inputs 87..95 = 0.
+ * Inputs are then normalised by per-input mean and 1/std.  The 3 outputs,
+ * times per-output scales and A, are added to m_c in the (n, t) frame, so
+ * the correction scales with the disturbance and vanishes with it (A = 0
+ * keeps m_c).
  *
  * All pointers are device memory owned by the caller unless marked host.
  * Return codes and asynchrony as in lbm.h.
@@ -34,7 +41,7 @@ extern "C" {
 #endif
 
 #define LBM_MLP_INPUTS 96
-#define LBM_MLP_FEATURES 85
+#define LBM_MLP_FEATURES 87
 #define LBM_MLP_HIDDEN 64
 #define LBM_MLP_OUTPUTS 3
 /* packed fp32 parameters: W1 [64][96], b1 [64], W2 [64][64], b2 [64], W3 [3][64], b3 [3] */
@@ -44,8 +51,8 @@ extern "C" {
  * lbm_set_closure reads. */
 int lbm_closure_net_bytes(size_t* bytes);
 
-/* mode 1: every edge node with a single NSBC normal takes m_c + the network's
- * correction (`net`, a blob from lbm_mlp_export, borrowed while in use);
+/* mode 1: every edge node with a single NSBC normal takes m_c + A times the
+ * network's correction (`net`, a blob from lbm_mlp_export, borrowed while in use);
  * corners, non-finite outputs and outputs beyond the blob's trust bound keep
  * NSBC's m_c.  mode 0: plain NSBC (net may be NULL). */
 int lbm_set_closure(lbm_ctx* ctx, const void* net, int mode);
@@ -53,16 +60,22 @@ int lbm_set_closure(lbm_ctx* ctx, const void* net, int mode);
 /* Training samples of one lattice at its current time.  sites: int32 [n][4]
  * rows (x, y, edge, 0) with edge 0..3 = outward normal (-1,0), (1,0), (0,-1),
  * (0,1); the strip b - d n + k t (d = 0..2, k = -1..1) must lie inside the
- * lattice.  feat_out: float [n][96] raw (unnormalised) inputs; mc_out:
- * float [n][3] NSBC's m_c (rho - rho0, u.n, u.t) with the lattice's gamma,
- * beta, m0 and grad_order.  A site whose strip leaves the lattice yields NaN
- * rows.  Asynchronous. */
+ * lattice.  feat_out: float [n][96] inputs before normalisation (already
+ * divided by A); mc_out: float [n][4] = m_c - m0 as (rho, u.n, u.t), m_c
+ * being NSBC's prediction with the lattice's gamma, beta, m0 and grad_order,
+ * then A.  A site whose
+ * strip leaves the lattice yields NaN rows.  Asynchronous. */
 int lbm_closure_features(lbm_ctx* ctx, const int32_t* sites, int32_t n, float* feat_out, float* mc_out);
 
-/* (rho - rho0, u.n, u.t) at the sites' nodes, minus `sub` when it is not
- * NULL (float [n][3], e.g. the m_c of the previous step, giving training
- * residuals): m_out float [n][3]. */
+/* (rho - rho0, u.n, u.t) at the sites' nodes: m_out float [n][3].  With
+ * `sub` (float [n][4], the mc_out of the previous step) the result is the
+ * training residual (moments - m_c) / A instead, formed as
+ * ((moments - m0) - (m_c - m0)) / A so that no large values cancel in fp32. */
 int lbm_closure_moments(lbm_ctx* ctx, const int32_t* sites, int32_t n, const float* sub, float* m_out);
+
+/* lbm_set_closure for one member of an ensemble, or for all of them when
+ * member = -1. */
+int lbm_ens_set_closure(lbm_ens* e, int32_t member, const void* net, int mode);
 
 /* Ensemble versions: sites rows (member, x, y, edge); a row whose member is
  * not in [0, count) yields NaN. */
@@ -83,8 +96,12 @@ int lbm_mlp_init(lbm_mlp** out, int32_t max_batch, void* workspace, size_t bytes
                  void* hip_stream);
 
 /* Input mean / std and output scale (root mean square) from n training
- * samples: feat float [n][96] raw inputs, resid float [n][3] targets (true
- * next-step moments minus m_c).  fp64 reduction in a fixed order. */
+ * samples: feat float [n][96] inputs, resid float [n][3] targets (true
+ * next-step moments minus m_c, divided by A).  fp64 reduction in a fixed order.  Inputs
+ * 87..95, constant inputs (spread below 1e-7 of the mean), and strip-node inputs whose standard deviation is
+ * below 1e-3 of the largest standard deviation of the same moment over the
+ * nine strip nodes (rounding noise of a moment that vanishes exactly, such as
+ * the odd moments at the boundary row) get mean 0 and 1/std 0. */
 int lbm_mlp_fit_normalization(lbm_mlp* m, const float* feat, const float* resid, int64_t n);
 
 /* Normalise n samples: x_out BF16 [n][96] (round to nearest even), t_out
@@ -112,6 +129,10 @@ int lbm_mlp_params(lbm_mlp* m, float* params_out);
 
 /* Normalisation in use: mean_out, inv_std_out float [96], scale_out float [3]. */
 int lbm_mlp_normalization(lbm_mlp* m, float* mean_out, float* inv_std_out, float* scale_out);
+
+/* Replace the normalisation (device float [96], [96], [3]; scales > 0), e.g.
+ * to restore a trained network together with lbm_mlp_init's parameters. */
+int lbm_mlp_set_normalization(lbm_mlp* m, const float* mean, const float* inv_std, const float* scale);
 
 /* Write the network blob (lbm_closure_net_bytes bytes) for lbm_set_closure;
  * `trust` is the largest |normalised output| accepted at run time. */

@@ -115,6 +115,22 @@ class Trainer:
         self.stream.synchronize()
         return out.cpu().numpy()
 
+    def set_normalization(self, mean, inv_std, scale):
+        t = [torch.as_tensor(np.asarray(v, np.float32)).to(self.device) for v in (mean, inv_std, scale)]
+        L.lbm_mlp_set_normalization(self.m, t[0].data_ptr(), t[1].data_ptr(), t[2].data_ptr())
+        self.stream.synchronize()
+
+    def save(self, path):
+        mean, inv, sc = self.normalization()
+        np.savez(path, params=self.params(), feat_mean=mean, feat_inv_std=inv, out_scale=sc)
+
+    @classmethod
+    def load(cls, path, max_batch=4096, device="cuda"):
+        d = np.load(path)
+        tr = cls(d["params"], max_batch=max_batch, device=device)
+        tr.set_normalization(d["feat_mean"], d["feat_inv_std"], d["out_scale"])
+        return tr
+
     def export(self, trust: float = 6.0) -> torch.Tensor:
         blob = torch.empty(L.lbm_closure_net_bytes(), dtype=torch.uint8, device=self.device)
         L.lbm_mlp_export(self.m, trust, blob.data_ptr())
@@ -175,51 +191,162 @@ def twin_fields(member_fields_fn, m, pad_x, pad_y):
 
 
 def generate_dataset(members, member_fields_fn, member_m0_fn, steps=2000, log_every=10, stride=4, store="f32",
-                     gamma=0.6, device="cuda", log=None):
-    """Run the twins of `members` as one ensemble and collect (raw inputs, residual targets).
+                     gamma=0.6, net=None, amp_min=1e-8, device="cuda", log=None):
+    """Run every member (NSBC edges, or the closure `net` with NSBC fallback) beside its twin in one
+    ensemble and collect (raw inputs, residual targets).
 
-    Returns (feat [M, 96] float32, resid [M, 3] float32) device tensors."""
+    Inputs come from the member's own boundary nodes, so they carry what the boundary condition in
+    use did at earlier steps; targets are the twin's moments at the same physical nodes one step
+    later, minus the member's NSBC prediction m_c, divided by the strip amplitude A.  Sites whose A
+    is at most `amp_min` (no disturbance yet, only rounding noise) are left out.  Returns
+    (feat [M, 96], resid [M, 3]) float32 device tensors."""
     from .ensemble import Ensemble, member_params
-    twins, fields, sites, t_clean = [], [], [], []
+    count = len(members)
+    lat, fields, msites, tsites, t_clean, m0s = [], [], [], [], [], []
     for k, m in enumerate(members):
-        px, py = m.nx // 2, m.ny // 2
-        u0 = member_m0_fn(m)[1:]
-        twins.append(member_params(m.nx + 2 * px, m.ny + 2 * py, m.tau, store=store, gamma=gamma,
-                                   ubase=u0 if m.kind == "vortex" else (0.0, 0.0)))
-        fields.append(twin_fields(member_fields_fn, m, px, py))
-        s = edge_sites(m.nx, m.ny, stride, px, py)
-        sites.append(np.concatenate([np.full((len(s), 1), k, np.int32), s, np.zeros((len(s), 1), np.int32)], 1)[:, :4])
+        u0 = tuple(member_m0_fn(m)[1:])
+        ub = u0 if m.kind == "vortex" else (0.0, 0.0)
+        lat.append(member_params(m.nx, m.ny, m.tau, store=store, gamma=gamma, ubase=ub))
+        fields.append(member_fields_fn(m))
+        s = edge_sites(m.nx, m.ny, stride)
+        msites.append(np.concatenate([np.full((len(s), 1), k, np.int32), s], 1))
+        m0s.append(member_m0_fn(m))
         speed = CS + math.hypot(*u0)
         t_clean.append(math.inf if m.kind == "vortex" else 1.25 * min(m.nx, m.ny) / speed)
-    ens = Ensemble(twins, fields, device=device)
     for k, m in enumerate(members):
-        ens.set_farfield(k, 0.0, *member_m0_fn(m))
+        px, py = m.nx // 2, m.ny // 2
+        u0 = tuple(member_m0_fn(m)[1:])
+        ub = u0 if m.kind == "vortex" else (0.0, 0.0)
+        lat.append(member_params(m.nx + 2 * px, m.ny + 2 * py, m.tau, store=store, gamma=gamma, ubase=ub))
+        fields.append(twin_fields(member_fields_fn, m, px, py))
+        s = msites[k].copy()
+        s[:, 0] = count + k
+        s[:, 1] += px
+        s[:, 2] += py
+        tsites.append(s)
+    ens = Ensemble(lat, fields, device=device)
+    for k in range(count):
+        ens.set_farfield(k, 0.0, *m0s[k])
+        ens.set_farfield(count + k, 0.0, *m0s[k])
+    if net is not None:
+        for k in range(count):
+            L.lbm_ens_set_closure(ens.ens, k, net.data_ptr(), 1)
     feats, resids = [], []
     t = 0
-    while t + 1 <= steps:
-        live = np.concatenate([s for s, tc in zip(sites, t_clean) if t + 1 <= tc])
-        if len(live):
-            sd = torch.from_numpy(np.ascontiguousarray(live)).to(device)
-            n = len(live)
+    while t < steps:
+        keep = [k for k in range(count) if t + 1 <= t_clean[k]]
+        adv = 0
+        if keep:
+            ms = torch.from_numpy(np.ascontiguousarray(np.concatenate([msites[k] for k in keep]))).to(device)
+            ts = torch.from_numpy(np.ascontiguousarray(np.concatenate([tsites[k] for k in keep]))).to(device)
+            n = ms.shape[0]
             f = torch.empty((n, IN), dtype=torch.float32, device=device)
-            mc = torch.empty((n, OUT), dtype=torch.float32, device=device)
-            L.lbm_ens_closure_features(ens.ens, sd.data_ptr(), n, f.data_ptr(), mc.data_ptr())
+            mc = torch.empty((n, OUT + 1), dtype=torch.float32, device=device)
+            L.lbm_ens_closure_features(ens.ens, ms.data_ptr(), n, f.data_ptr(), mc.data_ptr())
             ens.step(1)
             r = torch.empty((n, OUT), dtype=torch.float32, device=device)
-            L.lbm_ens_closure_moments(ens.ens, sd.data_ptr(), n, mc.data_ptr(), r.data_ptr())
-            feats.append(f)
-            resids.append(r)
+            L.lbm_ens_closure_moments(ens.ens, ts.data_ptr(), n, mc.data_ptr(), r.data_ptr())
+            keep_rows = mc[:, OUT] > amp_min
+            feats.append(f[keep_rows])
+            resids.append(r[keep_rows])
             adv = 1
-        else:
-            adv = 0
         rest = min(log_every - adv, steps - t - adv)
         if rest > 0:
             ens.step_graph(rest)
         t += adv + max(rest, 0)
-        if log and len(feats) % 20 == 1:
+        if log and len(feats) % 50 == 1:
             log(f"t={t} samples={sum(x.shape[0] for x in feats)}")
     ens.close()
     feat = torch.cat(feats)
     resid = torch.cat(resids)
     ok = torch.isfinite(feat).all(1) & torch.isfinite(resid).all(1)
     return feat[ok].contiguous(), resid[ok].contiguous()
+
+
+def heldout_mse(trainer: "Trainer", x, t, chunk=None):
+    """Mean squared error of the trained network on packed samples (library loss kernel, no update)."""
+    chunk = chunk or trainer.max_batch
+    tot, n = 0.0, x.shape[0]
+    for s in range(0, n, chunk):
+        b = min(chunk, n - s)
+        _, loss = trainer.grads(x[s:s + b], t[s:s + b])
+        tot += loss * b
+    return tot / n
+
+
+def main(argv=None):
+    """Train the closure on the batched-ensemble twins and report its gain on held-out members."""
+    import argparse
+    import json
+    import sys
+    import time
+    from . import workloads as W
+
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--members", type=int, default=256)
+    ap.add_argument("--seed", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--log-every", type=int, default=10)
+    ap.add_argument("--stride", type=int, default=4)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--lr-end", type=float, default=1e-4)
+    ap.add_argument("--heldout-members", type=int, default=32)
+    ap.add_argument("--heldout-seed", type=int, default=40)
+    ap.add_argument("--rounds", type=int, default=2, help="data rounds; rounds >= 1 run the members with the "
+                                                           "previous round's network")
+    ap.add_argument("--trust", type=float, default=4.0)
+    ap.add_argument("--out", default=None, help="save params + normalisation (.npz)")
+    args = ap.parse_args(argv)
+
+    def log(*a):
+        print(*a, file=sys.stderr, flush=True)
+
+    t0 = time.time()
+    members = W.ensemble_members(args.members, seed=args.seed)
+    feat, resid = generate_dataset(members, W.member_fields, W.member_m0, steps=args.steps,
+                                   log_every=args.log_every, stride=args.stride, log=log)
+    t_data = time.time() - t0
+    log(f"dataset round 0 (NSBC edges): {feat.shape[0]} samples in {t_data:.1f} s")
+    tr = Trainer(max_batch=args.batch)
+    tr.fit_normalization(feat, resid)
+    x, t = tr.pack(feat, resid)
+    t1 = time.time()
+    losses = tr.train(x, t, epochs=args.epochs, batch=args.batch, lr=args.lr, lr_end=args.lr_end, log=log)
+    torch.cuda.synchronize()
+    t_train = time.time() - t1
+    for rnd in range(1, args.rounds):
+        # closed-loop data: the members now run with the current network on their edges
+        blob = tr.export(args.trust)
+        f2, r2 = generate_dataset(members, W.member_fields, W.member_m0, steps=args.steps,
+                                  log_every=args.log_every, stride=args.stride, net=blob, log=log)
+        log(f"dataset round {rnd} (closure edges): {f2.shape[0]} samples")
+        feat, resid = torch.cat([feat, f2]), torch.cat([resid, r2])
+        del f2, r2
+        x, t = tr.pack(feat, resid)
+        t1 = time.time()
+        losses = tr.train(x, t, epochs=args.epochs, batch=args.batch, lr=args.lr, lr_end=args.lr_end,
+                          seed=rnd, log=log)
+        torch.cuda.synchronize()
+        t_train += time.time() - t1
+    del feat, resid
+    ho = W.ensemble_members(args.heldout_members, seed=args.heldout_seed)
+    hf, hr = generate_dataset(ho, W.member_fields, W.member_m0, steps=args.steps, log_every=args.log_every,
+                              stride=args.stride)
+    hx, ht = tr.pack(hf, hr)
+    mse_net = heldout_mse(tr, hx, ht)
+    mse_nsbc = float((ht.double() ** 2).mean().item())  # NSBC predicts a zero residual
+    if args.out:
+        tr.save(args.out)
+    res = {"train_samples": int(x.shape[0]), "heldout_samples": int(hx.shape[0]), "epochs": args.epochs,
+           "first_loss": losses[0], "final_loss": losses[-1], "heldout_mse_closure": mse_net,
+           "heldout_mse_nsbc": mse_nsbc, "heldout_gain": 1.0 - mse_net / mse_nsbc,
+           "data_s": round(t_data, 2), "train_s": round(t_train, 2),
+           "train_steps": args.epochs * (x.shape[0] // args.batch)}
+    print(json.dumps(res), flush=True)
+    return res
+
+
+if __name__ == "__main__":
+    main()

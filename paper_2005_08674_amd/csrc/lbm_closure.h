@@ -4,12 +4,18 @@
 // tangent t = (-n_y, n_x), the network sees the nine strip nodes
 // s(d, k) = b - d n + k t, d = 0, 1, 2 (depth), k = -1, 0, 1 (tangential),
 // at time t, each described in the (n, t) frame by
-//   [drho, u.n, u.t, P_nn, P_nt, P_tt, Q_nnt, Q_ntt, R_nntt]
-// where P, Q, R are the 2nd/3rd/4th moments of the non-equilibrium part
-// f_i - f_i^eq (its 0th and 1st moments vanish), strip node j = 3 d + k + 1
-// filling features 9 j .. 9 j + 8; then omega = 1/tau (feature 81) and NSBC's
-// m_c = (drho_c, u_c.n, u_c.t) (features 82..84); 85..95 are zero.
-// The network's 3 outputs correct m_c in the same frame.
+//   [rho - rho_ref, (u - u_ref).n, (u - u_ref).t, P_nn, P_nt, P_tt, Q_nnt, Q_ntt, R_nntt]
+// where (rho_ref, u_ref) is the lattice's far-field state m0 and P, Q, R are
+// the 2nd/3rd/4th moments of the non-equilibrium part f_i - f_i^eq (its 0th
+// and 1st moments vanish); strip node j = 3 d + k + 1 fills inputs 9 j .. 9 j + 8.
+// These 81 values and NSBC's m_c - m0 (inputs 82..84, same frame) are divided
+// by the strip amplitude
+//   A = sqrt( (1/9) sum_j [c_s^2 (rho_j - rho_ref)^2 / rho0^2 + |u_j - u_ref|^2] ),
+// so the inputs describe the shape of the disturbance, not its size; input 81
+// is omega = 1/tau and inputs 85, 86 are u_ref.n, u_ref.t; 87..95 are zero.
+// The network's 3 outputs, times the output scales and A, correct m_c in the
+// (n, t) frame: the closure is homogeneous of degree one in the disturbance
+// and vanishes with it.
 #pragma once
 
 #include "lbm_device.h"
@@ -18,15 +24,18 @@
 namespace lbm {
 
 constexpr int NODE_FEAT = 9;
+constexpr int F_STRIP = 9 * NODE_FEAT;  // 81
+constexpr int F_OMEGA = 81, F_MC = 82, F_UREF = 85;
 
-// Features of one strip node from its 9 decoded deviations.
+// Unscaled features of one strip node from its 9 decoded deviations; ref =
+// m0 in the deviation form (rho_ref - rho0, u_ref - u_b).
 template <class R>
-__device__ inline void strip_node_features(const R g[9], R rho0, const Base<R>& b, int nx_, int ny_,
+__device__ inline void strip_node_features(const R g[9], R rho0, const Base<R>& b, const R ref[3], int nx_, int ny_,
                                            float f[NODE_FEAT]) {
   R dr, dux, duy, geq[9];
   moments<R>(g, rho0, b, dr, dux, duy);
   equilibrium<R>(rho0, b, dr, dux, duy, geq);
-  const R ux = dux + b.ubx, uy = duy + b.uby;
+  const R px = dux - ref[1], py = duy - ref[2];
   R pnn = 0, pnt = 0, ptt = 0, qnnt = 0, qntt = 0, rnntt = 0;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
@@ -40,9 +49,9 @@ __device__ inline void strip_node_features(const R g[9], R rho0, const Base<R>& 
     qntt += q * cn * ct * ct;
     rnntt += q * cn * cn * ct * ct;
   }
-  f[0] = float(dr);
-  f[1] = float(ux * R(nx_) + uy * R(ny_));
-  f[2] = float(-ux * R(ny_) + uy * R(nx_));
+  f[0] = float(dr - ref[0]);
+  f[1] = float(px * R(nx_) + py * R(ny_));
+  f[2] = float(-px * R(ny_) + py * R(nx_));
   f[3] = float(pnn);
   f[4] = float(pnt);
   f[5] = float(ptt);
@@ -58,6 +67,42 @@ __device__ inline void to_normal_frame(const R m[3], const Base<R>& b, int nx_, 
   out[0] = float(m[0]);
   out[1] = float(ux * R(nx_) + uy * R(ny_));
   out[2] = float(-ux * R(ny_) + uy * R(nx_));
+}
+
+// (a - b) in the (n, t) frame for two moment triples in the deviation form;
+// the difference is formed at the lattice's precision before rounding.
+template <class R>
+__device__ inline void normal_frame_diff(const R a[3], const R b[3], int nx_, int ny_, float out[3]) {
+  const R dx = a[1] - b[1], dy = a[2] - b[2];
+  out[0] = float(a[0] - b[0]);
+  out[1] = float(dx * R(nx_) + dy * R(ny_));
+  out[2] = float(-dx * R(ny_) + dy * R(nx_));
+}
+
+// Completes an input row x[0..86] whose strip part x[0..80] holds the
+// unscaled node features: appends omega, (m_c - m0)/A and u_ref, scales the
+// strip part by 1/A, zeroes 87..95 and returns A.  dmc: m_c - m0 and refn:
+// m0, both as (drho, u_n, u_t) in the edge frame.
+__device__ inline float finish_inputs(float* x, float rho0, float omega, const float dmc[3], const float refn[3]) {
+  constexpr float cs2 = 1.f / 3.f;
+  float s = 0.f;
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    const float r = x[NODE_FEAT * j] / rho0, un = x[NODE_FEAT * j + 1], ut = x[NODE_FEAT * j + 2];
+    s += cs2 * r * r + un * un + ut * ut;
+  }
+  const float A = sqrtf(s / 9.f);
+  const float inv = A > 0.f ? 1.f / A : 0.f;
+#pragma unroll
+  for (int q = 0; q < F_STRIP; ++q) x[q] *= inv;
+  x[F_OMEGA] = omega;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) x[F_MC + c] = dmc[c] * inv;
+  x[F_UREF] = refn[1];
+  x[F_UREF + 1] = refn[2];
+#pragma unroll
+  for (int q = mlp::NFEAT; q < mlp::IN; ++q) x[q] = 0.f;
+  return A;
 }
 
 }  // namespace lbm

@@ -45,6 +45,7 @@ __device__ void site_features_body(const LatDesc& L, int parity, int x, int y, i
   edge_normal(edge, enx, eny);
   const R rho0 = R(L.rho0);
   const Base<R> base(L);
+  const R ref[3] = {R(L.m0[0]), R(L.m0[1]), R(L.m0[2])};
   R mom[3][3];  // depth 0..2 at k = 0
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -54,7 +55,7 @@ __device__ void site_features_body(const LatDesc& L, int parity, int x, int y, i
       R g[9];
       load_node<S>(L, parity, sx, sy, g);
       float f[NODE_FEAT];
-      strip_node_features<R>(g, rho0, base, enx, eny, f);
+      strip_node_features<R>(g, rho0, base, ref, enx, eny, f);
 #pragma unroll
       for (int q = 0; q < NODE_FEAT; ++q) feat[(3 * d + k + 1) * NODE_FEAT + q] = f[q];
       if (k == 0) moments<R>(g, rho0, base, mom[d][0], mom[d][1], mom[d][2]);
@@ -66,22 +67,23 @@ __device__ void site_features_body(const LatDesc& L, int parity, int x, int y, i
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const R mp = mom[0][c] - gam * normal_diff(mom[0][c], mom[1][c], mom[2][c], L.grad_order);
-    m[c] = (R(1) - beta) * mp + beta * R(L.m0[c]);
+    m[c] = (R(1) - beta) * mp + beta * ref[c];
   }
-  float mn[3];
-  to_normal_frame<R>(m, base, enx, eny, mn);
-  feat[81] = float(L.omega);
-  feat[82] = mn[0];
-  feat[83] = mn[1];
-  feat[84] = mn[2];
-  for (int q = mlp::NFEAT; q < mlp::IN; ++q) feat[q] = 0.f;
-  mc[0] = mn[0];
-  mc[1] = mn[1];
-  mc[2] = mn[2];
+  float rn[3], dn[3];
+  to_normal_frame<R>(ref, base, enx, eny, rn);
+  normal_frame_diff<R>(m, ref, enx, eny, dn);
+  const float A = finish_inputs(feat, float(L.rho0), float(L.omega), dn, rn);
+  mc[0] = dn[0];
+  mc[1] = dn[1];
+  mc[2] = dn[2];
+  mc[3] = A;
 }
 
+// Moments of a site in the (n, t) frame; with `sub` (m_c - m0 and A of the
+// previous step) the training residual ((m - m0) - (m_c - m0)) / A, the first
+// difference formed at the lattice's precision.
 template <int S>
-__device__ void site_moments_body(const LatDesc& L, int parity, int x, int y, int edge, float* out) {
+__device__ void site_moments_body(const LatDesc& L, int parity, int x, int y, int edge, const float* sub, float* out) {
   using R = typename Codec<S>::R;
   int enx, eny;
   edge_normal(edge, enx, eny);
@@ -89,7 +91,15 @@ __device__ void site_moments_body(const LatDesc& L, int parity, int x, int y, in
   load_node<S>(L, parity, x, y, g);
   const Base<R> base(L);
   moments<R>(g, R(L.rho0), base, m[0], m[1], m[2]);
-  to_normal_frame<R>(m, base, enx, eny, out);
+  if (sub) {
+    const R ref[3] = {R(L.m0[0]), R(L.m0[1]), R(L.m0[2])};
+    float d[3];
+    normal_frame_diff<R>(m, ref, enx, eny, d);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[c] = (d[c] - sub[c]) / sub[3];
+  } else {
+    to_normal_frame<R>(m, base, enx, eny, out);
+  }
 }
 
 // Decode a site row; false when the strip (depth 0..2, tangential +-1) leaves the lattice.
@@ -126,10 +136,10 @@ __global__ void k_site_features(LatDesc single, const LatDesc* __restrict__ desc
   const LatDesc* D;
   int x, y, edge;
   float* f = feat + (size_t)i * mlp::IN;
-  float* m = mc + (size_t)i * 3;
+  float* m = mc + (size_t)i * 4;
   if (!site_of(sites + 4 * i, ens, count, single, descs, D, x, y, edge)) {
     for (int q = 0; q < mlp::IN; ++q) f[q] = NAN;
-    m[0] = m[1] = m[2] = NAN;
+    m[0] = m[1] = m[2] = m[3] = NAN;
     return;
   }
   const LatDesc L = *D;
@@ -154,16 +164,12 @@ __global__ void k_site_moments(LatDesc single, const LatDesc* __restrict__ descs
     return;
   }
   const LatDesc L = *D;
+  const float* sb = sub ? sub + (size_t)i * 4 : nullptr;
   switch (L.store) {
-    case ST_F64: site_moments_body<ST_F64>(L, parity, x, y, edge, o); break;
-    case ST_F32: site_moments_body<ST_F32>(L, parity, x, y, edge, o); break;
-    case ST_F16: site_moments_body<ST_F16>(L, parity, x, y, edge, o); break;
-    default: site_moments_body<ST_BF16>(L, parity, x, y, edge, o); break;
-  }
-  if (sub) {
-    o[0] -= sub[(size_t)i * 3];
-    o[1] -= sub[(size_t)i * 3 + 1];
-    o[2] -= sub[(size_t)i * 3 + 2];
+    case ST_F64: site_moments_body<ST_F64>(L, parity, x, y, edge, sb, o); break;
+    case ST_F32: site_moments_body<ST_F32>(L, parity, x, y, edge, sb, o); break;
+    case ST_F16: site_moments_body<ST_F16>(L, parity, x, y, edge, sb, o); break;
+    default: site_moments_body<ST_BF16>(L, parity, x, y, edge, sb, o); break;
   }
 }
 
@@ -452,19 +458,41 @@ __global__ void k_stats_partial(const float* __restrict__ feat, const float* __r
   part[((size_t)blockIdx.x * STAT_COLS + c) * 2 + 1] = q;
 }
 
+// Mean, 1/std and output scales from the partial sums.  A strip-node input
+// whose spread is below kNoiseFloor of the largest spread of the same moment
+// over the nine strip nodes is dropped (weight 0): moments that vanish in
+// exact arithmetic at the boundary row (e.g. the odd ones NSBC's
+// non-equilibrium bounce-back cancels) hold only rounding noise there, and
+// normalising that noise to unit spread would feed the network a
+// precision-dependent random input.
+constexpr double kNoiseFloor = 1e-3;
+
 __global__ void k_stats_final(const double* __restrict__ part, int nblocks, int64_t n, mlp::Net* __restrict__ net) {
+  __shared__ double sd_s[mlp::IN];
   const int c = threadIdx.x;
-  if (c >= STAT_COLS) return;
-  double s = 0.0, q = 0.0;
-  for (int b = 0; b < nblocks; ++b) {
-    s += part[((size_t)b * STAT_COLS + c) * 2];
-    q += part[((size_t)b * STAT_COLS + c) * 2 + 1];
-  }
-  const double mean = s / (double)n;
-  if (c < mlp::IN) {
+  double mean = 0.0, sd = 0.0, q = 0.0;
+  if (c < STAT_COLS) {
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) {
+      s += part[((size_t)b * STAT_COLS + c) * 2];
+      q += part[((size_t)b * STAT_COLS + c) * 2 + 1];
+    }
+    mean = s / (double)n;
     const double var = q / (double)n - mean * mean;
-    const double sd = var > 0.0 ? sqrt(var) : 0.0;
-    const bool used = c < mlp::NFEAT && sd > 1e-30;
+    sd = var > 0.0 ? sqrt(var) : 0.0;
+  }
+  if (c < mlp::IN) sd_s[c] = sd;
+  __syncthreads();
+  if (c >= STAT_COLS) return;
+  if (c < mlp::IN) {
+    // constant inputs (a spread at the fp64 rounding level of the mean) carry nothing
+    bool used = c < mlp::NFEAT && sd > 1e-30 && sd > 1e-7 * fabs(mean);
+    if (used && c < 9 * NODE_FEAT) {
+      const int kind = c % NODE_FEAT;
+      double top = 0.0;
+      for (int j = 0; j < 9; ++j) top = fmax(top, sd_s[NODE_FEAT * j + kind]);
+      used = sd > kNoiseFloor * top;
+    }
     net->feat_mean[c] = used ? (float)mean : 0.f;
     net->feat_inv_std[c] = used ? (float)(1.0 / sd) : 0.f;
   } else {
@@ -726,6 +754,15 @@ int lbm_mlp_normalization(lbm_mlp* m, float* mean_out, float* inv_std_out, float
   if (inv_std_out)
     HIPCHK(hipMemcpyAsync(inv_std_out, net->feat_inv_std, sizeof(float) * 96, hipMemcpyDeviceToDevice, m->stream));
   if (scale_out) HIPCHK(hipMemcpyAsync(scale_out, net->out_scale, sizeof(float) * 3, hipMemcpyDeviceToDevice, m->stream));
+  return LBM_OK;
+}
+
+int lbm_mlp_set_normalization(lbm_mlp* m, const float* mean, const float* inv_std, const float* scale) {
+  if (!m || !mean || !inv_std || !scale) return fail(LBM_ERR_ARG, "NULL argument");
+  lbm::mlp::Net* net = m->net();
+  HIPCHK(hipMemcpyAsync(net->feat_mean, mean, sizeof(float) * 96, hipMemcpyDeviceToDevice, m->stream));
+  HIPCHK(hipMemcpyAsync(net->feat_inv_std, inv_std, sizeof(float) * 96, hipMemcpyDeviceToDevice, m->stream));
+  HIPCHK(hipMemcpyAsync(net->out_scale, scale, sizeof(float) * 3, hipMemcpyDeviceToDevice, m->stream));
   return LBM_OK;
 }
 

@@ -49,6 +49,19 @@ __global__ __launch_bounds__(EDGE_THREADS) void k_ens_edge(const LatDesc* __rest
   edge_segment_body<S, false>(L, parity, sg.edge, sg.seg, mom, nullptr);
 }
 
+// Edge kernel of an ensemble in which some members use the learned closure;
+// a block of a member without it runs the plain NSBC path (uniform branch).
+template <int S>
+__global__ __launch_bounds__(EDGE_THREADS) void k_ens_edge_closure(const LatDesc* __restrict__ descs,
+                                                                  const EnsSeg* __restrict__ segs, int parity) {
+  __shared__ typename Codec<S>::R mom[3][DEPTH][STRIP];
+  __shared__ ClosureLds cl;
+  const EnsSeg sg = segs[blockIdx.x];
+  const LatDesc L = descs[sg.lat];
+  if (L.closure && L.net) edge_segment_body<S, true>(L, parity, sg.edge, sg.seg, mom, &cl);
+  else edge_segment_body<S, false>(L, parity, sg.edge, sg.seg, mom, nullptr);
+}
+
 struct EnsShape {
   int bx, by, nyt;
 };
@@ -101,16 +114,21 @@ static hipError_t launch_ens_bulk(int store, int shape, const LatDesc* d, const 
   return hipErrorInvalidValue;
 }
 
-static hipError_t launch_ens_edge(int store, const LatDesc* d, const EnsSeg* sg, int n, int parity, hipStream_t s) {
+static hipError_t launch_ens_edge(int store, bool closure, const LatDesc* d, const EnsSeg* sg, int n, int parity,
+                                  hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const dim3 grid(n), block(EDGE_THREADS);
+#define LBM_ENS_EDGE(ST)                                                             \
+  if (closure) k_ens_edge_closure<ST><<<grid, block, 0, s>>>(d, sg, parity);         \
+  else k_ens_edge<ST><<<grid, block, 0, s>>>(d, sg, parity);
   switch (store) {
-    case ST_F64: k_ens_edge<ST_F64><<<grid, block, 0, s>>>(d, sg, parity); break;
-    case ST_F32: k_ens_edge<ST_F32><<<grid, block, 0, s>>>(d, sg, parity); break;
-    case ST_F16: k_ens_edge<ST_F16><<<grid, block, 0, s>>>(d, sg, parity); break;
-    case ST_BF16: k_ens_edge<ST_BF16><<<grid, block, 0, s>>>(d, sg, parity); break;
+    case ST_F64: LBM_ENS_EDGE(ST_F64) break;
+    case ST_F32: LBM_ENS_EDGE(ST_F32) break;
+    case ST_F16: LBM_ENS_EDGE(ST_F16) break;
+    case ST_BF16: LBM_ENS_EDGE(ST_BF16) break;
     default: return hipErrorInvalidValue;
   }
+#undef LBM_ENS_EDGE
   return hipGetLastError();
 }
 
@@ -198,6 +216,7 @@ struct lbm_ens {
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;  // private stream used for graph capture
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+  bool any_closure = false;
 };
 
 namespace {
@@ -235,7 +254,7 @@ int build_tiles(lbm_ens* e, int shape) {
 
 int ens_launch_step(lbm_ens* e, int parity, hipStream_t s) {
   HIPCHK(lbm::launch_ens_bulk(e->store, e->shape, e->d_descs, e->d_tiles, e->ntiles, parity, s));
-  HIPCHK(lbm::launch_ens_edge(e->store, e->d_descs, e->d_segs, e->nsegs, parity, s));
+  HIPCHK(lbm::launch_ens_edge(e->store, e->any_closure, e->d_descs, e->d_segs, e->nsegs, parity, s));
   return LBM_OK;
 }
 
@@ -431,6 +450,23 @@ int lbm_ens_info(const lbm_ens* e, int64_t* nodes, int32_t* bulk_blocks, int32_t
   if (bulk_blocks) *bulk_blocks = e->ntiles;
   if (edge_blocks) *edge_blocks = e->nsegs;
   return LBM_OK;
+}
+
+int lbm_ens_set_closure(lbm_ens* e, int32_t member, const void* net, int mode) {
+  if (!e) return fail(LBM_ERR_ARG, "ensemble is NULL");
+  if (member < -1 || member >= e->count) return fail(LBM_ERR_ARG, "member %d out of range", member);
+  if (mode != 0 && mode != 1) return fail(LBM_ERR_ARG, "closure mode %d", mode);
+  if (mode == 1 && !net) return fail(LBM_ERR_ARG, "closure mode 1 needs a network");
+  if (net && ((uintptr_t)net & 15)) return fail(LBM_ERR_ARG, "network blob not 16-byte aligned");
+  for (int32_t k = (member < 0 ? 0 : member); k < (member < 0 ? e->count : member + 1); ++k) {
+    e->descs[k].net = mode ? net : nullptr;
+    e->descs[k].closure = mode;
+  }
+  bool any = false;
+  for (const auto& d : e->descs) any = any || (d.closure && d.net);
+  if (any != e->any_closure) drop_graphs(e);  // captured launches name the kernel variant
+  e->any_closure = any;
+  return upload_descs(e);
 }
 
 int lbm_ens_closure_features(lbm_ens* e, const int32_t* sites, int32_t n, float* feat_out, float* mc_out) {

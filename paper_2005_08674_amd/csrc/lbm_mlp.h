@@ -2,7 +2,7 @@
 // BF16 MFMA tiles for gfx950 (v_mfma_f32_16x16x32_bf16, FP32 accumulate),
 // one wavefront per 16 rows.
 //
-// Network: 96 features -> 64 (tanh) -> 64 (tanh) -> 3 outputs (padded to 16),
+// Network: 96 inputs (87 used) -> 64 (tanh) -> 64 (tanh) -> 3 outputs (padded to 16),
 // BF16 weights and layer inputs, FP32 accumulation, bias and tanh in FP32.
 //
 // MFMA lane layout (16x16x32): lane l holds A[l % 16][8 (l / 16) + j] and
@@ -16,7 +16,7 @@
 namespace lbm {
 namespace mlp {
 
-constexpr int IN = 96, HID = 64, OUT = 3, OUT_PAD = 16, NFEAT = 85;
+constexpr int IN = 96, HID = 64, OUT = 3, OUT_PAD = 16, NFEAT = 87;
 constexpr int XS = 104;  // LDS row stride (bf16) of a 96-wide tile: 16-byte rows, no bank conflicts
 constexpr int HS = 72;   // LDS row stride (bf16) of a 64-wide tile
 constexpr int YS = 40;   // LDS row stride (bf16) of the output-gradient tile (K padded to 32)

@@ -204,7 +204,10 @@ __device__ inline void edge_segment_body(const LatDesc& L, int parity, int edge,
 #pragma unroll
       for (int i = 0; i < 9; ++i) gs[i] = C::dec(A[i * plane + idx], L.ds[i]);
       moments<R>(gs, rho0, base, m[0], m[1], m[2]);
-      if (CLOSURE) strip_node_features<R>(gs, rho0, base, enx, eny, f);
+      if (CLOSURE) {
+        const R ref[3] = {R(L.m0[0]), R(L.m0[1]), R(L.m0[2])};
+        strip_node_features<R>(gs, rho0, base, ref, enx, eny, f);
+      }
     }
     mom[0][d][tt] = m[0];
     mom[1][d][tt] = m[1];
@@ -254,10 +257,10 @@ __device__ inline void edge_segment_body(const LatDesc& L, int parity, int edge,
   if (CLOSURE) {
     const mlp::Net& net = *static_cast<const mlp::Net*>(L.net);
     const bool eligible = nsbc_node && own && nn == 1;
-    float mcn[3] = {0.f, 0.f, 0.f};
+    float amp = 0.f;
     if (tid < SEG) {
-      // network input row of this lane: strip features, omega, m_c in the (n, t) frame
-      float xin[mlp::NFEAT];
+      // network input row of this lane: strip features, omega, m_c and m0 in the (n, t) frame
+      float xin[mlp::IN];
       if (eligible) {
 #pragma unroll
         for (int d = 0; d < DEPTH; ++d)
@@ -265,17 +268,17 @@ __device__ inline void edge_segment_body(const LatDesc& L, int parity, int edge,
           for (int k = -1; k <= 1; ++k)
 #pragma unroll
             for (int q = 0; q < NODE_FEAT; ++q) xin[(3 * d + k + 1) * NODE_FEAT + q] = cl->feat[q][d][tt + tsign * k];
-        xin[81] = float(L.omega);
-        R mcv[3] = {mc.v[0], mc.v[1], mc.v[2]};
-        to_normal_frame<R>(mcv, base, enx, eny, mcn);
-        xin[82] = mcn[0];
-        xin[83] = mcn[1];
-        xin[84] = mcn[2];
+        const R mcv[3] = {mc.v[0], mc.v[1], mc.v[2]};
+        const R ref[3] = {R(L.m0[0]), R(L.m0[1]), R(L.m0[2])};
+        float refn[3], dmc[3];
+        to_normal_frame<R>(ref, base, enx, eny, refn);
+        normal_frame_diff<R>(mcv, ref, enx, eny, dmc);
+        amp = finish_inputs(xin, float(L.rho0), float(L.omega), dmc, refn);
       }
       mlp::bf16* row = cl->X + tid * mlp::XS;
 #pragma unroll
       for (int q = 0; q < mlp::IN; ++q) {
-        const float v = (eligible && q < mlp::NFEAT) ? (xin[q] - net.feat_mean[q]) * net.feat_inv_std[q] : 0.f;
+        const float v = eligible ? (xin[q] - net.feat_mean[q]) * net.feat_inv_std[q] : 0.f;
         row[q] = (mlp::bf16)v;
       }
     }
@@ -291,19 +294,19 @@ __device__ inline void edge_segment_body(const LatDesc& L, int parity, int edge,
       }
     }
     __syncthreads();
-    if (eligible) {
+    if (eligible && amp > 0.f) {
       const float o0 = cl->Y[tid][0], o1 = cl->Y[tid][1], o2 = cl->Y[tid][2];
       // NSBC stays when an output is not finite or leaves the trust bound
       // (fmaxf would drop a NaN operand, so finiteness is tested first)
       const bool finite = isfinite(o0) && isfinite(o1) && isfinite(o2);
       if (finite && fmaxf(fabsf(o0), fmaxf(fabsf(o1), fabsf(o2))) <= net.trust) {
-        const float drho = mcn[0] + o0 * net.out_scale[0];
-        const float un = mcn[1] + o1 * net.out_scale[1];
-        const float ut = mcn[2] + o2 * net.out_scale[2];
-        // back to (drho, u - u_b) in the lattice frame: u = u_n n + u_t t, t = (-n_y, n_x)
-        mc.v[0] = R(drho);
-        mc.v[1] = R(un * float(enx) - ut * float(eny)) - base.ubx;
-        mc.v[2] = R(un * float(eny) + ut * float(enx)) - base.uby;
+        const float cr = amp * (o0 * net.out_scale[0]);
+        const float cn = amp * (o1 * net.out_scale[1]);
+        const float ct = amp * (o2 * net.out_scale[2]);
+        // back to the lattice frame: du = c_n n + c_t t, t = (-n_y, n_x)
+        mc.v[0] += R(cr);
+        mc.v[1] += R(cn * float(enx) - ct * float(eny));
+        mc.v[2] += R(cn * float(eny) + ct * float(enx));
       }
     }
   }

@@ -96,6 +96,7 @@ _SIGS = {
     "lbm_set_closure": [_P, _P, ctypes.c_int],
     "lbm_closure_features": [_P, _P, ctypes.c_int32, _P, _P],
     "lbm_closure_moments": [_P, _P, ctypes.c_int32, _P, _P],
+    "lbm_ens_set_closure": [_P, ctypes.c_int32, _P, ctypes.c_int],
     "lbm_ens_closure_features": [_P, _P, ctypes.c_int32, _P, _P],
     "lbm_ens_closure_moments": [_P, _P, ctypes.c_int32, _P, _P],
     "lbm_mlp_workspace_bytes": [ctypes.c_int32, _P],
@@ -108,6 +109,7 @@ _SIGS = {
     "lbm_mlp_params": [_P, _P],
     "lbm_mlp_normalization": [_P, _P, _P, _P],
     "lbm_mlp_export": [_P, ctypes.c_float, _P],
+    "lbm_mlp_set_normalization": [_P, _P, _P, _P],
 }
 
 
@@ -351,7 +353,7 @@ def lbm_ens_destroy(ens):
 # ------------------------------------------------------------------ closure
 
 LBM_MLP_INPUTS = 96
-LBM_MLP_FEATURES = 85
+LBM_MLP_FEATURES = 87
 LBM_MLP_NPARAM = 10563
 
 
@@ -371,6 +373,10 @@ def lbm_closure_features(ctx, sites_ptr, n, feat_ptr, mc_ptr):
 
 def lbm_closure_moments(ctx, sites_ptr, n, sub_ptr, m_ptr):
     _check(load().lbm_closure_moments(ctx, sites_ptr, int(n), sub_ptr, m_ptr), "lbm_closure_moments")
+
+
+def lbm_ens_set_closure(ens, member, net_ptr, mode: int):
+    _check(load().lbm_ens_set_closure(ens, int(member), net_ptr, int(mode)), "lbm_ens_set_closure")
 
 
 def lbm_ens_closure_features(ens, sites_ptr, n, feat_ptr, mc_ptr):
@@ -422,6 +428,10 @@ def lbm_mlp_params(m, out_ptr):
 
 def lbm_mlp_normalization(m, mean_ptr, inv_std_ptr, scale_ptr):
     _check(load().lbm_mlp_normalization(m, mean_ptr, inv_std_ptr, scale_ptr), "lbm_mlp_normalization")
+
+
+def lbm_mlp_set_normalization(m, mean_ptr, inv_std_ptr, scale_ptr):
+    _check(load().lbm_mlp_set_normalization(m, mean_ptr, inv_std_ptr, scale_ptr), "lbm_mlp_set_normalization")
 
 
 def lbm_mlp_export(m, trust, net_ptr):

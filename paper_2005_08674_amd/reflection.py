@@ -48,7 +48,7 @@ class ReflectionRun:
     """Test lattice plus ``scale``x reference lattice from one analytic field function."""
 
     def __init__(self, field_fn, nx, ny, tau, scale=4, store="f64", ref_store=None, u0=(0.0, 0.0),
-                 m0=None, ubase=(0.0, 0.0), test_kw=None, ref_kw=None, rho0=1.0):
+                 m0=None, ubase=(0.0, 0.0), test_kw=None, ref_kw=None, rho0=1.0, closure=None):
         self.nx, self.ny, self.scale, self.u0, self.rho0 = nx, ny, scale, tuple(u0), rho0
         self.rnx, self.rny = scale * nx, scale * ny
         self.ox, self.oy = (self.rnx - nx) // 2, (self.rny - ny) // 2
@@ -59,6 +59,8 @@ class ReflectionRun:
                             ubase=ubase, **tk)
         self.ref = Lattice(self.rnx, self.rny, tau, fields_on(field_fn, self.rnx, self.rny, -self.ox, -self.oy),
                            rho0=rho0, store=ref_store or store, m0=m0, ubase=ubase, **rk)
+        if closure is not None:  # a network blob (lbm_mlp_export) for the test lattice's edges
+            L.lbm_set_closure(self.test.ctx, closure.data_ptr(), 1)
         self.e0 = float(self.test.energy(ux_ref=u0[0], uy_ref=u0[1]).item())
 
     def t_clean(self) -> float:

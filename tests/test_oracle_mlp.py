@@ -97,27 +97,36 @@ def test_bf16_network_is_close_to_exact_network():
 
 def test_closure_inputs_at_equilibrium_and_symmetry():
     """At t = 0 every node is at equilibrium: all non-equilibrium moments vanish and the velocity
-    components are the initial field in the edge frame; mirroring the lattice maps a left-edge
-    site onto the right edge with identical inputs."""
+    components are the initial field in the edge frame, divided by the strip amplitude; mirroring the
+    lattice maps a left-edge site onto the right edge with identical inputs."""
     nx, ny = 24, 20
     f = W.lamb_oseen(nx, ny, 9.3, 10.1, 4.0, 0.03, (0.04, -0.01))
+    m0 = (1.0, 0.04, -0.01)
     lat = oracle.Lattice(nx, ny, 0.7, *f)
-    feat, mc = OC.site_features(lat, 0, 10, 0, gamma=0.6)
-    for j in range(9):
-        assert np.abs(feat[9 * j + 3:9 * j + 9]).max() < 1e-17
+    feat, mc, amp = OC.site_features(lat, 0, 10, 0, gamma=0.6, m0=m0)
+    for j in range(9):  # rounding of the populations (1e-17), divided by A (~0.05)
+        assert np.abs(feat[9 * j + 3:9 * j + 9]).max() < 1e-14
     # node (0, 10) is strip node j = 1 (d = 0, k = 0); normal (-1, 0), tangent (0, -1)
-    assert feat[1 * 9 + 1] == pytest.approx(-f[1][10, 0], abs=1e-16)
-    assert feat[1 * 9 + 2] == pytest.approx(-f[2][10, 0], abs=1e-16)
+    assert feat[1 * 9 + 1] * amp == pytest.approx(-(f[1][10, 0] - 0.04), abs=1e-16)
+    assert feat[1 * 9 + 2] * amp == pytest.approx(-(f[2][10, 0] + 0.01), abs=1e-16)
     # strip node d = 2, k = 1 sits at (2, 9)
-    assert feat[(3 * 2 + 2) * 9] == pytest.approx(f[0][9, 2], abs=1e-17)
+    assert feat[(3 * 2 + 2) * 9] * amp == pytest.approx(f[0][9, 2], abs=1e-17)
+    # the amplitude written out over the strip's nine nodes
+    pts = [(x, y) for x in (0, 1, 2) for y in (9, 10, 11)]
+    want = np.sqrt(np.mean([f[0][y, x] ** 2 / 3 + (f[1][y, x] - 0.04) ** 2 + (f[2][y, x] + 0.01) ** 2
+                            for x, y in pts]))
+    assert amp == pytest.approx(want, rel=1e-13)
     assert feat[81] == pytest.approx(1 / 0.7)
+    assert feat[85] == pytest.approx(-0.04) and feat[86] == pytest.approx(0.01)
+    assert np.all(feat[87:] == 0)
     lat.step(7)
-    fl, _ = OC.site_features(lat, 0, 10, 0, gamma=0.6)
+    fl, ml, al = OC.site_features(lat, 0, 10, 0, gamma=0.6)
     mir = tuple(a[:, ::-1].copy() for a in f)
     mir = (mir[0], -mir[1], mir[2])
     lat2 = oracle.Lattice(nx, ny, 0.7, *mir)
     lat2.step(7)
-    fr, _ = OC.site_features(lat2, nx - 1, 10, 1, gamma=0.6)
+    fr, mr, ar = OC.site_features(lat2, nx - 1, 10, 1, gamma=0.6)
+    assert al == pytest.approx(ar, rel=1e-11)
     # mirror x -> -x maps the left frame (n, t) = ((-1,0), (0,-1)) onto the right frame ((1,0), (0,1)):
     # normal components agree, tangential ones flip sign, and the strip's k order reverses
     sign = np.array([1, 1, -1, 1, -1, 1, -1, 1, 1])
@@ -126,6 +135,43 @@ def test_closure_inputs_at_equilibrium_and_symmetry():
             a = fl[9 * (3 * d + k + 1):9 * (3 * d + k + 2)]
             b = fr[9 * (3 * d - k + 1):9 * (3 * d - k + 2)]
             assert np.allclose(a, sign * b, atol=1e-15, rtol=1e-11), (d, k)
+    assert np.allclose(fl[82:85], fr[82:85] * [1, 1, -1], atol=1e-15, rtol=1e-11)
+    assert np.allclose(ml, mr * [1, 1, -1], atol=1e-17, rtol=1e-11)
+
+
+def test_closure_inputs_scale_with_the_disturbance():
+    """At equilibrium the unscaled inputs are linear in the disturbance, so doubling it doubles A and
+    leaves the inputs unchanged; the far-field flow enters only through inputs 85, 86."""
+    nx, ny = 20, 18
+    base = W.gaussian_pulses(nx, ny, [(4e-4, 3.0, 6.0, 9.0)], u0=(0.0, 0.0))
+    uf = (0.05, 0.02)
+    one = (base[0], base[1] + uf[0], base[2] + uf[1])
+    two = (2 * base[0], 2 * base[1] + uf[0], 2 * base[2] + uf[1])
+    m0 = (1.0, uf[0], uf[1])
+    a = oracle.Lattice(nx, ny, 0.6, *one)
+    b = oracle.Lattice(nx, ny, 0.6, *two)
+    fa, _, aa = OC.site_features(a, 0, 8, 0, gamma=0.6, m0=m0)
+    fb, _, ab = OC.site_features(b, 0, 8, 0, gamma=0.6, m0=m0)
+    assert ab == pytest.approx(2 * aa, rel=1e-12)
+    assert np.allclose(fa, fb, rtol=1e-10, atol=1e-11)
+    assert aa > 1e-5
+
+
+def test_nsbc_residual_is_zero_on_its_own_lattice():
+    """NSBC's assignment and correction make the boundary node's moments at t + 1 equal m_c, so the
+    target of an NSBC lattice against itself is zero on every edge."""
+    nx, ny = 30, 26
+    f = W.lamb_oseen(nx, ny, 14.0, 12.0, 4.0, 0.03, (0.05, 0.02))
+    m0 = (1.0002, 0.05, 0.02)
+    lat = oracle.Lattice(nx, ny, 0.62, *f, beta=0.2, m0=m0)
+    lat.step(6)
+    sites = [(0, 7, 0), (nx - 1, 12, 1), (9, 0, 2), (17, ny - 1, 3)]
+    pre = [OC.site_features(lat, x, y, e, gamma=0.6, beta=0.2, m0=m0) for x, y, e in sites]
+    lat.step(1)
+    for (x, y, e), (_, mcn, amp) in zip(sites, pre):
+        r = OC.site_target(lat, x, y, e, mcn, amp)
+        assert np.abs(r).max() < 1e-10, (x, y, e, r)
+        assert np.abs(OC.site_moments(lat, x, y, e) - mcn).max() < 1e-16
 
 
 def test_closure_mc_special_cases():
@@ -134,7 +180,8 @@ def test_closure_mc_special_cases():
     lat = oracle.Lattice(nx, ny, 0.6, *f)
     lat.step(3)
     m = OC.site_moments(lat, 5, ny - 1, 3)
-    _, mc0 = OC.site_features(lat, 5, ny - 1, 3, gamma=0.0)
+    _, mc0, _ = OC.site_features(lat, 5, ny - 1, 3, gamma=0.0)
     assert np.allclose(mc0, m, atol=1e-17)
-    _, mc1 = OC.site_features(lat, 5, ny - 1, 3, gamma=0.6, beta=1.0, m0=(1.001, 0.03, -0.02))
+    f1, mc1, _ = OC.site_features(lat, 5, ny - 1, 3, gamma=0.6, beta=1.0, m0=(1.001, 0.03, -0.02))
     assert np.allclose(mc1, [1e-3, -0.02, -0.03], atol=1e-16)
+    assert np.abs(f1[82:85]).max() < 1e-12
