@@ -6,7 +6,11 @@ plus the NSBC edge/corner kernel over the perimeter.  Workload: 4096 x 4096
 lattice, tau 0.51, 8 seeded Gaussian pulses (amplitude U[1e-4, 1e-3],
 half-width U[4, 16]), NSBC on all four edges, populations stored as FP32
 deviations f_i - w_i rho0 (the headline), plus FP16/BF16-deviation and FP64
-variants.  Inputs are resident in HBM before timing starts.
+variants.  Inputs are resident in HBM before timing starts.  Further
+variants: the 256-lattice batched ensemble in one graph launch, and the
+2048^2 vortex + pulse case run with plain NSBC (FP32, FP16 storage) and with
+the learned closure, each with its reflection coefficient against an 8192^2
+reference.
 
 Prints ONE JSON line (rank 0): metric/value (MLUPS), ms_per_step, the bulk
 kernel's roofline fraction from HIP-event durations measured in the timed
@@ -20,6 +24,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -189,6 +195,65 @@ def run_ensemble(torch, W, steps, count=256, seed=4):
             "step_GBs_algorithmic": round(72 * bulk_nodes / (ms_ / steps * 1e-3) / 1e9, 1)}
 
 
+CLOSURE_NET = os.path.join(ROOT, "paper_2005_08674_amd", "data", "closure_c4.npz")
+
+
+def run_c5(torch, W, steps, every=50, timing_steps=1000):
+    """Vortex + pulse on a 2048^2 lattice (tau 0.55, u0 = (0.1, 0)): plain NSBC in FP32, NSBC with FP16
+    deviation storage, and the learned closure (FP32), each with its MLUPS (test lattice alone) and its
+    reflection coefficient R_E against an 8192^2 FP32 reference over `steps` steps."""
+    from paper_2005_08674_amd import lbm
+    from paper_2005_08674_amd.lattice import Lattice
+    from paper_2005_08674_amd.reflection import ReflectionRun
+    w = W.vortex_pulse_2048()
+    ex = w.extra
+    u0 = (0.1, 0.0)
+    n = w.nx
+
+    def field(x, y):
+        dv, ux, uy = W.lamb_oseen_xy(x, y, ex["x0"], ex["y0"], ex["rc"], ex["uv"], u0)
+        dp = 1e-3 * np.exp(-np.log(2.0) * ((x - n / 2.0) ** 2 + (y - n / 2.0) ** 2) / 64.0)
+        return dv + dp, ux, uy
+
+    blob, net_note = None, None
+    if os.path.exists(CLOSURE_NET):
+        from paper_2005_08674_amd.closure import Trainer
+        tr = Trainer.load(CLOSURE_NET)
+        blob = tr.export()
+        net_note = {k: v for k, v in tr.meta.items()}
+    out = {"workload": f"vortexpulse{n}: {n}x{n} tau 0.55, u0 (0.1, 0), Lamb-Oseen vortex (R_c 12, max swirl "
+                       f"0.02) at ({ex['x0']:.1f}, {ex['y0']:.1f}) + pulse (1e-3, HWHM 8) at the centre; NSBC "
+                       f"gamma 0.6, beta 0, m0 (1, 0.1, 0); reference {4 * n}^2 FP32",
+           "steps": steps, "energy_every": every}
+    runs = [("nsbc_f32", "f32", None), ("nsbc_f16", "f16", None)]
+    if blob is not None:
+        runs.append(("closure_f32", "f32", blob))
+    for name, store, net in runs:
+        g = Lattice(n, n, w.tau, w.fields, store=store, m0=(1.0, 0.1, 0.0), ubase=u0)
+        if net is not None:
+            lbm.lbm_set_closure(g.ctx, net.data_ptr(), 1)
+        g.step(20)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(g.stream)
+        g.step(timing_steps)
+        b.record(g.stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        g.close()
+        rr = ReflectionRun(field, n, n, w.tau, scale=4, store=store, ref_store="f32", u0=u0, ubase=u0,
+                           closure=net)
+        res = rr.run(steps, every=every, respect_clean_time=True)
+        finite = rr.test.check_finite()
+        rr.close()
+        out[name] = {"mlups": round(n * n * timing_steps / (ms * 1e-3) / 1e6, 1),
+                     "ms_per_step": round(ms / timing_steps, 5), "R_E": float(res["R_E"]),
+                     "R_E_final": float(res["series"][-1]), "horizon": res["horizon"], "finite": bool(finite)}
+    if net_note is not None:
+        out["closure_net"] = {"file": os.path.relpath(CLOSURE_NET, ROOT), **net_note}
+    return out
+
+
 def cpu_baseline(W, w, budget_s=12.0):
     import oracle
     o = oracle.Lattice(w.nx, w.ny, w.tau, *w.fields)
@@ -219,6 +284,7 @@ def main():
     ap.add_argument("--tile", default=None, help="fix the FP32 bulk tile by name instead of autotuning")
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache and re-time all tiles")
     ap.add_argument("--ensemble-steps", type=int, default=2000, help="0 skips the ensemble variant")
+    ap.add_argument("--c5-steps", type=int, default=6000, help="0 skips the 2048^2 vortex+pulse reflection runs")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -246,6 +312,8 @@ def main():
                         "steps": args.variant_steps, "finite": r["finite"]}
     if args.ensemble_steps > 0:
         variants["ensemble256_f32"] = run_ensemble(torch, W, args.ensemble_steps)
+    if args.c5_steps > 0:
+        variants["vortexpulse2048_reflection"] = run_c5(torch, W, args.c5_steps)
     w = main_run["workload"]
     traffic = recorded_traffic(main_run["tile"])
     if traffic is not None:

@@ -135,8 +135,10 @@ int lbm_mlp_normalization(lbm_mlp* m, float* mean_out, float* inv_std_out, float
 int lbm_mlp_set_normalization(lbm_mlp* m, const float* mean, const float* inv_std, const float* scale);
 
 /* Write the network blob (lbm_closure_net_bytes bytes) for lbm_set_closure;
- * `trust` is the largest |normalised output| accepted at run time. */
-int lbm_mlp_export(lbm_mlp* m, float trust, void* net_out);
+ * `trust` (> 0) is the largest |normalised output| accepted at run time and
+ * `gain` (> 0) multiplies the correction (1 = as trained, < 1 under-relaxes
+ * it).  Synchronizes the trainer's stream. */
+int lbm_mlp_export(lbm_mlp* m, float trust, float gain, void* net_out);
 
 void lbm_mlp_destroy(lbm_mlp* m);
 

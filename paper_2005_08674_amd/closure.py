@@ -120,20 +120,28 @@ class Trainer:
         L.lbm_mlp_set_normalization(self.m, t[0].data_ptr(), t[1].data_ptr(), t[2].data_ptr())
         self.stream.synchronize()
 
-    def save(self, path):
+    def save(self, path, **meta):
+        """Parameters and normalisation (+ `meta` scalars such as trust and gain) as .npz."""
         mean, inv, sc = self.normalization()
-        np.savez(path, params=self.params(), feat_mean=mean, feat_inv_std=inv, out_scale=sc)
+        np.savez(path, params=self.params(), feat_mean=mean, feat_inv_std=inv, out_scale=sc,
+                 **{k: np.float64(v) for k, v in meta.items()})
 
     @classmethod
     def load(cls, path, max_batch=4096, device="cuda"):
         d = np.load(path)
         tr = cls(d["params"], max_batch=max_batch, device=device)
         tr.set_normalization(d["feat_mean"], d["feat_inv_std"], d["out_scale"])
+        tr.meta = {k: float(d[k]) for k in d.files if d[k].ndim == 0}
         return tr
 
-    def export(self, trust: float = 6.0) -> torch.Tensor:
+    def export(self, trust: float = None, gain: float = None) -> torch.Tensor:
+        """Network blob for lbm_set_closure; trust and gain default to the values saved with the
+        network (else 1.0 and 1.0)."""
+        meta = getattr(self, "meta", {})
+        trust = meta.get("trust", 1.0) if trust is None else trust
+        gain = meta.get("gain", 1.0) if gain is None else gain
         blob = torch.empty(L.lbm_closure_net_bytes(), dtype=torch.uint8, device=self.device)
-        L.lbm_mlp_export(self.m, trust, blob.data_ptr())
+        L.lbm_mlp_export(self.m, trust, gain, blob.data_ptr())
         return blob
 
     def train(self, x, t, epochs=20, batch=4096, lr=2e-3, lr_end=2e-4, seed=0, log=None):
@@ -191,15 +199,16 @@ def twin_fields(member_fields_fn, m, pad_x, pad_y):
 
 
 def generate_dataset(members, member_fields_fn, member_m0_fn, steps=2000, log_every=10, stride=4, store="f32",
-                     gamma=0.6, net=None, amp_min=1e-8, device="cuda", log=None):
+                     gamma=0.6, net=None, amp_min=1e-8, amp_rel=0.0, device="cuda", log=None):
     """Run every member (NSBC edges, or the closure `net` with NSBC fallback) beside its twin in one
     ensemble and collect (raw inputs, residual targets).
 
     Inputs come from the member's own boundary nodes, so they carry what the boundary condition in
     use did at earlier steps; targets are the twin's moments at the same physical nodes one step
     later, minus the member's NSBC prediction m_c, divided by the strip amplitude A.  Sites whose A
-    is at most `amp_min` (no disturbance yet, only rounding noise) are left out.  Returns
-    (feat [M, 96], resid [M, 3]) float32 device tensors."""
+    is at most `amp_min` (no disturbance yet, only rounding noise) or below `amp_rel` times the
+    largest A logged on the same member are left out.  Returns (feat [M, 96], resid [M, 3]) float32
+    device tensors."""
     from .ensemble import Ensemble, member_params
     count = len(members)
     lat, fields, msites, tsites, t_clean, m0s = [], [], [], [], [], []
@@ -231,7 +240,7 @@ def generate_dataset(members, member_fields_fn, member_m0_fn, steps=2000, log_ev
     if net is not None:
         for k in range(count):
             L.lbm_ens_set_closure(ens.ens, k, net.data_ptr(), 1)
-    feats, resids = [], []
+    feats, resids, amps, mids = [], [], [], []
     t = 0
     while t < steps:
         keep = [k for k in range(count) if t + 1 <= t_clean[k]]
@@ -249,6 +258,8 @@ def generate_dataset(members, member_fields_fn, member_m0_fn, steps=2000, log_ev
             keep_rows = mc[:, OUT] > amp_min
             feats.append(f[keep_rows])
             resids.append(r[keep_rows])
+            amps.append(mc[keep_rows, OUT])
+            mids.append(ms[keep_rows, 0].long())
             adv = 1
         rest = min(log_every - adv, steps - t - adv)
         if rest > 0:
@@ -260,6 +271,11 @@ def generate_dataset(members, member_fields_fn, member_m0_fn, steps=2000, log_ev
     feat = torch.cat(feats)
     resid = torch.cat(resids)
     ok = torch.isfinite(feat).all(1) & torch.isfinite(resid).all(1)
+    if amp_rel > 0.0:
+        amp, mid = torch.cat(amps), torch.cat(mids)
+        top = torch.zeros(count, dtype=amp.dtype, device=device).scatter_reduce(
+            0, mid[ok], amp[ok], reduce="amax", include_self=True)
+        ok &= amp >= amp_rel * top[mid]
     return feat[ok].contiguous(), resid[ok].contiguous()
 
 
@@ -275,7 +291,8 @@ def heldout_mse(trainer: "Trainer", x, t, chunk=None):
 
 
 def main(argv=None):
-    """Train the closure on the batched-ensemble twins and report its gain on held-out members."""
+    """Train the closure on the batched-ensemble members and their twins and report its one-step gain
+    on held-out members."""
     import argparse
     import json
     import sys
@@ -288,25 +305,31 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--log-every", type=int, default=10)
     ap.add_argument("--stride", type=int, default=4)
-    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--amp-rel", type=float, default=0.1,
+                    help="keep sites whose strip amplitude is at least this fraction of the member's largest")
+    ap.add_argument("--epochs", type=int, default=15)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--lr-end", type=float, default=1e-4)
     ap.add_argument("--heldout-members", type=int, default=32)
     ap.add_argument("--heldout-seed", type=int, default=40)
-    ap.add_argument("--rounds", type=int, default=2, help="data rounds; rounds >= 1 run the members with the "
+    ap.add_argument("--rounds", type=int, default=1, help="data rounds; rounds >= 1 run the members with the "
                                                            "previous round's network")
-    ap.add_argument("--trust", type=float, default=4.0)
+    ap.add_argument("--trust", type=float, default=1.0, help="trust bound saved with the network")
+    ap.add_argument("--gain", type=float, default=1.0, help="correction gain saved with the network")
     ap.add_argument("--out", default=None, help="save params + normalisation (.npz)")
     args = ap.parse_args(argv)
 
     def log(*a):
         print(*a, file=sys.stderr, flush=True)
 
+    def data(members, net=None):
+        return generate_dataset(members, W.member_fields, W.member_m0, steps=args.steps, log_every=args.log_every,
+                                stride=args.stride, amp_rel=args.amp_rel, net=net)
+
     t0 = time.time()
     members = W.ensemble_members(args.members, seed=args.seed)
-    feat, resid = generate_dataset(members, W.member_fields, W.member_m0, steps=args.steps,
-                                   log_every=args.log_every, stride=args.stride, log=log)
+    feat, resid = data(members)
     t_data = time.time() - t0
     log(f"dataset round 0 (NSBC edges): {feat.shape[0]} samples in {t_data:.1f} s")
     tr = Trainer(max_batch=args.batch)
@@ -318,9 +341,7 @@ def main(argv=None):
     t_train = time.time() - t1
     for rnd in range(1, args.rounds):
         # closed-loop data: the members now run with the current network on their edges
-        blob = tr.export(args.trust)
-        f2, r2 = generate_dataset(members, W.member_fields, W.member_m0, steps=args.steps,
-                                  log_every=args.log_every, stride=args.stride, net=blob, log=log)
+        f2, r2 = data(members, net=tr.export(args.trust, args.gain))
         log(f"dataset round {rnd} (closure edges): {f2.shape[0]} samples")
         feat, resid = torch.cat([feat, f2]), torch.cat([resid, r2])
         del f2, r2
@@ -332,13 +353,12 @@ def main(argv=None):
         t_train += time.time() - t1
     del feat, resid
     ho = W.ensemble_members(args.heldout_members, seed=args.heldout_seed)
-    hf, hr = generate_dataset(ho, W.member_fields, W.member_m0, steps=args.steps, log_every=args.log_every,
-                              stride=args.stride)
+    hf, hr = data(ho)
     hx, ht = tr.pack(hf, hr)
     mse_net = heldout_mse(tr, hx, ht)
     mse_nsbc = float((ht.double() ** 2).mean().item())  # NSBC predicts a zero residual
     if args.out:
-        tr.save(args.out)
+        tr.save(args.out, trust=args.trust, gain=args.gain)
     res = {"train_samples": int(x.shape[0]), "heldout_samples": int(hx.shape[0]), "epochs": args.epochs,
            "first_loss": losses[0], "final_loss": losses[-1], "heldout_mse_closure": mse_net,
            "heldout_mse_nsbc": mse_nsbc, "heldout_gain": 1.0 - mse_net / mse_nsbc,

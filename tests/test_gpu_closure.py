@@ -347,3 +347,62 @@ def test_closure_in_edge_kernel_matches_oracle(ubase):
         for (x, y_) in ((0, 0), (nx - 1, 0), (0, ny - 1), (nx - 1, ny - 1)):
             assert mg[c][y_, x] == pytest.approx(mo[c][y_, x], abs=1e-13)
         assert np.abs(mg[c][1:-1, 1:-1] - mo[c][1:-1, 1:-1]).max() < 1e-13
+
+
+def test_ensemble_closure_matches_standalone():
+    """Members running the closure inside the batched ensemble (one member on NSBC, the others on the
+    network) are bit-identical to the same lattices stepped alone, eagerly and through graphs."""
+    from paper_2005_08674_amd import lbm
+    from paper_2005_08674_amd.ensemble import Ensemble, member_params
+    from paper_2005_08674_amd.lattice import Lattice
+    p = _oracle_params(31)
+    tr = _trainer(p)
+    tr.set_normalization(np.zeros(96, np.float32), np.full(96, 0.5, np.float32), np.full(3, 0.05, np.float32))
+    blob = tr.export(4.0)
+    specs = [(90, 70, 0.6, (0.05, 0.01)), (130, 64, 0.55, (0.0, 0.0)), (64, 140, 0.7, (-0.03, 0.04))]
+    members, fields, far = [], [], []
+    for nx, ny, tau, u0 in specs:
+        members.append(member_params(nx, ny, tau, store="f32", ubase=u0))
+        fields.append(W.lamb_oseen(nx, ny, nx * 0.6, ny * 0.45, 6.0, 0.03, u0))
+        far.append((0.0, 1.0, u0[0], u0[1]))
+    ens = Ensemble(members, fields)
+    for k, fa in enumerate(far):
+        ens.set_farfield(k, *fa)
+    lbm.lbm_ens_set_closure(ens.ens, -1, blob.data_ptr(), 1)
+    lbm.lbm_ens_set_closure(ens.ens, 1, None, 0)
+    ens.step(5)
+    ens.step_graph(20)
+    for k, (pm, f) in enumerate(zip(members, fields)):
+        g = Lattice(pm.nx, pm.ny, pm.tau, f, store="f32", m0=far[k][1:], ubase=(pm.ubase[0], pm.ubase[1]))
+        if k != 1:
+            lbm.lbm_set_closure(g.ctx, blob.data_ptr(), 1)
+        g.step(25)
+        assert np.array_equal(ens.populations(k), g.populations().cpu().numpy()), k
+        g.close()
+    # the closure changed the members that run it
+    h = Lattice(members[0].nx, members[0].ny, members[0].tau, fields[0], store="f32", m0=far[0][1:],
+                ubase=(members[0].ubase[0], members[0].ubase[1]))
+    h.step(25)
+    assert not np.array_equal(ens.populations(0), h.populations().cpu().numpy())
+
+
+def test_trained_closure_beats_nsbc_one_step_on_heldout_members():
+    """Train on the ensemble members' NSBC edges with paired-twin targets (a small version of the
+    48-member, 800-step workload) and check the one-step error on held-out members: the network's
+    mean squared residual is below half of NSBC's."""
+    from paper_2005_08674_amd.closure import Trainer, generate_dataset, heldout_mse
+    members = W.ensemble_members(48, seed=4)
+    held = W.ensemble_members(8, seed=40)
+    f, r = generate_dataset(members, W.member_fields, W.member_m0, steps=800, log_every=10, stride=4, amp_rel=0.1)
+    hf, hr = generate_dataset(held, W.member_fields, W.member_m0, steps=800, log_every=10, stride=4, amp_rel=0.1)
+    assert f.shape[0] > 50000 and hf.shape[0] > 5000
+    tr = Trainer(max_batch=4096)
+    tr.fit_normalization(f, r)
+    x, t = tr.pack(f, r)
+    losses = tr.train(x, t, epochs=10, batch=4096, lr=2e-3, lr_end=1e-4)
+    hx, ht = tr.pack(hf, hr)
+    mse = heldout_mse(tr, hx, ht)
+    mse0 = float((ht.double() ** 2).mean().item())
+    print(f"\n[closure one-step, held-out] MSE network {mse:.4f} vs NSBC {mse0:.4f} "
+          f"(gain {1 - mse / mse0:.3f}); train loss {losses[0]:.3f} -> {losses[-1]:.3f}", flush=True)
+    assert mse < 0.5 * mse0
