@@ -200,6 +200,30 @@ int lbm_set_overlap(lbm_ctx* ctx, int on);
  * (nx-2)(ny-2) it updates per launch. */
 int lbm_bulk_traffic(const lbm_ctx* ctx, int64_t* bytes_per_node, int64_t* nodes_per_launch);
 
+/* Two-step sweep: for lattices with NSBC on all four edges and 16- or
+ * 32-bit storage, one launch advances two time steps (t -> t + 2), keeping
+ * level t + 1 in registers, so the state crosses HBM once per two steps
+ * (2 x 9 x bytes per stored population per node and launch).  Results are
+ * bit-identical to two single steps: the intermediate level is rounded
+ * through the storage format exactly as a store and reload would.
+ * lbm_two_step_count / lbm_two_step_describe list the candidate shapes;
+ * lbm_set_two_step selects one (-1 turns the sweep off, the default) and
+ * fails for lattices it does not support.  With a shape selected, lbm_step
+ * advances pairs of steps with it and an odd last step with the single-step
+ * kernels; the closure, the overlap option and periodic edges always use the
+ * single-step kernels.  lbm_autotune_two_step times every shape (`reps`
+ * launches each, median; the state is left unchanged), selects the fastest,
+ * writes its id to *best and the per-shape median launch times (ms, each
+ * launch = 2 steps) to times_ms if not NULL.  Synchronizes the stream.
+ * lbm_two_step_times returns the summed elapsed milliseconds and the count
+ * of two-step launches timed while lbm_enable_timing is on, and resets them. */
+int lbm_two_step_count(void);
+int lbm_two_step_describe(int32_t id, char* buf, size_t len);
+int lbm_set_two_step(lbm_ctx* ctx, int32_t id);
+int lbm_get_two_step(const lbm_ctx* ctx, int32_t* id);
+int lbm_autotune_two_step(lbm_ctx* ctx, int32_t reps, int32_t* best, float* times_ms);
+int lbm_two_step_times(lbm_ctx* ctx, double* ms, int64_t* launches);
+
 /* Plain device-to-device copy of `bytes` bytes (16-byte loads, non-temporal
  * stores) on `hip_stream`: the streaming-bandwidth reference the bulk kernel
  * is measured against, and the known-size kernel used to calibrate hardware

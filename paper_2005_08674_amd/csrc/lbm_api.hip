@@ -190,6 +190,11 @@ struct lbm_ctx {
   size_t ev_used = 0;
   double bulk_ms = 0, edge_ms = 0;
   int64_t bulk_n = 0, edge_n = 0;
+  std::vector<char> ev_two;  // per 4-event group: 1 = a two-step launch (events 0, 1)
+  double two_ms = 0;
+  int64_t two_n = 0;
+  // two-step sweep shape (-1: off)
+  int two_step = -1;
 };
 
 namespace {
@@ -201,6 +206,11 @@ int flush_timing(lbm_ctx* c) {
   for (size_t k = 0; k + 3 < c->ev_used; k += 4) {
     float a = 0, b = 0;
     HIPCHK(hipEventElapsedTime(&a, c->events[k], c->events[k + 1]));
+    if (c->ev_two[k / 4]) {
+      c->two_ms += a;
+      c->two_n += 1;
+      continue;
+    }
     HIPCHK(hipEventElapsedTime(&b, c->events[k + 2], c->events[k + 3]));
     c->bulk_ms += a;
     c->edge_ms += b;
@@ -208,6 +218,7 @@ int flush_timing(lbm_ctx* c) {
     c->edge_n += 1;
   }
   c->ev_used = 0;
+  c->ev_two.clear();
   return LBM_OK;
 }
 
@@ -238,6 +249,7 @@ int step_once(lbm_ctx* c) {
       int rc = next_event(c, &t[k]);
       if (rc) return rc;
     }
+    c->ev_two.push_back(0);
   }
   if (c->overlap) {
     HIPCHK(hipStreamWaitEvent(c->side, c->ev_bulk, 0));    // bulk kernel of the previous step
@@ -254,6 +266,34 @@ int step_once(lbm_ctx* c) {
   c->parity ^= 1;
   c->t += 1;
   return LBM_OK;
+}
+
+// Two steps in one launch of the two-step sweep (same results as two
+// step_once calls).
+int step_twice(lbm_ctx* c) {
+  hipEvent_t t[4] = {nullptr, nullptr, nullptr, nullptr};
+  if (c->timing) {
+    if (c->ev_used + 4 > 4 * 4096) {
+      int rc = flush_timing(c);
+      if (rc) return rc;
+    }
+    for (int k = 0; k < 4; ++k) {
+      int rc = next_event(c, &t[k]);
+      if (rc) return rc;
+    }
+    c->ev_two.push_back(1);
+  }
+  if (t[0]) HIPCHK(hipEventRecord(t[0], c->stream));
+  HIPCHK(lbm::launch_two_step(c->L, c->parity, c->two_step, c->stream));
+  if (t[1]) HIPCHK(hipEventRecord(t[1], c->stream));
+  // level t + 2 is in the other buffer: the launch wrote buffer parity ^ 1
+  c->parity ^= 1;
+  c->t += 2;
+  return LBM_OK;
+}
+
+bool use_two_step(const lbm_ctx* c) {
+  return c->two_step >= 0 && !c->overlap && !(c->L.closure && c->L.net) && lbm::two_step_supported(c->L);
 }
 
 }  // namespace
@@ -365,7 +405,14 @@ int lbm_step(lbm_ctx* c, int32_t n) {
     HIPCHK(hipEventRecord(c->ev_bulk, c->stream));
     HIPCHK(hipEventRecord(c->ev_edge, c->stream));
   }
-  for (int32_t s = 0; s < n; ++s) {
+  int32_t s = 0;
+  if (use_two_step(c)) {
+    for (; s + 1 < n; s += 2) {
+      int rc = step_twice(c);
+      if (rc) return rc;
+    }
+  }
+  for (; s < n; ++s) {
     int rc = step_once(c);
     if (rc) return rc;
   }
@@ -519,8 +566,85 @@ int lbm_enable_timing(lbm_ctx* c, int on) {
   int rc = flush_timing(c);
   if (rc) return rc;
   c->timing = on != 0;
-  c->bulk_ms = c->edge_ms = 0;
-  c->bulk_n = c->edge_n = 0;
+  c->bulk_ms = c->edge_ms = c->two_ms = 0;
+  c->bulk_n = c->edge_n = c->two_n = 0;
+  return LBM_OK;
+}
+
+int lbm_two_step_count(void) { return lbm::num_two_step(); }
+
+int lbm_two_step_describe(int32_t id, char* buf, size_t len) {
+  if (!buf || len == 0) return fail(LBM_ERR_ARG, "NULL buffer");
+  if (id < 0 || id >= lbm::num_two_step()) return fail(LBM_ERR_ARG, "two-step shape %d out of range", id);
+  lbm::two_step_name(id, buf, len);
+  return LBM_OK;
+}
+
+int lbm_set_two_step(lbm_ctx* c, int32_t id) {
+  if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
+  if (id < -1 || id >= lbm::num_two_step()) return fail(LBM_ERR_ARG, "two-step shape %d out of range", id);
+  if (id >= 0 && !lbm::two_step_supported(c->L))
+    return fail(LBM_ERR_ARG, "the two-step sweep needs NSBC on all four edges and 16- or 32-bit storage");
+  c->two_step = id;
+  return LBM_OK;
+}
+
+int lbm_get_two_step(const lbm_ctx* c, int32_t* id) {
+  if (!c || !id) return fail(LBM_ERR_ARG, "NULL argument");
+  *id = c->two_step;
+  return LBM_OK;
+}
+
+int lbm_autotune_two_step(lbm_ctx* c, int32_t reps, int32_t* best, float* times_ms) {
+  if (!c || !best) return fail(LBM_ERR_ARG, "NULL argument");
+  if (reps < 1 || reps > 1000) return fail(LBM_ERR_ARG, "reps = %d outside [1, 1000]", reps);
+  if (!lbm::two_step_supported(c->L))
+    return fail(LBM_ERR_ARG, "the two-step sweep needs NSBC on all four edges and 16- or 32-bit storage");
+  // the sweep reads buffer `parity` and writes only the other one, so
+  // relaunching it leaves the state untouched
+  const int nt = lbm::num_two_step();
+  std::vector<hipEvent_t> ev(2 * reps);
+  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+  float best_t = 1e30f;
+  int best_id = 0;
+  int rc = LBM_OK;
+  for (int id = 0; id < nt && rc == LBM_OK; ++id) {
+    hipError_t e = lbm::launch_two_step(c->L, c->parity, id, c->stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+      e = hipEventRecord(ev[2 * r], c->stream);
+      if (e == hipSuccess) e = lbm::launch_two_step(c->L, c->parity, id, c->stream);
+      if (e == hipSuccess) e = hipEventRecord(ev[2 * r + 1], c->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    std::vector<float> ts(reps);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = hipEventElapsedTime(&ts[r], ev[2 * r], ev[2 * r + 1]);
+    if (e != hipSuccess) {
+      rc = fail(LBM_ERR_HIP, "two-step candidate %d: %s", id, hipGetErrorString(e));
+      break;
+    }
+    std::sort(ts.begin(), ts.end());
+    const float med = ts[reps / 2];
+    if (times_ms) times_ms[id] = med;
+    if (med < best_t) {
+      best_t = med;
+      best_id = id;
+    }
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (rc) return rc;
+  c->two_step = best_id;
+  *best = best_id;
+  return LBM_OK;
+}
+
+int lbm_two_step_times(lbm_ctx* c, double* ms, int64_t* launches) {
+  if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
+  int rc = flush_timing(c);
+  if (rc) return rc;
+  if (ms) *ms = c->two_ms;
+  if (launches) *launches = c->two_n;
+  c->two_ms = 0;
+  c->two_n = 0;
   return LBM_OK;
 }
 

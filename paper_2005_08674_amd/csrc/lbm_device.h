@@ -119,6 +119,12 @@ template <class R> struct Base {
 };
 
 // ------------------------------------------------------------------ per-node arithmetic
+// 1 / x: fp64 divides (correctly rounded); fp32 takes the hardware
+// reciprocal (v_rcp_f32, within 1 ulp), which every kernel shares, so all
+// launch paths of one storage format still round alike.
+__device__ inline double recip(double x) { return 1.0 / x; }
+__device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // Moments of one node (eqs. cf_0/cf_1) from the deviations: with
 // sum_i f^eq_i(rho0, u_b) = rho0 and sum_i c_i f^eq_i(rho0, u_b) = rho0 u_b,
 //   drho = sum g_i,  rho u = rho0 u_b + sum c_i g_i,
@@ -128,7 +134,7 @@ __device__ inline void moments(const R g[9], R rho0, const Base<R>& b, R& drho, 
   drho = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
   const R jx = (g[1] - g[2]) + (g[5] - g[6]) + (g[8] - g[7]);
   const R jy = (g[3] - g[4]) + (g[5] - g[6]) + (g[7] - g[8]);
-  const R ir = R(1) / (rho0 + drho);
+  const R ir = recip(rho0 + drho);
   dux = (jx - drho * b.ubx) * ir;
   duy = (jy - drho * b.uby) * ir;
 }

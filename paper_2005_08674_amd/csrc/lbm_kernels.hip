@@ -23,6 +23,7 @@
 #include "lbm_device.h"
 #include "lbm_launch.h"
 #include "lbm_sweep.h"
+#include "lbm_twostep.h"
 
 namespace lbm {
 
@@ -35,6 +36,9 @@ namespace lbm {
 //            so the x-neighbours that share the shifted loads' straddling
 //            cache lines run back to back on one XCD, while the eight XCDs
 //            still work on eight adjacent rows.
+//   REMAP 3: block b sweeps the whole tile row b in x (a loop over the
+//            tiles), so every straddling cache line of the x-shifted loads is
+//            shared inside one workgroup and fetched from HBM once.
 template <int REMAP>
 __device__ inline bool bulk_tile(int tiles_x, int tiles_y, int& txi, int& tyi) {
   const int b = blockIdx.x;
@@ -59,6 +63,12 @@ __device__ inline bool bulk_tile(int tiles_x, int tiles_y, int& txi, int& tyi) {
 
 template <int S, int BX, int BY, int NYT, int REMAP, bool NTS, bool NTL>
 __global__ __launch_bounds__(BX* BY) void k_bulk(LatDesc L, int parity, int tiles_x, int tiles_y) {
+  if (REMAP == 3) {
+    const int tyi = blockIdx.x;
+    if (tyi >= tiles_y) return;
+    for (int txi = 0; txi < tiles_x; ++txi) bulk_tile_body<S, BX, BY, NYT, NTS, NTL>(L, parity, txi, tyi);
+    return;
+  }
   int txi, tyi;
   if (!bulk_tile<REMAP>(tiles_x, tiles_y, txi, tyi)) return;
   bulk_tile_body<S, BX, BY, NYT, NTS, NTL>(L, parity, txi, tyi);
@@ -98,7 +108,14 @@ struct TileShape {
   X(256, 1, 1, 0, false, false)        \
   X(256, 1, 2, 0, false, false)        \
   X(128, 2, 1, 0, false, false)        \
-  X(64, 4, 1, 0, false, false)
+  X(64, 4, 1, 0, false, false)         \
+  X(256, 1, 1, 3, true, true)          \
+  X(256, 1, 1, 3, true, false)         \
+  X(512, 1, 1, 3, true, true)          \
+  X(1024, 1, 1, 3, true, true)         \
+  X(256, 1, 2, 3, true, true)          \
+  X(128, 2, 1, 3, true, true)          \
+  X(256, 1, 2, 3, true, false)
 
 static const TileShape kTiles[] = {
 #define X(a, b, c, d, e, f) {a, b, c, d, e, f},
@@ -115,7 +132,8 @@ void tile_name(int id, char* buf, size_t len) {
     return;
   }
   const TileShape& t = kTiles[id];
-  snprintf(buf, len, "%dx%dx%d%s%s%s", t.bx, t.by, t.nyt, t.remap == 1 ? "+xcdband" : (t.remap == 2 ? "+xcdrow" : ""),
+  snprintf(buf, len, "%dx%dx%d%s%s%s", t.bx, t.by, t.nyt,
+           t.remap == 1 ? "+xcdband" : (t.remap == 2 ? "+xcdrow" : (t.remap == 3 ? "+rowsweep" : "")),
            t.nts ? "+nts" : "", t.ntl ? "+ntl" : "");
 }
 
@@ -127,7 +145,8 @@ static hipError_t launch_bulk_t(const LatDesc& L, int parity, hipStream_t s) {
   int grid;
   if (REMAP == 0) grid = tiles_x * tiles_y;
   else if (REMAP == 1) grid = ((tiles_x * tiles_y + 7) >> 3) * 8;
-  else grid = tiles_x * ((tiles_y + 7) >> 3) * 8;
+  else if (REMAP == 2) grid = tiles_x * ((tiles_y + 7) >> 3) * 8;
+  else grid = tiles_y;
   k_bulk<S, BX, BY, NYT, REMAP, NTS, NTL><<<dim3(grid), dim3(BX, BY), 0, s>>>(L, parity, tiles_x, tiles_y);
   return hipGetLastError();
 }
@@ -149,6 +168,93 @@ hipError_t launch_bulk(const LatDesc& L, int parity, int tile, hipStream_t s) {
     case ST_F32: return launch_bulk_s<ST_F32>(L, parity, tile, s);
     case ST_F16: return launch_bulk_s<ST_F16>(L, parity, tile, s);
     case ST_BF16: return launch_bulk_s<ST_BF16>(L, parity, tile, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------ two-step kernel
+// Candidate shapes of the two-step sweep: output rows per band (H),
+// non-temporal stores (NTS) and a register budget given as wavefronts per
+// SIMD (WPE; 0 = the compiler's choice; a larger count trades spills on the
+// lattice-edge path for occupancy on the interior path).
+#define LBM_TWO_STEP(X) \
+  X(32, true, 0)        \
+  X(64, true, 0)        \
+  X(128, true, 0)       \
+  X(64, false, 0)       \
+  X(32, true, 4)
+
+template <int S, int H, bool NTS>
+__global__ __launch_bounds__(64 * TS_WAVES) void k_two_step(LatDesc L, int parity) {
+  two_step_body<S, H, NTS>(L, parity);
+}
+template <int S, int H, bool NTS>
+__global__ __launch_bounds__(64 * TS_WAVES) __attribute__((amdgpu_waves_per_eu(4))) void k_two_step_w4(
+    LatDesc L, int parity) {
+  two_step_body<S, H, NTS>(L, parity);
+}
+template <int S, int H, bool NTS>
+__global__ __launch_bounds__(64 * TS_WAVES) __attribute__((amdgpu_waves_per_eu(5))) void k_two_step_w5(
+    LatDesc L, int parity) {
+  two_step_body<S, H, NTS>(L, parity);
+}
+
+struct TwoStepShape {
+  int h;
+  bool nts;
+  int wpe;
+};
+static const TwoStepShape kTwo[] = {
+#define X(a, b, c) {a, b, c},
+    LBM_TWO_STEP(X)
+#undef X
+};
+static constexpr int kNumTwo = sizeof(kTwo) / sizeof(kTwo[0]);
+
+int num_two_step() { return kNumTwo; }
+
+void two_step_name(int id, char* buf, size_t len) {
+  if (id < 0 || id >= kNumTwo) {
+    snprintf(buf, len, "invalid");
+    return;
+  }
+  const TwoStepShape& t = kTwo[id];
+  if (t.wpe) snprintf(buf, len, "2step:h%d%s+w%d", t.h, t.nts ? "+nts" : "", t.wpe);
+  else snprintf(buf, len, "2step:h%d%s", t.h, t.nts ? "+nts" : "");
+}
+
+bool two_step_supported(const LatDesc& L) {
+  return L.bc[E_LEFT] == BC_NSBC && L.bc[E_RIGHT] == BC_NSBC && L.bc[E_BOTTOM] == BC_NSBC &&
+         L.bc[E_TOP] == BC_NSBC && L.nx >= 3 && L.ny >= 3 && L.store != ST_F64;
+}
+
+template <int S, int H, bool NTS, int WPE>
+static hipError_t launch_two_t(const LatDesc& L, int parity, hipStream_t s) {
+  const int waves = (L.nx + TS_COLS - 1) / TS_COLS;
+  const dim3 grid((waves + TS_WAVES - 1) / TS_WAVES, (L.ny + H - 1) / H), block(64 * TS_WAVES);
+  if (WPE == 4) k_two_step_w4<S, H, NTS><<<grid, block, 0, s>>>(L, parity);
+  else if (WPE == 5) k_two_step_w5<S, H, NTS><<<grid, block, 0, s>>>(L, parity);
+  else k_two_step<S, H, NTS><<<grid, block, 0, s>>>(L, parity);
+  return hipGetLastError();
+}
+
+template <int S>
+static hipError_t launch_two_s(const LatDesc& L, int parity, int id, hipStream_t s) {
+  int k = 0;
+#define X(a, b, c)                                               \
+  if (id == k) return launch_two_t<S, a, b, c>(L, parity, s);   \
+  ++k;
+  LBM_TWO_STEP(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_two_step(const LatDesc& L, int parity, int id, hipStream_t s) {
+  if (!two_step_supported(L)) return hipErrorInvalidValue;
+  switch (L.store) {
+    case ST_F32: return launch_two_s<ST_F32>(L, parity, id, s);
+    case ST_F16: return launch_two_s<ST_F16>(L, parity, id, s);
+    case ST_BF16: return launch_two_s<ST_BF16>(L, parity, id, s);
   }
   return hipErrorInvalidValue;
 }

@@ -14,6 +14,10 @@ void tile_name(int id, char* buf, size_t len);
 hipError_t launch_bulk(const LatDesc& L, int parity, int tile, hipStream_t s);
 int edge_blocks(int nx, int ny);
 hipError_t launch_edge(const LatDesc& L, int parity, hipStream_t s);
+int num_two_step();
+void two_step_name(int id, char* buf, size_t len);
+bool two_step_supported(const LatDesc& L);
+hipError_t launch_two_step(const LatDesc& L, int parity, int id, hipStream_t s);
 hipError_t launch_init(const LatDesc& L, int parity, const double* drho, const double* ux, const double* uy,
                        hipStream_t s);
 int absmax_blocks();

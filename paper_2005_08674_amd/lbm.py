@@ -76,6 +76,12 @@ _SIGS = {
     "lbm_bulk_traffic": [_P, _P, _P],
     "lbm_set_overlap": [_P, ctypes.c_int],
     "lbm_stream_copy": [_P, _P, ctypes.c_size_t, _P],
+    "lbm_two_step_count": [],
+    "lbm_two_step_describe": [ctypes.c_int32, _P, ctypes.c_size_t],
+    "lbm_set_two_step": [_P, ctypes.c_int32],
+    "lbm_get_two_step": [_P, _P],
+    "lbm_autotune_two_step": [_P, ctypes.c_int32, _P, _P],
+    "lbm_two_step_times": [_P, _P, _P],
     # ensemble (include/lbm_ensemble.h)
     "lbm_ens_workspace_bytes": [_P, ctypes.c_int32, _P],
     "lbm_ens_init": [_P, _P, ctypes.c_int32, _P, ctypes.c_size_t, _P, _P, _P, _P],
@@ -259,6 +265,40 @@ def lbm_kernel_times(ctx):
     _check(load().lbm_kernel_times(ctx, ctypes.byref(bm), ctypes.byref(bn), ctypes.byref(em), ctypes.byref(en)),
            "lbm_kernel_times")
     return bm.value, bn.value, em.value, en.value
+
+
+def lbm_two_step_count() -> int:
+    return int(load().lbm_two_step_count())
+
+
+def lbm_two_step_describe(shape_id: int) -> str:
+    buf = ctypes.create_string_buffer(64)
+    _check(load().lbm_two_step_describe(int(shape_id), buf, 64), "lbm_two_step_describe")
+    return buf.value.decode()
+
+
+def lbm_set_two_step(ctx, shape_id: int):
+    _check(load().lbm_set_two_step(ctx, int(shape_id)), "lbm_set_two_step")
+
+
+def lbm_get_two_step(ctx) -> int:
+    t = ctypes.c_int32()
+    _check(load().lbm_get_two_step(ctx, ctypes.byref(t)), "lbm_get_two_step")
+    return t.value
+
+
+def lbm_autotune_two_step(ctx, reps: int = 5):
+    best = ctypes.c_int32()
+    n = lbm_two_step_count()
+    times = (ctypes.c_float * n)()
+    _check(load().lbm_autotune_two_step(ctx, int(reps), ctypes.byref(best), times), "lbm_autotune_two_step")
+    return best.value, list(times)
+
+
+def lbm_two_step_times(ctx):
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(load().lbm_two_step_times(ctx, ctypes.byref(ms), ctypes.byref(n)), "lbm_two_step_times")
+    return ms.value, n.value
 
 
 def lbm_set_overlap(ctx, on: bool):

@@ -1,0 +1,138 @@
+"""GPU two-step sweep: one launch advancing t -> t + 2 must give the same bits
+as two single steps (bulk + edge kernels), for every shape, storage format,
+NSBC reading and ragged size, and agree with the oracle at full size."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2005_08674_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2005_08674_amd import lbm
+    lbm.load()
+
+
+def _pair(nx, ny, store, shape, steps, **kw):
+    from paper_2005_08674_amd import lbm
+    from paper_2005_08674_amd.lattice import Lattice
+    rng = np.random.default_rng(nx * 1000 + ny)
+    f = W.gaussian_pulses(nx, ny, [(8e-4, max(2.0, min(nx, ny) / 6), rng.uniform(0, nx), rng.uniform(0, ny))],
+                          u0=kw.pop("u0", (0.03, -0.02)))
+    m0 = kw.pop("m0", (1.0002, 0.03, -0.02))
+    beta = kw.pop("beta", 0.2)
+    a = Lattice(nx, ny, 0.57, f, store=store, beta=beta, m0=m0, **kw)
+    b = Lattice(nx, ny, 0.57, f, store=store, beta=beta, m0=m0, **kw)
+    lbm.lbm_set_two_step(b.ctx, shape)
+    a.step(steps)
+    b.step(steps)
+    pa, pb = a.populations().cpu().numpy(), b.populations().cpu().numpy()
+    a.close()
+    b.close()
+    return pa, pb
+
+
+SIZES = [(203, 77), (61, 5), (3, 3), (4, 3), (3, 40), (62, 64), (121, 130), (240, 33), (241, 129), (480, 257)]
+
+
+@pytest.mark.parametrize("store", ["f32", "f16", "bf16"])
+def test_bitwise_equal_to_single_steps_all_shapes(store):
+    from paper_2005_08674_amd import lbm
+    for shape in range(lbm.lbm_two_step_count()):
+        name = lbm.lbm_two_step_describe(shape)
+        for nx, ny in SIZES:
+            print(f"[two-step] {store} {name} {nx}x{ny}", flush=True)
+            pa, pb = _pair(nx, ny, store, shape, 9)
+            assert np.isfinite(pa).all()
+            assert np.array_equal(pa, pb), (store, name, nx, ny, np.argwhere(pa != pb)[:5])
+
+
+@pytest.mark.parametrize("kw", [dict(grad_order=2), dict(corner_mode=1), dict(corr_mode=1),
+                                dict(ubase=(0.03, -0.02)), dict(gamma=0.3, beta=0.0)])
+def test_bitwise_equal_nsbc_readings(kw):
+    for nx, ny in [(130, 67), (64, 3)]:
+        print(f"[two-step] {kw} {nx}x{ny}", flush=True)
+        pa, pb = _pair(nx, ny, "f32", 1, 12, **dict(kw))
+        assert np.array_equal(pa, pb), (kw, nx, ny)
+
+
+def test_unsupported_lattices_are_refused():
+    from paper_2005_08674_amd import lbm
+    from paper_2005_08674_amd.lattice import Lattice
+    f = W.uniform(40, 30)
+    p = Lattice(40, 30, 0.6, f, store="f32", bc=(0, 0, 1, 1))
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_set_two_step(p.ctx, 0)
+    d = Lattice(40, 30, 0.6, f, store="f64")
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_set_two_step(d.ctx, 0)
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_set_two_step(d.ctx, lbm.lbm_two_step_count())
+    lbm.lbm_set_two_step(d.ctx, -1)
+
+
+def test_timing_counts_launches_and_odd_steps():
+    from paper_2005_08674_amd import lbm
+    from paper_2005_08674_amd.lattice import Lattice
+    f = W.gaussian_pulses(100, 90, [(1e-3, 5.0, 50.0, 45.0)])
+    g = Lattice(100, 90, 0.6, f, store="f32")
+    lbm.lbm_set_two_step(g.ctx, 1)
+    lbm.lbm_enable_timing(g.ctx, True)
+    g.step(7)
+    ms, n = lbm.lbm_two_step_times(g.ctx)
+    bm, bn, em, en = lbm.lbm_kernel_times(g.ctx)
+    assert n == 3 and bn == 1 and en == 1 and ms > 0
+    assert g.t == 7
+
+
+def test_closure_falls_back_to_single_steps():
+    """With the closure active the two-step shape is ignored: same bits as the closure alone."""
+    from paper_2005_08674_amd import lbm
+    from paper_2005_08674_amd.closure import Trainer, pack_params
+    from paper_2005_08674_amd.lattice import Lattice
+    p = {"W1": np.zeros((64, 96)), "b1": np.zeros(64), "W2": np.zeros((64, 64)), "b2": np.zeros(64),
+         "W3": np.zeros((3, 64)), "b3": np.array([0.01, 0.02, -0.01])}
+    tr = Trainer(pack_params(p), max_batch=1024)
+    blob = tr.export(4.0)
+    f = W.lamb_oseen(90, 70, 40.0, 30.0, 5.0, 0.03, (0.05, 0.0))
+    a = Lattice(90, 70, 0.6, f, store="f32", m0=(1.0, 0.05, 0.0))
+    b = Lattice(90, 70, 0.6, f, store="f32", m0=(1.0, 0.05, 0.0))
+    lbm.lbm_set_closure(a.ctx, blob.data_ptr(), 1)
+    lbm.lbm_set_closure(b.ctx, blob.data_ptr(), 1)
+    lbm.lbm_set_two_step(b.ctx, 0)
+    a.step(10)
+    b.step(10)
+    assert np.array_equal(a.populations().cpu().numpy(), b.populations().cpu().numpy())
+
+
+def test_full_size_4096_two_step_against_single_and_oracle():
+    """4096^2 FP32 (the HBM workload), tuned two-step shape: 10 steps bit-identical to the single-step
+    path and within the FP32 bound of the oracle."""
+    from paper_2005_08674_amd import lbm
+    from paper_2005_08674_amd.lattice import Lattice
+    w = W.pulses_4096()
+    a = Lattice(w.nx, w.ny, w.tau, w.fields, store="f32")
+    best, times = lbm.lbm_autotune_two_step(a.ctx, 3)
+    print(f"\n[two-step 4096^2] shapes: " + ", ".join(f"{lbm.lbm_two_step_describe(i)}={t:.4f} ms"
+                                                  for i, t in enumerate(times)), flush=True)
+    a.step(10)
+    ga = a.populations().cpu().numpy()
+    gm = a.moments_np()
+    a.close()
+    b = Lattice(w.nx, w.ny, w.tau, w.fields, store="f32")
+    b.step(10)
+    assert np.array_equal(ga, b.populations().cpu().numpy())
+    b.close()
+    o = oracle.Lattice(w.nx, w.ny, w.tau, *w.fields)
+    o.step(10)
+    om = o.moments()
+    er = np.abs(gm[0] - om[0]).max()
+    eu = max(np.abs(gm[1] - om[1]).max(), np.abs(gm[2] - om[2]).max()) / w.u_ref
+    print(f"[two-step 4096^2 fp32] e_rho={er:.3e} e_u={eu:.3e}", flush=True)
+    assert er <= 1e-5 and eu <= 1e-5
