@@ -181,7 +181,9 @@ int lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* best, float* times_ms);
 /* Per-kernel timing with HIP events on the context's stream.  While enabled,
  * every lbm_step launch of the bulk kernel and of the edge kernel is
  * bracketed by events; lbm_kernel_times synchronizes the stream and returns
- * the summed elapsed milliseconds and launch counts since the last reset. */
+ * the summed elapsed milliseconds and launch counts since the last reset.
+ * With the fused step launch (lbm_set_fused) each step is one launch, counted
+ * as a bulk launch; the edge count then stays 0. */
 int lbm_enable_timing(lbm_ctx* ctx, int on);
 int lbm_kernel_times(lbm_ctx* ctx, double* bulk_ms, int64_t* bulk_launches,
                      double* edge_ms, int64_t* edge_launches);
@@ -195,10 +197,17 @@ int lbm_kernel_times(lbm_ctx* ctx, double* bulk_ms, int64_t* bulk_launches,
  * lbm_step returns with the context's stream ordered after all its work. */
 int lbm_set_overlap(lbm_ctx* ctx, int on);
 
-/* Bytes the bulk kernel must move per interior node and step
- * (2 x 9 x bytes per stored population) and the interior node count
- * (nx-2)(ny-2) it updates per launch. */
+/* Bytes the bulk kernel must move per node and step (2 x 9 x bytes per
+ * stored population) and the node count it updates per launch: the interior
+ * (nx-2)(ny-2), or all nx*ny nodes with the fused step launch. */
 int lbm_bulk_traffic(const lbm_ctx* ctx, int64_t* bytes_per_node, int64_t* nodes_per_launch);
+
+/* on = 1 (the default): each single step is ONE launch whose first blocks
+ * run the edge/corner segments and the rest the bulk tiles, so the edge work
+ * overlaps the bulk stream instead of following it; results are identical to
+ * the two separate launches.  on = 0: separate edge and bulk launches.  The
+ * closure and the overlap option always use separate launches. */
+int lbm_set_fused(lbm_ctx* ctx, int on);
 
 /* Two-step sweep: for lattices with NSBC on all four edges and 16- or
  * 32-bit storage, one launch advances two time steps (t -> t + 2), keeping

@@ -53,9 +53,17 @@ int lbm_ens_set_farfield(lbm_ens* e, int32_t member, double beta, double rho_ref
 int lbm_ens_step(lbm_ens* e, int32_t n);
 
 /* Advance every member n >= 1 steps with one launch of a HIP graph holding
- * the n steps' 2n kernel launches.  The graph is captured and instantiated
- * on first use for this n (and step parity) and cached until lbm_ens_destroy. */
+ * the n steps' kernel launches (one per step when fused, else two).  The
+ * graph is captured and instantiated on first use for this n (and step
+ * parity) and cached until lbm_ens_destroy or a change of shape, fusion or
+ * closure set. */
 int lbm_ens_step_graph(lbm_ens* e, int32_t n);
+
+/* on = 1 (the default): each step is one launch whose first blocks run the
+ * members' edge segments and the rest their bulk tiles; on = 0: separate
+ * bulk and edge launches.  Identical results either way.  Steps in which a
+ * member runs the learned closure always use separate launches. */
+int lbm_ens_set_fused(lbm_ens* e, int on);
 
 /* Moments of one member, as lbm_moments. */
 int lbm_ens_moments(lbm_ens* e, int32_t member, void* drho_out, void* ux_out, void* uy_out, int out_f64,

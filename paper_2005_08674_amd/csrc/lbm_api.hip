@@ -195,6 +195,8 @@ struct lbm_ctx {
   int64_t two_n = 0;
   // two-step sweep shape (-1: off)
   int two_step = -1;
+  // edge segments and bulk tiles of a step in one launch
+  bool fused = true;
 };
 
 namespace {
@@ -206,9 +208,14 @@ int flush_timing(lbm_ctx* c) {
   for (size_t k = 0; k + 3 < c->ev_used; k += 4) {
     float a = 0, b = 0;
     HIPCHK(hipEventElapsedTime(&a, c->events[k], c->events[k + 1]));
-    if (c->ev_two[k / 4]) {
+    if (c->ev_two[k / 4] == 1) {
       c->two_ms += a;
       c->two_n += 1;
+      continue;
+    }
+    if (c->ev_two[k / 4] == 2) {  // fused step launch
+      c->bulk_ms += a;
+      c->bulk_n += 1;
       continue;
     }
     HIPCHK(hipEventElapsedTime(&b, c->events[k + 2], c->events[k + 3]));
@@ -237,7 +244,30 @@ int next_event(lbm_ctx* c, hipEvent_t* ev) {
 // Both read buffer `parity` and write disjoint node sets of the other one, so
 // within a step they are independent; across steps each waits for both
 // kernels of the previous step (events ev_bulk / ev_edge).
+bool use_fused(const lbm_ctx* c) { return c->fused && !c->overlap && !(c->L.closure && c->L.net); }
+
 int step_once(lbm_ctx* c) {
+  if (use_fused(c)) {
+    // one launch; timed as the step's bulk kernel (events 0, 1)
+    hipEvent_t t[4] = {nullptr, nullptr, nullptr, nullptr};
+    if (c->timing) {
+      if (c->ev_used + 4 > 4 * 4096) {
+        int rc = flush_timing(c);
+        if (rc) return rc;
+      }
+      for (int k = 0; k < 4; ++k) {
+        int rc = next_event(c, &t[k]);
+        if (rc) return rc;
+      }
+      c->ev_two.push_back(2);
+    }
+    if (t[0]) HIPCHK(hipEventRecord(t[0], c->stream));
+    HIPCHK(lbm::launch_step(c->L, c->parity, c->tile, c->stream));
+    if (t[1]) HIPCHK(hipEventRecord(t[1], c->stream));
+    c->parity ^= 1;
+    c->t += 1;
+    return LBM_OK;
+  }
   hipStream_t es = c->overlap ? c->side : c->stream;
   hipEvent_t t[4] = {nullptr, nullptr, nullptr, nullptr};
   if (c->timing) {
@@ -664,7 +694,14 @@ int lbm_kernel_times(lbm_ctx* c, double* bulk_ms, int64_t* bulk_launches, double
 int lbm_bulk_traffic(const lbm_ctx* c, int64_t* bytes_per_node, int64_t* nodes_per_launch) {
   if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
   if (bytes_per_node) *bytes_per_node = 18 * (int64_t)c->lay.esize;
-  if (nodes_per_launch) *nodes_per_launch = (int64_t)(c->p.nx - 2) * (c->p.ny - 2);
+  if (nodes_per_launch)
+    *nodes_per_launch = use_fused(c) ? (int64_t)c->p.nx * c->p.ny : (int64_t)(c->p.nx - 2) * (c->p.ny - 2);
+  return LBM_OK;
+}
+
+int lbm_set_fused(lbm_ctx* c, int on) {
+  if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
+  c->fused = on != 0;
   return LBM_OK;
 }
 

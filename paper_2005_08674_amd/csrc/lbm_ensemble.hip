@@ -62,6 +62,33 @@ __global__ __launch_bounds__(EDGE_THREADS) void k_ens_edge_closure(const LatDesc
   else edge_segment_body<S, false>(L, parity, sg.edge, sg.seg, mom, nullptr);
 }
 
+// Entry of the fused step's work list: a bulk tile (lat, txi, tyi), an edge
+// segment (lat, edge, seg) or padding.
+enum EnsWorkKind : int32_t { W_TILE = 0, W_SEG = 1, W_NONE = 2 };
+struct EnsWork {
+  int32_t lat, a, b, kind;
+};
+
+// One launch per ensemble step (no member on the closure).  Block i takes
+// work item i, and runs on XCD i mod 8: the host orders the list so that each
+// band of 64 rows of a member -- its bulk tiles, then the left and right edge
+// segments of those rows -- sits on one XCD back to back, so the edge blocks'
+// strided column reads find the lines the band's bulk tiles just pulled
+// through that XCD's L2.  Identical results to the separate launches.
+template <int S, int BX, int BY, int NYT>
+__global__ __launch_bounds__(BX* BY) void k_ens_step(const LatDesc* __restrict__ descs,
+                                                     const EnsWork* __restrict__ work, int parity) {
+  __shared__ typename Codec<S>::R mom[3][DEPTH][STRIP];
+  const EnsWork w = work[blockIdx.x];
+  if (w.kind == W_NONE) return;
+  const LatDesc L = descs[w.lat];
+  if (w.kind == W_SEG) {
+    edge_segment_body<S, false>(L, parity, w.a, w.b, mom, nullptr);
+    return;
+  }
+  bulk_tile_body<S, BX, BY, NYT, true, false>(L, parity, w.a, w.b);
+}
+
 struct EnsShape {
   int bx, by, nyt;
 };
@@ -114,6 +141,33 @@ static hipError_t launch_ens_bulk(int store, int shape, const LatDesc* d, const 
   return hipErrorInvalidValue;
 }
 
+template <int S>
+static hipError_t launch_ens_step_s(int shape, const LatDesc* d, const EnsWork* w, int nw, int parity,
+                                   hipStream_t s) {
+  int id = 0;
+#define X(a, b, c)                                                                 \
+  if (shape == id) {                                                               \
+    k_ens_step<S, a, b, c><<<dim3(nw), dim3(a, b), 0, s>>>(d, w, parity);          \
+    return hipGetLastError();                                                      \
+  }                                                                                \
+  ++id;
+  LBM_ENS_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+static hipError_t launch_ens_step(int store, int shape, const LatDesc* d, const EnsWork* w, int nw, int parity,
+                                  hipStream_t s) {
+  if (nw <= 0) return hipSuccess;
+  switch (store) {
+    case ST_F64: return launch_ens_step_s<ST_F64>(shape, d, w, nw, parity, s);
+    case ST_F32: return launch_ens_step_s<ST_F32>(shape, d, w, nw, parity, s);
+    case ST_F16: return launch_ens_step_s<ST_F16>(shape, d, w, nw, parity, s);
+    case ST_BF16: return launch_ens_step_s<ST_BF16>(shape, d, w, nw, parity, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 static hipError_t launch_ens_edge(int store, bool closure, const LatDesc* d, const EnsSeg* sg, int n, int parity,
                                   hipStream_t s) {
   if (n <= 0) return hipSuccess;
@@ -147,8 +201,8 @@ using lbm::host::fail;
 constexpr size_t kAlign = 4096;
 
 struct EnsLayout {
-  size_t off_descs, off_tiles, off_segs, off_scratch, off_lattices, total;
-  size_t max_tiles, nsegs;
+  size_t off_descs, off_tiles, off_segs, off_work, off_scratch, off_lattices, total;
+  size_t max_tiles, nsegs, max_work;
   std::vector<size_t> lat_off;  // member buffers, relative to the workspace
   std::vector<lbm::host::Layout> lat;
 };
@@ -183,6 +237,11 @@ int ens_layout(const lbm_params* m, int32_t count, EnsLayout& L) {
   off = round_up(off + sizeof(lbm::EnsTile) * L.max_tiles, kAlign);
   L.off_segs = off;
   off = round_up(off + sizeof(lbm::EnsSeg) * L.nsegs, kAlign);
+  // work list of the fused step: every tile and segment plus the padding that
+  // evens out the eight per-XCD lists (at most 7 entries per list item)
+  L.max_work = 8 * (L.max_tiles + L.nsegs) + 64;
+  L.off_work = off;
+  off = round_up(off + sizeof(lbm::EnsWork) * L.max_work, kAlign);
   L.off_scratch = off;
   off = round_up(off + lbm::host::kScratchBytes, (size_t)2 << 20);
   L.off_lattices = off;
@@ -209,7 +268,8 @@ struct lbm_ens {
   lbm::LatDesc* d_descs = nullptr;
   lbm::EnsTile* d_tiles = nullptr;
   lbm::EnsSeg* d_segs = nullptr;
-  int32_t ntiles = 0, nsegs = 0;
+  lbm::EnsWork* d_work = nullptr;
+  int32_t ntiles = 0, nsegs = 0, nwork = 0;
   int shape = 0;
   int parity = 0;
   int64_t t = 0;
@@ -217,6 +277,7 @@ struct lbm_ens {
   hipStream_t cap = nullptr;  // private stream used for graph capture
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
   bool any_closure = false;
+  bool fused = true;  // one launch per step when no member runs the closure
 };
 
 namespace {
@@ -243,16 +304,60 @@ int build_tiles(lbm_ens* e, int shape) {
       for (int i = 0; i < tx; ++i) tiles.push_back({k, i, j, 0});
   }
   if (tiles.size() > e->lay.max_tiles) return fail(LBM_ERR_STATE, "tile table overflow");
+  // Work list of the fused step: bands of SEG rows per member, each holding
+  // the bulk tiles whose first row lies in it, then that band's left and
+  // right edge segments (the bottom/top segments join the first/last band);
+  // bands go whole to the least loaded of the 8 XCD lists, which are then
+  // interleaved (entry 8 j + k is item j of list k) and padded to one length.
+  std::vector<std::vector<lbm::EnsWork>> xcd(8);
+  std::vector<size_t> load(8, 0);
+  const int rpt = s.by * s.nyt;
+  for (int32_t k = 0; k < e->count; ++k) {
+    const int nx = e->p[k].nx, ny = e->p[k].ny;
+    const int tx = (nx + s.bx - 1) / s.bx;
+    const int ty = (ny - 2 + rpt - 1) / rpt;
+    const int nsv = lbm::edge_segments_v(ny), nsh = lbm::edge_segments_h(nx);
+    std::vector<std::vector<lbm::EnsWork>> bands(nsv);
+    for (int j = 0; j < ty; ++j) {
+      const int band = std::min((1 + j * rpt) / lbm::SEG, nsv - 1);
+      for (int i = 0; i < tx; ++i) bands[band].push_back({k, i, j, lbm::W_TILE});
+    }
+    for (int b = 0; b < nsv; ++b) {
+      bands[b].push_back({k, lbm::E_LEFT, b, lbm::W_SEG});
+      bands[b].push_back({k, lbm::E_RIGHT, b, lbm::W_SEG});
+    }
+    for (int b = 0; b < nsh; ++b) {
+      bands[0].push_back({k, lbm::E_BOTTOM, b, lbm::W_SEG});
+      bands[nsv - 1].push_back({k, lbm::E_TOP, b, lbm::W_SEG});
+    }
+    for (auto& band : bands) {
+      const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      xcd[x].insert(xcd[x].end(), band.begin(), band.end());
+      load[x] += band.size();
+    }
+  }
+  const size_t len = *std::max_element(load.begin(), load.end());
+  std::vector<lbm::EnsWork> work(8 * len, lbm::EnsWork{0, 0, 0, lbm::W_NONE});
+  for (int x = 0; x < 8; ++x)
+    for (size_t j = 0; j < xcd[x].size(); ++j) work[8 * j + x] = xcd[x][j];
+  if (work.size() > e->lay.max_work) return fail(LBM_ERR_STATE, "work list overflow");
   HIPCHK(hipMemcpyAsync(e->d_tiles, tiles.data(), sizeof(lbm::EnsTile) * tiles.size(), hipMemcpyHostToDevice,
+                        e->stream));
+  HIPCHK(hipMemcpyAsync(e->d_work, work.data(), sizeof(lbm::EnsWork) * work.size(), hipMemcpyHostToDevice,
                         e->stream));
   HIPCHK(hipStreamSynchronize(e->stream));
   e->ntiles = (int32_t)tiles.size();
+  e->nwork = (int32_t)work.size();
   e->shape = shape;
   drop_graphs(e);
   return LBM_OK;
 }
 
 int ens_launch_step(lbm_ens* e, int parity, hipStream_t s) {
+  if (!e->any_closure && e->fused) {
+    HIPCHK(lbm::launch_ens_step(e->store, e->shape, e->d_descs, e->d_work, e->nwork, parity, s));
+    return LBM_OK;
+  }
   HIPCHK(lbm::launch_ens_bulk(e->store, e->shape, e->d_descs, e->d_tiles, e->ntiles, parity, s));
   HIPCHK(lbm::launch_ens_edge(e->store, e->any_closure, e->d_descs, e->d_segs, e->nsegs, parity, s));
   return LBM_OK;
@@ -306,6 +411,7 @@ int lbm_ens_init(lbm_ens** out, const lbm_params* members, int32_t count, void* 
   e->d_descs = reinterpret_cast<lbm::LatDesc*>(e->ws + lay.off_descs);
   e->d_tiles = reinterpret_cast<lbm::EnsTile*>(e->ws + lay.off_tiles);
   e->d_segs = reinterpret_cast<lbm::EnsSeg*>(e->ws + lay.off_segs);
+  e->d_work = reinterpret_cast<lbm::EnsWork*>(e->ws + lay.off_work);
   if (hipStreamCreateWithFlags(&e->cap, hipStreamNonBlocking) != hipSuccess) {
     lbm_ens_destroy(e);
     return fail(LBM_ERR_HIP, "capture stream creation failed");
@@ -467,6 +573,13 @@ int lbm_ens_set_closure(lbm_ens* e, int32_t member, const void* net, int mode) {
   if (any != e->any_closure) drop_graphs(e);  // captured launches name the kernel variant
   e->any_closure = any;
   return upload_descs(e);
+}
+
+int lbm_ens_set_fused(lbm_ens* e, int on) {
+  if (!e) return fail(LBM_ERR_ARG, "ensemble is NULL");
+  if ((on != 0) != e->fused) drop_graphs(e);  // captured launches name the kernels
+  e->fused = on != 0;
+  return LBM_OK;
 }
 
 int lbm_ens_closure_features(lbm_ens* e, const int32_t* sites, int32_t n, float* feat_out, float* mc_out) {

@@ -40,8 +40,7 @@ namespace lbm {
 //            tiles), so every straddling cache line of the x-shifted loads is
 //            shared inside one workgroup and fetched from HBM once.
 template <int REMAP>
-__device__ inline bool bulk_tile(int tiles_x, int tiles_y, int& txi, int& tyi) {
-  const int b = blockIdx.x;
+__device__ inline bool bulk_tile(int b, int tiles_x, int tiles_y, int& txi, int& tyi) {
   if (REMAP == 2) {
     const int seq = b >> 3;
     const int grp = seq / tiles_x;
@@ -61,17 +60,42 @@ __device__ inline bool bulk_tile(int tiles_x, int tiles_y, int& txi, int& tyi) {
   return true;
 }
 
+// Bulk block b (in the launch's own numbering) of the tile grid.
 template <int S, int BX, int BY, int NYT, int REMAP, bool NTS, bool NTL>
-__global__ __launch_bounds__(BX* BY) void k_bulk(LatDesc L, int parity, int tiles_x, int tiles_y) {
+__device__ inline void bulk_block(const LatDesc& L, int parity, int b, int tiles_x, int tiles_y) {
   if (REMAP == 3) {
-    const int tyi = blockIdx.x;
+    const int tyi = b;
     if (tyi >= tiles_y) return;
     for (int txi = 0; txi < tiles_x; ++txi) bulk_tile_body<S, BX, BY, NYT, NTS, NTL>(L, parity, txi, tyi);
     return;
   }
   int txi, tyi;
-  if (!bulk_tile<REMAP>(tiles_x, tiles_y, txi, tyi)) return;
+  if (!bulk_tile<REMAP>(b, tiles_x, tiles_y, txi, tyi)) return;
   bulk_tile_body<S, BX, BY, NYT, NTS, NTL>(L, parity, txi, tyi);
+}
+
+template <int S, int BX, int BY, int NYT, int REMAP, bool NTS, bool NTL>
+__global__ __launch_bounds__(BX* BY) void k_bulk(LatDesc L, int parity, int tiles_x, int tiles_y) {
+  bulk_block<S, BX, BY, NYT, REMAP, NTS, NTL>(L, parity, blockIdx.x, tiles_x, tiles_y);
+}
+
+// One launch per step: blocks [0, eblocks) run the edge kernel's segments,
+// the rest the bulk tiles (numbered from a multiple of 8, so the XCD-aware
+// block maps keep their meaning).  Both halves read buffer `parity` and write
+// disjoint nodes of the other buffer, exactly as the two separate launches.
+template <int S, int BX, int BY, int NYT, int REMAP, bool NTS, bool NTL>
+__global__ __launch_bounds__(BX* BY) void k_step(LatDesc L, int parity, int tiles_x, int tiles_y, int eblocks,
+                                                 int eoffset) {
+  __shared__ typename Codec<S>::R mom[3][DEPTH][STRIP];
+  const int b = blockIdx.x;
+  if (b < eoffset) {
+    if (b >= eblocks) return;  // padding to the multiple of 8 (uniform per block)
+    int seg = b, edge;
+    edge_of_block(L.nx, L.ny, seg, edge);
+    edge_segment_body<S, false>(L, parity, edge, seg, mom, nullptr);
+    return;
+  }
+  bulk_block<S, BX, BY, NYT, REMAP, NTS, NTL>(L, parity, b - eoffset, tiles_x, tiles_y);
 }
 
 struct TileShape {
@@ -135,6 +159,46 @@ void tile_name(int id, char* buf, size_t len) {
   snprintf(buf, len, "%dx%dx%d%s%s%s", t.bx, t.by, t.nyt,
            t.remap == 1 ? "+xcdband" : (t.remap == 2 ? "+xcdrow" : (t.remap == 3 ? "+rowsweep" : "")),
            t.nts ? "+nts" : "", t.ntl ? "+ntl" : "");
+}
+
+int edge_blocks(int nx, int ny);
+
+template <int S, int BX, int BY, int NYT, int REMAP, bool NTS, bool NTL>
+static hipError_t launch_step_t(const LatDesc& L, int parity, hipStream_t s) {
+  const int tiles_x = (L.nx + BX - 1) / BX;
+  const int tiles_y = (L.ny - 2 + BY * NYT - 1) / (BY * NYT);
+  int grid;
+  if (REMAP == 0) grid = tiles_x * tiles_y;
+  else if (REMAP == 1) grid = ((tiles_x * tiles_y + 7) >> 3) * 8;
+  else if (REMAP == 2) grid = tiles_x * ((tiles_y + 7) >> 3) * 8;
+  else grid = tiles_y;
+  const int eb = edge_blocks(L.nx, L.ny);
+  const int eo = (eb + 7) & ~7;
+  k_step<S, BX, BY, NYT, REMAP, NTS, NTL><<<dim3(eo + grid), dim3(BX, BY), 0, s>>>(L, parity, tiles_x, tiles_y,
+                                                                                   eb, eo);
+  return hipGetLastError();
+}
+
+template <int S>
+static hipError_t launch_step_s(const LatDesc& L, int parity, int tile, hipStream_t s) {
+  int id = 0;
+#define X(a, b, c, d, e, f)                                                \
+  if (tile == id) return launch_step_t<S, a, b, c, d, e, f>(L, parity, s); \
+  ++id;
+  LBM_TILES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_step(const LatDesc& L, int parity, int tile, hipStream_t s) {
+  if (L.closure && L.net) return hipErrorInvalidValue;
+  switch (L.store) {
+    case ST_F64: return launch_step_s<ST_F64>(L, parity, tile, s);
+    case ST_F32: return launch_step_s<ST_F32>(L, parity, tile, s);
+    case ST_F16: return launch_step_s<ST_F16>(L, parity, tile, s);
+    case ST_BF16: return launch_step_s<ST_BF16>(L, parity, tile, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <int S, int BX, int BY, int NYT, int REMAP, bool NTS, bool NTL>

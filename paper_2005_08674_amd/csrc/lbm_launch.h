@@ -14,6 +14,8 @@ void tile_name(int id, char* buf, size_t len);
 hipError_t launch_bulk(const LatDesc& L, int parity, int tile, hipStream_t s);
 int edge_blocks(int nx, int ny);
 hipError_t launch_edge(const LatDesc& L, int parity, hipStream_t s);
+// edge segments and bulk tiles of one step in a single launch (not with the closure)
+hipError_t launch_step(const LatDesc& L, int parity, int tile, hipStream_t s);
 int num_two_step();
 void two_step_name(int id, char* buf, size_t len);
 bool two_step_supported(const LatDesc& L);

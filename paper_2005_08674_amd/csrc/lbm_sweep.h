@@ -155,7 +155,10 @@ __device__ inline void edge_segment_body(const LatDesc& L, int parity, int edge,
   const int64_t plane = L.plane;
   const R rho0 = R(L.rho0);
   const Base<R> base(L);
-  const int tid = threadIdx.x;
+  // linear thread index: the edge body also runs in the fused step kernels,
+  // whose blocks are 2-D and may hold more than EDGE_THREADS threads (the
+  // extra ones only pass the barriers)
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x;
 
   // Lanes 0..SEG-1 own one boundary node each: pull its known populations
   // (wrapping across periodic edges) and mark those whose source lies

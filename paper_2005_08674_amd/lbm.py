@@ -75,6 +75,7 @@ _SIGS = {
     "lbm_kernel_times": [_P, _P, _P, _P, _P],
     "lbm_bulk_traffic": [_P, _P, _P],
     "lbm_set_overlap": [_P, ctypes.c_int],
+    "lbm_set_fused": [_P, ctypes.c_int],
     "lbm_stream_copy": [_P, _P, ctypes.c_size_t, _P],
     "lbm_two_step_count": [],
     "lbm_two_step_describe": [ctypes.c_int32, _P, ctypes.c_size_t],
@@ -89,6 +90,7 @@ _SIGS = {
                              ctypes.c_double],
     "lbm_ens_step": [_P, ctypes.c_int32],
     "lbm_ens_step_graph": [_P, ctypes.c_int32],
+    "lbm_ens_set_fused": [_P, ctypes.c_int],
     "lbm_ens_moments": [_P, ctypes.c_int32, _P, _P, _P, ctypes.c_int, ctypes.c_int],
     "lbm_ens_get_populations": [_P, ctypes.c_int32, _P],
     "lbm_ens_time": [_P, _P],
@@ -301,6 +303,10 @@ def lbm_two_step_times(ctx):
     return ms.value, n.value
 
 
+def lbm_set_fused(ctx, on: bool):
+    _check(load().lbm_set_fused(ctx, int(on)), "lbm_set_fused")
+
+
 def lbm_set_overlap(ctx, on: bool):
     _check(load().lbm_set_overlap(ctx, int(on)), "lbm_set_overlap")
 
@@ -342,6 +348,10 @@ def lbm_ens_step(ens, n: int):
 
 def lbm_ens_step_graph(ens, n: int):
     _check(load().lbm_ens_step_graph(ens, int(n)), "lbm_ens_step_graph")
+
+
+def lbm_ens_set_fused(ens, on: bool):
+    _check(load().lbm_ens_set_fused(ens, int(on)), "lbm_ens_set_fused")
 
 
 def lbm_ens_moments(ens, member, drho_ptr, ux_ptr, uy_ptr, out_f64=True, deviation=True):

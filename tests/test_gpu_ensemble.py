@@ -65,6 +65,32 @@ def test_members_bitwise_equal_standalone(store):
         g.close()
 
 
+@pytest.mark.parametrize("store", ["f32", "f16", "f64"])
+def test_fused_step_equals_separate_launches(store):
+    """One launch per ensemble step gives the bits of separate bulk and edge launches, eagerly and
+    through graphs, for every shape."""
+    from paper_2005_08674_amd import lbm
+    from paper_2005_08674_amd.ensemble import Ensemble
+    members, fields, far = _mixed_members(store)
+    for shape in range(lbm.lbm_ens_shape_count()):
+        a = Ensemble(members, fields)
+        b = Ensemble(members, fields)
+        for m, fa in enumerate(far):
+            a.set_farfield(m, *fa)
+            b.set_farfield(m, *fa)
+        lbm.lbm_ens_set_shape(a.ens, shape)
+        lbm.lbm_ens_set_shape(b.ens, shape)
+        lbm.lbm_ens_set_fused(b.ens, False)
+        a.step(3)
+        b.step(3)
+        a.step_graph(4)
+        b.step_graph(4)
+        for m in range(len(members)):
+            assert np.array_equal(a.populations(m), b.populations(m)), (store, shape, m)
+        a.close()
+        b.close()
+
+
 def test_fp64_members_match_oracle():
     from paper_2005_08674_amd.ensemble import Ensemble
     members, fields, far = _mixed_members("f64")
