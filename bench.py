@@ -203,8 +203,8 @@ CLOSURE_NET = os.path.join(ROOT, "paper_2005_08674_amd", "data", "closure_c4.npz
 
 
 def run_c5(torch, W, steps, every=50, timing_steps=1000):
-    """Vortex + pulse on a 2048^2 lattice (tau 0.55, u0 = (0.1, 0)): plain NSBC in FP32, NSBC with FP16
-    deviation storage, and the learned closure (FP32), each with its MLUPS (test lattice alone) and its
+    """Vortex + pulse on a 2048^2 lattice (tau 0.55, u0 = (0.1, 0)): plain NSBC and the learned closure,
+    each with FP32 and FP16 deviation storage, each with its MLUPS (test lattice alone) and its
     reflection coefficient R_E against an 8192^2 FP32 reference over `steps` steps."""
     from paper_2005_08674_amd import lbm
     from paper_2005_08674_amd.lattice import Lattice
@@ -231,7 +231,7 @@ def run_c5(torch, W, steps, every=50, timing_steps=1000):
            "steps": steps, "energy_every": every}
     runs = [("nsbc_f32", "f32", None), ("nsbc_f16", "f16", None)]
     if blob is not None:
-        runs.append(("closure_f32", "f32", blob))
+        runs += [("closure_f32", "f32", blob), ("closure_f16", "f16", blob)]
     for name, store, net in runs:
         g = Lattice(n, n, w.tau, w.fields, store=store, m0=(1.0, 0.1, 0.0), ubase=u0)
         if net is not None:

@@ -167,9 +167,10 @@ int lbm_energy(lbm_ctx* test, const lbm_ctx* ref, int32_t x_off, int32_t y_off,
  * shapes; lbm_tile_describe writes a short text name of candidate `id` into
  * buf; lbm_set_tile selects one for this context (the default is chosen from
  * the lattice and storage).  lbm_autotune times every candidate on the
- * context's own lattice (`reps` timed launches each, median of those, after
- * one warm-up; the state is saved and restored around the timing) and selects
- * the fastest; it writes the chosen id to *best and, if times_ms is not NULL,
+ * context's own lattice as the launch lbm_step uses (the fused step launch,
+ * or the bulk kernel when fusion is off), `reps` timed launches each, median
+ * of those, after one warm-up, leaving the state unchanged, and selects the
+ * fastest; it writes the chosen id to *best and, if times_ms is not NULL,
  * the per-candidate median launch time in milliseconds (length
  * lbm_tile_count).  Synchronizes the stream. */
 int lbm_tile_count(void);

@@ -120,7 +120,11 @@ void fill_desc(LatDesc& L, const lbm_params* p, const Layout& lay, void* buf0, v
   for (int i = 0; i < 9; ++i) {
     const double cu = kCx[i] * p->ubase[0] + kCy[i] * p->ubase[1];
     L.pb[i] = 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * (p->ubase[0] * p->ubase[0] + p->ubase[1] * p->ubase[1]);
+    L.pbf[i] = static_cast<float>(L.pb[i]);
   }
+  L.ubf[0] = static_cast<float>(L.ub[0]);
+  L.ubf[1] = static_cast<float>(L.ub[1]);
+  L.ub_zero = p->ubase[0] == 0.0 && p->ubase[1] == 0.0;
   // far field m0 = (rho0, 0, 0) until set
   L.m0[0] = 0.0;
   L.m0[1] = -p->ubase[0];
@@ -554,8 +558,14 @@ int lbm_get_tile(const lbm_ctx* c, int32_t* id) {
 int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* best, float* times_ms) {
   if (!c || !best) return fail(LBM_ERR_ARG, "NULL argument");
   if (reps < 1 || reps > 1000) return fail(LBM_ERR_ARG, "reps = %d outside [1, 1000]", reps);
-  // The bulk kernel reads buffer `parity` and writes only the other one, so
-  // relaunching it leaves the state untouched.
+  // The kernel timed is the one lbm_step launches: the fused step (edge
+  // segments + bulk tiles) or, without fusion, the bulk kernel.  Both read
+  // buffer `parity` and write only the other one, so relaunching them leaves
+  // the state untouched.
+  const bool fused = use_fused(c);
+  auto launch = [&](int id) {
+    return fused ? lbm::launch_step(c->L, c->parity, id, c->stream) : lbm::launch_bulk(c->L, c->parity, id, c->stream);
+  };
   const int nt = lbm::num_tiles();
   std::vector<hipEvent_t> ev(2 * reps);
   for (auto& e : ev) HIPCHK(hipEventCreate(&e));
@@ -563,10 +573,10 @@ int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* best, float* times_ms) {
   int best_id = c->tile;
   int rc = LBM_OK;
   for (int id = 0; id < nt && rc == LBM_OK; ++id) {
-    hipError_t e = lbm::launch_bulk(c->L, c->parity, id, c->stream);
+    hipError_t e = launch(id);
     for (int r = 0; r < reps && e == hipSuccess; ++r) {
       e = hipEventRecord(ev[2 * r], c->stream);
-      if (e == hipSuccess) e = lbm::launch_bulk(c->L, c->parity, id, c->stream);
+      if (e == hipSuccess) e = launch(id);
       if (e == hipSuccess) e = hipEventRecord(ev[2 * r + 1], c->stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);

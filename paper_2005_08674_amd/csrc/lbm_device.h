@@ -101,6 +101,9 @@ struct LatDesc {
   float es[9];      // encode scale per population
   const void* net;  // closure network (lbm::mlp::Net) or null
   int32_t closure;  // 1: the edge kernel replaces NSBC's m_c by the network's, NSBC as fallback
+  int32_t ub_zero;  // 1 when u_b = (0, 0): the arithmetic drops the u_b terms
+  float ubf[2];     // u_b and P_i(u_b) rounded to fp32 once, for the fp32 arithmetic
+  float pbf[9];
   int32_t _pad2;
 };
 
@@ -108,13 +111,27 @@ struct LatDesc {
 // access, so a descriptor copied into registers stays in registers.
 __host__ __device__ inline void* buf_of(const LatDesc& L, int parity) { return parity ? L.buf[1] : L.buf[0]; }
 
-// Base state of the deviation form in the arithmetic type.
-template <class R> struct Base {
-  R ubx, uby;
-  R pb[9];
-  __device__ inline explicit Base(const LatDesc& L) : ubx(R(L.ub[0])), uby(R(L.ub[1])) {
+// Base state of the deviation form in the arithmetic type.  `zero` marks
+// u_b = 0, for which the u_b terms below vanish exactly and are skipped (the
+// remaining operations and their order are unchanged, so both forms round
+// alike).
+template <class R> struct Base;
+template <> struct Base<double> {
+  double ubx, uby;
+  double pb[9];
+  bool zero;
+  __device__ inline explicit Base(const LatDesc& L) : ubx(L.ub[0]), uby(L.ub[1]), zero(L.ub_zero != 0) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) pb[i] = R(L.pb[i]);
+    for (int i = 0; i < 9; ++i) pb[i] = L.pb[i];
+  }
+};
+template <> struct Base<float> {
+  float ubx, uby;
+  float pb[9];
+  bool zero;
+  __device__ inline explicit Base(const LatDesc& L) : ubx(L.ubf[0]), uby(L.ubf[1]), zero(L.ub_zero != 0) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) pb[i] = L.pbf[i];
   }
 };
 
@@ -135,8 +152,13 @@ __device__ inline void moments(const R g[9], R rho0, const Base<R>& b, R& drho, 
   const R jx = (g[1] - g[2]) + (g[5] - g[6]) + (g[8] - g[7]);
   const R jy = (g[3] - g[4]) + (g[5] - g[6]) + (g[7] - g[8]);
   const R ir = recip(rho0 + drho);
-  dux = (jx - drho * b.ubx) * ir;
-  duy = (jy - drho * b.uby) * ir;
+  if (b.zero) {
+    dux = jx * ir;
+    duy = jy * ir;
+  } else {
+    dux = (jx - drho * b.ubx) * ir;
+    duy = (jy - drho * b.uby) * ir;
+  }
 }
 
 // Discrete equilibrium (eq. feq_1, c_s^2 = 1/3) minus the base equilibrium:
@@ -147,6 +169,16 @@ __device__ inline void moments(const R g[9], R rho0, const Base<R>& b, R& drho, 
 template <class R>
 __device__ inline void equilibrium(R rho0, const Base<R>& b, R drho, R dux, R duy, R geq[9]) {
   const R rho = rho0 + drho;
+  if (b.zero) {
+    // u_b = 0: b_i = 0 and P_i(u_b) = 1, so w_i [drho + rho (a (3 + 9/2 a) - 3/2 du.du)]
+    const R q = R(1.5) * (dux * dux + duy * duy);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const R a = R(kCx[i]) * dux + R(kCy[i]) * duy;
+      geq[i] = wgt<R>(i) * (drho + rho * fma(a, fma(R(4.5), a, R(3)), -q));
+    }
+    return;
+  }
   const R q = R(1.5) * (dux * (dux + R(2) * b.ubx) + duy * (duy + R(2) * b.uby));
 #pragma unroll
   for (int i = 0; i < 9; ++i) {

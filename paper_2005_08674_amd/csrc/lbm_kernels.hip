@@ -39,6 +39,10 @@ namespace lbm {
 //   REMAP 3: block b sweeps the whole tile row b in x (a loop over the
 //            tiles), so every straddling cache line of the x-shifted loads is
 //            shared inside one workgroup and fetched from HBM once.
+//   REMAP 4: in each run of 64 blocks, XCD k takes 8 consecutive tiles
+//            (tiles 64 g + 8 k .. 64 g + 8 k + 7), so only one tile boundary
+//            in 8 crosses XCDs, while the 64 blocks in flight still cover one
+//            contiguous stretch of tiles as in REMAP 0.
 template <int REMAP>
 __device__ inline bool bulk_tile(int b, int tiles_x, int tiles_y, int& txi, int& tyi) {
   if (REMAP == 2) {
@@ -50,6 +54,7 @@ __device__ inline bool bulk_tile(int b, int tiles_x, int tiles_y, int& txi, int&
   }
   const int ntiles = tiles_x * tiles_y;
   int tile = b;
+  if (REMAP == 4) tile = (b & ~63) + ((b & 7) << 3) + ((b >> 3) & 7);
   if (REMAP == 1) {
     const int per = (ntiles + 7) >> 3;
     tile = (b & 7) * per + (b >> 3);
@@ -139,7 +144,12 @@ struct TileShape {
   X(1024, 1, 1, 3, true, true)         \
   X(256, 1, 2, 3, true, true)          \
   X(128, 2, 1, 3, true, true)          \
-  X(256, 1, 2, 3, true, false)
+  X(256, 1, 2, 3, true, false)        \
+  X(256, 1, 1, 4, true, true)          \
+  X(256, 1, 1, 4, true, false)         \
+  X(512, 1, 1, 4, true, true)          \
+  X(128, 2, 1, 4, true, false)         \
+  X(256, 1, 2, 4, true, false)
 
 static const TileShape kTiles[] = {
 #define X(a, b, c, d, e, f) {a, b, c, d, e, f},
@@ -157,7 +167,8 @@ void tile_name(int id, char* buf, size_t len) {
   }
   const TileShape& t = kTiles[id];
   snprintf(buf, len, "%dx%dx%d%s%s%s", t.bx, t.by, t.nyt,
-           t.remap == 1 ? "+xcdband" : (t.remap == 2 ? "+xcdrow" : (t.remap == 3 ? "+rowsweep" : "")),
+           t.remap == 1 ? "+xcdband"
+                        : (t.remap == 2 ? "+xcdrow" : (t.remap == 3 ? "+rowsweep" : (t.remap == 4 ? "+xcd8" : ""))),
            t.nts ? "+nts" : "", t.ntl ? "+ntl" : "");
 }
 
@@ -171,6 +182,7 @@ static hipError_t launch_step_t(const LatDesc& L, int parity, hipStream_t s) {
   if (REMAP == 0) grid = tiles_x * tiles_y;
   else if (REMAP == 1) grid = ((tiles_x * tiles_y + 7) >> 3) * 8;
   else if (REMAP == 2) grid = tiles_x * ((tiles_y + 7) >> 3) * 8;
+  else if (REMAP == 4) grid = ((tiles_x * tiles_y + 63) >> 6) * 64;
   else grid = tiles_y;
   const int eb = edge_blocks(L.nx, L.ny);
   const int eo = (eb + 7) & ~7;
@@ -210,6 +222,7 @@ static hipError_t launch_bulk_t(const LatDesc& L, int parity, hipStream_t s) {
   if (REMAP == 0) grid = tiles_x * tiles_y;
   else if (REMAP == 1) grid = ((tiles_x * tiles_y + 7) >> 3) * 8;
   else if (REMAP == 2) grid = tiles_x * ((tiles_y + 7) >> 3) * 8;
+  else if (REMAP == 4) grid = ((tiles_x * tiles_y + 63) >> 6) * 64;
   else grid = tiles_y;
   k_bulk<S, BX, BY, NYT, REMAP, NTS, NTL><<<dim3(grid), dim3(BX, BY), 0, s>>>(L, parity, tiles_x, tiles_y);
   return hipGetLastError();
