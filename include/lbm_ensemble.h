@@ -79,10 +79,13 @@ int lbm_ens_time(const lbm_ens* e, int64_t* t);
  * launch for the current tile shape. */
 int lbm_ens_info(const lbm_ens* e, int64_t* nodes, int32_t* bulk_blocks, int32_t* edge_blocks);
 
-/* Bulk tile shapes of the ensemble kernel (rebuilds the tile table; cached
- * graphs are dropped).  lbm_ens_autotune times every shape (median of `reps`
- * launches after one warm-up; the state is not advanced) and keeps the
- * fastest; times_ms (optional) receives one median per shape. */
+/* Bulk tile shapes of the ensemble kernel, "BXxBYxNYT" (block BX x BY, NYT
+ * nodes per thread along y).  lbm_ens_set_shape rebuilds the tile table and
+ * work list (cached graphs are dropped).
+ * lbm_ens_autotune times every shape as the launch a step uses (the fused
+ * step, or the bulk kernel when fusion is off or a member runs the closure;
+ * median of `reps` launches after one warm-up; the state is not advanced) and
+ * keeps the fastest; times_ms (optional) receives one median per shape. */
 int lbm_ens_shape_count(void);
 int lbm_ens_shape_describe(int32_t id, char* buf, size_t len);
 int lbm_ens_set_shape(lbm_ens* e, int32_t id);

@@ -1,8 +1,8 @@
-"""Bulk-kernel tile autotuner with a JSON cache.
+"""Launch-shape autotuner with a JSON cache.
 
-The library's ``lbm_autotune`` times every compiled launch shape of the bulk
-kernel on a live lattice (median of repeated launches) and selects the
-fastest.  This module keeps the winners in ``tuning/tiles.json`` keyed by
+The library's ``lbm_autotune`` times every compiled launch shape of the step
+launch (the fused edge + bulk kernel) on a live lattice (median of repeated
+launches) and selects the fastest.  This module keeps the winners in ``tuning/tiles.json`` keyed by
 (GPU architecture, lattice size, storage), so later runs reuse a measured
 choice instead of re-timing, and records every candidate's time.
 

@@ -296,12 +296,16 @@ int upload_descs(lbm_ens* e) {
 
 int build_tiles(lbm_ens* e, int shape) {
   const lbm::EnsShape& s = lbm::kEnsShapes[shape];
+  // per member, its bulk tiles with the interior row on which each starts
   std::vector<lbm::EnsTile> tiles;
+  std::vector<std::vector<std::pair<lbm::EnsTile, int>>> mtiles(e->count);
   for (int32_t k = 0; k < e->count; ++k) {
-    const int tx = (e->p[k].nx + s.bx - 1) / s.bx;
-    const int ty = (e->p[k].ny - 2 + s.by * s.nyt - 1) / (s.by * s.nyt);
+    const int nx = e->p[k].nx, ny = e->p[k].ny;
+    const int tx = (nx + s.bx - 1) / s.bx;
+    const int ty = (ny - 2 + s.by * s.nyt - 1) / (s.by * s.nyt);
     for (int j = 0; j < ty; ++j)
-      for (int i = 0; i < tx; ++i) tiles.push_back({k, i, j, 0});
+      for (int i = 0; i < tx; ++i) mtiles[k].push_back({{k, i, j, 0}, j * s.by * s.nyt});
+    for (const auto& t : mtiles[k]) tiles.push_back(t.first);
   }
   if (tiles.size() > e->lay.max_tiles) return fail(LBM_ERR_STATE, "tile table overflow");
   // Work list of the fused step: bands of SEG rows per member, each holding
@@ -311,16 +315,13 @@ int build_tiles(lbm_ens* e, int shape) {
   // interleaved (entry 8 j + k is item j of list k) and padded to one length.
   std::vector<std::vector<lbm::EnsWork>> xcd(8);
   std::vector<size_t> load(8, 0);
-  const int rpt = s.by * s.nyt;
   for (int32_t k = 0; k < e->count; ++k) {
     const int nx = e->p[k].nx, ny = e->p[k].ny;
-    const int tx = (nx + s.bx - 1) / s.bx;
-    const int ty = (ny - 2 + rpt - 1) / rpt;
     const int nsv = lbm::edge_segments_v(ny), nsh = lbm::edge_segments_h(nx);
     std::vector<std::vector<lbm::EnsWork>> bands(nsv);
-    for (int j = 0; j < ty; ++j) {
-      const int band = std::min((1 + j * rpt) / lbm::SEG, nsv - 1);
-      for (int i = 0; i < tx; ++i) bands[band].push_back({k, i, j, lbm::W_TILE});
+    for (const auto& t : mtiles[k]) {
+      const int band = std::min((1 + t.second) / lbm::SEG, nsv - 1);  // lattice row = 1 + interior row
+      bands[band].push_back({k, t.first.txi, t.first.tyi, lbm::W_TILE});
     }
     for (int b = 0; b < nsv; ++b) {
       bands[b].push_back({k, lbm::E_LEFT, b, lbm::W_SEG});
@@ -623,13 +624,18 @@ int lbm_ens_autotune(lbm_ens* e, int32_t reps, int32_t* best, float* times_ms) {
   for (int id = 0; id < lbm::kNumEnsShapes && rc == LBM_OK; ++id) {
     rc = build_tiles(e, id);
     if (rc) break;
-    // the bulk kernel reads buffer `parity` and writes only the other one
-    hipError_t he =
-        lbm::launch_ens_bulk(e->store, id, e->d_descs, e->d_tiles, e->ntiles, e->parity, e->stream);
+    // timed: the launch a step uses (the fused step, or the bulk kernel when
+    // fusion is off or a member runs the closure); both read buffer `parity`
+    // and write only the other one
+    const bool fused = e->fused && !e->any_closure;
+    auto launch = [&]() {
+      return fused ? lbm::launch_ens_step(e->store, id, e->d_descs, e->d_work, e->nwork, e->parity, e->stream)
+                   : lbm::launch_ens_bulk(e->store, id, e->d_descs, e->d_tiles, e->ntiles, e->parity, e->stream);
+    };
+    hipError_t he = launch();
     for (int r = 0; r < reps && he == hipSuccess; ++r) {
       he = hipEventRecord(ev[2 * r], e->stream);
-      if (he == hipSuccess)
-        he = lbm::launch_ens_bulk(e->store, id, e->d_descs, e->d_tiles, e->ntiles, e->parity, e->stream);
+      if (he == hipSuccess) he = launch();
       if (he == hipSuccess) he = hipEventRecord(ev[2 * r + 1], e->stream);
     }
     if (he == hipSuccess) he = hipStreamSynchronize(e->stream);
