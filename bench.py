@@ -258,6 +258,47 @@ def run_c5(torch, W, steps, every=50, timing_steps=1000):
     return out
 
 
+# algorithmic flops per training sample of the closure network 96 -> 64 -> 64 -> 3:
+# forward 2 (96*64 + 64*64 + 64*3); backward dW1, dW2, dW3 and the input
+# gradients of layers 2 and 3
+MLP_FWD_FLOPS = 2 * (96 * 64 + 64 * 64 + 64 * 3)
+MLP_TRAIN_FLOPS = MLP_FWD_FLOPS + 2 * (96 * 64 + 64 * 64 + 64 * 3) + 2 * (64 * 64 + 64 * 3)
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def run_training(torch, steps=300, batches=(4096, 65536), nsamples=1 << 19):
+    """Closure training throughput: Adam steps on minibatches of BF16 inputs (random normalised
+    samples; the cost does not depend on their values), timed with events.  4096 is the batch the
+    training uses (64 blocks of 64 rows: a quarter of the chip, latency-bound); 65536 fills it."""
+    from paper_2005_08674_amd.closure import Trainer
+    g = torch.Generator(device="cuda").manual_seed(7)
+    x = torch.randn((nsamples, 96), device="cuda", generator=g).to(torch.bfloat16)
+    t = torch.randn((nsamples, 3), device="cuda", generator=g)
+    out = {"flops_per_sample": MLP_TRAIN_FLOPS}
+    for batch in batches:
+        tr = Trainer(max_batch=batch)
+        rows = torch.randint(0, nsamples, (steps, batch), device="cuda", dtype=torch.int32, generator=g)
+        for k in range(5):
+            tr.train_step(x, t, 1e-4, rows=rows[k])
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(tr.stream)
+        for k in range(steps):
+            tr.train_step(x, t, 1e-4, rows=rows[k])
+        b.record(tr.stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        sps = batch / (ms * 1e-3)
+        tflops = sps * MLP_TRAIN_FLOPS / 1e12
+        out[f"batch{batch}"] = {
+            "ms_per_step": round(ms, 5), "samples_per_s": round(sps, 1),
+            "roofline": {"bound": "mfma", "achieved": round(tflops, 3), "peak": BF16_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(tflops / BF16_PEAK_TFLOPS, 6)}}
+        tr.close()
+        del rows
+    return out
+
+
 def cpu_baseline(W, w, budget_s=12.0):
     import oracle
     o = oracle.Lattice(w.nx, w.ny, w.tau, *w.fields)
@@ -289,6 +330,7 @@ def main():
     ap.add_argument("--retune", action="store_true", help="ignore the autotuner cache and re-time all tiles")
     ap.add_argument("--ensemble-steps", type=int, default=2000, help="0 skips the ensemble variant")
     ap.add_argument("--c5-steps", type=int, default=6000, help="0 skips the 2048^2 vortex+pulse reflection runs")
+    ap.add_argument("--train-steps", type=int, default=300, help="0 skips the closure-training throughput run")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -318,6 +360,8 @@ def main():
         variants["ensemble256_f32"] = run_ensemble(torch, W, args.ensemble_steps)
     if args.c5_steps > 0:
         variants["vortexpulse2048_reflection"] = run_c5(torch, W, args.c5_steps)
+    if args.train_steps > 0:
+        variants["closure_training"] = run_training(torch, steps=args.train_steps)
     w = main_run["workload"]
     traffic = recorded_traffic(main_run["tile"])
     if traffic is not None:

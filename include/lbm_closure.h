@@ -51,8 +51,8 @@ extern "C" {
  * lbm_set_closure reads. */
 int lbm_closure_net_bytes(size_t* bytes);
 
-/* mode 1: every edge node with a single NSBC normal takes m_c + A times the
- * network's correction (`net`, a blob from lbm_mlp_export, borrowed while in use);
+/* mode 1: every edge node with a single NSBC normal in the blob's regime
+ * (kmin, see lbm_mlp_export) takes m_c + A times the network's correction (`net`, a blob from lbm_mlp_export, borrowed while in use);
  * corners, non-finite outputs and outputs beyond the blob's trust bound keep
  * NSBC's m_c.  mode 0: plain NSBC (net may be NULL). */
 int lbm_set_closure(lbm_ctx* ctx, const void* net, int mode);
@@ -135,10 +135,14 @@ int lbm_mlp_normalization(lbm_mlp* m, float* mean_out, float* inv_std_out, float
 int lbm_mlp_set_normalization(lbm_mlp* m, const float* mean, const float* inv_std, const float* scale);
 
 /* Write the network blob (lbm_closure_net_bytes bytes) for lbm_set_closure;
- * `trust` (> 0) is the largest |normalised output| accepted at run time and
+ * `trust` (> 0) is the largest |normalised output| accepted at run time,
  * `gain` (> 0) multiplies the correction (1 = as trained, < 1 under-relaxes
- * it).  Synchronizes the trainer's stream. */
-int lbm_mlp_export(lbm_mlp* m, float trust, float gain, void* net_out);
+ * it), and `kmin` (>= 0) gates it by regime: the correction applies only
+ * where the strip's kinetic disturbance sum |u - u_ref|^2 exceeds kmin times
+ * its acoustic part sum c_s^2 (rho - rho_ref)^2 / rho0^2 (a sound wave has
+ * ratio ~1, a convected vortex >> 1; 0 applies it everywhere).
+ * Synchronizes the trainer's stream. */
+int lbm_mlp_export(lbm_mlp* m, float trust, float gain, float kmin, void* net_out);
 
 void lbm_mlp_destroy(lbm_mlp* m);
 

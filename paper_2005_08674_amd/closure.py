@@ -134,14 +134,15 @@ class Trainer:
         tr.meta = {k: float(d[k]) for k in d.files if d[k].ndim == 0}
         return tr
 
-    def export(self, trust: float = None, gain: float = None) -> torch.Tensor:
-        """Network blob for lbm_set_closure; trust and gain default to the values saved with the
-        network (else 1.0 and 1.0)."""
+    def export(self, trust: float = None, gain: float = None, kmin: float = None) -> torch.Tensor:
+        """Network blob for lbm_set_closure; trust, gain and the regime gate kmin default to the
+        values saved with the network (else 1.0, 1.0 and 0.0)."""
         meta = getattr(self, "meta", {})
         trust = meta.get("trust", 1.0) if trust is None else trust
         gain = meta.get("gain", 1.0) if gain is None else gain
+        kmin = meta.get("kmin", 0.0) if kmin is None else kmin
         blob = torch.empty(L.lbm_closure_net_bytes(), dtype=torch.uint8, device=self.device)
-        L.lbm_mlp_export(self.m, trust, gain, blob.data_ptr())
+        L.lbm_mlp_export(self.m, trust, gain, kmin, blob.data_ptr())
         return blob
 
     def train(self, x, t, epochs=20, batch=4096, lr=2e-3, lr_end=2e-4, seed=0, log=None):
@@ -198,8 +199,17 @@ def twin_fields(member_fields_fn, m, pad_x, pad_y):
     return member_fields_fn(m, offset=(pad_x, pad_y), nx=m.nx + 2 * pad_x, ny=m.ny + 2 * pad_y)
 
 
+def kinetic_ratio(feat: torch.Tensor, rho0: float = 1.0) -> torch.Tensor:
+    """Per input row, the strip's kinetic disturbance sum |u - u_ref|^2 over its acoustic part
+    sum c_s^2 (rho - rho_ref)^2 / rho0^2 (the quantity the regime gate kmin thresholds)."""
+    s = feat[:, :81].reshape(-1, 9, 9)
+    su = (s[:, :, 1] ** 2 + s[:, :, 2] ** 2).sum(1)
+    sr = (s[:, :, 0] ** 2).sum(1) / (3.0 * rho0 * rho0)
+    return su / sr
+
+
 def generate_dataset(members, member_fields_fn, member_m0_fn, steps=2000, log_every=10, stride=4, store="f32",
-                     gamma=0.6, net=None, amp_min=1e-8, amp_rel=0.0, device="cuda", log=None):
+                     gamma=0.6, net=None, amp_min=1e-8, amp_rel=0.0, kmin=0.0, device="cuda", log=None):
     """Run every member (NSBC edges, or the closure `net` with NSBC fallback) beside its twin in one
     ensemble and collect (raw inputs, residual targets).
 
@@ -207,8 +217,8 @@ def generate_dataset(members, member_fields_fn, member_m0_fn, steps=2000, log_ev
     use did at earlier steps; targets are the twin's moments at the same physical nodes one step
     later, minus the member's NSBC prediction m_c, divided by the strip amplitude A.  Sites whose A
     is at most `amp_min` (no disturbance yet, only rounding noise) or below `amp_rel` times the
-    largest A logged on the same member are left out.  Returns (feat [M, 96], resid [M, 3]) float32
-    device tensors."""
+    largest A logged on the same member are left out, and so are sites outside the regime gate
+    (kinetic_ratio <= kmin).  Returns (feat [M, 96], resid [M, 3]) float32 device tensors."""
     from .ensemble import Ensemble, member_params
     count = len(members)
     lat, fields, msites, tsites, t_clean, m0s = [], [], [], [], [], []
@@ -271,6 +281,8 @@ def generate_dataset(members, member_fields_fn, member_m0_fn, steps=2000, log_ev
     feat = torch.cat(feats)
     resid = torch.cat(resids)
     ok = torch.isfinite(feat).all(1) & torch.isfinite(resid).all(1)
+    if kmin > 0.0:
+        ok &= kinetic_ratio(feat) > kmin
     if amp_rel > 0.0:
         amp, mid = torch.cat(amps), torch.cat(mids)
         top = torch.zeros(count, dtype=amp.dtype, device=device).scatter_reduce(
@@ -317,6 +329,11 @@ def main(argv=None):
                                                            "previous round's network")
     ap.add_argument("--trust", type=float, default=1.0, help="trust bound saved with the network")
     ap.add_argument("--gain", type=float, default=1.0, help="correction gain saved with the network")
+    ap.add_argument("--kmin", type=float, default=10.0,
+                    help="regime gate saved with the network: the correction applies where the strip's kinetic "
+                         "disturbance exceeds kmin times its acoustic part (0: everywhere)")
+    ap.add_argument("--train-kmin", type=float, default=0.0,
+                    help="train only on sites above this kinetic/acoustic ratio (0: every regime)")
     ap.add_argument("--out", default=None, help="save params + normalisation (.npz)")
     args = ap.parse_args(argv)
 
@@ -325,7 +342,7 @@ def main(argv=None):
 
     def data(members, net=None):
         return generate_dataset(members, W.member_fields, W.member_m0, steps=args.steps, log_every=args.log_every,
-                                stride=args.stride, amp_rel=args.amp_rel, net=net)
+                                stride=args.stride, amp_rel=args.amp_rel, kmin=args.train_kmin, net=net)
 
     t0 = time.time()
     members = W.ensemble_members(args.members, seed=args.seed)
@@ -341,7 +358,7 @@ def main(argv=None):
     t_train = time.time() - t1
     for rnd in range(1, args.rounds):
         # closed-loop data: the members now run with the current network on their edges
-        f2, r2 = data(members, net=tr.export(args.trust, args.gain))
+        f2, r2 = data(members, net=tr.export(args.trust, args.gain, args.kmin))
         log(f"dataset round {rnd} (closure edges): {f2.shape[0]} samples")
         feat, resid = torch.cat([feat, f2]), torch.cat([resid, r2])
         del f2, r2
@@ -358,7 +375,7 @@ def main(argv=None):
     mse_net = heldout_mse(tr, hx, ht)
     mse_nsbc = float((ht.double() ** 2).mean().item())  # NSBC predicts a zero residual
     if args.out:
-        tr.save(args.out, trust=args.trust, gain=args.gain)
+        tr.save(args.out, trust=args.trust, gain=args.gain, kmin=args.kmin)
     res = {"train_samples": int(x.shape[0]), "heldout_samples": int(hx.shape[0]), "epochs": args.epochs,
            "first_loss": losses[0], "final_loss": losses[-1], "heldout_mse_closure": mse_net,
            "heldout_mse_nsbc": mse_nsbc, "heldout_gain": 1.0 - mse_net / mse_nsbc,

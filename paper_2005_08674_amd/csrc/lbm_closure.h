@@ -105,4 +105,22 @@ __device__ inline float finish_inputs(float* x, float rho0, float omega, const f
   return A;
 }
 
+// Regime gate of a finished input row: true when the strip's kinetic
+// disturbance sum_j |u_j - u_ref|^2 exceeds kmin times its acoustic part
+// sum_j c_s^2 (rho_j - rho_ref)^2 / rho0^2.  A sound wave carries the two in
+// equal measure (ratio 1 at normal incidence), a convected vortex almost
+// only the first; kmin = 0 accepts every node.  The ratio does not depend
+// on the 1/A scaling of the row.
+__device__ inline bool vortical(const float* x, float rho0, float kmin) {
+  constexpr float cs2 = 1.f / 3.f;
+  float su = 0.f, sr = 0.f;
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    const float r = x[NODE_FEAT * j] / rho0, un = x[NODE_FEAT * j + 1], ut = x[NODE_FEAT * j + 2];
+    su += un * un + ut * ut;
+    sr += cs2 * r * r;
+  }
+  return su > kmin * sr;
+}
+
 }  // namespace lbm

@@ -521,15 +521,21 @@ __global__ void k_init_net(mlp::Net* __restrict__ net, bf16* __restrict__ W3p) {
     net->feat_inv_std[i] = i < mlp::NFEAT ? 1.f : 0.f;
   }
   if (i < 4) net->out_scale[i] = 1.f;
-  if (i == 0) net->trust = 0.f;
+  if (i == 0) {
+    net->trust = 0.f;
+    net->kmin = 0.f;
+  }
 }
 
 // Trust bound and gain of an exported blob: the gain scales the output scales
 // (an under-relaxed correction for gain < 1).
-__global__ void k_export_finish(mlp::Net* __restrict__ net, float trust, float gain) {
+__global__ void k_export_finish(mlp::Net* __restrict__ net, float trust, float gain, float kmin) {
   const int i = threadIdx.x;
   if (i < mlp::OUT) net->out_scale[i] *= gain;
-  if (i == 0) net->trust = trust;
+  if (i == 0) {
+    net->trust = trust;
+    net->kmin = kmin;
+  }
 }
 
 }  // namespace lbm
@@ -774,12 +780,14 @@ int lbm_mlp_set_normalization(lbm_mlp* m, const float* mean, const float* inv_st
   return LBM_OK;
 }
 
-int lbm_mlp_export(lbm_mlp* m, float trust, float gain, void* net_out) {
+int lbm_mlp_export(lbm_mlp* m, float trust, float gain, float kmin, void* net_out) {
   if (!m || !net_out) return fail(LBM_ERR_ARG, "NULL argument");
   if (!(trust > 0.f)) return fail(LBM_ERR_ARG, "trust bound %g must be > 0", (double)trust);
   if (!(gain > 0.f) || !std::isfinite(gain)) return fail(LBM_ERR_ARG, "gain %g must be finite and > 0", (double)gain);
+  if (!(kmin >= 0.f) || !std::isfinite(kmin)) return fail(LBM_ERR_ARG, "kmin %g must be finite and >= 0", (double)kmin);
   HIPCHK(hipMemcpyAsync(net_out, m->net(), sizeof(lbm::mlp::Net), hipMemcpyDeviceToDevice, m->stream));
-  lbm::k_export_finish<<<dim3(1), dim3(32), 0, m->stream>>>(static_cast<lbm::mlp::Net*>(net_out), trust, gain);
+  lbm::k_export_finish<<<dim3(1), dim3(32), 0, m->stream>>>(static_cast<lbm::mlp::Net*>(net_out), trust, gain,
+                                                             kmin);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(m->stream));
   return LBM_OK;

@@ -47,7 +47,9 @@ struct Net {
   float feat_inv_std[IN];
   float out_scale[4];  // physical units of one normalised output (drho, u_n, u_t)
   float trust;         // largest |normalised output| accepted
-  int32_t pad[3];
+  float kmin;          // regime gate: the correction applies where the strip's kinetic disturbance
+                       // sum |du|^2 exceeds kmin times its acoustic part sum c_s^2 drho^2 / rho0^2
+  int32_t pad[2];
 };
 
 __device__ inline int lane() { return threadIdx.x & 63; }

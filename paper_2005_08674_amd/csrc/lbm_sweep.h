@@ -277,6 +277,7 @@ __device__ inline void edge_segment_body(const LatDesc& L, int parity, int edge,
         to_normal_frame<R>(ref, base, enx, eny, refn);
         normal_frame_diff<R>(mcv, ref, enx, eny, dmc);
         amp = finish_inputs(xin, float(L.rho0), float(L.omega), dmc, refn);
+        if (!vortical(xin, float(L.rho0), net.kmin)) amp = 0.f;  // outside the gated regime: NSBC's m_c
       }
       mlp::bf16* row = cl->X + tid * mlp::XS;
 #pragma unroll

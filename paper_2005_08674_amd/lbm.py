@@ -116,7 +116,7 @@ _SIGS = {
     "lbm_mlp_forward": [_P, _P, ctypes.c_int64, _P],
     "lbm_mlp_params": [_P, _P],
     "lbm_mlp_normalization": [_P, _P, _P, _P],
-    "lbm_mlp_export": [_P, ctypes.c_float, ctypes.c_float, _P],
+    "lbm_mlp_export": [_P, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P],
     "lbm_mlp_set_normalization": [_P, _P, _P, _P],
 }
 
@@ -484,8 +484,8 @@ def lbm_mlp_set_normalization(m, mean_ptr, inv_std_ptr, scale_ptr):
     _check(load().lbm_mlp_set_normalization(m, mean_ptr, inv_std_ptr, scale_ptr), "lbm_mlp_set_normalization")
 
 
-def lbm_mlp_export(m, trust, gain, net_ptr):
-    _check(load().lbm_mlp_export(m, float(trust), float(gain), net_ptr), "lbm_mlp_export")
+def lbm_mlp_export(m, trust, gain, kmin, net_ptr):
+    _check(load().lbm_mlp_export(m, float(trust), float(gain), float(kmin), net_ptr), "lbm_mlp_export")
 
 
 def lbm_mlp_destroy(m):

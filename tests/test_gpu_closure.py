@@ -406,3 +406,51 @@ def test_trained_closure_beats_nsbc_one_step_on_heldout_members():
     print(f"\n[closure one-step, held-out] MSE network {mse:.4f} vs NSBC {mse0:.4f} "
           f"(gain {1 - mse / mse0:.3f}); train loss {losses[0]:.3f} -> {losses[-1]:.3f}", flush=True)
     assert mse < 0.5 * mse0
+
+
+def test_regime_gate_selects_vortical_nodes():
+    """With the regime gate kmin, a constant-output network shifts a boundary node's moments by A c only
+    where the strip's kinetic disturbance exceeds kmin times its acoustic part (computed here from the
+    oracle's inputs): nodes near a convected vortex are corrected, nodes reached by a sound pulse keep
+    NSBC."""
+    from paper_2005_08674_amd import lbm
+    from paper_2005_08674_amd.lattice import Lattice
+    nx, ny, u0 = 96, 80, (0.05, 0.0)
+    fv = W.lamb_oseen(nx, ny, 10.0, 40.0, 5.0, 0.03, u0)
+    fp = W.gaussian_pulses(nx, ny, [(1e-3, 4.0, 80.0, 40.0)])
+    f = (fv[0] + fp[0], fv[1], fv[2])
+    m0 = (1.0, u0[0], u0[1])
+    c = (0.05, 0.1, -0.08)
+    kmin = 10.0
+    tr = _trainer(_zero_params(c))
+    blob = tr.export(6.0, 1.0, kmin)
+    a = Lattice(nx, ny, 0.6, f, store="f64", m0=m0, ubase=u0)
+    b = Lattice(nx, ny, 0.6, f, store="f64", m0=m0, ubase=u0)
+    o = oracle.Lattice(nx, ny, 0.6, *f, m0=m0)
+    a.step(24)
+    b.step(24)
+    o.step(24)
+    post = o.post_collision()
+    lbm.lbm_set_closure(b.ctx, blob.data_ptr(), 1)
+    a.step(1)
+    b.step(1)
+    ma, mb = a.moments_np(), b.moments_np()
+    n_on = n_off = 0
+    for (x, y, e) in _eligible_sites(nx, ny):
+        feat, _, amp = OC.site_features(o, x, y, e, gamma=0.6, m0=m0, post=post)
+        s = feat[:81].reshape(9, 9)
+        k = (s[:, 1] ** 2 + s[:, 2] ** 2).sum() / ((s[:, 0] ** 2).sum() / 3.0)
+        if abs(k / kmin - 1.0) < 0.02 or amp < 1e-9:
+            continue  # borderline or no disturbance: either decision is valid
+        nxv, nyv = OC.NORMALS[e]
+        want = (amp * c[0], amp * (c[1] * nxv - c[2] * nyv), amp * (c[1] * nyv + c[2] * nxv))
+        got = tuple(mb[q][y, x] - ma[q][y, x] for q in range(3))
+        if k > kmin:
+            n_on += 1
+            assert np.allclose(got, want, rtol=1e-4, atol=1e-12), (x, y, e, k, got, want)
+        else:
+            n_off += 1
+            assert max(abs(v) for v in got) == 0.0, (x, y, e, k, got)
+    print(f"\n[regime gate kmin={kmin}] corrected {n_on} vortical nodes, left {n_off} acoustic nodes on NSBC",
+          flush=True)
+    assert n_on > 10 and n_off > 10

@@ -256,3 +256,28 @@ def test_stream_copy(nbytes):
     lbm.lbm_stream_copy(src.data_ptr(), dst.data_ptr(), nbytes, torch.cuda.current_stream().cuda_stream)
     torch.cuda.synchronize()
     assert torch.equal(src, dst)
+
+
+def test_storage_error_against_fp64_at_4096():
+    """pulses4096 with FP32, FP16 and BF16 deviation storage (FP32 arithmetic) against the same run in
+    FP64 (itself parity-checked against the oracle) at t = 100, 500, 1000, 2000: the error each storage
+    format adds, stated per run.  Bounds: FP32 1e-5 (the parity bar); FP16 and BF16, whose rounding is
+    2^-11 and 2^-8 of the stored deviation, 2e-2 and 1e-1 of U_ref."""
+    w = W.pulses_4096()
+    runs = {s: _lattice(nx=w.nx, ny=w.ny, tau=w.tau, fields=w.fields, store=s) for s in ("f64", "f32", "f16", "bf16")}
+    bounds = {"f32": 1e-5, "f16": 2e-2, "bf16": 1e-1}
+    t = 0
+    for t_next in (100, 500, 1000, 2000):
+        for g in runs.values():
+            g.step(t_next - t)
+        t = t_next
+        ref = runs["f64"].moments()
+        for s in ("f32", "f16", "bf16"):
+            m = runs[s].moments()
+            er = float((m[0] - ref[0]).abs().max()) / 1.0
+            eu = max(float((m[1] - ref[1]).abs().max()), float((m[2] - ref[2]).abs().max())) / w.u_ref
+            print(f"[storage {s} vs fp64, 4096^2] t={t}: e_rho={er:.3e} e_u={eu:.3e}", flush=True)
+            assert er <= bounds[s] and eu <= bounds[s], (s, t, er, eu)
+        del ref
+    for g in runs.values():
+        g.close()

@@ -129,11 +129,10 @@ def test_vortex512x256_is_absorbed():
 
 
 def test_committed_closure_closed_loop_against_nsbc():
-    """The committed closure network (trained on the 256-member ensemble) in closed loop against plain
-    NSBC, each test lattice against its 4x reference: reported per case.  What holds: every run stays
-    finite and bounded; on the convected vortex, the case the closure was trained to correct, it does
-    not reflect more than NSBC.  (On the acoustic pulse, where NSBC's own one-step error is a few
-    per cent of the disturbance, the network's error is larger and R_E rises -- recorded, not hidden.)"""
+    """The committed closure network (trained on the 256-member ensemble, run with its saved trust
+    bound, gain and regime gate) in closed loop against plain NSBC, each test lattice against its 4x
+    reference.  Sound waves stay below the gate, so the two acoustic cases reflect as with NSBC (to
+    1e-3); on the convected vortex the closure reflects at most 0.8x as much as NSBC."""
     import os
     from paper_2005_08674_amd.closure import Trainer
     from paper_2005_08674_amd.reflection import ReflectionRun
@@ -166,4 +165,7 @@ def test_committed_closure_closed_loop_against_nsbc():
         print(f"\n[closure closed loop] {name}: R_E NSBC {ra['R_E']:.4e}, closure {rb['R_E']:.4e} "
               f"(ratio {rb['R_E'] / ra['R_E']:.3f})", flush=True)
         assert finite and np.isfinite(rb["R_E"]) and rb["R_E"] < 0.1
-    assert out["vortex512x256"][1] <= out["vortex512x256"][0]
+    for name in ("pulse128", "pulse_on_flow"):
+        # equal up to the few rounding-noise nodes (A ~ 1e-12) whose tiny disturbance the gate may pass
+        assert out[name][1] <= out[name][0] * (1.0 + 1e-3), name
+    assert out["vortex512x256"][1] <= 0.8 * out["vortex512x256"][0]
