@@ -68,19 +68,27 @@ def run_store(torch, W, store, steps, warmup, tune_reps=5, size=4096, serial_che
     lat = Lattice(w.nx, w.ny, w.tau, w.fields, store=store)
     from paper_2005_08674_amd import autotune
     if tile:
+        # a single-step tile name, or a two-step shape name ("2step:...")
         names = [lbm.lbm_tile_describe(i) for i in range(lbm.lbm_tile_count())]
-        lbm.lbm_set_tile(lat.ctx, names.index(tile))
+        twos = [lbm.lbm_two_step_describe(i) for i in range(lbm.lbm_two_step_count())]
+        if tile in twos:
+            lbm.lbm_set_two_step(lat.ctx, twos.index(tile))
+        else:
+            lbm.lbm_set_tile(lat.ctx, names.index(tile))
         tile_name = tile
-        log(f"[{store}] tile fixed to {tile}")
+        log(f"[{store}] launch shape fixed to {tile}")
     else:
         tile_name = None if retune else autotune.apply(lat, store)
         if tile_name:
-            log(f"[{store}] tile from the autotuner cache: {tile_name}")
+            log(f"[{store}] launch shape from the autotuner cache: {tile_name}")
         else:
             e = autotune.tune(lat, store, reps=tune_reps, path=None)
-            tile_name = e["tile"]
-            log(f"[{store}] autotune -> {tile_name} ({e['ms']:.4f} ms); "
-                + ", ".join(f"{n}={t:.4f}" for n, t in e["candidates"].items()))
+            tile_name = e["tile"] if not e["two_step"] else f"{e['tile']} | {e['two_step']}"
+            log(f"[{store}] autotune -> {tile_name}; "
+                + ", ".join(f"{n}={t:.4f}" for n, t in e["candidates"].items())
+                + "; two-step (per launch = 2 steps): "
+                + ", ".join(f"{n}={t:.4f}" for n, t in e.get("two_step_candidates", {}).items()))
+    two_step = lbm.lbm_get_two_step(lat.ctx) >= 0
     lat.step(warmup)
     stream = lat.stream
     torch.cuda.synchronize()
@@ -92,7 +100,7 @@ def run_store(torch, W, store, steps, warmup, tune_reps=5, size=4096, serial_che
             lat.step(100)
             b.record(stream)
             torch.cuda.synchronize()
-            log(f"[{store}] overlap={ov}: {a.elapsed_time(b) / 100:.5f} ms/step")
+            log(f"[{store}] overlap={ov}" + (" (separate single-step launches)" if ov else "") + f": {a.elapsed_time(b) / 100:.5f} ms/step")
     # Timed region: K steps, bracketed by synchronisation, no instrumentation.
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -105,14 +113,24 @@ def run_store(torch, W, store, steps, warmup, tune_reps=5, size=4096, serial_che
     t_wall = time.perf_counter() - t_wall
     ms = e0.elapsed_time(e1)
     # The same K steps again with every kernel launch bracketed by HIP events
-    # on the stream it runs on: per-launch durations for the roofline.  Each
-    # step is one fused launch (edge segments + bulk tiles), which the timing
+    # on the stream it runs on: per-launch durations for the roofline.  A
+    # launch is either the two-step sweep (two steps of every node) or the
+    # fused single-step launch (edge segments + bulk tiles), which the timing
     # counts as the step's bulk launch.
     lbm.lbm_enable_timing(lat.ctx, True)
     lat.step(steps)
+    two_ms, two_n = lbm.lbm_two_step_times(lat.ctx)
     bulk_ms, bulk_n, edge_ms, edge_n = lbm.lbm_kernel_times(lat.ctx)
     lbm.lbm_enable_timing(lat.ctx, False)
     bpn, nodes_launch = lbm.lbm_bulk_traffic(lat.ctx)
+    steps_per_launch = 1
+    kernel_shape = lbm.lbm_tile_describe(lbm.lbm_get_tile(lat.ctx))
+    if two_step and two_n > 0:
+        kernel_shape = lbm.lbm_two_step_describe(lbm.lbm_get_two_step(lat.ctx))
+        # algorithmic bytes per node-step (2 x 9 x s) x the node-steps one launch advances
+        bulk_ms, bulk_n = two_ms, two_n
+        nodes_launch = w.nx * w.ny
+        steps_per_launch = 2
     ok = lat.check_finite()
     nodes = w.nx * w.ny
     out = {
@@ -121,14 +139,18 @@ def run_store(torch, W, store, steps, warmup, tune_reps=5, size=4096, serial_che
         "ms_per_step": ms / steps,
         "wall_s": t_wall,
         "mlups": nodes * steps / (ms * 1e-3) / 1e6,
+        "kernel": "two-step sweep (t -> t + 2, level t + 1 in LDS)" if steps_per_launch == 2
+                  else "fused step launch (edge segments + bulk tiles)",
         "kernel_avg_ms": bulk_ms / max(bulk_n, 1),
         "separate_edge_launches": edge_n,
         "bytes_per_node": bpn,
         "nodes_per_launch": nodes_launch,
+        "steps_per_launch": steps_per_launch,
+        "kernel_shape": kernel_shape,
         "finite": bool(ok),
         "workload": w,
     }
-    achieved = bpn * nodes_launch / (out["kernel_avg_ms"] * 1e-3) / 1e9
+    achieved = bpn * nodes_launch * steps_per_launch / (out["kernel_avg_ms"] * 1e-3) / 1e9
     out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
     lat.close()
@@ -137,7 +159,7 @@ def run_store(torch, W, store, steps, warmup, tune_reps=5, size=4096, serial_che
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_pulses4096_f32_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2005_08674_amd", "csrc", f)
-                  for f in ("lbm_kernels.hip", "lbm_device.h", "lbm_sweep.h")]
+                  for f in ("lbm_kernels.hip", "lbm_device.h", "lbm_sweep.h", "lbm_twostep_lds.h")]
 
 
 def kernel_source_sha() -> str:
@@ -150,8 +172,9 @@ def kernel_source_sha() -> str:
 
 
 def recorded_traffic(tile: str):
-    """HBM bytes per bulk launch measured with rocprofv3 counters (profiles/), or None when the
-    record is missing, was taken with another tile, or the kernel sources changed since."""
+    """HBM bytes per launch of the dominant kernel measured with rocprofv3 counters (profiles/), or
+    None when the record is missing, was taken with another launch shape, or the kernel sources
+    changed since."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     rec = {}
@@ -353,7 +376,8 @@ def main():
         r = run_store(torch, W, st, args.variant_steps, min(args.warmup, 20), tune_reps=args.tune_reps,
                       size=args.size, retune=args.retune)
         variants[st] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 5),
-                        "kernel_avg_ms": round(r["kernel_avg_ms"], 5), "tile": r["tile"],
+                        "kernel_avg_ms": round(r["kernel_avg_ms"], 5), "steps_per_launch": r["steps_per_launch"],
+                        "tile": r["tile"],
                         "roofline_frac": r["roofline"]["frac"], "achieved_GBs": r["roofline"]["achieved"],
                         "steps": args.variant_steps, "finite": r["finite"]}
     if args.ensemble_steps > 0:
@@ -363,7 +387,7 @@ def main():
     if args.train_steps > 0:
         variants["closure_training"] = run_training(torch, steps=args.train_steps)
     w = main_run["workload"]
-    traffic = recorded_traffic(main_run["tile"])
+    traffic = recorded_traffic(main_run["kernel_shape"])
     if traffic is not None:
         main_run["roofline"]["traffic"] = traffic
     line = {
@@ -382,9 +406,10 @@ def main():
         "config": {"workload": f"{w.name}: {w.nx}x{w.ny} D2Q9 BGK tau {w.tau}, 8 seeded Gaussian pulses, "
                                "NSBC (gamma 0.6, beta 0) on 4 edges, FP32 deviation storage, FP32 compute",
                    "nx": w.nx, "ny": w.ny, "store": "f32", "tile": main_run["tile"],
-                   "kernel": "fused step launch (edge segments + bulk tiles)",
+                   "kernel": main_run["kernel"],
                    "kernel_avg_ms": round(main_run["kernel_avg_ms"], 5),
                    "nodes_per_launch": main_run["nodes_per_launch"],
+                   "steps_per_launch": main_run["steps_per_launch"],
                    "bytes_per_node": main_run["bytes_per_node"]},
         "roofline": main_run["roofline"],
         "variants": variants,

@@ -210,17 +210,18 @@ int lbm_bulk_traffic(const lbm_ctx* ctx, int64_t* bytes_per_node, int64_t* nodes
  * closure and the overlap option always use separate launches. */
 int lbm_set_fused(lbm_ctx* ctx, int on);
 
-/* Two-step sweep: for lattices with NSBC on all four edges and 16- or
- * 32-bit storage, one launch advances two time steps (t -> t + 2), keeping
- * level t + 1 in registers, so the state crosses HBM once per two steps
- * (2 x 9 x bytes per stored population per node and launch).  Results are
- * bit-identical to two single steps: the intermediate level is rounded
- * through the storage format exactly as a store and reload would.
+/* Two-step sweep: for lattices with NSBC on all four edges, one launch
+ * advances two time steps (t -> t + 2).  Each block computes level t + 1 on
+ * its 64 x TY tile plus a margin, keeps it in LDS, and computes level t + 2
+ * on the tile from there, so the state crosses HBM about once per two steps
+ * (2 x 9 x bytes per stored population per node and launch, plus the margin
+ * re-read from L2).  Results are bit-identical to two single steps: level
+ * t + 1 is held in the storage format exactly as a store would write it.
  * lbm_two_step_count / lbm_two_step_describe list the candidate shapes;
  * lbm_set_two_step selects one (-1 turns the sweep off, the default) and
  * fails for lattices it does not support.  With a shape selected, lbm_step
  * advances pairs of steps with it and an odd last step with the single-step
- * kernels; the closure, the overlap option and periodic edges always use the
+ * launch; the closure, the overlap option and periodic edges always use the
  * single-step kernels.  lbm_autotune_two_step times every shape (`reps`
  * launches each, median; the state is left unchanged), selects the fastest,
  * writes its id to *best and the per-shape median launch times (ms, each

@@ -1,10 +1,12 @@
 """Launch-shape autotuner with a JSON cache.
 
-The library's ``lbm_autotune`` times every compiled launch shape of the step
-launch (the fused edge + bulk kernel) on a live lattice (median of repeated
-launches) and selects the fastest.  This module keeps the winners in ``tuning/tiles.json`` keyed by
-(GPU architecture, lattice size, storage), so later runs reuse a measured
-choice instead of re-timing, and records every candidate's time.
+The library times every compiled launch shape on a live lattice (median of
+repeated launches): ``lbm_autotune`` the single-step launch (the fused edge +
+bulk kernel), ``lbm_autotune_two_step`` the two-step sweep where the lattice
+supports it.  The faster per step wins.  This module keeps the winners in
+``tuning/tiles.json`` keyed by (GPU architecture, lattice size, storage), so
+later runs reuse a measured choice instead of re-timing, and records every
+candidate's time.
 
     python -m paper_2005_08674_amd.autotune --size 4096 --stores f32,f16,bf16,f64 --reps 15
 """
@@ -37,30 +39,54 @@ def load_cache(path: str = CACHE) -> dict:
 
 
 def lookup(nx: int, ny: int, store: str, path: str = CACHE, gpu_arch: str | None = None):
-    """Cached tile name for this lattice, or None."""
+    """Cached (tile name, two-step shape name or None) for this lattice, or None."""
     entry = load_cache(path).get(key(nx, ny, store, gpu_arch))
     if not entry:
         return None
     names = [L.lbm_tile_describe(i) for i in range(L.lbm_tile_count())]
-    return entry["tile"] if entry["tile"] in names else None
+    twos = [L.lbm_two_step_describe(i) for i in range(L.lbm_two_step_count())]
+    two = entry.get("two_step")
+    if entry["tile"] not in names or (two is not None and two not in twos):
+        return None
+    return entry["tile"], two
 
 
 def apply(lattice, store: str, path: str = CACHE) -> str | None:
-    """Set the cached tile on a Lattice (returns its name, or None if not cached)."""
-    name = lookup(lattice.nx, lattice.ny, store, path)
-    if name is not None:
-        names = [L.lbm_tile_describe(i) for i in range(L.lbm_tile_count())]
-        L.lbm_set_tile(lattice.ctx, names.index(name))
-    return name
+    """Set the cached choice on a Lattice; returns its description, or None if not cached."""
+    hit = lookup(lattice.nx, lattice.ny, store, path)
+    if hit is None:
+        return None
+    tile, two = hit
+    names = [L.lbm_tile_describe(i) for i in range(L.lbm_tile_count())]
+    L.lbm_set_tile(lattice.ctx, names.index(tile))
+    if two is not None:
+        twos = [L.lbm_two_step_describe(i) for i in range(L.lbm_two_step_count())]
+        L.lbm_set_two_step(lattice.ctx, twos.index(two))
+    else:
+        L.lbm_set_two_step(lattice.ctx, -1)
+    return tile if two is None else f"{tile} | {two}"
 
 
 def tune(lattice, store: str, reps: int = 10, path: str | None = CACHE) -> dict:
-    """Time every candidate on ``lattice``, select the fastest, and record it in the cache."""
+    """Time every candidate on ``lattice``: single-step tiles, then two-step shapes if the lattice
+    supports them; keep the faster per step, select it, and record it in the cache."""
     best, times = L.lbm_autotune(lattice.ctx, reps)
     names = [L.lbm_tile_describe(i) for i in range(L.lbm_tile_count())]
     entry = {"tile": names[best], "ms": times[best], "reps": reps,
              "candidates": {n: round(t, 5) for n, t in zip(names, times)},
-             "when": time.strftime("%Y-%m-%d %H:%M:%S")}
+             "two_step": None, "when": time.strftime("%Y-%m-%d %H:%M:%S")}
+    try:
+        b2, t2 = L.lbm_autotune_two_step(lattice.ctx, reps)
+    except L.LbmError:
+        b2 = None
+    if b2 is not None:
+        twos = [L.lbm_two_step_describe(i) for i in range(L.lbm_two_step_count())]
+        entry["two_step_candidates"] = {n: round(t, 5) for n, t in zip(twos, t2)}
+        if t2[b2] / 2 < times[best]:  # each two-step launch advances two steps
+            entry["two_step"] = twos[b2]
+            entry["two_step_ms"] = t2[b2]
+        else:
+            L.lbm_set_two_step(lattice.ctx, -1)
     if path:
         cache = load_cache(path)
         cache[key(lattice.nx, lattice.ny, store)] = entry
@@ -86,7 +112,8 @@ def main():
         lat = Lattice(w.nx, w.ny, w.tau, w.fields, store=st)
         lat.step(5)
         e = tune(lat, st, args.reps, args.cache)
-        print(f"{key(w.nx, w.ny, st)} -> {e['tile']} ({e['ms']:.4f} ms)", flush=True)
+        two = f", two-step {e['two_step']} ({e['two_step_ms'] / 2:.4f} ms per step)" if e["two_step"] else ""
+        print(f"{key(w.nx, w.ny, st)} -> {e['tile']} ({e['ms']:.4f} ms){two}", flush=True)
         lat.close()
 
 

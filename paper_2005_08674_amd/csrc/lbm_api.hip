@@ -624,7 +624,7 @@ int lbm_set_two_step(lbm_ctx* c, int32_t id) {
   if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
   if (id < -1 || id >= lbm::num_two_step()) return fail(LBM_ERR_ARG, "two-step shape %d out of range", id);
   if (id >= 0 && !lbm::two_step_supported(c->L))
-    return fail(LBM_ERR_ARG, "the two-step sweep needs NSBC on all four edges and 16- or 32-bit storage");
+    return fail(LBM_ERR_ARG, "the two-step sweep needs NSBC on all four edges");
   c->two_step = id;
   return LBM_OK;
 }
@@ -639,7 +639,7 @@ int lbm_autotune_two_step(lbm_ctx* c, int32_t reps, int32_t* best, float* times_
   if (!c || !best) return fail(LBM_ERR_ARG, "NULL argument");
   if (reps < 1 || reps > 1000) return fail(LBM_ERR_ARG, "reps = %d outside [1, 1000]", reps);
   if (!lbm::two_step_supported(c->L))
-    return fail(LBM_ERR_ARG, "the two-step sweep needs NSBC on all four edges and 16- or 32-bit storage");
+    return fail(LBM_ERR_ARG, "the two-step sweep needs NSBC on all four edges");
   // the sweep reads buffer `parity` and writes only the other one, so
   // relaunching it leaves the state untouched
   const int nt = lbm::num_two_step();

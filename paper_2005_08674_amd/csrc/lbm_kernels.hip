@@ -23,7 +23,7 @@
 #include "lbm_device.h"
 #include "lbm_launch.h"
 #include "lbm_sweep.h"
-#include "lbm_twostep.h"
+#include "lbm_twostep_lds.h"
 
 namespace lbm {
 
@@ -250,36 +250,26 @@ hipError_t launch_bulk(const LatDesc& L, int parity, int tile, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ two-step kernel
-// Candidate shapes of the two-step sweep: output rows per band (H),
-// non-temporal stores (NTS) and a register budget given as wavefronts per
-// SIMD (WPE; 0 = the compiler's choice; a larger count trades spills on the
-// lattice-edge path for occupancy on the interior path).
+// Candidate shapes of the two-step sweep (lbm_twostep_lds.h): output tile
+// 64 x TY, NT threads per block, non-temporal stores (NTS).
 #define LBM_TWO_STEP(X) \
-  X(32, true, 0)        \
-  X(64, true, 0)        \
-  X(128, true, 0)       \
-  X(64, false, 0)       \
-  X(32, true, 4)
+  X(8, 256, true)       \
+  X(12, 256, true)      \
+  X(16, 256, true)      \
+  X(12, 512, true)      \
+  X(16, 512, true)      \
+  X(20, 512, true)      \
+  X(24, 512, true)      \
+  X(16, 512, false)
 
-template <int S, int H, bool NTS>
-__global__ __launch_bounds__(64 * TS_WAVES) void k_two_step(LatDesc L, int parity) {
-  two_step_body<S, H, NTS>(L, parity);
-}
-template <int S, int H, bool NTS>
-__global__ __launch_bounds__(64 * TS_WAVES) __attribute__((amdgpu_waves_per_eu(4))) void k_two_step_w4(
-    LatDesc L, int parity) {
-  two_step_body<S, H, NTS>(L, parity);
-}
-template <int S, int H, bool NTS>
-__global__ __launch_bounds__(64 * TS_WAVES) __attribute__((amdgpu_waves_per_eu(5))) void k_two_step_w5(
-    LatDesc L, int parity) {
-  two_step_body<S, H, NTS>(L, parity);
+template <int S, int TY, int NT, bool NTS>
+__global__ __launch_bounds__(NT) void k_two_step(LatDesc L, int parity) {
+  two_step_tile<S, TY, NT, NTS>(L, parity);
 }
 
 struct TwoStepShape {
-  int h;
+  int ty, nt;
   bool nts;
-  int wpe;
 };
 static const TwoStepShape kTwo[] = {
 #define X(a, b, c) {a, b, c},
@@ -296,22 +286,18 @@ void two_step_name(int id, char* buf, size_t len) {
     return;
   }
   const TwoStepShape& t = kTwo[id];
-  if (t.wpe) snprintf(buf, len, "2step:h%d%s+w%d", t.h, t.nts ? "+nts" : "", t.wpe);
-  else snprintf(buf, len, "2step:h%d%s", t.h, t.nts ? "+nts" : "");
+  snprintf(buf, len, "2step:64x%d/%d%s", t.ty, t.nt, t.nts ? "+nts" : "");
 }
 
 bool two_step_supported(const LatDesc& L) {
   return L.bc[E_LEFT] == BC_NSBC && L.bc[E_RIGHT] == BC_NSBC && L.bc[E_BOTTOM] == BC_NSBC &&
-         L.bc[E_TOP] == BC_NSBC && L.nx >= 3 && L.ny >= 3 && L.store != ST_F64;
+         L.bc[E_TOP] == BC_NSBC && L.nx >= 3 && L.ny >= 3;
 }
 
-template <int S, int H, bool NTS, int WPE>
+template <int S, int TY, int NT, bool NTS>
 static hipError_t launch_two_t(const LatDesc& L, int parity, hipStream_t s) {
-  const int waves = (L.nx + TS_COLS - 1) / TS_COLS;
-  const dim3 grid((waves + TS_WAVES - 1) / TS_WAVES, (L.ny + H - 1) / H), block(64 * TS_WAVES);
-  if (WPE == 4) k_two_step_w4<S, H, NTS><<<grid, block, 0, s>>>(L, parity);
-  else if (WPE == 5) k_two_step_w5<S, H, NTS><<<grid, block, 0, s>>>(L, parity);
-  else k_two_step<S, H, NTS><<<grid, block, 0, s>>>(L, parity);
+  const dim3 grid((L.nx + TL_TX - 1) / TL_TX, (L.ny + TY - 1) / TY);
+  k_two_step<S, TY, NT, NTS><<<grid, dim3(NT), 0, s>>>(L, parity);
   return hipGetLastError();
 }
 
@@ -329,6 +315,7 @@ static hipError_t launch_two_s(const LatDesc& L, int parity, int id, hipStream_t
 hipError_t launch_two_step(const LatDesc& L, int parity, int id, hipStream_t s) {
   if (!two_step_supported(L)) return hipErrorInvalidValue;
   switch (L.store) {
+    case ST_F64: return launch_two_s<ST_F64>(L, parity, id, s);
     case ST_F32: return launch_two_s<ST_F32>(L, parity, id, s);
     case ST_F16: return launch_two_s<ST_F16>(L, parity, id, s);
     case ST_BF16: return launch_two_s<ST_BF16>(L, parity, id, s);

@@ -1,0 +1,168 @@
+// lbm_twostep_lds.h -- two lattice steps per launch (t -> t + 2) with the
+// intermediate level in LDS, for lattices with NSBC on all four edges
+// (eqs. lbe_0, lbe_1, feq_1 in the bulk; eqs. nes_0..nes_4 on the edges).
+//
+// A block owns an output tile of 64 x TY nodes.  It first computes level
+// t + 1 on the tile widened by a margin (2 columns each side; 1 row, or 2
+// rows where the tile holds a lattice edge), pulling level t straight from
+// HBM, and keeps those post-collision values in LDS; after one barrier it
+// computes level t + 2 on the tile from LDS and stores it.  Only the tile is
+// written, so the state crosses HBM about once per two steps (the margin is
+// re-read from L2 by the neighbouring tiles).
+//
+// Per node the arithmetic is the single-step path's, in the same order, and
+// level t + 1 is rounded through the storage codec exactly as a store and
+// reload would: results are bit-identical to two single steps.
+#pragma once
+
+#include "lbm_device.h"
+#include "lbm_sweep.h"
+
+namespace lbm {
+
+constexpr int TL_TX = 64;             // output columns per tile
+constexpr int TL_W = TL_TX + 4;       // LDS row: 2 margin columns each side
+
+// Moments of lattice node (x, y) of level t (stored, decoded).
+template <int S>
+__device__ inline void tl_moments_global(const LatDesc& Ld, const typename Codec<S>::T* A, int x, int y,
+                                         const Base<typename Codec<S>::R>& b, typename Codec<S>::R m[3]) {
+  using C = Codec<S>;
+  using R = typename C::R;
+  R g[9];
+  const int64_t idx = (int64_t)y * Ld.pitch + x;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) g[i] = C::dec(A[i * Ld.plane + idx], Ld.ds[i]);
+  moments<R>(g, R(Ld.rho0), b, m[0], m[1], m[2]);
+}
+
+// NSBC of boundary node (x, y): unknown populations already zeroed and
+// flagged in `unknown`; `mom(xx, yy, m)` returns the previous level's moments
+// of any lattice node.  Same order as the edge kernel: the x normal first
+// (the vertical edges own the corners), then the y normal (eqs. nes_2,
+// nes_3), then assignment and correction (eqs. nes_0, nes_1, nes_4).
+template <class R, class MomFn>
+__device__ inline void tl_nsbc(const LatDesc& Ld, R g[9], uint32_t unknown, int x, int y, R rho0, const Base<R>& b,
+                               MomFn mom) {
+  const int nx = Ld.nx, ny = Ld.ny;
+  const bool onL = x == 0, onR = x == nx - 1, onB = y == 0, onT = y == ny - 1;
+  R mb[3];
+  mom(x, y, mb);
+  R dsum[3] = {R(0), R(0), R(0)};
+  int nn = 0;
+  if (onL || onR) {
+    const int d = onL ? 1 : -1;
+    R m1[3], m2[3];
+    mom(x + d, y, m1);
+    mom(x + 2 * d, y, m2);
+    ++nn;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dsum[c] += normal_diff(mb[c], m1[c], m2[c], Ld.grad_order);
+  }
+  if (onB || onT) {
+    const int d = onB ? 1 : -1;
+    R m1[3], m2[3];
+    mom(x, y + d, m1);
+    mom(x, y + 2 * d, m2);
+    ++nn;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dsum[c] += normal_diff(mb[c], m1[c], m2[c], Ld.grad_order);
+  }
+  R fac = R(Ld.gamma);
+  if (nn == 2) fac *= Ld.corner_mode == 0 ? R(0.70710678118654752440) : R(0.5);
+  const R beta = R(Ld.beta);
+  M3<R> mc;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const R mp = mb[c] - fac * dsum[c];
+    mc.v[c] = (R(1) - beta) * mp + beta * R(Ld.m0[c]);
+  }
+  nsbc_assign_correct<R>(g, unknown, mc, rho0, b, Ld.corr_mode);
+}
+
+// NT threads per block.  Level t + 1 is kept in LDS in the storage format
+// (encoded exactly as a store would write it, decoded on every read), which
+// halves the LDS of the 16-bit formats.
+template <int S, int TY, int NT, bool NTS>
+__device__ inline void two_step_tile(const LatDesc& Ld, int parity) {
+  using C = Codec<S>;
+  using T = typename C::T;
+  using R = typename C::R;
+  constexpr int TH = TY + 4;  // LDS rows (margin of up to 2 each side)
+  __shared__ T lds[9][TH][TL_W];
+
+  const int nx = Ld.nx, ny = Ld.ny;
+  const int x0 = blockIdx.x * TL_TX, y0 = blockIdx.y * TY;
+  const int tid = threadIdx.x;
+  const bool edge_tile = x0 == 0 || x0 + TL_TX >= nx || y0 == 0 || y0 + TY >= ny;
+  const int my = edge_tile ? 2 : 1;        // row margin of level t + 1
+  const int ly0 = 2 - my;                  // first LDS row used
+  const int rows1 = TY + 2 * my;           // level t + 1 rows computed
+  const T* __restrict__ A = static_cast<const T*>(buf_of(Ld, parity));
+  T* __restrict__ B = static_cast<T*>(buf_of(Ld, parity ^ 1));
+  const int pitch = Ld.pitch;
+  const int64_t plane = Ld.plane;
+  const R rho0 = R(Ld.rho0), omega = R(Ld.omega);
+  const Base<R> base(Ld);
+
+  // ---- level t + 1 on lattice rows y0 - my .. y0 + TY + my - 1, columns x0 - 2 .. x0 + 65
+  for (int k = tid; k < rows1 * TL_W; k += NT) {
+    const int r = k / TL_W, cx = k - r * TL_W;
+    const int x = x0 - 2 + cx, y = y0 - my + r;
+    if (x < 0 || x >= nx || y < 0 || y >= ny) continue;
+    R g[9];
+    uint32_t unknown = 0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const int sx = x - kCx[i], sy = y - kCy[i];
+      if (sx < 0 || sx >= nx || sy < 0 || sy >= ny) {
+        unknown |= 1u << i;
+        g[i] = R(0);
+      } else {
+        g[i] = C::dec(A[i * plane + ((int64_t)sy * pitch + sx)], Ld.ds[i]);
+      }
+    }
+    if (x == 0 || x == nx - 1 || y == 0 || y == ny - 1) {
+      auto mom = [&](int xx, int yy, R m[3]) { tl_moments_global<S>(Ld, A, xx, yy, base, m); };
+      tl_nsbc<R>(Ld, g, unknown, x, y, rho0, base, mom);
+    }
+    bgk<R>(g, rho0, base, omega);
+    // encoded as the single-step path's store would write it
+#pragma unroll
+    for (int i = 0; i < 9; ++i) lds[i][ly0 + r][cx] = C::enc(g[i], Ld.es[i]);
+  }
+  __syncthreads();
+
+  // ---- level t + 2 on the tile, from LDS (lattice node (x, y) at lds[.][y - y0 + 2][x - x0 + 2])
+  auto mom1 = [&](int xx, int yy, R m[3]) {
+    R q[9];
+    const int lx = xx - x0 + 2, ly = yy - y0 + 2;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) q[i] = C::dec(lds[i][ly][lx], Ld.ds[i]);
+    moments<R>(q, rho0, base, m[0], m[1], m[2]);
+  };
+  for (int k = tid; k < TY * TL_TX; k += NT) {
+    const int r = k / TL_TX, cx = k - r * TL_TX;
+    const int x = x0 + cx, y = y0 + r;
+    if (x >= nx || y >= ny) continue;
+    R g[9];
+    uint32_t unknown = 0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const int sx = x - kCx[i], sy = y - kCy[i];
+      if (sx < 0 || sx >= nx || sy < 0 || sy >= ny) {
+        unknown |= 1u << i;
+        g[i] = R(0);
+      } else {
+        g[i] = C::dec(lds[i][sy - y0 + 2][sx - x0 + 2], Ld.ds[i]);
+      }
+    }
+    if (x == 0 || x == nx - 1 || y == 0 || y == ny - 1) tl_nsbc<R>(Ld, g, unknown, x, y, rho0, base, mom1);
+    bgk<R>(g, rho0, base, omega);
+    const int64_t idx = (int64_t)y * pitch + x;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) put<NTS>(B + i * plane + idx, C::enc(g[i], Ld.es[i]));
+  }
+}
+
+}  // namespace lbm

@@ -1,6 +1,6 @@
-"""GPU two-step sweep: one launch advancing t -> t + 2 must give the same bits
-as two single steps (bulk + edge kernels), for every shape, storage format,
-NSBC reading and ragged size, and agree with the oracle at full size."""
+"""GPU two-step sweep: one launch advancing t -> t + 2 (level t + 1 in LDS) must
+give the same bits as two single steps, for every shape, storage format, NSBC
+reading and ragged size, and agree with the oracle at full size."""
 import numpy as np
 import pytest
 
@@ -41,7 +41,7 @@ def _pair(nx, ny, store, shape, steps, **kw):
 SIZES = [(203, 77), (61, 5), (3, 3), (4, 3), (3, 40), (62, 64), (121, 130), (240, 33), (241, 129), (480, 257)]
 
 
-@pytest.mark.parametrize("store", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("store", ["f64", "f32", "f16", "bf16"])
 def test_bitwise_equal_to_single_steps_all_shapes(store):
     from paper_2005_08674_amd import lbm
     for shape in range(lbm.lbm_two_step_count()):
@@ -70,8 +70,7 @@ def test_unsupported_lattices_are_refused():
     with pytest.raises(lbm.LbmError):
         lbm.lbm_set_two_step(p.ctx, 0)
     d = Lattice(40, 30, 0.6, f, store="f64")
-    with pytest.raises(lbm.LbmError):
-        lbm.lbm_set_two_step(d.ctx, 0)
+    lbm.lbm_set_two_step(d.ctx, 0)
     with pytest.raises(lbm.LbmError):
         lbm.lbm_set_two_step(d.ctx, lbm.lbm_two_step_count())
     lbm.lbm_set_two_step(d.ctx, -1)
