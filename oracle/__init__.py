@@ -1,4 +1,4 @@
-"""CPU oracle for D2Q9 BGK + NSBC (Euser & Vuik, arXiv 2005.08674).
+"""CPU oracle for D2Q9 BGK/MRT + NSBC (Euser & Vuik, arXiv 2005.08674).
 
 TEST INFRASTRUCTURE ONLY: the test-suite, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py`` are the only users.  The product path
@@ -50,7 +50,9 @@ class OrcParams(ctypes.Structure):
                 ("gamma", ctypes.c_double), ("beta", ctypes.c_double),
                 ("m0_rho", ctypes.c_double), ("m0_ux", ctypes.c_double), ("m0_uy", ctypes.c_double),
                 ("corr_mode", ctypes.c_int), ("grad_order", ctypes.c_int),
-                ("corner_mode", ctypes.c_int)]
+                ("corner_mode", ctypes.c_int),
+                ("coll", ctypes.c_int),
+                ("omega_e", ctypes.c_double), ("omega_eps", ctypes.c_double), ("omega_q", ctypes.c_double)]
 
 
 _handles: dict = {}
@@ -66,6 +68,8 @@ def _lib(kind: str = "double"):
     P = ctypes.c_void_p
     for name, args in [("orc_feq", [ctypes.c_double] * 4 + [P]),
                        ("orc_collide_node", [ctypes.c_double, ctypes.c_double, P, P]),
+                       ("orc_collide_node_mrt", [ctypes.c_double] * 5 + [P, P]),
+                       ("orc_mrt_matrix", [P]),
                        ("orc_moments_node", [ctypes.c_double, P, P]),
                        ("orc_lattice_c", [P, P, P, P]),
                        ("orc_init", [P, P, P, P, P]),
@@ -113,6 +117,23 @@ def collide_node(tau, rho0, g9, kind: str = "double") -> np.ndarray:
     return out
 
 
+def collide_node_mrt(tau, rates, rho0, g9, kind: str = "double") -> np.ndarray:
+    """One MRT collision (Sec. 4, eq. mrt_lbe); rates = (omega_e, omega_eps, omega_q), omega_nu = 1/tau."""
+    g9 = np.ascontiguousarray(g9, dtype=_dtype(kind))
+    out = np.zeros(9, _dtype(kind))
+    we, weps, wq = (float(r) for r in rates)
+    if _lib(kind).orc_collide_node_mrt(float(tau), we, weps, wq, float(rho0), _ptr(g9), _ptr(out)) != 0:
+        raise ValueError("oracle rejected the MRT parameters")
+    return out
+
+
+def mrt_matrix(kind: str = "double") -> np.ndarray:
+    """The oracle's transformation matrix M (eq. mrt_vm), [moment][direction]."""
+    out = np.zeros(81, _dtype(kind))
+    _lib(kind).orc_mrt_matrix(_ptr(out))
+    return out.reshape(9, 9)
+
+
 def moments_node(rho0, g9, kind: str = "double") -> np.ndarray:
     g9 = np.ascontiguousarray(g9, dtype=_dtype(kind))
     out = np.zeros(3, _dtype(kind))
@@ -124,12 +145,14 @@ class Lattice:
     """One D2Q9 lattice advanced by the oracle.
 
     ``bc`` is (left, right, bottom, top), each BC_PERIODIC or BC_NSBC.
-    Fields are [ny][nx] arrays; ``drho`` is rho - rho0.
+    Fields are [ny][nx] arrays; ``drho`` is rho - rho0.  ``mrt`` = (omega_e,
+    omega_eps, omega_q) selects the MRT collision of Sec. 4 with omega_nu =
+    1/tau; None keeps BGK.
     """
 
     def __init__(self, nx, ny, tau, drho, ux, uy, rho0=1.0, bc=(1, 1, 1, 1),
                  gamma=0.6, beta=0.0, m0=(1.0, 0.0, 0.0), corr_mode=0,
-                 grad_order=1, corner_mode=0, kind: str = "double"):
+                 grad_order=1, corner_mode=0, mrt=None, kind: str = "double"):
         self.kind = kind
         self.lib = _lib(kind)
         p = OrcParams()
@@ -139,6 +162,9 @@ class Lattice:
         p.gamma, p.beta = float(gamma), float(beta)
         p.m0_rho, p.m0_ux, p.m0_uy = (float(v) for v in m0)
         p.corr_mode, p.grad_order, p.corner_mode = int(corr_mode), int(grad_order), int(corner_mode)
+        if mrt is not None:
+            p.coll = 1
+            p.omega_e, p.omega_eps, p.omega_q = (float(r) for r in mrt)
         self.p = p
         self.nx, self.ny, self.rho0 = int(nx), int(ny), float(rho0)
         self.t = 0

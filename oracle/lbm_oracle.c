@@ -19,7 +19,8 @@
  * One time step, written in the order the paper describes it (Sec. 3,
  * eqs. lbe_0/lbe_1/feq_1; Sec. 5, eqs. nes_0..nes_4):
  *   1. moments m(x,t) = (rho, u) of every node          (eqs. cf_0, cf_1)
- *   2. BGK collision of every node                      (eqs. lbe_1, feq_1)
+ *   2. collision of every node: BGK (eqs. lbe_1, feq_1), or the
+ *      multiple-relaxation-time model of Sec. 4 (eqs. mrt_lbe, mrt_vm, mrt_rm)
  *   3. streaming, pull form: g_i(x,t+1) = g*_i(x - c_i); a population whose
  *      source lies outside the domain across a non-periodic edge is unknown
  *   4. NSBC on every node of an NSBC edge:
@@ -76,6 +77,8 @@ typedef struct {
     int corr_mode;        /* 0: shift by w_i (drho + c_i.dj / c_s^2); 1: literal w_i (drho + c_i.dj) */
     int grad_order;       /* 1: two-point one-sided difference; 2: three-point */
     int corner_mode;      /* 0: diagonal normal, gamma/sqrt(2); 1: gamma/2 */
+    int coll;             /* 0: BGK, eq. lbe_1; 1: MRT, eq. mrt_lbe (omega_nu = 1/tau) */
+    double omega_e, omega_eps, omega_q;  /* MRT rates of e, epsilon and q (eq. mrt_rm) */
 } orc_params;
 
 enum { BC_PERIODIC = 0, BC_NSBC = 1 };
@@ -118,9 +121,133 @@ static void collide(real tau, real rho0, const real g[Q], real out[Q]) {
     for (int i = 0; i < Q; ++i) out[i] = g[i] - (g[i] - geq[i]) / tau;
 }
 
+/* ------------------------------------------------------------------ MRT (Sec. 4)
+ * Eq. mrt_lbe: f* = f - M^-1 S (m - m^eq), m = M f, m^eq = M f^eq (eq. mrt_vm).
+ * The rows of M are the Gram-Schmidt orthogonalisation, under the plain sum
+ * over the nine directions, of the moments named by the relaxation matrix of
+ * eq. mrt_rm, in its order: density, energy e, energy square epsilon, momentum
+ * j_x, energy flux q_x, j_y, q_y and the two stress components p_xx, p_xy.
+ * The raw moments taken for them are
+ *   1, |c|^2, |c|^4, c_x, c_x |c|^2, c_y, c_y |c|^2, c_x^2 - c_y^2, c_x c_y.
+ * S = diag(C_rho, w_e, w_eps, C_jx, w_q, C_jy, w_q, w_nu, w_nu) with
+ * w_nu = 1/tau; the conserved moments' constants C are free (the paper lets
+ * them take any value) and are set to 0 here: those moments are not relaxed. */
+static real raw_moment(int k, int i) {
+    const real cx = (real)CX[i], cy = (real)CY[i], c2 = cx * cx + cy * cy;
+    switch (k) {
+        case 0: return 1;
+        case 1: return c2;
+        case 2: return c2 * c2;
+        case 3: return cx;
+        case 4: return cx * c2;
+        case 5: return cy;
+        case 6: return cy * c2;
+        case 7: return cx * cx - cy * cy;
+        default: return cx * cy;
+    }
+}
+
+/* Gram-Schmidt: row k = raw moment k minus its projections on rows 0..k-1. */
+static void mrt_matrix(real M[Q][Q]) {
+    for (int k = 0; k < Q; ++k) {
+        for (int i = 0; i < Q; ++i) M[k][i] = raw_moment(k, i);
+        for (int j = 0; j < k; ++j) {
+            real num = 0, den = 0;
+            for (int i = 0; i < Q; ++i) {
+                num += M[k][i] * M[j][i];
+                den += M[j][i] * M[j][i];
+            }
+            for (int i = 0; i < Q; ++i) M[k][i] -= num / den * M[j][i];
+        }
+    }
+}
+
+/* Inverse of a 9 x 9 matrix by Gauss-Jordan elimination with partial pivoting. */
+static int invert9(real A[Q][Q], real X[Q][Q]) {
+    real a[Q][2 * Q];
+    for (int r = 0; r < Q; ++r)
+        for (int c = 0; c < 2 * Q; ++c) a[r][c] = c < Q ? A[r][c] : (real)(c - Q == r);
+    for (int c = 0; c < Q; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < Q; ++r)
+            if (fabsl((long double)a[r][c]) > fabsl((long double)a[piv][c])) piv = r;
+        if (a[piv][c] == 0) return -1;
+        if (piv != c)
+            for (int k = 0; k < 2 * Q; ++k) {
+                real t = a[c][k];
+                a[c][k] = a[piv][k];
+                a[piv][k] = t;
+            }
+        const real d = a[c][c];
+        for (int k = 0; k < 2 * Q; ++k) a[c][k] /= d;
+        for (int r = 0; r < Q; ++r) {
+            if (r == c || a[r][c] == 0) continue;
+            const real f = a[r][c];
+            for (int k = 0; k < 2 * Q; ++k) a[r][k] -= f * a[c][k];
+        }
+    }
+    for (int r = 0; r < Q; ++r)
+        for (int c = 0; c < Q; ++c) X[r][c] = a[r][Q + c];
+    return 0;
+}
+
+typedef struct {
+    int on;              /* 0: BGK */
+    real tau;
+    real M[Q][Q], Minv[Q][Q], S[Q];
+} orc_coll;
+
+static int coll_setup(const orc_params *p, orc_coll *c) {
+    c->on = p->coll;
+    c->tau = (real)p->tau;
+    if (!c->on) return 0;
+    mrt_matrix(c->M);
+    if (invert9(c->M, c->Minv)) return -1;
+    const real wnu = (real)1 / (real)p->tau;
+    const real S[Q] = {0, (real)p->omega_e, (real)p->omega_eps, 0, (real)p->omega_q,
+                       0, (real)p->omega_q, wnu, wnu};
+    for (int k = 0; k < Q; ++k) c->S[k] = S[k];
+    return 0;
+}
+
+/* Eq. mrt_lbe on one node (deviation form: the constant w_i rho0 cancels in
+ * m - m^eq). */
+static void collide_mrt(const orc_coll *c, real rho0, const real g[Q], real out[Q]) {
+    real drho, ux, uy, geq[Q], m[Q], meq[Q], d[Q];
+    node_moments(g, rho0, &drho, &ux, &uy);
+    equilibrium(rho0, drho, ux, uy, geq);
+    for (int k = 0; k < Q; ++k) {
+        m[k] = 0;
+        meq[k] = 0;
+        for (int i = 0; i < Q; ++i) {
+            m[k] += c->M[k][i] * g[i];
+            meq[k] += c->M[k][i] * geq[i];
+        }
+        d[k] = c->S[k] * (m[k] - meq[k]);
+    }
+    for (int i = 0; i < Q; ++i) {
+        real s = 0;
+        for (int k = 0; k < Q; ++k) s += c->Minv[i][k] * d[k];
+        out[i] = g[i] - s;
+    }
+}
+
+static void collide_node_any(const orc_coll *c, real rho0, const real g[Q], real out[Q]) {
+    if (c->on) collide_mrt(c, rho0, g, out);
+    else collide(c->tau, rho0, g, out);
+}
+
 static int check_params(const orc_params *p) {
     if (!p || p->nx < 3 || p->ny < 3) return -1;
-    if (!(p->tau > 0.5)) return -1;
+    if (p->coll != 0 && p->coll != 1) return -1;
+    if (p->coll == 0 && !(p->tau > 0.5)) return -1;
+    if (p->coll == 1) {
+        /* every rate in (0, 2]: tau = 1/2 (zero viscosity) is allowed */
+        if (!(p->tau >= 0.5)) return -1;
+        const double r[3] = {p->omega_e, p->omega_eps, p->omega_q};
+        for (int k = 0; k < 3; ++k)
+            if (!(r[k] > 0 && r[k] <= 2)) return -1;
+    }
     for (int e = 0; e < 4; ++e)
         if (p->bc[e] != BC_PERIODIC && p->bc[e] != BC_NSBC) return -1;
     if ((p->bc[E_LEFT] == BC_PERIODIC) != (p->bc[E_RIGHT] == BC_PERIODIC)) return -1;
@@ -142,6 +269,33 @@ int orc_feq(double rho0, double drho, double ux, double uy, real *out9) {
 /* One BGK collision of one node. */
 int orc_collide_node(double tau, double rho0, const real *g9, real *out9) {
     collide((real)tau, (real)rho0, g9, out9);
+    return 0;
+}
+
+/* One MRT collision of one node (eq. mrt_lbe), omega_nu = 1/tau. */
+int orc_collide_node_mrt(double tau, double we, double weps, double wq, double rho0, const real *g9, real *out9) {
+    orc_params p;
+    memset(&p, 0, sizeof p);
+    p.nx = p.ny = 3;
+    p.grad_order = 1;
+    p.tau = tau;
+    p.coll = 1;
+    p.omega_e = we;
+    p.omega_eps = weps;
+    p.omega_q = wq;
+    if (check_params(&p)) return -1;
+    orc_coll c;
+    if (coll_setup(&p, &c)) return -1;
+    collide_mrt(&c, (real)rho0, g9, out9);
+    return 0;
+}
+
+/* The transformation matrix M of eq. mrt_vm, row-major (row k = moment k). */
+int orc_mrt_matrix(real *out81) {
+    real M[Q][Q];
+    mrt_matrix(M);
+    for (int k = 0; k < Q; ++k)
+        for (int i = 0; i < Q; ++i) out81[k * Q + i] = M[k][i];
     return 0;
 }
 
@@ -195,11 +349,13 @@ int orc_moments(const orc_params *p, const real *g, double *drho, double *ux, do
  * alone): the quantity the GPU library keeps in its buffers. */
 int orc_post_collision(const orc_params *p, const real *g, real *out) {
     if (check_params(p)) return -1;
+    orc_coll c;
+    if (coll_setup(p, &c)) return -1;
     const size_t n = (size_t)p->nx * p->ny;
     for (size_t k = 0; k < n; ++k) {
         real gn[Q], gs[Q];
         for (int i = 0; i < Q; ++i) gn[i] = g[(size_t)i * n + k];
-        collide((real)p->tau, (real)p->rho0, gn, gs);
+        collide_node_any(&c, (real)p->rho0, gn, gs);
         for (int i = 0; i < Q; ++i) out[(size_t)i * n + k] = gs[i];
     }
     return 0;
@@ -231,9 +387,11 @@ static real normal_diff(const real *m, int nx, int x, int y, int ix, int iy, int
 /* Advance the pre-collision state g by nsteps time steps. */
 int orc_step(const orc_params *p, real *g, int nsteps) {
     if (check_params(p) || nsteps < 0) return -1;
+    orc_coll coll;
+    if (coll_setup(p, &coll)) return -1;
     const int nx = p->nx, ny = p->ny;
     const size_t n = (size_t)nx * ny;
-    const real rho0 = (real)p->rho0, tau = (real)p->tau;
+    const real rho0 = (real)p->rho0;
     const real gamma = (real)p->gamma, beta = (real)p->beta;
     const real m0[3] = {(real)p->m0_rho - rho0, (real)p->m0_ux, (real)p->m0_uy};
 
@@ -249,7 +407,7 @@ int orc_step(const orc_params *p, real *g, int nsteps) {
     for (int i = 0; i < Q; ++i) opp[i] = opposite(i);
 
     for (int step = 0; step < nsteps; ++step) {
-        /* 1 + 2: moments at time t and collision of every node. */
+        /* 1 + 2: moments at time t and collision of every node (BGK or MRT). */
 #pragma omp parallel for schedule(static)
         for (int y = 0; y < ny; ++y) {
             for (int x = 0; x < nx; ++x) {
@@ -257,7 +415,7 @@ int orc_step(const orc_params *p, real *g, int nsteps) {
                 real gn[Q], gs[Q];
                 for (int i = 0; i < Q; ++i) gn[i] = g[(size_t)i * n + k];
                 node_moments(gn, rho0, &mr[k], &mu[k], &mv[k]);
-                collide(tau, rho0, gn, gs);
+                collide_node_any(&coll, rho0, gn, gs);
                 for (int i = 0; i < Q; ++i) post[(size_t)i * n + k] = gs[i];
             }
         }

@@ -118,6 +118,7 @@ class Workload:
     m0: Tuple[float, float, float] = (1.0, 0.0, 0.0)
     u_ref: float = 0.0            # velocity scale for relative velocity errors
     extra: dict = field(default_factory=dict)
+    mrt: Tuple[float, float, float] = None   # (omega_e, omega_eps, omega_q) for the MRT collision, else BGK
 
 
 def pulse_128(nx: int = 128, ny: int = 128) -> Workload:
@@ -125,6 +126,17 @@ def pulse_128(nx: int = 128, ny: int = 128) -> Workload:
     a, w = 1e-3, 6.0
     f = gaussian_pulses(nx, ny, [(a, w, (nx - 1) / 2.0, (ny - 1) / 2.0)])
     return Workload("pulse128_f64", nx, ny, 0.6, 1000, f, u_ref=CS * a)
+
+
+def plane_wave_tc1(n: int = 128, theta_deg: float = 60.0) -> Workload:
+    """Test case 1 of Sec. 6: n x n (128^2), NSBC on all edges (gamma 0.6, beta 0), a Gaussian plane
+    wave (rho0 1, zeta 0.01, lambda = n/32) through the centre travelling at 60 degrees to the x axis;
+    tau = 1/2 (zero shear viscosity) with the MRT rates omega_e = omega_eps = omega_q = 1.9."""
+    zeta, lam = 0.01, n / 32.0
+    th = math.radians(theta_deg)
+    f = plane_wave(n, n, th, zeta, lam, ((n - 1) / 2.0, (n - 1) / 2.0))
+    return Workload(f"planewave{n}_tc1", n, n, 0.5, 400, f, u_ref=CS * zeta, mrt=(1.9, 1.9, 1.9),
+                    extra={"theta": th, "zeta": zeta, "lam": lam})
 
 
 def vortex_512x256(seed: int = 2, nx: int = 512, ny: int = 256) -> Workload:
