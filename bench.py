@@ -60,12 +60,16 @@ def copy_ceiling(torch, nbytes, reps=20):
     return 2 * nbytes / (ms * 1e-3) / 1e9, ms
 
 
-def run_store(torch, W, store, steps, warmup, tune_reps=5, size=4096, serial_check=False, tile=None, retune=False):
+MRT_RATES = (1.9, 1.9, 1.9)   # omega_e, omega_eps, omega_q of the paper's test case 1 (Sec. 6)
+
+
+def run_store(torch, W, store, steps, warmup, tune_reps=5, size=4096, serial_check=False, tile=None, retune=False,
+              mrt=None):
     from paper_2005_08674_amd import lbm
     from paper_2005_08674_amd.lattice import Lattice
 
     w = W.pulses_4096(n=size)
-    lat = Lattice(w.nx, w.ny, w.tau, w.fields, store=store)
+    lat = Lattice(w.nx, w.ny, w.tau, w.fields, store=store, mrt=mrt)
     from paper_2005_08674_amd import autotune
     if tile:
         # a single-step tile name, or a two-step shape name ("2step:...")
@@ -189,6 +193,25 @@ def recorded_traffic(tile: str):
         return float(rec["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def run_tc1(torch, W):
+    """Test case 1 of Sec. 6 (128^2 plane wave at 60 degrees, MRT at tau = 1/2, rates 1.9, NSBC gamma 0.6):
+    the acoustic energy left in the domain after the wave has crossed it, relative to the wave's own
+    (the library's fp64 energy reduction), for FP32 and FP64 storage."""
+    from paper_2005_08674_amd.lattice import Lattice
+
+    w = W.plane_wave_tc1()
+    out = {"workload": f"{w.name}: {w.nx}x{w.ny}, theta 60 deg, zeta 0.01, lambda {w.nx / 32:g}, tau 0.5, "
+                       f"MRT rates {w.mrt}, NSBC gamma 0.6 beta 0", "steps": w.steps}
+    for store in ("f32", "f64"):
+        lat = Lattice(w.nx, w.ny, w.tau, w.fields, store=store, mrt=w.mrt)
+        e0 = float(lat.energy().item())
+        lat.step(w.steps)
+        out[f"residual_energy_{store}"] = float(lat.energy().item()) / e0
+        out[f"finite_{store}"] = bool(lat.check_finite())
+        lat.close()
+    return out
 
 
 def run_ensemble(torch, W, steps, count=256, seed=4):
@@ -344,7 +367,9 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--size", type=int, default=4096)
-    ap.add_argument("--variants", default="f16,bf16,f64", help="extra storage variants ('' for none)")
+    ap.add_argument("--variants", default="f16,bf16,f64,mrt_f32,mrt_f16",
+                    help="extra variants: storage formats, mrt_<store> for the MRT collision ('' for none)")
+    ap.add_argument("--tc1", type=int, default=1, help="0 skips the test-case-1 plane-wave run")
     ap.add_argument("--variant-steps", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune-reps", type=int, default=5)
@@ -373,13 +398,16 @@ def main():
                          serial_check=True, tile=args.tile, retune=args.retune)
     variants = {}
     for st in [s for s in args.variants.split(",") if s]:
-        r = run_store(torch, W, st, args.variant_steps, min(args.warmup, 20), tune_reps=args.tune_reps,
-                      size=args.size, retune=args.retune)
+        mrt = MRT_RATES if st.startswith("mrt_") else None
+        r = run_store(torch, W, st[4:] if mrt else st, args.variant_steps, min(args.warmup, 20),
+                      tune_reps=args.tune_reps, size=args.size, retune=args.retune, mrt=mrt)
         variants[st] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 5),
                         "kernel_avg_ms": round(r["kernel_avg_ms"], 5), "steps_per_launch": r["steps_per_launch"],
                         "tile": r["tile"],
                         "roofline_frac": r["roofline"]["frac"], "achieved_GBs": r["roofline"]["achieved"],
                         "steps": args.variant_steps, "finite": r["finite"]}
+    if args.tc1:
+        variants["planewave128_tc1"] = run_tc1(torch, W)
     if args.ensemble_steps > 0:
         variants["ensemble256_f32"] = run_ensemble(torch, W, args.ensemble_steps)
     if args.c5_steps > 0:

@@ -60,6 +60,16 @@ enum { LBM_BC_PERIODIC = 0, LBM_BC_NSBC = 1 };
  * of two that keeps s_i in FP16's normal range), k = 0 for BF16. */
 enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16DEV = 2, LBM_STORE_BF16DEV = 3 };
 
+/* Collision model (lbm_params.collision).
+ * LBM_COLL_BGK: single relaxation time, eq. lbe_1 (Sec. 3), rate 1/tau.
+ * LBM_COLL_MRT: multiple relaxation times, eqs. mrt_lbe, mrt_vm, mrt_rm
+ *   (Sec. 4): f* = f - M^-1 S (M f - M f^eq), the rows of M the Gram-Schmidt
+ *   orthogonalisation of the moments 1, |c|^2, |c|^4, c_x, c_x|c|^2, c_y,
+ *   c_y|c|^2, c_x^2 - c_y^2, c_x c_y, and
+ *   S = diag(0, omega_e, omega_eps, 0, omega_q, 0, omega_q, 1/tau, 1/tau):
+ *   the viscous rate is 1/tau and density and momentum are not relaxed. */
+enum { LBM_COLL_BGK = 0, LBM_COLL_MRT = 1 };
+
 /* lbm_params.f16_exp value asking lbm_init to choose k from the initial
  * fields so that max |g_i / w_i| * 2^k is close to 2^12. */
 #define LBM_F16_EXP_AUTO (-1000)
@@ -68,7 +78,8 @@ typedef struct lbm_ctx lbm_ctx;
 
 typedef struct {
     int32_t nx, ny;       /* lattice size, each >= 3 */
-    double tau;           /* BGK relaxation time, eq. lbe_1 with dt = 1; must be > 0.5 */
+    double tau;           /* relaxation time, dt = 1: BGK's (eq. lbe_1), > 0.5; or MRT's viscous
+                             rate omega_nu = 1/tau (eq. mrt_rm), >= 0.5 (0.5: zero viscosity) */
     double rho0;          /* base density of the deviation form, > 0 */
     int32_t bc[4];        /* LBM_BC_* per edge; periodic edges come in pairs (left+right, bottom+top) */
     double gamma;         /* NSBC relaxation parameter, eq. nes_2 (the paper uses 0.6) */
@@ -79,13 +90,17 @@ typedef struct {
     int32_t corner_mode;  /* corner nodes of two NSBC edges: 0 = diagonal normal (gamma/sqrt 2),
                              1 = gamma/2 */
     int32_t f16_exp;      /* k of the FP16 codec, or LBM_F16_EXP_AUTO; ignored by other stores */
-    int32_t reserved0;    /* set to 0 */
+    int32_t collision;    /* LBM_COLL_BGK (default) or LBM_COLL_MRT */
     double ubase[2];      /* base velocity u_b of the deviation form, |u_b| <= 0.5 (default 0) */
+    double omega_e;       /* MRT rates of the energy, energy-square and energy-flux moments */
+    double omega_eps;     /* (eq. mrt_rm), each in (0, 2]; ignored by BGK; default 1.9 */
+    double omega_q;
 } lbm_params;
 
 /* Fill *p with defaults: 3x3 lattice, tau 0.6, rho0 1, NSBC on all edges,
  * gamma 0.6, FP32 storage, corr_mode 0, grad_order 1, corner_mode 0,
- * f16_exp auto, u_b = 0.  Always succeeds for a non-null p. */
+ * f16_exp auto, u_b = 0, BGK collision (MRT rates 1.9 when MRT is chosen).
+ * Always succeeds for a non-null p. */
 int lbm_params_default(lbm_params* p);
 
 /* Device workspace, in bytes, that lbm_init needs for these parameters: two

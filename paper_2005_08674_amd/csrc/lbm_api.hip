@@ -63,8 +63,18 @@ int check_params(const lbm_params* p) {
   if (p->nx < 3 || p->ny < 3) return fail(LBM_ERR_ARG, "lattice %dx%d: each side must be >= 3", p->nx, p->ny);
   if ((int64_t)p->nx * p->ny > (int64_t)1 << 28)
     return fail(LBM_ERR_ARG, "lattice %dx%d exceeds 2^28 nodes", p->nx, p->ny);
-  if (!(p->tau > 0.5) || !std::isfinite(p->tau))
+  if (p->collision != LBM_COLL_BGK && p->collision != LBM_COLL_MRT)
+    return fail(LBM_ERR_ARG, "collision = %d is not LBM_COLL_BGK or LBM_COLL_MRT", p->collision);
+  if (p->collision == LBM_COLL_BGK && (!(p->tau > 0.5) || !std::isfinite(p->tau)))
     return fail(LBM_ERR_ARG, "tau = %g: BGK needs tau > 0.5", p->tau);
+  if (p->collision == LBM_COLL_MRT) {
+    if (!(p->tau >= 0.5) || !std::isfinite(p->tau))
+      return fail(LBM_ERR_ARG, "tau = %g: MRT needs tau >= 0.5 (omega_nu <= 2)", p->tau);
+    const double r[3] = {p->omega_e, p->omega_eps, p->omega_q};
+    for (int k = 0; k < 3; ++k)
+      if (!(r[k] > 0.0 && r[k] <= 2.0))
+        return fail(LBM_ERR_ARG, "MRT rates (%g, %g, %g) must lie in (0, 2]", r[0], r[1], r[2]);
+  }
   if (!(p->rho0 > 0) || !std::isfinite(p->rho0)) return fail(LBM_ERR_ARG, "rho0 = %g must be > 0", p->rho0);
   for (int e = 0; e < 4; ++e)
     if (p->bc[e] != LBM_BC_PERIODIC && p->bc[e] != LBM_BC_NSBC)
@@ -112,6 +122,15 @@ void fill_desc(LatDesc& L, const lbm_params* p, const Layout& lay, void* buf0, v
   L.grad_order = p->grad_order;
   L.corner_mode = p->corner_mode;
   L.omega = 1.0 / p->tau;
+  L.coll = p->collision == LBM_COLL_MRT ? COLL_MRT : COLL_BGK;
+  if (L.coll == COLL_MRT) {
+    // s_k / |row_k|^2 for the e, eps, q and stress rows (lbm_device.h, mrt())
+    L.mk[0] = p->omega_e / 36.0;
+    L.mk[1] = p->omega_eps / 36.0;
+    L.mk[2] = p->omega_q / 12.0;
+    L.mk[3] = L.omega / 4.0;
+    for (int k = 0; k < 4; ++k) L.mkf[k] = static_cast<float>(L.mk[k]);
+  }
   L.rho0 = p->rho0;
   L.gamma = p->gamma;
   L.beta = 0.0;
@@ -348,6 +367,8 @@ int lbm_params_default(lbm_params* p) {
   p->grad_order = 1;
   p->corner_mode = 0;
   p->f16_exp = LBM_F16_EXP_AUTO;
+  p->collision = LBM_COLL_BGK;
+  p->omega_e = p->omega_eps = p->omega_q = 1.9;
   return LBM_OK;
 }
 

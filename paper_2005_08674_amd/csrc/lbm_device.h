@@ -1,9 +1,11 @@
-// lbm_device.h -- device-side building blocks of the D2Q9 BGK + NSBC sweep
-// for gfx950: lattice constants, storage codecs, the per-node BGK update, the
-// NSBC boundary-node update, and the lattice descriptor every kernel takes.
+// lbm_device.h -- device-side building blocks of the D2Q9 BGK/MRT + NSBC
+// sweep for gfx950: lattice constants, storage codecs, the per-node BGK and
+// MRT updates, the NSBC boundary-node update, and the lattice descriptor every
+// kernel takes.
 //
 // Method: Euser & Vuik (arXiv 2005.08674), Sec. 3 (eqs. lbe_0, lbe_1, feq_1,
-// moments eqs. cf_0/cf_1) and Sec. 5 (eqs. nes_0..nes_4).
+// moments eqs. cf_0/cf_1), Sec. 4 (eqs. mrt_lbe, mrt_vm, mrt_rm) and Sec. 5
+// (eqs. nes_0..nes_4).
 //
 // State convention: a population buffer holds the POST-collision deviations
 // g*_i = f*_i - f^eq_i(rho0, u_b) of time t, the distance from the discrete
@@ -37,6 +39,7 @@ __host__ __device__ constexpr R wgt(int i) {
 enum Store : int { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3 };
 enum Edge : int { E_LEFT = 0, E_RIGHT = 1, E_BOTTOM = 2, E_TOP = 3 };
 enum Bc : int { BC_PERIODIC = 0, BC_NSBC = 1 };
+enum Coll : int { COLL_BGK = 0, COLL_MRT = 1 };
 
 // ------------------------------------------------------------------ codecs
 // Stored type T, arithmetic type R.  The 16-bit codecs keep s = g / w_i * 2^k;
@@ -104,7 +107,9 @@ struct LatDesc {
   int32_t ub_zero;  // 1 when u_b = (0, 0): the arithmetic drops the u_b terms
   float ubf[2];     // u_b and P_i(u_b) rounded to fp32 once, for the fp32 arithmetic
   float pbf[9];
-  int32_t _pad2;
+  int32_t coll;     // COLL_BGK or COLL_MRT
+  double mk[4];     // MRT: omega_e/36, omega_eps/36, omega_q/12, omega_nu/4 (see mrt())
+  float mkf[4];     // the same rounded to fp32
 };
 
 // Buffer `parity` (0 or 1) of a lattice.  A select rather than an indexed
@@ -196,6 +201,66 @@ __device__ inline void bgk(R g[9], R rho0, const Base<R>& b, R omega) {
   equilibrium(rho0, b, drho, dux, duy, geq);
 #pragma unroll
   for (int i = 0; i < 9; ++i) g[i] = fma(omega, geq[i] - g[i], g[i]);
+}
+
+// MRT collision in place (eq. mrt_lbe): g <- g - M^-1 S M (g - g^eq).
+// The rows of M are orthogonal, so M^-1 = M^T diag(1 / |row_k|^2) and the
+// update is a sum over the six non-conserved moments k of
+//   row_k[i] * s_k / |row_k|^2 * (row_k . n),   n = g - g^eq.
+// For the Fig. 1 numbering the rows (Gram-Schmidt of 1, |c|^2, |c|^4, c_x,
+// c_x |c|^2, c_y, c_y |c|^2, c_x^2 - c_y^2, c_x c_y, up to a scale each) are
+//   e   = (-4, -1, -1, -1, -1,  2,  2,  2,  2)     |e|^2   = 36
+//   eps = ( 4, -2, -2, -2, -2,  1,  1,  1,  1)     |eps|^2 = 36
+//   q_x = ( 0, -2,  2,  0,  0,  1, -1, -1,  1)     |q|^2   = 12
+//   q_y = ( 0,  0,  0, -2,  2,  1, -1,  1, -1)
+//   p_xx = (0,  1,  1, -1, -1,  0,  0,  0,  0)     |p|^2   = 4
+//   p_xy = (0,  0,  0,  0,  0,  1,  1, -1, -1)
+// k = (omega_e/36, omega_eps/36, omega_q/12, omega_nu/4).  The conserved
+// moments (density, momentum) are not relaxed: their non-equilibrium parts
+// are zero up to rounding.
+template <class R>
+__device__ inline void mrt(R g[9], R rho0, const Base<R>& b, const R k[4]) {
+  R drho, dux, duy, n[9];
+  moments(g, rho0, b, drho, dux, duy);
+  equilibrium(rho0, b, drho, dux, duy, n);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) n[i] = g[i] - n[i];
+  const R ax = (n[1] + n[2]) + (n[3] + n[4]);
+  const R dg = (n[5] + n[6]) + (n[7] + n[8]);
+  const R E = k[0] * ((dg + dg) - (ax + R(4) * n[0]));
+  const R P = k[1] * ((R(4) * n[0] + dg) - (ax + ax));
+  const R d56 = n[5] - n[6], d78 = n[7] - n[8];
+  const R QX = k[2] * ((d56 - d78) - R(2) * (n[1] - n[2]));
+  const R QY = k[2] * ((d56 + d78) - R(2) * (n[3] - n[4]));
+  const R XX = k[3] * ((n[1] + n[2]) - (n[3] + n[4]));
+  const R XY = k[3] * ((n[5] + n[6]) - (n[7] + n[8]));
+  const R axial = E + R(2) * P;                 // common part of directions 1..4: -(-E - 2P)
+  const R diag = R(2) * E + P;                  // common part of directions 5..8
+  g[0] -= R(4) * (P - E);
+  g[1] += axial + R(2) * QX - XX;
+  g[2] += axial - R(2) * QX - XX;
+  g[3] += axial + R(2) * QY + XX;
+  g[4] += axial - R(2) * QY + XX;
+  g[5] -= diag + (QX + QY) + XY;
+  g[6] -= diag - (QX + QY) + XY;
+  g[7] -= diag - (QX - QY) - XY;
+  g[8] -= diag + (QX - QY) - XY;
+}
+
+template <class R> __device__ inline const R* mrt_k(const LatDesc& L);
+template <> __device__ inline const double* mrt_k<double>(const LatDesc& L) { return L.mk; }
+template <> __device__ inline const float* mrt_k<float>(const LatDesc& L) { return L.mkf; }
+
+// The lattice's collision (BGK, eq. lbe_1, or MRT, eq. mrt_lbe), in place.
+template <class R>
+__device__ inline void collide(const LatDesc& L, R g[9], R rho0, const Base<R>& b, R omega) {
+  if (L.coll == COLL_MRT) {
+    const R* kp = mrt_k<R>(L);
+    const R k[4] = {kp[0], kp[1], kp[2], kp[3]};
+    mrt<R>(g, rho0, b, k);
+  } else {
+    bgk<R>(g, rho0, b, omega);
+  }
 }
 
 template <int S>

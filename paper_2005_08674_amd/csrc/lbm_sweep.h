@@ -59,7 +59,7 @@ __device__ inline void bulk_tile_body(const LatDesc& L, int parity, int txi, int
   for (int j = 0; j < NYT; ++j) {
     const int y = y0 + j * BY;
     if (y <= L.ny - 2) {
-      bgk<R>(g[j], rho0, base, omega);
+      collide<R>(L, g[j], rho0, base, omega);
       const int idx = y * pitch + x;
 #pragma unroll
       for (int i = 0; i < 9; ++i) put<NTS>(B + i * plane + idx, C::enc(g[j][i], L.es[i]));
@@ -316,7 +316,7 @@ __device__ inline void edge_segment_body(const LatDesc& L, int parity, int edge,
   }
   if (!owner) return;
   if (nsbc_node) nsbc_assign_correct<R>(g, unknown, mc, rho0, base, L.corr_mode);
-  bgk<R>(g, rho0, base, R(L.omega));
+  collide<R>(L, g, rho0, base, R(L.omega));
   const int idx = y * pitch + x;
 #pragma unroll
   for (int i = 0; i < 9; ++i) put<true>(B + i * plane + idx, C::enc(g[i], L.es[i]));

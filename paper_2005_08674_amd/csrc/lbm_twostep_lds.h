@@ -126,7 +126,7 @@ __device__ inline void two_step_tile(const LatDesc& Ld, int parity) {
       auto mom = [&](int xx, int yy, R m[3]) { tl_moments_global<S>(Ld, A, xx, yy, base, m); };
       tl_nsbc<R>(Ld, g, unknown, x, y, rho0, base, mom);
     }
-    bgk<R>(g, rho0, base, omega);
+    collide<R>(Ld, g, rho0, base, omega);
     // encoded as the single-step path's store would write it
 #pragma unroll
     for (int i = 0; i < 9; ++i) lds[i][ly0 + r][cx] = C::enc(g[i], Ld.es[i]);
@@ -158,7 +158,7 @@ __device__ inline void two_step_tile(const LatDesc& Ld, int parity) {
       }
     }
     if (x == 0 || x == nx - 1 || y == 0 || y == ny - 1) tl_nsbc<R>(Ld, g, unknown, x, y, rho0, base, mom1);
-    bgk<R>(g, rho0, base, omega);
+    collide<R>(Ld, g, rho0, base, omega);
     const int64_t idx = (int64_t)y * pitch + x;
 #pragma unroll
     for (int i = 0; i < 9; ++i) put<NTS>(B + i * plane + idx, C::enc(g[i], Ld.es[i]));

@@ -10,7 +10,7 @@ from . import lbm as L
 
 
 def member_params(nx, ny, tau, rho0=1.0, bc=(1, 1, 1, 1), gamma=0.6, store="f32", corr_mode=0, grad_order=1,
-                  corner_mode=0, ubase=(0.0, 0.0), f16_exp=None):
+                  corner_mode=0, ubase=(0.0, 0.0), f16_exp=None, mrt=None):
     p = L.lbm_params_default()
     p.nx, p.ny, p.tau, p.rho0, p.gamma = int(nx), int(ny), float(tau), float(rho0), float(gamma)
     for e in range(4):
@@ -19,6 +19,9 @@ def member_params(nx, ny, tau, rho0=1.0, bc=(1, 1, 1, 1), gamma=0.6, store="f32"
     p.corr_mode, p.grad_order, p.corner_mode = int(corr_mode), int(grad_order), int(corner_mode)
     p.f16_exp = L.LBM_F16_EXP_AUTO if f16_exp is None else int(f16_exp)
     p.ubase[0], p.ubase[1] = float(ubase[0]), float(ubase[1])
+    if mrt is not None:
+        p.collision = L.LBM_COLL_MRT
+        p.omega_e, p.omega_eps, p.omega_q = (float(r) for r in mrt)
     return p
 
 

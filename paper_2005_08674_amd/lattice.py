@@ -10,7 +10,8 @@ from . import lbm as L
 
 
 class Lattice:
-    """D2Q9 BGK lattice with NSBC/periodic edges on one GPU.
+    """D2Q9 lattice (BGK, or MRT with ``mrt`` = (omega_e, omega_eps, omega_q)) with NSBC/periodic
+    edges on one GPU.
 
     ``fields`` = (drho, ux, uy), [ny][nx] arrays (numpy or torch) with
     drho = rho - rho0.  ``bc`` = (left, right, bottom, top), 1 = NSBC,
@@ -20,7 +21,7 @@ class Lattice:
 
     def __init__(self, nx, ny, tau, fields, rho0=1.0, bc=(1, 1, 1, 1), gamma=0.6, store="f32",
                  beta=0.0, m0=None, corr_mode=0, grad_order=1, corner_mode=0, f16_exp=None,
-                 ubase=(0.0, 0.0), device="cuda", stream=None):
+                 ubase=(0.0, 0.0), mrt=None, device="cuda", stream=None):
         p = L.lbm_params_default()
         p.nx, p.ny, p.tau, p.rho0, p.gamma = int(nx), int(ny), float(tau), float(rho0), float(gamma)
         for e in range(4):
@@ -29,6 +30,9 @@ class Lattice:
         p.corr_mode, p.grad_order, p.corner_mode = int(corr_mode), int(grad_order), int(corner_mode)
         p.f16_exp = L.LBM_F16_EXP_AUTO if f16_exp is None else int(f16_exp)
         p.ubase[0], p.ubase[1] = float(ubase[0]), float(ubase[1])
+        if mrt is not None:
+            p.collision = L.LBM_COLL_MRT
+            p.omega_e, p.omega_eps, p.omega_q = (float(r) for r in mrt)
         self.params = p
         self.nx, self.ny, self.rho0 = int(nx), int(ny), float(rho0)
         self.device = torch.device(device)

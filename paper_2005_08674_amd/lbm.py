@@ -29,6 +29,8 @@ LBM_STORE_F32 = 1
 LBM_STORE_F16DEV = 2
 LBM_STORE_BF16DEV = 3
 LBM_F16_EXP_AUTO = -1000
+LBM_COLL_BGK = 0
+LBM_COLL_MRT = 1
 
 STORE_NAMES = {"f64": LBM_STORE_F64, "f32": LBM_STORE_F32, "f16": LBM_STORE_F16DEV, "bf16": LBM_STORE_BF16DEV}
 
@@ -46,8 +48,9 @@ class lbm_params(ctypes.Structure):
                 ("gamma", ctypes.c_double),
                 ("store", ctypes.c_int32), ("corr_mode", ctypes.c_int32),
                 ("grad_order", ctypes.c_int32), ("corner_mode", ctypes.c_int32),
-                ("f16_exp", ctypes.c_int32), ("reserved0", ctypes.c_int32),
-                ("ubase", ctypes.c_double * 2)]
+                ("f16_exp", ctypes.c_int32), ("collision", ctypes.c_int32),
+                ("ubase", ctypes.c_double * 2),
+                ("omega_e", ctypes.c_double), ("omega_eps", ctypes.c_double), ("omega_q", ctypes.c_double)]
 
 
 _lib = None

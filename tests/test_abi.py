@@ -73,6 +73,29 @@ def test_invalid_params_rejected(lib, field, value, msg):
     assert e.value.code == L.LBM_ERR_ARG and msg in str(e.value)
 
 
+def test_collision_model_parameters(lib):
+    """BGK needs tau > 1/2; MRT (Sec. 4) takes tau >= 1/2 and rates in (0, 2]."""
+    p = L.lbm_params_default()
+    assert p.collision == L.LBM_COLL_BGK and (p.omega_e, p.omega_eps, p.omega_q) == (1.9, 1.9, 1.9)
+    p.nx = p.ny = 16
+    p.collision = 7
+    with pytest.raises(L.LbmError, match="collision"):
+        L.lbm_workspace_bytes(p)
+    p.collision = L.LBM_COLL_MRT
+    p.tau = 0.5
+    assert L.lbm_workspace_bytes(p) > 0
+    p.tau = 0.49
+    with pytest.raises(L.LbmError, match="tau"):
+        L.lbm_workspace_bytes(p)
+    p.tau = 0.6
+    for bad in (0.0, 2.01, float("nan")):
+        p.omega_q = bad
+        with pytest.raises(L.LbmError, match="MRT rates"):
+            L.lbm_workspace_bytes(p)
+    p.omega_q = 2.0
+    assert L.lbm_workspace_bytes(p) > 0
+
+
 def test_unpaired_periodic_edges_rejected(lib):
     p = L.lbm_params_default()
     p.nx = p.ny = 16
