@@ -252,9 +252,11 @@ template <> __device__ inline const double* mrt_k<double>(const LatDesc& L) { re
 template <> __device__ inline const float* mrt_k<float>(const LatDesc& L) { return L.mkf; }
 
 // The lattice's collision (BGK, eq. lbe_1, or MRT, eq. mrt_lbe), in place.
-template <class R>
+// CM fixes the model at compile time (COLL_BGK or COLL_MRT); the default -1
+// reads it from the descriptor.
+template <class R, int CM = -1>
 __device__ inline void collide(const LatDesc& L, R g[9], R rho0, const Base<R>& b, R omega) {
-  if (L.coll == COLL_MRT) {
+  if (CM == COLL_MRT || (CM < 0 && L.coll == COLL_MRT)) {
     const R* kp = mrt_k<R>(L);
     const R k[4] = {kp[0], kp[1], kp[2], kp[3]};
     mrt<R>(g, rho0, b, k);

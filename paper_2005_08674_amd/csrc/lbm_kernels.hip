@@ -23,7 +23,6 @@
 #include "lbm_device.h"
 #include "lbm_launch.h"
 #include "lbm_sweep.h"
-#include "lbm_twostep_lds.h"
 
 namespace lbm {
 
@@ -245,80 +244,6 @@ hipError_t launch_bulk(const LatDesc& L, int parity, int tile, hipStream_t s) {
     case ST_F32: return launch_bulk_s<ST_F32>(L, parity, tile, s);
     case ST_F16: return launch_bulk_s<ST_F16>(L, parity, tile, s);
     case ST_BF16: return launch_bulk_s<ST_BF16>(L, parity, tile, s);
-  }
-  return hipErrorInvalidValue;
-}
-
-// ------------------------------------------------------------------ two-step kernel
-// Candidate shapes of the two-step sweep (lbm_twostep_lds.h): output tile
-// 64 x TY, NT threads per block, non-temporal stores (NTS).
-#define LBM_TWO_STEP(X) \
-  X(8, 256, true)       \
-  X(12, 256, true)      \
-  X(16, 256, true)      \
-  X(12, 512, true)      \
-  X(16, 512, true)      \
-  X(20, 512, true)      \
-  X(24, 512, true)      \
-  X(16, 512, false)
-
-template <int S, int TY, int NT, bool NTS>
-__global__ __launch_bounds__(NT) void k_two_step(LatDesc L, int parity) {
-  two_step_tile<S, TY, NT, NTS>(L, parity);
-}
-
-struct TwoStepShape {
-  int ty, nt;
-  bool nts;
-};
-static const TwoStepShape kTwo[] = {
-#define X(a, b, c) {a, b, c},
-    LBM_TWO_STEP(X)
-#undef X
-};
-static constexpr int kNumTwo = sizeof(kTwo) / sizeof(kTwo[0]);
-
-int num_two_step() { return kNumTwo; }
-
-void two_step_name(int id, char* buf, size_t len) {
-  if (id < 0 || id >= kNumTwo) {
-    snprintf(buf, len, "invalid");
-    return;
-  }
-  const TwoStepShape& t = kTwo[id];
-  snprintf(buf, len, "2step:64x%d/%d%s", t.ty, t.nt, t.nts ? "+nts" : "");
-}
-
-bool two_step_supported(const LatDesc& L) {
-  return L.bc[E_LEFT] == BC_NSBC && L.bc[E_RIGHT] == BC_NSBC && L.bc[E_BOTTOM] == BC_NSBC &&
-         L.bc[E_TOP] == BC_NSBC && L.nx >= 3 && L.ny >= 3;
-}
-
-template <int S, int TY, int NT, bool NTS>
-static hipError_t launch_two_t(const LatDesc& L, int parity, hipStream_t s) {
-  const dim3 grid((L.nx + TL_TX - 1) / TL_TX, (L.ny + TY - 1) / TY);
-  k_two_step<S, TY, NT, NTS><<<grid, dim3(NT), 0, s>>>(L, parity);
-  return hipGetLastError();
-}
-
-template <int S>
-static hipError_t launch_two_s(const LatDesc& L, int parity, int id, hipStream_t s) {
-  int k = 0;
-#define X(a, b, c)                                               \
-  if (id == k) return launch_two_t<S, a, b, c>(L, parity, s);   \
-  ++k;
-  LBM_TWO_STEP(X)
-#undef X
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_two_step(const LatDesc& L, int parity, int id, hipStream_t s) {
-  if (!two_step_supported(L)) return hipErrorInvalidValue;
-  switch (L.store) {
-    case ST_F64: return launch_two_s<ST_F64>(L, parity, id, s);
-    case ST_F32: return launch_two_s<ST_F32>(L, parity, id, s);
-    case ST_F16: return launch_two_s<ST_F16>(L, parity, id, s);
-    case ST_BF16: return launch_two_s<ST_BF16>(L, parity, id, s);
   }
   return hipErrorInvalidValue;
 }

@@ -1,0 +1,129 @@
+// lbm_twostep.hip -- the two-step sweep (t -> t + 2 in one launch, level
+// t + 1 in LDS; lbm_twostep_lds.h) for lattices with NSBC on all four edges:
+// its compile-time shapes, one instance per storage format and collision
+// model, and its host-side launcher.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+
+#include "lbm_device.h"
+#include "lbm_launch.h"
+#include "lbm_twostep_lds.h"
+
+namespace lbm {
+
+// ------------------------------------------------------------------ two-step kernel
+// Candidate shapes of the two-step sweep (lbm_twostep_lds.h): output tile
+// 64 x TY, NT threads per block, non-temporal stores (NTS), block -> tile map
+// (MAP).  Workgroups go to the 8 XCDs round-robin (block b on XCD b mod 8),
+// each XCD with its own L2, and a tile re-reads its neighbours' edge cache
+// lines for its margin:
+//   MAP 0: a 2-D grid, tile = (blockIdx.x, blockIdx.y); horizontal
+//          neighbours run on different XCDs.
+//   MAP 1: a 1-D grid over the row-major tiles in runs of 64 blocks; XCD k
+//          takes 8 consecutive tiles of each run, so 7 of 8 horizontal
+//          neighbours share an L2.
+//   MAP 2: XCD k takes the k-th contiguous eighth of the row-major tiles, so
+//          horizontal and vertical neighbours share an L2 except at the
+//          eight band boundaries.
+#define LBM_TWO_STEP(X)  \
+  X(12, 256, true, 0)    \
+  X(16, 256, true, 0)    \
+  X(12, 512, true, 0)    \
+  X(16, 512, true, 0)    \
+  X(20, 512, true, 0)    \
+  X(24, 512, true, 0)    \
+  X(12, 512, true, 1)    \
+  X(16, 512, true, 1)    \
+  X(20, 512, true, 1)    \
+  X(12, 512, true, 2)    \
+  X(16, 512, true, 2)    \
+  X(20, 512, true, 2)
+
+template <int S, int TY, int NT, bool NTS, int CM, int MAP>
+__global__ __launch_bounds__(NT) void k_two_step(LatDesc L, int parity, int tiles_x, int tiles_y) {
+  int txi, tyi;
+  if (MAP == 0) {
+    txi = blockIdx.x;
+    tyi = blockIdx.y;
+  } else {
+    const int b = blockIdx.x, ntiles = tiles_x * tiles_y;
+    int tile;
+    if (MAP == 1) {
+      tile = (b & ~63) + ((b & 7) << 3) + ((b >> 3) & 7);
+    } else {
+      const int per = (ntiles + 7) >> 3;
+      tile = (b & 7) * per + (b >> 3);
+    }
+    if (tile >= ntiles) return;  // padding blocks: the whole block leaves before any barrier
+    tyi = tile / tiles_x;
+    txi = tile - tyi * tiles_x;
+  }
+  two_step_tile<S, TY, NT, NTS, CM>(L, parity, txi, tyi);
+}
+
+struct TwoStepShape {
+  int ty, nt;
+  bool nts;
+  int map;
+};
+static const TwoStepShape kTwo[] = {
+#define X(a, b, c, d) {a, b, c, d},
+    LBM_TWO_STEP(X)
+#undef X
+};
+static constexpr int kNumTwo = sizeof(kTwo) / sizeof(kTwo[0]);
+
+int num_two_step() { return kNumTwo; }
+
+void two_step_name(int id, char* buf, size_t len) {
+  if (id < 0 || id >= kNumTwo) {
+    snprintf(buf, len, "invalid");
+    return;
+  }
+  const TwoStepShape& t = kTwo[id];
+  snprintf(buf, len, "2step:64x%d/%d%s%s", t.ty, t.nt, t.map == 1 ? "+xcd8" : (t.map == 2 ? "+xcdband" : ""),
+           t.nts ? "+nts" : "");
+}
+
+bool two_step_supported(const LatDesc& L) {
+  return L.bc[E_LEFT] == BC_NSBC && L.bc[E_RIGHT] == BC_NSBC && L.bc[E_BOTTOM] == BC_NSBC &&
+         L.bc[E_TOP] == BC_NSBC && L.nx >= 3 && L.ny >= 3;
+}
+
+template <int S, int TY, int NT, bool NTS, int MAP>
+static hipError_t launch_two_t(const LatDesc& L, int parity, hipStream_t s) {
+  const int tiles_x = (L.nx + TL_TX - 1) / TL_TX, tiles_y = (L.ny + TY - 1) / TY;
+  dim3 grid(tiles_x, tiles_y);
+  if (MAP == 1) grid = dim3(((tiles_x * tiles_y + 63) >> 6) * 64);
+  if (MAP == 2) grid = dim3(((tiles_x * tiles_y + 7) >> 3) * 8);
+  if (L.coll == COLL_MRT)
+    k_two_step<S, TY, NT, NTS, COLL_MRT, MAP><<<grid, dim3(NT), 0, s>>>(L, parity, tiles_x, tiles_y);
+  else
+    k_two_step<S, TY, NT, NTS, COLL_BGK, MAP><<<grid, dim3(NT), 0, s>>>(L, parity, tiles_x, tiles_y);
+  return hipGetLastError();
+}
+
+template <int S>
+static hipError_t launch_two_s(const LatDesc& L, int parity, int id, hipStream_t s) {
+  int k = 0;
+#define X(a, b, c, d)                                               \
+  if (id == k) return launch_two_t<S, a, b, c, d>(L, parity, s);   \
+  ++k;
+  LBM_TWO_STEP(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_two_step(const LatDesc& L, int parity, int id, hipStream_t s) {
+  if (!two_step_supported(L)) return hipErrorInvalidValue;
+  switch (L.store) {
+    case ST_F64: return launch_two_s<ST_F64>(L, parity, id, s);
+    case ST_F32: return launch_two_s<ST_F32>(L, parity, id, s);
+    case ST_F16: return launch_two_s<ST_F16>(L, parity, id, s);
+    case ST_BF16: return launch_two_s<ST_BF16>(L, parity, id, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace lbm

@@ -82,9 +82,10 @@ __device__ inline void tl_nsbc(const LatDesc& Ld, R g[9], uint32_t unknown, int 
 
 // NT threads per block.  Level t + 1 is kept in LDS in the storage format
 // (encoded exactly as a store would write it, decoded on every read), which
-// halves the LDS of the 16-bit formats.
-template <int S, int TY, int NT, bool NTS>
-__device__ inline void two_step_tile(const LatDesc& Ld, int parity) {
+// halves the LDS of the 16-bit formats.  CM is the collision model, fixed at
+// compile time (COLL_BGK or COLL_MRT).
+template <int S, int TY, int NT, bool NTS, int CM>
+__device__ inline void two_step_tile(const LatDesc& Ld, int parity, int txi, int tyi) {
   using C = Codec<S>;
   using T = typename C::T;
   using R = typename C::R;
@@ -92,7 +93,7 @@ __device__ inline void two_step_tile(const LatDesc& Ld, int parity) {
   __shared__ T lds[9][TH][TL_W];
 
   const int nx = Ld.nx, ny = Ld.ny;
-  const int x0 = blockIdx.x * TL_TX, y0 = blockIdx.y * TY;
+  const int x0 = txi * TL_TX, y0 = tyi * TY;
   const int tid = threadIdx.x;
   const bool edge_tile = x0 == 0 || x0 + TL_TX >= nx || y0 == 0 || y0 + TY >= ny;
   const int my = edge_tile ? 2 : 1;        // row margin of level t + 1
@@ -126,7 +127,7 @@ __device__ inline void two_step_tile(const LatDesc& Ld, int parity) {
       auto mom = [&](int xx, int yy, R m[3]) { tl_moments_global<S>(Ld, A, xx, yy, base, m); };
       tl_nsbc<R>(Ld, g, unknown, x, y, rho0, base, mom);
     }
-    collide<R>(Ld, g, rho0, base, omega);
+    collide<R, CM>(Ld, g, rho0, base, omega);
     // encoded as the single-step path's store would write it
 #pragma unroll
     for (int i = 0; i < 9; ++i) lds[i][ly0 + r][cx] = C::enc(g[i], Ld.es[i]);
@@ -158,7 +159,7 @@ __device__ inline void two_step_tile(const LatDesc& Ld, int parity) {
       }
     }
     if (x == 0 || x == nx - 1 || y == 0 || y == ny - 1) tl_nsbc<R>(Ld, g, unknown, x, y, rho0, base, mom1);
-    collide<R>(Ld, g, rho0, base, omega);
+    collide<R, CM>(Ld, g, rho0, base, omega);
     const int64_t idx = (int64_t)y * pitch + x;
 #pragma unroll
     for (int i = 0; i < 9; ++i) put<NTS>(B + i * plane + idx, C::enc(g[i], Ld.es[i]));
