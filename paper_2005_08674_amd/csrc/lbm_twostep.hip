@@ -26,19 +26,19 @@ namespace lbm {
 //   MAP 2: XCD k takes the k-th contiguous eighth of the row-major tiles, so
 //          horizontal and vertical neighbours share an L2 except at the
 //          eight band boundaries.
+// TY and NT trade the margin's share of the work, the idle lanes of the last
+// pass over the (TY + 2) x 68 and TY x 64 nodes, and the blocks that fit in
+// a CU's LDS.
 #define LBM_TWO_STEP(X)  \
-  X(12, 256, true, 0)    \
-  X(16, 256, true, 0)    \
   X(12, 512, true, 0)    \
   X(16, 512, true, 0)    \
-  X(20, 512, true, 0)    \
-  X(24, 512, true, 0)    \
-  X(12, 512, true, 1)    \
   X(16, 512, true, 1)    \
-  X(20, 512, true, 1)    \
   X(12, 512, true, 2)    \
   X(16, 512, true, 2)    \
-  X(20, 512, true, 2)
+  X(20, 512, true, 2)    \
+  X(8, 256, true, 2)     \
+  X(12, 384, true, 2)    \
+  X(24, 768, true, 2)
 
 template <int S, int TY, int NT, bool NTS, int CM, int MAP>
 __global__ __launch_bounds__(NT) void k_two_step(LatDesc L, int parity, int tiles_x, int tiles_y) {

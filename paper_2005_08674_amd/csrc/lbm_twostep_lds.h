@@ -106,6 +106,45 @@ __device__ inline void two_step_tile(const LatDesc& Ld, int parity, int txi, int
   const R rho0 = R(Ld.rho0), omega = R(Ld.omega);
   const Base<R> base(Ld);
 
+  // Inner tile: every level t + 1 node (rows y0 - 1 .. y0 + TY, columns
+  // x0 - 2 .. x0 + 65) is an interior lattice node, so no pull leaves the
+  // lattice and no NSBC node occurs: the loops drop those checks (same
+  // arithmetic, same bits) and have trip counts known at compile time.
+  const bool inner = x0 >= 3 && x0 + TL_TX + 3 <= nx && y0 >= 2 && y0 + TY + 2 <= ny;
+  if (inner) {
+    constexpr int N1 = (TY + 2) * TL_W, N2 = TY * TL_TX;
+#pragma unroll
+    for (int it = 0; it < (N1 + NT - 1) / NT; ++it) {
+      const int k = tid + it * NT;
+      if (k < N1) {
+        const int r = k / TL_W, cx = k - r * TL_W;
+        const int64_t idx = (int64_t)(y0 - 1 + r) * pitch + (x0 - 2 + cx);
+        R g[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) g[i] = C::dec(A[i * plane + idx - (kCy[i] * pitch + kCx[i])], Ld.ds[i]);
+        collide<R, CM>(Ld, g, rho0, base, omega);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) lds[i][1 + r][cx] = C::enc(g[i], Ld.es[i]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < (N2 + NT - 1) / NT; ++it) {
+      const int k = tid + it * NT;
+      if (k < N2) {
+        const int r = k / TL_TX, cx = k - r * TL_TX;
+        R g[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) g[i] = C::dec(lds[i][r + 2 - kCy[i]][cx + 2 - kCx[i]], Ld.ds[i]);
+        collide<R, CM>(Ld, g, rho0, base, omega);
+        const int64_t idx = (int64_t)(y0 + r) * pitch + (x0 + cx);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) put<NTS>(B + i * plane + idx, C::enc(g[i], Ld.es[i]));
+      }
+    }
+    return;
+  }
+
   // ---- level t + 1 on lattice rows y0 - my .. y0 + TY + my - 1, columns x0 - 2 .. x0 + 65
   for (int k = tid; k < rows1 * TL_W; k += NT) {
     const int r = k / TL_W, cx = k - r * TL_W;
