@@ -49,14 +49,17 @@ int lbm_ens_init(lbm_ens** out, const lbm_params* members, int32_t count, void* 
  * effect from the next step, including steps of already captured graphs. */
 int lbm_ens_set_farfield(lbm_ens* e, int32_t member, double beta, double rho_ref, double ux_ref, double uy_ref);
 
-/* Advance every member n >= 0 steps with two kernel launches per step. */
+/* Advance every member n >= 0 steps: one launch per step (fused edge and
+ * bulk work), two per step when fusion is off or a member runs the closure,
+ * or one launch per two steps when the two-step sweep is on (an odd last
+ * step runs singly). */
 int lbm_ens_step(lbm_ens* e, int32_t n);
 
 /* Advance every member n >= 1 steps with one launch of a HIP graph holding
- * the n steps' kernel launches (one per step when fused, else two).  The
+ * the n steps' kernel launches (as lbm_ens_step would issue them).  The
  * graph is captured and instantiated on first use for this n (and step
- * parity) and cached until lbm_ens_destroy or a change of shape, fusion or
- * closure set. */
+ * parity) and cached until lbm_ens_destroy or a change of shape, fusion,
+ * two-step shape or closure set. */
 int lbm_ens_step_graph(lbm_ens* e, int32_t n);
 
 /* on = 1 (the default): each step is one launch whose first blocks run the
@@ -90,6 +93,25 @@ int lbm_ens_shape_count(void);
 int lbm_ens_shape_describe(int32_t id, char* buf, size_t len);
 int lbm_ens_set_shape(lbm_ens* e, int32_t id);
 int lbm_ens_autotune(lbm_ens* e, int32_t reps, int32_t* best, float* times_ms);
+
+/* Two-step sweep over the whole ensemble (the single-lattice sweep of
+ * lbm_set_two_step, lbm.h: level t + 1 of each 64 x TY tile kept in LDS,
+ * eqs. lbe_0, lbe_1 / mrt_lbe and nes_0..nes_4 applied twice; results
+ * bit-identical to single steps).  Shapes are the lbm_two_step_count /
+ * lbm_two_step_describe candidates; the ensemble lays every member's tiles
+ * out in one list whose contiguous eighths run on the 8 XCDs (the shape's
+ * own block map is not used).  lbm_ens_set_two_step selects a shape (-1, the
+ * default, turns the sweep off); LBM_ERR_UNSUPPORTED unless every member has
+ * NSBC on all four edges.  While a member runs the learned closure the
+ * ensemble steps singly.  lbm_ens_autotune_two_step times every shape (median
+ * of `reps` launches, after one warm-up; the state is not advanced), selects
+ * the fastest and writes its id to *best and, if times_ms is not NULL, the
+ * per-shape median time of one launch (two steps) in milliseconds (length
+ * lbm_two_step_count).  Both drop cached graphs; the autotuner synchronizes
+ * the stream. */
+int lbm_ens_set_two_step(lbm_ens* e, int32_t id);
+int lbm_ens_get_two_step(const lbm_ens* e, int32_t* id);
+int lbm_ens_autotune_two_step(lbm_ens* e, int32_t reps, int32_t* best, float* times_ms);
 
 /* Release the ensemble (waits for its stream; destroys cached graphs). */
 void lbm_ens_destroy(lbm_ens* e);

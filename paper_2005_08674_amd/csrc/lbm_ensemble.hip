@@ -22,6 +22,7 @@
 #include "lbm_host.h"
 #include "lbm_launch.h"
 #include "lbm_sweep.h"
+#include "lbm_twostep_lds.h"
 
 namespace lbm {
 
@@ -201,8 +202,8 @@ using lbm::host::fail;
 constexpr size_t kAlign = 4096;
 
 struct EnsLayout {
-  size_t off_descs, off_tiles, off_segs, off_work, off_scratch, off_lattices, total;
-  size_t max_tiles, nsegs, max_work;
+  size_t off_descs, off_tiles, off_segs, off_work, off_two, off_scratch, off_lattices, total;
+  size_t max_tiles, nsegs, max_work, max_two;
   std::vector<size_t> lat_off;  // member buffers, relative to the workspace
   std::vector<lbm::host::Layout> lat;
 };
@@ -242,6 +243,14 @@ int ens_layout(const lbm_params* m, int32_t count, EnsLayout& L) {
   L.max_work = 8 * (L.max_tiles + L.nsegs) + 64;
   L.off_work = off;
   off = round_up(off + sizeof(lbm::EnsWork) * L.max_work, kAlign);
+  // tile list of the two-step sweep at its shortest tiles, padded to a multiple of 8
+  L.max_two = 8;
+  const int tymin = lbm::two_step_min_rows();
+  for (int32_t k = 0; k < count; ++k)
+    L.max_two += (size_t)((m[k].nx + lbm::TL_TX - 1) / lbm::TL_TX) * ((m[k].ny + tymin - 1) / tymin);
+  if (L.max_two > (size_t)INT32_MAX) return fail(LBM_ERR_ARG, "ensemble too large");
+  L.off_two = off;
+  off = round_up(off + sizeof(lbm::TwoTile) * L.max_two, kAlign);
   L.off_scratch = off;
   off = round_up(off + lbm::host::kScratchBytes, (size_t)2 << 20);
   L.off_lattices = off;
@@ -278,6 +287,9 @@ struct lbm_ens {
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
   bool any_closure = false;
   bool fused = true;  // one launch per step when no member runs the closure
+  int two = -1;       // two-step shape, or -1 (single steps)
+  lbm::TwoTile* d_two = nullptr;
+  int32_t ntwo = 0;
 };
 
 namespace {
@@ -354,6 +366,49 @@ int build_tiles(lbm_ens* e, int shape) {
   return LBM_OK;
 }
 
+// Two-step tile list in block order: the member-major, row-major list of
+// 64 x TY tiles is cut into 8 contiguous stretches and block b takes item
+// (b mod 8) * per + b / 8, so XCD k (block b runs on XCD b mod 8) works through
+// stretch k and neighbouring tiles share its L2; the tail pads with lat = -1.
+int build_two(lbm_ens* e, int id) {
+  const int ty = lbm::two_step_tile_rows(id);
+  if (ty <= 0) return fail(LBM_ERR_ARG, "two-step shape %d out of range", id);
+  std::vector<lbm::TwoTile> items;
+  for (int32_t k = 0; k < e->count; ++k) {
+    const int tx = (e->p[k].nx + lbm::TL_TX - 1) / lbm::TL_TX, tyn = (e->p[k].ny + ty - 1) / ty;
+    for (int j = 0; j < tyn; ++j)
+      for (int i = 0; i < tx; ++i) items.push_back({k, i, j, 0});
+  }
+  const size_t n = items.size(), per = (n + 7) / 8;
+  std::vector<lbm::TwoTile> list(8 * per, lbm::TwoTile{-1, 0, 0, 0});
+  for (size_t b = 0; b < list.size(); ++b) {
+    const size_t item = (b & 7) * per + (b >> 3);
+    if (item < n) list[b] = items[item];
+  }
+  if (list.size() > e->lay.max_two) return fail(LBM_ERR_STATE, "two-step list overflow");
+  HIPCHK(hipMemcpyAsync(e->d_two, list.data(), sizeof(lbm::TwoTile) * list.size(), hipMemcpyHostToDevice,
+                        e->stream));
+  HIPCHK(hipStreamSynchronize(e->stream));
+  e->ntwo = (int32_t)list.size();
+  e->two = id;
+  drop_graphs(e);
+  return LBM_OK;
+}
+
+bool two_supported(const lbm_ens* e) {
+  for (const auto& d : e->descs)
+    if (!lbm::two_step_supported(d)) return false;
+  return true;
+}
+
+// Members on the learned closure need the separate edge launch, so they step singly.
+bool use_two(const lbm_ens* e) { return e->two >= 0 && !e->any_closure; }
+
+int ens_launch_two(lbm_ens* e, int parity, hipStream_t s) {
+  HIPCHK(lbm::launch_ens_two_step(e->store, e->two, e->d_descs, e->d_two, e->ntwo, parity, s));
+  return LBM_OK;
+}
+
 int ens_launch_step(lbm_ens* e, int parity, hipStream_t s) {
   if (!e->any_closure && e->fused) {
     HIPCHK(lbm::launch_ens_step(e->store, e->shape, e->d_descs, e->d_work, e->nwork, parity, s));
@@ -413,6 +468,7 @@ int lbm_ens_init(lbm_ens** out, const lbm_params* members, int32_t count, void* 
   e->d_tiles = reinterpret_cast<lbm::EnsTile*>(e->ws + lay.off_tiles);
   e->d_segs = reinterpret_cast<lbm::EnsSeg*>(e->ws + lay.off_segs);
   e->d_work = reinterpret_cast<lbm::EnsWork*>(e->ws + lay.off_work);
+  e->d_two = reinterpret_cast<lbm::TwoTile*>(e->ws + lay.off_two);
   if (hipStreamCreateWithFlags(&e->cap, hipStreamNonBlocking) != hipSuccess) {
     lbm_ens_destroy(e);
     return fail(LBM_ERR_HIP, "capture stream creation failed");
@@ -489,11 +545,13 @@ int lbm_ens_set_farfield(lbm_ens* e, int32_t member, double beta, double rho_ref
 int lbm_ens_step(lbm_ens* e, int32_t n) {
   if (!e) return fail(LBM_ERR_ARG, "ensemble is NULL");
   if (n < 0) return fail(LBM_ERR_ARG, "n = %d < 0", n);
-  for (int32_t s = 0; s < n; ++s) {
-    int rc = ens_launch_step(e, e->parity, e->stream);
+  for (int32_t s = 0; s < n;) {
+    const bool two = use_two(e) && n - s >= 2;
+    int rc = two ? ens_launch_two(e, e->parity, e->stream) : ens_launch_step(e, e->parity, e->stream);
     if (rc) return rc;
-    e->parity ^= 1;
-    e->t += 1;
+    e->parity ^= 1;  // a two-step launch writes t + 2 into the other buffer
+    e->t += two ? 2 : 1;
+    s += two ? 2 : 1;
   }
   return LBM_OK;
 }
@@ -501,13 +559,20 @@ int lbm_ens_step(lbm_ens* e, int32_t n) {
 int lbm_ens_step_graph(lbm_ens* e, int32_t n) {
   if (!e) return fail(LBM_ERR_ARG, "ensemble is NULL");
   if (n < 1 || n > 100000) return fail(LBM_ERR_ARG, "n = %d outside [1, 100000]", n);
+  const bool two = use_two(e);
+  const int launches = two ? n / 2 + (n & 1) : n;
   const std::pair<int, int> key(n, e->parity);
   auto it = e->graphs.find(key);
   if (it == e->graphs.end()) {
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(e->cap, hipStreamCaptureModeThreadLocal));
     int rc = LBM_OK;
-    for (int32_t s = 0; s < n && rc == LBM_OK; ++s) rc = ens_launch_step(e, e->parity ^ (s & 1), e->cap);
+    int p = e->parity;
+    for (int32_t s = 0; s < n && rc == LBM_OK; p ^= 1) {
+      const bool pair = two && n - s >= 2;
+      rc = pair ? ens_launch_two(e, p, e->cap) : ens_launch_step(e, p, e->cap);
+      s += pair ? 2 : 1;
+    }
     hipError_t he = hipStreamEndCapture(e->cap, &g);
     if (rc) {
       if (g) (void)hipGraphDestroy(g);
@@ -521,7 +586,7 @@ int lbm_ens_step_graph(lbm_ens* e, int32_t n) {
     it = e->graphs.emplace(key, x).first;
   }
   HIPCHK(hipGraphLaunch(it->second, e->stream));
-  e->parity ^= (n & 1);
+  e->parity ^= (launches & 1);
   e->t += n;
   return LBM_OK;
 }
@@ -655,6 +720,66 @@ int lbm_ens_autotune(lbm_ens* e, int32_t reps, int32_t* best, float* times_ms) {
   for (auto& x : ev) (void)hipEventDestroy(x);
   if (rc) return rc;
   rc = build_tiles(e, best_id);
+  if (rc) return rc;
+  *best = best_id;
+  return LBM_OK;
+}
+
+int lbm_ens_set_two_step(lbm_ens* e, int32_t id) {
+  if (!e) return fail(LBM_ERR_ARG, "ensemble is NULL");
+  if (id == -1) {
+    if (e->two != -1) drop_graphs(e);
+    e->two = -1;
+    return LBM_OK;
+  }
+  if (id < 0 || id >= lbm::num_two_step()) return fail(LBM_ERR_ARG, "two-step shape %d out of range", id);
+  if (!two_supported(e)) return fail(LBM_ERR_UNSUPPORTED, "the two-step sweep needs NSBC on all four edges of every member");
+  return build_two(e, id);
+}
+
+int lbm_ens_get_two_step(const lbm_ens* e, int32_t* id) {
+  if (!e || !id) return fail(LBM_ERR_ARG, "NULL argument");
+  *id = e->two;
+  return LBM_OK;
+}
+
+int lbm_ens_autotune_two_step(lbm_ens* e, int32_t reps, int32_t* best, float* times_ms) {
+  if (!e || !best) return fail(LBM_ERR_ARG, "NULL argument");
+  if (reps < 1 || reps > 1000) return fail(LBM_ERR_ARG, "reps = %d outside [1, 1000]", reps);
+  if (!two_supported(e)) return fail(LBM_ERR_UNSUPPORTED, "the two-step sweep needs NSBC on all four edges of every member");
+  std::vector<hipEvent_t> ev(2 * reps);
+  for (auto& x : ev) HIPCHK(hipEventCreate(&x));
+  float best_t = 1e30f;
+  int best_id = 0;
+  int rc = LBM_OK;
+  for (int id = 0; id < lbm::num_two_step() && rc == LBM_OK; ++id) {
+    rc = build_two(e, id);
+    if (rc) break;
+    // the sweep reads buffer `parity` and writes only the other one: the state is not advanced
+    hipError_t he = lbm::launch_ens_two_step(e->store, id, e->d_descs, e->d_two, e->ntwo, e->parity, e->stream);
+    for (int r = 0; r < reps && he == hipSuccess; ++r) {
+      he = hipEventRecord(ev[2 * r], e->stream);
+      if (he == hipSuccess)
+        he = lbm::launch_ens_two_step(e->store, id, e->d_descs, e->d_two, e->ntwo, e->parity, e->stream);
+      if (he == hipSuccess) he = hipEventRecord(ev[2 * r + 1], e->stream);
+    }
+    if (he == hipSuccess) he = hipStreamSynchronize(e->stream);
+    std::vector<float> ts(reps);
+    for (int r = 0; r < reps && he == hipSuccess; ++r) he = hipEventElapsedTime(&ts[r], ev[2 * r], ev[2 * r + 1]);
+    if (he != hipSuccess) {
+      rc = fail(LBM_ERR_HIP, "ensemble two-step shape %d: %s", id, hipGetErrorString(he));
+      break;
+    }
+    std::sort(ts.begin(), ts.end());
+    if (times_ms) times_ms[id] = ts[reps / 2];
+    if (ts[reps / 2] < best_t) {
+      best_t = ts[reps / 2];
+      best_id = id;
+    }
+  }
+  for (auto& x : ev) (void)hipEventDestroy(x);
+  if (rc) return rc;
+  rc = build_two(e, best_id);
   if (rc) return rc;
   *best = best_id;
   return LBM_OK;

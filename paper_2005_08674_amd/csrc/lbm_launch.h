@@ -20,6 +20,15 @@ int num_two_step();
 void two_step_name(int id, char* buf, size_t len);
 bool two_step_supported(const LatDesc& L);
 hipError_t launch_two_step(const LatDesc& L, int parity, int id, hipStream_t s);
+// output tile rows of two-step shape id (0 if invalid), and the smallest over all shapes
+int two_step_tile_rows(int id);
+int two_step_min_rows();
+// ensemble two-step: one block per list entry (member, 64-column tile x, tile y); lat < 0 = padding
+struct TwoTile {
+  int32_t lat, txi, tyi, pad;
+};
+hipError_t launch_ens_two_step(int store, int id, const LatDesc* d, const TwoTile* list, int n, int parity,
+                               hipStream_t s);
 hipError_t launch_init(const LatDesc& L, int parity, const double* drho, const double* ux, const double* uy,
                        hipStream_t s);
 int absmax_blocks();

@@ -126,4 +126,53 @@ hipError_t launch_two_step(const LatDesc& L, int parity, int id, hipStream_t s) 
   return hipErrorInvalidValue;
 }
 
+// ------------------------------------------------------------------ ensemble
+// One block per entry of a device list of (member, tile) in block order (the
+// host lays the list out so that each XCD takes a contiguous stretch of it);
+// entries with lat < 0 pad the grid.  The member's descriptor carries its
+// collision model, read at run time.
+template <int S, int TY, int NT, bool NTS>
+__global__ __launch_bounds__(NT) void k_ens_two_step(const LatDesc* __restrict__ descs,
+                                                     const TwoTile* __restrict__ list, int parity) {
+  const TwoTile t = list[blockIdx.x];
+  if (t.lat < 0) return;  // padding: the whole block leaves before any barrier
+  const LatDesc L = descs[t.lat];
+  two_step_tile<S, TY, NT, NTS, -1>(L, parity, t.txi, t.tyi);
+}
+
+int two_step_tile_rows(int id) { return id >= 0 && id < kNumTwo ? kTwo[id].ty : 0; }
+
+int two_step_min_rows() {
+  int m = kTwo[0].ty;
+  for (int i = 1; i < kNumTwo; ++i) m = kTwo[i].ty < m ? kTwo[i].ty : m;
+  return m;
+}
+
+template <int S>
+static hipError_t launch_ens_two_s(int id, const LatDesc* d, const TwoTile* list, int n, int parity,
+                                   hipStream_t s) {
+  int k = 0;
+#define X(a, b, c, m)                                                                   \
+  if (id == k) {                                                                        \
+    k_ens_two_step<S, a, b, c><<<dim3(n), dim3(b), 0, s>>>(d, list, parity);            \
+    return hipGetLastError();                                                           \
+  }                                                                                     \
+  ++k;
+  LBM_TWO_STEP(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_ens_two_step(int store, int id, const LatDesc* d, const TwoTile* list, int n, int parity,
+                               hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  switch (store) {
+    case ST_F64: return launch_ens_two_s<ST_F64>(id, d, list, n, parity, s);
+    case ST_F32: return launch_ens_two_s<ST_F32>(id, d, list, n, parity, s);
+    case ST_F16: return launch_ens_two_s<ST_F16>(id, d, list, n, parity, s);
+    case ST_BF16: return launch_ens_two_s<ST_BF16>(id, d, list, n, parity, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 }  // namespace lbm

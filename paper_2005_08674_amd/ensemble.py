@@ -74,6 +74,13 @@ class Ensemble:
     def autotune(self, reps=5):
         return L.lbm_ens_autotune(self.ens, reps)
 
+    def set_two_step(self, shape_id):
+        """Two-step sweep shape (-1: single steps)."""
+        L.lbm_ens_set_two_step(self.ens, shape_id)
+
+    def autotune_two_step(self, reps=5):
+        return L.lbm_ens_autotune_two_step(self.ens, reps)
+
     def close(self):
         if getattr(self, "ens", None) is not None:
             L.lbm_ens_destroy(self.ens)

@@ -102,6 +102,9 @@ _SIGS = {
     "lbm_ens_shape_describe": [ctypes.c_int32, _P, ctypes.c_size_t],
     "lbm_ens_set_shape": [_P, ctypes.c_int32],
     "lbm_ens_autotune": [_P, ctypes.c_int32, _P, _P],
+    "lbm_ens_set_two_step": [_P, ctypes.c_int32],
+    "lbm_ens_get_two_step": [_P, _P],
+    "lbm_ens_autotune_two_step": [_P, ctypes.c_int32, _P, _P],
     # learned closure (include/lbm_closure.h)
     "lbm_closure_net_bytes": [_P],
     "lbm_set_closure": [_P, _P, ctypes.c_int],
@@ -396,6 +399,23 @@ def lbm_ens_autotune(ens, reps: int = 5):
     best = ctypes.c_int32()
     times = (ctypes.c_float * lbm_ens_shape_count())()
     _check(load().lbm_ens_autotune(ens, int(reps), ctypes.byref(best), times), "lbm_ens_autotune")
+    return best.value, list(times)
+
+
+def lbm_ens_set_two_step(ens, shape_id: int):
+    _check(load().lbm_ens_set_two_step(ens, int(shape_id)), "lbm_ens_set_two_step")
+
+
+def lbm_ens_get_two_step(ens) -> int:
+    v = ctypes.c_int32()
+    _check(load().lbm_ens_get_two_step(ens, ctypes.byref(v)), "lbm_ens_get_two_step")
+    return v.value
+
+
+def lbm_ens_autotune_two_step(ens, reps: int = 5):
+    best = ctypes.c_int32()
+    times = (ctypes.c_float * lbm_two_step_count())()
+    _check(load().lbm_ens_autotune_two_step(ens, int(reps), ctypes.byref(best), times), "lbm_ens_autotune_two_step")
     return best.value, list(times)
 
 

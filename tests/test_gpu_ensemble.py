@@ -176,3 +176,93 @@ def test_ensemble_256_one_graph_launch():
         g = _standalone(members[k], fields[k], (0.0, *W.member_m0(ms[k])))
         g.step(400)
         assert np.array_equal(ens.populations(k), g.populations().cpu().numpy()), k
+
+
+def _nsbc_members(store, mrt_every=0):
+    """Uneven lattices with NSBC on all four edges (what the two-step sweep needs), the reading
+    variants, base velocity and, every `mrt_every`-th member, the MRT collision."""
+    from paper_2005_08674_amd.ensemble import member_params
+    rng = np.random.default_rng(41)
+    specs = [dict(nx=67, ny=45), dict(nx=100, ny=90, grad_order=2), dict(nx=3, ny=3), dict(nx=3, ny=150, corner_mode=1),
+             dict(nx=257, ny=64, corr_mode=1), dict(nx=64, ny=257), dict(nx=130, ny=3),
+             dict(nx=333, ny=129, ubase=(0.05, -0.02)), dict(nx=65, ny=66)]
+    members, fields, far = [], [], []
+    for k, sp in enumerate(specs):
+        nx, ny = sp.pop("nx"), sp.pop("ny")
+        tau = float(rng.uniform(0.52, 0.8))
+        mrt = (1.6, 1.4, 1.8) if mrt_every and k % mrt_every == 0 else None
+        members.append(member_params(nx, ny, tau, store=store, mrt=mrt, **sp))
+        u0 = (float(rng.uniform(-0.05, 0.05)), float(rng.uniform(-0.05, 0.05)))
+        fields.append(W.gaussian_pulses(nx, ny, [(1e-3, 5.0, rng.uniform(0, nx), rng.uniform(0, ny))], u0=u0))
+        far.append((float(rng.uniform(0, 0.5)), 1.0 + 1e-4, u0[0], u0[1]))
+    return members, fields, far
+
+
+@pytest.mark.parametrize("store", ["f32", "f16", "f64", "bf16"])
+def test_two_step_equals_single_steps_every_shape(store):
+    """The ensemble two-step sweep (one launch per two steps over every member's tiles) gives the bits of
+    single steps for every shape, eagerly (with an odd step count) and through graphs."""
+    from paper_2005_08674_amd import lbm
+    from paper_2005_08674_amd.ensemble import Ensemble
+    members, fields, far = _nsbc_members(store, mrt_every=3)
+    ref = Ensemble(members, fields)
+    for m, fa in enumerate(far):
+        ref.set_farfield(m, *fa)
+    ref.step(7)
+    ref.step(8)
+    want = [ref.populations(m) for m in range(len(members))]
+    ref.close()
+    for shape in range(lbm.lbm_two_step_count()):
+        print(f"[ensemble two-step] {store} {lbm.lbm_two_step_describe(shape)}", flush=True)
+        e = Ensemble(members, fields)
+        for m, fa in enumerate(far):
+            e.set_farfield(m, *fa)
+        e.set_two_step(shape)
+        assert lbm.lbm_ens_get_two_step(e.ens) == shape
+        e.step(7)
+        e.step_graph(8)
+        assert e.t == 15
+        for m in range(len(members)):
+            assert np.array_equal(e.populations(m), want[m]), (store, shape, m)
+        e.close()
+
+
+def test_two_step_graph_replays_and_autotune():
+    """Replays of a captured two-step graph (odd length) with eager work and a far-field change between
+    them match eager single steps; the autotuner leaves the state untouched and selects a shape."""
+    from paper_2005_08674_amd import lbm
+    from paper_2005_08674_amd.ensemble import Ensemble
+    members, fields, far = _nsbc_members("f32")
+    a = Ensemble(members, fields)
+    b = Ensemble(members, fields)
+    for m, fa in enumerate(far):
+        a.set_farfield(m, *fa)
+        b.set_farfield(m, *fa)
+    best, times = a.autotune_two_step(reps=3)
+    assert 0 <= best < lbm.lbm_two_step_count() and min(times) > 0
+    assert a.t == 0
+    for rep in range(4):
+        if rep == 2:
+            a.set_farfield(1, 0.7, 1.0, 0.01, 0.0)
+            b.set_farfield(1, 0.7, 1.0, 0.01, 0.0)
+        a.step_graph(9)
+        b.step(9)
+        x = torch.randn(1000, device="cuda").sum().item()
+        assert np.isfinite(x)
+        for m in range(len(members)):
+            assert np.array_equal(a.populations(m), b.populations(m)), (rep, m)
+    a.close()
+    b.close()
+
+
+def test_two_step_refused_with_periodic_member_and_off_with_closure():
+    from paper_2005_08674_amd import lbm
+    from paper_2005_08674_amd.ensemble import Ensemble
+    members, fields, far = _mixed_members("f32")      # has periodic members
+    e = Ensemble(members, fields)
+    with pytest.raises(lbm.LbmError):
+        e.set_two_step(0)
+    with pytest.raises(lbm.LbmError):
+        e.autotune_two_step(reps=1)
+    e.set_two_step(-1)
+    e.close()
