@@ -26,6 +26,7 @@ LIBS = {"double": os.path.join(BUILD_DIR, "liblbm_oracle.so"),
 
 BC_PERIODIC = 0
 BC_NSBC = 1
+BC_VELOCITY = 2
 
 
 def build(verbose: bool = False) -> None:
@@ -52,7 +53,8 @@ class OrcParams(ctypes.Structure):
                 ("corr_mode", ctypes.c_int), ("grad_order", ctypes.c_int),
                 ("corner_mode", ctypes.c_int),
                 ("coll", ctypes.c_int),
-                ("omega_e", ctypes.c_double), ("omega_eps", ctypes.c_double), ("omega_q", ctypes.c_double)]
+                ("omega_e", ctypes.c_double), ("omega_eps", ctypes.c_double), ("omega_q", ctypes.c_double),
+                ("uw_x", ctypes.c_double), ("uw_y", ctypes.c_double)]
 
 
 _handles: dict = {}
@@ -144,7 +146,8 @@ def moments_node(rho0, g9, kind: str = "double") -> np.ndarray:
 class Lattice:
     """One D2Q9 lattice advanced by the oracle.
 
-    ``bc`` is (left, right, bottom, top), each BC_PERIODIC or BC_NSBC.
+    ``bc`` is (left, right, bottom, top), each BC_PERIODIC, BC_NSBC or (left/right, with periodic
+    bottom and top) BC_VELOCITY, a Dirichlet velocity edge at velocity ``uw``.
     Fields are [ny][nx] arrays; ``drho`` is rho - rho0.  ``mrt`` = (omega_e,
     omega_eps, omega_q) selects the MRT collision of Sec. 4 with omega_nu =
     1/tau; None keeps BGK.
@@ -152,7 +155,7 @@ class Lattice:
 
     def __init__(self, nx, ny, tau, drho, ux, uy, rho0=1.0, bc=(1, 1, 1, 1),
                  gamma=0.6, beta=0.0, m0=(1.0, 0.0, 0.0), corr_mode=0,
-                 grad_order=1, corner_mode=0, mrt=None, kind: str = "double"):
+                 grad_order=1, corner_mode=0, mrt=None, uw=(0.0, 0.0), kind: str = "double"):
         self.kind = kind
         self.lib = _lib(kind)
         p = OrcParams()
@@ -162,6 +165,7 @@ class Lattice:
         p.gamma, p.beta = float(gamma), float(beta)
         p.m0_rho, p.m0_ux, p.m0_uy = (float(v) for v in m0)
         p.corr_mode, p.grad_order, p.corner_mode = int(corr_mode), int(grad_order), int(corner_mode)
+        p.uw_x, p.uw_y = float(uw[0]), float(uw[1])
         if mrt is not None:
             p.coll = 1
             p.omega_e, p.omega_eps, p.omega_q = (float(r) for r in mrt)

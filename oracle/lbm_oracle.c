@@ -31,6 +31,12 @@
  *        correct all nine populations so that the node carries m_c (eq. nes_4)
  *   5. the corrected boundary node collides like any other node at the next
  *      step (the paragraph after eq. nes_4).
+ * A left or right edge may instead be a Dirichlet velocity edge (the inlet of
+ * the paper's test case 2, whose scheme the paper only cites): its node takes
+ * the prescribed velocity u_w and the density that the known populations fix,
+ * rho_w = (sum_{c.n = 0} f + 2 sum_{c.n > 0} f) / (1 + u_w.n) with n the
+ * outward normal (mass and normal momentum of the node), and then the same
+ * assignment and correction as NSBC at m = (rho_w, u_w).
  *
  * Readings taken where the paper is silent or ambiguous are listed in the
  * design notes; the flags below select the alternatives.
@@ -70,7 +76,8 @@ typedef struct {
     int nx, ny;
     double tau;           /* BGK relaxation time, dt = 1 (eq. lbe_1) */
     double rho0;          /* deviation base density */
-    int bc[4];            /* 0 = periodic, 1 = NSBC; [left x=0, right, bottom y=0, top] */
+    int bc[4];            /* 0 = periodic, 1 = NSBC, 2 = Dirichlet velocity (left/right only, with
+                             periodic bottom and top); [left x=0, right, bottom y=0, top] */
     double gamma;         /* eq. nes_2 */
     double beta;          /* eq. nes_3, far-field factor */
     double m0_rho, m0_ux, m0_uy;  /* eq. nes_3 reference fluid vector */
@@ -79,9 +86,10 @@ typedef struct {
     int corner_mode;      /* 0: diagonal normal, gamma/sqrt(2); 1: gamma/2 */
     int coll;             /* 0: BGK, eq. lbe_1; 1: MRT, eq. mrt_lbe (omega_nu = 1/tau) */
     double omega_e, omega_eps, omega_q;  /* MRT rates of e, epsilon and q (eq. mrt_rm) */
+    double uw_x, uw_y;    /* velocity of the Dirichlet velocity edges */
 } orc_params;
 
-enum { BC_PERIODIC = 0, BC_NSBC = 1 };
+enum { BC_PERIODIC = 0, BC_NSBC = 1, BC_VELOCITY = 2 };
 enum { E_LEFT = 0, E_RIGHT = 1, E_BOTTOM = 2, E_TOP = 3 };
 
 static const real CS2 = (real)1 / (real)3; /* c_s = 1/sqrt(3) */
@@ -249,7 +257,9 @@ static int check_params(const orc_params *p) {
             if (!(r[k] > 0 && r[k] <= 2)) return -1;
     }
     for (int e = 0; e < 4; ++e)
-        if (p->bc[e] != BC_PERIODIC && p->bc[e] != BC_NSBC) return -1;
+        if (p->bc[e] != BC_PERIODIC && p->bc[e] != BC_NSBC && p->bc[e] != BC_VELOCITY) return -1;
+    if (p->bc[E_BOTTOM] == BC_VELOCITY || p->bc[E_TOP] == BC_VELOCITY) return -1;
+    if ((p->bc[E_LEFT] == BC_VELOCITY || p->bc[E_RIGHT] == BC_VELOCITY) && p->bc[E_BOTTOM] != BC_PERIODIC) return -1;
     if ((p->bc[E_LEFT] == BC_PERIODIC) != (p->bc[E_RIGHT] == BC_PERIODIC)) return -1;
     if ((p->bc[E_BOTTOM] == BC_PERIODIC) != (p->bc[E_TOP] == BC_PERIODIC)) return -1;
     if (p->grad_order != 1 && p->grad_order != 2) return -1;
@@ -432,7 +442,8 @@ int orc_step(const orc_params *p, real *g, int nsteps) {
                 }
             }
         }
-        /* 4: NSBC on every node that lies on an NSBC edge. */
+        /* 4: NSBC on every node that lies on an NSBC edge; the Dirichlet
+         * velocity rule on every node of a velocity edge. */
 #pragma omp parallel for schedule(static)
         for (int y = 0; y < ny; ++y) {
             for (int x = 0; x < nx; ++x) {
@@ -441,8 +452,49 @@ int orc_step(const orc_params *p, real *g, int nsteps) {
                              y == 0 && p->bc[E_BOTTOM] == BC_NSBC,
                              y == ny - 1 && p->bc[E_TOP] == BC_NSBC};
                 int count = on[0] + on[1] + on[2] + on[3];
-                if (!count) continue;
+                int vel_nx = 0;   /* outward normal x of a velocity edge this node is on */
+                if (x == 0 && p->bc[E_LEFT] == BC_VELOCITY) vel_nx = -1;
+                if (x == nx - 1 && p->bc[E_RIGHT] == BC_VELOCITY) vel_nx = 1;
+                if (!count && !vel_nx) continue;
                 size_t k = (size_t)y * nx + x;
+                if (vel_nx) {
+                    /* rho_w from the known populations (mass and normal momentum), then
+                     * assignment and correction at m = (rho_w, u_w) */
+                    real f[Q], known = 0;
+                    for (int i = 0; i < Q; ++i) f[i] = g[(size_t)i * n + k] + weight(i) * rho0;
+                    for (int i = 0; i < Q; ++i) {
+                        int cn = CX[i] * vel_nx;
+                        if (cn == 0) known += f[i];
+                        else if (cn > 0) known += 2 * f[i];
+                    }
+                    const real uwx = (real)p->uw_x, uwy = (real)p->uw_y;
+                    const real rhow = known / (1 + uwx * (real)vel_nx);
+                    real mcv[3] = {rhow - rho0, uwx, uwy}, gn[Q], geq[Q];
+                    int unknown[Q];
+                    for (int i = 0; i < Q; ++i) {
+                        gn[i] = g[(size_t)i * n + k];
+                        unknown[i] = is_unknown(p, x, y, i);
+                    }
+                    equilibrium(rho0, mcv[0], mcv[1], mcv[2], geq);
+                    for (int i = 0; i < Q; ++i) {
+                        if (!unknown[i]) continue;
+                        int o = opp[i];
+                        gn[i] = unknown[o] ? geq[i] : geq[i] + (gn[o] - geq[o]);
+                    }
+                    real sm = 0, jx = 0, jy = 0;
+                    for (int i = 0; i < Q; ++i) {
+                        sm += gn[i];
+                        jx += (real)CX[i] * gn[i];
+                        jy += (real)CY[i] * gn[i];
+                    }
+                    const real rc = rho0 + mcv[0];
+                    const real ddr = sm - mcv[0], djx = jx - rc * mcv[1], djy = jy - rc * mcv[2];
+                    const real kf = p->corr_mode == 0 ? (real)1 / CS2 : (real)1;
+                    for (int i = 0; i < Q; ++i)
+                        gn[i] -= weight(i) * (ddr + kf * ((real)CX[i] * djx + (real)CY[i] * djy));
+                    for (int i = 0; i < Q; ++i) g[(size_t)i * n + k] = gn[i];
+                    continue;
+                }
                 /* inward unit steps of the (at most two) NSBC edges this node is on */
                 int inx[2], iny[2], ne = 0;
                 if (on[E_LEFT])   { inx[ne] = 1;  iny[ne] = 0;  ++ne; }

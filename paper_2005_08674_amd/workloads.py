@@ -18,7 +18,7 @@ from typing import List, Sequence, Tuple
 import numpy as np
 
 CS = 1.0 / math.sqrt(3.0)  # lattice speed of sound (Sec. 3)
-NSBC_ALL = (1, 1, 1, 1)    # (left, right, bottom, top), 1 = NSBC, 0 = periodic
+NSBC_ALL = (1, 1, 1, 1)    # (left, right, bottom, top), 1 = NSBC, 0 = periodic, 2 = Dirichlet velocity
 
 
 def _grid(nx: int, ny: int):
@@ -119,6 +119,7 @@ class Workload:
     u_ref: float = 0.0            # velocity scale for relative velocity errors
     extra: dict = field(default_factory=dict)
     mrt: Tuple[float, float, float] = None   # (omega_e, omega_eps, omega_q) for the MRT collision, else BGK
+    uw: Tuple[float, float] = (0.0, 0.0)     # velocity of Dirichlet velocity edges
 
 
 def pulse_128(nx: int = 128, ny: int = 128) -> Workload:
@@ -137,6 +138,21 @@ def plane_wave_tc1(n: int = 128, theta_deg: float = 60.0) -> Workload:
     f = plane_wave(n, n, th, zeta, lam, ((n - 1) / 2.0, (n - 1) / 2.0))
     return Workload(f"planewave{n}_tc1", n, n, 0.5, 400, f, u_ref=CS * zeta, mrt=(1.9, 1.9, 1.9),
                     extra={"theta": th, "zeta": zeta, "lam": lam})
+
+
+def convected_vortex_tc2(n: int = 128, nx: int = None) -> Workload:
+    """Test case 2 of Sec. 7: n x n (128^2), a Dirichlet velocity inlet u_w = (u0, 0) on the left, NSBC
+    (gamma 0.6, beta 0, m0 = (1, u0, 0)) on the right, periodic bottom and top; Lamb-Oseen vortex with
+    u0 = 0.1, U_v = beta u0 = 0.05, R_c = 20 centred in the n x n window; Re = u0 n / nu = 1000, so
+    tau = 1/2 + 3 u0 n / 1000; MRT rates omega_e = omega_eps = 1.4, omega_q = 1.2.  `nx` widens the lattice
+    to the right (a reference for the window [0, n) x [0, n))."""
+    u0, uv, rc = 0.1, 0.05, 20.0
+    nx = nx or n
+    c = (n - 1) / 2.0
+    f = lamb_oseen(nx, n, c, c, rc, uv, (u0, 0.0))
+    return Workload(f"convectedvortex{n}_tc2", nx, n, 0.5 + 3.0 * u0 * n / 1000.0, 2000, f, bc=(2, 1, 0, 0),
+                    m0=(1.0, u0, 0.0), u_ref=u0, mrt=(1.4, 1.4, 1.2), uw=(u0, 0.0),
+                    extra={"x0": c, "y0": c, "rc": rc, "uv": uv})
 
 
 def vortex_512x256(seed: int = 2, nx: int = 512, ny: int = 256) -> Workload:

@@ -152,8 +152,9 @@ def _rat_mom(fs):
     return rho, sum(c[0] * f for c, f in zip(CXY, fs)) / rho, sum(c[1] * f for c, f in zip(CXY, fs)) / rho
 
 
-def _rat_run(nx, ny, f, steps, tau, gamma, beta, m0, bc, corr_literal, order, corner_half):
-    """f: dict (x, y) -> list of 9 Fractions (absolute populations, pre-collision)."""
+def _rat_run(nx, ny, f, steps, tau, gamma, beta, m0, bc, corr_literal, order, corner_half, uw=None):
+    """f: dict (x, y) -> list of 9 Fractions (absolute populations, pre-collision).  bc entries: 0
+    periodic, 1 NSBC, 2 Dirichlet velocity at `uw` (left/right only)."""
     opp = [CXY.index((-a, -b)) for a, b in CXY]
     for _ in range(steps):
         mom = {k: _rat_mom(v) for k, v in f.items()}
@@ -176,14 +177,15 @@ def _rat_run(nx, ny, f, steps, tau, gamma, beta, m0, bc, corr_literal, order, co
         for (x, y), cur in new.items():
             if None not in cur:
                 continue
+            vel_n = -1 if (x == 0 and bc[0] == 2) else (1 if (x == nx - 1 and bc[1] == 2) else 0)
             inward = []
-            if x == 0 and bc[0]:
+            if x == 0 and bc[0] == 1:
                 inward.append((1, 0))
-            if x == nx - 1 and bc[1]:
+            if x == nx - 1 and bc[1] == 1:
                 inward.append((-1, 0))
-            if y == 0 and bc[2]:
+            if y == 0 and bc[2] == 1:
                 inward.append((0, 1))
-            if y == ny - 1 and bc[3]:
+            if y == ny - 1 and bc[3] == 1:
                 inward.append((0, -1))
             mb = mom[(x, y)]
 
@@ -194,14 +196,20 @@ def _rat_run(nx, ny, f, steps, tau, gamma, beta, m0, bc, corr_literal, order, co
                 m2 = mom[(x + 2 * dx, y + 2 * dy)]
                 return [(3 * a - 4 * b + c) / 2 for a, b, c in zip(mb, m1, m2)]
 
-            if len(inward) == 1:
+            if vel_n:
+                # velocity edge: the density the known populations fix (mass and normal momentum)
+                known = sum(v if c[0] * vel_n == 0 else 2 * v for c, v in zip(CXY, cur)
+                            if v is not None and c[0] * vel_n >= 0)
+                mc = [known / (1 + uw[0] * vel_n), uw[0], uw[1]]
+            elif len(inward) == 1:
                 d = dn(*inward[0])
                 mp = [a - gamma * b for a, b in zip(mb, d)]
             else:
                 assert corner_half
                 d1, d2 = dn(*inward[0]), dn(*inward[1])
                 mp = [a - gamma * F(1, 2) * (b + c) for a, b, c in zip(mb, d1, d2)]
-            mc = [(1 - beta) * a + beta * b for a, b in zip(mp, m0)]
+            if not vel_n:
+                mc = [(1 - beta) * a + beta * b for a, b in zip(mp, m0)]
             eq = _rat_feq(*mc)
             fill = list(cur)
             for i in range(9):
@@ -224,6 +232,10 @@ def _rat_run(nx, ny, f, steps, tau, gamma, beta, m0, bc, corr_literal, order, co
          corr=1, order=2, corner=1),
     dict(nx=4, ny=5, bc=(0, 0, 1, 1), tau=F(9, 10), gamma=F(1, 2), beta=F(0), m0=(F(1), F(0), F(0)),
          corr=0, order=1, corner=0),
+    dict(nx=6, ny=4, bc=(2, 1, 0, 0), tau=F(3, 5), gamma=F(3, 5), beta=F(1, 10), m0=(F(1), F(1, 20), F(0)),
+         corr=0, order=1, corner=0, uw=(F(1, 20), F(1, 100))),
+    dict(nx=5, ny=3, bc=(1, 2, 0, 0), tau=F(4, 5), gamma=F(1, 2), beta=F(0), m0=(F(1), F(0), F(0)),
+         corr=1, order=2, corner=0, uw=(F(-1, 25), F(0))),
 ])
 def test_exact_rational_bruteforce(case):
     nx, ny = case["nx"], case["ny"]
@@ -234,14 +246,16 @@ def test_exact_rational_bruteforce(case):
     uy = {(x, y): F(int(rng.integers(-50, 50)), 2 ** 10) for x in range(nx) for y in range(ny)}
     f0 = {k: _rat_feq(1 + drho[k], ux[k], uy[k]) for k in drho}
     steps = 3
+    uw = case.get("uw", (F(0), F(0)))
     fr = _rat_run(nx, ny, f0, steps, case["tau"], case["gamma"], case["beta"], case["m0"], case["bc"],
-                  case["corr"] == 1, case["order"], case["corner"] == 1)
+                  case["corr"] == 1, case["order"], case["corner"] == 1, uw=uw)
 
     arr = lambda d: np.array([[float(d[(x, y)]) for x in range(nx)] for y in range(ny)])
     L = oracle.Lattice(nx, ny, float(case["tau"]), arr(drho), arr(ux), arr(uy), bc=case["bc"],
                        gamma=float(case["gamma"]), beta=float(case["beta"]),
                        m0=tuple(float(v) for v in case["m0"]), corr_mode=case["corr"],
-                       grad_order=case["order"], corner_mode=case["corner"], kind="longdouble")
+                       grad_order=case["order"], corner_mode=case["corner"], uw=tuple(float(v) for v in uw),
+                       kind="longdouble")
     L.step(steps)
     for (x, y), pops in fr.items():
         exact = np.array([float(p - w) for p, w in zip(pops, WQ)])
@@ -311,3 +325,63 @@ def test_vortex_is_absorbed():
     assert np.abs(v).max() < 1e-2 * peak
     assert abs(u.mean() - 0.1) < 1e-3
     assert np.abs(d).max() < 1e-3
+
+
+# --------------------------------------------------------------------------
+# Dirichlet velocity edge (the inlet of test case 2) and test case 2 itself
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("bc,uw", [((2, 1, 0, 0), (0.08, 0.01)), ((1, 2, 0, 0), (-0.05, 0.0)),
+                                   ((2, 2, 0, 0), (0.03, -0.02))])
+def test_uniform_flow_at_the_inlet_velocity_is_a_fixed_point(bc, uw):
+    f = W.uniform(24, 16, 0.0, uw)
+    L = oracle.Lattice(24, 16, 0.6, *f, bc=bc, m0=(1.0, uw[0], uw[1]), uw=uw)
+    g0 = L.g.copy()
+    L.step(50)
+    assert np.abs(L.g - g0).max() < 1e-15
+
+
+def test_inlet_nodes_carry_the_prescribed_velocity():
+    """After every step the inlet nodes hold u = u_w exactly (up to rounding), whatever arrives."""
+    w = W.pulse_128(40, 24)
+    L = oracle.Lattice(40, 24, 0.6, *w.fields, bc=(2, 1, 0, 0), uw=(0.05, 0.0))
+    for _ in range(3):
+        L.step(7)
+        d, u, v = L.moments()
+        assert np.abs(u[:, 0] - 0.05).max() < 1e-15 and np.abs(v[:, 0]).max() < 1e-15
+
+
+def test_velocity_edges_need_periodic_neighbours():
+    f = W.uniform(8, 8)
+    with pytest.raises(ValueError):
+        oracle.Lattice(8, 8, 0.6, *f, bc=(2, 1, 1, 1))
+    with pytest.raises(ValueError):
+        oracle.Lattice(8, 8, 0.6, *f, bc=(0, 0, 2, 1))
+
+
+def test_paper_test_case_2_vortex_is_absorbed():
+    """Sec. 7, test case 2 (128^2, inlet left, NSBC right, periodic bottom/top, MRT 1.4/1.2, Re 1000):
+    the vortex leaves through the NSBC edge.  Against a lattice 4x wider to the right (the window's
+    exact continuation), the worst error energy is well below that of gamma = 0, and once the vortex
+    has left the transverse velocity is 1000x below its initial peak, 10x below gamma = 0's."""
+    w = W.convected_vortex_tc2()
+    wr = W.convected_vortex_tc2(nx=4 * w.nx)
+
+    def lat(wk, gamma):
+        return oracle.Lattice(wk.nx, wk.ny, wk.tau, *wk.fields, bc=wk.bc, gamma=gamma, m0=wk.m0, mrt=wk.mrt,
+                              uw=wk.uw)
+
+    ref, a, b = lat(wr, 0.6), lat(w, 0.6), lat(w, 0.0)
+    e0 = R.energy(w.fields[0], w.fields[1] - w.uw[0], w.fields[2])
+    worst = {0.6: 0.0, 0.0: 0.0}
+    for _ in range(0, w.steps, 50):
+        rw = tuple(m[:, :w.nx] for m in ref.moments())
+        for g, L in ((0.6, a), (0.0, b)):
+            worst[g] = max(worst[g], R.energy_diff(L.moments(), rw) / e0)
+        for L in (ref, a, b):
+            L.step(50)
+    v0 = np.abs(w.fields[2]).max()
+    va, vb = np.abs(a.moments()[2]).max(), np.abs(b.moments()[2]).max()
+    assert np.isfinite(a.g).all()
+    assert worst[0.6] < 0.5 * worst[0.0]
+    assert va < 2e-3 * v0 and vb > 10 * va
