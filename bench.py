@@ -214,6 +214,46 @@ def run_tc1(torch, W):
     return out
 
 
+def run_tc2(torch, W, every=50):
+    """Test case 2 of Sec. 7 (128^2 convected vortex: velocity inlet left, NSBC right, periodic bottom and
+    top, MRT 1.4/1.2, Re 1000): R_E against a lattice 4x wider to the right (the window's continuation,
+    the library's fp64 energy reduction every `every` steps) and the transverse velocity left after the
+    vortex has gone, for NSBC (gamma 0.6) and, for comparison, gamma 0."""
+    from paper_2005_08674_amd.lattice import Lattice
+
+    w = W.convected_vortex_tc2()
+    wr = W.convected_vortex_tc2(nx=4 * w.nx)
+    out = {"workload": f"{w.name}: {w.nx}x{w.ny}, Lamb-Oseen u0 0.1, U_v 0.05, R_c 20, tau {w.tau:.4f}, MRT rates "
+                       f"{w.mrt}, inlet u_w {w.uw}, NSBC right (beta 0), periodic bottom/top; reference "
+                       f"{wr.nx}x{wr.ny}", "steps": w.steps, "energy_every": every}
+
+    def lat(wk, gamma, store):
+        return Lattice(wk.nx, wk.ny, wk.tau, wk.fields, store=store, bc=wk.bc, gamma=gamma, m0=wk.m0, mrt=wk.mrt,
+                       uw=wk.uw, ubase=wk.uw)
+
+    v0 = float(np.abs(w.fields[2]).max())
+    for store in ("f32", "f64"):
+        ref = lat(wr, 0.6, store)
+        for gamma in (0.6, 0.0):
+            test = lat(w, gamma, store)
+            e0 = float(test.energy(ux_ref=w.uw[0], uy_ref=w.uw[1]).item())
+            series = torch.zeros(w.steps // every + 1, dtype=torch.float64, device=test.device)
+            r = lat(wr, 0.6, store) if gamma != 0.6 else ref
+            for k in range(series.numel()):
+                test.energy(ref=r, out=series[k:k + 1])
+                if k + 1 < series.numel():
+                    test.step(every)
+                    r.step(every)
+            v = float(np.abs(test.moments_np()[2]).max())
+            out[f"{store}_gamma{gamma}"] = {"R_E": float(series.max().item()) / e0, "vmax_final_rel": v / v0,
+                                            "finite": bool(test.check_finite())}
+            test.close()
+            if r is not ref:
+                r.close()
+        ref.close()
+    return out
+
+
 def run_ensemble(torch, W, steps, count=256, seed=4):
     """The batched-ensemble workload: `count` lattices with sides U{64..512}, tau U[0.52, 0.8], pulse or
     vortex, FP32 storage; `steps` steps in ONE graph launch (captured beforehand)."""
@@ -392,7 +432,7 @@ def main():
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--variants", default="f16,bf16,f64,mrt_f32,mrt_f16",
                     help="extra variants: storage formats, mrt_<store> for the MRT collision ('' for none)")
-    ap.add_argument("--tc1", type=int, default=1, help="0 skips the test-case-1 plane-wave run")
+    ap.add_argument("--tc1", type=int, default=1, help="0 skips the paper's test cases 1 and 2")
     ap.add_argument("--variant-steps", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune-reps", type=int, default=5)
@@ -431,6 +471,7 @@ def main():
                         "steps": args.variant_steps, "finite": r["finite"]}
     if args.tc1:
         variants["planewave128_tc1"] = run_tc1(torch, W)
+        variants["convectedvortex128_tc2"] = run_tc2(torch, W)
     if args.ensemble_steps > 0:
         variants["ensemble256_f32"] = run_ensemble(torch, W, args.ensemble_steps)
     if args.c5_steps > 0:

@@ -51,8 +51,17 @@ enum {
 };
 
 /* Edge index in lbm_params.bc: 0 = left (x = 0), 1 = right (x = nx-1),
- * 2 = bottom (y = 0), 3 = top (y = ny-1). */
-enum { LBM_BC_PERIODIC = 0, LBM_BC_NSBC = 1 };
+ * 2 = bottom (y = 0), 3 = top (y = ny-1).
+ * LBM_BC_PERIODIC: wrap-around (edges come in pairs).
+ * LBM_BC_NSBC: the non-reflective boundary of Sec. 5 (eqs. nes_0..nes_4).
+ * LBM_BC_VELOCITY: a Dirichlet velocity edge, the inlet of the paper's test
+ *   case 2 (Sec. 7, which only cites the scheme): the node takes the velocity
+ *   set by lbm_set_velocity_edge and the density its known populations fix,
+ *   rho_w = (sum_{c.n = 0} f + 2 sum_{c.n > 0} f) / (1 + u_w.n) with n the
+ *   outward normal, then the incoming populations and the correction of eqs.
+ *   nes_1 and nes_4 at (rho_w, u_w).  Left and right edges only, with
+ *   periodic bottom and top (no corners). */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_NSBC = 1, LBM_BC_VELOCITY = 2 };
 
 /* Storage of the populations.  Arithmetic is fp64 for LBM_STORE_F64 and fp32
  * for the three others.  The 16-bit codecs store s_i = g_i / w_i * 2^k with
@@ -123,6 +132,11 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* workspace, size_t bytes,
  * m0 = (rho_ref, ux_ref, uy_ref) (absolute density).  beta in [0, 1].
  * Takes effect from the next step. */
 int lbm_set_farfield(lbm_ctx* ctx, double beta, double rho_ref, double ux_ref, double uy_ref);
+
+/* Velocity u_w = (ux, uy) of the lattice's LBM_BC_VELOCITY edges (both take
+ * the same one), |u_w| <= 0.5; (0, 0) after lbm_init.  Takes effect from the
+ * next step. */
+int lbm_set_velocity_edge(lbm_ctx* ctx, double ux, double uy);
 
 /* Advance n >= 0 time steps (stream, NSBC, collide; eqs. lbe_0, nes_0..nes_4,
  * lbe_1).  Asynchronous; the context's time advances by n. */

@@ -49,6 +49,10 @@ int lbm_ens_init(lbm_ens** out, const lbm_params* members, int32_t count, void* 
  * effect from the next step, including steps of already captured graphs. */
 int lbm_ens_set_farfield(lbm_ens* e, int32_t member, double beta, double rho_ref, double ux_ref, double uy_ref);
 
+/* Velocity of one member's LBM_BC_VELOCITY edges, as lbm_set_velocity_edge.
+ * Takes effect from the next step, including steps of captured graphs. */
+int lbm_ens_set_velocity_edge(lbm_ens* e, int32_t member, double ux, double uy);
+
 /* Advance every member n >= 0 steps: one launch per step (fused edge and
  * bulk work), two per step when fusion is off or a member runs the closure,
  * or one launch per two steps when the two-step sweep is on (an odd last

@@ -77,8 +77,12 @@ int check_params(const lbm_params* p) {
   }
   if (!(p->rho0 > 0) || !std::isfinite(p->rho0)) return fail(LBM_ERR_ARG, "rho0 = %g must be > 0", p->rho0);
   for (int e = 0; e < 4; ++e)
-    if (p->bc[e] != LBM_BC_PERIODIC && p->bc[e] != LBM_BC_NSBC)
-      return fail(LBM_ERR_ARG, "bc[%d] = %d is not LBM_BC_PERIODIC or LBM_BC_NSBC", e, p->bc[e]);
+    if (p->bc[e] != LBM_BC_PERIODIC && p->bc[e] != LBM_BC_NSBC && p->bc[e] != LBM_BC_VELOCITY)
+      return fail(LBM_ERR_ARG, "bc[%d] = %d is not LBM_BC_PERIODIC, LBM_BC_NSBC or LBM_BC_VELOCITY", e, p->bc[e]);
+  if (p->bc[2] == LBM_BC_VELOCITY || p->bc[3] == LBM_BC_VELOCITY)
+    return fail(LBM_ERR_ARG, "velocity edges are supported on the left and right edges only");
+  if ((p->bc[0] == LBM_BC_VELOCITY || p->bc[1] == LBM_BC_VELOCITY) && p->bc[2] != LBM_BC_PERIODIC)
+    return fail(LBM_ERR_ARG, "a velocity edge needs periodic bottom and top edges");
   if ((p->bc[0] == LBM_BC_PERIODIC) != (p->bc[1] == LBM_BC_PERIODIC) ||
       (p->bc[2] == LBM_BC_PERIODIC) != (p->bc[3] == LBM_BC_PERIODIC))
     return fail(LBM_ERR_ARG, "periodic edges must come in pairs (left+right, bottom+top)");
@@ -149,6 +153,21 @@ void fill_desc(LatDesc& L, const lbm_params* p, const Layout& lay, void* buf0, v
   L.m0[1] = -p->ubase[0];
   L.m0[2] = -p->ubase[1];
   set_scales(L, p->store, 0);
+  set_velocity_edge(L, 0.0, 0.0);
+}
+
+int set_velocity_edge(LatDesc& L, double ux, double uy) {
+  if (!std::isfinite(ux) || !std::isfinite(uy) || ux * ux + uy * uy > 0.25)
+    return fail(LBM_ERR_ARG, "velocity (%g, %g) must be finite with |u| <= 0.5", ux, uy);
+  L.uw[0] = ux;
+  L.uw[1] = uy;
+  L.duw[0] = ux - L.ub[0];
+  L.duw[1] = uy - L.ub[1];
+  for (int k = 0; k < 2; ++k) {
+    L.uwf[k] = static_cast<float>(L.uw[k]);
+    L.duwf[k] = static_cast<float>(L.duw[k]);
+  }
+  return LBM_OK;
 }
 
 int set_farfield(LatDesc& L, double beta, double rho_ref, double ux_ref, double uy_ref) {
@@ -449,6 +468,11 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* workspace, size_t bytes, 
 int lbm_set_farfield(lbm_ctx* c, double beta, double rho_ref, double ux_ref, double uy_ref) {
   if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
   return lbm::host::set_farfield(c->L, beta, rho_ref, ux_ref, uy_ref);
+}
+
+int lbm_set_velocity_edge(lbm_ctx* c, double ux, double uy) {
+  if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
+  return lbm::host::set_velocity_edge(c->L, ux, uy);
 }
 
 int lbm_step(lbm_ctx* c, int32_t n) {

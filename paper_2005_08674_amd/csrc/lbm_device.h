@@ -38,7 +38,7 @@ __host__ __device__ constexpr R wgt(int i) {
 
 enum Store : int { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3 };
 enum Edge : int { E_LEFT = 0, E_RIGHT = 1, E_BOTTOM = 2, E_TOP = 3 };
-enum Bc : int { BC_PERIODIC = 0, BC_NSBC = 1 };
+enum Bc : int { BC_PERIODIC = 0, BC_NSBC = 1, BC_VELOCITY = 2 };
 enum Coll : int { COLL_BGK = 0, COLL_MRT = 1 };
 
 // ------------------------------------------------------------------ codecs
@@ -110,6 +110,10 @@ struct LatDesc {
   int32_t coll;     // COLL_BGK or COLL_MRT
   double mk[4];     // MRT: omega_e/36, omega_eps/36, omega_q/12, omega_nu/4 (see mrt())
   float mkf[4];     // the same rounded to fp32
+  double uw[2];     // velocity of Dirichlet velocity edges
+  double duw[2];    // uw - u_b
+  float uwf[2];     // the same two rounded to fp32
+  float duwf[2];
 };
 
 // Buffer `parity` (0 or 1) of a lattice.  A select rather than an indexed
@@ -247,6 +251,11 @@ __device__ inline void mrt(R g[9], R rho0, const Base<R>& b, const R k[4]) {
   g[8] -= diag + (QX - QY) - XY;
 }
 
+// A descriptor value in the arithmetic type: the fp64 field, or its fp32 copy.
+template <class R> __device__ inline R in_type(double d, float f);
+template <> __device__ inline double in_type<double>(double d, float) { return d; }
+template <> __device__ inline float in_type<float>(double, float f) { return f; }
+
 template <class R> __device__ inline const R* mrt_k(const LatDesc& L);
 template <> __device__ inline const double* mrt_k<double>(const LatDesc& L) { return L.mk; }
 template <> __device__ inline const float* mrt_k<float>(const LatDesc& L) { return L.mkf; }
@@ -276,6 +285,32 @@ __device__ inline typename Codec<S>::R load_pop(const LatDesc& L, const typename
 template <class R> struct M3 {
   R v[3];
 };
+
+// Dirichlet velocity edge (left or right, with periodic bottom and top): the
+// node takes the prescribed velocity u_w and the density its known
+// populations fix -- mass and normal momentum give
+//   rho_w (1 + u_w.n) = sum_{c.n = 0} f + 2 sum_{c.n > 0} f,
+// n the outward normal; with f = g + f^eq(rho0, u_b), whose own sums give
+// rho0 (1 + u_b.n), that is
+//   rho_w - rho0 = (sum_{c.n = 0} g + 2 sum_{c.n > 0} g - rho0 (u_w - u_b).n) / (1 + u_w.n).
+// The caller then applies NSBC's assignment and correction at that vector.
+template <class R>
+__device__ inline M3<R> velocity_edge_moments(const R g[9], int nout_x, R rho0, R uwx, R duwx, R duwy) {
+  R s = R(0);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int cn = kCx[i] * nout_x;
+    if (cn == 0) s += g[i];
+    else if (cn > 0) s += R(2) * g[i];
+  }
+  const R un = R(nout_x) * uwx, dn = R(nout_x) * duwx;
+  M3<R> m;
+  m.v[0] = (s - rho0 * dn) * recip(R(1) + un);
+  m.v[1] = duwx;
+  m.v[2] = duwy;
+  return m;
+}
+
 
 // Rebuild the unknown populations of one boundary node and correct it
 // (eqs. nes_0..nes_4).  `unknown` has bit i set for every population whose

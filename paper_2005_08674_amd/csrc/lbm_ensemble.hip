@@ -542,6 +542,16 @@ int lbm_ens_set_farfield(lbm_ens* e, int32_t member, double beta, double rho_ref
   return upload_descs(e);
 }
 
+int lbm_ens_set_velocity_edge(lbm_ens* e, int32_t member, double ux, double uy) {
+  int rc = check_member(e, member);
+  if (rc) return rc;
+  lbm::LatDesc L = e->descs[member];
+  rc = lbm::host::set_velocity_edge(L, ux, uy);
+  if (rc) return rc;
+  e->descs[member] = L;
+  return upload_descs(e);
+}
+
 int lbm_ens_step(lbm_ens* e, int32_t n) {
   if (!e) return fail(LBM_ERR_ARG, "ensemble is NULL");
   if (n < 0) return fail(LBM_ERR_ARG, "n = %d < 0", n);

@@ -38,6 +38,7 @@ int check_params(const lbm_params* p);
 void set_scales(LatDesc& L, int store, int k);
 void fill_desc(LatDesc& L, const lbm_params* p, const Layout& lay, void* buf0, void* buf1);
 int set_farfield(LatDesc& L, double beta, double rho_ref, double ux_ref, double uy_ref);
+int set_velocity_edge(LatDesc& L, double ux, double uy);
 int f16_exp_from_max(float mx);
 
 // Closure sampling launchers (lbm_closure.hip).  Exactly one of `single`

@@ -315,7 +315,15 @@ __device__ inline void edge_segment_body(const LatDesc& L, int parity, int edge,
     }
   }
   if (!owner) return;
-  if (nsbc_node) nsbc_assign_correct<R>(g, unknown, mc, rho0, base, L.corr_mode);
+  // Dirichlet velocity edge (left or right, bottom and top periodic): the
+  // prescribed velocity and the density the known populations fix, then the
+  // same assignment and correction as NSBC
+  const int vel_nx = (x == 0 && L.bc[E_LEFT] == BC_VELOCITY) ? -1 : ((x == nx - 1 && L.bc[E_RIGHT] == BC_VELOCITY) ? 1 : 0);
+  if (vel_nx) {
+    mc = velocity_edge_moments<R>(g, vel_nx, rho0, in_type<R>(L.uw[0], L.uwf[0]), in_type<R>(L.duw[0], L.duwf[0]),
+                                  in_type<R>(L.duw[1], L.duwf[1]));
+  }
+  if (nsbc_node || vel_nx) nsbc_assign_correct<R>(g, unknown, mc, rho0, base, L.corr_mode);
   collide<R>(L, g, rho0, base, R(L.omega));
   const int idx = y * pitch + x;
 #pragma unroll

@@ -44,6 +44,9 @@ class Ensemble:
     def set_farfield(self, member, beta, rho_ref, ux_ref, uy_ref):
         L.lbm_ens_set_farfield(self.ens, member, beta, rho_ref, ux_ref, uy_ref)
 
+    def set_velocity_edge(self, member, ux, uy):
+        L.lbm_ens_set_velocity_edge(self.ens, member, ux, uy)
+
     def step(self, n=1):
         L.lbm_ens_step(self.ens, n)
 

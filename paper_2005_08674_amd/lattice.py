@@ -11,7 +11,8 @@ from . import lbm as L
 
 class Lattice:
     """D2Q9 lattice (BGK, or MRT with ``mrt`` = (omega_e, omega_eps, omega_q)) with NSBC/periodic
-    edges on one GPU.
+    edges on one GPU.  Edges: 1 = NSBC, 0 = periodic, 2 = Dirichlet velocity at ``uw`` (left/right
+    with periodic bottom/top).
 
     ``fields`` = (drho, ux, uy), [ny][nx] arrays (numpy or torch) with
     drho = rho - rho0.  ``bc`` = (left, right, bottom, top), 1 = NSBC,
@@ -21,7 +22,7 @@ class Lattice:
 
     def __init__(self, nx, ny, tau, fields, rho0=1.0, bc=(1, 1, 1, 1), gamma=0.6, store="f32",
                  beta=0.0, m0=None, corr_mode=0, grad_order=1, corner_mode=0, f16_exp=None,
-                 ubase=(0.0, 0.0), mrt=None, device="cuda", stream=None):
+                 ubase=(0.0, 0.0), mrt=None, uw=None, device="cuda", stream=None):
         p = L.lbm_params_default()
         p.nx, p.ny, p.tau, p.rho0, p.gamma = int(nx), int(ny), float(tau), float(rho0), float(gamma)
         for e in range(4):
@@ -48,6 +49,8 @@ class Lattice:
             self.set_farfield(beta, *m0)
         elif beta:
             self.set_farfield(beta, rho0, 0.0, 0.0)
+        if uw is not None:
+            L.lbm_set_velocity_edge(self.ctx, *uw)
 
     # --------------------------------------------------------------- calls
     def set_farfield(self, beta, rho_ref, ux_ref, uy_ref):

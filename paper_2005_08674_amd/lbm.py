@@ -23,6 +23,7 @@ LBM_ERR_UNSUPPORTED = -5
 
 LBM_BC_PERIODIC = 0
 LBM_BC_NSBC = 1
+LBM_BC_VELOCITY = 2
 
 LBM_STORE_F64 = 0
 LBM_STORE_F32 = 1
@@ -61,6 +62,7 @@ _SIGS = {
     "lbm_workspace_bytes": [_P, _P],
     "lbm_init": [_P, _P, _P, ctypes.c_size_t, _P, _P, _P, _P],
     "lbm_set_farfield": [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double],
+    "lbm_set_velocity_edge": [_P, ctypes.c_double, ctypes.c_double],
     "lbm_step": [_P, ctypes.c_int32],
     "lbm_moments": [_P, _P, _P, _P, ctypes.c_int, ctypes.c_int],
     "lbm_time": [_P, _P],
@@ -91,6 +93,7 @@ _SIGS = {
     "lbm_ens_init": [_P, _P, ctypes.c_int32, _P, ctypes.c_size_t, _P, _P, _P, _P],
     "lbm_ens_set_farfield": [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                              ctypes.c_double],
+    "lbm_ens_set_velocity_edge": [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_double],
     "lbm_ens_step": [_P, ctypes.c_int32],
     "lbm_ens_step_graph": [_P, ctypes.c_int32],
     "lbm_ens_set_fused": [_P, ctypes.c_int],
@@ -188,6 +191,10 @@ def lbm_init(p: lbm_params, workspace_ptr: int, nbytes: int, drho_ptr: int, ux_p
 
 def lbm_set_farfield(ctx, beta, rho_ref, ux_ref, uy_ref):
     _check(load().lbm_set_farfield(ctx, beta, rho_ref, ux_ref, uy_ref), "lbm_set_farfield")
+
+
+def lbm_set_velocity_edge(ctx, ux, uy):
+    _check(load().lbm_set_velocity_edge(ctx, float(ux), float(uy)), "lbm_set_velocity_edge")
 
 
 def lbm_step(ctx, n: int):
@@ -346,6 +353,10 @@ def lbm_ens_init(members, workspace_ptr, nbytes, drho_ptr, ux_ptr, uy_ptr, strea
 
 def lbm_ens_set_farfield(ens, member, beta, rho_ref, ux_ref, uy_ref):
     _check(load().lbm_ens_set_farfield(ens, int(member), beta, rho_ref, ux_ref, uy_ref), "lbm_ens_set_farfield")
+
+
+def lbm_ens_set_velocity_edge(ens, member, ux, uy):
+    _check(load().lbm_ens_set_velocity_edge(ens, int(member), float(ux), float(uy)), "lbm_ens_set_velocity_edge")
 
 
 def lbm_ens_step(ens, n: int):

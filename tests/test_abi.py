@@ -96,6 +96,20 @@ def test_collision_model_parameters(lib):
     assert L.lbm_workspace_bytes(p) > 0
 
 
+@pytest.mark.parametrize("bc,ok", [((2, 1, 0, 0), True), ((1, 2, 0, 0), True), ((2, 2, 0, 0), True),
+                                   ((2, 1, 1, 1), False), ((1, 1, 2, 0), False), ((0, 0, 2, 2), False)])
+def test_velocity_edges_left_right_with_periodic_bottom_top(lib, bc, ok):
+    p = L.lbm_params_default()
+    p.nx = p.ny = 16
+    for e in range(4):
+        p.bc[e] = bc[e]
+    if ok:
+        assert L.lbm_workspace_bytes(p) > 0
+    else:
+        with pytest.raises(L.LbmError, match="velocity edge"):
+            L.lbm_workspace_bytes(p)
+
+
 def test_unpaired_periodic_edges_rejected(lib):
     p = L.lbm_params_default()
     p.nx = p.ny = 16
