@@ -198,10 +198,36 @@ __device__ inline void equilibrium(R rho0, const Base<R>& b, R drho, R dux, R du
 }
 
 // BGK collision in place (eq. lbe_1, dt = 1): g <- g + omega (g^eq - g).
+// For u_b = 0 the update is written per pair of opposite directions (i, i'),
+// whose a = c_i.du differ in sign only:
+//   g^eq_i = w_i (E + rho (9/2 a^2 +- 3 a)),  E = drho - 3/2 rho |du|^2,
+//   g_i <- (1 - omega) g_i + (omega w_i) (E + 9/2 rho a^2 +- 3 rho a),
+// which shares the even part between the two directions and folds w_i into
+// omega (about a fifth fewer operations than the per-direction form below).
 template <class R>
 __device__ inline void bgk(R g[9], R rho0, const Base<R>& b, R omega) {
-  R drho, dux, duy, geq[9];
+  R drho, dux, duy;
   moments(g, rho0, b, drho, dux, duy);
+  if (b.zero) {
+    const R rho = rho0 + drho;
+    const R e = fma(-rho, R(1.5) * fma(dux, dux, duy * duy), drho);
+    const R r45 = R(4.5) * rho, r3 = R(3) * rho;
+    const R om1 = R(1) - omega;
+    const R ow0 = omega * wgt<R>(0), ow1 = omega * wgt<R>(1), ow5 = omega * wgt<R>(5);
+    g[0] = fma(ow0, e, om1 * g[0]);
+    // one pair: directions i (a) and j (-a)
+    auto pair = [&](int i, int j, R a, R ow) {
+      const R even = fma(r45 * a, a, e), odd = r3 * a;
+      g[i] = fma(ow, even + odd, om1 * g[i]);
+      g[j] = fma(ow, even - odd, om1 * g[j]);
+    };
+    pair(1, 2, dux, ow1);
+    pair(3, 4, duy, ow1);
+    pair(5, 6, dux + duy, ow5);
+    pair(7, 8, duy - dux, ow5);
+    return;
+  }
+  R geq[9];
   equilibrium(rho0, b, drho, dux, duy, geq);
 #pragma unroll
   for (int i = 0; i < 9; ++i) g[i] = fma(omega, geq[i] - g[i], g[i]);

@@ -43,15 +43,23 @@ __device__ inline void bulk_tile_body(const LatDesc& L, int parity, int txi, int
   const R rho0 = R(L.rho0), omega = R(L.omega);
   const Base<R> base(L);
 
+  // Interior nodes pull from inside the lattice: every access is a per-plane
+  // (uniform) base pointer plus a 32-bit unsigned byte offset (a plane is
+  // below 4 GiB), one per source row, with the x shift as a constant.
   R g[NYT][9];
 #pragma unroll
   for (int j = 0; j < NYT; ++j) {
     const int y = y0 + j * BY;
     if (y <= L.ny - 2) {
+      const uint32_t idx = (uint32_t)(y * pitch + x);
+      const uint32_t ro[3] = {(idx + (uint32_t)pitch) * (uint32_t)sizeof(T), idx * (uint32_t)sizeof(T),
+                              (idx - (uint32_t)pitch) * (uint32_t)sizeof(T)};
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        const int idx = (y - kCy[i]) * pitch + (x - kCx[i]);
-        g[j][i] = C::dec(get(A + i * plane + idx, NTL && kCx[i] == 0), L.ds[i]);
+        const char* Ai = reinterpret_cast<const char*>(A + i * plane);
+        g[j][i] = C::dec(get(reinterpret_cast<const T*>(Ai + ro[1 + kCy[i]] - kCx[i] * (int)sizeof(T)),
+                             NTL && kCx[i] == 0),
+                         L.ds[i]);
       }
     }
   }
@@ -60,9 +68,10 @@ __device__ inline void bulk_tile_body(const LatDesc& L, int parity, int txi, int
     const int y = y0 + j * BY;
     if (y <= L.ny - 2) {
       collide<R>(L, g[j], rho0, base, omega);
-      const int idx = y * pitch + x;
+      const uint32_t off = (uint32_t)(y * pitch + x) * (uint32_t)sizeof(T);
 #pragma unroll
-      for (int i = 0; i < 9; ++i) put<NTS>(B + i * plane + idx, C::enc(g[j][i], L.es[i]));
+      for (int i = 0; i < 9; ++i)
+        put<NTS>(reinterpret_cast<T*>(reinterpret_cast<char*>(B + i * plane) + off), C::enc(g[j][i], L.es[i]));
     }
   }
 }

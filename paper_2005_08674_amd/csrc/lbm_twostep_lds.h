@@ -113,15 +113,24 @@ __device__ inline void two_step_tile(const LatDesc& Ld, int parity, int txi, int
   const bool inner = x0 >= 3 && x0 + TL_TX + 3 <= nx && y0 >= 2 && y0 + TY + 2 <= ny;
   if (inner) {
     constexpr int N1 = (TY + 2) * TL_W, N2 = TY * TL_TX;
+    // per-plane base pointers (uniform) and 32-bit unsigned byte offsets (a
+    // plane is below 4 GiB), so each access is a scalar base plus one vector
+    // offset
 #pragma unroll
     for (int it = 0; it < (N1 + NT - 1) / NT; ++it) {
       const int k = tid + it * NT;
       if (k < N1) {
         const int r = k / TL_W, cx = k - r * TL_W;
-        const int64_t idx = (int64_t)(y0 - 1 + r) * pitch + (x0 - 2 + cx);
+        const uint32_t idx = (uint32_t)((y0 - 1 + r) * pitch + (x0 - 2 + cx));
+        // byte offsets of the source rows y + 1, y, y - 1; the x shift is a constant
+        const uint32_t ro[3] = {(idx + (uint32_t)pitch) * (uint32_t)sizeof(T), idx * (uint32_t)sizeof(T),
+                                (idx - (uint32_t)pitch) * (uint32_t)sizeof(T)};
         R g[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = C::dec(A[i * plane + idx - (kCy[i] * pitch + kCx[i])], Ld.ds[i]);
+        for (int i = 0; i < 9; ++i) {
+          const char* __restrict__ Ai = reinterpret_cast<const char*>(A + i * plane);
+          g[i] = C::dec(*reinterpret_cast<const T*>(Ai + ro[1 + kCy[i]] - kCx[i] * (int)sizeof(T)), Ld.ds[i]);
+        }
         collide<R, CM>(Ld, g, rho0, base, omega);
 #pragma unroll
         for (int i = 0; i < 9; ++i) lds[i][1 + r][cx] = C::enc(g[i], Ld.es[i]);
@@ -137,9 +146,10 @@ __device__ inline void two_step_tile(const LatDesc& Ld, int parity, int txi, int
 #pragma unroll
         for (int i = 0; i < 9; ++i) g[i] = C::dec(lds[i][r + 2 - kCy[i]][cx + 2 - kCx[i]], Ld.ds[i]);
         collide<R, CM>(Ld, g, rho0, base, omega);
-        const int64_t idx = (int64_t)(y0 + r) * pitch + (x0 + cx);
+        const uint32_t off = (uint32_t)((y0 + r) * pitch + (x0 + cx)) * (uint32_t)sizeof(T);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) put<NTS>(B + i * plane + idx, C::enc(g[i], Ld.es[i]));
+        for (int i = 0; i < 9; ++i)
+          put<NTS>(reinterpret_cast<T*>(reinterpret_cast<char*>(B + i * plane) + off), C::enc(g[i], Ld.es[i]));
       }
     }
     return;
