@@ -38,7 +38,8 @@ namespace lbm {
   X(20, 512, true, 2)    \
   X(8, 256, true, 2)     \
   X(12, 384, true, 2)    \
-  X(24, 768, true, 2)
+  X(24, 768, true, 2)    \
+  X(20, 768, true, 2)
 
 template <int S, int TY, int NT, bool NTS, int CM, int MAP>
 __global__ __launch_bounds__(NT) void k_two_step(LatDesc L, int parity, int tiles_x, int tiles_y) {
