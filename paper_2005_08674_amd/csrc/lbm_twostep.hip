@@ -41,8 +41,18 @@ namespace lbm {
   X(24, 768, true, 2)    \
   X(20, 768, true, 2)
 
+// Register budget: the 32-bit arithmetic formats are held to 80 VGPRs, which
+// lets 6 waves share a SIMD (the LDS of the larger tiles allows no more); the
+// boundary-tile path would otherwise take a few more and cost every tile that
+// occupancy.
+template <int S>
+constexpr int two_step_waves() {
+  return S == ST_F64 ? 1 : 6;
+}
+
 template <int S, int TY, int NT, bool NTS, int CM, int MAP>
-__global__ __launch_bounds__(NT) void k_two_step(LatDesc L, int parity, int tiles_x, int tiles_y) {
+__global__ __launch_bounds__(NT, two_step_waves<S>()) void k_two_step(LatDesc L, int parity, int tiles_x,
+                                                                    int tiles_y) {
   int txi, tyi;
   if (MAP == 0) {
     txi = blockIdx.x;
@@ -133,7 +143,7 @@ hipError_t launch_two_step(const LatDesc& L, int parity, int id, hipStream_t s) 
 // entries with lat < 0 pad the grid.  The member's descriptor carries its
 // collision model, read at run time.
 template <int S, int TY, int NT, bool NTS>
-__global__ __launch_bounds__(NT) void k_ens_two_step(const LatDesc* __restrict__ descs,
+__global__ __launch_bounds__(NT, two_step_waves<S>()) void k_ens_two_step(const LatDesc* __restrict__ descs,
                                                      const TwoTile* __restrict__ list, int parity) {
   const TwoTile t = list[blockIdx.x];
   if (t.lat < 0) return;  // padding: the whole block leaves before any barrier

@@ -36,6 +36,20 @@ __device__ inline void tl_moments_global(const LatDesc& Ld, const typename Codec
   moments<R>(g, R(Ld.rho0), b, m[0], m[1], m[2]);
 }
 
+// Populations of node (x, y) whose pull source x - c_i lies outside the
+// lattice (all four edges non-periodic): c_x = +1 at x = 0, c_x = -1 at
+// x = nx - 1, and the same in y.  Non-zero exactly on boundary nodes.
+__device__ inline uint32_t tl_unknown(int x, int y, int nx, int ny) {
+  uint32_t u = 0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const bool out = (x == 0 && kCx[i] > 0) || (x == nx - 1 && kCx[i] < 0) || (y == 0 && kCy[i] > 0) ||
+                     (y == ny - 1 && kCy[i] < 0);
+    u |= out ? (1u << i) : 0u;
+  }
+  return u;
+}
+
 // NSBC of boundary node (x, y): unknown populations already zeroed and
 // flagged in `unknown`; `mom(xx, yy, m)` returns the previous level's moments
 // of any lattice node.  Same order as the edge kernel: the x normal first
@@ -155,24 +169,28 @@ __device__ inline void two_step_tile(const LatDesc& Ld, int parity, int txi, int
     return;
   }
 
-  // ---- level t + 1 on lattice rows y0 - my .. y0 + TY + my - 1, columns x0 - 2 .. x0 + 65
+  // ---- level t + 1 on lattice rows y0 - my .. y0 + TY + my - 1, columns x0 - 2 .. x0 + 65.
+  // A population whose pull source lies outside the lattice is unknown (set
+  // by the node's position alone); the others are pulled from sources clamped
+  // into the lattice (a clamped source is only ever an unknown one), so every
+  // lane runs the same loads and selects instead of branching per population.
   for (int k = tid; k < rows1 * TL_W; k += NT) {
     const int r = k / TL_W, cx = k - r * TL_W;
     const int x = x0 - 2 + cx, y = y0 - my + r;
     if (x < 0 || x >= nx || y < 0 || y >= ny) continue;
+    const uint32_t unknown = tl_unknown(x, y, nx, ny);
+    // source column for c_x = -1, 0, +1 and byte offset of the source row for c_y = -1, 0, +1
+    const int sxs[3] = {min(x + 1, nx - 1), x, max(x - 1, 0)};
+    const uint32_t srow[3] = {(uint32_t)(min(y + 1, ny - 1) * pitch), (uint32_t)(y * pitch),
+                              (uint32_t)(max(y - 1, 0) * pitch)};
     R g[9];
-    uint32_t unknown = 0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      const int sx = x - kCx[i], sy = y - kCy[i];
-      if (sx < 0 || sx >= nx || sy < 0 || sy >= ny) {
-        unknown |= 1u << i;
-        g[i] = R(0);
-      } else {
-        g[i] = C::dec(A[i * plane + ((int64_t)sy * pitch + sx)], Ld.ds[i]);
-      }
+      const T* __restrict__ Ai = A + i * plane;
+      const R v = C::dec(Ai[srow[1 + kCy[i]] + (uint32_t)sxs[1 + kCx[i]]], Ld.ds[i]);
+      g[i] = (unknown >> i) & 1u ? R(0) : v;
     }
-    if (x == 0 || x == nx - 1 || y == 0 || y == ny - 1) {
+    if (unknown) {
       auto mom = [&](int xx, int yy, R m[3]) { tl_moments_global<S>(Ld, A, xx, yy, base, m); };
       tl_nsbc<R>(Ld, g, unknown, x, y, rho0, base, mom);
     }
@@ -195,23 +213,21 @@ __device__ inline void two_step_tile(const LatDesc& Ld, int parity, int txi, int
     const int r = k / TL_TX, cx = k - r * TL_TX;
     const int x = x0 + cx, y = y0 + r;
     if (x >= nx || y >= ny) continue;
+    const uint32_t unknown = tl_unknown(x, y, nx, ny);
+    const int lxs[3] = {min(x + 1, nx - 1) - x0 + 2, cx + 2, max(x - 1, 0) - x0 + 2};
+    const int lys[3] = {min(y + 1, ny - 1) - y0 + 2, r + 2, max(y - 1, 0) - y0 + 2};
     R g[9];
-    uint32_t unknown = 0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      const int sx = x - kCx[i], sy = y - kCy[i];
-      if (sx < 0 || sx >= nx || sy < 0 || sy >= ny) {
-        unknown |= 1u << i;
-        g[i] = R(0);
-      } else {
-        g[i] = C::dec(lds[i][sy - y0 + 2][sx - x0 + 2], Ld.ds[i]);
-      }
+      const R v = C::dec(lds[i][lys[1 + kCy[i]]][lxs[1 + kCx[i]]], Ld.ds[i]);
+      g[i] = (unknown >> i) & 1u ? R(0) : v;
     }
-    if (x == 0 || x == nx - 1 || y == 0 || y == ny - 1) tl_nsbc<R>(Ld, g, unknown, x, y, rho0, base, mom1);
+    if (unknown) tl_nsbc<R>(Ld, g, unknown, x, y, rho0, base, mom1);
     collide<R, CM>(Ld, g, rho0, base, omega);
-    const int64_t idx = (int64_t)y * pitch + x;
+    const uint32_t off = (uint32_t)(y * pitch + x) * (uint32_t)sizeof(T);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) put<NTS>(B + i * plane + idx, C::enc(g[i], Ld.es[i]));
+    for (int i = 0; i < 9; ++i)
+      put<NTS>(reinterpret_cast<T*>(reinterpret_cast<char*>(B + i * plane) + off), C::enc(g[i], Ld.es[i]));
   }
 }
 
