@@ -194,6 +194,25 @@ def test_zero_network_equals_nsbc():
     assert np.array_equal(a.populations().cpu().numpy(), b.populations().cpu().numpy())
 
 
+def test_closure_with_overlapped_edge_kernel_matches_serial():
+    """The closure edge kernel on a second stream beside the bulk kernel gives the bits of the serial
+    launches (a network with non-zero outputs, so the closure really acts)."""
+    from paper_2005_08674_amd import lbm
+    from paper_2005_08674_amd.lattice import Lattice
+    blob = _trainer(_oracle_params(3)).export(6.0)
+    nx, ny = 150, 70
+    f = W.lamb_oseen(nx, ny, 60.0, 35.0, 6.0, 0.03, (0.05, 0.0))
+    a = Lattice(nx, ny, 0.6, f, store="f32", m0=(1.0, 0.05, 0.0))
+    b = Lattice(nx, ny, 0.6, f, store="f32", m0=(1.0, 0.05, 0.0))
+    for g in (a, b):
+        lbm.lbm_set_closure(g.ctx, blob.data_ptr(), 1)
+    lbm.lbm_set_overlap(a.ctx, True)
+    for n in (1, 6, 31):
+        a.step(n)
+        b.step(n)
+        assert np.array_equal(a.populations().cpu().numpy(), b.populations().cpu().numpy()), n
+
+
 def test_nonfinite_or_untrusted_output_falls_back_to_nsbc():
     p = _zero_params()
     p["b3"] = np.array([np.nan, 0.0, 0.0])
