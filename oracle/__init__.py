@@ -6,8 +6,8 @@ TEST INFRASTRUCTURE ONLY: the test-suite, ``__graft_entry__.smoke()`` and the
 this package imports nothing from the product package.
 
 ``lbm_oracle.c`` holds the lattice arithmetic (plain C, fp64, or x87 extended
-precision when built with ``-DORC_LONG_DOUBLE``); this module builds it with
-gcc and wraps it with ctypes.  ``mlp.py`` is the numpy fp64 oracle of the
+precision when built with ``-DORC_LONG_DOUBLE``) and ``lbm_oracle3d.c`` the
+same for D3Q19; this module builds both with gcc and wraps them with ctypes.  ``mlp.py`` is the numpy fp64 oracle of the
 boundary-closure network and ``reflection.py`` the fp64 reflection-energy norm.
 """
 from __future__ import annotations
@@ -21,8 +21,11 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 BUILD_DIR = os.path.join(HERE, "_build")
 SRC = os.path.join(HERE, "lbm_oracle.c")
+SRC3 = os.path.join(HERE, "lbm_oracle3d.c")
 LIBS = {"double": os.path.join(BUILD_DIR, "liblbm_oracle.so"),
-        "longdouble": os.path.join(BUILD_DIR, "liblbm_oracle_ld.so")}
+        "longdouble": os.path.join(BUILD_DIR, "liblbm_oracle_ld.so"),
+        "3d": os.path.join(BUILD_DIR, "liblbm_oracle3d.so"),
+        "3d_longdouble": os.path.join(BUILD_DIR, "liblbm_oracle3d_ld.so")}
 
 BC_PERIODIC = 0
 BC_NSBC = 1
@@ -32,11 +35,11 @@ BC_VELOCITY = 2
 def build(verbose: bool = False) -> None:
     """Compile both precisions of the oracle with gcc (always recompiles)."""
     os.makedirs(BUILD_DIR, exist_ok=True)
-    base = ["gcc", "-O2", "-std=c11", "-fno-fast-math", "-ffp-contract=off",
-            "-fopenmp", "-shared", "-fPIC", SRC, "-lm"]
     for kind, out in LIBS.items():
-        cmd = list(base) + ["-o", out + ".tmp"]
-        if kind == "longdouble":
+        src = SRC3 if kind.startswith("3d") else SRC
+        cmd = ["gcc", "-O2", "-std=c11", "-fno-fast-math", "-ffp-contract=off",
+               "-fopenmp", "-shared", "-fPIC", src, "-lm", "-o", out + ".tmp"]
+        if kind.endswith("longdouble"):
             cmd.insert(1, "-DORC_LONG_DOUBLE")
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -199,6 +202,109 @@ class Lattice:
         """(rho - rho0, ux, uy), each [ny][nx] float64."""
         out = [np.zeros((self.ny, self.nx), np.float64) for _ in range(3)]
         self.lib.orc_moments(ctypes.byref(self.p), _ptr(self.g), _ptr(out[0]), _ptr(out[1]), _ptr(out[2]))
+        return tuple(out)
+
+
+class Orc3Params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("tau", ctypes.c_double), ("rho0", ctypes.c_double),
+                ("bc", ctypes.c_int * 6),
+                ("gamma", ctypes.c_double), ("beta", ctypes.c_double),
+                ("m0", ctypes.c_double * 4)]
+
+
+_handles3: dict = {}
+
+
+def _lib3(kind: str = "double"):
+    key = "3d" if kind == "double" else "3d_longdouble"
+    if key in _handles3:
+        return _handles3[key]
+    if not os.path.exists(LIBS[key]):
+        build()
+    lib = ctypes.CDLL(LIBS[key])
+    P = ctypes.c_void_p
+    for name, args in [("orc3_lattice", [P, P, P]), ("orc3_feq", [ctypes.c_double, P, P]),
+                       ("orc3_collide_node", [ctypes.c_double, ctypes.c_double, P, P]),
+                       ("orc3_moments_node", [ctypes.c_double, P, P]),
+                       ("orc3_init", [P, P, P, P, P, P]), ("orc3_moments", [P, P, P]),
+                       ("orc3_step", [P, P, ctypes.c_int])]:
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    _handles3[key] = lib
+    return lib
+
+
+def lattice_constants_3d(kind: str = "double"):
+    """(c [19][3], w [19], opp [19]) of the oracle's D3Q19 lattice."""
+    c = np.zeros((19, 3), np.int32)
+    w = np.zeros(19, _dtype(kind))
+    opp = np.zeros(19, np.int32)
+    _lib3(kind).orc3_lattice(_ptr(c), _ptr(w), _ptr(opp))
+    return c, w, opp
+
+
+def feq_3d(rho0, m4, kind: str = "double") -> np.ndarray:
+    m = np.ascontiguousarray(m4, dtype=np.float64)
+    out = np.zeros(19, _dtype(kind))
+    _lib3(kind).orc3_feq(float(rho0), _ptr(m), _ptr(out))
+    return out
+
+
+def collide_node_3d(tau, rho0, g19, kind: str = "double") -> np.ndarray:
+    g19 = np.ascontiguousarray(g19, dtype=_dtype(kind))
+    out = np.zeros(19, _dtype(kind))
+    _lib3(kind).orc3_collide_node(float(tau), float(rho0), _ptr(g19), _ptr(out))
+    return out
+
+
+def moments_node_3d(rho0, g19, kind: str = "double") -> np.ndarray:
+    g19 = np.ascontiguousarray(g19, dtype=_dtype(kind))
+    out = np.zeros(4, _dtype(kind))
+    _lib3(kind).orc3_moments_node(float(rho0), _ptr(g19), _ptr(out))
+    return out
+
+
+class Lattice3D:
+    """One D3Q19 lattice advanced by the oracle.  ``bc`` = (x low, x high, y low, y high, z low, z high),
+    each BC_PERIODIC or BC_NSBC.  Fields are [nz][ny][nx] arrays; ``drho`` is rho - rho0."""
+
+    def __init__(self, nx, ny, nz, tau, drho, ux, uy, uz, rho0=1.0, bc=(1, 1, 1, 1, 1, 1), gamma=0.6, beta=0.0,
+                 m0=(1.0, 0.0, 0.0, 0.0), kind: str = "double"):
+        self.kind = kind
+        self.lib = _lib3(kind)
+        p = Orc3Params()
+        p.nx, p.ny, p.nz, p.tau, p.rho0 = int(nx), int(ny), int(nz), float(tau), float(rho0)
+        for f in range(6):
+            p.bc[f] = int(bc[f])
+        p.gamma, p.beta = float(gamma), float(beta)
+        for a in range(4):
+            p.m0[a] = float(m0[a])
+        self.p = p
+        self.shape = (int(nz), int(ny), int(nx))
+        self.rho0 = float(rho0)
+        self.t = 0
+        self.g = np.zeros((19,) + self.shape, _dtype(kind))
+        f = [np.ascontiguousarray(a, dtype=np.float64).reshape(self.shape) for a in (drho, ux, uy, uz)]
+        if self.lib.orc3_init(ctypes.byref(p), _ptr(f[0]), _ptr(f[1]), _ptr(f[2]), _ptr(f[3]), _ptr(self.g)) != 0:
+            raise ValueError("oracle rejected the lattice parameters")
+
+    def set_farfield(self, beta, rho, ux, uy, uz):
+        self.p.beta = float(beta)
+        for a, v in enumerate((rho, ux, uy, uz)):
+            self.p.m0[a] = float(v)
+
+    def step(self, n: int = 1):
+        if self.lib.orc3_step(ctypes.byref(self.p), _ptr(self.g), int(n)) != 0:
+            raise RuntimeError("orc3_step failed")
+        self.t += int(n)
+        return self
+
+    def moments(self):
+        """(rho - rho0, ux, uy, uz), each [nz][ny][nx] float64."""
+        out = np.zeros((4,) + self.shape, np.float64)
+        self.lib.orc3_moments(ctypes.byref(self.p), _ptr(self.g), _ptr(out))
         return tuple(out)
 
 
