@@ -1,0 +1,546 @@
+// lbm3d.hip -- the D3Q19 sweep for gfx950: one launch per step, every node
+// pulled (eq. lbe_0), collided with BGK (eqs. lbe_1, feq_1) and, on NSBC
+// faces, rebuilt and corrected first (eqs. nes_0..nes_4 with the normal of
+// the faces the node lies on); plus the C ABI of include/lbm3d.h.
+//
+// Pull streaming reads every stored value exactly once, so the sweep moves
+// 2 x 19 x s bytes per node (152 B in FP32) and is bound by HBM bandwidth.
+// Threads map to consecutive x (64-wide wavefronts, coalesced); each access
+// is a per-plane (uniform) base pointer plus a 32-bit byte offset, one offset
+// per source row (y, z shift) with the x shift as an immediate.  The only
+// lines fetched twice are those a row's x-shifted pulls straddle at a block
+// edge; the block order keeps x-neighbouring blocks on one XCD so that the
+// second fetch hits its L2.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm3d.h"
+#include "lbm_device.h"
+#include "lbm_host.h"
+
+namespace lbm {
+namespace d3 {
+
+constexpr int Q = 19;
+constexpr int kC[Q][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+                          {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
+                          {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+
+template <class R>
+__host__ __device__ constexpr R w3(int i) {
+  return i == 0 ? R(1) / R(3) : (i <= 6 ? R(1) / R(18) : R(1) / R(36));
+}
+
+// Everything a kernel needs about one lattice.
+struct Lat3 {
+  void* buf[2];
+  int32_t nx, ny, nz, pitch;
+  int64_t slab;   // elements per z-slab (ny * pitch)
+  int64_t plane;  // elements per population plane
+  int32_t bc[6];
+  int32_t store, _pad;
+  double omega, rho0, gamma, beta;
+  double m0[4];   // far field (rho - rho0, ux, uy, uz)
+};
+
+template <class R>
+__device__ inline void moments3(const R g[Q], R rho0, R m[4]) {
+  R s = R(0), j[3] = {R(0), R(0), R(0)};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    s += g[i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      if (kC[i][a]) j[a] += kC[i][a] > 0 ? g[i] : -g[i];
+  }
+  const R ir = recip(rho0 + s);
+  m[0] = s;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) m[1 + a] = j[a] * ir;
+}
+
+// g^eq_i - w_i rho0 = w_i [drho + rho (3 c.u + 9/2 (c.u)^2 - 3/2 u.u)]
+template <class R>
+__device__ inline void equilibrium3(R rho0, const R m[4], R geq[Q]) {
+  const R rho = rho0 + m[0];
+  const R q = R(1.5) * (m[1] * m[1] + m[2] * m[2] + m[3] * m[3]);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    R a = R(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      if (kC[i][k]) a += kC[i][k] > 0 ? m[1 + k] : -m[1 + k];
+    geq[i] = w3<R>(i) * (m[0] + rho * fma(a, fma(R(4.5), a, R(3)), -q));
+  }
+}
+
+// BGK in place, written per pair of opposite directions (2i-1, 2i): the even
+// part E + 9/2 rho a^2 is shared, w_i is folded into omega.
+template <class R>
+__device__ inline void bgk3(R g[Q], R rho0, R omega) {
+  R m[4];
+  moments3<R>(g, rho0, m);
+  const R rho = rho0 + m[0];
+  const R e = fma(-rho, R(1.5) * (m[1] * m[1] + m[2] * m[2] + m[3] * m[3]), m[0]);
+  const R r45 = R(4.5) * rho, r3 = R(3) * rho, om1 = R(1) - omega;
+  g[0] = fma(omega * w3<R>(0), e, om1 * g[0]);
+#pragma unroll
+  for (int p = 1; p < Q; p += 2) {
+    R a = R(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      if (kC[p][k]) a += kC[p][k] > 0 ? m[1 + k] : -m[1 + k];
+    const R ow = omega * w3<R>(p);
+    const R even = fma(r45 * a, a, e), odd = r3 * a;
+    g[p] = fma(ow, even + odd, om1 * g[p]);
+    g[p + 1] = fma(ow, even - odd, om1 * g[p + 1]);
+  }
+}
+
+// Moments of node (x, y, z) of the stored level.
+template <int S>
+__device__ inline void node_moments3(const Lat3& L, const typename Codec<S>::T* A, int x, int y, int z,
+                                     typename Codec<S>::R m[4]) {
+  using C = Codec<S>;
+  using R = typename C::R;
+  R g[Q];
+  const int64_t idx = (int64_t)z * L.slab + (int64_t)y * L.pitch + x;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) g[i] = C::dec(A[i * L.plane + idx], 1.0f);
+  moments3<R>(g, R(L.rho0), m);
+}
+
+// Boundary node: pulls with wrap-around on periodic faces; populations whose
+// source lies outside across an NSBC face are rebuilt by NSBC.
+template <int S>
+__device__ inline void boundary_node3(const Lat3& L, const typename Codec<S>::T* A, int x, int y, int z,
+                                      typename Codec<S>::R g[Q]) {
+  using C = Codec<S>;
+  using R = typename C::R;
+  const int n[3] = {L.nx, L.ny, L.nz}, p[3] = {x, y, z};
+  uint32_t unknown = 0;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    int s[3];
+    bool out = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      s[a] = p[a] - kC[i][a];
+      if (s[a] < 0 || s[a] >= n[a]) {
+        if (L.bc[2 * a] == BC_PERIODIC) s[a] = s[a] < 0 ? s[a] + n[a] : s[a] - n[a];
+        else out = true;
+      }
+    }
+    if (out) {
+      unknown |= 1u << i;
+      g[i] = R(0);
+    } else {
+      g[i] = C::dec(A[i * L.plane + ((int64_t)s[2] * L.slab + (int64_t)s[1] * L.pitch + s[0])], 1.0f);
+    }
+  }
+  if (!unknown) return;
+  // eq. nes_2 with the normalised normal of the k NSBC faces the node is on
+  const R rho0 = R(L.rho0);
+  R mb[4], d[4] = {R(0), R(0), R(0), R(0)};
+  node_moments3<S>(L, A, x, y, z, mb);
+  int k = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (L.bc[2 * a] != BC_NSBC) continue;
+    const int step = p[a] == 0 ? 1 : (p[a] == n[a] - 1 ? -1 : 0);
+    if (!step) continue;
+    int q[3] = {x, y, z};
+    q[a] += step;
+    R mn[4];
+    node_moments3<S>(L, A, q[0], q[1], q[2], mn);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) d[c] += mb[c] - mn[c];
+    ++k;
+  }
+  const R fac = R(L.gamma) * (k == 1 ? R(1) : (k == 2 ? R(0.70710678118654752440) : R(0.57735026918962576451)));
+  const R beta = R(L.beta);
+  R mc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) mc[c] = (R(1) - beta) * (mb[c] - fac * d[c]) + beta * R(L.m0[c]);  // eq. nes_3
+  // eqs. nes_0/nes_1, then eq. nes_4 with 1/c_s^2 = 3
+  R geq[Q];
+  equilibrium3<R>(rho0, mc, geq);
+  R gn[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int o = (i == 0) ? 0 : (i & 1 ? i + 1 : i - 1);
+    gn[i] = (unknown >> i) & 1u ? ((unknown >> o) & 1u ? geq[i] : geq[i] + (g[o] - geq[o])) : g[i];
+  }
+  R s = R(0), j[3] = {R(0), R(0), R(0)};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    s += gn[i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      if (kC[i][a]) j[a] += kC[i][a] > 0 ? gn[i] : -gn[i];
+  }
+  const R rc = rho0 + mc[0];
+  const R dr = s - mc[0];
+  R dj[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) dj[a] = R(3) * (j[a] - rc * mc[1 + a]);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    R cd = R(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      if (kC[i][a]) cd += kC[i][a] > 0 ? dj[a] : -dj[a];
+    g[i] = gn[i] - w3<R>(i) * (dr + cd);
+  }
+}
+
+// One launch per step.  Block b takes item (b mod 8) * per + b / 8 of the
+// list of (z chunk, tile row, tile column) in that order, so XCD k (blocks
+// b = k mod 8) works through the k-th contiguous stretch: x-neighbouring
+// tiles, which share the lines their shifted pulls straddle, run on one XCD.
+template <int S, int BX, int BY, int ZC>
+__global__ __launch_bounds__(BX* BY) void k3_step(Lat3 L, int parity, int tiles_x, int tiles_y, int nitems,
+                                                  int per) {
+  using C = Codec<S>;
+  using T = typename C::T;
+  using R = typename C::R;
+  const int b = blockIdx.x;
+  const int item = (b & 7) * per + (b >> 3);
+  if (item >= nitems) return;  // no barrier in this kernel
+  const int ntile = tiles_x * tiles_y;
+  const int zc = item / ntile, t = item - zc * ntile;
+  const int ty = t / tiles_x, tx = t - ty * tiles_x;
+  const int x = tx * BX + threadIdx.x, y = ty * BY + threadIdx.y;
+  const int nx = L.nx, ny = L.ny, nz = L.nz;
+  if (x >= nx || y >= ny) return;
+  const T* __restrict__ A = static_cast<const T*>(parity ? L.buf[1] : L.buf[0]);
+  T* __restrict__ B = static_cast<T*>(parity ? L.buf[0] : L.buf[1]);
+  const int pitch = L.pitch;
+  const int64_t slab = L.slab, plane = L.plane;
+  const R rho0 = R(L.rho0), omega = R(L.omega);
+  const bool xy_inner = x >= 1 && x <= nx - 2 && y >= 1 && y <= ny - 2;
+  const int z1 = min(nz, (zc + 1) * ZC);
+  for (int z = zc * ZC; z < z1; ++z) {
+    R g[Q];
+    if (xy_inner && z >= 1 && z <= nz - 2) {
+      const uint32_t idx = (uint32_t)((int64_t)z * slab + (int64_t)y * pitch + x);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const char* Ai = reinterpret_cast<const char*>(A + i * plane);
+        const uint32_t row = (idx - (uint32_t)(kC[i][2] * slab + kC[i][1] * pitch)) * (uint32_t)sizeof(T);
+        g[i] = C::dec(*reinterpret_cast<const T*>(Ai + row - kC[i][0] * (int)sizeof(T)), 1.0f);
+      }
+    } else {
+      boundary_node3<S>(L, A, x, y, z, g);
+    }
+    bgk3<R>(g, rho0, omega);
+    const uint32_t off = (uint32_t)((int64_t)z * slab + (int64_t)y * pitch + x) * (uint32_t)sizeof(T);
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      __builtin_nontemporal_store(C::enc(g[i], 1.0f), reinterpret_cast<T*>(reinterpret_cast<char*>(B + i * plane) + off));
+  }
+}
+
+struct Shape3 {
+  int bx, by, zc;
+};
+#define LBM3D_SHAPES(X) \
+  X(64, 4, 1)           \
+  X(64, 4, 4)           \
+  X(64, 4, 16)          \
+  X(128, 2, 4)          \
+  X(256, 1, 4)          \
+  X(64, 8, 4)           \
+  X(256, 1, 16)
+static const Shape3 kShapes3[] = {
+#define X(a, b, c) {a, b, c},
+    LBM3D_SHAPES(X)
+#undef X
+};
+static constexpr int kNumShapes3 = sizeof(kShapes3) / sizeof(kShapes3[0]);
+
+template <int S, int BX, int BY, int ZC>
+static hipError_t launch3_t(const Lat3& L, int parity, hipStream_t s) {
+  const int tiles_x = (L.nx + BX - 1) / BX, tiles_y = (L.ny + BY - 1) / BY, zch = (L.nz + ZC - 1) / ZC;
+  const int nitems = tiles_x * tiles_y * zch, per = (nitems + 7) / 8;
+  k3_step<S, BX, BY, ZC><<<dim3(8 * per), dim3(BX, BY), 0, s>>>(L, parity, tiles_x, tiles_y, nitems, per);
+  return hipGetLastError();
+}
+
+template <int S>
+static hipError_t launch3_s(const Lat3& L, int parity, int shape, hipStream_t s) {
+  int k = 0;
+#define X(a, b, c)                                                  \
+  if (shape == k) return launch3_t<S, a, b, c>(L, parity, s);      \
+  ++k;
+  LBM3D_SHAPES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+static hipError_t launch3(const Lat3& L, int parity, int shape, hipStream_t s) {
+  return L.store == ST_F64 ? launch3_s<ST_F64>(L, parity, shape, s) : launch3_s<ST_F32>(L, parity, shape, s);
+}
+
+// f = f^eq(rho, u) of the initial fields, as deviations
+template <int S>
+__global__ void k3_init(Lat3 L, const double* __restrict__ drho, const double* __restrict__ ux,
+                        const double* __restrict__ uy, const double* __restrict__ uz) {
+  using T = typename Codec<S>::T;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+  if (x >= L.nx) return;
+  const int64_t k = ((int64_t)z * L.ny + y) * L.nx + x;
+  const double m[4] = {drho[k], ux[k], uy[k], uz[k]};
+  double geq[Q];
+  equilibrium3<double>(L.rho0, m, geq);
+  T* B = static_cast<T*>(L.buf[0]);
+  const int64_t idx = (int64_t)z * L.slab + (int64_t)y * L.pitch + x;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) B[i * L.plane + idx] = (T)geq[i];
+}
+
+template <int S>
+__global__ void k3_moments(Lat3 L, int parity, double* __restrict__ out) {
+  using T = typename Codec<S>::T;
+  using R = typename Codec<S>::R;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+  if (x >= L.nx) return;
+  R m[4];
+  node_moments3<S>(L, static_cast<const T*>(parity ? L.buf[1] : L.buf[0]), x, y, z, m);
+  const int64_t n = (int64_t)L.nx * L.ny * L.nz, k = ((int64_t)z * L.ny + y) * L.nx + x;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) out[c * n + k] = (double)m[c];
+}
+
+}  // namespace d3
+}  // namespace lbm
+
+// ------------------------------------------------------------------ C ABI
+using lbm::host::fail;
+
+#define HIPCHK3(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail(LBM_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+struct lbm3d_ctx {
+  lbm::d3::Lat3 L;
+  int parity = 0;
+  int64_t t = 0;
+  int shape = 1;
+  hipStream_t stream = nullptr;
+};
+
+namespace {
+
+struct Layout3 {
+  size_t esize;
+  int32_t pitch;
+  int64_t slab, plane;
+  size_t buf_bytes, total;
+};
+
+int check3(const lbm3d_params* p) {
+  if (!p) return fail(LBM_ERR_ARG, "params is NULL");
+  if (p->nx < 3 || p->ny < 3 || p->nz < 3) return fail(LBM_ERR_ARG, "lattice %dx%dx%d: each side must be >= 3", p->nx, p->ny, p->nz);
+  if ((int64_t)p->nx * p->ny * p->nz > (int64_t)1 << 28) return fail(LBM_ERR_ARG, "lattice exceeds 2^28 nodes");
+  if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_ERR_ARG, "tau = %g: BGK needs tau > 0.5", p->tau);
+  if (!(p->rho0 > 0) || !std::isfinite(p->rho0)) return fail(LBM_ERR_ARG, "rho0 = %g must be > 0", p->rho0);
+  for (int f = 0; f < 6; ++f)
+    if (p->bc[f] != LBM_BC_PERIODIC && p->bc[f] != LBM_BC_NSBC)
+      return fail(LBM_ERR_ARG, "bc[%d] = %d is not LBM_BC_PERIODIC or LBM_BC_NSBC", f, p->bc[f]);
+  for (int a = 0; a < 3; ++a)
+    if ((p->bc[2 * a] == LBM_BC_PERIODIC) != (p->bc[2 * a + 1] == LBM_BC_PERIODIC))
+      return fail(LBM_ERR_ARG, "periodic faces must come in pairs");
+  if (!std::isfinite(p->gamma)) return fail(LBM_ERR_ARG, "gamma must be finite");
+  if (p->store != LBM_STORE_F64 && p->store != LBM_STORE_F32)
+    return fail(LBM_ERR_ARG, "store = %d: the 3-D lattice stores FP64 or FP32", p->store);
+  return LBM_OK;
+}
+
+Layout3 layout3(const lbm3d_params* p) {
+  using lbm::host::round_up;
+  Layout3 l;
+  l.esize = p->store == LBM_STORE_F64 ? 8 : 4;
+  const size_t row = round_up((size_t)p->nx * l.esize, 256);
+  l.pitch = (int32_t)(row / l.esize);
+  l.slab = (int64_t)l.pitch * p->ny;
+  size_t plane_bytes = round_up(row * (size_t)p->ny * p->nz, 4096);
+  if (plane_bytes % 65536 == 0) plane_bytes += 4096;  // planes not a large power of two apart
+  l.plane = (int64_t)(plane_bytes / l.esize);
+  l.buf_bytes = round_up(19 * plane_bytes, (size_t)2 << 20);
+  l.total = 2 * l.buf_bytes;
+  return l;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm3d_params_default(lbm3d_params* p) {
+  if (!p) return fail(LBM_ERR_ARG, "params is NULL");
+  std::memset(p, 0, sizeof(*p));
+  p->nx = p->ny = p->nz = 3;
+  p->tau = 0.6;
+  p->rho0 = 1.0;
+  for (int f = 0; f < 6; ++f) p->bc[f] = LBM_BC_NSBC;
+  p->gamma = 0.6;
+  p->store = LBM_STORE_F32;
+  return LBM_OK;
+}
+
+int lbm3d_workspace_bytes(const lbm3d_params* p, size_t* bytes) {
+  if (!bytes) return fail(LBM_ERR_ARG, "bytes is NULL");
+  int rc = check3(p);
+  if (rc) return rc;
+  *bytes = layout3(p).total;
+  return LBM_OK;
+}
+
+int lbm3d_init(lbm3d_ctx** out, const lbm3d_params* p, void* workspace, size_t bytes, const double* drho,
+               const double* ux, const double* uy, const double* uz, void* hip_stream) {
+  if (!out) return fail(LBM_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = check3(p);
+  if (rc) return rc;
+  const Layout3 lay = layout3(p);
+  if (!workspace || ((uintptr_t)workspace & 255)) return fail(LBM_ERR_ARG, "workspace NULL or not 256-byte aligned");
+  if (bytes < lay.total) return fail(LBM_ERR_ARG, "workspace of %zu bytes < %zu required", bytes, lay.total);
+  if (!drho || !ux || !uy || !uz) return fail(LBM_ERR_ARG, "initial fields must not be NULL");
+  lbm3d_ctx* c = new lbm3d_ctx();
+  lbm::d3::Lat3& L = c->L;
+  std::memset(&L, 0, sizeof(L));
+  L.buf[0] = workspace;
+  L.buf[1] = static_cast<char*>(workspace) + lay.buf_bytes;
+  L.nx = p->nx;
+  L.ny = p->ny;
+  L.nz = p->nz;
+  L.pitch = lay.pitch;
+  L.slab = lay.slab;
+  L.plane = lay.plane;
+  for (int f = 0; f < 6; ++f) L.bc[f] = p->bc[f];
+  L.store = p->store == LBM_STORE_F64 ? lbm::ST_F64 : lbm::ST_F32;
+  L.omega = 1.0 / p->tau;
+  L.rho0 = p->rho0;
+  L.gamma = p->gamma;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  const dim3 grid((p->nx + 255) / 256, p->ny, p->nz);
+  if (L.store == lbm::ST_F64) lbm::d3::k3_init<lbm::ST_F64><<<grid, dim3(256), 0, c->stream>>>(L, drho, ux, uy, uz);
+  else lbm::d3::k3_init<lbm::ST_F32><<<grid, dim3(256), 0, c->stream>>>(L, drho, ux, uy, uz);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    delete c;
+    return fail(LBM_ERR_HIP, "init: %s", hipGetErrorString(e));
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+int lbm3d_set_farfield(lbm3d_ctx* c, double beta, double rho, double ux, double uy, double uz) {
+  if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
+  if (!(beta >= 0.0 && beta <= 1.0)) return fail(LBM_ERR_ARG, "beta = %g outside [0, 1]", beta);
+  if (!std::isfinite(rho) || !std::isfinite(ux) || !std::isfinite(uy) || !std::isfinite(uz))
+    return fail(LBM_ERR_ARG, "reference vector must be finite");
+  c->L.beta = beta;
+  c->L.m0[0] = rho - c->L.rho0;
+  c->L.m0[1] = ux;
+  c->L.m0[2] = uy;
+  c->L.m0[3] = uz;
+  return LBM_OK;
+}
+
+int lbm3d_step(lbm3d_ctx* c, int32_t n) {
+  if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
+  if (n < 0) return fail(LBM_ERR_ARG, "n = %d < 0", n);
+  for (int32_t s = 0; s < n; ++s) {
+    HIPCHK3(lbm::d3::launch3(c->L, c->parity, c->shape, c->stream));
+    c->parity ^= 1;
+    c->t += 1;
+  }
+  return LBM_OK;
+}
+
+int lbm3d_moments(lbm3d_ctx* c, double* out) {
+  if (!c || !out) return fail(LBM_ERR_ARG, "NULL argument");
+  const dim3 grid((c->L.nx + 255) / 256, c->L.ny, c->L.nz);
+  if (c->L.store == lbm::ST_F64)
+    lbm::d3::k3_moments<lbm::ST_F64><<<grid, dim3(256), 0, c->stream>>>(c->L, c->parity, out);
+  else
+    lbm::d3::k3_moments<lbm::ST_F32><<<grid, dim3(256), 0, c->stream>>>(c->L, c->parity, out);
+  HIPCHK3(hipGetLastError());
+  return LBM_OK;
+}
+
+int lbm3d_time(const lbm3d_ctx* c, int64_t* t) {
+  if (!c || !t) return fail(LBM_ERR_ARG, "NULL argument");
+  *t = c->t;
+  return LBM_OK;
+}
+
+int lbm3d_shape_count(void) { return lbm::d3::kNumShapes3; }
+
+int lbm3d_shape_describe(int32_t id, char* buf, size_t len) {
+  if (!buf || len == 0) return fail(LBM_ERR_ARG, "NULL buffer");
+  if (id < 0 || id >= lbm::d3::kNumShapes3) return fail(LBM_ERR_ARG, "shape id %d out of range", id);
+  const lbm::d3::Shape3& s = lbm::d3::kShapes3[id];
+  snprintf(buf, len, "%dx%dxz%d", s.bx, s.by, s.zc);
+  return LBM_OK;
+}
+
+int lbm3d_set_shape(lbm3d_ctx* c, int32_t id) {
+  if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
+  if (id < 0 || id >= lbm::d3::kNumShapes3) return fail(LBM_ERR_ARG, "shape id %d out of range", id);
+  c->shape = id;
+  return LBM_OK;
+}
+
+int lbm3d_autotune(lbm3d_ctx* c, int32_t reps, int32_t* best, float* times_ms) {
+  if (!c || !best) return fail(LBM_ERR_ARG, "NULL argument");
+  if (reps < 1 || reps > 1000) return fail(LBM_ERR_ARG, "reps = %d outside [1, 1000]", reps);
+  std::vector<hipEvent_t> ev(2 * reps);
+  for (auto& x : ev) HIPCHK3(hipEventCreate(&x));
+  float best_t = 1e30f;
+  int best_id = c->shape, rc = LBM_OK;
+  for (int id = 0; id < lbm::d3::kNumShapes3 && rc == LBM_OK; ++id) {
+    // a step reads buffer `parity` and writes only the other: the state is not advanced
+    hipError_t e = lbm::d3::launch3(c->L, c->parity, id, c->stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+      e = hipEventRecord(ev[2 * r], c->stream);
+      if (e == hipSuccess) e = lbm::d3::launch3(c->L, c->parity, id, c->stream);
+      if (e == hipSuccess) e = hipEventRecord(ev[2 * r + 1], c->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    std::vector<float> ts(reps);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = hipEventElapsedTime(&ts[r], ev[2 * r], ev[2 * r + 1]);
+    if (e != hipSuccess) {
+      rc = fail(LBM_ERR_HIP, "3-D shape %d: %s", id, hipGetErrorString(e));
+      break;
+    }
+    std::sort(ts.begin(), ts.end());
+    if (times_ms) times_ms[id] = ts[reps / 2];
+    if (ts[reps / 2] < best_t) {
+      best_t = ts[reps / 2];
+      best_id = id;
+    }
+  }
+  for (auto& x : ev) (void)hipEventDestroy(x);
+  if (rc) return rc;
+  c->shape = best_id;
+  *best = best_id;
+  return LBM_OK;
+}
+
+void lbm3d_destroy(lbm3d_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  delete c;
+}
+
+}  // extern "C"

@@ -108,6 +108,17 @@ _SIGS = {
     "lbm_ens_set_two_step": [_P, ctypes.c_int32],
     "lbm_ens_get_two_step": [_P, _P],
     "lbm_ens_autotune_two_step": [_P, ctypes.c_int32, _P, _P],
+    "lbm3d_params_default": [_P],
+    "lbm3d_workspace_bytes": [_P, _P],
+    "lbm3d_init": [_P, _P, _P, ctypes.c_size_t, _P, _P, _P, _P, _P],
+    "lbm3d_set_farfield": [_P] + [ctypes.c_double] * 5,
+    "lbm3d_step": [_P, ctypes.c_int32],
+    "lbm3d_moments": [_P, _P],
+    "lbm3d_time": [_P, _P],
+    "lbm3d_shape_count": [],
+    "lbm3d_shape_describe": [ctypes.c_int32, _P, ctypes.c_size_t],
+    "lbm3d_set_shape": [_P, ctypes.c_int32],
+    "lbm3d_autotune": [_P, ctypes.c_int32, _P, _P],
     # learned closure (include/lbm_closure.h)
     "lbm_closure_net_bytes": [_P],
     "lbm_set_closure": [_P, _P, ctypes.c_int],
@@ -151,12 +162,14 @@ def load():
     lib.lbm_ens_destroy.restype = None
     lib.lbm_mlp_destroy.argtypes = [_P]
     lib.lbm_mlp_destroy.restype = None
+    lib.lbm3d_destroy.argtypes = [_P]
+    lib.lbm3d_destroy.restype = None
     _lib = lib
     return lib
 
 
 def exported_symbols():
-    return list(_SIGS) + ["lbm_last_error", "lbm_destroy", "lbm_ens_destroy", "lbm_mlp_destroy"]
+    return list(_SIGS) + ["lbm_last_error", "lbm_destroy", "lbm_ens_destroy", "lbm_mlp_destroy", "lbm3d_destroy"]
 
 
 def _check(rc: int, where: str):
@@ -524,3 +537,75 @@ def lbm_mlp_export(m, trust, gain, kmin, net_ptr):
 
 def lbm_mlp_destroy(m):
     load().lbm_mlp_destroy(m)
+
+
+# ------------------------------------------------------------------ D3Q19 (include/lbm3d.h)
+
+class lbm3d_params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("tau", ctypes.c_double), ("rho0", ctypes.c_double),
+                ("bc", ctypes.c_int32 * 6),
+                ("gamma", ctypes.c_double),
+                ("store", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
+
+
+def lbm3d_params_default() -> lbm3d_params:
+    p = lbm3d_params()
+    _check(load().lbm3d_params_default(ctypes.byref(p)), "lbm3d_params_default")
+    return p
+
+
+def lbm3d_workspace_bytes(p: lbm3d_params) -> int:
+    n = ctypes.c_size_t()
+    _check(load().lbm3d_workspace_bytes(ctypes.byref(p), ctypes.byref(n)), "lbm3d_workspace_bytes")
+    return n.value
+
+
+def lbm3d_init(p: lbm3d_params, ws_ptr, nbytes, drho_ptr, ux_ptr, uy_ptr, uz_ptr, stream_ptr):
+    ctx = ctypes.c_void_p()
+    _check(load().lbm3d_init(ctypes.byref(ctx), ctypes.byref(p), ws_ptr, nbytes, drho_ptr, ux_ptr, uy_ptr, uz_ptr,
+                             stream_ptr), "lbm3d_init")
+    return ctx
+
+
+def lbm3d_set_farfield(ctx, beta, rho, ux, uy, uz):
+    _check(load().lbm3d_set_farfield(ctx, beta, rho, ux, uy, uz), "lbm3d_set_farfield")
+
+
+def lbm3d_step(ctx, n: int):
+    _check(load().lbm3d_step(ctx, int(n)), "lbm3d_step")
+
+
+def lbm3d_moments(ctx, out_ptr):
+    _check(load().lbm3d_moments(ctx, out_ptr), "lbm3d_moments")
+
+
+def lbm3d_time(ctx) -> int:
+    t = ctypes.c_int64()
+    _check(load().lbm3d_time(ctx, ctypes.byref(t)), "lbm3d_time")
+    return t.value
+
+
+def lbm3d_shape_count() -> int:
+    return int(load().lbm3d_shape_count())
+
+
+def lbm3d_shape_describe(shape_id: int) -> str:
+    buf = ctypes.create_string_buffer(64)
+    _check(load().lbm3d_shape_describe(int(shape_id), buf, 64), "lbm3d_shape_describe")
+    return buf.value.decode()
+
+
+def lbm3d_set_shape(ctx, shape_id: int):
+    _check(load().lbm3d_set_shape(ctx, int(shape_id)), "lbm3d_set_shape")
+
+
+def lbm3d_autotune(ctx, reps: int = 5):
+    best = ctypes.c_int32()
+    times = (ctypes.c_float * lbm3d_shape_count())()
+    _check(load().lbm3d_autotune(ctx, int(reps), ctypes.byref(best), times), "lbm3d_autotune")
+    return best.value, list(times)
+
+
+def lbm3d_destroy(ctx):
+    load().lbm3d_destroy(ctx)

@@ -190,6 +190,20 @@ def vortex_pulse_2048(seed: int = 5, n: int = 2048) -> Workload:
                     u_ref=0.1, extra={"x0": x0, "y0": y0, "rc": 12.0, "uv": uv})
 
 
+def pulses_3d(n: int = 256, seed: int = 6, count: int = 8):
+    """n^3 D3Q19 workload: `count` seeded Gaussian pulses (A ~ U[1e-4, 1e-3], HWHM ~ U[4, 16], centres
+    ~ U[n/16, 15n/16]^3) at rest; returns (fields, pulses) with fields [nz][ny][nx] (drho, ux, uy, uz)."""
+    rng = np.random.default_rng(seed)
+    lo, hi = n / 16.0, n - n / 16.0
+    pulses = [(rng.uniform(1e-4, 1e-3), rng.uniform(4, 16), *rng.uniform(lo, hi, 3)) for _ in range(count)]
+    z, y, x = np.mgrid[0:n, 0:n, 0:n].astype(np.float32)
+    dr = np.zeros((n, n, n), np.float64)
+    for a, w, cx, cy, cz in pulses:
+        dr += a * np.exp(-math.log(2.0) * ((x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2) / (w * w))
+    zero = np.zeros_like(dr)
+    return (dr, zero, zero.copy(), zero.copy()), pulses
+
+
 @dataclass
 class EnsembleMember:
     nx: int

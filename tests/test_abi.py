@@ -110,6 +110,25 @@ def test_velocity_edges_left_right_with_periodic_bottom_top(lib, bc, ok):
             L.lbm_workspace_bytes(p)
 
 
+def test_3d_parameters(lib):
+    p = L.lbm3d_params_default()
+    assert (p.nx, p.ny, p.nz, p.tau, p.gamma, p.store) == (3, 3, 3, 0.6, 0.6, L.LBM_STORE_F32)
+    p.nx = p.ny = p.nz = 64
+    n32 = L.lbm3d_workspace_bytes(p)
+    assert n32 >= 2 * 19 * 64 ** 3 * 4
+    p.store = L.LBM_STORE_F64
+    assert L.lbm3d_workspace_bytes(p) >= 2 * 19 * 64 ** 3 * 8
+    for field, value, msg in [("nz", 2, "each side"), ("tau", 0.5, "tau"), ("store", L.LBM_STORE_F16DEV, "store")]:
+        q = L.lbm3d_params_default()
+        setattr(q, field, value)
+        with pytest.raises(L.LbmError, match=msg):
+            L.lbm3d_workspace_bytes(q)
+    q = L.lbm3d_params_default()
+    q.bc[4] = L.LBM_BC_PERIODIC
+    with pytest.raises(L.LbmError, match="pairs"):
+        L.lbm3d_workspace_bytes(q)
+
+
 def test_unpaired_periodic_edges_rejected(lib):
     p = L.lbm_params_default()
     p.nx = p.ny = 16

@@ -1,0 +1,88 @@
+"""GPU D3Q19 sweep (include/lbm3d.h) against the CPU D3Q19 oracle: fp64 storage within 1e-12 and fp32
+within 1e-5 (relative, as the 2-D parity tests), every launch shape bit-identical, periodic and NSBC
+face mixes, the smallest lattice."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2005_08674_amd import lbm
+    lbm.load()
+
+
+def _fields(nx, ny, nz, u0=(0.03, -0.02, 0.01), a=1e-3, w=3.0, seed=0):
+    rng = np.random.default_rng(seed)
+    z, y, x = np.mgrid[0:nz, 0:ny, 0:nx].astype(float)
+    c = rng.uniform(0.3, 0.7, 3) * np.array([nx, ny, nz])
+    dr = a * np.exp(-math.log(2) * ((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2) / w ** 2)
+    return dr, np.full_like(dr, u0[0]), np.full_like(dr, u0[1]), np.full_like(dr, u0[2])
+
+
+def _pair(nx, ny, nz, store, tol, checkpoints, bc=(1,) * 6, beta=0.3, u0=(0.03, -0.02, 0.01), tau=0.58):
+    from paper_2005_08674_amd.lattice3d import Lattice3D
+    print(f"\n[3d parity] {nx}x{ny}x{nz} store={store} bc={bc}", flush=True)
+    f = _fields(nx, ny, nz, u0)
+    m0 = (1.0002, *u0)
+    g = Lattice3D(nx, ny, nz, tau, f, bc=bc, store=store, beta=beta, m0=m0)
+    o = oracle.Lattice3D(nx, ny, nz, tau, *f, bc=bc, beta=beta, m0=m0)
+    u_ref = 0.03
+    for t in checkpoints:
+        g.step(t - g.t)
+        o.step(t - o.t)
+        gm, om = g.moments(), o.moments()
+        er = np.abs(gm[0] - om[0]).max()
+        eu = max(np.abs(gm[a] - om[a]).max() for a in (1, 2, 3)) / u_ref
+        print(f"  t={t:4d} e_rho={er:.3e} e_u={eu:.3e}", flush=True)
+        assert er <= tol and eu <= tol, (t, er, eu)
+    g.close()
+
+
+@pytest.mark.parametrize("dims,bc", [((20, 18, 16), (1,) * 6), ((70, 9, 11), (1, 1, 0, 0, 1, 1)),
+                                     ((13, 14, 15), (0,) * 6), ((3, 3, 3), (1,) * 6), ((66, 5, 4), (0, 0, 1, 1, 0, 0))])
+def test_fp64_against_oracle(dims, bc):
+    _pair(*dims, "f64", 1e-12, [1, 5, 30, 80], bc=bc)
+
+
+def test_fp32_against_oracle():
+    _pair(40, 36, 32, "f32", 1e-5, [1, 20, 100])
+
+
+@pytest.mark.parametrize("store", ["f32", "f64"])
+def test_every_shape_bitwise_identical(store):
+    from paper_2005_08674_amd import lbm
+    from paper_2005_08674_amd.lattice3d import Lattice3D
+    f = _fields(70, 19, 23)
+    ref = None
+    for shape in range(lbm.lbm3d_shape_count()):
+        g = Lattice3D(70, 19, 23, 0.6, f, store=store, beta=0.2, m0=(1.0, 0.03, -0.02, 0.01))
+        lbm.lbm3d_set_shape(g.ctx, shape)
+        g.step(7)
+        m = np.array(g.moments())
+        g.close()
+        if ref is None:
+            ref = m
+        else:
+            assert np.array_equal(m, ref), (store, lbm.lbm3d_shape_describe(shape))
+
+
+def test_autotune_leaves_the_state_and_picks_a_shape():
+    from paper_2005_08674_amd import lbm
+    from paper_2005_08674_amd.lattice3d import Lattice3D
+    f = _fields(64, 32, 16)
+    a = Lattice3D(64, 32, 16, 0.6, f)
+    b = Lattice3D(64, 32, 16, 0.6, f)
+    best, times = a.autotune(reps=2)
+    assert 0 <= best < lbm.lbm3d_shape_count() and min(times) > 0 and a.t == 0
+    a.step(5)
+    b.step(5)
+    assert np.array_equal(np.array(a.moments()), np.array(b.moments()))
