@@ -40,7 +40,8 @@ extern "C" {
 typedef struct lbm3d_ctx lbm3d_ctx;
 
 typedef struct {
-    int32_t nx, ny, nz;   /* each >= 3, nx * ny * nz <= 2^28 */
+    int32_t nx, ny, nz;   /* each >= 3, nx * ny * nz <= 2^28, and a plane with rows padded to
+                             256 bytes (ny * nz * that row) under 4 GiB */
     double tau;           /* BGK relaxation time, > 0.5 */
     double rho0;          /* base density of the deviation form, > 0 */
     int32_t bc[6];        /* LBM_BC_PERIODIC or LBM_BC_NSBC per face: x = 0, x = nx-1, y = 0,
@@ -53,7 +54,8 @@ typedef struct {
 /* Defaults: 3x3x3, tau 0.6, rho0 1, NSBC on all faces, gamma 0.6, FP32. */
 int lbm3d_params_default(lbm3d_params* p);
 
-/* Device workspace in bytes: two population buffers of 19 planes. */
+/* Device workspace in bytes: two population buffers of 19 planes and two
+ * small buffers of moments of the nodes next to the x faces. */
 int lbm3d_workspace_bytes(const lbm3d_params* p, size_t* bytes);
 
 /* Create a context on `workspace` (device memory of at least

@@ -40,6 +40,12 @@ __host__ __device__ constexpr R w3(int i) {
 // Everything a kernel needs about one lattice.
 struct Lat3 {
   void* buf[2];
+  // Moments (rho - rho0, ux, uy, uz) at time t of the nodes x = 0, 1,
+  // nx - 2, nx - 1, for NSBC on the x faces: mx[p] goes with buf[p], element
+  // ((side * 2 + layer) * 4 + c) * mxs + z * ny + y, side 0 at x = 0 and 1
+  // at x = nx - 1, layer 0 the face node and 1 its inner neighbour.
+  void* mx[2];
+  int64_t mxs;
   int32_t nx, ny, nz, pitch;
   int64_t slab;   // elements per z-slab (ny * pitch)
   int64_t plane;  // elements per population plane
@@ -83,8 +89,7 @@ __device__ inline void equilibrium3(R rho0, const R m[4], R geq[Q]) {
 // BGK in place, written per pair of opposite directions (2i-1, 2i): the even
 // part E + 9/2 rho a^2 is shared, w_i is folded into omega.
 template <class R>
-__device__ inline void bgk3(R g[Q], R rho0, R omega) {
-  R m[4];
+__device__ inline void bgk3(R g[Q], R rho0, R omega, R m[4]) {
   moments3<R>(g, rho0, m);
   const R rho = rho0 + m[0];
   const R e = fma(-rho, R(1.5) * (m[1] * m[1] + m[2] * m[2] + m[3] * m[3]), m[0]);
@@ -103,62 +108,82 @@ __device__ inline void bgk3(R g[Q], R rho0, R omega) {
   }
 }
 
-// Moments of node (x, y, z) of the stored level.
-template <int S>
-__device__ inline void node_moments3(const Lat3& L, const typename Codec<S>::T* A, int x, int y, int z,
-                                     typename Codec<S>::R m[4]) {
-  using C = Codec<S>;
-  using R = typename C::R;
-  R g[Q];
-  const int64_t idx = (int64_t)z * L.slab + (int64_t)y * L.pitch + x;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) g[i] = C::dec(A[i * L.plane + idx], 1.0f);
-  moments3<R>(g, R(L.rho0), m);
+template <class R>
+__device__ inline void bgk3(R g[Q], R rho0, R omega) {
+  R m[4];
+  bgk3<R>(g, rho0, omega, m);
 }
 
-// Boundary node: pulls with wrap-around on periodic faces; populations whose
-// source lies outside across an NSBC face are rebuilt by NSBC.
+// Moments of the stored node at byte offset `off` of each plane.
+template <int S>
+__device__ inline void node_moments3(const Lat3& L, const typename Codec<S>::T* A, uint32_t off,
+                                     typename Codec<S>::R m[4]) {
+  using C = Codec<S>;
+  using T = typename C::T;
+  using R = typename C::R;
+  R s = R(0), j[3] = {R(0), R(0), R(0)};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const R v = C::dec(*reinterpret_cast<const T*>(reinterpret_cast<const char*>(A + i * L.plane) + off), 1.0f);
+    s += v;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      if (kC[i][a]) j[a] += kC[i][a] > 0 ? v : -v;
+  }
+  const R ir = recip(R(L.rho0) + s);
+  m[0] = s;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) m[1 + a] = j[a] * ir;
+}
+
+// Node on the lattice's outer shell: pulls wrap across periodic faces; a
+// population whose source lies beyond an NSBC face is unknown and rebuilt.
+// Written to keep few values live (no equilibrium or copy arrays: rebuilt
+// populations are formed in place from their opposites), so that the sweep
+// that carries it keeps the occupancy of its interior path.
 template <int S>
 __device__ inline void boundary_node3(const Lat3& L, const typename Codec<S>::T* A, int x, int y, int z,
                                       typename Codec<S>::R g[Q]) {
   using C = Codec<S>;
+  using T = typename C::T;
   using R = typename C::R;
   const int n[3] = {L.nx, L.ny, L.nz}, p[3] = {x, y, z};
+  const uint32_t stride[3] = {1u, (uint32_t)L.pitch, (uint32_t)L.slab};
   uint32_t unknown = 0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    int s[3];
+    uint32_t src = 0;
     bool out = false;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      s[a] = p[a] - kC[i][a];
-      if (s[a] < 0 || s[a] >= n[a]) {
-        if (L.bc[2 * a] == BC_PERIODIC) s[a] = s[a] < 0 ? s[a] + n[a] : s[a] - n[a];
-        else out = true;
+      int s = p[a] - kC[i][a];
+      if (s < 0 || s >= n[a]) {
+        if (L.bc[2 * a] == BC_PERIODIC) {
+          s = s < 0 ? s + n[a] : s - n[a];
+        } else {
+          out = true;
+          s = p[a];  // any node in range: the value is replaced below
+        }
       }
+      src += (uint32_t)s * stride[a];
     }
-    if (out) {
-      unknown |= 1u << i;
-      g[i] = R(0);
-    } else {
-      g[i] = C::dec(A[i * L.plane + ((int64_t)s[2] * L.slab + (int64_t)s[1] * L.pitch + s[0])], 1.0f);
-    }
+    unknown |= (uint32_t)out << i;
+    g[i] = C::dec(*reinterpret_cast<const T*>(reinterpret_cast<const char*>(A + i * L.plane) + src * sizeof(T)),
+                  1.0f);
   }
   if (!unknown) return;
   // eq. nes_2 with the normalised normal of the k NSBC faces the node is on
-  const R rho0 = R(L.rho0);
+  const uint32_t own = ((uint32_t)z * stride[2] + (uint32_t)y * stride[1] + (uint32_t)x) * (uint32_t)sizeof(T);
   R mb[4], d[4] = {R(0), R(0), R(0), R(0)};
-  node_moments3<S>(L, A, x, y, z, mb);
+  node_moments3<S>(L, A, own, mb);
   int k = 0;
-#pragma unroll
+#pragma unroll 1
   for (int a = 0; a < 3; ++a) {
     if (L.bc[2 * a] != BC_NSBC) continue;
     const int step = p[a] == 0 ? 1 : (p[a] == n[a] - 1 ? -1 : 0);
     if (!step) continue;
-    int q[3] = {x, y, z};
-    q[a] += step;
     R mn[4];
-    node_moments3<S>(L, A, q[0], q[1], q[2], mn);
+    node_moments3<S>(L, A, own + (uint32_t)(step * (int)sizeof(T)) * stride[a], mn);
 #pragma unroll
     for (int c = 0; c < 4; ++c) d[c] += mb[c] - mn[c];
     ++k;
@@ -168,24 +193,30 @@ __device__ inline void boundary_node3(const Lat3& L, const typename Codec<S>::T*
   R mc[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) mc[c] = (R(1) - beta) * (mb[c] - fac * d[c]) + beta * R(L.m0[c]);  // eq. nes_3
-  // eqs. nes_0/nes_1, then eq. nes_4 with 1/c_s^2 = 3
-  R geq[Q];
-  equilibrium3<R>(rho0, mc, geq);
-  R gn[Q];
+  // eqs. nes_0/nes_1: f_i = f^eq_i + (f_o - f^eq_o) = f_o + 6 w_i rho_c (c_i . u_c) when the opposite o is
+  // known, f^eq_i(m_c) when it is not
+  const R rc = R(L.rho0) + mc[0];
+  const R uu = R(1.5) * (mc[1] * mc[1] + mc[2] * mc[2] + mc[3] * mc[3]);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const int o = (i == 0) ? 0 : (i & 1 ? i + 1 : i - 1);
-    gn[i] = (unknown >> i) & 1u ? ((unknown >> o) & 1u ? geq[i] : geq[i] + (g[o] - geq[o])) : g[i];
+  for (int i = 1; i < Q; ++i) {
+    if (!((unknown >> i) & 1u)) continue;
+    const int o = i & 1 ? i + 1 : i - 1;
+    R cu = R(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      if (kC[i][a]) cu += kC[i][a] > 0 ? mc[1 + a] : -mc[1 + a];
+    g[i] = (unknown >> o) & 1u ? w3<R>(i) * (mc[0] + rc * fma(cu, fma(R(4.5), cu, R(3)), -uu))
+                               : fma(R(6) * w3<R>(i) * rc, cu, g[o]);
   }
+  // eq. nes_4 with 1/c_s^2 = 3: shift all nineteen so the node carries m_c
   R s = R(0), j[3] = {R(0), R(0), R(0)};
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    s += gn[i];
+    s += g[i];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
-      if (kC[i][a]) j[a] += kC[i][a] > 0 ? gn[i] : -gn[i];
+      if (kC[i][a]) j[a] += kC[i][a] > 0 ? g[i] : -g[i];
   }
-  const R rc = rho0 + mc[0];
   const R dr = s - mc[0];
   R dj[3];
 #pragma unroll
@@ -196,7 +227,81 @@ __device__ inline void boundary_node3(const Lat3& L, const typename Codec<S>::T*
 #pragma unroll
     for (int a = 0; a < 3; ++a)
       if (kC[i][a]) cd += kC[i][a] > 0 ? dj[a] : -dj[a];
-    g[i] = gn[i] - w3<R>(i) * (dr + cd);
+    g[i] -= w3<R>(i) * (dr + cd);
+  }
+}
+
+// NSBC on an x face, for a node whose y and z neighbours all lie inside: `g`
+// holds its pulls with the unknown ones (c_x = side, side = +1 at x = 0 and
+// -1 at x = nx - 1) loaded from any node in range; mb and mn are the moments
+// at time t of the node and of its inner x neighbour.  Same arithmetic as
+// boundary_node3 with k = 1.
+template <int S>
+__device__ inline void xface_nsbc3(const Lat3& L, const typename Codec<S>::R mb[4],
+                                   const typename Codec<S>::R mn[4], int side, typename Codec<S>::R g[Q]) {
+  using R = typename Codec<S>::R;
+  const R fac = R(L.gamma), beta = R(L.beta);
+  R mc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) mc[c] = (R(1) - beta) * (mb[c] - fac * (mb[c] - mn[c])) + beta * R(L.m0[c]);
+  const R rc = R(L.rho0) + mc[0];
+#pragma unroll
+  for (int p = 1; p < Q; p += 2) {
+    if (!kC[p][0]) continue;
+    R cu = R(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      if (kC[p][a]) cu += kC[p][a] > 0 ? mc[1 + a] : -mc[1 + a];
+    const R t = R(6) * w3<R>(p) * rc;
+    const bool p_unknown = kC[p][0] == side;
+    const R gp = fma(t, cu, g[p + 1]), go = fma(t, -cu, g[p]);
+    g[p] = p_unknown ? gp : g[p];
+    g[p + 1] = p_unknown ? g[p + 1] : go;
+  }
+  R s = R(0), j[3] = {R(0), R(0), R(0)};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    s += g[i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      if (kC[i][a]) j[a] += kC[i][a] > 0 ? g[i] : -g[i];
+  }
+  const R dr = s - mc[0];
+  R dj[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) dj[a] = R(3) * (j[a] - rc * mc[1 + a]);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    R cd = R(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      if (kC[i][a]) cd += kC[i][a] > 0 ? dj[a] : -dj[a];
+    g[i] -= w3<R>(i) * (dr + cd);
+  }
+}
+
+// Register budget: the shell paths would otherwise take more registers than
+// the interior path and cost every node occupancy (6 waves per SIMD in FP32,
+// 4 in FP64 fit them without spills).
+template <int S>
+constexpr int k3_waves() {
+  return S == ST_F64 ? 4 : 6;
+}
+
+// Pulls of a node whose y and z neighbours all lie inside.  `idx` is its
+// element index; sxm and sxp are the byte shifts of the pulls with c_x = +1
+// (source x - 1) and c_x = -1 (source x + 1).
+template <int S>
+__device__ __forceinline__ void pull_row3(const Lat3& L, const typename Codec<S>::T* A, uint32_t idx, int sxm,
+                                          int sxp, typename Codec<S>::R g[Q]) {
+  using C = Codec<S>;
+  using T = typename C::T;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const char* Ai = reinterpret_cast<const char*>(A + i * L.plane);
+    const uint32_t row = (idx - (uint32_t)(kC[i][2] * L.slab + kC[i][1] * L.pitch)) * (uint32_t)sizeof(T);
+    const int sh = kC[i][0] > 0 ? sxm : (kC[i][0] < 0 ? sxp : 0);
+    g[i] = C::dec(*reinterpret_cast<const T*>(Ai + (row + (uint32_t)sh)), 1.0f);
   }
 }
 
@@ -204,9 +309,19 @@ __device__ inline void boundary_node3(const Lat3& L, const typename Codec<S>::T*
 // list of (z chunk, tile row, tile column) in that order, so XCD k (blocks
 // b = k mod 8) works through the k-th contiguous stretch: x-neighbouring
 // tiles, which share the lines their shifted pulls straddle, run on one XCD.
+// Tile rows on a y or z face take boundary_node3 (whole wavefronts, as a
+// wavefront is a run of x).  In the other rows an x-face node is one lane of
+// a wavefront: it pulls with the others (the x shift adjusted), and on a NSBC
+// face it takes the moments at time t of itself and of its inner neighbour
+// from Lat3::mx instead of loading 38 stored populations (BGK conserves mass
+// and momentum, so the moments the collision of the previous step computed
+// are those of the populations it stored).  Every x-face lane and its inner
+// neighbour lane write their moments for the next step.  Nodes with y and z
+// inside are written by the wavefront that holds their whole row segment:
+// no cache line of the output is written in parts by different blocks.
 template <int S, int BX, int BY, int ZC>
-__global__ __launch_bounds__(BX* BY) void k3_step(Lat3 L, int parity, int tiles_x, int tiles_y, int nitems,
-                                                  int per) {
+__global__ __launch_bounds__(BX* BY, k3_waves<S>()) void k3_step(Lat3 L, int parity, int tiles_x, int tiles_y,
+                                                                int nitems, int per) {
   using C = Codec<S>;
   using T = typename C::T;
   using R = typename C::R;
@@ -221,29 +336,58 @@ __global__ __launch_bounds__(BX* BY) void k3_step(Lat3 L, int parity, int tiles_
   if (x >= nx || y >= ny) return;
   const T* __restrict__ A = static_cast<const T*>(parity ? L.buf[1] : L.buf[0]);
   T* __restrict__ B = static_cast<T*>(parity ? L.buf[0] : L.buf[1]);
-  const int pitch = L.pitch;
-  const int64_t slab = L.slab, plane = L.plane;
+  const T* __restrict__ MA = static_cast<const T*>(parity ? L.mx[1] : L.mx[0]);
+  T* __restrict__ MB = static_cast<T*>(parity ? L.mx[0] : L.mx[1]);
   const R rho0 = R(L.rho0), omega = R(L.omega);
-  const bool xy_inner = x >= 1 && x <= nx - 2 && y >= 1 && y <= ny - 2;
+  const bool y_inner = y >= 1 && y <= ny - 2;
+  // Byte shifts of the pulls with c_x = +1 (source x - 1) and c_x = -1
+  // (source x + 1).  Beyond an x face the source wraps (periodic) or is a node
+  // in range whose value xface_nsbc3 replaces (NSBC).
+  const bool xper = L.bc[0] == BC_PERIODIC;
+  const int sxm = (x > 0 ? -1 : (xper ? nx - 1 : 0)) * (int)sizeof(T);
+  const int sxp = (x < nx - 1 ? 1 : (xper ? 1 - nx : 0)) * (int)sizeof(T);
+  const int xside = xper ? 0 : (x == 0 ? 1 : (x == nx - 1 ? -1 : 0));
+  // does this lane write slots of Lat3::mx (x = 0, 1, nx - 2, nx - 1)?
+  const bool mwrite = !xper && (x <= 1 || x >= nx - 2);
+  const uint32_t mxs = (uint32_t)L.mxs;
   const int z1 = min(nz, (zc + 1) * ZC);
   for (int z = zc * ZC; z < z1; ++z) {
     R g[Q];
-    if (xy_inner && z >= 1 && z <= nz - 2) {
-      const uint32_t idx = (uint32_t)((int64_t)z * slab + (int64_t)y * pitch + x);
+    const uint32_t idx = (uint32_t)((int64_t)z * L.slab + (int64_t)y * L.pitch + x);
+    const bool inner_row = y_inner && z >= 1 && z <= nz - 2;
+    if (inner_row) {
+      pull_row3<S>(L, A, idx, sxm, sxp, g);
+      if (xside) {
+        const uint32_t mo = (uint32_t)z * (uint32_t)ny + (uint32_t)y;
+        const T* Mb = MA + (x == 0 ? 0 : 8 * mxs);  // slots 0, 1 (x = 0) or 2, 3
+        R mb[4], mn[4];
 #pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const char* Ai = reinterpret_cast<const char*>(A + i * plane);
-        const uint32_t row = (idx - (uint32_t)(kC[i][2] * slab + kC[i][1] * pitch)) * (uint32_t)sizeof(T);
-        g[i] = C::dec(*reinterpret_cast<const T*>(Ai + row - kC[i][0] * (int)sizeof(T)), 1.0f);
+        for (int c = 0; c < 4; ++c) {
+          mb[c] = R(Mb[c * mxs + mo]);
+          mn[c] = R(Mb[(4 + c) * mxs + mo]);
+        }
+        xface_nsbc3<S>(L, mb, mn, xside, g);
       }
     } else {
       boundary_node3<S>(L, A, x, y, z, g);
     }
-    bgk3<R>(g, rho0, omega);
-    const uint32_t off = (uint32_t)((int64_t)z * slab + (int64_t)y * pitch + x) * (uint32_t)sizeof(T);
+    R m[4];
+    bgk3<R>(g, rho0, omega, m);
+    if (inner_row && mwrite) {
+      // slot 0: x = 0, 1: x = 1, 2: x = nx - 1, 3: x = nx - 2 (both 1 and 3 when nx = 3)
+      const uint32_t mo = (uint32_t)z * (uint32_t)ny + (uint32_t)y;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (x == 0) MB[c * mxs + mo] = T(m[c]);
+        if (x == 1) MB[(4 + c) * mxs + mo] = T(m[c]);
+        if (x == nx - 1) MB[(8 + c) * mxs + mo] = T(m[c]);
+        if (x == nx - 2) MB[(12 + c) * mxs + mo] = T(m[c]);
+      }
+    }
+    const uint32_t off = idx * (uint32_t)sizeof(T);
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-      __builtin_nontemporal_store(C::enc(g[i], 1.0f), reinterpret_cast<T*>(reinterpret_cast<char*>(B + i * plane) + off));
+      __builtin_nontemporal_store(C::enc(g[i], 1.0f), reinterpret_cast<T*>(reinterpret_cast<char*>(B + i * L.plane) + off));
   }
 }
 
@@ -303,6 +447,23 @@ __global__ void k3_init(Lat3 L, const double* __restrict__ drho, const double* _
   const int64_t idx = (int64_t)z * L.slab + (int64_t)y * L.pitch + x;
 #pragma unroll
   for (int i = 0; i < Q; ++i) B[i * L.plane + idx] = (T)geq[i];
+  // moments of the stored populations for the x-face slots of Lat3::mx
+  const int nx = L.nx;
+  if (x > 1 && x < nx - 2) return;
+  using R = typename Codec<S>::R;
+  R g[Q], ms[4];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) g[i] = R((T)geq[i]);
+  moments3<R>(g, R(L.rho0), ms);
+  T* M = static_cast<T*>(L.mx[0]);
+  const int64_t mo = (int64_t)z * L.ny + y;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (x == 0) M[(0 * 4 + c) * L.mxs + mo] = T(ms[c]);
+    if (x == 1) M[(1 * 4 + c) * L.mxs + mo] = T(ms[c]);
+    if (x == nx - 2) M[(3 * 4 + c) * L.mxs + mo] = T(ms[c]);
+    if (x == nx - 1) M[(2 * 4 + c) * L.mxs + mo] = T(ms[c]);
+  }
 }
 
 template <int S>
@@ -312,7 +473,8 @@ __global__ void k3_moments(Lat3 L, int parity, double* __restrict__ out) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
   if (x >= L.nx) return;
   R m[4];
-  node_moments3<S>(L, static_cast<const T*>(parity ? L.buf[1] : L.buf[0]), x, y, z, m);
+  const uint32_t off = (uint32_t)((int64_t)z * L.slab + (int64_t)y * L.pitch + x) * (uint32_t)sizeof(T);
+  node_moments3<S>(L, static_cast<const T*>(parity ? L.buf[1] : L.buf[0]), off, m);
   const int64_t n = (int64_t)L.nx * L.ny * L.nz, k = ((int64_t)z * L.ny + y) * L.nx + x;
 #pragma unroll
   for (int c = 0; c < 4; ++c) out[c * n + k] = (double)m[c];
@@ -344,13 +506,20 @@ struct Layout3 {
   size_t esize;
   int32_t pitch;
   int64_t slab, plane;
-  size_t buf_bytes, total;
+  size_t buf_bytes, mx_bytes, total;
 };
 
 int check3(const lbm3d_params* p) {
   if (!p) return fail(LBM_ERR_ARG, "params is NULL");
   if (p->nx < 3 || p->ny < 3 || p->nz < 3) return fail(LBM_ERR_ARG, "lattice %dx%dx%d: each side must be >= 3", p->nx, p->ny, p->nz);
   if ((int64_t)p->nx * p->ny * p->nz > (int64_t)1 << 28) return fail(LBM_ERR_ARG, "lattice exceeds 2^28 nodes");
+  {
+    // the kernels address a plane with 32-bit byte offsets
+    const int64_t row = ((int64_t)p->nx * (p->store == LBM_STORE_F64 ? 8 : 4) + 255) / 256 * 256;
+    if (row * p->ny * p->nz > ((int64_t)1 << 32) - 65536)
+      return fail(LBM_ERR_ARG, "lattice %dx%dx%d: a plane with rows padded to 256 bytes exceeds 4 GiB", p->nx,
+                  p->ny, p->nz);
+  }
   if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_ERR_ARG, "tau = %g: BGK needs tau > 0.5", p->tau);
   if (!(p->rho0 > 0) || !std::isfinite(p->rho0)) return fail(LBM_ERR_ARG, "rho0 = %g must be > 0", p->rho0);
   for (int f = 0; f < 6; ++f)
@@ -376,7 +545,8 @@ Layout3 layout3(const lbm3d_params* p) {
   if (plane_bytes % 65536 == 0) plane_bytes += 4096;  // planes not a large power of two apart
   l.plane = (int64_t)(plane_bytes / l.esize);
   l.buf_bytes = round_up(19 * plane_bytes, (size_t)2 << 20);
-  l.total = 2 * l.buf_bytes;
+  l.mx_bytes = round_up((size_t)16 * p->ny * p->nz * l.esize, 4096);
+  l.total = 2 * l.buf_bytes + 2 * l.mx_bytes;
   return l;
 }
 
@@ -419,6 +589,9 @@ int lbm3d_init(lbm3d_ctx** out, const lbm3d_params* p, void* workspace, size_t b
   std::memset(&L, 0, sizeof(L));
   L.buf[0] = workspace;
   L.buf[1] = static_cast<char*>(workspace) + lay.buf_bytes;
+  L.mx[0] = static_cast<char*>(workspace) + 2 * lay.buf_bytes;
+  L.mx[1] = static_cast<char*>(workspace) + 2 * lay.buf_bytes + lay.mx_bytes;
+  L.mxs = (int64_t)p->ny * p->nz;
   L.nx = p->nx;
   L.ny = p->ny;
   L.nz = p->nz;
