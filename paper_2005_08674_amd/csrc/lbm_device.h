@@ -75,11 +75,8 @@ template <> struct Codec<ST_BF16> {
     return __uint_as_float(static_cast<uint32_t>(v) << 16) * s;
   }
   __device__ static inline T enc(R v, float s) {
-    // round to nearest, ties to even, on the top 16 bits of the fp32 pattern
-    uint32_t u = __float_as_uint(v * s);
-    if ((u & 0x7f800000u) == 0x7f800000u) return static_cast<T>((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return static_cast<T>(u >> 16);
+    // round to nearest, ties to even (one v_cvt_pk_bf16_f32 on gfx950)
+    return __builtin_bit_cast(T, static_cast<__bf16>(v * s));
   }
 };
 
