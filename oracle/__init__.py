@@ -210,7 +210,7 @@ class Orc3Params(ctypes.Structure):
                 ("tau", ctypes.c_double), ("rho0", ctypes.c_double),
                 ("bc", ctypes.c_int * 6),
                 ("gamma", ctypes.c_double), ("beta", ctypes.c_double),
-                ("m0", ctypes.c_double * 4)]
+                ("m0", ctypes.c_double * 4), ("q", ctypes.c_int)]
 
 
 _handles3: dict = {}
@@ -224,9 +224,10 @@ def _lib3(kind: str = "double"):
         build()
     lib = ctypes.CDLL(LIBS[key])
     P = ctypes.c_void_p
-    for name, args in [("orc3_lattice", [P, P, P]), ("orc3_feq", [ctypes.c_double, P, P]),
-                       ("orc3_collide_node", [ctypes.c_double, ctypes.c_double, P, P]),
-                       ("orc3_moments_node", [ctypes.c_double, P, P]),
+    I = ctypes.c_int
+    for name, args in [("orc3_lattice", [I, P, P, P]), ("orc3_feq", [I, ctypes.c_double, P, P]),
+                       ("orc3_collide_node", [I, ctypes.c_double, ctypes.c_double, P, P]),
+                       ("orc3_moments_node", [I, ctypes.c_double, P, P]),
                        ("orc3_init", [P, P, P, P, P, P]), ("orc3_moments", [P, P, P]),
                        ("orc3_step", [P, P, ctypes.c_int])]:
         f = getattr(lib, name)
@@ -236,42 +237,49 @@ def _lib3(kind: str = "double"):
     return lib
 
 
-def lattice_constants_3d(kind: str = "double"):
-    """(c [19][3], w [19], opp [19]) of the oracle's D3Q19 lattice."""
-    c = np.zeros((19, 3), np.int32)
-    w = np.zeros(19, _dtype(kind))
-    opp = np.zeros(19, np.int32)
-    _lib3(kind).orc3_lattice(_ptr(c), _ptr(w), _ptr(opp))
+def lattice_constants_3d(kind: str = "double", q: int = 19):
+    """(c [q][3], w [q], opp [q]) of the oracle's D3Q19 (q = 19) or D3Q27 (q = 27) lattice."""
+    c = np.zeros((q, 3), np.int32)
+    w = np.zeros(q, _dtype(kind))
+    opp = np.zeros(q, np.int32)
+    if _lib3(kind).orc3_lattice(int(q), _ptr(c), _ptr(w), _ptr(opp)) != 0:
+        raise ValueError(f"no {q}-velocity set")
     return c, w, opp
 
 
-def feq_3d(rho0, m4, kind: str = "double") -> np.ndarray:
+def feq_3d(rho0, m4, kind: str = "double", q: int = 19) -> np.ndarray:
     m = np.ascontiguousarray(m4, dtype=np.float64)
-    out = np.zeros(19, _dtype(kind))
-    _lib3(kind).orc3_feq(float(rho0), _ptr(m), _ptr(out))
+    out = np.zeros(q, _dtype(kind))
+    if _lib3(kind).orc3_feq(int(q), float(rho0), _ptr(m), _ptr(out)) != 0:
+        raise ValueError(f"no {q}-velocity set")
     return out
 
 
-def collide_node_3d(tau, rho0, g19, kind: str = "double") -> np.ndarray:
-    g19 = np.ascontiguousarray(g19, dtype=_dtype(kind))
-    out = np.zeros(19, _dtype(kind))
-    _lib3(kind).orc3_collide_node(float(tau), float(rho0), _ptr(g19), _ptr(out))
+def collide_node_3d(tau, rho0, g, kind: str = "double") -> np.ndarray:
+    """BGK of one node; the velocity set is len(g) (19 or 27)."""
+    g = np.ascontiguousarray(g, dtype=_dtype(kind))
+    out = np.zeros(len(g), _dtype(kind))
+    if _lib3(kind).orc3_collide_node(len(g), float(tau), float(rho0), _ptr(g), _ptr(out)) != 0:
+        raise ValueError(f"no {len(g)}-velocity set")
     return out
 
 
-def moments_node_3d(rho0, g19, kind: str = "double") -> np.ndarray:
-    g19 = np.ascontiguousarray(g19, dtype=_dtype(kind))
+def moments_node_3d(rho0, g, kind: str = "double") -> np.ndarray:
+    """(rho - rho0, ux, uy, uz) of one node; the velocity set is len(g)."""
+    g = np.ascontiguousarray(g, dtype=_dtype(kind))
     out = np.zeros(4, _dtype(kind))
-    _lib3(kind).orc3_moments_node(float(rho0), _ptr(g19), _ptr(out))
+    if _lib3(kind).orc3_moments_node(len(g), float(rho0), _ptr(g), _ptr(out)) != 0:
+        raise ValueError(f"no {len(g)}-velocity set")
     return out
 
 
 class Lattice3D:
-    """One D3Q19 lattice advanced by the oracle.  ``bc`` = (x low, x high, y low, y high, z low, z high),
-    each BC_PERIODIC or BC_NSBC.  Fields are [nz][ny][nx] arrays; ``drho`` is rho - rho0."""
+    """One D3Q19 (q = 19) or D3Q27 (q = 27) lattice advanced by the oracle.  ``bc`` = (x low, x high,
+    y low, y high, z low, z high), each BC_PERIODIC or BC_NSBC.  Fields are [nz][ny][nx] arrays;
+    ``drho`` is rho - rho0."""
 
     def __init__(self, nx, ny, nz, tau, drho, ux, uy, uz, rho0=1.0, bc=(1, 1, 1, 1, 1, 1), gamma=0.6, beta=0.0,
-                 m0=(1.0, 0.0, 0.0, 0.0), kind: str = "double"):
+                 m0=(1.0, 0.0, 0.0, 0.0), kind: str = "double", q: int = 19):
         self.kind = kind
         self.lib = _lib3(kind)
         p = Orc3Params()
@@ -281,11 +289,13 @@ class Lattice3D:
         p.gamma, p.beta = float(gamma), float(beta)
         for a in range(4):
             p.m0[a] = float(m0[a])
+        p.q = int(q)
+        self.q = int(q)
         self.p = p
         self.shape = (int(nz), int(ny), int(nx))
         self.rho0 = float(rho0)
         self.t = 0
-        self.g = np.zeros((19,) + self.shape, _dtype(kind))
+        self.g = np.zeros((self.q,) + self.shape, _dtype(kind))
         f = [np.ascontiguousarray(a, dtype=np.float64).reshape(self.shape) for a in (drho, ux, uy, uz)]
         if self.lib.orc3_init(ctypes.byref(p), _ptr(f[0]), _ptr(f[1]), _ptr(f[2]), _ptr(f[3]), _ptr(self.g)) != 0:
             raise ValueError("oracle rejected the lattice parameters")

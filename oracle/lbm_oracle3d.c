@@ -1,8 +1,8 @@
 /*
- * lbm_oracle3d.c -- plain, slow CPU oracle for the D3Q19 BGK lattice
- * Boltzmann method with the Non-equilibrium Symmetry Boundary Condition
- * (NSBC) of Euser & Vuik (arXiv 2005.08674), carried from the paper's D2Q9
- * setting (Secs. 3 and 5) to three dimensions.
+ * lbm_oracle3d.c -- plain, slow CPU oracle for the D3Q19 and D3Q27 BGK
+ * lattice Boltzmann method with the Non-equilibrium Symmetry Boundary
+ * Condition (NSBC) of Euser & Vuik (arXiv 2005.08674), carried from the
+ * paper's D2Q9 setting (Secs. 3 and 5) to three dimensions.
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
  * call this file; only the test-suite and the benchmark's CPU baseline use
@@ -11,10 +11,14 @@
  * Arithmetic type `real`: double, or x87 extended precision with
  * -DORC_LONG_DOUBLE.
  *
- * Lattice (D3Q19): c_0 = 0 (w 1/3); the six axis directions (w 1/18) in the
- * order +x, -x, +y, -y, +z, -z; the twelve face diagonals (w 1/36) in
+ * Lattices: D3Q19 is c_0 = 0 (w 1/3); the six axis directions (w 1/18) in
+ * the order +x, -x, +y, -y, +z, -z; the twelve face diagonals (w 1/36) in
  * opposite pairs (1,1,0), (-1,-1,0), (1,-1,0), (-1,1,0), (1,0,1), (-1,0,-1),
- * (1,0,-1), (-1,0,1), (0,1,1), (0,-1,-1), (0,1,-1), (0,-1,1).  c_s^2 = 1/3.
+ * (1,0,-1), (-1,0,1), (0,1,1), (0,-1,-1), (0,1,-1), (0,-1,1).  D3Q27 is the
+ * same 19 directions followed by the eight cube diagonals in opposite pairs
+ * (1,1,1), (-1,-1,-1), (1,1,-1), (-1,-1,1), (1,-1,1), (-1,1,-1), (-1,1,1),
+ * (1,-1,-1), with weights 8/27, 2/27, 1/54 and 1/216 by |c|^2 = 0, 1, 2, 3.
+ * c_s^2 = 1/3 for both.  Each lattice carries its own q (19 or 27).
  *
  * State: the PRE-collision deviation g_i = f_i - w_i rho0, layout
  * g[i][z][y][x] (x fastest).  One step, in the paper's order:
@@ -41,22 +45,31 @@ typedef long double real;
 typedef double real;
 #endif
 
-#define Q 19
+#define QMAX 27
 
-static const int CX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
-static const int CY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
-static const int CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+static const int CX[QMAX] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0,
+                             1, -1, 1, -1, 1, -1, -1, 1};
+static const int CY[QMAX] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1,
+                             1, -1, 1, -1, -1, 1, 1, -1};
+static const int CZ[QMAX] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1,
+                             1, -1, -1, 1, 1, -1, 1, -1};
 
-/* weight from |c|^2: 0 -> 1/3, 1 -> 1/18, 2 -> 1/36 */
-static real weight(int i) {
+/* weight from |c|^2: D3Q19 1/3, 1/18, 1/36; D3Q27 8/27, 2/27, 1/54, 1/216 */
+static real weight(int q, int i) {
     int c2 = CX[i] * CX[i] + CY[i] * CY[i] + CZ[i] * CZ[i];
-    if (c2 == 0) return (real)1 / (real)3;
-    if (c2 == 1) return (real)1 / (real)18;
-    return (real)1 / (real)36;
+    if (q == 19) {
+        if (c2 == 0) return (real)1 / (real)3;
+        if (c2 == 1) return (real)1 / (real)18;
+        return (real)1 / (real)36;
+    }
+    if (c2 == 0) return (real)8 / (real)27;
+    if (c2 == 1) return (real)2 / (real)27;
+    if (c2 == 2) return (real)1 / (real)54;
+    return (real)1 / (real)216;
 }
 
-static int opposite(int i) {
-    for (int j = 0; j < Q; ++j)
+static int opposite(int q, int i) {
+    for (int j = 0; j < q; ++j)
         if (CX[j] == -CX[i] && CY[j] == -CY[i] && CZ[j] == -CZ[i]) return j;
     return -1;
 }
@@ -67,13 +80,14 @@ typedef struct {
     int bc[6];            /* 0 periodic, 1 NSBC: [x=0, x=nx-1, y=0, y=ny-1, z=0, z=nz-1] */
     double gamma, beta;
     double m0[4];         /* far-field vector (rho, ux, uy, uz) */
+    int q;                /* velocity set: 19 or 27 */
 } orc3_params;
 
 static const real CS2 = (real)1 / (real)3;
 
-static void node_moments(const real g[Q], real rho0, real m[4]) {
+static void node_moments(int q, const real *g, real rho0, real m[4]) {
     real s = 0, j[3] = {0, 0, 0};
-    for (int i = 0; i < Q; ++i) {
+    for (int i = 0; i < q; ++i) {
         s += g[i];
         j[0] += (real)CX[i] * g[i];
         j[1] += (real)CY[i] * g[i];
@@ -85,24 +99,25 @@ static void node_moments(const real g[Q], real rho0, real m[4]) {
 }
 
 /* eq. feq_1 minus w_i rho0 */
-static void equilibrium(real rho0, const real m[4], real geq[Q]) {
+static void equilibrium(int q, real rho0, const real m[4], real *geq) {
     real rho = rho0 + m[0];
     real uu = m[1] * m[1] + m[2] * m[2] + m[3] * m[3];
-    for (int i = 0; i < Q; ++i) {
+    for (int i = 0; i < q; ++i) {
         real cu = (real)CX[i] * m[1] + (real)CY[i] * m[2] + (real)CZ[i] * m[3];
-        geq[i] = weight(i) * (m[0] + rho * (cu / CS2 + cu * cu / (2 * CS2 * CS2) - uu / (2 * CS2)));
+        geq[i] = weight(q, i) * (m[0] + rho * (cu / CS2 + cu * cu / (2 * CS2 * CS2) - uu / (2 * CS2)));
     }
 }
 
-static void collide(real tau, real rho0, const real g[Q], real out[Q]) {
-    real m[4], geq[Q];
-    node_moments(g, rho0, m);
-    equilibrium(rho0, m, geq);
-    for (int i = 0; i < Q; ++i) out[i] = g[i] - (g[i] - geq[i]) / tau;
+static void collide(int q, real tau, real rho0, const real *g, real *out) {
+    real m[4], geq[QMAX];
+    node_moments(q, g, rho0, m);
+    equilibrium(q, rho0, m, geq);
+    for (int i = 0; i < q; ++i) out[i] = g[i] - (g[i] - geq[i]) / tau;
 }
 
 static int check_params(const orc3_params *p) {
     if (!p || p->nx < 3 || p->ny < 3 || p->nz < 3) return -1;
+    if (p->q != 19 && p->q != 27) return -1;
     if (!(p->tau > 0.5)) return -1;
     for (int f = 0; f < 6; ++f)
         if (p->bc[f] != 0 && p->bc[f] != 1) return -1;
@@ -115,30 +130,35 @@ static int wrap(int v, int n) { return ((v % n) + n) % n; }
 
 /* ---------------------------------------------------------------- node API */
 
-int orc3_lattice(int *c57, real *w19, int *opp19) {
-    for (int i = 0; i < Q; ++i) {
-        c57[3 * i] = CX[i];
-        c57[3 * i + 1] = CY[i];
-        c57[3 * i + 2] = CZ[i];
-        w19[i] = weight(i);
-        opp19[i] = opposite(i);
+/* Node functions take the velocity set q (19 or 27) and arrays of q values. */
+int orc3_lattice(int q, int *c, real *w, int *opp) {
+    if (q != 19 && q != 27) return -1;
+    for (int i = 0; i < q; ++i) {
+        c[3 * i] = CX[i];
+        c[3 * i + 1] = CY[i];
+        c[3 * i + 2] = CZ[i];
+        w[i] = weight(q, i);
+        opp[i] = opposite(q, i);
     }
     return 0;
 }
 
-int orc3_feq(double rho0, const double *m4, real *out19) {
+int orc3_feq(int q, double rho0, const double *m4, real *out) {
+    if (q != 19 && q != 27) return -1;
     real m[4] = {(real)m4[0], (real)m4[1], (real)m4[2], (real)m4[3]};
-    equilibrium((real)rho0, m, out19);
+    equilibrium(q, (real)rho0, m, out);
     return 0;
 }
 
-int orc3_collide_node(double tau, double rho0, const real *g19, real *out19) {
-    collide((real)tau, (real)rho0, g19, out19);
+int orc3_collide_node(int q, double tau, double rho0, const real *g, real *out) {
+    if (q != 19 && q != 27) return -1;
+    collide(q, (real)tau, (real)rho0, g, out);
     return 0;
 }
 
-int orc3_moments_node(double rho0, const real *g19, real *out4) {
-    node_moments(g19, (real)rho0, out4);
+int orc3_moments_node(int q, double rho0, const real *g, real *out4) {
+    if (q != 19 && q != 27) return -1;
+    node_moments(q, g, (real)rho0, out4);
     return 0;
 }
 
@@ -149,9 +169,9 @@ int orc3_init(const orc3_params *p, const double *drho, const double *ux, const 
     if (check_params(p)) return -1;
     const size_t n = (size_t)p->nx * p->ny * p->nz;
     for (size_t k = 0; k < n; ++k) {
-        real m[4] = {(real)drho[k], (real)ux[k], (real)uy[k], (real)uz[k]}, geq[Q];
-        equilibrium((real)p->rho0, m, geq);
-        for (int i = 0; i < Q; ++i) g[(size_t)i * n + k] = geq[i];
+        real m[4] = {(real)drho[k], (real)ux[k], (real)uy[k], (real)uz[k]}, geq[QMAX];
+        equilibrium(p->q, (real)p->rho0, m, geq);
+        for (int i = 0; i < p->q; ++i) g[(size_t)i * n + k] = geq[i];
     }
     return 0;
 }
@@ -160,9 +180,9 @@ int orc3_moments(const orc3_params *p, const real *g, double *out /* [4][n] */) 
     if (check_params(p)) return -1;
     const size_t n = (size_t)p->nx * p->ny * p->nz;
     for (size_t k = 0; k < n; ++k) {
-        real gn[Q], m[4];
-        for (int i = 0; i < Q; ++i) gn[i] = g[(size_t)i * n + k];
-        node_moments(gn, (real)p->rho0, m);
+        real gn[QMAX], m[4];
+        for (int i = 0; i < p->q; ++i) gn[i] = g[(size_t)i * n + k];
+        node_moments(p->q, gn, (real)p->rho0, m);
         for (int a = 0; a < 4; ++a) out[(size_t)a * n + k] = (double)m[a];
     }
     return 0;
@@ -179,31 +199,31 @@ static int is_unknown(const orc3_params *p, int x, int y, int z, int i) {
 
 int orc3_step(const orc3_params *p, real *g, int nsteps) {
     if (check_params(p) || nsteps < 0) return -1;
-    const int nx = p->nx, ny = p->ny, nz = p->nz;
+    const int nx = p->nx, ny = p->ny, nz = p->nz, q = p->q;
     const size_t n = (size_t)nx * ny * nz;
     const real rho0 = (real)p->rho0, tau = (real)p->tau;
     const real gamma = (real)p->gamma, beta = (real)p->beta;
     const real m0[4] = {(real)p->m0[0] - rho0, (real)p->m0[1], (real)p->m0[2], (real)p->m0[3]};
     real *mom = malloc(4 * n * sizeof(real));
-    real *post = malloc(Q * n * sizeof(real));
+    real *post = malloc((size_t)q * n * sizeof(real));
     if (!mom || !post) {
         free(mom);
         free(post);
         return -2;
     }
-    int opp[Q];
-    for (int i = 0; i < Q; ++i) opp[i] = opposite(i);
+    int opp[QMAX];
+    for (int i = 0; i < q; ++i) opp[i] = opposite(q, i);
 
     for (int step = 0; step < nsteps; ++step) {
         /* 1 + 2: moments and collision */
 #pragma omp parallel for schedule(static)
         for (size_t k = 0; k < n; ++k) {
-            real gn[Q], gs[Q], m[4];
-            for (int i = 0; i < Q; ++i) gn[i] = g[(size_t)i * n + k];
-            node_moments(gn, rho0, m);
+            real gn[QMAX], gs[QMAX], m[4];
+            for (int i = 0; i < q; ++i) gn[i] = g[(size_t)i * n + k];
+            node_moments(q, gn, rho0, m);
             for (int a = 0; a < 4; ++a) mom[(size_t)a * n + k] = m[a];
-            collide(tau, rho0, gn, gs);
-            for (int i = 0; i < Q; ++i) post[(size_t)i * n + k] = gs[i];
+            collide(q, tau, rho0, gn, gs);
+            for (int i = 0; i < q; ++i) post[(size_t)i * n + k] = gs[i];
         }
         /* 3: pull streaming; unknown populations are NaN until the boundary step */
 #pragma omp parallel for schedule(static)
@@ -211,7 +231,7 @@ int orc3_step(const orc3_params *p, real *g, int nsteps) {
             for (int y = 0; y < ny; ++y)
                 for (int x = 0; x < nx; ++x) {
                     size_t k = ((size_t)z * ny + y) * nx + x;
-                    for (int i = 0; i < Q; ++i) {
+                    for (int i = 0; i < q; ++i) {
                         if (is_unknown(p, x, y, z, i)) {
                             g[(size_t)i * n + k] = (real)NAN;
                             continue;
@@ -250,21 +270,21 @@ int orc3_step(const orc3_params *p, real *g, int nsteps) {
                         real mp = mb - fac * d;                 /* eq. nes_2 */
                         mc[a] = (1 - beta) * mp + beta * m0[a]; /* eq. nes_3 */
                     }
-                    real gn[Q], geq[Q];
-                    int unk[Q];
-                    for (int i = 0; i < Q; ++i) {
+                    real gn[QMAX], geq[QMAX];
+                    int unk[QMAX];
+                    for (int i = 0; i < q; ++i) {
                         gn[i] = g[(size_t)i * n + kb];
                         unk[i] = is_unknown(p, x, y, z, i);
                     }
-                    equilibrium(rho0, mc, geq);
-                    for (int i = 0; i < Q; ++i) {
+                    equilibrium(q, rho0, mc, geq);
+                    for (int i = 0; i < q; ++i) {
                         if (!unk[i]) continue;
                         int o = opp[i];
                         gn[i] = unk[o] ? geq[i] : geq[i] + (gn[o] - geq[o]); /* eqs. nes_0, nes_1 */
                     }
                     /* eq. nes_4, shift with 1/c_s^2 so the node carries m_c */
                     real s = 0, j[3] = {0, 0, 0};
-                    for (int i = 0; i < Q; ++i) {
+                    for (int i = 0; i < q; ++i) {
                         s += gn[i];
                         j[0] += (real)CX[i] * gn[i];
                         j[1] += (real)CY[i] * gn[i];
@@ -273,9 +293,9 @@ int orc3_step(const orc3_params *p, real *g, int nsteps) {
                     real rc = rho0 + mc[0];
                     real dr = s - mc[0];
                     real dj[3] = {j[0] - rc * mc[1], j[1] - rc * mc[2], j[2] - rc * mc[3]};
-                    for (int i = 0; i < Q; ++i)
-                        gn[i] -= weight(i) * (dr + ((real)CX[i] * dj[0] + (real)CY[i] * dj[1] + (real)CZ[i] * dj[2]) / CS2);
-                    for (int i = 0; i < Q; ++i) g[(size_t)i * n + kb] = gn[i];
+                    for (int i = 0; i < q; ++i)
+                        gn[i] -= weight(q, i) * (dr + ((real)CX[i] * dj[0] + (real)CY[i] * dj[1] + (real)CZ[i] * dj[2]) / CS2);
+                    for (int i = 0; i < q; ++i) g[(size_t)i * n + kb] = gn[i];
                 }
     }
     free(mom);
