@@ -254,18 +254,19 @@ def run_tc2(torch, W, every=50):
     return out
 
 
-def run_3d(torch, W, steps, n=256):
-    """The D3Q19 sweep on an n^3 lattice (8 seeded pulses, tau 0.55, NSBC on all six faces), FP32 and
-    FP64 storage: MLUPS over `steps` steps in one timed region after the shape autotuner, and the
-    algorithmic-bytes fraction of the HBM peak (2 x 19 x s bytes per node-step, one launch per step)."""
+def run_3d(torch, W, steps, n=256, q=19):
+    """The D3Q19 (q = 19) or D3Q27 (q = 27) sweep on an n^3 lattice (8 seeded pulses, tau 0.55, NSBC on all
+    six faces), FP32 and FP64 storage: MLUPS over `steps` steps in one timed region after the shape
+    autotuner, and the algorithmic-bytes fraction of the HBM peak (2 x q x s bytes per node-step, one
+    launch per step)."""
     from paper_2005_08674_amd import lbm
     from paper_2005_08674_amd.lattice3d import Lattice3D
 
     fields, _ = W.pulses_3d(n)
-    out = {"workload": f"pulses3d{n}: {n}^3 D3Q19 BGK tau 0.55, 8 seeded Gaussian pulses, NSBC (gamma 0.6, "
+    out = {"workload": f"pulses3d{n}: {n}^3 D3Q{q} BGK tau 0.55, 8 seeded Gaussian pulses, NSBC (gamma 0.6, "
                        "beta 0) on 6 faces", "steps": steps}
     for store, s in (("f32", 4), ("f64", 8)):
-        lat = Lattice3D(n, n, n, 0.55, fields, store=store)
+        lat = Lattice3D(n, n, n, 0.55, fields, store=store, q=q)
         best, times = lat.autotune(reps=5)
         lat.step(10)
         torch.cuda.synchronize()
@@ -277,11 +278,11 @@ def run_3d(torch, W, steps, n=256):
         ms = a.elapsed_time(b) / steps
         ok = all(np.isfinite(m).all() for m in lat.moments())
         lat.close()
-        gbs = 2 * 19 * s * n ** 3 / (ms * 1e-3) / 1e9
+        gbs = 2 * q * s * n ** 3 / (ms * 1e-3) / 1e9
         out[store] = {"mlups": round(n ** 3 / (ms * 1e-3) / 1e6, 1), "ms_per_step": round(ms, 5),
                       "shape": lbm.lbm3d_shape_describe(best),
                       "shape_ms": {lbm.lbm3d_shape_describe(i): round(t, 5) for i, t in enumerate(times)},
-                      "bytes_per_node": 2 * 19 * s, "achieved_GBs": round(gbs, 1),
+                      "bytes_per_node": 2 * q * s, "achieved_GBs": round(gbs, 1),
                       "roofline_frac": round(gbs / HBM_PEAK_GBS, 4), "finite": bool(ok)}
     return out
 
@@ -496,7 +497,7 @@ def main():
     ap.add_argument("--ensemble-steps", type=int, default=2000, help="0 skips the ensemble variant")
     ap.add_argument("--c5-steps", type=int, default=6000, help="0 skips the 2048^2 vortex+pulse reflection runs")
     ap.add_argument("--train-steps", type=int, default=300, help="0 skips the closure-training throughput run")
-    ap.add_argument("--d3-steps", type=int, default=200, help="0 skips the D3Q19 256^3 run")
+    ap.add_argument("--d3-steps", type=int, default=200, help="0 skips the D3Q19 and D3Q27 256^3 runs")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -531,6 +532,7 @@ def main():
         variants["ensemble256_f32"] = run_ensemble(torch, W, args.ensemble_steps)
     if args.d3_steps > 0:
         variants["pulses3d256_d3q19"] = run_3d(torch, W, args.d3_steps)
+        variants["pulses3d256_d3q27"] = run_3d(torch, W, args.d3_steps, q=27)
     if args.c5_steps > 0:
         variants["vortexpulse2048_reflection"] = run_c5(torch, W, args.c5_steps)
     if args.train_steps > 0:

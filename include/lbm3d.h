@@ -1,13 +1,16 @@
 /*
- * lbm3d.h -- C ABI of the D3Q19 lattice: the BGK collide-and-stream sweep
- * with the non-reflective NSBC boundary of Euser & Vuik (arXiv 2005.08674,
- * Secs. 3 and 5) carried to three dimensions.
+ * lbm3d.h -- C ABI of the D3Q19 and D3Q27 lattices: the BGK collide-and-
+ * stream sweep with the non-reflective NSBC boundary of Euser & Vuik
+ * (arXiv 2005.08674, Secs. 3 and 5) carried to three dimensions.
  *
- * Lattice: c_0 = 0 (w 1/3); the six axis directions +x, -x, +y, -y, +z, -z
+ * D3Q19: c_0 = 0 (w 1/3); the six axis directions +x, -x, +y, -y, +z, -z
  * (w 1/18); the twelve face diagonals (w 1/36) in opposite pairs (1,1,0),
  * (-1,-1,0), (1,-1,0), (-1,1,0), (1,0,1), (-1,0,-1), (1,0,-1), (-1,0,1),
- * (0,1,1), (0,-1,-1), (0,1,-1), (0,-1,1); c_s^2 = 1/3.  Equilibrium eq.
- * feq_1, collision eq. lbe_1, pull streaming eq. lbe_0.
+ * (0,1,1), (0,-1,-1), (0,1,-1), (0,-1,1).  D3Q27: the same 19 (weights
+ * 8/27, 2/27, 1/54) followed by the eight cube diagonals (w 1/216) in
+ * opposite pairs (1,1,1), (-1,-1,-1), (1,1,-1), (-1,-1,1), (1,-1,1),
+ * (-1,1,-1), (-1,1,1), (1,-1,-1).  c_s^2 = 1/3.  Equilibrium eq. feq_1,
+ * collision eq. lbe_1, pull streaming eq. lbe_0.
  *
  * NSBC in 3-D: a node on k NSBC faces (k = 1 face, 2 edge, 3 corner) takes
  * the normalised sum of the faces' outward normals as its normal, so eq.
@@ -15,12 +18,12 @@
  * first-order one-sided differences at time t; eq. nes_3 blends the far
  * field, eqs. nes_0/nes_1 rebuild every population whose pull source lies
  * outside the lattice (f^eq_i(m_c) + f_opp - f^eq_opp(m_c), or f^eq_i(m_c)
- * when the opposite is unknown too), and eq. nes_4 shifts all nineteen by
+ * when the opposite is unknown too), and eq. nes_4 shifts all q of them by
  * w_i (drho + c_i . dj / c_s^2) so the node carries m_c.
  *
  * Memory: all device memory belongs to the caller (a workspace of
  * lbm3d_workspace_bytes); the context is a host object.  Population i of
- * node (x, y, z) is stored as the deviation f_i - w_i rho0 in 19 planes of
+ * node (x, y, z) is stored as the deviation f_i - w_i rho0 in q planes of
  * [nz][ny][pitch].  Calls return 0 or a negative LBM_ERR_* code (lbm.h) and
  * never abort; lbm_last_error() describes the last failure.  Work is
  * asynchronous on the stream given at init.
@@ -39,6 +42,8 @@ extern "C" {
 
 typedef struct lbm3d_ctx lbm3d_ctx;
 
+enum { LBM3D_D3Q19 = 0, LBM3D_D3Q27 = 1 };
+
 typedef struct {
     int32_t nx, ny, nz;   /* each >= 3, nx * ny * nz <= 2^28, and a plane with rows padded to
                              256 bytes (ny * nz * that row) under 4 GiB */
@@ -48,13 +53,13 @@ typedef struct {
                              y = ny-1, z = 0, z = nz-1; periodic faces come in pairs */
     double gamma;         /* eq. nes_2 */
     int32_t store;        /* LBM_STORE_F64 or LBM_STORE_F32 */
-    int32_t reserved0;    /* set to 0 */
+    int32_t velocity_set; /* LBM3D_D3Q19 (q = 19) or LBM3D_D3Q27 (q = 27) */
 } lbm3d_params;
 
-/* Defaults: 3x3x3, tau 0.6, rho0 1, NSBC on all faces, gamma 0.6, FP32. */
+/* Defaults: 3x3x3, tau 0.6, rho0 1, NSBC on all faces, gamma 0.6, FP32, D3Q19. */
 int lbm3d_params_default(lbm3d_params* p);
 
-/* Device workspace in bytes: two population buffers of 19 planes and two
+/* Device workspace in bytes: two population buffers of q planes and two
  * small buffers of moments of the nodes next to the x faces. */
 int lbm3d_workspace_bytes(const lbm3d_params* p, size_t* bytes);
 

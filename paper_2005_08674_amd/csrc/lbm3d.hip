@@ -1,13 +1,13 @@
-// lbm3d.hip -- the D3Q19 sweep for gfx950: one launch per step, every node
+// lbm3d.hip -- the D3Q19 / D3Q27 sweep for gfx950: one launch per step, every node
 // pulled (eq. lbe_0), collided with BGK (eqs. lbe_1, feq_1) and, on NSBC
 // faces, rebuilt and corrected first (eqs. nes_0..nes_4 with the normal of
 // the faces the node lies on); plus the C ABI of include/lbm3d.h.
 //
 // Pull streaming reads every stored value exactly once, so the sweep moves
-// 2 x 19 x s bytes per node (152 B in FP32) and is bound by HBM bandwidth.
+// 2 x q x s bytes per node (D3Q19 FP32: 152 B) and is bound by HBM bandwidth.
 // Threads map to consecutive x (64-wide wavefronts, coalesced); each access
 // is a per-plane (uniform) base pointer plus a 32-bit byte offset, one offset
-// per source row (y, z shift) with the x shift as an immediate.  The only
+// per source row (y, z shift) plus the lane's x shift.  The only
 // lines fetched twice are those a row's x-shifted pulls straddle at a block
 // edge; the block order keeps x-neighbouring blocks on one XCD so that the
 // second fetch hits its L2.
@@ -27,14 +27,19 @@
 namespace lbm {
 namespace d3 {
 
-constexpr int Q = 19;
-constexpr int kC[Q][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
-                          {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
-                          {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+// Velocities: D3Q19 is the first 19 rows (rest, the six axis directions,
+// the twelve face diagonals), D3Q27 all 27 (then the eight cube diagonals).
+// Opposite directions are the pairs (2k - 1, 2k).
+constexpr int kC[27][3] = {{0, 0, 0},   {1, 0, 0},   {-1, 0, 0},  {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+                           {1, 1, 0},   {-1, -1, 0}, {1, -1, 0},  {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
+                           {-1, 0, 1},  {0, 1, 1},   {0, -1, -1}, {0, 1, -1}, {0, -1, 1}, {1, 1, 1},  {-1, -1, -1},
+                           {1, 1, -1},  {-1, -1, 1}, {1, -1, 1},  {-1, 1, -1}, {-1, 1, 1}, {1, -1, -1}};
 
-template <class R>
+// Weights by speed: D3Q19 1/3, 1/18, 1/36; D3Q27 8/27, 2/27, 1/54, 1/216.
+template <int NQ, class R>
 __host__ __device__ constexpr R w3(int i) {
-  return i == 0 ? R(1) / R(3) : (i <= 6 ? R(1) / R(18) : R(1) / R(36));
+  return NQ == 19 ? (i == 0 ? R(1) / R(3) : (i <= 6 ? R(1) / R(18) : R(1) / R(36)))
+                  : (i == 0 ? R(8) / R(27) : (i <= 6 ? R(2) / R(27) : (i <= 18 ? R(1) / R(54) : R(1) / R(216))));
 }
 
 // Everything a kernel needs about one lattice.
@@ -50,16 +55,16 @@ struct Lat3 {
   int64_t slab;   // elements per z-slab (ny * pitch)
   int64_t plane;  // elements per population plane
   int32_t bc[6];
-  int32_t store, _pad;
+  int32_t store, q;  // q: velocity set, 19 or 27
   double omega, rho0, gamma, beta;
   double m0[4];   // far field (rho - rho0, ux, uy, uz)
 };
 
-template <class R>
-__device__ inline void moments3(const R g[Q], R rho0, R m[4]) {
+template <int NQ, class R>
+__device__ inline void moments3(const R g[NQ], R rho0, R m[4]) {
   R s = R(0), j[3] = {R(0), R(0), R(0)};
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
+  for (int i = 0; i < NQ; ++i) {
     s += g[i];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
@@ -72,50 +77,50 @@ __device__ inline void moments3(const R g[Q], R rho0, R m[4]) {
 }
 
 // g^eq_i - w_i rho0 = w_i [drho + rho (3 c.u + 9/2 (c.u)^2 - 3/2 u.u)]
-template <class R>
-__device__ inline void equilibrium3(R rho0, const R m[4], R geq[Q]) {
+template <int NQ, class R>
+__device__ inline void equilibrium3(R rho0, const R m[4], R geq[NQ]) {
   const R rho = rho0 + m[0];
   const R q = R(1.5) * (m[1] * m[1] + m[2] * m[2] + m[3] * m[3]);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
+  for (int i = 0; i < NQ; ++i) {
     R a = R(0);
 #pragma unroll
     for (int k = 0; k < 3; ++k)
       if (kC[i][k]) a += kC[i][k] > 0 ? m[1 + k] : -m[1 + k];
-    geq[i] = w3<R>(i) * (m[0] + rho * fma(a, fma(R(4.5), a, R(3)), -q));
+    geq[i] = w3<NQ, R>(i) * (m[0] + rho * fma(a, fma(R(4.5), a, R(3)), -q));
   }
 }
 
 // BGK in place, written per pair of opposite directions (2i-1, 2i): the even
 // part E + 9/2 rho a^2 is shared, w_i is folded into omega.
-template <class R>
-__device__ inline void bgk3(R g[Q], R rho0, R omega, R m[4]) {
-  moments3<R>(g, rho0, m);
+template <int NQ, class R>
+__device__ inline void bgk3(R g[NQ], R rho0, R omega, R m[4]) {
+  moments3<NQ, R>(g, rho0, m);
   const R rho = rho0 + m[0];
   const R e = fma(-rho, R(1.5) * (m[1] * m[1] + m[2] * m[2] + m[3] * m[3]), m[0]);
   const R r45 = R(4.5) * rho, r3 = R(3) * rho, om1 = R(1) - omega;
-  g[0] = fma(omega * w3<R>(0), e, om1 * g[0]);
+  g[0] = fma(omega * w3<NQ, R>(0), e, om1 * g[0]);
 #pragma unroll
-  for (int p = 1; p < Q; p += 2) {
+  for (int p = 1; p < NQ; p += 2) {
     R a = R(0);
 #pragma unroll
     for (int k = 0; k < 3; ++k)
       if (kC[p][k]) a += kC[p][k] > 0 ? m[1 + k] : -m[1 + k];
-    const R ow = omega * w3<R>(p);
+    const R ow = omega * w3<NQ, R>(p);
     const R even = fma(r45 * a, a, e), odd = r3 * a;
     g[p] = fma(ow, even + odd, om1 * g[p]);
     g[p + 1] = fma(ow, even - odd, om1 * g[p + 1]);
   }
 }
 
-template <class R>
-__device__ inline void bgk3(R g[Q], R rho0, R omega) {
+template <int NQ, class R>
+__device__ inline void bgk3(R g[NQ], R rho0, R omega) {
   R m[4];
-  bgk3<R>(g, rho0, omega, m);
+  bgk3<NQ, R>(g, rho0, omega, m);
 }
 
 // Moments of the stored node at byte offset `off` of each plane.
-template <int S>
+template <int S, int NQ>
 __device__ inline void node_moments3(const Lat3& L, const typename Codec<S>::T* A, uint32_t off,
                                      typename Codec<S>::R m[4]) {
   using C = Codec<S>;
@@ -123,7 +128,7 @@ __device__ inline void node_moments3(const Lat3& L, const typename Codec<S>::T* 
   using R = typename C::R;
   R s = R(0), j[3] = {R(0), R(0), R(0)};
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
+  for (int i = 0; i < NQ; ++i) {
     const R v = C::dec(*reinterpret_cast<const T*>(reinterpret_cast<const char*>(A + i * L.plane) + off), 1.0f);
     s += v;
 #pragma unroll
@@ -141,9 +146,9 @@ __device__ inline void node_moments3(const Lat3& L, const typename Codec<S>::T* 
 // Written to keep few values live (no equilibrium or copy arrays: rebuilt
 // populations are formed in place from their opposites), so that the sweep
 // that carries it keeps the occupancy of its interior path.
-template <int S>
+template <int S, int NQ>
 __device__ inline void boundary_node3(const Lat3& L, const typename Codec<S>::T* A, int x, int y, int z,
-                                      typename Codec<S>::R g[Q]) {
+                                      typename Codec<S>::R g[NQ]) {
   using C = Codec<S>;
   using T = typename C::T;
   using R = typename C::R;
@@ -151,7 +156,7 @@ __device__ inline void boundary_node3(const Lat3& L, const typename Codec<S>::T*
   const uint32_t stride[3] = {1u, (uint32_t)L.pitch, (uint32_t)L.slab};
   uint32_t unknown = 0;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
+  for (int i = 0; i < NQ; ++i) {
     uint32_t src = 0;
     bool out = false;
 #pragma unroll
@@ -175,7 +180,7 @@ __device__ inline void boundary_node3(const Lat3& L, const typename Codec<S>::T*
   // eq. nes_2 with the normalised normal of the k NSBC faces the node is on
   const uint32_t own = ((uint32_t)z * stride[2] + (uint32_t)y * stride[1] + (uint32_t)x) * (uint32_t)sizeof(T);
   R mb[4], d[4] = {R(0), R(0), R(0), R(0)};
-  node_moments3<S>(L, A, own, mb);
+  node_moments3<S, NQ>(L, A, own, mb);
   int k = 0;
 #pragma unroll 1
   for (int a = 0; a < 3; ++a) {
@@ -183,7 +188,7 @@ __device__ inline void boundary_node3(const Lat3& L, const typename Codec<S>::T*
     const int step = p[a] == 0 ? 1 : (p[a] == n[a] - 1 ? -1 : 0);
     if (!step) continue;
     R mn[4];
-    node_moments3<S>(L, A, own + (uint32_t)(step * (int)sizeof(T)) * stride[a], mn);
+    node_moments3<S, NQ>(L, A, own + (uint32_t)(step * (int)sizeof(T)) * stride[a], mn);
 #pragma unroll
     for (int c = 0; c < 4; ++c) d[c] += mb[c] - mn[c];
     ++k;
@@ -198,20 +203,20 @@ __device__ inline void boundary_node3(const Lat3& L, const typename Codec<S>::T*
   const R rc = R(L.rho0) + mc[0];
   const R uu = R(1.5) * (mc[1] * mc[1] + mc[2] * mc[2] + mc[3] * mc[3]);
 #pragma unroll
-  for (int i = 1; i < Q; ++i) {
+  for (int i = 1; i < NQ; ++i) {
     if (!((unknown >> i) & 1u)) continue;
     const int o = i & 1 ? i + 1 : i - 1;
     R cu = R(0);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
       if (kC[i][a]) cu += kC[i][a] > 0 ? mc[1 + a] : -mc[1 + a];
-    g[i] = (unknown >> o) & 1u ? w3<R>(i) * (mc[0] + rc * fma(cu, fma(R(4.5), cu, R(3)), -uu))
-                               : fma(R(6) * w3<R>(i) * rc, cu, g[o]);
+    g[i] = (unknown >> o) & 1u ? w3<NQ, R>(i) * (mc[0] + rc * fma(cu, fma(R(4.5), cu, R(3)), -uu))
+                               : fma(R(6) * w3<NQ, R>(i) * rc, cu, g[o]);
   }
-  // eq. nes_4 with 1/c_s^2 = 3: shift all nineteen so the node carries m_c
+  // eq. nes_4 with 1/c_s^2 = 3: shift all populations so the node carries m_c
   R s = R(0), j[3] = {R(0), R(0), R(0)};
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
+  for (int i = 0; i < NQ; ++i) {
     s += g[i];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
@@ -222,12 +227,12 @@ __device__ inline void boundary_node3(const Lat3& L, const typename Codec<S>::T*
 #pragma unroll
   for (int a = 0; a < 3; ++a) dj[a] = R(3) * (j[a] - rc * mc[1 + a]);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
+  for (int i = 0; i < NQ; ++i) {
     R cd = R(0);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
       if (kC[i][a]) cd += kC[i][a] > 0 ? dj[a] : -dj[a];
-    g[i] -= w3<R>(i) * (dr + cd);
+    g[i] -= w3<NQ, R>(i) * (dr + cd);
   }
 }
 
@@ -236,9 +241,9 @@ __device__ inline void boundary_node3(const Lat3& L, const typename Codec<S>::T*
 // -1 at x = nx - 1) loaded from any node in range; mb and mn are the moments
 // at time t of the node and of its inner x neighbour.  Same arithmetic as
 // boundary_node3 with k = 1.
-template <int S>
+template <int S, int NQ>
 __device__ inline void xface_nsbc3(const Lat3& L, const typename Codec<S>::R mb[4],
-                                   const typename Codec<S>::R mn[4], int side, typename Codec<S>::R g[Q]) {
+                                   const typename Codec<S>::R mn[4], int side, typename Codec<S>::R g[NQ]) {
   using R = typename Codec<S>::R;
   const R fac = R(L.gamma), beta = R(L.beta);
   R mc[4];
@@ -246,13 +251,13 @@ __device__ inline void xface_nsbc3(const Lat3& L, const typename Codec<S>::R mb[
   for (int c = 0; c < 4; ++c) mc[c] = (R(1) - beta) * (mb[c] - fac * (mb[c] - mn[c])) + beta * R(L.m0[c]);
   const R rc = R(L.rho0) + mc[0];
 #pragma unroll
-  for (int p = 1; p < Q; p += 2) {
+  for (int p = 1; p < NQ; p += 2) {
     if (!kC[p][0]) continue;
     R cu = R(0);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
       if (kC[p][a]) cu += kC[p][a] > 0 ? mc[1 + a] : -mc[1 + a];
-    const R t = R(6) * w3<R>(p) * rc;
+    const R t = R(6) * w3<NQ, R>(p) * rc;
     const bool p_unknown = kC[p][0] == side;
     const R gp = fma(t, cu, g[p + 1]), go = fma(t, -cu, g[p]);
     g[p] = p_unknown ? gp : g[p];
@@ -260,7 +265,7 @@ __device__ inline void xface_nsbc3(const Lat3& L, const typename Codec<S>::R mb[
   }
   R s = R(0), j[3] = {R(0), R(0), R(0)};
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
+  for (int i = 0; i < NQ; ++i) {
     s += g[i];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
@@ -271,33 +276,33 @@ __device__ inline void xface_nsbc3(const Lat3& L, const typename Codec<S>::R mb[
 #pragma unroll
   for (int a = 0; a < 3; ++a) dj[a] = R(3) * (j[a] - rc * mc[1 + a]);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
+  for (int i = 0; i < NQ; ++i) {
     R cd = R(0);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
       if (kC[i][a]) cd += kC[i][a] > 0 ? dj[a] : -dj[a];
-    g[i] -= w3<R>(i) * (dr + cd);
+    g[i] -= w3<NQ, R>(i) * (dr + cd);
   }
 }
 
 // Register budget: the shell paths would otherwise take more registers than
-// the interior path and cost every node occupancy (6 waves per SIMD in FP32,
-// 4 in FP64 fit them without spills).
-template <int S>
+// the interior path and cost every node occupancy.  D3Q19 fits 6 waves per
+// SIMD in FP32 and 4 in FP64 without spills, D3Q27 5 and 3.
+template <int S, int NQ>
 constexpr int k3_waves() {
-  return S == ST_F64 ? 4 : 6;
+  return NQ == 19 ? (S == ST_F64 ? 4 : 6) : (S == ST_F64 ? 3 : 5);
 }
 
 // Pulls of a node whose y and z neighbours all lie inside.  `idx` is its
 // element index; sxm and sxp are the byte shifts of the pulls with c_x = +1
 // (source x - 1) and c_x = -1 (source x + 1).
-template <int S>
+template <int S, int NQ>
 __device__ __forceinline__ void pull_row3(const Lat3& L, const typename Codec<S>::T* A, uint32_t idx, int sxm,
-                                          int sxp, typename Codec<S>::R g[Q]) {
+                                          int sxp, typename Codec<S>::R g[NQ]) {
   using C = Codec<S>;
   using T = typename C::T;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
+  for (int i = 0; i < NQ; ++i) {
     const char* Ai = reinterpret_cast<const char*>(A + i * L.plane);
     const uint32_t row = (idx - (uint32_t)(kC[i][2] * L.slab + kC[i][1] * L.pitch)) * (uint32_t)sizeof(T);
     const int sh = kC[i][0] > 0 ? sxm : (kC[i][0] < 0 ? sxp : 0);
@@ -313,14 +318,14 @@ __device__ __forceinline__ void pull_row3(const Lat3& L, const typename Codec<S>
 // wavefront is a run of x).  In the other rows an x-face node is one lane of
 // a wavefront: it pulls with the others (the x shift adjusted), and on a NSBC
 // face it takes the moments at time t of itself and of its inner neighbour
-// from Lat3::mx instead of loading 38 stored populations (BGK conserves mass
+// from Lat3::mx instead of loading 2 q stored populations (BGK conserves mass
 // and momentum, so the moments the collision of the previous step computed
 // are those of the populations it stored).  Every x-face lane and its inner
 // neighbour lane write their moments for the next step.  Nodes with y and z
 // inside are written by the wavefront that holds their whole row segment:
 // no cache line of the output is written in parts by different blocks.
-template <int S, int BX, int BY, int ZC>
-__global__ __launch_bounds__(BX* BY, k3_waves<S>()) void k3_step(Lat3 L, int parity, int tiles_x, int tiles_y,
+template <int S, int NQ, int BX, int BY, int ZC>
+__global__ __launch_bounds__(BX* BY, (k3_waves<S, NQ>())) void k3_step(Lat3 L, int parity, int tiles_x, int tiles_y,
                                                                 int nitems, int per) {
   using C = Codec<S>;
   using T = typename C::T;
@@ -352,11 +357,11 @@ __global__ __launch_bounds__(BX* BY, k3_waves<S>()) void k3_step(Lat3 L, int par
   const uint32_t mxs = (uint32_t)L.mxs;
   const int z1 = min(nz, (zc + 1) * ZC);
   for (int z = zc * ZC; z < z1; ++z) {
-    R g[Q];
+    R g[NQ];
     const uint32_t idx = (uint32_t)((int64_t)z * L.slab + (int64_t)y * L.pitch + x);
     const bool inner_row = y_inner && z >= 1 && z <= nz - 2;
     if (inner_row) {
-      pull_row3<S>(L, A, idx, sxm, sxp, g);
+      pull_row3<S, NQ>(L, A, idx, sxm, sxp, g);
       if (xside) {
         const uint32_t mo = (uint32_t)z * (uint32_t)ny + (uint32_t)y;
         const T* Mb = MA + (x == 0 ? 0 : 8 * mxs);  // slots 0, 1 (x = 0) or 2, 3
@@ -366,13 +371,13 @@ __global__ __launch_bounds__(BX* BY, k3_waves<S>()) void k3_step(Lat3 L, int par
           mb[c] = R(Mb[c * mxs + mo]);
           mn[c] = R(Mb[(4 + c) * mxs + mo]);
         }
-        xface_nsbc3<S>(L, mb, mn, xside, g);
+        xface_nsbc3<S, NQ>(L, mb, mn, xside, g);
       }
     } else {
-      boundary_node3<S>(L, A, x, y, z, g);
+      boundary_node3<S, NQ>(L, A, x, y, z, g);
     }
     R m[4];
-    bgk3<R>(g, rho0, omega, m);
+    bgk3<NQ, R>(g, rho0, omega, m);
     if (inner_row && mwrite) {
       // slot 0: x = 0, 1: x = 1, 2: x = nx - 1, 3: x = nx - 2 (both 1 and 3 when nx = 3)
       const uint32_t mo = (uint32_t)z * (uint32_t)ny + (uint32_t)y;
@@ -386,7 +391,7 @@ __global__ __launch_bounds__(BX* BY, k3_waves<S>()) void k3_step(Lat3 L, int par
     }
     const uint32_t off = idx * (uint32_t)sizeof(T);
 #pragma unroll
-    for (int i = 0; i < Q; ++i)
+    for (int i = 0; i < NQ; ++i)
       __builtin_nontemporal_store(C::enc(g[i], 1.0f), reinterpret_cast<T*>(reinterpret_cast<char*>(B + i * L.plane) + off));
   }
 }
@@ -409,19 +414,19 @@ static const Shape3 kShapes3[] = {
 };
 static constexpr int kNumShapes3 = sizeof(kShapes3) / sizeof(kShapes3[0]);
 
-template <int S, int BX, int BY, int ZC>
+template <int S, int NQ, int BX, int BY, int ZC>
 static hipError_t launch3_t(const Lat3& L, int parity, hipStream_t s) {
   const int tiles_x = (L.nx + BX - 1) / BX, tiles_y = (L.ny + BY - 1) / BY, zch = (L.nz + ZC - 1) / ZC;
   const int nitems = tiles_x * tiles_y * zch, per = (nitems + 7) / 8;
-  k3_step<S, BX, BY, ZC><<<dim3(8 * per), dim3(BX, BY), 0, s>>>(L, parity, tiles_x, tiles_y, nitems, per);
+  k3_step<S, NQ, BX, BY, ZC><<<dim3(8 * per), dim3(BX, BY), 0, s>>>(L, parity, tiles_x, tiles_y, nitems, per);
   return hipGetLastError();
 }
 
-template <int S>
+template <int S, int NQ>
 static hipError_t launch3_s(const Lat3& L, int parity, int shape, hipStream_t s) {
   int k = 0;
-#define X(a, b, c)                                                  \
-  if (shape == k) return launch3_t<S, a, b, c>(L, parity, s);      \
+#define X(a, b, c)                                                    \
+  if (shape == k) return launch3_t<S, NQ, a, b, c>(L, parity, s);    \
   ++k;
   LBM3D_SHAPES(X)
 #undef X
@@ -429,11 +434,13 @@ static hipError_t launch3_s(const Lat3& L, int parity, int shape, hipStream_t s)
 }
 
 static hipError_t launch3(const Lat3& L, int parity, int shape, hipStream_t s) {
-  return L.store == ST_F64 ? launch3_s<ST_F64>(L, parity, shape, s) : launch3_s<ST_F32>(L, parity, shape, s);
+  if (L.q == 27)
+    return L.store == ST_F64 ? launch3_s<ST_F64, 27>(L, parity, shape, s) : launch3_s<ST_F32, 27>(L, parity, shape, s);
+  return L.store == ST_F64 ? launch3_s<ST_F64, 19>(L, parity, shape, s) : launch3_s<ST_F32, 19>(L, parity, shape, s);
 }
 
 // f = f^eq(rho, u) of the initial fields, as deviations
-template <int S>
+template <int S, int NQ>
 __global__ void k3_init(Lat3 L, const double* __restrict__ drho, const double* __restrict__ ux,
                         const double* __restrict__ uy, const double* __restrict__ uz) {
   using T = typename Codec<S>::T;
@@ -441,20 +448,20 @@ __global__ void k3_init(Lat3 L, const double* __restrict__ drho, const double* _
   if (x >= L.nx) return;
   const int64_t k = ((int64_t)z * L.ny + y) * L.nx + x;
   const double m[4] = {drho[k], ux[k], uy[k], uz[k]};
-  double geq[Q];
-  equilibrium3<double>(L.rho0, m, geq);
+  double geq[NQ];
+  equilibrium3<NQ, double>(L.rho0, m, geq);
   T* B = static_cast<T*>(L.buf[0]);
   const int64_t idx = (int64_t)z * L.slab + (int64_t)y * L.pitch + x;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) B[i * L.plane + idx] = (T)geq[i];
+  for (int i = 0; i < NQ; ++i) B[i * L.plane + idx] = (T)geq[i];
   // moments of the stored populations for the x-face slots of Lat3::mx
   const int nx = L.nx;
   if (x > 1 && x < nx - 2) return;
   using R = typename Codec<S>::R;
-  R g[Q], ms[4];
+  R g[NQ], ms[4];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) g[i] = R((T)geq[i]);
-  moments3<R>(g, R(L.rho0), ms);
+  for (int i = 0; i < NQ; ++i) g[i] = R((T)geq[i]);
+  moments3<NQ, R>(g, R(L.rho0), ms);
   T* M = static_cast<T*>(L.mx[0]);
   const int64_t mo = (int64_t)z * L.ny + y;
 #pragma unroll
@@ -466,7 +473,7 @@ __global__ void k3_init(Lat3 L, const double* __restrict__ drho, const double* _
   }
 }
 
-template <int S>
+template <int S, int NQ>
 __global__ void k3_moments(Lat3 L, int parity, double* __restrict__ out) {
   using T = typename Codec<S>::T;
   using R = typename Codec<S>::R;
@@ -474,10 +481,35 @@ __global__ void k3_moments(Lat3 L, int parity, double* __restrict__ out) {
   if (x >= L.nx) return;
   R m[4];
   const uint32_t off = (uint32_t)((int64_t)z * L.slab + (int64_t)y * L.pitch + x) * (uint32_t)sizeof(T);
-  node_moments3<S>(L, static_cast<const T*>(parity ? L.buf[1] : L.buf[0]), off, m);
+  node_moments3<S, NQ>(L, static_cast<const T*>(parity ? L.buf[1] : L.buf[0]), off, m);
   const int64_t n = (int64_t)L.nx * L.ny * L.nz, k = ((int64_t)z * L.ny + y) * L.nx + x;
 #pragma unroll
   for (int c = 0; c < 4; ++c) out[c * n + k] = (double)m[c];
+}
+
+static hipError_t launch_init3(const Lat3& L, const double* drho, const double* ux, const double* uy,
+                               const double* uz, hipStream_t s) {
+  const dim3 grid((L.nx + 255) / 256, L.ny, L.nz);
+  if (L.q == 27) {
+    if (L.store == ST_F64) k3_init<ST_F64, 27><<<grid, dim3(256), 0, s>>>(L, drho, ux, uy, uz);
+    else k3_init<ST_F32, 27><<<grid, dim3(256), 0, s>>>(L, drho, ux, uy, uz);
+  } else {
+    if (L.store == ST_F64) k3_init<ST_F64, 19><<<grid, dim3(256), 0, s>>>(L, drho, ux, uy, uz);
+    else k3_init<ST_F32, 19><<<grid, dim3(256), 0, s>>>(L, drho, ux, uy, uz);
+  }
+  return hipGetLastError();
+}
+
+static hipError_t launch_moments3(const Lat3& L, int parity, double* out, hipStream_t s) {
+  const dim3 grid((L.nx + 255) / 256, L.ny, L.nz);
+  if (L.q == 27) {
+    if (L.store == ST_F64) k3_moments<ST_F64, 27><<<grid, dim3(256), 0, s>>>(L, parity, out);
+    else k3_moments<ST_F32, 27><<<grid, dim3(256), 0, s>>>(L, parity, out);
+  } else {
+    if (L.store == ST_F64) k3_moments<ST_F64, 19><<<grid, dim3(256), 0, s>>>(L, parity, out);
+    else k3_moments<ST_F32, 19><<<grid, dim3(256), 0, s>>>(L, parity, out);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace d3
@@ -506,6 +538,7 @@ struct Layout3 {
   size_t esize;
   int32_t pitch;
   int64_t slab, plane;
+  int q;
   size_t buf_bytes, mx_bytes, total;
 };
 
@@ -531,6 +564,8 @@ int check3(const lbm3d_params* p) {
   if (!std::isfinite(p->gamma)) return fail(LBM_ERR_ARG, "gamma must be finite");
   if (p->store != LBM_STORE_F64 && p->store != LBM_STORE_F32)
     return fail(LBM_ERR_ARG, "store = %d: the 3-D lattice stores FP64 or FP32", p->store);
+  if (p->velocity_set != LBM3D_D3Q19 && p->velocity_set != LBM3D_D3Q27)
+    return fail(LBM_ERR_ARG, "velocity_set = %d is not LBM3D_D3Q19 or LBM3D_D3Q27", p->velocity_set);
   return LBM_OK;
 }
 
@@ -544,7 +579,8 @@ Layout3 layout3(const lbm3d_params* p) {
   size_t plane_bytes = round_up(row * (size_t)p->ny * p->nz, 4096);
   if (plane_bytes % 65536 == 0) plane_bytes += 4096;  // planes not a large power of two apart
   l.plane = (int64_t)(plane_bytes / l.esize);
-  l.buf_bytes = round_up(19 * plane_bytes, (size_t)2 << 20);
+  l.q = p->velocity_set == LBM3D_D3Q27 ? 27 : 19;
+  l.buf_bytes = round_up((size_t)l.q * plane_bytes, (size_t)2 << 20);
   l.mx_bytes = round_up((size_t)16 * p->ny * p->nz * l.esize, 4096);
   l.total = 2 * l.buf_bytes + 2 * l.mx_bytes;
   return l;
@@ -600,14 +636,12 @@ int lbm3d_init(lbm3d_ctx** out, const lbm3d_params* p, void* workspace, size_t b
   L.plane = lay.plane;
   for (int f = 0; f < 6; ++f) L.bc[f] = p->bc[f];
   L.store = p->store == LBM_STORE_F64 ? lbm::ST_F64 : lbm::ST_F32;
+  L.q = lay.q;
   L.omega = 1.0 / p->tau;
   L.rho0 = p->rho0;
   L.gamma = p->gamma;
   c->stream = static_cast<hipStream_t>(hip_stream);
-  const dim3 grid((p->nx + 255) / 256, p->ny, p->nz);
-  if (L.store == lbm::ST_F64) lbm::d3::k3_init<lbm::ST_F64><<<grid, dim3(256), 0, c->stream>>>(L, drho, ux, uy, uz);
-  else lbm::d3::k3_init<lbm::ST_F32><<<grid, dim3(256), 0, c->stream>>>(L, drho, ux, uy, uz);
-  hipError_t e = hipGetLastError();
+  hipError_t e = lbm::d3::launch_init3(L, drho, ux, uy, uz, c->stream);
   if (e != hipSuccess) {
     delete c;
     return fail(LBM_ERR_HIP, "init: %s", hipGetErrorString(e));
@@ -642,12 +676,7 @@ int lbm3d_step(lbm3d_ctx* c, int32_t n) {
 
 int lbm3d_moments(lbm3d_ctx* c, double* out) {
   if (!c || !out) return fail(LBM_ERR_ARG, "NULL argument");
-  const dim3 grid((c->L.nx + 255) / 256, c->L.ny, c->L.nz);
-  if (c->L.store == lbm::ST_F64)
-    lbm::d3::k3_moments<lbm::ST_F64><<<grid, dim3(256), 0, c->stream>>>(c->L, c->parity, out);
-  else
-    lbm::d3::k3_moments<lbm::ST_F32><<<grid, dim3(256), 0, c->stream>>>(c->L, c->parity, out);
-  HIPCHK3(hipGetLastError());
+  HIPCHK3(lbm::d3::launch_moments3(c->L, c->parity, out, c->stream));
   return LBM_OK;
 }
 

@@ -1,5 +1,5 @@
-"""Convenience wrapper: one D3Q19 lattice on the GPU whose device memory and stream come from
-PyTorch.  Marshalling only -- every computation is a call into liblbm.so (include/lbm3d.h)."""
+"""Convenience wrapper: one D3Q19 or D3Q27 lattice on the GPU whose device memory and stream come
+from PyTorch.  Marshalling only -- every computation is a call into liblbm.so (include/lbm3d.h)."""
 from __future__ import annotations
 
 import numpy as np
@@ -10,15 +10,18 @@ from . import lbm as L
 
 class Lattice3D:
     """``fields`` = (drho, ux, uy, uz), [nz][ny][nx] arrays with drho = rho - rho0.  ``bc`` = (x low,
-    x high, y low, y high, z low, z high), 1 = NSBC, 0 = periodic.  ``store`` is "f64" or "f32"."""
+    x high, y low, y high, z low, z high), 1 = NSBC, 0 = periodic.  ``store`` is "f64" or "f32"; ``q`` is
+    19 (D3Q19) or 27 (D3Q27)."""
 
     def __init__(self, nx, ny, nz, tau, fields, rho0=1.0, bc=(1,) * 6, gamma=0.6, store="f32", beta=0.0, m0=None,
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, q=19):
         p = L.lbm3d_params_default()
         p.nx, p.ny, p.nz, p.tau, p.rho0, p.gamma = int(nx), int(ny), int(nz), float(tau), float(rho0), float(gamma)
         for f in range(6):
             p.bc[f] = int(bc[f])
         p.store = L.STORE_NAMES[store] if isinstance(store, str) else int(store)
+        p.velocity_set = L.VELOCITY_SETS[int(q)]
+        self.q = int(q)
         self.params = p
         self.shape = (int(nz), int(ny), int(nx))
         self.device = torch.device(device)

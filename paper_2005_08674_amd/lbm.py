@@ -539,14 +539,19 @@ def lbm_mlp_destroy(m):
     load().lbm_mlp_destroy(m)
 
 
-# ------------------------------------------------------------------ D3Q19 (include/lbm3d.h)
+# ------------------------------------------------------------------ D3Q19 / D3Q27 (include/lbm3d.h)
+
+LBM3D_D3Q19 = 0
+LBM3D_D3Q27 = 1
+VELOCITY_SETS = {19: LBM3D_D3Q19, 27: LBM3D_D3Q27}
+
 
 class lbm3d_params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("tau", ctypes.c_double), ("rho0", ctypes.c_double),
                 ("bc", ctypes.c_int32 * 6),
                 ("gamma", ctypes.c_double),
-                ("store", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
+                ("store", ctypes.c_int32), ("velocity_set", ctypes.c_int32)]
 
 
 def lbm3d_params_default() -> lbm3d_params:

@@ -113,14 +113,21 @@ def test_velocity_edges_left_right_with_periodic_bottom_top(lib, bc, ok):
 def test_3d_parameters(lib):
     p = L.lbm3d_params_default()
     assert (p.nx, p.ny, p.nz, p.tau, p.gamma, p.store) == (3, 3, 3, 0.6, 0.6, L.LBM_STORE_F32)
+    assert p.velocity_set == L.LBM3D_D3Q19
     p.nx = p.ny = p.nz = 64
     n32 = L.lbm3d_workspace_bytes(p)
     assert n32 >= 2 * 19 * 64 ** 3 * 4
     p.store = L.LBM_STORE_F64
     assert L.lbm3d_workspace_bytes(p) >= 2 * 19 * 64 ** 3 * 8
-    for field, value, msg in [("nz", 2, "each side"), ("tau", 0.5, "tau"), ("store", L.LBM_STORE_F16DEV, "store")]:
+    p.velocity_set = L.LBM3D_D3Q27
+    assert L.lbm3d_workspace_bytes(p) >= 2 * 27 * 64 ** 3 * 8
+    for field, value, msg in [("nz", 2, "each side"), ("tau", 0.5, "tau"), ("store", L.LBM_STORE_F16DEV, "store"),
+                              ("velocity_set", 2, "velocity_set"), ("nx", 1 << 27, "2\\^28"),
+                              ("ny", 1 << 13, "4 GiB")]:
         q = L.lbm3d_params_default()
         setattr(q, field, value)
+        if field == "ny":
+            q.nz = 1 << 13      # 3 x 8192 x 8192 nodes (< 2^28), but rows padded to 256 B make 16 GiB planes
         with pytest.raises(L.LbmError, match=msg):
             L.lbm3d_workspace_bytes(q)
     q = L.lbm3d_params_default()

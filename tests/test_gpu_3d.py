@@ -1,6 +1,6 @@
-"""GPU D3Q19 sweep (include/lbm3d.h) against the CPU D3Q19 oracle: fp64 storage within 1e-12 and fp32
-within 1e-5 (relative, as the 2-D parity tests), every launch shape bit-identical, periodic and NSBC
-face mixes, the smallest lattice."""
+"""GPU D3Q19 and D3Q27 sweeps (include/lbm3d.h) against the CPU oracle of the same velocity set: fp64
+storage within 1e-12 and fp32 within 1e-5 (relative, as the 2-D parity tests), every launch shape
+bit-identical, periodic and NSBC face mixes, the smallest lattice."""
 import math
 
 import numpy as np
@@ -28,13 +28,13 @@ def _fields(nx, ny, nz, u0=(0.03, -0.02, 0.01), a=1e-3, w=3.0, seed=0):
     return dr, np.full_like(dr, u0[0]), np.full_like(dr, u0[1]), np.full_like(dr, u0[2])
 
 
-def _pair(nx, ny, nz, store, tol, checkpoints, bc=(1,) * 6, beta=0.3, u0=(0.03, -0.02, 0.01), tau=0.58):
+def _pair(nx, ny, nz, store, tol, checkpoints, bc=(1,) * 6, beta=0.3, u0=(0.03, -0.02, 0.01), tau=0.58, q=19):
     from paper_2005_08674_amd.lattice3d import Lattice3D
-    print(f"\n[3d parity] {nx}x{ny}x{nz} store={store} bc={bc}", flush=True)
+    print(f"\n[3d parity] D3Q{q} {nx}x{ny}x{nz} store={store} bc={bc}", flush=True)
     f = _fields(nx, ny, nz, u0)
     m0 = (1.0002, *u0)
-    g = Lattice3D(nx, ny, nz, tau, f, bc=bc, store=store, beta=beta, m0=m0)
-    o = oracle.Lattice3D(nx, ny, nz, tau, *f, bc=bc, beta=beta, m0=m0)
+    g = Lattice3D(nx, ny, nz, tau, f, bc=bc, store=store, beta=beta, m0=m0, q=q)
+    o = oracle.Lattice3D(nx, ny, nz, tau, *f, bc=bc, beta=beta, m0=m0, q=q)
     u_ref = 0.03
     for t in checkpoints:
         g.step(t - g.t)
@@ -49,22 +49,25 @@ def _pair(nx, ny, nz, store, tol, checkpoints, bc=(1,) * 6, beta=0.3, u0=(0.03, 
 
 @pytest.mark.parametrize("dims,bc", [((20, 18, 16), (1,) * 6), ((70, 9, 11), (1, 1, 0, 0, 1, 1)),
                                      ((13, 14, 15), (0,) * 6), ((3, 3, 3), (1,) * 6), ((66, 5, 4), (0, 0, 1, 1, 0, 0))])
-def test_fp64_against_oracle(dims, bc):
-    _pair(*dims, "f64", 1e-12, [1, 5, 30, 80], bc=bc)
+@pytest.mark.parametrize("q", [19, 27])
+def test_fp64_against_oracle(dims, bc, q):
+    _pair(*dims, "f64", 1e-12, [1, 5, 30, 80], bc=bc, q=q)
 
 
-def test_fp32_against_oracle():
-    _pair(40, 36, 32, "f32", 1e-5, [1, 20, 100])
+@pytest.mark.parametrize("q", [19, 27])
+def test_fp32_against_oracle(q):
+    _pair(40, 36, 32, "f32", 1e-5, [1, 20, 100], q=q)
 
 
+@pytest.mark.parametrize("q", [19, 27])
 @pytest.mark.parametrize("store", ["f32", "f64"])
-def test_every_shape_bitwise_identical(store):
+def test_every_shape_bitwise_identical(store, q):
     from paper_2005_08674_amd import lbm
     from paper_2005_08674_amd.lattice3d import Lattice3D
     f = _fields(70, 19, 23)
     ref = None
     for shape in range(lbm.lbm3d_shape_count()):
-        g = Lattice3D(70, 19, 23, 0.6, f, store=store, beta=0.2, m0=(1.0, 0.03, -0.02, 0.01))
+        g = Lattice3D(70, 19, 23, 0.6, f, store=store, beta=0.2, m0=(1.0, 0.03, -0.02, 0.01), q=q)
         lbm.lbm3d_set_shape(g.ctx, shape)
         g.step(7)
         m = np.array(g.moments())
@@ -75,12 +78,13 @@ def test_every_shape_bitwise_identical(store):
             assert np.array_equal(m, ref), (store, lbm.lbm3d_shape_describe(shape))
 
 
-def test_autotune_leaves_the_state_and_picks_a_shape():
+@pytest.mark.parametrize("q", [19, 27])
+def test_autotune_leaves_the_state_and_picks_a_shape(q):
     from paper_2005_08674_amd import lbm
     from paper_2005_08674_amd.lattice3d import Lattice3D
     f = _fields(64, 32, 16)
-    a = Lattice3D(64, 32, 16, 0.6, f)
-    b = Lattice3D(64, 32, 16, 0.6, f)
+    a = Lattice3D(64, 32, 16, 0.6, f, q=q)
+    b = Lattice3D(64, 32, 16, 0.6, f, q=q)
     best, times = a.autotune(reps=2)
     assert 0 <= best < lbm.lbm3d_shape_count() and min(times) > 0 and a.t == 0
     a.step(5)
