@@ -84,13 +84,15 @@ int lbm3d_moments(lbm3d_ctx* ctx, double* out);
 int lbm3d_time(const lbm3d_ctx* ctx, int64_t* t);
 
 /* Launch shapes of the step kernel: a block of BX x BY threads owns a
- * BX x BY column of nodes and marches through ZC consecutive z-planes; the
+ * BX x BY column of nodes and marches through ZC consecutive z-planes
+ * ("BXxBYxzZC", "+ntl" when the pulls are loaded non-temporally); the
  * blocks' columns are cut into eight contiguous stretches, one per XCD, so
- * that the y- and z-neighbour rows each pull re-reads are found in the same
- * L2.  lbm3d_shape_describe names candidate `id`; lbm3d_set_shape selects
- * one; lbm3d_autotune times each (median of `reps` launches after a warm-up;
- * the state is not advanced), keeps the fastest and writes its id to *best
- * and, if times_ms is not NULL, one median per shape. */
+ * that x-neighbouring blocks, which share the cache lines their shifted
+ * pulls straddle, run on one L2.  All shapes give identical results.
+ * lbm3d_shape_describe names candidate `id`; lbm3d_set_shape selects one
+ * (default 128x1xz1); lbm3d_autotune times each (median of `reps` launches
+ * after a warm-up; the state is not advanced), keeps the fastest and writes
+ * its id to *best and, if times_ms is not NULL, one median per shape. */
 int lbm3d_shape_count(void);
 int lbm3d_shape_describe(int32_t id, char* buf, size_t len);
 int lbm3d_set_shape(lbm3d_ctx* ctx, int32_t id);

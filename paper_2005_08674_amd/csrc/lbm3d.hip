@@ -296,7 +296,7 @@ constexpr int k3_waves() {
 // Pulls of a node whose y and z neighbours all lie inside.  `idx` is its
 // element index; sxm and sxp are the byte shifts of the pulls with c_x = +1
 // (source x - 1) and c_x = -1 (source x + 1).
-template <int S, int NQ>
+template <int S, int NQ, bool NTL = false>
 __device__ __forceinline__ void pull_row3(const Lat3& L, const typename Codec<S>::T* A, uint32_t idx, int sxm,
                                           int sxp, typename Codec<S>::R g[NQ]) {
   using C = Codec<S>;
@@ -306,7 +306,8 @@ __device__ __forceinline__ void pull_row3(const Lat3& L, const typename Codec<S>
     const char* Ai = reinterpret_cast<const char*>(A + i * L.plane);
     const uint32_t row = (idx - (uint32_t)(kC[i][2] * L.slab + kC[i][1] * L.pitch)) * (uint32_t)sizeof(T);
     const int sh = kC[i][0] > 0 ? sxm : (kC[i][0] < 0 ? sxp : 0);
-    g[i] = C::dec(*reinterpret_cast<const T*>(Ai + (row + (uint32_t)sh)), 1.0f);
+    const T* src = reinterpret_cast<const T*>(Ai + (row + (uint32_t)sh));
+    g[i] = C::dec(NTL ? __builtin_nontemporal_load(src) : *src, 1.0f);
   }
 }
 
@@ -324,7 +325,7 @@ __device__ __forceinline__ void pull_row3(const Lat3& L, const typename Codec<S>
 // neighbour lane write their moments for the next step.  Nodes with y and z
 // inside are written by the wavefront that holds their whole row segment:
 // no cache line of the output is written in parts by different blocks.
-template <int S, int NQ, int BX, int BY, int ZC>
+template <int S, int NQ, int BX, int BY, int ZC, bool NTL>
 __global__ __launch_bounds__(BX* BY, (k3_waves<S, NQ>())) void k3_step(Lat3 L, int parity, int tiles_x, int tiles_y,
                                                                 int nitems, int per) {
   using C = Codec<S>;
@@ -361,7 +362,7 @@ __global__ __launch_bounds__(BX* BY, (k3_waves<S, NQ>())) void k3_step(Lat3 L, i
     const uint32_t idx = (uint32_t)((int64_t)z * L.slab + (int64_t)y * L.pitch + x);
     const bool inner_row = y_inner && z >= 1 && z <= nz - 2;
     if (inner_row) {
-      pull_row3<S, NQ>(L, A, idx, sxm, sxp, g);
+      pull_row3<S, NQ, NTL>(L, A, idx, sxm, sxp, g);
       if (xside) {
         const uint32_t mo = (uint32_t)z * (uint32_t)ny + (uint32_t)y;
         const T* Mb = MA + (x == 0 ? 0 : 8 * mxs);  // slots 0, 1 (x = 0) or 2, 3
@@ -396,37 +397,44 @@ __global__ __launch_bounds__(BX* BY, (k3_waves<S, NQ>())) void k3_step(Lat3 L, i
   }
 }
 
+// Launch shapes: block BX x BY, ZC z-planes per block, non-temporal pull
+// loads (NTL; every stored value is read once, so caching it only displaces
+// the lines that x-neighbouring blocks share).
 struct Shape3 {
   int bx, by, zc;
+  bool ntl;
 };
 #define LBM3D_SHAPES(X) \
-  X(64, 4, 1)           \
-  X(64, 4, 4)           \
-  X(64, 4, 16)          \
-  X(128, 2, 4)          \
-  X(256, 1, 4)          \
-  X(64, 8, 4)           \
-  X(256, 1, 16)
+  X(64, 4, 1, false)    \
+  X(64, 4, 2, false)    \
+  X(64, 4, 4, false)    \
+  X(64, 2, 1, false)    \
+  X(128, 1, 1, false)   \
+  X(128, 2, 4, false)   \
+  X(256, 1, 4, false)   \
+  X(64, 4, 1, true)     \
+  X(64, 2, 1, true)     \
+  X(128, 1, 1, true)
 static const Shape3 kShapes3[] = {
-#define X(a, b, c) {a, b, c},
+#define X(a, b, c, d) {a, b, c, d},
     LBM3D_SHAPES(X)
 #undef X
 };
 static constexpr int kNumShapes3 = sizeof(kShapes3) / sizeof(kShapes3[0]);
 
-template <int S, int NQ, int BX, int BY, int ZC>
+template <int S, int NQ, int BX, int BY, int ZC, bool NTL>
 static hipError_t launch3_t(const Lat3& L, int parity, hipStream_t s) {
   const int tiles_x = (L.nx + BX - 1) / BX, tiles_y = (L.ny + BY - 1) / BY, zch = (L.nz + ZC - 1) / ZC;
   const int nitems = tiles_x * tiles_y * zch, per = (nitems + 7) / 8;
-  k3_step<S, NQ, BX, BY, ZC><<<dim3(8 * per), dim3(BX, BY), 0, s>>>(L, parity, tiles_x, tiles_y, nitems, per);
+  k3_step<S, NQ, BX, BY, ZC, NTL><<<dim3(8 * per), dim3(BX, BY), 0, s>>>(L, parity, tiles_x, tiles_y, nitems, per);
   return hipGetLastError();
 }
 
 template <int S, int NQ>
 static hipError_t launch3_s(const Lat3& L, int parity, int shape, hipStream_t s) {
   int k = 0;
-#define X(a, b, c)                                                    \
-  if (shape == k) return launch3_t<S, NQ, a, b, c>(L, parity, s);    \
+#define X(a, b, c, d)                                                    \
+  if (shape == k) return launch3_t<S, NQ, a, b, c, d>(L, parity, s);    \
   ++k;
   LBM3D_SHAPES(X)
 #undef X
@@ -528,7 +536,7 @@ struct lbm3d_ctx {
   lbm::d3::Lat3 L;
   int parity = 0;
   int64_t t = 0;
-  int shape = 1;
+  int shape = 4;  // 128x1xz1, the fastest on 256^3 in both formats
   hipStream_t stream = nullptr;
 };
 
@@ -692,7 +700,7 @@ int lbm3d_shape_describe(int32_t id, char* buf, size_t len) {
   if (!buf || len == 0) return fail(LBM_ERR_ARG, "NULL buffer");
   if (id < 0 || id >= lbm::d3::kNumShapes3) return fail(LBM_ERR_ARG, "shape id %d out of range", id);
   const lbm::d3::Shape3& s = lbm::d3::kShapes3[id];
-  snprintf(buf, len, "%dx%dxz%d", s.bx, s.by, s.zc);
+  snprintf(buf, len, "%dx%dxz%d%s", s.bx, s.by, s.zc, s.ntl ? "+ntl" : "");
   return LBM_OK;
 }
 
