@@ -59,8 +59,8 @@ typedef struct {
 /* Defaults: 3x3x3, tau 0.6, rho0 1, NSBC on all faces, gamma 0.6, FP32, D3Q19. */
 int lbm3d_params_default(lbm3d_params* p);
 
-/* Device workspace in bytes: two population buffers of q planes and two
- * small buffers of moments of the nodes next to the x faces. */
+/* Device workspace in bytes: two population buffers of q planes, two small
+ * buffers of moments of the nodes next to the x faces, and a flag. */
 int lbm3d_workspace_bytes(const lbm3d_params* p, size_t* bytes);
 
 /* Create a context on `workspace` (device memory of at least
@@ -82,6 +82,17 @@ int lbm3d_moments(lbm3d_ctx* ctx, double* out);
 
 /* Steps taken. */
 int lbm3d_time(const lbm3d_ctx* ctx, int64_t* t);
+
+/* Checkpoint and restore: the state (the post-collision populations of the
+ * current time, f_i - w_i rho0) to or from a device float64 [q][nz][ny][nx]
+ * array.  Setting also refreshes the x-face moments the next step reads.
+ * Asynchronous. */
+int lbm3d_get_populations(lbm3d_ctx* ctx, double* out);
+int lbm3d_set_populations(lbm3d_ctx* ctx, const double* in);
+
+/* *ok = 1 if every stored population is finite, else 0 (and the call returns
+ * LBM_ERR_NONFINITE).  Synchronizes the stream. */
+int lbm3d_check_finite(lbm3d_ctx* ctx, int* ok);
 
 /* Launch shapes of the step kernel: a block of BX x BY threads owns a
  * BX x BY column of nodes and marches through ZC consecutive z-planes

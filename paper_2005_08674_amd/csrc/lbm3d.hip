@@ -319,10 +319,10 @@ __device__ __forceinline__ void pull_row3(const Lat3& L, const typename Codec<S>
 // wavefront is a run of x).  In the other rows an x-face node is one lane of
 // a wavefront: it pulls with the others (the x shift adjusted), and on a NSBC
 // face it takes the moments at time t of itself and of its inner neighbour
-// from Lat3::mx instead of loading 2 q stored populations (BGK conserves mass
-// and momentum, so the moments the collision of the previous step computed
-// are those of the populations it stored).  Every x-face lane and its inner
-// neighbour lane write their moments for the next step.  Nodes with y and z
+// from Lat3::mx instead of loading 2 q stored populations: the lanes of those
+// nodes in the previous step summed the populations they stored (the same
+// sums node_moments3 would form from memory) and wrote them there.  Nodes
+// with y and z
 // inside are written by the wavefront that holds their whole row segment:
 // no cache line of the output is written in parts by different blocks.
 template <int S, int NQ, int BX, int BY, int ZC, bool NTL>
@@ -377,10 +377,13 @@ __global__ __launch_bounds__(BX* BY, (k3_waves<S, NQ>())) void k3_step(Lat3 L, i
     } else {
       boundary_node3<S, NQ>(L, A, x, y, z, g);
     }
-    R m[4];
-    bgk3<NQ, R>(g, rho0, omega, m);
+    bgk3<NQ, R>(g, rho0, omega);
     if (inner_row && mwrite) {
-      // slot 0: x = 0, 1: x = 1, 2: x = nx - 1, 3: x = nx - 2 (both 1 and 3 when nx = 3)
+      // moments of the populations stored below (the storage formats here
+      // hold R exactly); slot 0: x = 0, 1: x = 1, 2: x = nx - 1, 3: x = nx - 2
+      // (both 1 and 3 when nx = 3)
+      R m[4];
+      moments3<NQ, R>(g, rho0, m);
       const uint32_t mo = (uint32_t)z * (uint32_t)ny + (uint32_t)y;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
@@ -447,6 +450,30 @@ static hipError_t launch3(const Lat3& L, int parity, int shape, hipStream_t s) {
   return L.store == ST_F64 ? launch3_s<ST_F64, 19>(L, parity, shape, s) : launch3_s<ST_F32, 19>(L, parity, shape, s);
 }
 
+// The x-face slots of Lat3::mx[parity] for node (x, y, z) (x = 0, 1, nx - 2,
+// nx - 1 only), from the values just written to the node: the moments of the
+// populations as stored.
+template <int S, int NQ>
+__device__ inline void mx_from_stored(const Lat3& L, int parity, int x, int y, int z, const double v[NQ]) {
+  using T = typename Codec<S>::T;
+  using R = typename Codec<S>::R;
+  const int nx = L.nx;
+  if (x > 1 && x < nx - 2) return;
+  R g[NQ], ms[4];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) g[i] = R((T)v[i]);
+  moments3<NQ, R>(g, R(L.rho0), ms);
+  T* M = static_cast<T*>(L.mx[parity]);
+  const int64_t mo = (int64_t)z * L.ny + y;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (x == 0) M[(0 * 4 + c) * L.mxs + mo] = T(ms[c]);
+    if (x == 1) M[(1 * 4 + c) * L.mxs + mo] = T(ms[c]);
+    if (x == nx - 2) M[(3 * 4 + c) * L.mxs + mo] = T(ms[c]);
+    if (x == nx - 1) M[(2 * 4 + c) * L.mxs + mo] = T(ms[c]);
+  }
+}
+
 // f = f^eq(rho, u) of the initial fields, as deviations
 template <int S, int NQ>
 __global__ void k3_init(Lat3 L, const double* __restrict__ drho, const double* __restrict__ ux,
@@ -462,23 +489,7 @@ __global__ void k3_init(Lat3 L, const double* __restrict__ drho, const double* _
   const int64_t idx = (int64_t)z * L.slab + (int64_t)y * L.pitch + x;
 #pragma unroll
   for (int i = 0; i < NQ; ++i) B[i * L.plane + idx] = (T)geq[i];
-  // moments of the stored populations for the x-face slots of Lat3::mx
-  const int nx = L.nx;
-  if (x > 1 && x < nx - 2) return;
-  using R = typename Codec<S>::R;
-  R g[NQ], ms[4];
-#pragma unroll
-  for (int i = 0; i < NQ; ++i) g[i] = R((T)geq[i]);
-  moments3<NQ, R>(g, R(L.rho0), ms);
-  T* M = static_cast<T*>(L.mx[0]);
-  const int64_t mo = (int64_t)z * L.ny + y;
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    if (x == 0) M[(0 * 4 + c) * L.mxs + mo] = T(ms[c]);
-    if (x == 1) M[(1 * 4 + c) * L.mxs + mo] = T(ms[c]);
-    if (x == nx - 2) M[(3 * 4 + c) * L.mxs + mo] = T(ms[c]);
-    if (x == nx - 1) M[(2 * 4 + c) * L.mxs + mo] = T(ms[c]);
-  }
+  mx_from_stored<S, NQ>(L, 0, x, y, z, geq);
 }
 
 template <int S, int NQ>
@@ -493,6 +504,79 @@ __global__ void k3_moments(Lat3 L, int parity, double* __restrict__ out) {
   const int64_t n = (int64_t)L.nx * L.ny * L.nz, k = ((int64_t)z * L.ny + y) * L.nx + x;
 #pragma unroll
   for (int c = 0; c < 4; ++c) out[c * n + k] = (double)m[c];
+}
+
+// Stored populations (f_i - w_i rho0) of buffer `parity` into out[q][nz][ny][nx].
+template <int S, int NQ>
+__global__ void k3_get_pops(Lat3 L, int parity, double* __restrict__ out) {
+  using T = typename Codec<S>::T;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+  if (x >= L.nx) return;
+  const T* A = static_cast<const T*>(parity ? L.buf[1] : L.buf[0]);
+  const int64_t idx = (int64_t)z * L.slab + (int64_t)y * L.pitch + x;
+  const int64_t n = (int64_t)L.nx * L.ny * L.nz, k = ((int64_t)z * L.ny + y) * L.nx + x;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) out[i * n + k] = (double)A[i * L.plane + idx];
+}
+
+// Overwrite buffer `parity` (and its x-face moments) with in[q][nz][ny][nx].
+template <int S, int NQ>
+__global__ void k3_set_pops(Lat3 L, int parity, const double* __restrict__ in) {
+  using T = typename Codec<S>::T;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+  if (x >= L.nx) return;
+  T* A = static_cast<T*>(parity ? L.buf[1] : L.buf[0]);
+  const int64_t idx = (int64_t)z * L.slab + (int64_t)y * L.pitch + x;
+  const int64_t n = (int64_t)L.nx * L.ny * L.nz, k = ((int64_t)z * L.ny + y) * L.nx + x;
+  double v[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    v[i] = in[i * n + k];
+    A[i * L.plane + idx] = (T)v[i];
+  }
+  mx_from_stored<S, NQ>(L, parity, x, y, z, v);
+}
+
+// *bad = 1 if a stored population of buffer `parity` is not finite.
+template <int S, int NQ>
+__global__ void k3_finite(Lat3 L, int parity, int* bad) {
+  using T = typename Codec<S>::T;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+  if (x >= L.nx) return;
+  const T* A = static_cast<const T*>(parity ? L.buf[1] : L.buf[0]);
+  const int64_t idx = (int64_t)z * L.slab + (int64_t)y * L.pitch + x;
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) ok = ok && isfinite((double)A[i * L.plane + idx]);
+  if (!ok) *bad = 1;
+}
+
+// Launch one of the per-node kernels above for the context's store and q.
+#define LBM3D_NODE_LAUNCH(KERNEL, L, s, ...)                                                   \
+  do {                                                                                       \
+    const dim3 grid_((L.nx + 255) / 256, L.ny, L.nz);                                          \
+    if (L.q == 27) {                                                                         \
+      if (L.store == ST_F64) KERNEL<ST_F64, 27><<<grid_, dim3(256), 0, s>>>(L, __VA_ARGS__);   \
+      else KERNEL<ST_F32, 27><<<grid_, dim3(256), 0, s>>>(L, __VA_ARGS__);                     \
+    } else {                                                                                 \
+      if (L.store == ST_F64) KERNEL<ST_F64, 19><<<grid_, dim3(256), 0, s>>>(L, __VA_ARGS__);   \
+      else KERNEL<ST_F32, 19><<<grid_, dim3(256), 0, s>>>(L, __VA_ARGS__);                     \
+    }                                                                                        \
+  } while (0)
+
+static hipError_t launch_get_pops3(const Lat3& L, int parity, double* out, hipStream_t s) {
+  LBM3D_NODE_LAUNCH(k3_get_pops, L, s, parity, out);
+  return hipGetLastError();
+}
+
+static hipError_t launch_set_pops3(const Lat3& L, int parity, const double* in, hipStream_t s) {
+  LBM3D_NODE_LAUNCH(k3_set_pops, L, s, parity, in);
+  return hipGetLastError();
+}
+
+static hipError_t launch_finite3(const Lat3& L, int parity, int* bad, hipStream_t s) {
+  LBM3D_NODE_LAUNCH(k3_finite, L, s, parity, bad);
+  return hipGetLastError();
 }
 
 static hipError_t launch_init3(const Lat3& L, const double* drho, const double* ux, const double* uy,
@@ -538,6 +622,7 @@ struct lbm3d_ctx {
   int64_t t = 0;
   int shape = 4;  // 128x1xz1, the fastest on 256^3 in both formats
   hipStream_t stream = nullptr;
+  int* flag = nullptr;  // device int in the workspace (lbm3d_check_finite)
 };
 
 namespace {
@@ -590,7 +675,7 @@ Layout3 layout3(const lbm3d_params* p) {
   l.q = p->velocity_set == LBM3D_D3Q27 ? 27 : 19;
   l.buf_bytes = round_up((size_t)l.q * plane_bytes, (size_t)2 << 20);
   l.mx_bytes = round_up((size_t)16 * p->ny * p->nz * l.esize, 4096);
-  l.total = 2 * l.buf_bytes + 2 * l.mx_bytes;
+  l.total = 2 * l.buf_bytes + 2 * l.mx_bytes + 256;  // + the check_finite flag
   return l;
 }
 
@@ -635,6 +720,7 @@ int lbm3d_init(lbm3d_ctx** out, const lbm3d_params* p, void* workspace, size_t b
   L.buf[1] = static_cast<char*>(workspace) + lay.buf_bytes;
   L.mx[0] = static_cast<char*>(workspace) + 2 * lay.buf_bytes;
   L.mx[1] = static_cast<char*>(workspace) + 2 * lay.buf_bytes + lay.mx_bytes;
+  c->flag = reinterpret_cast<int*>(static_cast<char*>(workspace) + 2 * lay.buf_bytes + 2 * lay.mx_bytes);
   L.mxs = (int64_t)p->ny * p->nz;
   L.nx = p->nx;
   L.ny = p->ny;
@@ -686,6 +772,29 @@ int lbm3d_moments(lbm3d_ctx* c, double* out) {
   if (!c || !out) return fail(LBM_ERR_ARG, "NULL argument");
   HIPCHK3(lbm::d3::launch_moments3(c->L, c->parity, out, c->stream));
   return LBM_OK;
+}
+
+int lbm3d_get_populations(lbm3d_ctx* c, double* out) {
+  if (!c || !out) return fail(LBM_ERR_ARG, "NULL argument");
+  HIPCHK3(lbm::d3::launch_get_pops3(c->L, c->parity, out, c->stream));
+  return LBM_OK;
+}
+
+int lbm3d_set_populations(lbm3d_ctx* c, const double* in) {
+  if (!c || !in) return fail(LBM_ERR_ARG, "NULL argument");
+  HIPCHK3(lbm::d3::launch_set_pops3(c->L, c->parity, in, c->stream));
+  return LBM_OK;
+}
+
+int lbm3d_check_finite(lbm3d_ctx* c, int* ok) {
+  if (!c || !ok) return fail(LBM_ERR_ARG, "NULL argument");
+  int host = 0;
+  HIPCHK3(hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
+  HIPCHK3(lbm::d3::launch_finite3(c->L, c->parity, c->flag, c->stream));
+  HIPCHK3(hipMemcpyAsync(&host, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK3(hipStreamSynchronize(c->stream));
+  *ok = host ? 0 : 1;
+  return host ? fail(LBM_ERR_NONFINITE, "populations hold a non-finite value at t = %lld", (long long)c->t) : LBM_OK;
 }
 
 int lbm3d_time(const lbm3d_ctx* c, int64_t* t) {

@@ -55,6 +55,21 @@ class Lattice3D:
         self.stream.synchronize()
         return tuple(out.cpu().numpy())
 
+    def populations(self):
+        """The state (post-collision f_i - w_i rho0) as a float64 torch tensor [q][nz][ny][nx] on the device."""
+        g = torch.empty((self.q,) + self.shape, dtype=torch.float64, device=self.device)
+        L.lbm3d_get_populations(self.ctx, g.data_ptr())
+        self.stream.synchronize()
+        return g
+
+    def set_populations(self, g):
+        g = torch.as_tensor(g).to(device=self.device, dtype=torch.float64).contiguous()
+        L.lbm3d_set_populations(self.ctx, g.data_ptr())
+        self.stream.synchronize()
+
+    def check_finite(self) -> bool:
+        return L.lbm3d_check_finite(self.ctx)
+
     def autotune(self, reps=5):
         return L.lbm3d_autotune(self.ctx, reps)
 

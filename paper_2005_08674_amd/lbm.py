@@ -115,6 +115,9 @@ _SIGS = {
     "lbm3d_step": [_P, ctypes.c_int32],
     "lbm3d_moments": [_P, _P],
     "lbm3d_time": [_P, _P],
+    "lbm3d_get_populations": [_P, _P],
+    "lbm3d_set_populations": [_P, _P],
+    "lbm3d_check_finite": [_P, _P],
     "lbm3d_shape_count": [],
     "lbm3d_shape_describe": [ctypes.c_int32, _P, ctypes.c_size_t],
     "lbm3d_set_shape": [_P, ctypes.c_int32],
@@ -583,6 +586,23 @@ def lbm3d_step(ctx, n: int):
 
 def lbm3d_moments(ctx, out_ptr):
     _check(load().lbm3d_moments(ctx, out_ptr), "lbm3d_moments")
+
+
+def lbm3d_get_populations(ctx, out_ptr):
+    _check(load().lbm3d_get_populations(ctx, out_ptr), "lbm3d_get_populations")
+
+
+def lbm3d_set_populations(ctx, in_ptr):
+    _check(load().lbm3d_set_populations(ctx, in_ptr), "lbm3d_set_populations")
+
+
+def lbm3d_check_finite(ctx) -> bool:
+    """True if every stored population is finite (synchronizes the stream)."""
+    ok = ctypes.c_int()
+    rc = load().lbm3d_check_finite(ctx, ctypes.byref(ok))
+    if rc not in (LBM_OK, LBM_ERR_NONFINITE):
+        _check(rc, "lbm3d_check_finite")
+    return bool(ok.value)
 
 
 def lbm3d_time(ctx) -> int:

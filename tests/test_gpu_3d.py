@@ -90,3 +90,74 @@ def test_autotune_leaves_the_state_and_picks_a_shape(q):
     a.step(5)
     b.step(5)
     assert np.array_equal(np.array(a.moments()), np.array(b.moments()))
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_checkpoint_restore_continues_bitwise(q):
+    """get_populations / set_populations round-trip the state: a lattice restored from a checkpoint
+    steps on exactly as the one it was taken from (the x-face moments are rebuilt on restore)."""
+    from paper_2005_08674_amd.lattice3d import Lattice3D
+    f = _fields(40, 12, 10)
+    a = Lattice3D(40, 12, 10, 0.6, f, store="f64", beta=0.2, m0=(1.0, 0.03, -0.02, 0.01), q=q)
+    b = Lattice3D(40, 12, 10, 0.6, f, store="f64", beta=0.2, m0=(1.0, 0.03, -0.02, 0.01), q=q)
+    a.step(7)
+    snap = a.populations()
+    b.set_populations(torch.zeros_like(snap))
+    b.set_populations(snap)
+    assert torch.equal(b.populations(), snap)
+    a.step(9)
+    b.step(9)
+    assert np.array_equal(np.array(a.moments()), np.array(b.moments()))
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("bc", [(1,) * 6, (1, 1, 0, 0, 1, 1)])
+def test_non_equilibrium_state_against_oracle(q, bc):
+    """Start from populations away from equilibrium (f^eq plus seeded noise), set on the GPU as the
+    post-collision state P.  The oracle holds the pre-collision state G whose BGK collision is P:
+    G = (tau P - f^eq(m(P))) / (tau - 1), with m and f^eq from the oracle's own node functions.
+    FP64 moments must agree within 1e-12 over 40 steps."""
+    from paper_2005_08674_amd.lattice3d import Lattice3D
+    nx, ny, nz, tau = 11, 9, 8, 0.62
+    rng = np.random.default_rng(11)
+    zero = np.zeros((nz, ny, nx))
+    u0 = (0.02, -0.01, 0.015)
+    base = [zero] + [np.full_like(zero, v) for v in u0]
+    m0 = (1.0, *u0)
+    g = Lattice3D(nx, ny, nz, tau, base, store="f64", bc=bc, beta=0.2, m0=m0, q=q)
+    P = g.populations().cpu().numpy() + 2e-4 * rng.standard_normal((q, nz, ny, nx)) / q
+    g.set_populations(P)
+    o = oracle.Lattice3D(nx, ny, nz, tau, *base, bc=bc, beta=0.2, m0=m0, q=q)
+    G = np.empty_like(P)
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                p = P[:, z, y, x]
+                geq = oracle.feq_3d(1.0, oracle.moments_node_3d(1.0, p), q=q)
+                G[:, z, y, x] = (tau * p - geq) / (tau - 1)
+    o.g[...] = G
+    assert np.allclose(oracle.collide_node_3d(tau, 1.0, G[:, 3, 4, 5]), P[:, 3, 4, 5], atol=1e-17)
+    for t in (1, 10, 40):
+        g.step(t - g.t)
+        o.step(t - o.t)
+        gm, om = g.moments(), o.moments()
+        er = np.abs(gm[0] - om[0]).max()
+        eu = max(np.abs(gm[a] - om[a]).max() for a in (1, 2, 3)) / 0.02
+        print(f"  D3Q{q} bc={bc} t={t} e_rho={er:.3e} e_u={eu:.3e}", flush=True)
+        assert er <= 1e-12 and eu <= 1e-12, (t, er, eu)
+    g.close()
+
+
+def test_check_finite():
+    from paper_2005_08674_amd.lattice3d import Lattice3D
+    f = _fields(20, 6, 5)
+    g = Lattice3D(20, 6, 5, 0.6, f, store="f32")
+    g.step(3)
+    assert g.check_finite()
+    p = g.populations()
+    p[7, 2, 3, 4] = float("nan")
+    g.set_populations(p)
+    assert not g.check_finite()
+    g.close()
