@@ -256,16 +256,16 @@ def run_tc2(torch, W, every=50):
 
 def run_3d(torch, W, steps, n=256, q=19):
     """The D3Q19 (q = 19) or D3Q27 (q = 27) sweep on an n^3 lattice (8 seeded pulses, tau 0.55, NSBC on all
-    six faces), FP32 and FP64 storage: MLUPS over `steps` steps in one timed region after the shape
-    autotuner, and the algorithmic-bytes fraction of the HBM peak (2 x q x s bytes per node-step, one
-    launch per step)."""
+    six faces), FP32, FP64, FP16 and BF16 storage: MLUPS over `steps` steps in one timed region after the
+    shape autotuner, and the algorithmic-bytes fraction of the HBM peak (2 x q x s bytes per node-step,
+    one launch per step)."""
     from paper_2005_08674_amd import lbm
     from paper_2005_08674_amd.lattice3d import Lattice3D
 
     fields, _ = W.pulses_3d(n)
     out = {"workload": f"pulses3d{n}: {n}^3 D3Q{q} BGK tau 0.55, 8 seeded Gaussian pulses, NSBC (gamma 0.6, "
                        "beta 0) on 6 faces", "steps": steps}
-    for store, s in (("f32", 4), ("f64", 8)):
+    for store, s in (("f32", 4), ("f64", 8), ("f16", 2), ("bf16", 2)):
         lat = Lattice3D(n, n, n, 0.55, fields, store=store, q=q)
         best, times = lat.autotune(reps=5)
         lat.step(10)

@@ -23,8 +23,8 @@
  *
  * Memory: all device memory belongs to the caller (a workspace of
  * lbm3d_workspace_bytes); the context is a host object.  Population i of
- * node (x, y, z) is stored as the deviation f_i - w_i rho0 in q planes of
- * [nz][ny][pitch].  Calls return 0 or a negative LBM_ERR_* code (lbm.h) and
+ * node (x, y, z) is stored as the deviation f_i - w_i rho0 (encoded in the
+ * storage format) in q planes of [nz][ny][pitch].  Calls return 0 or a negative LBM_ERR_* code (lbm.h) and
  * never abort; lbm_last_error() describes the last failure.  Work is
  * asynchronous on the stream given at init.
  */
@@ -52,7 +52,10 @@ typedef struct {
     int32_t bc[6];        /* LBM_BC_PERIODIC or LBM_BC_NSBC per face: x = 0, x = nx-1, y = 0,
                              y = ny-1, z = 0, z = nz-1; periodic faces come in pairs */
     double gamma;         /* eq. nes_2 */
-    int32_t store;        /* LBM_STORE_F64 or LBM_STORE_F32 */
+    int32_t store;        /* LBM_STORE_F64, LBM_STORE_F32, LBM_STORE_F16DEV or LBM_STORE_BF16DEV
+                             (FP32 arithmetic for the last three; the 16-bit formats store
+                             g_i / w_i, FP16 also scaled by 2^k, k chosen at init so the largest
+                             initial value is about 2^12, as in lbm.h) */
     int32_t velocity_set; /* LBM3D_D3Q19 (q = 19) or LBM3D_D3Q27 (q = 27) */
 } lbm3d_params;
 
@@ -60,7 +63,8 @@ typedef struct {
 int lbm3d_params_default(lbm3d_params* p);
 
 /* Device workspace in bytes: two population buffers of q planes, two small
- * buffers of moments of the nodes next to the x faces, and a flag. */
+ * buffers of moments of the nodes next to the x faces, and 1.25 KiB of
+ * scratch (a flag, the FP16 exponent reduction). */
 int lbm3d_workspace_bytes(const lbm3d_params* p, size_t* bytes);
 
 /* Create a context on `workspace` (device memory of at least
@@ -82,6 +86,9 @@ int lbm3d_moments(lbm3d_ctx* ctx, double* out);
 
 /* Steps taken. */
 int lbm3d_time(const lbm3d_ctx* ctx, int64_t* t);
+
+/* FP16 scale exponent k in use (0 for the other formats). */
+int lbm3d_f16_exp(const lbm3d_ctx* ctx, int32_t* k);
 
 /* Checkpoint and restore: the state (the post-collision populations of the
  * current time, f_i - w_i rho0) to or from a device float64 [q][nz][ny][nx]

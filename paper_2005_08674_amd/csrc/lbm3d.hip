@@ -58,6 +58,10 @@ struct Lat3 {
   int32_t store, q;  // q: velocity set, 19 or 27
   double omega, rho0, gamma, beta;
   double m0[4];   // far field (rho - rho0, ux, uy, uz)
+  // storage codec scales per population: a stored value is enc(g_i, es[i])
+  // and decodes as dec(v, ds[i]) (1 for FP64/FP32; 2^k / w_i and w_i 2^-k for
+  // FP16, k chosen at init; 1 / w_i and w_i for BF16)
+  float es[27], ds[27];
 };
 
 template <int NQ, class R>
@@ -129,7 +133,7 @@ __device__ inline void node_moments3(const Lat3& L, const typename Codec<S>::T* 
   R s = R(0), j[3] = {R(0), R(0), R(0)};
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
-    const R v = C::dec(*reinterpret_cast<const T*>(reinterpret_cast<const char*>(A + i * L.plane) + off), 1.0f);
+    const R v = C::dec(*reinterpret_cast<const T*>(reinterpret_cast<const char*>(A + i * L.plane) + off), L.ds[i]);
     s += v;
 #pragma unroll
     for (int a = 0; a < 3; ++a)
@@ -174,7 +178,7 @@ __device__ inline void boundary_node3(const Lat3& L, const typename Codec<S>::T*
     }
     unknown |= (uint32_t)out << i;
     g[i] = C::dec(*reinterpret_cast<const T*>(reinterpret_cast<const char*>(A + i * L.plane) + src * sizeof(T)),
-                  1.0f);
+                  L.ds[i]);
   }
   if (!unknown) return;
   // eq. nes_2 with the normalised normal of the k NSBC faces the node is on
@@ -286,11 +290,12 @@ __device__ inline void xface_nsbc3(const Lat3& L, const typename Codec<S>::R mb[
 }
 
 // Register budget: the shell paths would otherwise take more registers than
-// the interior path and cost every node occupancy.  D3Q19 fits 6 waves per
-// SIMD in FP32 and 4 in FP64 without spills, D3Q27 5 and 3.
+// the interior path and cost every node occupancy.  Without spills D3Q19 fits
+// 6 waves per SIMD in FP32, 5 with a 16-bit format (its per-population
+// scales take registers) and 4 in FP64; D3Q27 5, 4 and 3.
 template <int S, int NQ>
 constexpr int k3_waves() {
-  return NQ == 19 ? (S == ST_F64 ? 4 : 6) : (S == ST_F64 ? 3 : 5);
+  return S == ST_F64 ? (NQ == 19 ? 4 : 3) : S == ST_F32 ? (NQ == 19 ? 6 : 5) : (NQ == 19 ? 5 : 4);
 }
 
 // Pulls of a node whose y and z neighbours all lie inside.  `idx` is its
@@ -307,7 +312,7 @@ __device__ __forceinline__ void pull_row3(const Lat3& L, const typename Codec<S>
     const uint32_t row = (idx - (uint32_t)(kC[i][2] * L.slab + kC[i][1] * L.pitch)) * (uint32_t)sizeof(T);
     const int sh = kC[i][0] > 0 ? sxm : (kC[i][0] < 0 ? sxp : 0);
     const T* src = reinterpret_cast<const T*>(Ai + (row + (uint32_t)sh));
-    g[i] = C::dec(NTL ? __builtin_nontemporal_load(src) : *src, 1.0f);
+    g[i] = C::dec(NTL ? __builtin_nontemporal_load(src) : *src, L.ds[i]);
   }
 }
 
@@ -342,8 +347,8 @@ __global__ __launch_bounds__(BX* BY, (k3_waves<S, NQ>())) void k3_step(Lat3 L, i
   if (x >= nx || y >= ny) return;
   const T* __restrict__ A = static_cast<const T*>(parity ? L.buf[1] : L.buf[0]);
   T* __restrict__ B = static_cast<T*>(parity ? L.buf[0] : L.buf[1]);
-  const T* __restrict__ MA = static_cast<const T*>(parity ? L.mx[1] : L.mx[0]);
-  T* __restrict__ MB = static_cast<T*>(parity ? L.mx[0] : L.mx[1]);
+  const R* __restrict__ MA = static_cast<const R*>(parity ? L.mx[1] : L.mx[0]);
+  R* __restrict__ MB = static_cast<R*>(parity ? L.mx[0] : L.mx[1]);
   const R rho0 = R(L.rho0), omega = R(L.omega);
   const bool y_inner = y >= 1 && y <= ny - 2;
   // Byte shifts of the pulls with c_x = +1 (source x - 1) and c_x = -1
@@ -365,7 +370,7 @@ __global__ __launch_bounds__(BX* BY, (k3_waves<S, NQ>())) void k3_step(Lat3 L, i
       pull_row3<S, NQ, NTL>(L, A, idx, sxm, sxp, g);
       if (xside) {
         const uint32_t mo = (uint32_t)z * (uint32_t)ny + (uint32_t)y;
-        const T* Mb = MA + (x == 0 ? 0 : 8 * mxs);  // slots 0, 1 (x = 0) or 2, 3
+        const R* Mb = MA + (x == 0 ? 0 : 8 * mxs);  // slots 0, 1 (x = 0) or 2, 3
         R mb[4], mn[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -379,24 +384,26 @@ __global__ __launch_bounds__(BX* BY, (k3_waves<S, NQ>())) void k3_step(Lat3 L, i
     }
     bgk3<NQ, R>(g, rho0, omega);
     if (inner_row && mwrite) {
-      // moments of the populations stored below (the storage formats here
-      // hold R exactly); slot 0: x = 0, 1: x = 1, 2: x = nx - 1, 3: x = nx - 2
-      // (both 1 and 3 when nx = 3)
-      R m[4];
-      moments3<NQ, R>(g, rho0, m);
+      // moments of the populations stored below, as they decode; slot 0:
+      // x = 0, 1: x = 1, 2: x = nx - 1, 3: x = nx - 2 (both 1 and 3 when nx = 3)
+      R gs[NQ], m[4];
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) gs[i] = C::dec(C::enc(g[i], L.es[i]), L.ds[i]);
+      moments3<NQ, R>(gs, rho0, m);
       const uint32_t mo = (uint32_t)z * (uint32_t)ny + (uint32_t)y;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        if (x == 0) MB[c * mxs + mo] = T(m[c]);
-        if (x == 1) MB[(4 + c) * mxs + mo] = T(m[c]);
-        if (x == nx - 1) MB[(8 + c) * mxs + mo] = T(m[c]);
-        if (x == nx - 2) MB[(12 + c) * mxs + mo] = T(m[c]);
+        if (x == 0) MB[c * mxs + mo] = m[c];
+        if (x == 1) MB[(4 + c) * mxs + mo] = m[c];
+        if (x == nx - 1) MB[(8 + c) * mxs + mo] = m[c];
+        if (x == nx - 2) MB[(12 + c) * mxs + mo] = m[c];
       }
     }
     const uint32_t off = idx * (uint32_t)sizeof(T);
 #pragma unroll
     for (int i = 0; i < NQ; ++i)
-      __builtin_nontemporal_store(C::enc(g[i], 1.0f), reinterpret_cast<T*>(reinterpret_cast<char*>(B + i * L.plane) + off));
+      __builtin_nontemporal_store(C::enc(g[i], L.es[i]),
+                                  reinterpret_cast<T*>(reinterpret_cast<char*>(B + i * L.plane) + off));
   }
 }
 
@@ -444,34 +451,70 @@ static hipError_t launch3_s(const Lat3& L, int parity, int shape, hipStream_t s)
   return hipErrorInvalidValue;
 }
 
+template <int NQ>
+static hipError_t launch3_q(const Lat3& L, int parity, int shape, hipStream_t s) {
+  switch (L.store) {
+    case ST_F64: return launch3_s<ST_F64, NQ>(L, parity, shape, s);
+    case ST_F32: return launch3_s<ST_F32, NQ>(L, parity, shape, s);
+    case ST_F16: return launch3_s<ST_F16, NQ>(L, parity, shape, s);
+    case ST_BF16: return launch3_s<ST_BF16, NQ>(L, parity, shape, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 static hipError_t launch3(const Lat3& L, int parity, int shape, hipStream_t s) {
-  if (L.q == 27)
-    return L.store == ST_F64 ? launch3_s<ST_F64, 27>(L, parity, shape, s) : launch3_s<ST_F32, 27>(L, parity, shape, s);
-  return L.store == ST_F64 ? launch3_s<ST_F64, 19>(L, parity, shape, s) : launch3_s<ST_F32, 19>(L, parity, shape, s);
+  return L.q == 27 ? launch3_q<27>(L, parity, shape, s) : launch3_q<19>(L, parity, shape, s);
 }
 
 // The x-face slots of Lat3::mx[parity] for node (x, y, z) (x = 0, 1, nx - 2,
-// nx - 1 only), from the values just written to the node: the moments of the
-// populations as stored.
+// nx - 1 only), from the values `v` just stored at the node: the moments of
+// the populations as they decode.
 template <int S, int NQ>
-__device__ inline void mx_from_stored(const Lat3& L, int parity, int x, int y, int z, const double v[NQ]) {
-  using T = typename Codec<S>::T;
-  using R = typename Codec<S>::R;
+__device__ inline void mx_from_stored(const Lat3& L, int parity, int x, int y, int z,
+                                      const typename Codec<S>::T v[NQ]) {
+  using C = Codec<S>;
+  using R = typename C::R;
   const int nx = L.nx;
   if (x > 1 && x < nx - 2) return;
   R g[NQ], ms[4];
 #pragma unroll
-  for (int i = 0; i < NQ; ++i) g[i] = R((T)v[i]);
+  for (int i = 0; i < NQ; ++i) g[i] = C::dec(v[i], L.ds[i]);
   moments3<NQ, R>(g, R(L.rho0), ms);
-  T* M = static_cast<T*>(L.mx[parity]);
+  R* M = static_cast<R*>(L.mx[parity]);
   const int64_t mo = (int64_t)z * L.ny + y;
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    if (x == 0) M[(0 * 4 + c) * L.mxs + mo] = T(ms[c]);
-    if (x == 1) M[(1 * 4 + c) * L.mxs + mo] = T(ms[c]);
-    if (x == nx - 2) M[(3 * 4 + c) * L.mxs + mo] = T(ms[c]);
-    if (x == nx - 1) M[(2 * 4 + c) * L.mxs + mo] = T(ms[c]);
+    if (x == 0) M[(0 * 4 + c) * L.mxs + mo] = ms[c];
+    if (x == 1) M[(1 * 4 + c) * L.mxs + mo] = ms[c];
+    if (x == nx - 2) M[(3 * 4 + c) * L.mxs + mo] = ms[c];
+    if (x == nx - 1) M[(2 * 4 + c) * L.mxs + mo] = ms[c];
   }
+}
+
+// Largest |g^eq_i / w_i| of the initial state (deviation form), one partial
+// per block of a fixed 256 x 256 grid (a fixed-order tree in each block): the
+// host picks the FP16 scale exponent from it.
+template <int NQ>
+__global__ __launch_bounds__(256) void k3_absmax(Lat3 L, const double* __restrict__ drho,
+                                                 const double* __restrict__ ux, const double* __restrict__ uy,
+                                                 const double* __restrict__ uz, float* __restrict__ part) {
+  __shared__ float red[256];
+  const int64_t n = (int64_t)L.nx * L.ny * L.nz;
+  float mx = 0.f;
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += 256 * 256) {
+    const double m[4] = {drho[k], ux[k], uy[k], uz[k]};
+    double geq[NQ];
+    equilibrium3<NQ, double>(L.rho0, m, geq);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) mx = fmaxf(mx, (float)fabs(geq[i] / w3<NQ, double>(i)));
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
 // f = f^eq(rho, u) of the initial fields, as deviations
@@ -485,11 +528,16 @@ __global__ void k3_init(Lat3 L, const double* __restrict__ drho, const double* _
   const double m[4] = {drho[k], ux[k], uy[k], uz[k]};
   double geq[NQ];
   equilibrium3<NQ, double>(L.rho0, m, geq);
+  using C = Codec<S>;
   T* B = static_cast<T*>(L.buf[0]);
   const int64_t idx = (int64_t)z * L.slab + (int64_t)y * L.pitch + x;
+  T v[NQ];
 #pragma unroll
-  for (int i = 0; i < NQ; ++i) B[i * L.plane + idx] = (T)geq[i];
-  mx_from_stored<S, NQ>(L, 0, x, y, z, geq);
+  for (int i = 0; i < NQ; ++i) {
+    v[i] = C::enc(typename C::R(geq[i] * (double)L.es[i]), 1.0f);
+    B[i * L.plane + idx] = v[i];
+  }
+  mx_from_stored<S, NQ>(L, 0, x, y, z, v);
 }
 
 template <int S, int NQ>
@@ -516,7 +564,7 @@ __global__ void k3_get_pops(Lat3 L, int parity, double* __restrict__ out) {
   const int64_t idx = (int64_t)z * L.slab + (int64_t)y * L.pitch + x;
   const int64_t n = (int64_t)L.nx * L.ny * L.nz, k = ((int64_t)z * L.ny + y) * L.nx + x;
 #pragma unroll
-  for (int i = 0; i < NQ; ++i) out[i * n + k] = (double)A[i * L.plane + idx];
+  for (int i = 0; i < NQ; ++i) out[i * n + k] = (double)Codec<S>::dec(A[i * L.plane + idx], L.ds[i]);
 }
 
 // Overwrite buffer `parity` (and its x-face moments) with in[q][nz][ny][nx].
@@ -528,11 +576,12 @@ __global__ void k3_set_pops(Lat3 L, int parity, const double* __restrict__ in) {
   T* A = static_cast<T*>(parity ? L.buf[1] : L.buf[0]);
   const int64_t idx = (int64_t)z * L.slab + (int64_t)y * L.pitch + x;
   const int64_t n = (int64_t)L.nx * L.ny * L.nz, k = ((int64_t)z * L.ny + y) * L.nx + x;
-  double v[NQ];
+  using C = Codec<S>;
+  T v[NQ];
 #pragma unroll
   for (int i = 0; i < NQ; ++i) {
-    v[i] = in[i * n + k];
-    A[i * L.plane + idx] = (T)v[i];
+    v[i] = C::enc(typename C::R(in[i * n + k] * (double)L.es[i]), 1.0f);
+    A[i * L.plane + idx] = v[i];
   }
   mx_from_stored<S, NQ>(L, parity, x, y, z, v);
 }
@@ -547,21 +596,26 @@ __global__ void k3_finite(Lat3 L, int parity, int* bad) {
   const int64_t idx = (int64_t)z * L.slab + (int64_t)y * L.pitch + x;
   bool ok = true;
 #pragma unroll
-  for (int i = 0; i < NQ; ++i) ok = ok && isfinite((double)A[i * L.plane + idx]);
+  for (int i = 0; i < NQ; ++i) ok = ok && isfinite((double)Codec<S>::dec(A[i * L.plane + idx], L.ds[i]));
   if (!ok) *bad = 1;
 }
 
 // Launch one of the per-node kernels above for the context's store and q.
-#define LBM3D_NODE_LAUNCH(KERNEL, L, s, ...)                                                   \
-  do {                                                                                       \
-    const dim3 grid_((L.nx + 255) / 256, L.ny, L.nz);                                          \
-    if (L.q == 27) {                                                                         \
-      if (L.store == ST_F64) KERNEL<ST_F64, 27><<<grid_, dim3(256), 0, s>>>(L, __VA_ARGS__);   \
-      else KERNEL<ST_F32, 27><<<grid_, dim3(256), 0, s>>>(L, __VA_ARGS__);                     \
-    } else {                                                                                 \
-      if (L.store == ST_F64) KERNEL<ST_F64, 19><<<grid_, dim3(256), 0, s>>>(L, __VA_ARGS__);   \
-      else KERNEL<ST_F32, 19><<<grid_, dim3(256), 0, s>>>(L, __VA_ARGS__);                     \
-    }                                                                                        \
+#define LBM3D_NODE_LAUNCH_S(KERNEL, NQ, L, s, ...)                                   \
+  do {                                                                             \
+    const dim3 grid_((L.nx + 255) / 256, L.ny, L.nz);                                \
+    switch (L.store) {                                                             \
+      case ST_F64: KERNEL<ST_F64, NQ><<<grid_, dim3(256), 0, s>>>(L, __VA_ARGS__); break;   \
+      case ST_F32: KERNEL<ST_F32, NQ><<<grid_, dim3(256), 0, s>>>(L, __VA_ARGS__); break;   \
+      case ST_F16: KERNEL<ST_F16, NQ><<<grid_, dim3(256), 0, s>>>(L, __VA_ARGS__); break;   \
+      case ST_BF16: KERNEL<ST_BF16, NQ><<<grid_, dim3(256), 0, s>>>(L, __VA_ARGS__); break; \
+      default: return hipErrorInvalidValue;                                        \
+    }                                                                              \
+  } while (0)
+#define LBM3D_NODE_LAUNCH(KERNEL, L, s, ...)                  \
+  do {                                                      \
+    if (L.q == 27) LBM3D_NODE_LAUNCH_S(KERNEL, 27, L, s, __VA_ARGS__); \
+    else LBM3D_NODE_LAUNCH_S(KERNEL, 19, L, s, __VA_ARGS__);           \
   } while (0)
 
 static hipError_t launch_get_pops3(const Lat3& L, int parity, double* out, hipStream_t s) {
@@ -581,26 +635,19 @@ static hipError_t launch_finite3(const Lat3& L, int parity, int* bad, hipStream_
 
 static hipError_t launch_init3(const Lat3& L, const double* drho, const double* ux, const double* uy,
                                const double* uz, hipStream_t s) {
-  const dim3 grid((L.nx + 255) / 256, L.ny, L.nz);
-  if (L.q == 27) {
-    if (L.store == ST_F64) k3_init<ST_F64, 27><<<grid, dim3(256), 0, s>>>(L, drho, ux, uy, uz);
-    else k3_init<ST_F32, 27><<<grid, dim3(256), 0, s>>>(L, drho, ux, uy, uz);
-  } else {
-    if (L.store == ST_F64) k3_init<ST_F64, 19><<<grid, dim3(256), 0, s>>>(L, drho, ux, uy, uz);
-    else k3_init<ST_F32, 19><<<grid, dim3(256), 0, s>>>(L, drho, ux, uy, uz);
-  }
+  LBM3D_NODE_LAUNCH(k3_init, L, s, drho, ux, uy, uz);
   return hipGetLastError();
 }
 
 static hipError_t launch_moments3(const Lat3& L, int parity, double* out, hipStream_t s) {
-  const dim3 grid((L.nx + 255) / 256, L.ny, L.nz);
-  if (L.q == 27) {
-    if (L.store == ST_F64) k3_moments<ST_F64, 27><<<grid, dim3(256), 0, s>>>(L, parity, out);
-    else k3_moments<ST_F32, 27><<<grid, dim3(256), 0, s>>>(L, parity, out);
-  } else {
-    if (L.store == ST_F64) k3_moments<ST_F64, 19><<<grid, dim3(256), 0, s>>>(L, parity, out);
-    else k3_moments<ST_F32, 19><<<grid, dim3(256), 0, s>>>(L, parity, out);
-  }
+  LBM3D_NODE_LAUNCH(k3_moments, L, s, parity, out);
+  return hipGetLastError();
+}
+
+static hipError_t launch_absmax3(const Lat3& L, const double* drho, const double* ux, const double* uy,
+                                 const double* uz, float* part, hipStream_t s) {
+  if (L.q == 27) k3_absmax<27><<<dim3(256), dim3(256), 0, s>>>(L, drho, ux, uy, uz, part);
+  else k3_absmax<19><<<dim3(256), dim3(256), 0, s>>>(L, drho, ux, uy, uz, part);
   return hipGetLastError();
 }
 
@@ -622,13 +669,15 @@ struct lbm3d_ctx {
   int64_t t = 0;
   int shape = 4;  // 128x1xz1, the fastest on 256^3 in both formats
   hipStream_t stream = nullptr;
-  int* flag = nullptr;  // device int in the workspace (lbm3d_check_finite)
+  int* flag = nullptr;    // device int in the workspace (lbm3d_check_finite)
+  float* part = nullptr;  // 256 device floats in the workspace (FP16 exponent at init)
+  int f16_exp = 0;
 };
 
 namespace {
 
 struct Layout3 {
-  size_t esize;
+  size_t esize, rsize;  // stored and arithmetic element sizes
   int32_t pitch;
   int64_t slab, plane;
   int q;
@@ -641,7 +690,8 @@ int check3(const lbm3d_params* p) {
   if ((int64_t)p->nx * p->ny * p->nz > (int64_t)1 << 28) return fail(LBM_ERR_ARG, "lattice exceeds 2^28 nodes");
   {
     // the kernels address a plane with 32-bit byte offsets
-    const int64_t row = ((int64_t)p->nx * (p->store == LBM_STORE_F64 ? 8 : 4) + 255) / 256 * 256;
+    const int64_t es = p->store == LBM_STORE_F64 ? 8 : (p->store == LBM_STORE_F32 ? 4 : 2);
+    const int64_t row = ((int64_t)p->nx * es + 255) / 256 * 256;
     if (row * p->ny * p->nz > ((int64_t)1 << 32) - 65536)
       return fail(LBM_ERR_ARG, "lattice %dx%dx%d: a plane with rows padded to 256 bytes exceeds 4 GiB", p->nx,
                   p->ny, p->nz);
@@ -655,8 +705,9 @@ int check3(const lbm3d_params* p) {
     if ((p->bc[2 * a] == LBM_BC_PERIODIC) != (p->bc[2 * a + 1] == LBM_BC_PERIODIC))
       return fail(LBM_ERR_ARG, "periodic faces must come in pairs");
   if (!std::isfinite(p->gamma)) return fail(LBM_ERR_ARG, "gamma must be finite");
-  if (p->store != LBM_STORE_F64 && p->store != LBM_STORE_F32)
-    return fail(LBM_ERR_ARG, "store = %d: the 3-D lattice stores FP64 or FP32", p->store);
+  if (p->store != LBM_STORE_F64 && p->store != LBM_STORE_F32 && p->store != LBM_STORE_F16DEV &&
+      p->store != LBM_STORE_BF16DEV)
+    return fail(LBM_ERR_ARG, "store = %d is not an LBM_STORE_* format", p->store);
   if (p->velocity_set != LBM3D_D3Q19 && p->velocity_set != LBM3D_D3Q27)
     return fail(LBM_ERR_ARG, "velocity_set = %d is not LBM3D_D3Q19 or LBM3D_D3Q27", p->velocity_set);
   return LBM_OK;
@@ -665,7 +716,8 @@ int check3(const lbm3d_params* p) {
 Layout3 layout3(const lbm3d_params* p) {
   using lbm::host::round_up;
   Layout3 l;
-  l.esize = p->store == LBM_STORE_F64 ? 8 : 4;
+  l.esize = p->store == LBM_STORE_F64 ? 8 : (p->store == LBM_STORE_F32 ? 4 : 2);
+  l.rsize = p->store == LBM_STORE_F64 ? 8 : 4;
   const size_t row = round_up((size_t)p->nx * l.esize, 256);
   l.pitch = (int32_t)(row / l.esize);
   l.slab = (int64_t)l.pitch * p->ny;
@@ -674,8 +726,8 @@ Layout3 layout3(const lbm3d_params* p) {
   l.plane = (int64_t)(plane_bytes / l.esize);
   l.q = p->velocity_set == LBM3D_D3Q27 ? 27 : 19;
   l.buf_bytes = round_up((size_t)l.q * plane_bytes, (size_t)2 << 20);
-  l.mx_bytes = round_up((size_t)16 * p->ny * p->nz * l.esize, 4096);
-  l.total = 2 * l.buf_bytes + 2 * l.mx_bytes + 256;  // + the check_finite flag
+  l.mx_bytes = round_up((size_t)16 * p->ny * p->nz * l.rsize, 4096);
+  l.total = 2 * l.buf_bytes + 2 * l.mx_bytes + 256 + 1024;  // + the check_finite flag, the FP16 partials
   return l;
 }
 
@@ -721,6 +773,7 @@ int lbm3d_init(lbm3d_ctx** out, const lbm3d_params* p, void* workspace, size_t b
   L.mx[0] = static_cast<char*>(workspace) + 2 * lay.buf_bytes;
   L.mx[1] = static_cast<char*>(workspace) + 2 * lay.buf_bytes + lay.mx_bytes;
   c->flag = reinterpret_cast<int*>(static_cast<char*>(workspace) + 2 * lay.buf_bytes + 2 * lay.mx_bytes);
+  c->part = reinterpret_cast<float*>(static_cast<char*>(workspace) + 2 * lay.buf_bytes + 2 * lay.mx_bytes + 256);
   L.mxs = (int64_t)p->ny * p->nz;
   L.nx = p->nx;
   L.ny = p->ny;
@@ -729,12 +782,42 @@ int lbm3d_init(lbm3d_ctx** out, const lbm3d_params* p, void* workspace, size_t b
   L.slab = lay.slab;
   L.plane = lay.plane;
   for (int f = 0; f < 6; ++f) L.bc[f] = p->bc[f];
-  L.store = p->store == LBM_STORE_F64 ? lbm::ST_F64 : lbm::ST_F32;
+  L.store = p->store == LBM_STORE_F64   ? lbm::ST_F64
+            : p->store == LBM_STORE_F32 ? lbm::ST_F32
+            : p->store == LBM_STORE_F16DEV ? lbm::ST_F16
+                                           : lbm::ST_BF16;
   L.q = lay.q;
   L.omega = 1.0 / p->tau;
   L.rho0 = p->rho0;
   L.gamma = p->gamma;
   c->stream = static_cast<hipStream_t>(hip_stream);
+  // codec scales: FP16 stores g_i / w_i * 2^k with k chosen so that the
+  // largest initial |g_i / w_i| 2^k is about 2^12; BF16 stores g_i / w_i
+  int k = 0;
+  if (p->store == LBM_STORE_F16DEV) {
+    float host[256];
+    hipError_t e = lbm::d3::launch_absmax3(L, drho, ux, uy, uz, c->part, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(host, c->part, sizeof(host), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+      delete c;
+      return fail(LBM_ERR_HIP, "f16 exponent reduction: %s", hipGetErrorString(e));
+    }
+    float mx = 0.f;
+    for (float v : host) mx = std::max(mx, v);
+    if (!std::isfinite(mx)) {
+      delete c;
+      return fail(LBM_ERR_ARG, "initial fields are not finite");
+    }
+    k = lbm::host::f16_exp_from_max(mx);
+  }
+  c->f16_exp = k;
+  for (int i = 0; i < 27; ++i) {
+    const double w = L.q == 27 ? lbm::d3::w3<27, double>(i) : (i < 19 ? lbm::d3::w3<19, double>(i) : 1.0);
+    const bool scaled = p->store == LBM_STORE_F16DEV || p->store == LBM_STORE_BF16DEV;
+    L.es[i] = scaled ? (float)std::ldexp(1.0 / w, k) : 1.0f;  // 1/w_i: 3, 18, 36, 13.5, 54, 216 times 2^k, exact
+    L.ds[i] = scaled ? (float)std::ldexp(w, -k) : 1.0f;
+  }
   hipError_t e = lbm::d3::launch_init3(L, drho, ux, uy, uz, c->stream);
   if (e != hipSuccess) {
     delete c;
@@ -795,6 +878,12 @@ int lbm3d_check_finite(lbm3d_ctx* c, int* ok) {
   HIPCHK3(hipStreamSynchronize(c->stream));
   *ok = host ? 0 : 1;
   return host ? fail(LBM_ERR_NONFINITE, "populations hold a non-finite value at t = %lld", (long long)c->t) : LBM_OK;
+}
+
+int lbm3d_f16_exp(const lbm3d_ctx* c, int32_t* k) {
+  if (!c || !k) return fail(LBM_ERR_ARG, "NULL argument");
+  *k = c->f16_exp;
+  return LBM_OK;
 }
 
 int lbm3d_time(const lbm3d_ctx* c, int64_t* t) {

@@ -118,6 +118,7 @@ _SIGS = {
     "lbm3d_get_populations": [_P, _P],
     "lbm3d_set_populations": [_P, _P],
     "lbm3d_check_finite": [_P, _P],
+    "lbm3d_f16_exp": [_P, _P],
     "lbm3d_shape_count": [],
     "lbm3d_shape_describe": [ctypes.c_int32, _P, ctypes.c_size_t],
     "lbm3d_set_shape": [_P, ctypes.c_int32],
@@ -603,6 +604,12 @@ def lbm3d_check_finite(ctx) -> bool:
     if rc not in (LBM_OK, LBM_ERR_NONFINITE):
         _check(rc, "lbm3d_check_finite")
     return bool(ok.value)
+
+
+def lbm3d_f16_exp(ctx) -> int:
+    k = ctypes.c_int32()
+    _check(load().lbm3d_f16_exp(ctx, ctypes.byref(k)), "lbm3d_f16_exp")
+    return k.value
 
 
 def lbm3d_time(ctx) -> int:

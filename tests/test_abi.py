@@ -121,7 +121,7 @@ def test_3d_parameters(lib):
     assert L.lbm3d_workspace_bytes(p) >= 2 * 19 * 64 ** 3 * 8
     p.velocity_set = L.LBM3D_D3Q27
     assert L.lbm3d_workspace_bytes(p) >= 2 * 27 * 64 ** 3 * 8
-    for field, value, msg in [("nz", 2, "each side"), ("tau", 0.5, "tau"), ("store", L.LBM_STORE_F16DEV, "store"),
+    for field, value, msg in [("nz", 2, "each side"), ("tau", 0.5, "tau"), ("store", 7, "store"),
                               ("velocity_set", 2, "velocity_set"), ("nx", 1 << 27, "2\\^28"),
                               ("ny", 1 << 13, "4 GiB")]:
         q = L.lbm3d_params_default()

@@ -60,7 +60,7 @@ def test_fp32_against_oracle(q):
 
 
 @pytest.mark.parametrize("q", [19, 27])
-@pytest.mark.parametrize("store", ["f32", "f64"])
+@pytest.mark.parametrize("store", ["f32", "f64", "f16", "bf16"])
 def test_every_shape_bitwise_identical(store, q):
     from paper_2005_08674_amd import lbm
     from paper_2005_08674_amd.lattice3d import Lattice3D
@@ -92,14 +92,16 @@ def test_autotune_leaves_the_state_and_picks_a_shape(q):
     assert np.array_equal(np.array(a.moments()), np.array(b.moments()))
 
 
+@pytest.mark.parametrize("store", ["f64", "f16", "bf16"])
 @pytest.mark.parametrize("q", [19, 27])
-def test_checkpoint_restore_continues_bitwise(q):
+def test_checkpoint_restore_continues_bitwise(q, store):
     """get_populations / set_populations round-trip the state: a lattice restored from a checkpoint
-    steps on exactly as the one it was taken from (the x-face moments are rebuilt on restore)."""
+    steps on exactly as the one it was taken from (the x-face moments are rebuilt on restore; a
+    16-bit value decoded and encoded again is the same value)."""
     from paper_2005_08674_amd.lattice3d import Lattice3D
     f = _fields(40, 12, 10)
-    a = Lattice3D(40, 12, 10, 0.6, f, store="f64", beta=0.2, m0=(1.0, 0.03, -0.02, 0.01), q=q)
-    b = Lattice3D(40, 12, 10, 0.6, f, store="f64", beta=0.2, m0=(1.0, 0.03, -0.02, 0.01), q=q)
+    a = Lattice3D(40, 12, 10, 0.6, f, store=store, beta=0.2, m0=(1.0, 0.03, -0.02, 0.01), q=q)
+    b = Lattice3D(40, 12, 10, 0.6, f, store=store, beta=0.2, m0=(1.0, 0.03, -0.02, 0.01), q=q)
     a.step(7)
     snap = a.populations()
     b.set_populations(torch.zeros_like(snap))
@@ -161,3 +163,37 @@ def test_check_finite():
     g.set_populations(p)
     assert not g.check_finite()
     g.close()
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_storage_error_against_fp64(q):
+    """96^3 pulses (the bench workload's recipe at a smaller size) with FP32, FP16 and BF16 storage
+    (FP32 arithmetic) against the same run in FP64 (parity-checked against the oracle above) at
+    t = 50 and 200: the error each format adds, relative to U_ref = c_s A_max.  Bounds as in 2-D:
+    FP32 1e-5, FP16 2e-2, BF16 1e-1 (rounding of 2^-11 and 2^-8 of the stored g_i / w_i)."""
+    from paper_2005_08674_amd import lbm
+    from paper_2005_08674_amd import workloads as W
+    from paper_2005_08674_amd.lattice3d import Lattice3D
+    n = 96
+    fields, pulses = W.pulses_3d(n)
+    u_ref = max(p[0] for p in pulses) / math.sqrt(3)
+    runs = {s: Lattice3D(n, n, n, 0.55, fields, store=s, q=q) for s in ("f64", "f32", "f16", "bf16")}
+    # at rest g_i / w_i = rho - rho0, so the FP16 exponent follows from the largest density deviation
+    assert lbm.lbm3d_f16_exp(runs["f16"].ctx) == math.floor(math.log2(4096 / float(np.abs(fields[0]).max())))
+    assert lbm.lbm3d_f16_exp(runs["f32"].ctx) == 0
+    bounds = {"f32": 1e-5, "f16": 2e-2, "bf16": 1e-1}
+    t = 0
+    for t_next in (50, 200):
+        for g in runs.values():
+            g.step(t_next - t)
+        t = t_next
+        ref = runs["f64"].moments()
+        for s in ("f32", "f16", "bf16"):
+            m = runs[s].moments()
+            er = float(np.abs(m[0] - ref[0]).max())
+            eu = max(float(np.abs(m[a] - ref[a]).max()) for a in (1, 2, 3)) / u_ref
+            print(f"[3d storage D3Q{q} {s} vs fp64] t={t}: e_rho={er:.3e} e_u={eu:.3e}", flush=True)
+            assert er <= bounds[s] and eu <= bounds[s], (s, t, er, eu)
+    for g in runs.values():
+        assert g.check_finite()
+        g.close()
