@@ -72,7 +72,7 @@ def run_store(torch, W, store, steps, warmup, tune_reps=5, size=4096, serial_che
     lat = Lattice(w.nx, w.ny, w.tau, w.fields, store=store, mrt=mrt)
     from paper_2005_08674_amd import autotune
     if tile:
-        # a single-step tile name, or a two-step shape name ("2step:...")
+        # a single-step tile name, or a multi-step shape name ("2step:..." or "3step:...")
         names = [lbm.lbm_tile_describe(i) for i in range(lbm.lbm_tile_count())]
         twos = [lbm.lbm_two_step_describe(i) for i in range(lbm.lbm_two_step_count())]
         if tile in twos:
@@ -90,7 +90,7 @@ def run_store(torch, W, store, steps, warmup, tune_reps=5, size=4096, serial_che
             tile_name = e["tile"] if not e["two_step"] else f"{e['tile']} | {e['two_step']}"
             log(f"[{store}] autotune -> {tile_name}; "
                 + ", ".join(f"{n}={t:.4f}" for n, t in e["candidates"].items())
-                + "; two-step (per launch = 2 steps): "
+                + "; multi-step (ms per step): "
                 + ", ".join(f"{n}={t:.4f}" for n, t in e.get("two_step_candidates", {}).items()))
     two_step = lbm.lbm_get_two_step(lat.ctx) >= 0
     lat.step(warmup)
@@ -134,7 +134,7 @@ def run_store(torch, W, store, steps, warmup, tune_reps=5, size=4096, serial_che
         # algorithmic bytes per node-step (2 x 9 x s) x the node-steps one launch advances
         bulk_ms, bulk_n = two_ms, two_n
         nodes_launch = w.nx * w.ny
-        steps_per_launch = 2
+        steps_per_launch = lbm.lbm_two_step_steps(lbm.lbm_get_two_step(lat.ctx))
     ok = lat.check_finite()
     nodes = w.nx * w.ny
     out = {
@@ -143,8 +143,9 @@ def run_store(torch, W, store, steps, warmup, tune_reps=5, size=4096, serial_che
         "ms_per_step": ms / steps,
         "wall_s": t_wall,
         "mlups": nodes * steps / (ms * 1e-3) / 1e6,
-        "kernel": "two-step sweep (t -> t + 2, level t + 1 in LDS)" if steps_per_launch == 2
-                  else "fused step launch (edge segments + bulk tiles)",
+        "kernel": ("two-step sweep (t -> t + 2, level t + 1 in LDS)" if steps_per_launch == 2 else
+                   "three-step sweep (t -> t + 3, levels t + 1 and t + 2 in LDS)" if steps_per_launch == 3 else
+                   "fused step launch (edge segments + bulk tiles)"),
         "kernel_avg_ms": bulk_ms / max(bulk_n, 1),
         "separate_edge_launches": edge_n,
         "bytes_per_node": bpn,
@@ -360,10 +361,10 @@ def run_c5(torch, W, steps, every=50, timing_steps=1000):
     if blob is not None:
         runs += [("closure_f32", "f32", blob), ("closure_f16", "f16", blob)]
     def fastest(lat, reps=3):
-        """Tune the launch on `lat`; keep the two-step sweep when one launch beats two single steps."""
+        """Tune the launch on `lat`; keep the multi-step sweep when it beats single steps per step."""
         best, times = lbm.lbm_autotune(lat.ctx, reps)
         b2, t2 = lbm.lbm_autotune_two_step(lat.ctx, reps)
-        if t2[b2] / 2 < times[best]:
+        if t2[b2] < times[best]:
             return lbm.lbm_two_step_describe(b2)
         lbm.lbm_set_two_step(lat.ctx, -1)
         return lbm.lbm_tile_describe(best)

@@ -239,26 +239,35 @@ int lbm_bulk_traffic(const lbm_ctx* ctx, int64_t* bytes_per_node, int64_t* nodes
  * closure and the overlap option always use separate launches. */
 int lbm_set_fused(lbm_ctx* ctx, int on);
 
-/* Two-step sweep: for lattices with NSBC on all four edges, one launch
- * advances two time steps (t -> t + 2).  Each block computes level t + 1 on
- * its 64 x TY tile plus a margin, keeps it in LDS, and computes level t + 2
- * on the tile from there, so the state crosses HBM about once per two steps
- * (2 x 9 x bytes per stored population per node and launch, plus the margin
- * re-read from L2).  Results are bit-identical to two single steps: level
- * t + 1 is held in the storage format exactly as a store would write it.
- * lbm_two_step_count / lbm_two_step_describe list the candidate shapes;
- * lbm_set_two_step selects one (-1 turns the sweep off, the default) and
- * fails for lattices it does not support.  With a shape selected, lbm_step
- * advances pairs of steps with it and an odd last step with the single-step
- * launch; the closure, the overlap option and periodic edges always use the
- * single-step kernels.  lbm_autotune_two_step times every shape (`reps`
- * launches each, median; the state is left unchanged), selects the fastest,
- * writes its id to *best and the per-shape median launch times (ms, each
- * launch = 2 steps) to times_ms if not NULL.  Synchronizes the stream.
- * lbm_two_step_times returns the summed elapsed milliseconds and the count
- * of two-step launches timed while lbm_enable_timing is on, and resets them. */
+/* Multi-step sweeps: for lattices with NSBC on all four edges, one launch
+ * advances two (t -> t + 2) or three (t -> t + 3) time steps.  Two-step
+ * shapes: each block computes level t + 1 on its 64 x TY tile plus a
+ * margin, keeps it in LDS, and computes level t + 2 on the tile from there.
+ * Three-step shapes keep levels t + 1 and t + 2 in LDS (margins 2 and 1
+ * around whole 64 x TY tiles: the last tile of a row or column overlaps its
+ * neighbour), and need nx >= 64, ny >= TY and, for FP64, TY <= 12.  Either
+ * way the state crosses HBM about once per launch (2 x 9 x bytes per stored
+ * population per node, plus margins re-read from L2), and results are
+ * bit-identical to single steps: intermediate levels are held in the
+ * storage format exactly as a store would write them.
+ * lbm_two_step_count / lbm_two_step_describe ("2step:..." or "3step:...")
+ * list the candidate shapes and lbm_two_step_steps gives a shape's steps per
+ * launch; lbm_set_two_step selects one (-1 turns the sweeps off, the
+ * default) and fails for lattices it does not support.  With a shape
+ * selected, lbm_step advances groups of that many steps with it and the
+ * remainder with the single-step launch; the closure, the overlap option
+ * and periodic edges always use the single-step kernels.
+ * lbm_autotune_two_step times every shape the lattice supports (`reps`
+ * launches each, median; the state is left unchanged), selects the one with
+ * the least time per step, writes its id to *best and, if times_ms is not
+ * NULL, per shape the median launch time divided by its steps per launch
+ * (ms per step; -1 for shapes the lattice cannot take).  Synchronizes the
+ * stream.  lbm_two_step_times returns the summed elapsed milliseconds and
+ * the count of multi-step launches timed while lbm_enable_timing is on, and
+ * resets them. */
 int lbm_two_step_count(void);
 int lbm_two_step_describe(int32_t id, char* buf, size_t len);
+int lbm_two_step_steps(int32_t id, int32_t* steps);
 int lbm_set_two_step(lbm_ctx* ctx, int32_t id);
 int lbm_get_two_step(const lbm_ctx* ctx, int32_t* id);
 int lbm_autotune_two_step(lbm_ctx* ctx, int32_t reps, int32_t* best, float* times_ms);

@@ -101,8 +101,9 @@ int lbm_ens_autotune(lbm_ens* e, int32_t reps, int32_t* best, float* times_ms);
 /* Two-step sweep over the whole ensemble (the single-lattice sweep of
  * lbm_set_two_step, lbm.h: level t + 1 of each 64 x TY tile kept in LDS,
  * eqs. lbe_0, lbe_1 / mrt_lbe and nes_0..nes_4 applied twice; results
- * bit-identical to single steps).  Shapes are the lbm_two_step_count /
- * lbm_two_step_describe candidates; the ensemble lays every member's tiles
+ * bit-identical to single steps).  Shapes are the two-step candidates of
+ * lbm_two_step_count / lbm_two_step_describe (those with two steps per
+ * launch, which come first: ids 0 .. n2 - 1); the ensemble lays every member's tiles
  * out in one list whose contiguous eighths run on the 8 XCDs (the shape's
  * own block map is not used).  lbm_ens_set_two_step selects a shape (-1, the
  * default, turns the sweep off); LBM_ERR_UNSUPPORTED unless every member has
@@ -111,8 +112,7 @@ int lbm_ens_autotune(lbm_ens* e, int32_t reps, int32_t* best, float* times_ms);
  * of `reps` launches, after one warm-up; the state is not advanced), selects
  * the fastest and writes its id to *best and, if times_ms is not NULL, the
  * per-shape median time of one launch (two steps) in milliseconds (length
- * lbm_two_step_count).  Both drop cached graphs; the autotuner synchronizes
- * the stream. */
+ * n2).  Both drop cached graphs; the autotuner synchronizes the stream. */
 int lbm_ens_set_two_step(lbm_ens* e, int32_t id);
 int lbm_ens_get_two_step(const lbm_ens* e, int32_t* id);
 int lbm_ens_autotune_two_step(lbm_ens* e, int32_t reps, int32_t* best, float* times_ms);

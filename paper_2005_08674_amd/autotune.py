@@ -68,8 +68,9 @@ def apply(lattice, store: str, path: str = CACHE) -> str | None:
 
 
 def tune(lattice, store: str, reps: int = 10, path: str | None = CACHE) -> dict:
-    """Time every candidate on ``lattice``: single-step tiles, then two-step shapes if the lattice
-    supports them; keep the faster per step, select it, and record it in the cache."""
+    """Time every candidate on ``lattice``: single-step tiles, then the multi-step shapes (two and three
+    steps per launch) if the lattice supports them; keep the fastest per step, select it, and record it
+    in the cache."""
     best, times = L.lbm_autotune(lattice.ctx, reps)
     names = [L.lbm_tile_describe(i) for i in range(L.lbm_tile_count())]
     entry = {"tile": names[best], "ms": times[best], "reps": reps,
@@ -82,7 +83,7 @@ def tune(lattice, store: str, reps: int = 10, path: str | None = CACHE) -> dict:
     if b2 is not None:
         twos = [L.lbm_two_step_describe(i) for i in range(L.lbm_two_step_count())]
         entry["two_step_candidates"] = {n: round(t, 5) for n, t in zip(twos, t2)}
-        if t2[b2] / 2 < times[best]:  # each two-step launch advances two steps
+        if t2[b2] < times[best]:  # both per step (a multi-step launch advances two or three)
             entry["two_step"] = twos[b2]
             entry["two_step_ms"] = t2[b2]
         else:

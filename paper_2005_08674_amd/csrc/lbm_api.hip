@@ -340,8 +340,21 @@ int step_once(lbm_ctx* c) {
   return LBM_OK;
 }
 
-// Two steps in one launch of the two-step sweep (same results as two
-// step_once calls).
+// Multi-step sweep shapes: ids below num_two_step() are two-step shapes,
+// the next num_three_step() are three-step shapes.
+int multi_count() { return lbm::num_two_step() + lbm::num_three_step(); }
+int multi_steps(int id) { return id < lbm::num_two_step() ? 2 : 3; }
+bool multi_supported(const lbm::LatDesc& L, int id) {
+  if (id < 0 || id >= multi_count()) return false;
+  return id < lbm::num_two_step() ? lbm::two_step_supported(L) : lbm::three_step_supported(L, id - lbm::num_two_step());
+}
+hipError_t launch_multi(const lbm::LatDesc& L, int parity, int id, hipStream_t s) {
+  return id < lbm::num_two_step() ? lbm::launch_two_step(L, parity, id, s)
+                                  : lbm::launch_three_step(L, parity, id - lbm::num_two_step(), s);
+}
+
+// Two or three steps in one launch of the multi-step sweep (same results as
+// that many step_once calls).
 int step_twice(lbm_ctx* c) {
   hipEvent_t t[4] = {nullptr, nullptr, nullptr, nullptr};
   if (c->timing) {
@@ -356,16 +369,16 @@ int step_twice(lbm_ctx* c) {
     c->ev_two.push_back(1);
   }
   if (t[0]) HIPCHK(hipEventRecord(t[0], c->stream));
-  HIPCHK(lbm::launch_two_step(c->L, c->parity, c->two_step, c->stream));
+  HIPCHK(launch_multi(c->L, c->parity, c->two_step, c->stream));
   if (t[1]) HIPCHK(hipEventRecord(t[1], c->stream));
-  // level t + 2 is in the other buffer: the launch wrote buffer parity ^ 1
+  // the last level is in the other buffer: the launch wrote buffer parity ^ 1
   c->parity ^= 1;
-  c->t += 2;
+  c->t += multi_steps(c->two_step);
   return LBM_OK;
 }
 
 bool use_two_step(const lbm_ctx* c) {
-  return c->two_step >= 0 && !c->overlap && !(c->L.closure && c->L.net) && lbm::two_step_supported(c->L);
+  return c->two_step >= 0 && !c->overlap && !(c->L.closure && c->L.net) && multi_supported(c->L, c->two_step);
 }
 
 }  // namespace
@@ -486,7 +499,8 @@ int lbm_step(lbm_ctx* c, int32_t n) {
   }
   int32_t s = 0;
   if (use_two_step(c)) {
-    for (; s + 1 < n; s += 2) {
+    const int k = multi_steps(c->two_step);
+    for (; s + k <= n; s += k) {
       int rc = step_twice(c);
       if (rc) return rc;
     }
@@ -656,20 +670,32 @@ int lbm_enable_timing(lbm_ctx* c, int on) {
   return LBM_OK;
 }
 
-int lbm_two_step_count(void) { return lbm::num_two_step(); }
+int lbm_two_step_count(void) { return multi_count(); }
 
 int lbm_two_step_describe(int32_t id, char* buf, size_t len) {
   if (!buf || len == 0) return fail(LBM_ERR_ARG, "NULL buffer");
-  if (id < 0 || id >= lbm::num_two_step()) return fail(LBM_ERR_ARG, "two-step shape %d out of range", id);
-  lbm::two_step_name(id, buf, len);
+  if (id < 0 || id >= multi_count()) return fail(LBM_ERR_ARG, "multi-step shape %d out of range", id);
+  if (id < lbm::num_two_step())
+    lbm::two_step_name(id, buf, len);
+  else
+    lbm::three_step_name(id - lbm::num_two_step(), buf, len);
+  return LBM_OK;
+}
+
+int lbm_two_step_steps(int32_t id, int32_t* steps) {
+  if (!steps) return fail(LBM_ERR_ARG, "NULL argument");
+  if (id < 0 || id >= multi_count()) return fail(LBM_ERR_ARG, "multi-step shape %d out of range", id);
+  *steps = multi_steps(id);
   return LBM_OK;
 }
 
 int lbm_set_two_step(lbm_ctx* c, int32_t id) {
   if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
-  if (id < -1 || id >= lbm::num_two_step()) return fail(LBM_ERR_ARG, "two-step shape %d out of range", id);
+  if (id < -1 || id >= multi_count()) return fail(LBM_ERR_ARG, "multi-step shape %d out of range", id);
   if (id >= 0 && !lbm::two_step_supported(c->L))
-    return fail(LBM_ERR_ARG, "the two-step sweep needs NSBC on all four edges");
+    return fail(LBM_ERR_ARG, "the multi-step sweeps need NSBC on all four edges");
+  if (id >= 0 && !multi_supported(c->L, id))
+    return fail(LBM_ERR_ARG, "three-step shape %d needs whole tiles (nx >= 64, ny >= its tile rows) and LDS for this format", id);
   c->two_step = id;
   return LBM_OK;
 }
@@ -684,20 +710,25 @@ int lbm_autotune_two_step(lbm_ctx* c, int32_t reps, int32_t* best, float* times_
   if (!c || !best) return fail(LBM_ERR_ARG, "NULL argument");
   if (reps < 1 || reps > 1000) return fail(LBM_ERR_ARG, "reps = %d outside [1, 1000]", reps);
   if (!lbm::two_step_supported(c->L))
-    return fail(LBM_ERR_ARG, "the two-step sweep needs NSBC on all four edges");
-  // the sweep reads buffer `parity` and writes only the other one, so
-  // relaunching it leaves the state untouched
-  const int nt = lbm::num_two_step();
+    return fail(LBM_ERR_ARG, "the multi-step sweeps need NSBC on all four edges");
+  // a sweep reads buffer `parity` and writes only the other one, so
+  // relaunching it leaves the state untouched; shapes are compared by time
+  // per step, and a shape the lattice cannot take reports a negative time
+  const int nt = multi_count();
   std::vector<hipEvent_t> ev(2 * reps);
   for (auto& e : ev) HIPCHK(hipEventCreate(&e));
   float best_t = 1e30f;
   int best_id = 0;
   int rc = LBM_OK;
   for (int id = 0; id < nt && rc == LBM_OK; ++id) {
-    hipError_t e = lbm::launch_two_step(c->L, c->parity, id, c->stream);
+    if (!multi_supported(c->L, id)) {
+      if (times_ms) times_ms[id] = -1.f;
+      continue;
+    }
+    hipError_t e = launch_multi(c->L, c->parity, id, c->stream);
     for (int r = 0; r < reps && e == hipSuccess; ++r) {
       e = hipEventRecord(ev[2 * r], c->stream);
-      if (e == hipSuccess) e = lbm::launch_two_step(c->L, c->parity, id, c->stream);
+      if (e == hipSuccess) e = launch_multi(c->L, c->parity, id, c->stream);
       if (e == hipSuccess) e = hipEventRecord(ev[2 * r + 1], c->stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -708,7 +739,7 @@ int lbm_autotune_two_step(lbm_ctx* c, int32_t reps, int32_t* best, float* times_
       break;
     }
     std::sort(ts.begin(), ts.end());
-    const float med = ts[reps / 2];
+    const float med = ts[reps / 2] / (float)multi_steps(id);
     if (times_ms) times_ms[id] = med;
     if (med < best_t) {
       best_t = med;

@@ -23,6 +23,11 @@ hipError_t launch_two_step(const LatDesc& L, int parity, int id, hipStream_t s);
 // output tile rows of two-step shape id (0 if invalid), and the smallest over all shapes
 int two_step_tile_rows(int id);
 int two_step_min_rows();
+// three-step sweep (t -> t + 3), single lattices
+int num_three_step();
+void three_step_name(int id, char* buf, size_t len);
+bool three_step_supported(const LatDesc& L, int id);
+hipError_t launch_three_step(const LatDesc& L, int parity, int id, hipStream_t s);
 // ensemble two-step: one block per list entry (member, 64-column tile x, tile y); lat < 0 = padding
 struct TwoTile {
   int32_t lat, txi, tyi, pad;

@@ -1,7 +1,8 @@
 // lbm_twostep.hip -- the two-step sweep (t -> t + 2 in one launch, level
-// t + 1 in LDS; lbm_twostep_lds.h) for lattices with NSBC on all four edges:
-// its compile-time shapes, one instance per storage format and collision
-// model, and its host-side launcher.
+// t + 1 in LDS) and the three-step sweep (t -> t + 3, levels t + 1 and t + 2
+// in LDS; lbm_twostep_lds.h) for lattices with NSBC on all four edges: their
+// compile-time shapes, one instance per storage format and collision model,
+// and their host-side launchers.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -133,6 +134,116 @@ hipError_t launch_two_step(const LatDesc& L, int parity, int id, hipStream_t s) 
     case ST_F32: return launch_two_s<ST_F32>(L, parity, id, s);
     case ST_F16: return launch_two_s<ST_F16>(L, parity, id, s);
     case ST_BF16: return launch_two_s<ST_BF16>(L, parity, id, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------ three-step kernel
+// Candidate shapes of the three-step sweep (three_step_tile): output tile
+// 64 x TY, NT threads, non-temporal stores (NTS); tiles in XCD bands (as MAP
+// 2 above).  A shape whose two LDS levels exceed a workgroup's 160 KiB for a
+// storage format is not built for it (FP64 at TY >= 16).
+#define LBM_THREE_STEP(X) \
+  X(8, 512, true)         \
+  X(12, 512, true)        \
+  X(12, 768, true)        \
+  X(16, 512, true)        \
+  X(16, 768, true)        \
+  X(20, 768, true)
+
+template <int S, int TY>
+constexpr bool three_step_fits() {
+  return three_step_lds_bytes<S, TY>() <= 160 * 1024;
+}
+
+template <int S, int TY, int NT, bool NTS, int CM>
+__global__ __launch_bounds__(NT, two_step_waves<S>()) void k_three_step(LatDesc L, int parity, int tiles_x,
+                                                                      int tiles_y) {
+  const int b = blockIdx.x, ntiles = tiles_x * tiles_y;
+  const int per = (ntiles + 7) >> 3;
+  const int tile = (b & 7) * per + (b >> 3);
+  if (tile >= ntiles) return;  // padding blocks: the whole block leaves before any barrier
+  const int tyi = tile / tiles_x, txi = tile - tyi * tiles_x;
+  three_step_tile<S, TY, NT, NTS, CM>(L, parity, txi, tyi);
+}
+
+struct ThreeStepShape {
+  int ty, nt;
+  bool nts;
+};
+static const ThreeStepShape kThree[] = {
+#define X(a, b, c) {a, b, c},
+    LBM_THREE_STEP(X)
+#undef X
+};
+static constexpr int kNumThree = sizeof(kThree) / sizeof(kThree[0]);
+
+int num_three_step() { return kNumThree; }
+
+void three_step_name(int id, char* buf, size_t len) {
+  if (id < 0 || id >= kNumThree) {
+    snprintf(buf, len, "invalid");
+    return;
+  }
+  snprintf(buf, len, "3step:64x%d/%d+xcdband%s", kThree[id].ty, kThree[id].nt, kThree[id].nts ? "+nts" : "");
+}
+
+static bool three_step_fits_store(int store, int id) {
+  int k = 0;
+#define X(a, b, c)                                                                                   \
+  if (id == k) {                                                                                     \
+    switch (store) {                                                                                 \
+      case ST_F64: return three_step_fits<ST_F64, a>();                                              \
+      case ST_F32: return three_step_fits<ST_F32, a>();                                              \
+      case ST_F16: return three_step_fits<ST_F16, a>();                                              \
+      case ST_BF16: return three_step_fits<ST_BF16, a>();                                            \
+    }                                                                                                \
+    return false;                                                                                    \
+  }                                                                                                  \
+  ++k;
+  LBM_THREE_STEP(X)
+#undef X
+  return false;
+}
+
+bool three_step_supported(const LatDesc& L, int id) {
+  return id >= 0 && id < kNumThree && two_step_supported(L) && L.nx >= TL_TX && L.ny >= kThree[id].ty &&
+         three_step_fits_store(L.store, id);
+}
+
+template <int S, int TY, int NT, bool NTS>
+static hipError_t launch_three_t(const LatDesc& L, int parity, hipStream_t s) {
+  if constexpr (!three_step_fits<S, TY>()) {
+    return hipErrorInvalidValue;
+  } else {
+    const int tiles_x = (L.nx + TL_TX - 1) / TL_TX, tiles_y = (L.ny + TY - 1) / TY;
+    const dim3 grid(((tiles_x * tiles_y + 7) >> 3) * 8);
+    if (L.coll == COLL_MRT)
+      k_three_step<S, TY, NT, NTS, COLL_MRT><<<grid, dim3(NT), 0, s>>>(L, parity, tiles_x, tiles_y);
+    else
+      k_three_step<S, TY, NT, NTS, COLL_BGK><<<grid, dim3(NT), 0, s>>>(L, parity, tiles_x, tiles_y);
+    return hipGetLastError();
+  }
+}
+
+template <int S>
+static hipError_t launch_three_s(const LatDesc& L, int parity, int id, hipStream_t s) {
+  int k = 0;
+#define X(a, b, c)                                                 \
+  if (id == k) return launch_three_t<S, a, b, c>(L, parity, s);   \
+  ++k;
+  LBM_THREE_STEP(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_three_step(const LatDesc& L, int parity, int id, hipStream_t s) {
+  if (!three_step_supported(L, id)) return hipErrorInvalidValue;
+  switch (L.store) {
+    case ST_F64: return launch_three_s<ST_F64>(L, parity, id, s);
+    case ST_F32: return launch_three_s<ST_F32>(L, parity, id, s);
+    case ST_F16: return launch_three_s<ST_F16>(L, parity, id, s);
+    case ST_BF16: return launch_three_s<ST_BF16>(L, parity, id, s);
   }
   return hipErrorInvalidValue;
 }

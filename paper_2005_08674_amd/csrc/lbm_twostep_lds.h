@@ -232,3 +232,185 @@ __device__ inline void two_step_tile(const LatDesc& Ld, int parity, int txi, int
 }
 
 }  // namespace lbm
+
+namespace lbm {
+
+// ------------------------------------------------------------------ three steps per launch
+// t -> t + 3 with levels t + 1 and t + 2 in LDS.  The output tile is 64 x TY
+// at (x0, y0) = (min(64 txi, nx - 64), min(TY tyi, ny - TY)): every tile is
+// whole (the last tile of a row or column overlaps its neighbour and writes
+// the same values), so a lattice edge that crosses a level's region has the
+// two nodes NSBC reads inward of it inside the previous level's region.
+// Level t + 1 covers columns x0 - 2 .. x0 + 65 and rows y0 - 2 .. y0 + TY + 1
+// (lds1), level t + 2 columns x0 - 1 .. x0 + 64 and rows y0 - 1 .. y0 + TY
+// (lds2), level t + 3 the tile.  Per node the arithmetic is the single-step
+// path's and each level is rounded through the storage codec: bit-identical
+// to three single steps.
+constexpr int T3_W1 = TL_TX + 4;
+constexpr int T3_W2 = TL_TX + 2;
+
+template <int S, int TY>
+constexpr int three_step_lds_bytes() {
+  return 9 * ((TY + 4) * T3_W1 + (TY + 2) * T3_W2) * (int)sizeof(typename Codec<S>::T);
+}
+
+template <int S, int TY, int NT, bool NTS, int CM>
+__device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, int tyi) {
+  using C = Codec<S>;
+  using T = typename C::T;
+  using R = typename C::R;
+  __shared__ T lds1[9][TY + 4][T3_W1];
+  __shared__ T lds2[9][TY + 2][T3_W2];
+
+  const int nx = Ld.nx, ny = Ld.ny;
+  const int x0 = min(txi * TL_TX, nx - TL_TX), y0 = min(tyi * TY, ny - TY);
+  const int tid = threadIdx.x;
+  const T* __restrict__ A = static_cast<const T*>(buf_of(Ld, parity));
+  T* __restrict__ B = static_cast<T*>(buf_of(Ld, parity ^ 1));
+  const int pitch = Ld.pitch;
+  const int64_t plane = Ld.plane;
+  const R rho0 = R(Ld.rho0), omega = R(Ld.omega);
+  const Base<R> base(Ld);
+
+  // Inner tile: every level t + 1 node and its pull sources lie inside the
+  // lattice and away from its edges: no clamps, no NSBC.
+  const bool inner = x0 >= 3 && x0 + TL_TX + 3 <= nx && y0 >= 3 && y0 + TY + 3 <= ny;
+  if (inner) {
+    constexpr int N1 = (TY + 4) * T3_W1, N2 = (TY + 2) * T3_W2, N3 = TY * TL_TX;
+#pragma unroll
+    for (int it = 0; it < (N1 + NT - 1) / NT; ++it) {
+      const int k = tid + it * NT;
+      if (k < N1) {
+        const int r = k / T3_W1, cx = k - r * T3_W1;
+        const uint32_t idx = (uint32_t)((y0 - 2 + r) * pitch + (x0 - 2 + cx));
+        const uint32_t ro[3] = {(idx + (uint32_t)pitch) * (uint32_t)sizeof(T), idx * (uint32_t)sizeof(T),
+                                (idx - (uint32_t)pitch) * (uint32_t)sizeof(T)};
+        R g[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          const char* __restrict__ Ai = reinterpret_cast<const char*>(A + i * plane);
+          g[i] = C::dec(*reinterpret_cast<const T*>(Ai + ro[1 + kCy[i]] - kCx[i] * (int)sizeof(T)), Ld.ds[i]);
+        }
+        collide<R, CM>(Ld, g, rho0, base, omega);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) lds1[i][r][cx] = C::enc(g[i], Ld.es[i]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < (N2 + NT - 1) / NT; ++it) {
+      const int k = tid + it * NT;
+      if (k < N2) {
+        const int r = k / T3_W2, cx = k - r * T3_W2;
+        R g[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) g[i] = C::dec(lds1[i][r + 1 - kCy[i]][cx + 1 - kCx[i]], Ld.ds[i]);
+        collide<R, CM>(Ld, g, rho0, base, omega);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) lds2[i][r][cx] = C::enc(g[i], Ld.es[i]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < (N3 + NT - 1) / NT; ++it) {
+      const int k = tid + it * NT;
+      if (k < N3) {
+        const int r = k / TL_TX, cx = k - r * TL_TX;
+        R g[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) g[i] = C::dec(lds2[i][r + 1 - kCy[i]][cx + 1 - kCx[i]], Ld.ds[i]);
+        collide<R, CM>(Ld, g, rho0, base, omega);
+        const uint32_t off = (uint32_t)((y0 + r) * pitch + (x0 + cx)) * (uint32_t)sizeof(T);
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+          put<NTS>(reinterpret_cast<T*>(reinterpret_cast<char*>(B + i * plane) + off), C::enc(g[i], Ld.es[i]));
+      }
+    }
+    return;
+  }
+
+  // ---- level t + 1 from HBM (sources clamped into the lattice; a clamped
+  // source is only ever an unknown population's, which NSBC replaces)
+  for (int k = tid; k < (TY + 4) * T3_W1; k += NT) {
+    const int r = k / T3_W1, cx = k - r * T3_W1;
+    const int x = x0 - 2 + cx, y = y0 - 2 + r;
+    if (x < 0 || x >= nx || y < 0 || y >= ny) continue;
+    const uint32_t unknown = tl_unknown(x, y, nx, ny);
+    const int sxs[3] = {min(x + 1, nx - 1), x, max(x - 1, 0)};
+    const uint32_t srow[3] = {(uint32_t)(min(y + 1, ny - 1) * pitch), (uint32_t)(y * pitch),
+                              (uint32_t)(max(y - 1, 0) * pitch)};
+    R g[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const T* __restrict__ Ai = A + i * plane;
+      const R v = C::dec(Ai[srow[1 + kCy[i]] + (uint32_t)sxs[1 + kCx[i]]], Ld.ds[i]);
+      g[i] = (unknown >> i) & 1u ? R(0) : v;
+    }
+    if (unknown) {
+      auto mom = [&](int xx, int yy, R m[3]) { tl_moments_global<S>(Ld, A, xx, yy, base, m); };
+      tl_nsbc<R>(Ld, g, unknown, x, y, rho0, base, mom);
+    }
+    collide<R, CM>(Ld, g, rho0, base, omega);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) lds1[i][r][cx] = C::enc(g[i], Ld.es[i]);
+  }
+  __syncthreads();
+
+  // ---- level t + 2 from lds1 (lattice node (x, y) at lds1[.][y - y0 + 2][x - x0 + 2])
+  auto mom1 = [&](int xx, int yy, R m[3]) {
+    R q[9];
+    const int lx = xx - x0 + 2, ly = yy - y0 + 2;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) q[i] = C::dec(lds1[i][ly][lx], Ld.ds[i]);
+    moments<R>(q, rho0, base, m[0], m[1], m[2]);
+  };
+  for (int k = tid; k < (TY + 2) * T3_W2; k += NT) {
+    const int r = k / T3_W2, cx = k - r * T3_W2;
+    const int x = x0 - 1 + cx, y = y0 - 1 + r;
+    if (x < 0 || x >= nx || y < 0 || y >= ny) continue;
+    const uint32_t unknown = tl_unknown(x, y, nx, ny);
+    const int lxs[3] = {min(x + 1, nx - 1) - x0 + 2, x - x0 + 2, max(x - 1, 0) - x0 + 2};
+    const int lys[3] = {min(y + 1, ny - 1) - y0 + 2, y - y0 + 2, max(y - 1, 0) - y0 + 2};
+    R g[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const R v = C::dec(lds1[i][lys[1 + kCy[i]]][lxs[1 + kCx[i]]], Ld.ds[i]);
+      g[i] = (unknown >> i) & 1u ? R(0) : v;
+    }
+    if (unknown) tl_nsbc<R>(Ld, g, unknown, x, y, rho0, base, mom1);
+    collide<R, CM>(Ld, g, rho0, base, omega);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) lds2[i][r][cx] = C::enc(g[i], Ld.es[i]);
+  }
+  __syncthreads();
+
+  // ---- level t + 3 on the tile from lds2 (lattice node (x, y) at lds2[.][y - y0 + 1][x - x0 + 1])
+  auto mom2 = [&](int xx, int yy, R m[3]) {
+    R q[9];
+    const int lx = xx - x0 + 1, ly = yy - y0 + 1;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) q[i] = C::dec(lds2[i][ly][lx], Ld.ds[i]);
+    moments<R>(q, rho0, base, m[0], m[1], m[2]);
+  };
+  for (int k = tid; k < TY * TL_TX; k += NT) {
+    const int r = k / TL_TX, cx = k - r * TL_TX;
+    const int x = x0 + cx, y = y0 + r;
+    const uint32_t unknown = tl_unknown(x, y, nx, ny);
+    const int lxs[3] = {min(x + 1, nx - 1) - x0 + 1, cx + 1, max(x - 1, 0) - x0 + 1};
+    const int lys[3] = {min(y + 1, ny - 1) - y0 + 1, r + 1, max(y - 1, 0) - y0 + 1};
+    R g[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const R v = C::dec(lds2[i][lys[1 + kCy[i]]][lxs[1 + kCx[i]]], Ld.ds[i]);
+      g[i] = (unknown >> i) & 1u ? R(0) : v;
+    }
+    if (unknown) tl_nsbc<R>(Ld, g, unknown, x, y, rho0, base, mom2);
+    collide<R, CM>(Ld, g, rho0, base, omega);
+    const uint32_t off = (uint32_t)(y * pitch + x) * (uint32_t)sizeof(T);
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+      put<NTS>(reinterpret_cast<T*>(reinterpret_cast<char*>(B + i * plane) + off), C::enc(g[i], Ld.es[i]));
+  }
+}
+
+}  // namespace lbm

@@ -84,6 +84,7 @@ _SIGS = {
     "lbm_stream_copy": [_P, _P, ctypes.c_size_t, _P],
     "lbm_two_step_count": [],
     "lbm_two_step_describe": [ctypes.c_int32, _P, ctypes.c_size_t],
+    "lbm_two_step_steps": [ctypes.c_int32, _P],
     "lbm_set_two_step": [_P, ctypes.c_int32],
     "lbm_get_two_step": [_P, _P],
     "lbm_autotune_two_step": [_P, ctypes.c_int32, _P, _P],
@@ -309,6 +310,13 @@ def lbm_two_step_describe(shape_id: int) -> str:
     return buf.value.decode()
 
 
+def lbm_two_step_steps(shape_id: int) -> int:
+    """Steps one launch of multi-step shape `shape_id` advances (2 or 3)."""
+    k = ctypes.c_int32()
+    _check(load().lbm_two_step_steps(int(shape_id), ctypes.byref(k)), "lbm_two_step_steps")
+    return k.value
+
+
 def lbm_set_two_step(ctx, shape_id: int):
     _check(load().lbm_set_two_step(ctx, int(shape_id)), "lbm_set_two_step")
 
@@ -440,9 +448,14 @@ def lbm_ens_get_two_step(ens) -> int:
     return v.value
 
 
+def lbm_two_step_pairs_count() -> int:
+    """Number of two-step shapes (the first ids of lbm_two_step_count; the ensemble runs only these)."""
+    return sum(1 for k in range(lbm_two_step_count()) if lbm_two_step_steps(k) == 2)
+
+
 def lbm_ens_autotune_two_step(ens, reps: int = 5):
     best = ctypes.c_int32()
-    times = (ctypes.c_float * lbm_two_step_count())()
+    times = (ctypes.c_float * lbm_two_step_pairs_count())()
     _check(load().lbm_ens_autotune_two_step(ens, int(reps), ctypes.byref(best), times), "lbm_ens_autotune_two_step")
     return best.value, list(times)
 

@@ -134,7 +134,15 @@ def test_every_launch_path_bitwise_identical(store):
         for shape in range(lbm.lbm_two_step_count()):
             print(f"[mrt two-step] {store} {lbm.lbm_two_step_describe(shape)} {nx}x{ny}", flush=True)
             g = _gpu_lattice(nx, ny, 0.55, f, **mk)
-            lbm.lbm_set_two_step(g.ctx, shape)
+            try:
+                lbm.lbm_set_two_step(g.ctx, shape)
+            except lbm.LbmError:
+                # three-step shapes need whole tiles (nx >= 64, ny >= their rows), and FP64 LDS for
+                # two levels only up to 12 rows
+                ty = int(lbm.lbm_two_step_describe(shape).split("x")[1].split("/")[0])
+                assert lbm.lbm_two_step_steps(shape) == 3 and (nx < 64 or ny < ty or (store == "f64" and ty > 12))
+                g.close()
+                continue
             g.step(9)
             assert np.array_equal(g.populations().cpu().numpy(), want), (store, nx, ny, shape)
             g.close()

@@ -1,6 +1,7 @@
-"""GPU two-step sweep: one launch advancing t -> t + 2 (level t + 1 in LDS) must
-give the same bits as two single steps, for every shape, storage format, NSBC
-reading and ragged size, and agree with the oracle at full size."""
+"""GPU multi-step sweeps: one launch advancing t -> t + 2 (level t + 1 in LDS)
+or t -> t + 3 (levels t + 1 and t + 2 in LDS) must give the same bits as single
+steps, for every shape, storage format, NSBC reading and ragged size, and agree
+with the oracle at full size."""
 import numpy as np
 import pytest
 
@@ -41,14 +42,28 @@ def _pair(nx, ny, store, shape, steps, **kw):
 SIZES = [(203, 77), (61, 5), (3, 3), (4, 3), (3, 40), (62, 64), (121, 130), (240, 33), (241, 129), (480, 257)]
 
 
+def _three_step_takes(name, store, nx, ny):
+    """Whether three-step shape `name` ("3step:64xTY/...") runs on an nx x ny lattice in `store`:
+    whole tiles, and two LDS levels within 160 KiB (FP64 only up to TY = 12)."""
+    ty = int(name.split("x")[1].split("/")[0])
+    return nx >= 64 and ny >= ty and not (store == "f64" and ty > 12)
+
+
 @pytest.mark.parametrize("store", ["f64", "f32", "f16", "bf16"])
 def test_bitwise_equal_to_single_steps_all_shapes(store):
+    """9 steps (two-step: 4 launches and a single step) or 11 (three-step: 3 launches and 2 single
+    steps); three-step shapes refuse exactly the lattices they cannot take."""
     from paper_2005_08674_amd import lbm
     for shape in range(lbm.lbm_two_step_count()):
         name = lbm.lbm_two_step_describe(shape)
+        k = lbm.lbm_two_step_steps(shape)
         for nx, ny in SIZES:
-            print(f"[two-step] {store} {name} {nx}x{ny}", flush=True)
-            pa, pb = _pair(nx, ny, store, shape, 9)
+            print(f"[multi-step] {store} {name} {nx}x{ny}", flush=True)
+            if k == 3 and not _three_step_takes(name, store, nx, ny):
+                with pytest.raises(lbm.LbmError):
+                    _pair(nx, ny, store, shape, 11)
+                continue
+            pa, pb = _pair(nx, ny, store, shape, 9 if k == 2 else 11)
             assert np.isfinite(pa).all()
             assert np.array_equal(pa, pb), (store, name, nx, ny, np.argwhere(pa != pb)[:5])
 
@@ -56,9 +71,15 @@ def test_bitwise_equal_to_single_steps_all_shapes(store):
 @pytest.mark.parametrize("kw", [dict(grad_order=2), dict(corner_mode=1), dict(corr_mode=1),
                                 dict(ubase=(0.03, -0.02)), dict(gamma=0.3, beta=0.0)])
 def test_bitwise_equal_nsbc_readings(kw):
+    from paper_2005_08674_amd import lbm
+    three = [k for k in range(lbm.lbm_two_step_count()) if lbm.lbm_two_step_steps(k) == 3]
     for nx, ny in [(130, 67), (64, 3)]:
         print(f"[two-step] {kw} {nx}x{ny}", flush=True)
         pa, pb = _pair(nx, ny, "f32", 1, 12, **dict(kw))
+        assert np.array_equal(pa, pb), (kw, nx, ny)
+    for nx, ny in [(130, 67), (64, 12)]:
+        print(f"[three-step] {kw} {nx}x{ny}", flush=True)
+        pa, pb = _pair(nx, ny, "f32", three[0], 13, **dict(kw))
         assert np.array_equal(pa, pb), (kw, nx, ny)
 
 
