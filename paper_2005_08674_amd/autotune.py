@@ -2,8 +2,8 @@
 
 The library times every compiled launch shape on a live lattice (median of
 repeated launches): ``lbm_autotune`` the single-step launch (the fused edge +
-bulk kernel), ``lbm_autotune_two_step`` the two-step sweep where the lattice
-supports it.  The faster per step wins.  This module keeps the winners in
+bulk kernel), ``lbm_autotune_two_step`` the multi-step sweeps (two or three
+steps per launch) where the lattice supports them.  The fastest per step wins.  This module keeps the winners in
 ``tuning/tiles.json`` keyed by (GPU architecture, lattice size, storage), so
 later runs reuse a measured choice instead of re-timing, and records every
 candidate's time.
@@ -113,7 +113,7 @@ def main():
         lat = Lattice(w.nx, w.ny, w.tau, w.fields, store=st)
         lat.step(5)
         e = tune(lat, st, args.reps, args.cache)
-        two = f", two-step {e['two_step']} ({e['two_step_ms'] / 2:.4f} ms per step)" if e["two_step"] else ""
+        two = f", multi-step {e['two_step']} ({e['two_step_ms']:.4f} ms per step)" if e["two_step"] else ""
         print(f"{key(w.nx, w.ny, st)} -> {e['tile']} ({e['ms']:.4f} ms){two}", flush=True)
         lat.close()
 
