@@ -162,7 +162,7 @@ def run_store(torch, W, store, steps, warmup, tune_reps=5, size=4096, serial_che
     return out
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "twostep_pulses4096_f32_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "multistep_pulses4096_f32_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2005_08674_amd", "csrc", f)
                   for f in ("lbm_kernels.hip", "lbm_twostep.hip", "lbm_device.h", "lbm_sweep.h", "lbm_twostep_lds.h")]
 
@@ -547,7 +547,7 @@ def main():
     if main_run["steps_per_launch"] > 1:
         main_run["roofline"]["basis"] = (
             f"achieved counts the algorithmic bytes of {main_run['steps_per_launch']} single steps "
-            f"({main_run['bytes_per_node']} B per node-step); the kernel keeps the intermediate level on chip, "
+            f"({main_run['bytes_per_node']} B per node-step); the kernel keeps the intermediate levels on chip, "
             "so it moves fewer bytes (traffic) and frac can exceed 1")
     line = {
         "metric": METRIC,
