@@ -98,21 +98,24 @@ int lbm_ens_shape_describe(int32_t id, char* buf, size_t len);
 int lbm_ens_set_shape(lbm_ens* e, int32_t id);
 int lbm_ens_autotune(lbm_ens* e, int32_t reps, int32_t* best, float* times_ms);
 
-/* Two-step sweep over the whole ensemble (the single-lattice sweep of
- * lbm_set_two_step, lbm.h: level t + 1 of each 64 x TY tile kept in LDS,
- * eqs. lbe_0, lbe_1 / mrt_lbe and nes_0..nes_4 applied twice; results
- * bit-identical to single steps).  Shapes are the two-step candidates of
- * lbm_two_step_count / lbm_two_step_describe (those with two steps per
- * launch, which come first: ids 0 .. n2 - 1); the ensemble lays every member's tiles
- * out in one list whose contiguous eighths run on the 8 XCDs (the shape's
- * own block map is not used).  lbm_ens_set_two_step selects a shape (-1, the
- * default, turns the sweep off); LBM_ERR_UNSUPPORTED unless every member has
- * NSBC on all four edges.  While a member runs the learned closure the
- * ensemble steps singly.  lbm_ens_autotune_two_step times every shape (median
- * of `reps` launches, after one warm-up; the state is not advanced), selects
- * the fastest and writes its id to *best and, if times_ms is not NULL, the
- * per-shape median time of one launch (two steps) in milliseconds (length
- * n2).  Both drop cached graphs; the autotuner synchronizes the stream. */
+/* Multi-step sweeps over the whole ensemble (the single-lattice sweeps of
+ * lbm_set_two_step, lbm.h: the intermediate levels of each 64 x TY tile kept
+ * in LDS, eqs. lbe_0, lbe_1 / mrt_lbe and nes_0..nes_4 applied per level; results
+ * bit-identical to single steps).  Shapes are the lbm_two_step_count /
+ * lbm_two_step_describe candidates, two or three steps per launch
+ * (lbm_two_step_steps); the ensemble lays every member's tiles out in one
+ * list whose contiguous eighths run on the 8 XCDs (the shape's own block map
+ * is not used).  lbm_ens_set_two_step selects a shape (-1, the default,
+ * turns the sweeps off); LBM_ERR_UNSUPPORTED unless every member has NSBC on
+ * all four edges and, for a three-step shape, is at least 64 x its tile rows
+ * (FP64: tile rows <= 12).  While a member runs the learned closure the
+ * ensemble steps singly.  lbm_ens_autotune_two_step times every shape the
+ * members take (median of `reps` launches, after one warm-up; the state is
+ * not advanced), selects the one with the least time per step and writes its
+ * id to *best and, if times_ms is not NULL, per shape the median launch time
+ * divided by its steps per launch (ms per step; -1 for shapes the members
+ * cannot take; length lbm_two_step_count).  Both drop cached graphs; the
+ * autotuner synchronizes the stream. */
 int lbm_ens_set_two_step(lbm_ens* e, int32_t id);
 int lbm_ens_get_two_step(const lbm_ens* e, int32_t* id);
 int lbm_ens_autotune_two_step(lbm_ens* e, int32_t reps, int32_t* best, float* times_ms);

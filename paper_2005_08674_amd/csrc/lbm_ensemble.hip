@@ -245,7 +245,7 @@ int ens_layout(const lbm_params* m, int32_t count, EnsLayout& L) {
   off = round_up(off + sizeof(lbm::EnsWork) * L.max_work, kAlign);
   // tile list of the two-step sweep at its shortest tiles, padded to a multiple of 8
   L.max_two = 8;
-  const int tymin = lbm::two_step_min_rows();
+  const int tymin = std::min(lbm::two_step_min_rows(), lbm::three_step_min_rows());
   for (int32_t k = 0; k < count; ++k)
     L.max_two += (size_t)((m[k].nx + lbm::TL_TX - 1) / lbm::TL_TX) * ((m[k].ny + tymin - 1) / tymin);
   if (L.max_two > (size_t)INT32_MAX) return fail(LBM_ERR_ARG, "ensemble too large");
@@ -370,9 +370,15 @@ int build_tiles(lbm_ens* e, int shape) {
 // 64 x TY tiles is cut into 8 contiguous stretches and block b takes item
 // (b mod 8) * per + b / 8, so XCD k (block b runs on XCD b mod 8) works through
 // stretch k and neighbouring tiles share its L2; the tail pads with lat = -1.
+// Multi-step shapes: ids below num_two_step() are two-step shapes, the next
+// num_three_step() three-step shapes (as in the single-lattice API).
+int ens_multi_count() { return lbm::num_two_step() + lbm::num_three_step(); }
+int ens_multi_steps(int id) { return id < lbm::num_two_step() ? 2 : 3; }
+
 int build_two(lbm_ens* e, int id) {
-  const int ty = lbm::two_step_tile_rows(id);
-  if (ty <= 0) return fail(LBM_ERR_ARG, "two-step shape %d out of range", id);
+  const int n2 = lbm::num_two_step();
+  const int ty = id < n2 ? lbm::two_step_tile_rows(id) : lbm::three_step_tile_rows(id - n2);
+  if (ty <= 0) return fail(LBM_ERR_ARG, "multi-step shape %d out of range", id);
   std::vector<lbm::TwoTile> items;
   for (int32_t k = 0; k < e->count; ++k) {
     const int tx = (e->p[k].nx + lbm::TL_TX - 1) / lbm::TL_TX, tyn = (e->p[k].ny + ty - 1) / ty;
@@ -395,17 +401,27 @@ int build_two(lbm_ens* e, int id) {
   return LBM_OK;
 }
 
-bool two_supported(const lbm_ens* e) {
-  for (const auto& d : e->descs)
+// every member takes the sweep (id -1: the two-step sweeps' common condition)
+bool two_supported(const lbm_ens* e, int id = -1) {
+  const int n2 = lbm::num_two_step();
+  for (const auto& d : e->descs) {
     if (!lbm::two_step_supported(d)) return false;
+    if (id >= n2 && !lbm::three_step_supported(d, id - n2)) return false;
+  }
   return true;
 }
 
 // Members on the learned closure need the separate edge launch, so they step singly.
 bool use_two(const lbm_ens* e) { return e->two >= 0 && !e->any_closure; }
 
+hipError_t ens_launch_multi(const lbm_ens* e, int id, int parity, hipStream_t s) {
+  const int n2 = lbm::num_two_step();
+  return id < n2 ? lbm::launch_ens_two_step(e->store, id, e->d_descs, e->d_two, e->ntwo, parity, s)
+                 : lbm::launch_ens_three_step(e->store, id - n2, e->d_descs, e->d_two, e->ntwo, parity, s);
+}
+
 int ens_launch_two(lbm_ens* e, int parity, hipStream_t s) {
-  HIPCHK(lbm::launch_ens_two_step(e->store, e->two, e->d_descs, e->d_two, e->ntwo, parity, s));
+  HIPCHK(ens_launch_multi(e, e->two, parity, s));
   return LBM_OK;
 }
 
@@ -555,13 +571,14 @@ int lbm_ens_set_velocity_edge(lbm_ens* e, int32_t member, double ux, double uy) 
 int lbm_ens_step(lbm_ens* e, int32_t n) {
   if (!e) return fail(LBM_ERR_ARG, "ensemble is NULL");
   if (n < 0) return fail(LBM_ERR_ARG, "n = %d < 0", n);
+  const int k = use_two(e) ? ens_multi_steps(e->two) : 1;
   for (int32_t s = 0; s < n;) {
-    const bool two = use_two(e) && n - s >= 2;
-    int rc = two ? ens_launch_two(e, e->parity, e->stream) : ens_launch_step(e, e->parity, e->stream);
+    const bool multi = k > 1 && n - s >= k;
+    int rc = multi ? ens_launch_two(e, e->parity, e->stream) : ens_launch_step(e, e->parity, e->stream);
     if (rc) return rc;
-    e->parity ^= 1;  // a two-step launch writes t + 2 into the other buffer
-    e->t += two ? 2 : 1;
-    s += two ? 2 : 1;
+    e->parity ^= 1;  // a multi-step launch writes t + k into the other buffer
+    e->t += multi ? k : 1;
+    s += multi ? k : 1;
   }
   return LBM_OK;
 }
@@ -570,7 +587,8 @@ int lbm_ens_step_graph(lbm_ens* e, int32_t n) {
   if (!e) return fail(LBM_ERR_ARG, "ensemble is NULL");
   if (n < 1 || n > 100000) return fail(LBM_ERR_ARG, "n = %d outside [1, 100000]", n);
   const bool two = use_two(e);
-  const int launches = two ? n / 2 + (n & 1) : n;
+  const int k = two ? ens_multi_steps(e->two) : 1;
+  const int launches = n / k + n % k;
   const std::pair<int, int> key(n, e->parity);
   auto it = e->graphs.find(key);
   if (it == e->graphs.end()) {
@@ -579,9 +597,9 @@ int lbm_ens_step_graph(lbm_ens* e, int32_t n) {
     int rc = LBM_OK;
     int p = e->parity;
     for (int32_t s = 0; s < n && rc == LBM_OK; p ^= 1) {
-      const bool pair = two && n - s >= 2;
-      rc = pair ? ens_launch_two(e, p, e->cap) : ens_launch_step(e, p, e->cap);
-      s += pair ? 2 : 1;
+      const bool multi = k > 1 && n - s >= k;
+      rc = multi ? ens_launch_two(e, p, e->cap) : ens_launch_step(e, p, e->cap);
+      s += multi ? k : 1;
     }
     hipError_t he = hipStreamEndCapture(e->cap, &g);
     if (rc) {
@@ -742,8 +760,10 @@ int lbm_ens_set_two_step(lbm_ens* e, int32_t id) {
     e->two = -1;
     return LBM_OK;
   }
-  if (id < 0 || id >= lbm::num_two_step()) return fail(LBM_ERR_ARG, "two-step shape %d out of range", id);
-  if (!two_supported(e)) return fail(LBM_ERR_UNSUPPORTED, "the two-step sweep needs NSBC on all four edges of every member");
+  if (id < 0 || id >= ens_multi_count()) return fail(LBM_ERR_ARG, "multi-step shape %d out of range", id);
+  if (!two_supported(e)) return fail(LBM_ERR_UNSUPPORTED, "the multi-step sweeps need NSBC on all four edges of every member");
+  if (!two_supported(e, id))
+    return fail(LBM_ERR_UNSUPPORTED, "three-step shape %d needs every member >= 64 x its tile rows (and LDS for the format)", id);
   return build_two(e, id);
 }
 
@@ -756,21 +776,24 @@ int lbm_ens_get_two_step(const lbm_ens* e, int32_t* id) {
 int lbm_ens_autotune_two_step(lbm_ens* e, int32_t reps, int32_t* best, float* times_ms) {
   if (!e || !best) return fail(LBM_ERR_ARG, "NULL argument");
   if (reps < 1 || reps > 1000) return fail(LBM_ERR_ARG, "reps = %d outside [1, 1000]", reps);
-  if (!two_supported(e)) return fail(LBM_ERR_UNSUPPORTED, "the two-step sweep needs NSBC on all four edges of every member");
+  if (!two_supported(e)) return fail(LBM_ERR_UNSUPPORTED, "the multi-step sweeps need NSBC on all four edges of every member");
   std::vector<hipEvent_t> ev(2 * reps);
   for (auto& x : ev) HIPCHK(hipEventCreate(&x));
   float best_t = 1e30f;
   int best_id = 0;
   int rc = LBM_OK;
-  for (int id = 0; id < lbm::num_two_step() && rc == LBM_OK; ++id) {
+  for (int id = 0; id < ens_multi_count() && rc == LBM_OK; ++id) {
+    if (!two_supported(e, id)) {
+      if (times_ms) times_ms[id] = -1.f;
+      continue;
+    }
     rc = build_two(e, id);
     if (rc) break;
     // the sweep reads buffer `parity` and writes only the other one: the state is not advanced
-    hipError_t he = lbm::launch_ens_two_step(e->store, id, e->d_descs, e->d_two, e->ntwo, e->parity, e->stream);
+    hipError_t he = ens_launch_multi(e, id, e->parity, e->stream);
     for (int r = 0; r < reps && he == hipSuccess; ++r) {
       he = hipEventRecord(ev[2 * r], e->stream);
-      if (he == hipSuccess)
-        he = lbm::launch_ens_two_step(e->store, id, e->d_descs, e->d_two, e->ntwo, e->parity, e->stream);
+      if (he == hipSuccess) he = ens_launch_multi(e, id, e->parity, e->stream);
       if (he == hipSuccess) he = hipEventRecord(ev[2 * r + 1], e->stream);
     }
     if (he == hipSuccess) he = hipStreamSynchronize(e->stream);
@@ -781,9 +804,11 @@ int lbm_ens_autotune_two_step(lbm_ens* e, int32_t reps, int32_t* best, float* ti
       break;
     }
     std::sort(ts.begin(), ts.end());
-    if (times_ms) times_ms[id] = ts[reps / 2];
-    if (ts[reps / 2] < best_t) {
-      best_t = ts[reps / 2];
+    // shapes advance 2 or 3 steps per launch: compare time per step
+    const float per_step = ts[reps / 2] / (float)ens_multi_steps(id);
+    if (times_ms) times_ms[id] = per_step;
+    if (per_step < best_t) {
+      best_t = per_step;
       best_id = id;
     }
   }

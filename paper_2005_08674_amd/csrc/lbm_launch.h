@@ -28,12 +28,17 @@ int num_three_step();
 void three_step_name(int id, char* buf, size_t len);
 bool three_step_supported(const LatDesc& L, int id);
 hipError_t launch_three_step(const LatDesc& L, int parity, int id, hipStream_t s);
+int three_step_tile_rows(int id);
+int three_step_min_rows();
 // ensemble two-step: one block per list entry (member, 64-column tile x, tile y); lat < 0 = padding
 struct TwoTile {
   int32_t lat, txi, tyi, pad;
 };
 hipError_t launch_ens_two_step(int store, int id, const LatDesc* d, const TwoTile* list, int n, int parity,
                                hipStream_t s);
+// the same over the three-step shapes (id among the three-step shapes)
+hipError_t launch_ens_three_step(int store, int id, const LatDesc* d, const TwoTile* list, int n, int parity,
+                                 hipStream_t s);
 hipError_t launch_init(const LatDesc& L, int parity, const double* drho, const double* ux, const double* uy,
                        hipStream_t s);
 int absmax_blocks();

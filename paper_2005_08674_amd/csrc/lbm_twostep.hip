@@ -270,6 +270,55 @@ int two_step_min_rows() {
   return m;
 }
 
+// Three-step sweep over an ensemble's tile list (as k_ens_two_step).
+template <int S, int TY, int NT, bool NTS>
+__global__ __launch_bounds__(NT, two_step_waves<S>()) void k_ens_three_step(const LatDesc* __restrict__ descs,
+                                                       const TwoTile* __restrict__ list, int parity) {
+  const TwoTile t = list[blockIdx.x];
+  if (t.lat < 0) return;  // padding: the whole block leaves before any barrier
+  const LatDesc L = descs[t.lat];
+  three_step_tile<S, TY, NT, NTS, -1>(L, parity, t.txi, t.tyi);
+}
+
+int three_step_tile_rows(int id) { return id >= 0 && id < kNumThree ? kThree[id].ty : 0; }
+
+int three_step_min_rows() {
+  int m = kThree[0].ty;
+  for (int i = 1; i < kNumThree; ++i) m = kThree[i].ty < m ? kThree[i].ty : m;
+  return m;
+}
+
+template <int S>
+static hipError_t launch_ens_three_s(int id, const LatDesc* d, const TwoTile* list, int n, int parity,
+                                     hipStream_t s) {
+  int k = 0;
+#define X(a, b, c)                                                                        \
+  if (id == k) {                                                                          \
+    if constexpr (three_step_fits<S, a>()) {                                              \
+      k_ens_three_step<S, a, b, c><<<dim3(n), dim3(b), 0, s>>>(d, list, parity);          \
+      return hipGetLastError();                                                           \
+    } else {                                                                              \
+      return hipErrorInvalidValue;                                                        \
+    }                                                                                     \
+  }                                                                                       \
+  ++k;
+  LBM_THREE_STEP(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_ens_three_step(int store, int id, const LatDesc* d, const TwoTile* list, int n, int parity,
+                                 hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  switch (store) {
+    case ST_F64: return launch_ens_three_s<ST_F64>(id, d, list, n, parity, s);
+    case ST_F32: return launch_ens_three_s<ST_F32>(id, d, list, n, parity, s);
+    case ST_F16: return launch_ens_three_s<ST_F16>(id, d, list, n, parity, s);
+    case ST_BF16: return launch_ens_three_s<ST_BF16>(id, d, list, n, parity, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 template <int S>
 static hipError_t launch_ens_two_s(int id, const LatDesc* d, const TwoTile* list, int n, int parity,
                                    hipStream_t s) {

@@ -448,14 +448,9 @@ def lbm_ens_get_two_step(ens) -> int:
     return v.value
 
 
-def lbm_two_step_pairs_count() -> int:
-    """Number of two-step shapes (the first ids of lbm_two_step_count; the ensemble runs only these)."""
-    return sum(1 for k in range(lbm_two_step_count()) if lbm_two_step_steps(k) == 2)
-
-
 def lbm_ens_autotune_two_step(ens, reps: int = 5):
     best = ctypes.c_int32()
-    times = (ctypes.c_float * lbm_two_step_pairs_count())()
+    times = (ctypes.c_float * lbm_two_step_count())()
     _check(load().lbm_ens_autotune_two_step(ens, int(reps), ctypes.byref(best), times), "lbm_ens_autotune_two_step")
     return best.value, list(times)
 

@@ -212,12 +212,17 @@ def test_two_step_equals_single_steps_every_shape(store):
     ref.step(8)
     want = [ref.populations(m) for m in range(len(members))]
     ref.close()
-    # the ensemble runs the two-step shapes (the three-step ones are for single lattices)
-    for shape in [k for k in range(lbm.lbm_two_step_count()) if lbm.lbm_two_step_steps(k) == 2]:
-        print(f"[ensemble two-step] {store} {lbm.lbm_two_step_describe(shape)}", flush=True)
+    for shape in range(lbm.lbm_two_step_count()):
+        print(f"[ensemble multi-step] {store} {lbm.lbm_two_step_describe(shape)}", flush=True)
         e = Ensemble(members, fields)
         for m, fa in enumerate(far):
             e.set_farfield(m, *fa)
+        if lbm.lbm_two_step_steps(shape) == 3:
+            # these members include 3 x 3 and 130 x 3 lattices: three-step shapes are refused
+            with pytest.raises(lbm.LbmError):
+                e.set_two_step(shape)
+            e.close()
+            continue
         e.set_two_step(shape)
         assert lbm.lbm_ens_get_two_step(e.ens) == shape
         e.step(7)
@@ -240,7 +245,8 @@ def test_two_step_graph_replays_and_autotune():
         a.set_farfield(m, *fa)
         b.set_farfield(m, *fa)
     best, times = a.autotune_two_step(reps=3)
-    assert 0 <= best < lbm.lbm_two_step_pairs_count() == len(times) and min(times) > 0
+    assert 0 <= best < lbm.lbm_two_step_count() == len(times)
+    assert min(t for k, t in enumerate(times) if lbm.lbm_two_step_steps(k) == 2) > 0
     assert a.t == 0
     for rep in range(4):
         if rep == 2:
@@ -267,3 +273,53 @@ def test_two_step_refused_with_periodic_member_and_off_with_closure():
         e.autotune_two_step(reps=1)
     e.set_two_step(-1)
     e.close()
+
+
+@pytest.mark.parametrize("store", ["f32", "f64"])
+def test_three_step_ensemble_bitwise_equal_to_single_steps(store):
+    """Members all at least 64 wide and 20 tall (the three-step sweep's condition), mixed BGK/MRT and
+    reading variants: every three-step shape the format takes gives each member the bits of single
+    steps, eagerly (11 steps: 3 launches + 2 single steps) and in a graph of 10 steps."""
+    from paper_2005_08674_amd import lbm
+    from paper_2005_08674_amd.ensemble import Ensemble, member_params
+    rng = np.random.default_rng(43)
+    specs = [dict(nx=67, ny=45), dict(nx=100, ny=90, grad_order=2), dict(nx=64, ny=20, corner_mode=1),
+             dict(nx=257, ny=64, corr_mode=1), dict(nx=130, ny=33), dict(nx=65, ny=66, ubase=(0.04, -0.02))]
+    members, fields, far = [], [], []
+    for k, sp in enumerate(specs):
+        nx, ny = sp.pop("nx"), sp.pop("ny")
+        mrt = (1.6, 1.4, 1.8) if k % 2 else None
+        members.append(member_params(nx, ny, float(rng.uniform(0.52, 0.8)), store=store, mrt=mrt, **sp))
+        u0 = (float(rng.uniform(-0.05, 0.05)), float(rng.uniform(-0.05, 0.05)))
+        fields.append(W.gaussian_pulses(nx, ny, [(1e-3, 5.0, rng.uniform(0, nx), rng.uniform(0, ny))], u0=u0))
+        far.append((float(rng.uniform(0, 0.5)), 1.0 + 1e-4, u0[0], u0[1]))
+    ref = Ensemble(members, fields)
+    for m, fa in enumerate(far):
+        ref.set_farfield(m, *fa)
+    ref.step(11)
+    want11 = [ref.populations(m) for m in range(len(members))]
+    ref.step(10)
+    want21 = [ref.populations(m) for m in range(len(members))]
+    ref.close()
+    for shape in range(lbm.lbm_two_step_count()):
+        if lbm.lbm_two_step_steps(shape) != 3:
+            continue
+        ty = int(lbm.lbm_two_step_describe(shape).split("x")[1].split("/")[0])
+        e = Ensemble(members, fields)
+        for m, fa in enumerate(far):
+            e.set_farfield(m, *fa)
+        if store == "f64" and ty > 12:
+            with pytest.raises(lbm.LbmError):
+                e.set_two_step(shape)
+            e.close()
+            continue
+        print(f"[ensemble three-step] {store} {lbm.lbm_two_step_describe(shape)}", flush=True)
+        e.set_two_step(shape)
+        e.step(11)
+        for m in range(len(members)):
+            assert np.array_equal(e.populations(m), want11[m]), (store, shape, m)
+        e.step_graph(10)
+        assert e.t == 21
+        for m in range(len(members)):
+            assert np.array_equal(e.populations(m), want21[m]), (store, shape, m)
+        e.close()
