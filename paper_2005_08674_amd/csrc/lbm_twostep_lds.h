@@ -125,7 +125,9 @@ __device__ inline void two_step_tile(const LatDesc& Ld, int parity, int txi, int
   // lattice and no NSBC node occurs: the loops drop those checks (same
   // arithmetic, same bits) and have trip counts known at compile time.
   const bool inner = x0 >= 3 && x0 + TL_TX + 3 <= nx && y0 >= 2 && y0 + TY + 2 <= ny;
-  if (inner) {
+  // Inlined twice, with the base state's u_b = 0 flag a known constant in
+  // each copy (the per-node arithmetic keeps only the branch that runs).
+  auto inner_sweep = [&](const Base<R>& base) __attribute__((always_inline)) {
     constexpr int N1 = (TY + 2) * TL_W, N2 = TY * TL_TX;
     // per-plane base pointers (uniform) and 32-bit unsigned byte offsets (a
     // plane is below 4 GiB), so each access is a scalar base plus one vector
@@ -165,6 +167,16 @@ __device__ inline void two_step_tile(const LatDesc& Ld, int parity, int txi, int
         for (int i = 0; i < 9; ++i)
           put<NTS>(reinterpret_cast<T*>(reinterpret_cast<char*>(B + i * plane) + off), C::enc(g[i], Ld.es[i]));
       }
+    }
+  };
+  if (inner) {
+    Base<R> b = base;
+    if (base.zero) {
+      b.zero = true;
+      inner_sweep(b);
+    } else {
+      b.zero = false;
+      inner_sweep(b);
     }
     return;
   }
@@ -275,7 +287,10 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
   // Inner tile: every level t + 1 node and its pull sources lie inside the
   // lattice and away from its edges: no clamps, no NSBC.
   const bool inner = x0 >= 3 && x0 + TL_TX + 3 <= nx && y0 >= 3 && y0 + TY + 3 <= ny;
-  if (inner) {
+  // The inner sweep is inlined twice, with the base state's u_b = 0 flag a
+  // known constant in each copy, so the per-node arithmetic carries only the
+  // branch that runs (the operations and their order are unchanged).
+  auto inner_sweep = [&](const Base<R>& base) __attribute__((always_inline)) {
     constexpr int N1 = (TY + 4) * T3_W1, N2 = (TY + 2) * T3_W2, N3 = TY * TL_TX;
 #pragma unroll
     for (int it = 0; it < (N1 + NT - 1) / NT; ++it) {
@@ -325,6 +340,16 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
         for (int i = 0; i < 9; ++i)
           put<NTS>(reinterpret_cast<T*>(reinterpret_cast<char*>(B + i * plane) + off), C::enc(g[i], Ld.es[i]));
       }
+    }
+  };
+  if (inner) {
+    Base<R> b = base;
+    if (base.zero) {
+      b.zero = true;
+      inner_sweep(b);
+    } else {
+      b.zero = false;
+      inner_sweep(b);
     }
     return;
   }
