@@ -55,15 +55,15 @@ int lbm_ens_set_velocity_edge(lbm_ens* e, int32_t member, double ux, double uy);
 
 /* Advance every member n >= 0 steps: one launch per step (fused edge and
  * bulk work), two per step when fusion is off or a member runs the closure,
- * or one launch per two steps when the two-step sweep is on (an odd last
- * step runs singly). */
+ * or one launch per 2 or 3 steps when a multi-step shape is set (the steps
+ * left over at the end run singly). */
 int lbm_ens_step(lbm_ens* e, int32_t n);
 
 /* Advance every member n >= 1 steps with one launch of a HIP graph holding
  * the n steps' kernel launches (as lbm_ens_step would issue them).  The
  * graph is captured and instantiated on first use for this n (and step
  * parity) and cached until lbm_ens_destroy or a change of shape, fusion,
- * two-step shape or closure set. */
+ * multi-step shape or closure set. */
 int lbm_ens_step_graph(lbm_ens* e, int32_t n);
 
 /* on = 1 (the default): each step is one launch whose first blocks run the
