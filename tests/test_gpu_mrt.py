@@ -137,10 +137,10 @@ def test_every_launch_path_bitwise_identical(store):
             try:
                 lbm.lbm_set_two_step(g.ctx, shape)
             except lbm.LbmError:
-                # three-step shapes need whole tiles (nx >= 64, ny >= their rows), and FP64 LDS for
-                # two levels only up to 12 rows
+                # three-step shapes need whole tiles (nx >= 64, ny >= their rows) and their two LDS
+                # levels within 160 KiB
                 ty = int(lbm.lbm_two_step_describe(shape).split("x")[1].split("/")[0])
-                assert lbm.lbm_two_step_steps(shape) == 3 and (nx < 64 or ny < ty or (store == "f64" and ty > 12))
+                assert lbm.lbm_two_step_steps(shape) == 3 and (nx < 64 or ny < ty or 9 * ((ty + 4) * 68 + (ty + 2) * 66) * {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[store] > 160 * 1024)
                 g.close()
                 continue
             g.step(9)

@@ -44,9 +44,15 @@ SIZES = [(203, 77), (61, 5), (3, 3), (4, 3), (3, 40), (62, 64), (121, 130), (240
 
 def _three_step_takes(name, store, nx, ny):
     """Whether three-step shape `name` ("3step:64xTY/...") runs on an nx x ny lattice in `store`:
-    whole tiles, and two LDS levels within 160 KiB (FP64 only up to TY = 12)."""
+    whole tiles, and the two LDS levels (9 x ((TY + 4) x 68 + (TY + 2) x 66) stored values) within
+    160 KiB."""
     ty = int(name.split("x")[1].split("/")[0])
-    return nx >= 64 and ny >= ty and not (store == "f64" and ty > 12)
+    return nx >= 64 and ny >= ty and three_step_lds_fits(store, ty)
+
+
+def three_step_lds_fits(store, ty):
+    es = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[store]
+    return 9 * ((ty + 4) * 68 + (ty + 2) * 66) * es <= 160 * 1024
 
 
 @pytest.mark.parametrize("store", ["f64", "f32", "f16", "bf16"])
