@@ -275,7 +275,7 @@ def test_two_step_refused_with_periodic_member_and_off_with_closure():
     e.close()
 
 
-@pytest.mark.parametrize("store", ["f32", "f64"])
+@pytest.mark.parametrize("store", ["f32", "f64", "f16", "bf16"])
 def test_three_step_ensemble_bitwise_equal_to_single_steps(store):
     """Members all at least 64 wide and 20 tall (the three-step sweep's condition), mixed BGK/MRT and
     reading variants: every three-step shape the format takes gives each member the bits of single
@@ -308,7 +308,7 @@ def test_three_step_ensemble_bitwise_equal_to_single_steps(store):
         e = Ensemble(members, fields)
         for m, fa in enumerate(far):
             e.set_farfield(m, *fa)
-        if 9 * ((ty + 4) * 68 + (ty + 2) * 66) * {"f64": 8, "f32": 4}[store] > 160 * 1024 or ty > 20:
+        if 9 * ((ty + 4) * 68 + (ty + 2) * 66) * {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[store] > 160 * 1024 or ty > 20:
             # the two LDS levels do not fit, or a member (64 x 20) is shorter than the tile
             with pytest.raises(lbm.LbmError):
                 e.set_two_step(shape)
