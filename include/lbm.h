@@ -262,7 +262,11 @@ int lbm_set_fused(lbm_ctx* ctx, int on);
  * the least time per step, writes its id to *best and, if times_ms is not
  * NULL, per shape the median launch time divided by its steps per launch
  * (ms per step; -1 for shapes the lattice cannot take).  Synchronizes the
- * stream.  lbm_two_step_times returns the summed elapsed milliseconds and
+ * stream.  Both autotuners repeat launches on one unchanged input: for a
+ * state small enough to stay in the GPU's last-level cache (256 MB on
+ * MI355X) those reads can hit the cache, which consecutive steps over two
+ * buffers do not, so such lattices are better confirmed by timing a few
+ * dozen consecutive steps per candidate.  lbm_two_step_times returns the summed elapsed milliseconds and
  * the count of multi-step launches timed while lbm_enable_timing is on, and
  * resets them. */
 int lbm_two_step_count(void);
