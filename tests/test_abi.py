@@ -160,3 +160,19 @@ def test_tile_table(lib):
     assert len(set(names)) == n
     with pytest.raises(L.LbmError):
         L.lbm_tile_describe(n)
+
+
+def test_multi_step_shape_table(lib):
+    """Two-step shapes first, then three-step shapes; each name's prefix agrees with its steps per
+    launch, names are unique, and ids outside the table are refused (host-only calls)."""
+    n = L.lbm_two_step_count()
+    names = [L.lbm_two_step_describe(i) for i in range(n)]
+    steps = [L.lbm_two_step_steps(i) for i in range(n)]
+    assert len(set(names)) == n
+    assert all(name.startswith(f"{k}step:64x") for name, k in zip(names, steps))
+    assert 2 in steps and 3 in steps and steps == sorted(steps)
+    for bad in (-1, n):
+        with pytest.raises(L.LbmError):
+            L.lbm_two_step_steps(bad)
+        with pytest.raises(L.LbmError):
+            L.lbm_two_step_describe(bad)
