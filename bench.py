@@ -155,9 +155,15 @@ def run_store(torch, W, store, steps, warmup, tune_reps=5, size=4096, serial_che
         "finite": bool(ok),
         "workload": w,
     }
-    achieved = bpn * nodes_launch * steps_per_launch / (out["kernel_avg_ms"] * 1e-3) / 1e9
+    # The bytes one launch must move: one read and one write of every node's 9 populations (2 x 9 x s
+    # per node), whatever number of steps the launch advances -- a multi-step launch keeps its
+    # intermediate levels on chip, so this one pass is its HBM floor.  The single-step-equivalent
+    # rate (2 x 9 x s per node and step advanced) is kept beside it under its own name.
+    dur = out["kernel_avg_ms"] * 1e-3
+    achieved = bpn * nodes_launch / dur / 1e9
     out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+                       "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                       "step_equivalent_GBs": round(bpn * nodes_launch * steps_per_launch / dur / 1e9, 1)}
     lat.close()
     return out
 
@@ -194,6 +200,32 @@ def recorded_traffic(tile: str):
         return float(rec["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "multistep_pulses4096_f32_sq_counters.md")
+
+
+def recorded_counters(tile: str):
+    """The dominant kernel's SQ counter summary (VALU issue fraction and the like) from profiles/,
+    when it was taken on the current kernel sources and this launch shape; else None."""
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    rec = {}
+    with open(COUNTERS_FILE) as f:
+        for line in f:
+            line = line.strip().lstrip("-* ").strip()
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                rec[k.strip().strip("`")] = v.strip().strip("`")
+    if rec.get("kernel_source_sha256") != kernel_source_sha() or rec.get("tile") != tile:
+        return None
+    out = {}
+    for k in ("valu_issue_frac", "wave_wait_frac", "valu_insts_per_node_update", "node_updates_per_output_node"):
+        try:
+            out[k] = float(rec[k])
+        except (KeyError, ValueError):
+            pass
+    return out or None
 
 
 def run_tc1(torch, W):
@@ -493,20 +525,67 @@ def run_training(torch, steps=300, batches=(4096, 65536), nsamples=1 << 19):
     return out
 
 
-def cpu_baseline(W, w, budget_s=12.0):
-    import oracle
-    o = oracle.Lattice(w.nx, w.ny, w.tau, *w.fields)
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        o.step(1)
-        steps += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": round(w.nx * w.ny * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{w.nx}x{w.ny} pulse workload, {steps} fp64 oracle steps ({dt:.1f} s, init excluded)"}
+CPU_RUNS = [
+    # (name, workload factory, steps with one thread, steps with all threads)
+    ("pulse128", "pulse_128", 1000, 1000),
+    ("vortex512x256", "vortex_512x256", 200, 1000),
+    ("pulses4096", "pulses_4096", 3, 20),
+]
+
+_CPU_CHILD = r"""
+import json, sys, time
+sys.path.insert(0, {root!r})
+import oracle
+from paper_2005_08674_amd import workloads as W
+w = getattr(W, {factory!r})()
+o = oracle.Lattice(w.nx, w.ny, w.tau, *w.fields, m0=getattr(w, "m0", None) or (1.0, 0.0, 0.0))
+o.step(1)
+t0 = time.perf_counter()
+o.step({steps})
+dt = time.perf_counter() - t0
+print(json.dumps({{"nodes": w.nx * w.ny, "steps": {steps}, "s": dt, "threads": oracle.num_threads()}}))
+"""
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(W, w):
+    """The fp64 oracle (plain C, OpenMP over rows) timed on the host: the 128^2 pulse in full (1000
+    steps), the 512x256 vortex and the 4096^2 pulses for a bounded number of steps, each with one
+    thread and with every thread the process may use (OMP_NUM_THREADS, else the CPU count), each in
+    a child process, one untimed step and lattice set-up excluded.  `value` is the 4096^2 figure with
+    all threads, the workload `value` of this line is measured on."""
+    import subprocess
+    nproc = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    runs = []
+    for threads in (1, nproc):
+        for name, factory, s1, sn in CPU_RUNS:
+            steps = s1 if threads == 1 else sn
+            env = {**os.environ, "OMP_NUM_THREADS": str(threads)}
+            r = subprocess.run([sys.executable, "-c", _CPU_CHILD.format(root=ROOT, factory=factory, steps=steps)],
+                               env=env, capture_output=True, text=True, timeout=600)
+            if r.returncode != 0:
+                log(f"[cpu_baseline] {name} x{threads} failed: {r.stderr[-500:]}")
+                continue
+            d = json.loads(r.stdout.strip().splitlines()[-1])
+            runs.append({"workload": name, "threads": d["threads"], "steps": d["steps"], "seconds": round(d["s"], 3),
+                         "MLUPS": round(d["nodes"] * d["steps"] / d["s"] / 1e6, 3)})
+            log(f"[cpu_baseline] {runs[-1]}")
+    head = [r for r in runs if r["workload"] == "pulses4096" and r["threads"] == nproc]
+    return {"value": head[0]["MLUPS"] if head else None, "unit": "MLUPS",
+            "cores": head[0]["threads"] if head else nproc, "kind": "oracle",
+            "sample": f"{w.nx}x{w.ny} pulse workload, {CPU_RUNS[2][3]} fp64 oracle steps with {nproc} threads "
+                      "(set-up and one step excluded); runs lists the other samples",
+            "cpu_model": cpu_model(), "runs": runs}
 
 
 def main():
@@ -573,11 +652,15 @@ def main():
         main_run["roofline"]["traffic"] = traffic
         # the counters' bytes over the same launch duration: the HBM bandwidth the kernel really draws
         main_run["roofline"]["traffic_GBs"] = round(traffic / (main_run["kernel_avg_ms"] * 1e-3) / 1e9, 1)
-    if main_run["steps_per_launch"] > 1:
-        main_run["roofline"]["basis"] = (
-            f"achieved counts the algorithmic bytes of {main_run['steps_per_launch']} single steps "
-            f"({main_run['bytes_per_node']} B per node-step); the kernel keeps the intermediate levels on chip, "
-            "so it moves fewer bytes (traffic) and frac can exceed 1")
+    main_run["roofline"]["basis"] = (
+        f"achieved = the bytes one launch must move, one read and one write of the state "
+        f"({main_run['bytes_per_node']} B per node = 2 x 9 x 4 B, x {main_run['nodes_per_launch']} nodes), "
+        f"over the kernel's average launch duration ({main_run['kernel_avg_ms']:.5f} ms, HIP events on its stream); "
+        f"the launch advances {main_run['steps_per_launch']} step(s), keeping intermediate levels on chip; "
+        "step_equivalent_GBs counts 2 x 9 x 4 B per node and step advanced instead")
+    sq = recorded_counters(main_run["kernel_shape"])
+    if sq:
+        main_run["roofline"]["counters"] = sq
     line = {
         "metric": METRIC,
         "value": round(main_run["mlups"], 1),

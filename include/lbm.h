@@ -176,6 +176,42 @@ int lbm_set_populations(lbm_ctx* ctx, const double* g);
  * LBM_ERR_NONFINITE).  Synchronizes the stream. */
 int lbm_check_finite(lbm_ctx* ctx, int* ok);
 
+/* Checkpoint of the whole state as host bytes, for continuing a run in a
+ * later process (the paper's state at time t is the population set, Sec. 3,
+ * eq. lbe_0, plus the far-field criterion of eq. nes_3).
+ * lbm_save_bytes: the size lbm_save writes, 256 + 9 * nx * ny * (bytes per
+ * stored population).
+ * lbm_save: writes into host_buf (>= that size, caller-owned) a 256-byte
+ * header -- magic "LBMCKPT1", version 1, lattice size, storage and FP16
+ * exponent, edges, NSBC readings, collision model and rates, tau, rho0, u_b,
+ * gamma, the time step t, the far-field factor beta and vector m0, the
+ * velocity-edge velocity u_w, the closure mode with the byte count and
+ * 64-bit FNV-1a hash of the network the context uses, and the payload's
+ * size and hash -- followed by the populations exactly as stored, as a
+ * compact [9][ny][nx] array in the storage format.  Synchronizes the stream.
+ * lbm_load: restores such a checkpoint into a context created with the same
+ * lattice size, storage, edges, readings, collision model and rates, tau,
+ * rho0, u_b and gamma (else LBM_ERR_STATE) and using the same closure
+ * network, or none, as the saved one (else LBM_ERR_STATE); a damaged or
+ * foreign buffer gives LBM_ERR_ARG.  It sets the populations, t, beta, m0,
+ * u_w and, for FP16 storage, the codec exponent the values were saved with,
+ * so the run continues bit for bit as the saved one would have.  A refused
+ * checkpoint leaves the context unchanged.  Synchronizes the stream. */
+int lbm_save_bytes(const lbm_ctx* ctx, size_t* bytes);
+int lbm_save(lbm_ctx* ctx, void* host_buf, size_t bytes);
+int lbm_load(lbm_ctx* ctx, const void* host_buf, size_t bytes);
+
+/* Debug mode.  level 0: off.  level 1: every call of this library that
+ * enqueues work on a stream synchronizes that stream before returning and
+ * reports a failed kernel or HIP call as LBM_ERR_HIP with the call's name in
+ * lbm_last_error().  level 2: in addition every step call checks that the
+ * populations are finite and returns LBM_ERR_NONFINITE when they are not.
+ * The initial level is read once from the environment variable LBM_DEBUG
+ * ("0", "1" or "2"; unset = 0); lbm_set_debug changes it for the whole
+ * process (level in [0, 2], else LBM_ERR_ARG). */
+int lbm_set_debug(int32_t level);
+int lbm_debug_level(int32_t* level);
+
 /* FP16 codec exponent k in use (0 for the other stores). */
 int lbm_f16_exp(const lbm_ctx* ctx, int32_t* k);
 
@@ -254,9 +290,11 @@ int lbm_set_fused(lbm_ctx* ctx, int on);
  * list the candidate shapes and lbm_two_step_steps gives a shape's steps per
  * launch; lbm_set_two_step selects one (-1 turns the sweeps off, the
  * default) and fails for lattices it does not support.  With a shape
- * selected, lbm_step advances groups of that many steps with it and the
- * remainder with the single-step launch; the closure, the overlap option
- * and periodic edges always use the single-step kernels.
+ * selected, lbm_step advances groups of that many steps with it; after
+ * three-step launches a remainder of two steps takes one two-step launch
+ * (the best two-step shape lbm_autotune_two_step timed, else a default per
+ * storage format), any other remainder single-step launches.  The closure,
+ * the overlap option and periodic edges always use the single-step kernels.
  * lbm_autotune_two_step times every shape the lattice supports (`reps`
  * launches each, median; the state is left unchanged), selects the one with
  * the least time per step, writes its id to *best and, if times_ms is not

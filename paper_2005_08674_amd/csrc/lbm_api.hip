@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -63,6 +64,12 @@ int check_params(const lbm_params* p) {
   if (p->nx < 3 || p->ny < 3) return fail(LBM_ERR_ARG, "lattice %dx%d: each side must be >= 3", p->nx, p->ny);
   if ((int64_t)p->nx * p->ny > (int64_t)1 << 28)
     return fail(LBM_ERR_ARG, "lattice %dx%d exceeds 2^28 nodes", p->nx, p->ny);
+  if (p->store >= LBM_STORE_F64 && p->store <= LBM_STORE_BF16DEV) {
+    // the sweeps address a plane with 32-bit byte offsets (row * pitch + x)
+    const int64_t row = ((int64_t)p->nx * (int64_t)elem_bytes(p->store) + 255) / 256 * 256;
+    if (row * p->ny > ((int64_t)1 << 32) - 65536)
+      return fail(LBM_ERR_ARG, "lattice %dx%d: a plane with rows padded to 256 bytes exceeds 4 GiB", p->nx, p->ny);
+  }
   if (p->collision != LBM_COLL_BGK && p->collision != LBM_COLL_MRT)
     return fail(LBM_ERR_ARG, "collision = %d is not LBM_COLL_BGK or LBM_COLL_MRT", p->collision);
   if (p->collision == LBM_COLL_BGK && (!(p->tau > 0.5) || !std::isfinite(p->tau)))
@@ -181,6 +188,37 @@ int set_farfield(LatDesc& L, double beta, double rho_ref, double ux_ref, double 
   return LBM_OK;
 }
 
+namespace {
+int g_debug = -1;  // -1: not read from the environment yet
+}
+
+int debug_level() {
+  if (g_debug < 0) {
+    const char* e = std::getenv("LBM_DEBUG");
+    g_debug = e ? std::max(0, std::min(2, std::atoi(e))) : 0;
+  }
+  return g_debug;
+}
+
+void set_debug_level(int level) { g_debug = std::max(0, std::min(2, level)); }
+
+int debug_sync(hipStream_t s, const char* call) {
+  if (debug_level() == 0) return LBM_OK;
+  hipError_t e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return fail(LBM_ERR_HIP, "%s (LBM_DEBUG): %s", call, hipGetErrorString(e));
+  return LBM_OK;
+}
+
+uint64_t fnv1a(const void* p, size_t n, uint64_t h) {
+  const unsigned char* b = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
 int f16_exp_from_max(float mx) {
   int k = mx > 1e-30f ? (int)std::floor(std::log2(4096.0 / (double)mx)) : 12;
   return std::min(60, std::max(-30, k));
@@ -235,8 +273,12 @@ struct lbm_ctx {
   std::vector<char> ev_two;  // per 4-event group: 1 = a two-step launch (events 0, 1)
   double two_ms = 0;
   int64_t two_n = 0;
-  // two-step sweep shape (-1: off)
+  // multi-step sweep shape (-1: off)
   int two_step = -1;
+  // shape per steps-per-launch k (2..4) that runs a remainder of k steps
+  // after launches of the selected shape (the autotuner's best shape with
+  // that many steps, else a default)
+  int rem_best[5] = {-1, -1, -1, -1, -1};
   // edge segments and bulk tiles of a step in one launch
   bool fused = true;
 };
@@ -352,10 +394,16 @@ hipError_t launch_multi(const lbm::LatDesc& L, int parity, int id, hipStream_t s
   return id < lbm::num_two_step() ? lbm::launch_two_step(L, parity, id, s)
                                   : lbm::launch_three_step(L, parity, id - lbm::num_two_step(), s);
 }
+void multi_name(int id, char* buf, size_t len) {
+  if (id < lbm::num_two_step())
+    lbm::two_step_name(id, buf, len);
+  else
+    lbm::three_step_name(id - lbm::num_two_step(), buf, len);
+}
 
-// Two or three steps in one launch of the multi-step sweep (same results as
+// Two or three steps in one launch of multi-step shape `id` (same results as
 // that many step_once calls).
-int step_twice(lbm_ctx* c) {
+int step_multi(lbm_ctx* c, int id) {
   hipEvent_t t[4] = {nullptr, nullptr, nullptr, nullptr};
   if (c->timing) {
     if (c->ev_used + 4 > 4 * 4096) {
@@ -369,12 +417,29 @@ int step_twice(lbm_ctx* c) {
     c->ev_two.push_back(1);
   }
   if (t[0]) HIPCHK(hipEventRecord(t[0], c->stream));
-  HIPCHK(launch_multi(c->L, c->parity, c->two_step, c->stream));
+  HIPCHK(launch_multi(c->L, c->parity, id, c->stream));
   if (t[1]) HIPCHK(hipEventRecord(t[1], c->stream));
   // the last level is in the other buffer: the launch wrote buffer parity ^ 1
   c->parity ^= 1;
-  c->t += multi_steps(c->two_step);
+  c->t += multi_steps(id);
   return LBM_OK;
+}
+
+// Shape that runs a remainder of k steps (2 <= k <= 4): the autotuner's best
+// supported shape with k steps per launch, else (k = 2) the band-mapped two-step
+// shape 64x12/512 for FP64 or 64x20/768 for the other formats; -1 if none.
+int rem_shape(const lbm_ctx* c, int k) {
+  if (k < 2 || k > 4) return -1;
+  if (c->rem_best[k] >= 0 && multi_supported(c->L, c->rem_best[k])) return c->rem_best[k];
+  if (k == 2) {
+    const char* want = c->p.store == LBM_STORE_F64 ? "2step:64x12/512+xcdband+nts" : "2step:64x20/768+xcdband+nts";
+    char buf[64];
+    for (int id = 0; id < lbm::num_two_step(); ++id) {
+      lbm::two_step_name(id, buf, sizeof(buf));
+      if (std::strcmp(buf, want) == 0 && multi_supported(c->L, id)) return id;
+    }
+  }
+  return -1;
 }
 
 bool use_two_step(const lbm_ctx* c) {
@@ -501,8 +566,18 @@ int lbm_step(lbm_ctx* c, int32_t n) {
   if (use_two_step(c)) {
     const int k = multi_steps(c->two_step);
     for (; s + k <= n; s += k) {
-      int rc = step_twice(c);
+      int rc = step_multi(c, c->two_step);
       if (rc) return rc;
+    }
+    // a remainder of two or more steps: one launch of a shape with that
+    // many steps instead of single steps (same results)
+    if (n - s >= 2) {
+      const int r = rem_shape(c, n - s);
+      if (r >= 0) {
+        int rc = step_multi(c, r);
+        if (rc) return rc;
+        s += multi_steps(r);
+      }
     }
   }
   for (; s < n; ++s) {
@@ -511,7 +586,12 @@ int lbm_step(lbm_ctx* c, int32_t n) {
   }
   // join: later work on the stream sees the last edge kernel too
   if (c->overlap) HIPCHK(hipStreamWaitEvent(c->stream, c->ev_edge, 0));
-  return LBM_OK;
+  int rc = lbm::host::debug_sync(c->stream, "lbm_step");
+  if (rc == LBM_OK && lbm::host::debug_level() >= 2) {
+    int ok = 1;
+    rc = lbm_check_finite(c, &ok);
+  }
+  return rc;
 }
 
 int lbm_set_overlap(lbm_ctx* c, int on) {
@@ -523,7 +603,7 @@ int lbm_set_overlap(lbm_ctx* c, int on) {
 int lbm_moments(lbm_ctx* c, void* r, void* u, void* v, int out_f64, int deviation) {
   if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
   HIPCHK(lbm::launch_moments(c->L, c->parity, r, u, v, out_f64 ? 1 : 0, deviation ? 1 : 0, c->stream));
-  return LBM_OK;
+  return lbm::host::debug_sync(c->stream, "lbm_moments");
 }
 
 int lbm_time(const lbm_ctx* c, int64_t* t) {
@@ -550,13 +630,13 @@ void lbm_destroy(lbm_ctx* c) {
 int lbm_get_populations(lbm_ctx* c, double* g_out) {
   if (!c || !g_out) return fail(LBM_ERR_ARG, "NULL argument");
   HIPCHK(lbm::launch_get_pops(c->L, c->parity, g_out, c->stream));
-  return LBM_OK;
+  return lbm::host::debug_sync(c->stream, "lbm_get_populations");
 }
 
 int lbm_set_populations(lbm_ctx* c, const double* g) {
   if (!c || !g) return fail(LBM_ERR_ARG, "NULL argument");
   HIPCHK(lbm::launch_set_pops(c->L, c->parity, g, c->stream));
-  return LBM_OK;
+  return lbm::host::debug_sync(c->stream, "lbm_set_populations");
 }
 
 int lbm_check_finite(lbm_ctx* c, int* ok) {
@@ -589,7 +669,7 @@ int lbm_energy(lbm_ctx* test, const lbm_ctx* ref, int32_t x_off, int32_t y_off, 
   double* part = reinterpret_cast<double*>(test->scratch + kOffEnergy);
   HIPCHK(lbm::launch_energy(test->L, test->parity, ref ? &ref->L : nullptr, ref ? ref->parity : 0, x_off, y_off,
                             ux_ref, uy_ref, part, out_dev, test->stream));
-  return LBM_OK;
+  return lbm::host::debug_sync(test->stream, "lbm_energy");
 }
 
 int lbm_tile_count(void) { return lbm::num_tiles(); }
@@ -675,10 +755,7 @@ int lbm_two_step_count(void) { return multi_count(); }
 int lbm_two_step_describe(int32_t id, char* buf, size_t len) {
   if (!buf || len == 0) return fail(LBM_ERR_ARG, "NULL buffer");
   if (id < 0 || id >= multi_count()) return fail(LBM_ERR_ARG, "multi-step shape %d out of range", id);
-  if (id < lbm::num_two_step())
-    lbm::two_step_name(id, buf, len);
-  else
-    lbm::three_step_name(id - lbm::num_two_step(), buf, len);
+  multi_name(id, buf, len);
   return LBM_OK;
 }
 
@@ -695,7 +772,10 @@ int lbm_set_two_step(lbm_ctx* c, int32_t id) {
   if (id >= 0 && !lbm::two_step_supported(c->L))
     return fail(LBM_ERR_ARG, "the multi-step sweeps need NSBC on all four edges");
   if (id >= 0 && !multi_supported(c->L, id))
-    return fail(LBM_ERR_ARG, "three-step shape %d needs whole tiles (nx >= 64, ny >= its tile rows) and LDS for this format", id);
+    return fail(LBM_ERR_ARG,
+                "multi-step shape %d: three-step shapes need whole tiles (nx >= 64, ny >= its tile rows), column-march "
+                "shapes nx >= their strip width and the first-order gradient, and both LDS for this format",
+                id);
   c->two_step = id;
   return LBM_OK;
 }
@@ -717,8 +797,8 @@ int lbm_autotune_two_step(lbm_ctx* c, int32_t reps, int32_t* best, float* times_
   const int nt = multi_count();
   std::vector<hipEvent_t> ev(2 * reps);
   for (auto& e : ev) HIPCHK(hipEventCreate(&e));
-  float best_t = 1e30f;
-  int best_id = 0;
+  float best_t = 1e30f, best_k_t[5] = {1e30f, 1e30f, 1e30f, 1e30f, 1e30f};
+  int best_id = 0, best_k[5] = {-1, -1, -1, -1, -1};
   int rc = LBM_OK;
   for (int id = 0; id < nt && rc == LBM_OK; ++id) {
     if (!multi_supported(c->L, id)) {
@@ -745,10 +825,17 @@ int lbm_autotune_two_step(lbm_ctx* c, int32_t reps, int32_t* best, float* times_
       best_t = med;
       best_id = id;
     }
+    const int k = multi_steps(id);
+    if (med < best_k_t[k]) {
+      best_k_t[k] = med;
+      best_k[k] = id;
+    }
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
   if (rc) return rc;
   c->two_step = best_id;
+  for (int k = 2; k <= 4; ++k)
+    if (best_k[k] >= 0) c->rem_best[k] = best_k[k];
   *best = best_id;
   return LBM_OK;
 }
@@ -812,6 +899,182 @@ int lbm_closure_moments(lbm_ctx* c, const int32_t* sites, int32_t n, const float
   if (!c || (n > 0 && (!sites || !m_out))) return fail(LBM_ERR_ARG, "NULL argument");
   if (n < 0) return fail(LBM_ERR_ARG, "n < 0");
   HIPCHK(lbm::host::closure_moments(&c->L, nullptr, 1, c->parity, sites, n, sub, m_out, c->stream));
+  return LBM_OK;
+}
+
+int lbm_set_debug(int32_t level) {
+  if (level < 0 || level > 2) return fail(LBM_ERR_ARG, "debug level %d outside [0, 2]", level);
+  lbm::host::set_debug_level(level);
+  return LBM_OK;
+}
+
+int lbm_debug_level(int32_t* level) {
+  if (!level) return fail(LBM_ERR_ARG, "NULL argument");
+  *level = lbm::host::debug_level();
+  return LBM_OK;
+}
+
+}  // extern "C"
+
+extern "C" int lbm_closure_net_bytes(size_t* bytes);  // include/lbm_closure.h
+
+namespace {
+
+// Checkpoint header (include/lbm.h, lbm_save): fixed 256 bytes, host byte
+// order, followed by the populations of the 9 planes as stored, [9][ny][nx].
+struct SaveHeader {
+  char magic[8];
+  uint32_t version, header_bytes;
+  int32_t nx, ny, store, f16_exp;
+  int32_t bc[4];
+  int32_t corr_mode, grad_order, corner_mode, collision;
+  int64_t t;
+  double tau, rho0, ubase[2], gamma, omega_e, omega_eps, omega_q;
+  double beta, m0[3], uw[2];
+  int32_t closure, _pad;
+  uint64_t net_bytes, net_hash;
+  uint64_t payload_bytes, payload_hash;
+};
+static_assert(sizeof(SaveHeader) <= 256, "checkpoint header exceeds 256 bytes");
+constexpr char kSaveMagic[8] = {'L', 'B', 'M', 'C', 'K', 'P', 'T', '1'};
+constexpr size_t kHeaderBytes = 256;
+
+size_t payload_bytes(const lbm_ctx* c) { return 9 * (size_t)c->p.nx * c->p.ny * c->lay.esize; }
+
+// Hash of the closure network the context uses (0 bytes, hash 0 without one).
+int net_identity(lbm_ctx* c, uint64_t* bytes, uint64_t* hash) {
+  *bytes = 0;
+  *hash = 0;
+  if (!(c->L.closure && c->L.net)) return LBM_OK;
+  size_t nb = 0;
+  int rc = lbm_closure_net_bytes(&nb);
+  if (rc) return rc;
+  std::vector<unsigned char> host(nb);
+  HIPCHK(hipMemcpyAsync(host.data(), c->L.net, nb, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  *bytes = nb;
+  *hash = lbm::host::fnv1a(host.data(), nb);
+  return LBM_OK;
+}
+
+// Copy the current buffer's 9 planes to/from a compact host [9][ny][nx] array.
+int copy_planes(lbm_ctx* c, void* host, bool to_host) {
+  const size_t es = c->lay.esize, row = (size_t)c->p.nx * es;
+  char* dev = static_cast<char*>(lbm::buf_of(c->L, c->parity));
+  char* h = static_cast<char*>(host);
+  for (int i = 0; i < 9; ++i) {
+    char* d = dev + (size_t)i * c->lay.plane * es;
+    char* hp = h + (size_t)i * row * c->p.ny;
+    if (to_host)
+      HIPCHK(hipMemcpy2DAsync(hp, row, d, (size_t)c->lay.pitch * es, row, c->p.ny, hipMemcpyDeviceToHost, c->stream));
+    else
+      HIPCHK(hipMemcpy2DAsync(d, (size_t)c->lay.pitch * es, hp, row, row, c->p.ny, hipMemcpyHostToDevice, c->stream));
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_save_bytes(const lbm_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return fail(LBM_ERR_ARG, "NULL argument");
+  *bytes = kHeaderBytes + payload_bytes(c);
+  return LBM_OK;
+}
+
+int lbm_save(lbm_ctx* c, void* host_buf, size_t bytes) {
+  if (!c || !host_buf) return fail(LBM_ERR_ARG, "NULL argument");
+  const size_t need = kHeaderBytes + payload_bytes(c);
+  if (bytes < need) return fail(LBM_ERR_ARG, "checkpoint buffer of %zu bytes < %zu required", bytes, need);
+  SaveHeader h;
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, kSaveMagic, 8);
+  h.version = 1;
+  h.header_bytes = kHeaderBytes;
+  h.nx = c->p.nx;
+  h.ny = c->p.ny;
+  h.store = c->p.store;
+  h.f16_exp = c->p.store == LBM_STORE_F16DEV ? c->f16_exp : 0;
+  for (int e = 0; e < 4; ++e) h.bc[e] = c->p.bc[e];
+  h.corr_mode = c->p.corr_mode;
+  h.grad_order = c->p.grad_order;
+  h.corner_mode = c->p.corner_mode;
+  h.collision = c->p.collision;
+  h.t = c->t;
+  h.tau = c->p.tau;
+  h.rho0 = c->p.rho0;
+  h.ubase[0] = c->p.ubase[0];
+  h.ubase[1] = c->p.ubase[1];
+  h.gamma = c->p.gamma;
+  h.omega_e = c->p.omega_e;
+  h.omega_eps = c->p.omega_eps;
+  h.omega_q = c->p.omega_q;
+  h.beta = c->L.beta;
+  for (int k = 0; k < 3; ++k) h.m0[k] = c->L.m0[k];
+  h.uw[0] = c->L.uw[0];
+  h.uw[1] = c->L.uw[1];
+  h.closure = (c->L.closure && c->L.net) ? 1 : 0;
+  int rc = net_identity(c, &h.net_bytes, &h.net_hash);
+  if (rc) return rc;
+  char* out = static_cast<char*>(host_buf);
+  rc = copy_planes(c, out + kHeaderBytes, true);
+  if (rc) return rc;
+  h.payload_bytes = payload_bytes(c);
+  h.payload_hash = lbm::host::fnv1a(out + kHeaderBytes, h.payload_bytes);
+  std::memset(out, 0, kHeaderBytes);
+  std::memcpy(out, &h, sizeof(h));
+  return LBM_OK;
+}
+
+int lbm_load(lbm_ctx* c, const void* host_buf, size_t bytes) {
+  if (!c || !host_buf) return fail(LBM_ERR_ARG, "NULL argument");
+  if (bytes < kHeaderBytes) return fail(LBM_ERR_ARG, "checkpoint of %zu bytes is shorter than its header", bytes);
+  SaveHeader h;
+  std::memcpy(&h, host_buf, sizeof(h));
+  if (std::memcmp(h.magic, kSaveMagic, 8) != 0 || h.version != 1 || h.header_bytes != kHeaderBytes)
+    return fail(LBM_ERR_ARG, "not a version-1 lbm checkpoint");
+  if (h.payload_bytes != payload_bytes(c) || bytes < kHeaderBytes + h.payload_bytes)
+    return fail(LBM_ERR_ARG, "checkpoint payload of %llu bytes does not fit this %dx%d lattice or the buffer",
+                (unsigned long long)h.payload_bytes, c->p.nx, c->p.ny);
+  const char* in = static_cast<const char*>(host_buf);
+  if (lbm::host::fnv1a(in + kHeaderBytes, h.payload_bytes) != h.payload_hash)
+    return fail(LBM_ERR_ARG, "checkpoint payload is corrupt (hash mismatch)");
+  // the checkpoint continues the same problem: lattice, storage and physics must match
+  const lbm_params& p = c->p;
+  bool same = h.nx == p.nx && h.ny == p.ny && h.store == p.store &&
+              h.corr_mode == p.corr_mode && h.grad_order == p.grad_order && h.corner_mode == p.corner_mode &&
+              h.collision == p.collision && h.tau == p.tau && h.rho0 == p.rho0 && h.ubase[0] == p.ubase[0] &&
+              h.ubase[1] == p.ubase[1] && h.gamma == p.gamma;
+  for (int e = 0; e < 4; ++e) same = same && h.bc[e] == p.bc[e];
+  if (p.collision == LBM_COLL_MRT)
+    same = same && h.omega_e == p.omega_e && h.omega_eps == p.omega_eps && h.omega_q == p.omega_q;
+  if (!same) return fail(LBM_ERR_STATE, "checkpoint was taken on a lattice with other parameters or storage");
+  uint64_t nb = 0, nh = 0;
+  int rc = net_identity(c, &nb, &nh);
+  if (rc) return rc;
+  const int closure = (c->L.closure && c->L.net) ? 1 : 0;
+  if (closure != h.closure || nb != h.net_bytes || nh != h.net_hash)
+    return fail(LBM_ERR_STATE, "checkpoint closure (mode %d) differs from the context's (mode %d or another network)",
+                h.closure, closure);
+  if (!(h.beta >= 0.0 && h.beta <= 1.0)) return fail(LBM_ERR_ARG, "checkpoint beta %g outside [0, 1]", h.beta);
+  if (p.store == LBM_STORE_F16DEV && (h.f16_exp < -30 || h.f16_exp > 60))
+    return fail(LBM_ERR_ARG, "checkpoint FP16 exponent %d outside [-30, 60]", h.f16_exp);
+  lbm::LatDesc L = c->L;
+  rc = lbm::host::set_velocity_edge(L, h.uw[0], h.uw[1]);
+  if (rc) return rc;
+  rc = copy_planes(c, const_cast<char*>(in) + kHeaderBytes, false);
+  if (rc) return rc;
+  L.beta = h.beta;
+  for (int k = 0; k < 3; ++k) L.m0[k] = h.m0[k];
+  if (p.store == LBM_STORE_F16DEV) {
+    // the saved values are encoded with the saved exponent
+    c->f16_exp = h.f16_exp;
+    lbm::host::set_scales(L, p.store, h.f16_exp);
+  }
+  c->L = L;
+  c->t = h.t;
   return LBM_OK;
 }
 

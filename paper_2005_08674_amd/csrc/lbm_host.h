@@ -41,6 +41,20 @@ int set_farfield(LatDesc& L, double beta, double rho_ref, double ux_ref, double 
 int set_velocity_edge(LatDesc& L, double ux, double uy);
 int f16_exp_from_max(float mx);
 
+// Debug level: 0 off; 1 every call that enqueues work synchronizes its
+// stream and reports any HIP error as LBM_ERR_HIP; 2 also checks after every
+// step call that the populations are finite (LBM_ERR_NONFINITE).  Starts
+// from the environment variable LBM_DEBUG, read once; lbm_set_debug changes
+// it for the process.
+int debug_level();
+void set_debug_level(int level);
+// With debug on: synchronize `s` and turn a pending HIP error into
+// LBM_ERR_HIP naming `call`.  LBM_OK when debug is off.
+int debug_sync(hipStream_t s, const char* call);
+
+// 64-bit FNV-1a hash of `n` bytes (checkpoint integrity and identity).
+uint64_t fnv1a(const void* p, size_t n, uint64_t h = 1469598103934665603ull);
+
 // Closure sampling launchers (lbm_closure.hip).  Exactly one of `single`
 // (one lattice) or `descs` (device descriptors of an ensemble) is used.
 hipError_t closure_features(const LatDesc* single, const LatDesc* descs, int count, int parity, const int32_t* sites,

@@ -86,6 +86,14 @@ class Lattice:
         L.lbm_set_populations(self.ctx, g.data_ptr())
         self.stream.synchronize()
 
+    def save(self) -> bytes:
+        """Checkpoint (header + populations as stored) as host bytes (lbm_save)."""
+        return L.lbm_save(self.ctx)
+
+    def load(self, data: bytes):
+        """Restore a checkpoint taken on a lattice with the same parameters (lbm_load)."""
+        L.lbm_load(self.ctx, data)
+
     def check_finite(self) -> bool:
         return L.lbm_check_finite(self.ctx)
 

@@ -89,6 +89,11 @@ _SIGS = {
     "lbm_get_two_step": [_P, _P],
     "lbm_autotune_two_step": [_P, ctypes.c_int32, _P, _P],
     "lbm_two_step_times": [_P, _P, _P],
+    "lbm_save_bytes": [_P, _P],
+    "lbm_save": [_P, _P, ctypes.c_size_t],
+    "lbm_load": [_P, _P, ctypes.c_size_t],
+    "lbm_set_debug": [ctypes.c_int32],
+    "lbm_debug_level": [_P],
     # ensemble (include/lbm_ensemble.h)
     "lbm_ens_workspace_bytes": [_P, ctypes.c_int32, _P],
     "lbm_ens_init": [_P, _P, ctypes.c_int32, _P, ctypes.c_size_t, _P, _P, _P, _P],
@@ -239,6 +244,35 @@ def lbm_get_populations(ctx, g_ptr):
 
 def lbm_set_populations(ctx, g_ptr):
     _check(load().lbm_set_populations(ctx, g_ptr), "lbm_set_populations")
+
+
+def lbm_save_bytes(ctx) -> int:
+    n = ctypes.c_size_t()
+    _check(load().lbm_save_bytes(ctx, ctypes.byref(n)), "lbm_save_bytes")
+    return n.value
+
+
+def lbm_save(ctx) -> bytes:
+    """The context's checkpoint (header + populations as stored) as host bytes."""
+    n = lbm_save_bytes(ctx)
+    buf = ctypes.create_string_buffer(n)
+    _check(load().lbm_save(ctx, buf, n), "lbm_save")
+    return buf.raw
+
+
+def lbm_load(ctx, data: bytes):
+    buf = ctypes.create_string_buffer(bytes(data), len(data))
+    _check(load().lbm_load(ctx, buf, len(data)), "lbm_load")
+
+
+def lbm_set_debug(level: int):
+    _check(load().lbm_set_debug(int(level)), "lbm_set_debug")
+
+
+def lbm_debug_level() -> int:
+    k = ctypes.c_int32()
+    _check(load().lbm_debug_level(ctypes.byref(k)), "lbm_debug_level")
+    return k.value
 
 
 def lbm_check_finite(ctx) -> bool:

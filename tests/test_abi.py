@@ -73,6 +73,21 @@ def test_invalid_params_rejected(lib, field, value, msg):
     assert e.value.code == L.LBM_ERR_ARG and msg in str(e.value)
 
 
+@pytest.mark.parametrize("store,esize", [("LBM_STORE_F32", 4), ("LBM_STORE_F64", 8), ("LBM_STORE_BF16DEV", 2)])
+def test_plane_beyond_32bit_offsets_rejected(lib, store, esize):
+    """The sweeps address a plane with 32-bit byte offsets: a thin lattice under the 2^28-node cap whose
+    256-byte-padded rows make a plane of 4 GiB or more is refused, and one just below is accepted."""
+    p = L.lbm_params_default()
+    p.store = getattr(L, store)
+    p.nx = 9                                   # one 256-byte row per lattice row in every format
+    p.ny = (1 << 32) // 256                    # 2^24 rows: a 4 GiB plane, 1.5e8 nodes < 2^28
+    with pytest.raises(L.LbmError) as e:
+        L.lbm_workspace_bytes(p)
+    assert e.value.code == L.LBM_ERR_ARG and "4 GiB" in str(e.value)
+    p.ny = (1 << 32) // 256 - 1024             # 256 KiB below the bound
+    assert L.lbm_workspace_bytes(p) >= 2 * 9 * p.ny * 256
+
+
 def test_collision_model_parameters(lib):
     """BGK needs tau > 1/2; MRT (Sec. 4) takes tau >= 1/2 and rates in (0, 2]."""
     p = L.lbm_params_default()
@@ -176,3 +191,37 @@ def test_multi_step_shape_table(lib):
             L.lbm_two_step_steps(bad)
         with pytest.raises(L.LbmError):
             L.lbm_two_step_describe(bad)
+
+
+def test_debug_level_from_environment_and_setter(lib):
+    """LBM_DEBUG is read once from the environment; lbm_set_debug accepts 0..2 only."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r); from paper_2005_08674_amd import lbm; "
+            "print(lbm.lbm_debug_level())" % ROOT)
+    for env_val, want in (("2", 2), ("1", 1), ("0", 0), ("7", 2)):
+        out = subprocess.run([sys.executable, "-c", code], env={**os.environ, "LBM_DEBUG": env_val},
+                             capture_output=True, text=True, check=True).stdout.strip()
+        assert out == str(want), (env_val, out)
+    env = {k: v for k, v in os.environ.items() if k != "LBM_DEBUG"}
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, check=True)
+    assert out.stdout.strip() == "0"
+    old = L.lbm_debug_level()
+    try:
+        L.lbm_set_debug(1)
+        assert L.lbm_debug_level() == 1
+        for bad in (-1, 3):
+            with pytest.raises(L.LbmError) as e:
+                L.lbm_set_debug(bad)
+            assert e.value.code == L.LBM_ERR_ARG
+    finally:
+        L.lbm_set_debug(old)
+
+
+def test_checkpoint_calls_reject_null_context(lib):
+    import ctypes as C
+    n = C.c_size_t()
+    assert lib.lbm_save_bytes(None, C.byref(n)) == L.LBM_ERR_ARG
+    buf = C.create_string_buffer(16)
+    assert lib.lbm_save(None, buf, 16) == L.LBM_ERR_ARG
+    assert lib.lbm_load(None, buf, 16) == L.LBM_ERR_ARG

@@ -107,14 +107,17 @@ def test_forward_matches_oracle():
     X = _bf16_inputs(333, 2)
     y = tr.forward(torch.tensor(X, dtype=torch.bfloat16, device="cuda")).cpu().numpy()
     yo, _ = M.forward(p, X, bf16=True)
-    err = np.abs(y - yo).max() / np.abs(yo).max()
-    print(f"\n[mlp forward] max rel err {err:.2e}", flush=True)
-    assert err < 1e-2
+    # element by element, per output against that output's largest magnitude
+    err = (np.abs(y - yo) / np.abs(yo).max(axis=0)).max(axis=0)
+    print(f"\n[mlp forward] max error per output / its max: {err}", flush=True)
+    assert (err < 1e-3).all(), err
 
 
 def test_gradients_match_oracle():
-    """Per-tensor relative error of the GPU gradients (BF16 MFMA, FP32 accumulation) against the
-    fp64 oracle with the same BF16 rounding points."""
+    """GPU gradients (BF16 MFMA, FP32 accumulation) against the fp64 oracle with the same BF16
+    rounding points, element by element: every entry within 1e-3 of its tensor's largest entry.  FP32
+    accumulation over 1000 samples and tanh differences that flip a BF16 activation rounding stay
+    well below that; a wrong entry, a transposed block or a dropped term does not."""
     from paper_2005_08674_amd.closure import unpack_params
     p = _oracle_params(3)
     tr = _trainer(p)
@@ -127,8 +130,10 @@ def test_gradients_match_oracle():
     gu = unpack_params(g)
     for k in go:
         rel = np.linalg.norm(gu[k] - go[k]) / np.linalg.norm(go[k])
-        print(f"  grad {k}: rel err {rel:.2e}", flush=True)
-        assert rel < 2e-2, k
+        elem = np.abs(gu[k] - go[k]).max() / np.abs(go[k]).max()
+        print(f"  grad {k}: norm rel err {rel:.2e}, max element err / max {elem:.2e}", flush=True)
+        assert gu[k].shape == go[k].shape, k
+        assert elem < 1e-3, (k, elem)
 
 
 def test_adam_step_and_row_selection():

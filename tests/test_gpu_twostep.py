@@ -137,28 +137,66 @@ def test_closure_falls_back_to_single_steps():
     assert np.array_equal(a.populations().cpu().numpy(), b.populations().cpu().numpy())
 
 
-def test_full_size_4096_two_step_against_single_and_oracle():
-    """4096^2 FP32 (the HBM workload), tuned two-step shape: 10 steps bit-identical to the single-step
-    path and within the FP32 bound of the oracle."""
+def test_remainder_of_two_after_three_step_launches():
+    """After three-step launches a remainder of two steps runs as one two-step launch, any other
+    remainder as single steps: n = 1, 2, 4, 5 give the bits and the time of n single steps, and the
+    timing counts the launches that ran."""
     from paper_2005_08674_amd import lbm
+    from paper_2005_08674_amd.lattice import Lattice
+    three = [k for k in range(lbm.lbm_two_step_count()) if lbm.lbm_two_step_steps(k) == 3
+             and "64x12/768" in lbm.lbm_two_step_describe(k)][0]
+    f = W.gaussian_pulses(203, 77, [(1e-3, 6.0, 70.0, 40.0)], u0=(0.02, -0.01))
+    for store in ("f32", "f64", "f16"):
+        a = Lattice(203, 77, 0.57, f, store=store, beta=0.2, m0=(1.0002, 0.02, -0.01))
+        b = Lattice(203, 77, 0.57, f, store=store, beta=0.2, m0=(1.0002, 0.02, -0.01))
+        lbm.lbm_set_two_step(b.ctx, three)
+        for n, (multi, single) in zip((1, 2, 4, 5), ((0, 1), (1, 0), (1, 1), (2, 0))):
+            print(f"[remainder] {store} n={n}", flush=True)
+            lbm.lbm_enable_timing(b.ctx, True)
+            a.step(n)
+            b.step(n)
+            ms, nm = lbm.lbm_two_step_times(b.ctx)
+            bm, bn, em, en = lbm.lbm_kernel_times(b.ctx)
+            lbm.lbm_enable_timing(b.ctx, False)
+            assert (nm, bn) == (multi, single), (store, n, nm, bn)
+            assert a.t == b.t
+            assert np.array_equal(a.populations().cpu().numpy(), b.populations().cpu().numpy()), (store, n)
+        a.close()
+        b.close()
+
+
+def test_full_size_4096_tuned_launch_against_single_and_oracle():
+    """4096^2 FP32 (the HBM workload) in the launch the benchmark times (the autotuner's cached choice,
+    three steps per launch): 99 steps (33 launches) bit-identical to the single-step path and within
+    the FP32 bound of the oracle at t = 99."""
+    from paper_2005_08674_amd import autotune, lbm
     from paper_2005_08674_amd.lattice import Lattice
     w = W.pulses_4096()
     a = Lattice(w.nx, w.ny, w.tau, w.fields, store="f32")
-    best, times = lbm.lbm_autotune_two_step(a.ctx, 3)
-    print(f"\n[two-step 4096^2] shapes: " + ", ".join(f"{lbm.lbm_two_step_describe(i)}={t:.4f} ms"
-                                                  for i, t in enumerate(times)), flush=True)
-    a.step(10)
+    name = autotune.apply(a, "f32")
+    if name is None:
+        autotune.tune(a, "f32", reps=3, path=None)
+    shape = lbm.lbm_get_two_step(a.ctx)
+    print(f"\n[4096^2 tuned] {name} -> multi-step shape {lbm.lbm_two_step_describe(shape) if shape >= 0 else None}",
+          flush=True)
+    lbm.lbm_enable_timing(a.ctx, True)
+    a.step(99)
+    ms, launches = lbm.lbm_two_step_times(a.ctx)
+    lbm.lbm_enable_timing(a.ctx, False)
+    if shape >= 0:
+        assert launches == 99 // lbm.lbm_two_step_steps(shape)
     ga = a.populations().cpu().numpy()
     gm = a.moments_np()
     a.close()
     b = Lattice(w.nx, w.ny, w.tau, w.fields, store="f32")
-    b.step(10)
+    b.step(99)
     assert np.array_equal(ga, b.populations().cpu().numpy())
     b.close()
+    del ga
     o = oracle.Lattice(w.nx, w.ny, w.tau, *w.fields)
-    o.step(10)
+    o.step(99)
     om = o.moments()
     er = np.abs(gm[0] - om[0]).max()
     eu = max(np.abs(gm[1] - om[1]).max(), np.abs(gm[2] - om[2]).max()) / w.u_ref
-    print(f"[two-step 4096^2 fp32] e_rho={er:.3e} e_u={eu:.3e}", flush=True)
+    print(f"[4096^2 tuned fp32, t=99] e_rho={er:.3e} e_u={eu:.3e}", flush=True)
     assert er <= 1e-5 and eu <= 1e-5

@@ -341,3 +341,46 @@ def test_gamma_sweep_minimum_near_c_s_in_3d(q):
         r[g] = worst
     assert r[0.6] < r[0.45] and r[0.6] < r[0.75]
     assert r[0.6] < 1e-2 and r[0.0] > 10 * r[0.6]
+
+
+@pytest.mark.parametrize("q", QS)
+@pytest.mark.parametrize("gamma", [0.6, 1.0])
+def test_prediction_along_the_unit_normal_on_faces_edges_corners(q, gamma):
+    """eq. nes_2 in 3-D read as dm/dt + gamma dm/dn = 0 along the normalised sum n of the outward normals
+    of the k NSBC faces a node lies on (k = 1 faces, 2 edges, 3 corners; |sum| = sqrt(k)).  On a field
+    linear in x, y and z every one-sided difference is the exact directional derivative, so after one
+    step (beta = 0, the correction makes the node carry m_c) each boundary node holds
+    m_b - gamma grad(m).n, from the field's analytic gradient: the factor gamma/sqrt(k) on the sum of
+    the k one-sided differences.  gamma/k or gamma instead misses by more than 1e-6."""
+    nx, ny, nz = 7, 6, 5
+    a = np.array([3e-4, 0.01, -0.02, 0.005])
+    grad = np.array([[2e-5, -3e-5, 1e-5], [1e-3, 5e-4, -4e-4], [7e-4, -1.1e-3, 3e-4], [-6e-4, 2e-4, 9e-4]])
+    z, y, x = np.mgrid[0:nz, 0:ny, 0:nx].astype(float)
+    f = [a[k] + grad[k, 0] * x + grad[k, 1] * y + grad[k, 2] * z for k in range(4)]
+    L = oracle.Lattice3D(nx, ny, nz, 0.7, *f, gamma=gamma, beta=0.0, q=q)
+    L.step(1)
+    after = np.array(L.moments())
+    seen = {1: 0, 2: 0, 3: 0}
+    for zz in range(nz):
+        for yy in range(ny):
+            for xx in range(nx):
+                normals = []
+                for pos, hi, axis in ((xx, nx - 1, 0), (yy, ny - 1, 1), (zz, nz - 1, 2)):
+                    if pos in (0, hi):
+                        e = np.zeros(3)
+                        e[axis] = -1.0 if pos == 0 else 1.0
+                        normals.append(e)
+                if not normals:
+                    continue
+                k = len(normals)
+                seen[k] += 1
+                n = sum(normals) / math.sqrt(k)
+                for c in range(4):
+                    want = f[c][zz, yy, xx] - gamma * float(grad[c] @ n)
+                    assert abs(after[c, zz, yy, xx] - want) < 1e-15, (xx, yy, zz, c, after[c, zz, yy, xx], want)
+                if k > 1:
+                    wrong = f[1][zz, yy, xx] - gamma * float(grad[1] @ (sum(normals) / k))
+                    assert abs(after[1, zz, yy, xx] - wrong) > 1e-6
+    inner = (nx - 2, ny - 2, nz - 2)
+    assert seen == {1: 2 * (inner[0] * inner[1] + inner[1] * inner[2] + inner[0] * inner[2]),
+                    2: 4 * sum(inner), 3: 8}

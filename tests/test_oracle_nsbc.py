@@ -385,3 +385,56 @@ def test_paper_test_case_2_vortex_is_absorbed():
     assert np.isfinite(a.g).all()
     assert worst[0.6] < 0.5 * worst[0.0]
     assert va < 2e-3 * v0 and vb > 10 * va
+
+
+def _linear_fields(nx, ny):
+    """Moment fields linear in x and y, (drho, ux, uy) = a + b x + c y, with their gradients."""
+    a = np.array([3e-4, 0.01, -0.02])
+    b = np.array([2e-5, 1e-3, 7e-4])
+    c = np.array([-3e-5, 5e-4, -1.1e-3])
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    fields = tuple(a[k] + b[k] * x + c[k] * y for k in range(3))
+    return fields, b, c
+
+
+@pytest.mark.parametrize("corner_mode", [0, 1])
+@pytest.mark.parametrize("gamma", [0.6, 1.0])
+def test_corner_and_edge_prediction_on_a_linear_field(corner_mode, gamma):
+    """eq. nes_2 read as the upwind radiation condition dm/dt + gamma dm/dn = 0 along the outward unit
+    normal n.  On a field linear in x and y every one-sided difference is the exact directional
+    derivative, so after one step (beta = 0, exact correction: the node carries m_c) each NSBC node
+    holds m_b - gamma grad(m).n, with grad(m) the field's analytic gradient:
+      - edge nodes: n the edge's outward normal;
+      - corners, corner_mode 0: n the unit diagonal (n_x + n_y)/sqrt(2), i.e. the factor gamma/sqrt(2)
+        on the sum of the two one-sided differences;
+      - corners, corner_mode 1: the mean of the two edges' predictions, gamma/2 on that sum.
+    A swapped mode, a factor gamma or a flipped normal misses by at least 1e-6."""
+    nx, ny = 9, 8
+    fields, b, c = _linear_fields(nx, ny)
+    L = oracle.Lattice(nx, ny, 0.7, *fields, gamma=gamma, beta=0.0, corner_mode=corner_mode)
+    L.step(1)
+    after = L.moments()
+    nodes = [(x, y) for x in range(nx) for y in range(ny) if x in (0, nx - 1) or y in (0, ny - 1)]
+    worst = 0.0
+    for x, y in nodes:
+        normals = []
+        if x in (0, nx - 1):
+            normals.append(np.array([-1.0 if x == 0 else 1.0, 0.0]))
+        if y in (0, ny - 1):
+            normals.append(np.array([0.0, -1.0 if y == 0 else 1.0]))
+        if len(normals) == 1:
+            n = normals[0]
+        elif corner_mode == 0:
+            n = (normals[0] + normals[1]) / math.sqrt(2.0)
+        else:
+            n = (normals[0] + normals[1]) / 2.0
+        for k in range(3):
+            mb = fields[k][y, x]
+            want = mb - gamma * (b[k] * n[0] + c[k] * n[1])
+            err = abs(after[k][y, x] - want)
+            worst = max(worst, err)
+            assert err < 1e-15, (x, y, k, after[k][y, x], want)
+    # the two corner readings differ by far more than the tolerance
+    other = oracle.Lattice(nx, ny, 0.7, *fields, gamma=gamma, beta=0.0, corner_mode=1 - corner_mode)
+    other.step(1)
+    assert abs(other.moments()[1][0, 0] - after[1][0, 0]) > 1e-6
