@@ -228,6 +228,22 @@ int lbm_f16_exp(const lbm_ctx* ctx, int32_t* k);
 int lbm_energy(lbm_ctx* test, const lbm_ctx* ref, int32_t x_off, int32_t y_off,
                double ux_ref, double uy_ref, double* out_dev);
 
+/* lbm_energy without the context's workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same value, bit for bit,
+ * computed by the same kernels, whose 1024 fp64 block partials go to a
+ * static 8 KiB device array of the library instead of the workspace.  The
+ * call allocates nothing.  Each GPU holds one such array for the life of
+ * the process, looked up at lbm_init (or the first call on a device); every
+ * call on a GPU reuses it and each call overwrites all of it, so calls that
+ * overlap on one GPU (different streams, no ordering) race and must be
+ * serialized by the caller.  The contexts' device must be current
+ * (LBM_ERR_ARG otherwise); a reduction needing more partials than the array
+ * holds is refused with LBM_ERR_UNSUPPORTED.  Asynchronous on test's
+ * stream, as lbm_energy. */
+int lbm_energy_noalloc(lbm_ctx* test, const lbm_ctx* ref, int32_t x_off, int32_t y_off,
+                       double ux_ref, double uy_ref, double* out_dev);
+
 /* Bulk-kernel tile shapes.  lbm_tile_count gives the number of candidate
  * shapes; lbm_tile_describe writes a short text name of candidate `id` into
  * buf; lbm_set_tile selects one for this context (the default is chosen from

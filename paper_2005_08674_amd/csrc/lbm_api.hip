@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -249,7 +250,39 @@ int default_tile(const lbm_params*) { return 0; }
 
 }  // namespace
 
+// Scratch of lbm_energy_noalloc: the block partials of the fixed-grid fp64
+// energy reduction.  Each GPU holds its own copy for the life of the process;
+// host code reaches it only through the device address looked up per device.
+constexpr int kNoAllocPartials = 1024;  // 8 KiB
+static __device__ __align__(256) double scratch[kNoAllocPartials];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current GPU's `scratch`, looked up on the first call
+// on that device (the symbol's host-side name is not a device address).
+int scratch_of_current_device(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(LBM_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(LBM_ERR_UNSUPPORTED, "device %d beyond the %d supported", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(LBM_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return LBM_OK;
+}
+}  // namespace
+
 struct lbm_ctx {
+  int device = -1;  // GPU current at lbm_init
   lbm_params p;
   lbm::LatDesc L;
   Layout lay;
@@ -498,6 +531,16 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* workspace, size_t bytes, 
       return fail(LBM_ERR_HIP, "stream/event creation: %s", hipGetErrorString(e));
     }
   }
+  {
+    // set-up of the allocation-free entry point's scratch on this GPU
+    void* sp = nullptr;
+    int rc2 = hipGetDevice(&c->device) == hipSuccess ? scratch_of_current_device(&sp)
+                                                     : fail(LBM_ERR_HIP, "hipGetDevice failed");
+    if (rc2) {
+      lbm_destroy(c);
+      return rc2;
+    }
+  }
   c->p = *p;
   c->lay = lay;
   c->stream = static_cast<hipStream_t>(hip_stream);
@@ -670,6 +713,32 @@ int lbm_energy(lbm_ctx* test, const lbm_ctx* ref, int32_t x_off, int32_t y_off, 
   HIPCHK(lbm::launch_energy(test->L, test->parity, ref ? &ref->L : nullptr, ref ? ref->parity : 0, x_off, y_off,
                             ux_ref, uy_ref, part, out_dev, test->stream));
   return lbm::host::debug_sync(test->stream, "lbm_energy");
+}
+
+int lbm_energy_noalloc(lbm_ctx* test, const lbm_ctx* ref, int32_t x_off, int32_t y_off, double ux_ref,
+                       double uy_ref, double* out_dev) {
+  if (!test || !out_dev) return fail(LBM_ERR_ARG, "NULL argument");
+  if (ref) {
+    if (ref->p.rho0 != test->p.rho0) return fail(LBM_ERR_ARG, "test and reference rho0 differ");
+    if (x_off < 0 || y_off < 0 || x_off + test->p.nx > ref->p.nx || y_off + test->p.ny > ref->p.ny)
+      return fail(LBM_ERR_ARG, "window %dx%d at (%d, %d) does not fit in the %dx%d reference", test->p.nx,
+                  test->p.ny, x_off, y_off, ref->p.nx, ref->p.ny);
+  }
+  const int parts = lbm::energy_partials();
+  if (parts > kNoAllocPartials)
+    return fail(LBM_ERR_UNSUPPORTED, "the reduction needs %d partials; the static scratch holds %d", parts,
+                kNoAllocPartials);
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != test->device || (ref && ref->device != test->device))
+    return fail(LBM_ERR_ARG, "call with the contexts' device (%d) current, not %d", test->device, dev);
+  void* ptr = nullptr;
+  int rc = scratch_of_current_device(&ptr);
+  if (rc) return rc;
+  // every block writes its partial before the final sum reads it: nothing to clear
+  HIPCHK(lbm::launch_energy(test->L, test->parity, ref ? &ref->L : nullptr, ref ? ref->parity : 0, x_off, y_off,
+                            ux_ref, uy_ref, static_cast<double*>(ptr), out_dev, test->stream));
+  return lbm::host::debug_sync(test->stream, "lbm_energy_noalloc");
 }
 
 int lbm_tile_count(void) { return lbm::num_tiles(); }

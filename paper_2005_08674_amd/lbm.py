@@ -71,6 +71,7 @@ _SIGS = {
     "lbm_check_finite": [_P, _P],
     "lbm_f16_exp": [_P, _P],
     "lbm_energy": [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double, _P],
+    "lbm_energy_noalloc": [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double, _P],
     "lbm_tile_count": [],
     "lbm_tile_describe": [ctypes.c_int32, _P, ctypes.c_size_t],
     "lbm_set_tile": [_P, ctypes.c_int32],
@@ -292,6 +293,11 @@ def lbm_f16_exp(ctx) -> int:
 def lbm_energy(test_ctx, ref_ctx, x_off, y_off, ux_ref, uy_ref, out_ptr):
     _check(load().lbm_energy(test_ctx, ref_ctx, int(x_off), int(y_off), float(ux_ref), float(uy_ref), out_ptr),
            "lbm_energy")
+
+
+def lbm_energy_noalloc(test_ctx, ref_ctx, x_off, y_off, ux_ref, uy_ref, out_ptr):
+    _check(load().lbm_energy_noalloc(test_ctx, ref_ctx, int(x_off), int(y_off), float(ux_ref), float(uy_ref),
+                                     out_ptr), "lbm_energy_noalloc")
 
 
 def lbm_tile_count() -> int:
