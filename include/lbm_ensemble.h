@@ -59,12 +59,41 @@ int lbm_ens_set_velocity_edge(lbm_ens* e, int32_t member, double ux, double uy);
  * left over at the end run singly). */
 int lbm_ens_step(lbm_ens* e, int32_t n);
 
+/* Floats per logged site: the closure inputs (LBM_MLP_INPUTS = 96), m_c - m0
+ * and the strip amplitude A (4), and the residual target (3). */
+#define LBM_ENS_LOG_FLOATS 103
+
+/* Sites that lbm_ens_step_graph logs as closure training data (Sec. 5: the
+ * boundary-strip moments that eq. nes_2 extrapolates, and the moments the
+ * boundary node should carry one step later).  member_sites and twin_sites
+ * are device int32 arrays [n][4] of rows (member, x, y, edge) as for
+ * lbm_ens_closure_features: row i names a boundary node of a member and the
+ * same physical node in a larger "twin" member run alongside it (the
+ * reference whose moments are the target).  Borrowed until replaced; n = 0
+ * clears them.  n <= 2^24. */
+int lbm_ens_set_log_sites(lbm_ens* e, const int32_t* member_sites, const int32_t* twin_sites, int32_t n);
+
+/* Bytes lbm_ens_step_graph writes when logging every log_every steps over n
+ * steps: ceil(n / log_every) records of n_sites * LBM_ENS_LOG_FLOATS floats. */
+int lbm_ens_log_bytes(const lbm_ens* e, int32_t n, int32_t log_every, size_t* bytes);
+
 /* Advance every member n >= 1 steps with one launch of a HIP graph holding
- * the n steps' kernel launches (as lbm_ens_step would issue them).  The
- * graph is captured and instantiated on first use for this n (and step
- * parity) and cached until lbm_ens_destroy or a change of shape, fusion,
- * multi-step shape or closure set. */
-int lbm_ens_step_graph(lbm_ens* e, int32_t n);
+ * the n steps' kernel launches.  The graph is captured and instantiated on
+ * first use for these arguments (and step parity) and cached until
+ * lbm_ens_destroy or a change of shape, fusion, multi-step shape or closure
+ * set.
+ * log_buf = NULL: the launches lbm_ens_step would issue.
+ * log_buf != NULL (device, 16-byte aligned, >= lbm_ens_log_bytes bytes;
+ * log sites set): at every step s = j * log_every (j = 0, 1, ...) of the run
+ * the graph writes record j -- the closure inputs of the member sites at
+ * time s ([n_sites][96] floats, as lbm_ens_closure_features), then their
+ * m_c - m0 and A ([n_sites][4]), runs step s as one single step, and writes
+ * the residual target at time s + 1 from the twin sites ([n_sites][3], as
+ * lbm_ens_closure_moments with sub = that m_c) -- and advances the other
+ * steps as lbm_ens_step would.  The records are exactly what those calls
+ * return when issued between steps, so one graph launch generates a whole
+ * round of training data. */
+int lbm_ens_step_graph(lbm_ens* e, int32_t n, void* log_buf, size_t log_bytes, int32_t log_every);
 
 /* on = 1 (the default): each step is one launch whose first blocks run the
  * members' edge segments and the rest their bulk tiles; on = 0: separate

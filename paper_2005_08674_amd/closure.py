@@ -208,6 +208,30 @@ def kinetic_ratio(feat: torch.Tensor, rho0: float = 1.0) -> torch.Tensor:
     return su / sr
 
 
+def clean_time(m, u0, pad_x, pad_y, core=4.0):
+    """Last time at which the twin of member m (padded pad_x, pad_y per side) still gives clean targets
+    at the member's boundary nodes, i.e. before anything its own boundary did can have reached them.
+    - Pulse (acoustic) members: the sound from the disturbance, moving at c_s + |u0|, reaches the twin's
+      edge and comes back: 1.25 min(nx, ny) / (c_s + |u0|) (the twin edge lies N/2 beyond the member's).
+    - Vortex members: the swirl (significant within `core` core radii of the centre: 4 r_c leaves
+      1e-3 of its peak) is carried at u0 from (xc, yc); once it touches the twin's edge, the edge's
+      response needs min(pad_x, pad_y) / (c_s + |u0|) more steps to reach the member's boundary.
+      The acoustic transient of the vortex's initial state is left out of this bound.
+    The member's node (0, 0) is the twin's node (pad_x, pad_y)."""
+    speed = CS + math.hypot(*u0)
+    if m.kind != "vortex":
+        return 1.25 * min(m.nx, m.ny) / speed
+    p = m.params
+    rd = core * p["rc"]
+    t_touch = math.inf
+    for c, v, n, pad in ((p["xc"], u0[0], m.nx, pad_x), (p["yc"], u0[1], m.ny, pad_y)):
+        if v > 0:
+            t_touch = min(t_touch, max(0.0, (n - 1 + pad) - (c + rd)) / v)
+        elif v < 0:
+            t_touch = min(t_touch, max(0.0, (c - rd) - (-pad)) / -v)
+    return t_touch + min(pad_x, pad_y) / speed
+
+
 def generate_dataset(members, member_fields_fn, member_m0_fn, steps=2000, log_every=10, stride=4, store="f32",
                      gamma=0.6, net=None, amp_min=1e-8, amp_rel=0.0, kmin=0.0, device="cuda", log=None):
     """Run every member (NSBC edges, or the closure `net` with NSBC fallback) beside its twin in one
@@ -215,10 +239,12 @@ def generate_dataset(members, member_fields_fn, member_m0_fn, steps=2000, log_ev
 
     Inputs come from the member's own boundary nodes, so they carry what the boundary condition in
     use did at earlier steps; targets are the twin's moments at the same physical nodes one step
-    later, minus the member's NSBC prediction m_c, divided by the strip amplitude A.  Sites whose A
-    is at most `amp_min` (no disturbance yet, only rounding noise) or below `amp_rel` times the
-    largest A logged on the same member are left out, and so are sites outside the regime gate
-    (kinetic_ratio <= kmin).  Returns (feat [M, 96], resid [M, 3]) float32 device tensors."""
+    later, minus the member's NSBC prediction m_c, divided by the strip amplitude A.  The whole run is
+    one graph launch that logs every site every `log_every` steps (lbm_ens_step_graph); a record is
+    kept for a member only while the twin is clean there (clean_time).  Sites whose A is at most
+    `amp_min` (no disturbance yet, only rounding noise) or below `amp_rel` times the largest A logged
+    on the same member are left out, and so are sites outside the regime gate (kinetic_ratio <=
+    kmin).  Returns (feat [M, 96], resid [M, 3]) float32 device tensors."""
     from .ensemble import Ensemble, member_params
     count = len(members)
     lat, fields, msites, tsites, t_clean, m0s = [], [], [], [], [], []
@@ -230,8 +256,7 @@ def generate_dataset(members, member_fields_fn, member_m0_fn, steps=2000, log_ev
         s = edge_sites(m.nx, m.ny, stride)
         msites.append(np.concatenate([np.full((len(s), 1), k, np.int32), s], 1))
         m0s.append(member_m0_fn(m))
-        speed = CS + math.hypot(*u0)
-        t_clean.append(math.inf if m.kind == "vortex" else 1.25 * min(m.nx, m.ny) / speed)
+        t_clean.append(clean_time(m, u0, m.nx // 2, m.ny // 2))
     for k, m in enumerate(members):
         px, py = m.nx // 2, m.ny // 2
         u0 = tuple(member_m0_fn(m)[1:])
@@ -250,34 +275,19 @@ def generate_dataset(members, member_fields_fn, member_m0_fn, steps=2000, log_ev
     if net is not None:
         for k in range(count):
             L.lbm_ens_set_closure(ens.ens, k, net.data_ptr(), 1)
-    feats, resids, amps, mids = [], [], [], []
-    t = 0
-    while t < steps:
-        keep = [k for k in range(count) if t + 1 <= t_clean[k]]
-        adv = 0
-        if keep:
-            ms = torch.from_numpy(np.ascontiguousarray(np.concatenate([msites[k] for k in keep]))).to(device)
-            ts = torch.from_numpy(np.ascontiguousarray(np.concatenate([tsites[k] for k in keep]))).to(device)
-            n = ms.shape[0]
-            f = torch.empty((n, IN), dtype=torch.float32, device=device)
-            mc = torch.empty((n, OUT + 1), dtype=torch.float32, device=device)
-            L.lbm_ens_closure_features(ens.ens, ms.data_ptr(), n, f.data_ptr(), mc.data_ptr())
-            ens.step(1)
-            r = torch.empty((n, OUT), dtype=torch.float32, device=device)
-            L.lbm_ens_closure_moments(ens.ens, ts.data_ptr(), n, mc.data_ptr(), r.data_ptr())
-            keep_rows = mc[:, OUT] > amp_min
-            feats.append(f[keep_rows])
-            resids.append(r[keep_rows])
-            amps.append(mc[keep_rows, OUT])
-            mids.append(ms[keep_rows, 0].long())
-            adv = 1
-        rest = min(log_every - adv, steps - t - adv)
-        if rest > 0:
-            ens.step_graph(rest)
-        t += adv + max(rest, 0)
-        if log and len(feats) % 50 == 1:
-            log(f"t={t} samples={sum(x.shape[0] for x in feats)}")
+    ms = torch.from_numpy(np.ascontiguousarray(np.concatenate(msites))).to(device)
+    ts = torch.from_numpy(np.ascontiguousarray(np.concatenate(tsites))).to(device)
+    ens.set_log_sites(ms, ts)
+    f, mc, r = ens.step_graph_logged(steps, log_every)
     ens.close()
+    # record j holds step t_j = j * log_every; keep a member's rows while t_j + 1 <= its clean time
+    tc = torch.tensor(t_clean, dtype=torch.float64, device=device)[ms[:, 0].long()]
+    tj = torch.arange(f.shape[0], dtype=torch.float64, device=device)[:, None] * log_every
+    keep = (tj + 1 <= tc[None, :]) & (mc[:, :, OUT] > amp_min)
+    feats, resids, amps = [f[keep]], [r[keep]], [mc[:, :, OUT][keep]]
+    mids = [ms[:, 0].long()[None, :].expand(f.shape[0], -1)[keep]]
+    if log:
+        log(f"{f.shape[0]} records of {f.shape[1]} sites, {int(keep.sum())} kept")
     feat = torch.cat(feats)
     resid = torch.cat(resids)
     ok = torch.isfinite(feat).all(1) & torch.isfinite(resid).all(1)

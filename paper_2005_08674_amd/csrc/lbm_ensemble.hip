@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -284,7 +285,12 @@ struct lbm_ens {
   int64_t t = 0;
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;  // private stream used for graph capture
-  std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+  // captured graphs by (n, parity, log_every, log buffer, log sites)
+  std::map<std::tuple<int, int, int, uintptr_t, uintptr_t, uintptr_t, int>, hipGraphExec_t> graphs;
+  // training-data sites logged by lbm_ens_step_graph (device arrays, borrowed)
+  const int32_t* log_ms = nullptr;
+  const int32_t* log_ts = nullptr;
+  int32_t log_n = 0;
   bool any_closure = false;
   bool fused = true;  // one launch per step when no member runs the closure
   int two = -1;       // two-step shape, or -1 (single steps)
@@ -583,23 +589,112 @@ int lbm_ens_step(lbm_ens* e, int32_t n) {
   return LBM_OK;
 }
 
-int lbm_ens_step_graph(lbm_ens* e, int32_t n) {
+static_assert(LBM_ENS_LOG_FLOATS == lbm::mlp::IN + (lbm::mlp::OUT + 1) + lbm::mlp::OUT, "log record layout");
+
+int lbm_ens_set_log_sites(lbm_ens* e, const int32_t* member_sites, const int32_t* twin_sites, int32_t n) {
+  if (!e) return fail(LBM_ERR_ARG, "ensemble is NULL");
+  if (n < 0 || (n > 0 && (!member_sites || !twin_sites))) return fail(LBM_ERR_ARG, "bad log sites (n = %d)", n);
+  if (n > (1 << 24)) return fail(LBM_ERR_ARG, "%d log sites exceed 2^24", n);
+  e->log_ms = n ? member_sites : nullptr;
+  e->log_ts = n ? twin_sites : nullptr;
+  e->log_n = n;
+  return LBM_OK;
+}
+
+int lbm_ens_log_bytes(const lbm_ens* e, int32_t n, int32_t log_every, size_t* bytes) {
+  if (!e || !bytes) return fail(LBM_ERR_ARG, "NULL argument");
+  if (n < 1 || log_every < 1) return fail(LBM_ERR_ARG, "n = %d and log_every = %d must be >= 1", n, log_every);
+  const size_t logs = (size_t)((n + log_every - 1) / log_every);
+  *bytes = logs * (size_t)e->log_n * LBM_ENS_LOG_FLOATS * sizeof(float);
+  return LBM_OK;
+}
+
+int lbm_ens_step_graph(lbm_ens* e, int32_t n, void* log_buf, size_t log_bytes, int32_t log_every) {
   if (!e) return fail(LBM_ERR_ARG, "ensemble is NULL");
   if (n < 1 || n > 100000) return fail(LBM_ERR_ARG, "n = %d outside [1, 100000]", n);
+  const bool logging = log_buf != nullptr;
+  if (logging) {
+    if (log_every < 1) return fail(LBM_ERR_ARG, "log_every = %d must be >= 1", log_every);
+    if (e->log_n <= 0) return fail(LBM_ERR_STATE, "no log sites set (lbm_ens_set_log_sites)");
+    size_t need = 0;
+    int rc = lbm_ens_log_bytes(e, n, log_every, &need);
+    if (rc) return rc;
+    if (log_bytes < need) return fail(LBM_ERR_ARG, "log buffer of %zu bytes < %zu required", log_bytes, need);
+    if ((uintptr_t)log_buf & 15) return fail(LBM_ERR_ARG, "log buffer not 16-byte aligned");
+  } else {
+    log_every = 0;
+  }
   const bool two = use_two(e);
   const int k = two ? ens_multi_steps(e->two) : 1;
-  const int launches = n / k + n % k;
-  const std::pair<int, int> key(n, e->parity);
+  // launches of s steps from parity p: multi-step launches while they fit, then single steps
+  auto run = [&](int steps, int& p, hipStream_t st) -> int {
+    for (int32_t s = 0; s < steps;) {
+      const bool multi = k > 1 && steps - s >= k;
+      int rc = multi ? ens_launch_two(e, p, st) : ens_launch_step(e, p, st);
+      if (rc) return rc;
+      p ^= 1;
+      s += multi ? k : 1;
+    }
+    return LBM_OK;
+  };
+  const auto key = std::make_tuple(n, e->parity, log_every, (uintptr_t)log_buf, (uintptr_t)e->log_ms,
+                                   (uintptr_t)e->log_ts, logging ? e->log_n : 0);
   auto it = e->graphs.find(key);
+  int end_parity = e->parity;
+  {
+    // parity after the n steps (the same launches as the capture below)
+    int p = e->parity;
+    if (!logging) {
+      for (int32_t s = 0; s < n;) {
+        const bool multi = k > 1 && n - s >= k;
+        p ^= 1;
+        s += multi ? k : 1;
+      }
+    } else {
+      for (int32_t s = 0; s < n; s += log_every) {
+        p ^= 1;  // the logged step
+        const int rest = std::min(log_every - 1, n - s - 1);
+        for (int32_t q = 0; q < rest;) {
+          const bool multi = k > 1 && rest - q >= k;
+          p ^= 1;
+          q += multi ? k : 1;
+        }
+      }
+    }
+    end_parity = p;
+  }
   if (it == e->graphs.end()) {
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(e->cap, hipStreamCaptureModeThreadLocal));
     int rc = LBM_OK;
     int p = e->parity;
-    for (int32_t s = 0; s < n && rc == LBM_OK; p ^= 1) {
-      const bool multi = k > 1 && n - s >= k;
-      rc = multi ? ens_launch_two(e, p, e->cap) : ens_launch_step(e, p, e->cap);
-      s += multi ? k : 1;
+    if (!logging) {
+      rc = run(n, p, e->cap);
+    } else {
+      // record j (step s = j * log_every): inputs at time s at the member sites, one step, then the
+      // twin's moments at s + 1 at the twin sites minus m_c (the residual target), then the rest
+      const size_t rec = (size_t)e->log_n * LBM_ENS_LOG_FLOATS;
+      float* base = static_cast<float*>(log_buf);
+      for (int32_t s = 0, j = 0; s < n && rc == LBM_OK; s += log_every, ++j) {
+        float* feat = base + (size_t)j * rec;
+        float* mc = feat + (size_t)e->log_n * lbm::mlp::IN;
+        float* res = mc + (size_t)e->log_n * (lbm::mlp::OUT + 1);
+        hipError_t he = lbm::host::closure_features(nullptr, e->d_descs, e->count, p, e->log_ms, e->log_n, feat, mc,
+                                                    e->cap);
+        if (he != hipSuccess) {
+          rc = fail(LBM_ERR_HIP, "log features: %s", hipGetErrorString(he));
+          break;
+        }
+        rc = ens_launch_step(e, p, e->cap);
+        if (rc) break;
+        p ^= 1;
+        he = lbm::host::closure_moments(nullptr, e->d_descs, e->count, p, e->log_ts, e->log_n, mc, res, e->cap);
+        if (he != hipSuccess) {
+          rc = fail(LBM_ERR_HIP, "log moments: %s", hipGetErrorString(he));
+          break;
+        }
+        rc = run(std::min(log_every - 1, n - s - 1), p, e->cap);
+      }
     }
     hipError_t he = hipStreamEndCapture(e->cap, &g);
     if (rc) {
@@ -607,6 +702,10 @@ int lbm_ens_step_graph(lbm_ens* e, int32_t n) {
       return rc;
     }
     if (he != hipSuccess) return fail(LBM_ERR_HIP, "graph capture: %s", hipGetErrorString(he));
+    if (p != end_parity) {
+      (void)hipGraphDestroy(g);
+      return fail(LBM_ERR_STATE, "internal: captured parity %d != %d", p, end_parity);
+    }
     hipGraphExec_t x = nullptr;
     he = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
@@ -614,9 +713,9 @@ int lbm_ens_step_graph(lbm_ens* e, int32_t n) {
     it = e->graphs.emplace(key, x).first;
   }
   HIPCHK(hipGraphLaunch(it->second, e->stream));
-  e->parity ^= (launches & 1);
+  e->parity = end_parity;
   e->t += n;
-  return LBM_OK;
+  return lbm::host::debug_sync(e->stream, "lbm_ens_step_graph");
 }
 
 int lbm_ens_moments(lbm_ens* e, int32_t member, void* r, void* u, void* v, int out_f64, int deviation) {

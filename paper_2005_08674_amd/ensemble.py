@@ -53,6 +53,28 @@ class Ensemble:
     def step_graph(self, n):
         L.lbm_ens_step_graph(self.ens, n)
 
+    def set_log_sites(self, member_sites, twin_sites):
+        """Closure training-data sites: int32 device tensors [n][4] of (member, x, y, edge) (kept alive
+        here while the ensemble uses them)."""
+        self._log_sites = (member_sites.contiguous(), twin_sites.contiguous())
+        L.lbm_ens_set_log_sites(self.ens, self._log_sites[0].data_ptr(), self._log_sites[1].data_ptr(),
+                                self._log_sites[0].shape[0])
+
+    def step_graph_logged(self, n, log_every):
+        """n steps in one graph launch, logging a record every log_every steps.  Returns float32 device
+        views (feat [records][sites][96], mc [records][sites][4], resid [records][sites][3]) of the
+        log buffer: record j holds the inputs at step j * log_every and the targets one step later."""
+        nbytes = L.lbm_ens_log_bytes(self.ens, n, log_every)
+        nsites = self._log_sites[0].shape[0]
+        recs = (n + log_every - 1) // log_every
+        buf = torch.empty((recs, nsites * L.LBM_ENS_LOG_FLOATS), dtype=torch.float32, device=self.device)
+        assert buf.numel() * 4 == nbytes
+        L.lbm_ens_step_graph(self.ens, n, buf.data_ptr(), nbytes, log_every)
+        feat = buf[:, :nsites * 96].view(recs, nsites, 96)
+        mc = buf[:, nsites * 96:nsites * 100].view(recs, nsites, 4)
+        resid = buf[:, nsites * 100:].view(recs, nsites, 3)
+        return feat, mc, resid
+
     @property
     def t(self):
         return L.lbm_ens_time(self.ens)

@@ -102,7 +102,9 @@ _SIGS = {
                              ctypes.c_double],
     "lbm_ens_set_velocity_edge": [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_double],
     "lbm_ens_step": [_P, ctypes.c_int32],
-    "lbm_ens_step_graph": [_P, ctypes.c_int32],
+    "lbm_ens_step_graph": [_P, ctypes.c_int32, _P, ctypes.c_size_t, ctypes.c_int32],
+    "lbm_ens_set_log_sites": [_P, _P, _P, ctypes.c_int32],
+    "lbm_ens_log_bytes": [_P, ctypes.c_int32, ctypes.c_int32, _P],
     "lbm_ens_set_fused": [_P, ctypes.c_int],
     "lbm_ens_moments": [_P, ctypes.c_int32, _P, _P, _P, ctypes.c_int, ctypes.c_int],
     "lbm_ens_get_populations": [_P, ctypes.c_int32, _P],
@@ -428,8 +430,21 @@ def lbm_ens_step(ens, n: int):
     _check(load().lbm_ens_step(ens, int(n)), "lbm_ens_step")
 
 
-def lbm_ens_step_graph(ens, n: int):
-    _check(load().lbm_ens_step_graph(ens, int(n)), "lbm_ens_step_graph")
+LBM_ENS_LOG_FLOATS = 103
+
+
+def lbm_ens_step_graph(ens, n: int, log_ptr=None, log_bytes: int = 0, log_every: int = 0):
+    _check(load().lbm_ens_step_graph(ens, int(n), log_ptr, int(log_bytes), int(log_every)), "lbm_ens_step_graph")
+
+
+def lbm_ens_set_log_sites(ens, member_sites_ptr, twin_sites_ptr, n: int):
+    _check(load().lbm_ens_set_log_sites(ens, member_sites_ptr, twin_sites_ptr, int(n)), "lbm_ens_set_log_sites")
+
+
+def lbm_ens_log_bytes(ens, n: int, log_every: int) -> int:
+    b = ctypes.c_size_t()
+    _check(load().lbm_ens_log_bytes(ens, int(n), int(log_every), ctypes.byref(b)), "lbm_ens_log_bytes")
+    return b.value
 
 
 def lbm_ens_set_fused(ens, on: bool):

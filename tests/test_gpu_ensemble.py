@@ -324,3 +324,86 @@ def test_three_step_ensemble_bitwise_equal_to_single_steps(store):
         for m in range(len(members)):
             assert np.array_equal(e.populations(m), want21[m]), (store, shape, m)
         e.close()
+
+
+def _member_and_twin_ensemble(members, steps_shape=True):
+    """Members of `members` plus one twin each (padded N/2 per side, same analytic field), far field set
+    as the closure data generation does; returns (Ensemble, member sites, twin sites)."""
+    from paper_2005_08674_amd import lbm
+    from paper_2005_08674_amd.closure import edge_sites, twin_fields
+    from paper_2005_08674_amd.ensemble import Ensemble, member_params
+    lat, fields, ms, ts = [], [], [], []
+    for k, m in enumerate(members):
+        u0 = W.member_m0(m)[1:]
+        lat.append(member_params(m.nx, m.ny, m.tau, ubase=u0 if m.kind == "vortex" else (0.0, 0.0)))
+        fields.append(W.member_fields(m))
+        s = edge_sites(m.nx, m.ny, 3)
+        ms.append(np.concatenate([np.full((len(s), 1), k, np.int32), s], 1))
+    for k, m in enumerate(members):
+        u0 = W.member_m0(m)[1:]
+        px, py = m.nx // 2, m.ny // 2
+        lat.append(member_params(m.nx + 2 * px, m.ny + 2 * py, m.tau,
+                                 ubase=u0 if m.kind == "vortex" else (0.0, 0.0)))
+        fields.append(twin_fields(W.member_fields, m, px, py))
+        t = ms[k].copy()
+        t[:, 0] = len(members) + k
+        t[:, 1] += px
+        t[:, 2] += py
+        ts.append(t)
+    ens = Ensemble(lat, fields)
+    for k, m in enumerate(members):
+        ens.set_farfield(k, 0.0, *W.member_m0(m))
+        ens.set_farfield(len(members) + k, 0.0, *W.member_m0(m))
+    if steps_shape:
+        three = [i for i in range(lbm.lbm_two_step_count()) if lbm.lbm_two_step_describe(i).startswith("3step:64x12/768")]
+        ens.set_two_step(three[0])
+    cat = lambda a: torch.from_numpy(np.ascontiguousarray(np.concatenate(a))).to("cuda")
+    return ens, cat(ms), cat(ts)
+
+
+def test_graph_logging_equals_eager_sampling():
+    """lbm_ens_step_graph with a log buffer writes, every log_every steps, exactly what the sampling
+    calls (lbm_ens_closure_features / lbm_ens_closure_moments) return between eager steps: the closure
+    inputs at time t, m_c and A, and the twin's residual target at t + 1.  The members end in the same
+    state, and a replay of the cached graph from the new state matches eager sampling again."""
+    from paper_2005_08674_amd import lbm
+    members = W.ensemble_members(6, seed=11, lo=64, hi=120)
+    a, ms, ts = _member_and_twin_ensemble(members)
+    b, _, _ = _member_and_twin_ensemble(members)
+    a.set_log_sites(ms, ts)
+    n_sites = ms.shape[0]
+    for rep in range(2):
+        steps, every = 47, 10
+        f, mc, r = a.step_graph_logged(steps, every)
+        torch.cuda.synchronize()
+        assert f.shape == (5, n_sites, 96) and mc.shape == (5, n_sites, 4) and r.shape == (5, n_sites, 3)
+        for j in range(5):
+            fe = torch.empty((n_sites, 96), dtype=torch.float32, device="cuda")
+            me = torch.empty((n_sites, 4), dtype=torch.float32, device="cuda")
+            re = torch.empty((n_sites, 3), dtype=torch.float32, device="cuda")
+            lbm.lbm_ens_closure_features(b.ens, ms.data_ptr(), n_sites, fe.data_ptr(), me.data_ptr())
+            b.step(1)
+            lbm.lbm_ens_closure_moments(b.ens, ts.data_ptr(), n_sites, me.data_ptr(), re.data_ptr())
+            b.step(min(every - 1, steps - every * j - 1))
+            torch.cuda.synchronize()
+            print(f"[graph log] replay {rep} record {j}", flush=True)
+            # sites with no disturbance yet (A = 0) give NaN residuals on both sides: compare the bits
+            assert torch.isfinite(fe).all() and torch.isfinite(re).any()
+            bits = lambda x: x.contiguous().view(torch.int32)
+            assert torch.equal(bits(f[j]), bits(fe)) and torch.equal(bits(mc[j]), bits(me)), (rep, j)
+            assert torch.equal(bits(r[j]), bits(re)), (rep, j)
+        assert a.t == b.t == steps * (rep + 1)
+        for k in range(2 * len(members)):
+            assert np.array_equal(a.populations(k), b.populations(k)), (rep, k)
+    # refusals: a buffer that is too small, and logging without sites
+    nbytes = lbm.lbm_ens_log_bytes(a.ens, 47, 10)
+    assert nbytes == 5 * n_sites * 103 * 4
+    small = torch.empty(nbytes // 4 - 1, dtype=torch.float32, device="cuda")
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_ens_step_graph(a.ens, 47, small.data_ptr(), small.numel() * 4, 10)
+    lbm.lbm_ens_set_log_sites(a.ens, None, None, 0)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_ens_step_graph(a.ens, 47, small.data_ptr(), nbytes, 10)
+    assert e.value.code == lbm.LBM_ERR_STATE
+    a.close()
+    b.close()

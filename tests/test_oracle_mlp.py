@@ -3,6 +3,8 @@ oracle (oracle/closure.py) against independent references: central finite
 differences, PyTorch fp64 autograd and torch.optim.Adam (library routines
 implementing the published algorithms), torch's bfloat16 rounding, and
 invariants of the input definition."""
+import math
+
 import numpy as np
 import pytest
 
@@ -185,3 +187,26 @@ def test_closure_mc_special_cases():
     f1, mc1, _ = OC.site_features(lat, 5, ny - 1, 3, gamma=0.6, beta=1.0, m0=(1.001, 0.03, -0.02))
     assert np.allclose(mc1, [1e-3, -0.02, -0.03], atol=1e-16)
     assert np.abs(f1[82:85]).max() < 1e-12
+
+
+def test_twin_clean_time():
+    """The closure's training targets come from a twin padded N/2 per side; its clean time follows the
+    fastest signal from the disturbance to the twin's edge and back to the member's boundary: for a
+    pulse 1.25 N/(c_s + |u0|); for a vortex the time its core (4 r_c) needs at u0 to touch the twin's
+    edge, plus min(pad)/(c_s + |u0|), the slowest of the two axes never the binding one."""
+    from paper_2005_08674_amd.closure import clean_time
+    from paper_2005_08674_amd.workloads import EnsembleMember
+    cs = 1 / math.sqrt(3)
+    p = EnsembleMember(100, 80, 0.6, "pulse", {"a": 1e-3, "w": 5.0, "xc": 50.0, "yc": 40.0})
+    assert clean_time(p, (0.0, 0.0), 50, 40) == pytest.approx(1.25 * 80 / cs)
+    v = EnsembleMember(100, 80, 0.6, "vortex", {"u0": (0.1, 0.0), "uv": 0.02, "rc": 5.0, "xc": 40.0, "yc": 40.0})
+    t = clean_time(v, (0.1, 0.0), 50, 40)
+    assert t == pytest.approx(((100 - 1 + 50) - (40 + 20)) / 0.1 + 40 / (cs + 0.1))
+    # moving up-left: the x axis reaches its edge first here
+    v2 = EnsembleMember(100, 80, 0.6, "vortex", {"u0": (-0.08, 0.06), "uv": 0.02, "rc": 4.0, "xc": 30.0,
+                                                 "yc": 40.0})
+    tx = (30 - 16 + 50) / 0.08
+    ty = ((80 - 1 + 40) - (40 + 16)) / 0.06
+    assert clean_time(v2, (-0.08, 0.06), 50, 40) == pytest.approx(min(tx, ty) + 40 / (cs + 0.1))
+    # a vortex always leaves its twin, so its clean time is finite, unlike the old unbounded gate
+    assert math.isfinite(t) and t < 2000
