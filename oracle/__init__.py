@@ -19,7 +19,9 @@ import subprocess
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-BUILD_DIR = os.path.join(HERE, "_build")
+# ORACLE_BUILD_DIR selects another build of the same sources (the sanitizer build of
+# oracle/sanitize.py); the default is the plain build below
+BUILD_DIR = os.environ.get("ORACLE_BUILD_DIR") or os.path.join(HERE, "_build")
 SRC = os.path.join(HERE, "lbm_oracle.c")
 SRC3 = os.path.join(HERE, "lbm_oracle3d.c")
 LIBS = {"double": os.path.join(BUILD_DIR, "liblbm_oracle.so"),
@@ -32,13 +34,16 @@ BC_NSBC = 1
 BC_VELOCITY = 2
 
 
-def build(verbose: bool = False) -> None:
-    """Compile both precisions of the oracle with gcc (always recompiles)."""
-    os.makedirs(BUILD_DIR, exist_ok=True)
+def build(verbose: bool = False, extra_flags=(), build_dir: str | None = None) -> None:
+    """Compile both precisions of the oracle with gcc (always recompiles), into `build_dir`
+    (default BUILD_DIR) with `extra_flags` added."""
+    bdir = build_dir or BUILD_DIR
+    os.makedirs(bdir, exist_ok=True)
     for kind, out in LIBS.items():
+        out = os.path.join(bdir, os.path.basename(out))
         src = SRC3 if kind.startswith("3d") else SRC
         cmd = ["gcc", "-O2", "-std=c11", "-fno-fast-math", "-ffp-contract=off",
-               "-fopenmp", "-shared", "-fPIC", src, "-lm", "-o", out + ".tmp"]
+               "-fopenmp", "-shared", "-fPIC", *extra_flags, src, "-lm", "-o", out + ".tmp"]
         if kind.endswith("longdouble"):
             cmd.insert(1, "-DORC_LONG_DOUBLE")
         if verbose:

@@ -132,7 +132,7 @@ def test_committed_closure_closed_loop_against_nsbc():
     """The committed closure network (trained on the 256-member ensemble, run with its saved trust
     bound, gain and regime gate) in closed loop against plain NSBC, each test lattice against its 4x
     reference.  Sound waves stay below the gate, so the two acoustic cases reflect as with NSBC (to
-    1e-3); on the convected vortex the closure reflects at most 0.8x as much as NSBC."""
+    1e-3); on the convected vortex the closure reflects at most half as much as NSBC (0.24x measured)."""
     import os
     from paper_2005_08674_amd.closure import Trainer
     from paper_2005_08674_amd.reflection import ReflectionRun
@@ -168,4 +168,4 @@ def test_committed_closure_closed_loop_against_nsbc():
     for name in ("pulse128", "pulse_on_flow"):
         # equal up to the few rounding-noise nodes (A ~ 1e-12) whose tiny disturbance the gate may pass
         assert out[name][1] <= out[name][0] * (1.0 + 1e-3), name
-    assert out["vortex512x256"][1] <= 0.8 * out["vortex512x256"][0]
+    assert out["vortex512x256"][1] <= 0.5 * out["vortex512x256"][0]
