@@ -354,87 +354,172 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
     return;
   }
 
-  // ---- level t + 1 from HBM (sources clamped into the lattice; a clamped
-  // source is only ever an unknown population's, which NSBC replaces)
-  for (int k = tid; k < (TY + 4) * T3_W1; k += NT) {
-    const int r = k / T3_W1, cx = k - r * T3_W1;
-    const int x = x0 - 2 + cx, y = y0 - 2 + r;
-    if (x < 0 || x >= nx || y < 0 || y >= ny) continue;
-    const uint32_t unknown = tl_unknown(x, y, nx, ny);
-    const int sxs[3] = {min(x + 1, nx - 1), x, max(x - 1, 0)};
-    const uint32_t srow[3] = {(uint32_t)(min(y + 1, ny - 1) * pitch), (uint32_t)(y * pitch),
-                              (uint32_t)(max(y - 1, 0) * pitch)};
-    R g[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      const T* __restrict__ Ai = A + i * plane;
-      const R v = C::dec(Ai[srow[1 + kCy[i]] + (uint32_t)sxs[1 + kCx[i]]], Ld.ds[i]);
-      g[i] = (unknown >> i) & 1u ? R(0) : v;
+  // ---- edge tiles.  Each level first updates the nodes of its region that
+  // are inside the lattice and not on its edge (every pull source of such a
+  // node lies inside the lattice: no clamps, no NSBC), then the region's
+  // lattice-edge nodes, gathered into consecutive lanes so that NSBC runs on
+  // full wavefronts instead of one lane per row.  The per-node arithmetic is
+  // the one above, so the results do not change.
+  const Base<R>& b = base;
+  // region of a level: lattice rows ry0 .. ry0 + rh - 1, columns rx0 .. rx0 + rw - 1
+  auto edge_count = [&](int rx0, int ry0, int rw, int rh, int& xl, int& xh, int& yl, int& yh, int& ncol, int& nrow) {
+    xl = max(rx0, 0);
+    xh = min(rx0 + rw - 1, nx - 1);
+    yl = max(ry0, 0);
+    yh = min(ry0 + rh - 1, ny - 1);
+    const int left = xl == 0, right = xh == nx - 1;
+    ncol = (left + right) * (yh - yl + 1);                    // nodes of the x = 0 and x = nx - 1 columns
+    const int cx0 = xl + left, cx1 = xh - right;              // row nodes not already in those columns
+    nrow = ((yl == 0) + (yh == ny - 1)) * max(0, cx1 - cx0 + 1);
+  };
+  // lattice-edge node number e of a region (left column, right column, then bottom row, top row)
+  auto edge_node = [&](int e, int xl, int xh, int yl, int yh, int ncol, int& x, int& y) {
+    const int hcol = yh - yl + 1;
+    const int left = xl == 0, right = xh == nx - 1;
+    if (e < ncol) {
+      const bool first = left && e < hcol;
+      x = first ? 0 : nx - 1;
+      y = yl + (first ? e : e - left * hcol);
+      return;
     }
-    if (unknown) {
-      auto mom = [&](int xx, int yy, R m[3]) { tl_moments_global<S>(Ld, A, xx, yy, base, m); };
-      tl_nsbc<R>(Ld, g, unknown, x, y, rho0, base, mom);
-    }
-    collide<R, CM>(Ld, g, rho0, base, omega);
+    e -= ncol;
+    const int cx0 = xl + left, cw = (xh - right) - cx0 + 1;
+    const bool bottom = yl == 0 && e < cw;
+    y = bottom ? 0 : ny - 1;
+    x = cx0 + (bottom ? e : e - (yl == 0) * cw);
+  };
+  auto interior_node = [&](int x, int y) { return x >= 1 && x <= nx - 2 && y >= 1 && y <= ny - 2; };
+
+  // ---- level t + 1 from HBM
+  {
+    for (int k = tid; k < (TY + 4) * T3_W1; k += NT) {
+      const int r = k / T3_W1, cx = k - r * T3_W1;
+      const int x = x0 - 2 + cx, y = y0 - 2 + r;
+      if (!interior_node(x, y)) continue;
+      const uint32_t idx = (uint32_t)(y * pitch + x);
+      const uint32_t ro[3] = {(idx + (uint32_t)pitch) * (uint32_t)sizeof(T), idx * (uint32_t)sizeof(T),
+                              (idx - (uint32_t)pitch) * (uint32_t)sizeof(T)};
+      R g[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) lds1[i][r][cx] = C::enc(g[i], Ld.es[i]);
+      for (int i = 0; i < 9; ++i) {
+        const char* __restrict__ Ai = reinterpret_cast<const char*>(A + i * plane);
+        g[i] = C::dec(*reinterpret_cast<const T*>(Ai + ro[1 + kCy[i]] - kCx[i] * (int)sizeof(T)), Ld.ds[i]);
+      }
+      collide<R, CM>(Ld, g, rho0, b, omega);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) lds1[i][r][cx] = C::enc(g[i], Ld.es[i]);
+    }
+    int xl, xh, yl, yh, ncol, nrow;
+    edge_count(x0 - 2, y0 - 2, T3_W1, TY + 4, xl, xh, yl, yh, ncol, nrow);
+    for (int e = tid; e < ncol + nrow; e += NT) {
+      int x, y;
+      edge_node(e, xl, xh, yl, yh, ncol, x, y);
+      // sources clamped into the lattice (a clamped source is only ever an unknown population's)
+      const uint32_t unknown = tl_unknown(x, y, nx, ny);
+      const int sxs[3] = {min(x + 1, nx - 1), x, max(x - 1, 0)};
+      const uint32_t srow[3] = {(uint32_t)(min(y + 1, ny - 1) * pitch), (uint32_t)(y * pitch),
+                                (uint32_t)(max(y - 1, 0) * pitch)};
+      R g[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        const T* __restrict__ Ai = A + i * plane;
+        const R v = C::dec(Ai[srow[1 + kCy[i]] + (uint32_t)sxs[1 + kCx[i]]], Ld.ds[i]);
+        g[i] = (unknown >> i) & 1u ? R(0) : v;
+      }
+      auto mom = [&](int xx, int yy, R m[3]) { tl_moments_global<S>(Ld, A, xx, yy, b, m); };
+      tl_nsbc<R>(Ld, g, unknown, x, y, rho0, b, mom);
+      collide<R, CM>(Ld, g, rho0, b, omega);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) lds1[i][y - y0 + 2][x - x0 + 2] = C::enc(g[i], Ld.es[i]);
+    }
   }
   __syncthreads();
 
   // ---- level t + 2 from lds1 (lattice node (x, y) at lds1[.][y - y0 + 2][x - x0 + 2])
-  auto mom1 = [&](int xx, int yy, R m[3]) {
-    R q[9];
-    const int lx = xx - x0 + 2, ly = yy - y0 + 2;
+  {
+    auto mom1 = [&](int xx, int yy, R m[3]) {
+      R q[9];
+      const int lx = xx - x0 + 2, ly = yy - y0 + 2;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) q[i] = C::dec(lds1[i][ly][lx], Ld.ds[i]);
-    moments<R>(q, rho0, base, m[0], m[1], m[2]);
-  };
-  for (int k = tid; k < (TY + 2) * T3_W2; k += NT) {
-    const int r = k / T3_W2, cx = k - r * T3_W2;
-    const int x = x0 - 1 + cx, y = y0 - 1 + r;
-    if (x < 0 || x >= nx || y < 0 || y >= ny) continue;
-    const uint32_t unknown = tl_unknown(x, y, nx, ny);
-    const int lxs[3] = {min(x + 1, nx - 1) - x0 + 2, x - x0 + 2, max(x - 1, 0) - x0 + 2};
-    const int lys[3] = {min(y + 1, ny - 1) - y0 + 2, y - y0 + 2, max(y - 1, 0) - y0 + 2};
-    R g[9];
+      for (int i = 0; i < 9; ++i) q[i] = C::dec(lds1[i][ly][lx], Ld.ds[i]);
+      moments<R>(q, rho0, b, m[0], m[1], m[2]);
+    };
+    for (int k = tid; k < (TY + 2) * T3_W2; k += NT) {
+      const int r = k / T3_W2, cx = k - r * T3_W2;
+      const int x = x0 - 1 + cx, y = y0 - 1 + r;
+      if (!interior_node(x, y)) continue;
+      R g[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      const R v = C::dec(lds1[i][lys[1 + kCy[i]]][lxs[1 + kCx[i]]], Ld.ds[i]);
-      g[i] = (unknown >> i) & 1u ? R(0) : v;
+      for (int i = 0; i < 9; ++i) g[i] = C::dec(lds1[i][r + 1 - kCy[i]][cx + 1 - kCx[i]], Ld.ds[i]);
+      collide<R, CM>(Ld, g, rho0, b, omega);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) lds2[i][r][cx] = C::enc(g[i], Ld.es[i]);
     }
-    if (unknown) tl_nsbc<R>(Ld, g, unknown, x, y, rho0, base, mom1);
-    collide<R, CM>(Ld, g, rho0, base, omega);
+    int xl, xh, yl, yh, ncol, nrow;
+    edge_count(x0 - 1, y0 - 1, T3_W2, TY + 2, xl, xh, yl, yh, ncol, nrow);
+    for (int e = tid; e < ncol + nrow; e += NT) {
+      int x, y;
+      edge_node(e, xl, xh, yl, yh, ncol, x, y);
+      const uint32_t unknown = tl_unknown(x, y, nx, ny);
+      const int lxs[3] = {min(x + 1, nx - 1) - x0 + 2, x - x0 + 2, max(x - 1, 0) - x0 + 2};
+      const int lys[3] = {min(y + 1, ny - 1) - y0 + 2, y - y0 + 2, max(y - 1, 0) - y0 + 2};
+      R g[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) lds2[i][r][cx] = C::enc(g[i], Ld.es[i]);
+      for (int i = 0; i < 9; ++i) {
+        const R v = C::dec(lds1[i][lys[1 + kCy[i]]][lxs[1 + kCx[i]]], Ld.ds[i]);
+        g[i] = (unknown >> i) & 1u ? R(0) : v;
+      }
+      tl_nsbc<R>(Ld, g, unknown, x, y, rho0, b, mom1);
+      collide<R, CM>(Ld, g, rho0, b, omega);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) lds2[i][y - y0 + 1][x - x0 + 1] = C::enc(g[i], Ld.es[i]);
+    }
   }
   __syncthreads();
 
   // ---- level t + 3 on the tile from lds2 (lattice node (x, y) at lds2[.][y - y0 + 1][x - x0 + 1])
-  auto mom2 = [&](int xx, int yy, R m[3]) {
-    R q[9];
-    const int lx = xx - x0 + 1, ly = yy - y0 + 1;
+  {
+    auto mom2 = [&](int xx, int yy, R m[3]) {
+      R q[9];
+      const int lx = xx - x0 + 1, ly = yy - y0 + 1;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) q[i] = C::dec(lds2[i][ly][lx], Ld.ds[i]);
-    moments<R>(q, rho0, base, m[0], m[1], m[2]);
-  };
-  for (int k = tid; k < TY * TL_TX; k += NT) {
-    const int r = k / TL_TX, cx = k - r * TL_TX;
-    const int x = x0 + cx, y = y0 + r;
-    const uint32_t unknown = tl_unknown(x, y, nx, ny);
-    const int lxs[3] = {min(x + 1, nx - 1) - x0 + 1, cx + 1, max(x - 1, 0) - x0 + 1};
-    const int lys[3] = {min(y + 1, ny - 1) - y0 + 1, r + 1, max(y - 1, 0) - y0 + 1};
-    R g[9];
+      for (int i = 0; i < 9; ++i) q[i] = C::dec(lds2[i][ly][lx], Ld.ds[i]);
+      moments<R>(q, rho0, b, m[0], m[1], m[2]);
+    };
+    auto store = [&](int x, int y, const R g[9]) {
+      const uint32_t off = (uint32_t)(y * pitch + x) * (uint32_t)sizeof(T);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      const R v = C::dec(lds2[i][lys[1 + kCy[i]]][lxs[1 + kCx[i]]], Ld.ds[i]);
-      g[i] = (unknown >> i) & 1u ? R(0) : v;
+      for (int i = 0; i < 9; ++i)
+        put<NTS>(reinterpret_cast<T*>(reinterpret_cast<char*>(B + i * plane) + off), C::enc(g[i], Ld.es[i]));
+    };
+    for (int k = tid; k < TY * TL_TX; k += NT) {
+      const int r = k / TL_TX, cx = k - r * TL_TX;
+      const int x = x0 + cx, y = y0 + r;
+      if (!interior_node(x, y)) continue;
+      R g[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) g[i] = C::dec(lds2[i][r + 1 - kCy[i]][cx + 1 - kCx[i]], Ld.ds[i]);
+      collide<R, CM>(Ld, g, rho0, b, omega);
+      store(x, y, g);
     }
-    if (unknown) tl_nsbc<R>(Ld, g, unknown, x, y, rho0, base, mom2);
-    collide<R, CM>(Ld, g, rho0, base, omega);
-    const uint32_t off = (uint32_t)(y * pitch + x) * (uint32_t)sizeof(T);
+    int xl, xh, yl, yh, ncol, nrow;
+    edge_count(x0, y0, TL_TX, TY, xl, xh, yl, yh, ncol, nrow);
+    for (int e = tid; e < ncol + nrow; e += NT) {
+      int x, y;
+      edge_node(e, xl, xh, yl, yh, ncol, x, y);
+      const uint32_t unknown = tl_unknown(x, y, nx, ny);
+      const int lxs[3] = {min(x + 1, nx - 1) - x0 + 1, x - x0 + 1, max(x - 1, 0) - x0 + 1};
+      const int lys[3] = {min(y + 1, ny - 1) - y0 + 1, y - y0 + 1, max(y - 1, 0) - y0 + 1};
+      R g[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i)
-      put<NTS>(reinterpret_cast<T*>(reinterpret_cast<char*>(B + i * plane) + off), C::enc(g[i], Ld.es[i]));
+      for (int i = 0; i < 9; ++i) {
+        const R v = C::dec(lds2[i][lys[1 + kCy[i]]][lxs[1 + kCx[i]]], Ld.ds[i]);
+        g[i] = (unknown >> i) & 1u ? R(0) : v;
+      }
+      tl_nsbc<R>(Ld, g, unknown, x, y, rho0, b, mom2);
+      collide<R, CM>(Ld, g, rho0, b, omega);
+      store(x, y, g);
+    }
   }
 }
 
