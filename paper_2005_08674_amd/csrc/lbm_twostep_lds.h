@@ -15,6 +15,8 @@
 // reload would: results are bit-identical to two single steps.
 #pragma once
 
+#include <type_traits>
+
 #include "lbm_device.h"
 #include "lbm_sweep.h"
 
@@ -261,6 +263,12 @@ namespace lbm {
 constexpr int T3_W1 = TL_TX + 4;
 constexpr int T3_W2 = TL_TX + 2;
 
+// First thread of the waves that run one iteration fewer of a sweep over n
+// nodes by nt threads (0 when every wave runs the same number).
+__host__ __device__ constexpr int light_waves_start(int n, int nt) {
+  return n % nt == 0 ? 0 : ((n % nt + 63) / 64 * 64) % nt;
+}
+
 template <int S, int TY>
 constexpr int three_step_lds_bytes() {
   return 9 * ((TY + 4) * T3_W1 + (TY + 2) * T3_W2) * (int)sizeof(typename Codec<S>::T);
@@ -287,17 +295,32 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
   // Inner tile: every level t + 1 node and its pull sources lie inside the
   // lattice and away from its edges: no clamps, no NSBC.
   const bool inner = x0 >= 3 && x0 + TL_TX + 3 <= nx && y0 >= 3 && y0 + TY + 3 <= ny;
-  // The inner sweep is inlined twice, with the base state's u_b = 0 flag a
-  // known constant in each copy, so the per-node arithmetic carries only the
-  // branch that runs (the operations and their order are unchanged).
-  auto inner_sweep = [&](const Base<R>& base) __attribute__((always_inline)) {
-    constexpr int N1 = (TY + 4) * T3_W1, N2 = (TY + 2) * T3_W2, N3 = TY * TL_TX;
+  auto interior_node = [&](int x, int y) { return x >= 1 && x <= nx - 2 && y >= 1 && y <= ny - 2; };
+
+  // One sweep per level over the level's whole region, its iterations
+  // unrolled.  In an edge tile (edge = true) every node of the region runs the
+  // interior update, a node off the lattice or on its edge on sources clamped
+  // into the lattice, and only the lattice's interior nodes keep their result;
+  // the lattice-edge nodes follow in edge_pass.  Every lane thus issues the
+  // same unconditional loads, as in an inner tile.
+  auto level1 = [&](const Base<R>& b, auto edge) __attribute__((always_inline)) {
+    constexpr bool E = decltype(edge)::value;
+    constexpr int N1 = (TY + 4) * T3_W1;
 #pragma unroll
     for (int it = 0; it < (N1 + NT - 1) / NT; ++it) {
       const int k = tid + it * NT;
       if (k < N1) {
         const int r = k / T3_W1, cx = k - r * T3_W1;
-        const uint32_t idx = (uint32_t)((y0 - 2 + r) * pitch + (x0 - 2 + cx));
+        int x = x0 - 2 + cx, y = y0 - 2 + r;
+        bool keep = true;
+        if constexpr (E) {
+          keep = interior_node(x, y);
+          x = min(max(x, 1), nx - 2);
+          y = min(max(y, 1), ny - 2);
+        }
+        // per-plane base pointers (uniform) and 32-bit unsigned byte offsets
+        // (a plane is below 4 GiB): a scalar base plus one vector offset
+        const uint32_t idx = (uint32_t)(y * pitch + x);
         const uint32_t ro[3] = {(idx + (uint32_t)pitch) * (uint32_t)sizeof(T), idx * (uint32_t)sizeof(T),
                                 (idx - (uint32_t)pitch) * (uint32_t)sizeof(T)};
         R g[9];
@@ -306,12 +329,18 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
           const char* __restrict__ Ai = reinterpret_cast<const char*>(A + i * plane);
           g[i] = C::dec(*reinterpret_cast<const T*>(Ai + ro[1 + kCy[i]] - kCx[i] * (int)sizeof(T)), Ld.ds[i]);
         }
-        collide<R, CM>(Ld, g, rho0, base, omega);
+        collide<R, CM>(Ld, g, rho0, b, omega);
+        if (keep) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) lds1[i][r][cx] = C::enc(g[i], Ld.es[i]);
+          for (int i = 0; i < 9; ++i) lds1[i][r][cx] = C::enc(g[i], Ld.es[i]);
+        }
       }
     }
-    __syncthreads();
+  };
+  // (LDS reads of a dropped node stay inside the arrays; its values are unused.)
+  auto level2 = [&](const Base<R>& b, auto edge) __attribute__((always_inline)) {
+    constexpr bool E = decltype(edge)::value;
+    constexpr int N2 = (TY + 2) * T3_W2;
 #pragma unroll
     for (int it = 0; it < (N2 + NT - 1) / NT; ++it) {
       const int k = tid + it * NT;
@@ -320,12 +349,23 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
         R g[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) g[i] = C::dec(lds1[i][r + 1 - kCy[i]][cx + 1 - kCx[i]], Ld.ds[i]);
-        collide<R, CM>(Ld, g, rho0, base, omega);
+        collide<R, CM>(Ld, g, rho0, b, omega);
+        if (!E || interior_node(x0 - 1 + cx, y0 - 1 + r)) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) lds2[i][r][cx] = C::enc(g[i], Ld.es[i]);
+          for (int i = 0; i < 9; ++i) lds2[i][r][cx] = C::enc(g[i], Ld.es[i]);
+        }
       }
     }
-    __syncthreads();
+  };
+  auto store = [&](int x, int y, const R g[9]) {
+    const uint32_t off = (uint32_t)(y * pitch + x) * (uint32_t)sizeof(T);
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+      put<NTS>(reinterpret_cast<T*>(reinterpret_cast<char*>(B + i * plane) + off), C::enc(g[i], Ld.es[i]));
+  };
+  auto level3 = [&](const Base<R>& b, auto edge) __attribute__((always_inline)) {
+    constexpr bool E = decltype(edge)::value;
+    constexpr int N3 = TY * TL_TX;
 #pragma unroll
     for (int it = 0; it < (N3 + NT - 1) / NT; ++it) {
       const int k = tid + it * NT;
@@ -334,32 +374,38 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
         R g[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) g[i] = C::dec(lds2[i][r + 1 - kCy[i]][cx + 1 - kCx[i]], Ld.ds[i]);
-        collide<R, CM>(Ld, g, rho0, base, omega);
-        const uint32_t off = (uint32_t)((y0 + r) * pitch + (x0 + cx)) * (uint32_t)sizeof(T);
-#pragma unroll
-        for (int i = 0; i < 9; ++i)
-          put<NTS>(reinterpret_cast<T*>(reinterpret_cast<char*>(B + i * plane) + off), C::enc(g[i], Ld.es[i]));
+        collide<R, CM>(Ld, g, rho0, b, omega);
+        if (!E || interior_node(x0 + cx, y0 + r)) store(x0 + cx, y0 + r, g);
       }
     }
   };
   if (inner) {
+    // inlined twice, with the base state's u_b = 0 flag a known constant in
+    // each copy, so the per-node arithmetic carries only the branch that runs
+    // (the operations and their order are unchanged)
+    auto sweep = [&](const Base<R>& b) __attribute__((always_inline)) {
+      level1(b, std::false_type{});
+      __syncthreads();
+      level2(b, std::false_type{});
+      __syncthreads();
+      level3(b, std::false_type{});
+    };
     Base<R> b = base;
     if (base.zero) {
       b.zero = true;
-      inner_sweep(b);
+      sweep(b);
     } else {
       b.zero = false;
-      inner_sweep(b);
+      sweep(b);
     }
     return;
   }
 
-  // ---- edge tiles.  Each level first updates the nodes of its region that
-  // are inside the lattice and not on its edge (every pull source of such a
-  // node lies inside the lattice: no clamps, no NSBC), then the region's
-  // lattice-edge nodes, gathered into consecutive lanes so that NSBC runs on
-  // full wavefronts instead of one lane per row.  The per-node arithmetic is
-  // the one above, so the results do not change.
+  // ---- edge tiles.  After each level's sweep, the region's lattice-edge
+  // nodes are gathered into consecutive lanes, so that NSBC runs on full
+  // wavefronts instead of one lane per row, starting at the first wave that
+  // ran one iteration fewer of the sweep.  The per-node arithmetic is the
+  // single-step path's, so the results do not change.
   const Base<R>& b = base;
   // region of a level: lattice rows ry0 .. ry0 + rh - 1, columns rx0 .. rx0 + rw - 1
   auto edge_count = [&](int rx0, int ry0, int rw, int rh, int& xl, int& xh, int& yl, int& yh, int& ncol, int& nrow) {
@@ -388,30 +434,15 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
     y = bottom ? 0 : ny - 1;
     x = cx0 + (bottom ? e : e - (yl == 0) * cw);
   };
-  auto interior_node = [&](int x, int y) { return x >= 1 && x <= nx - 2 && y >= 1 && y <= ny - 2; };
+  // edge-pass lane of this thread for a sweep over N nodes
+  auto edge_lane = [&](int N) { return (tid + NT - light_waves_start(N, NT)) % NT; };
 
   // ---- level t + 1 from HBM
+  level1(b, std::true_type{});
   {
-    for (int k = tid; k < (TY + 4) * T3_W1; k += NT) {
-      const int r = k / T3_W1, cx = k - r * T3_W1;
-      const int x = x0 - 2 + cx, y = y0 - 2 + r;
-      if (!interior_node(x, y)) continue;
-      const uint32_t idx = (uint32_t)(y * pitch + x);
-      const uint32_t ro[3] = {(idx + (uint32_t)pitch) * (uint32_t)sizeof(T), idx * (uint32_t)sizeof(T),
-                              (idx - (uint32_t)pitch) * (uint32_t)sizeof(T)};
-      R g[9];
-#pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        const char* __restrict__ Ai = reinterpret_cast<const char*>(A + i * plane);
-        g[i] = C::dec(*reinterpret_cast<const T*>(Ai + ro[1 + kCy[i]] - kCx[i] * (int)sizeof(T)), Ld.ds[i]);
-      }
-      collide<R, CM>(Ld, g, rho0, b, omega);
-#pragma unroll
-      for (int i = 0; i < 9; ++i) lds1[i][r][cx] = C::enc(g[i], Ld.es[i]);
-    }
     int xl, xh, yl, yh, ncol, nrow;
     edge_count(x0 - 2, y0 - 2, T3_W1, TY + 4, xl, xh, yl, yh, ncol, nrow);
-    for (int e = tid; e < ncol + nrow; e += NT) {
+    for (int e = edge_lane((TY + 4) * T3_W1); e < ncol + nrow; e += NT) {
       int x, y;
       edge_node(e, xl, xh, yl, yh, ncol, x, y);
       // sources clamped into the lattice (a clamped source is only ever an unknown population's)
@@ -436,6 +467,7 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
   __syncthreads();
 
   // ---- level t + 2 from lds1 (lattice node (x, y) at lds1[.][y - y0 + 2][x - x0 + 2])
+  level2(b, std::true_type{});
   {
     auto mom1 = [&](int xx, int yy, R m[3]) {
       R q[9];
@@ -444,20 +476,9 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
       for (int i = 0; i < 9; ++i) q[i] = C::dec(lds1[i][ly][lx], Ld.ds[i]);
       moments<R>(q, rho0, b, m[0], m[1], m[2]);
     };
-    for (int k = tid; k < (TY + 2) * T3_W2; k += NT) {
-      const int r = k / T3_W2, cx = k - r * T3_W2;
-      const int x = x0 - 1 + cx, y = y0 - 1 + r;
-      if (!interior_node(x, y)) continue;
-      R g[9];
-#pragma unroll
-      for (int i = 0; i < 9; ++i) g[i] = C::dec(lds1[i][r + 1 - kCy[i]][cx + 1 - kCx[i]], Ld.ds[i]);
-      collide<R, CM>(Ld, g, rho0, b, omega);
-#pragma unroll
-      for (int i = 0; i < 9; ++i) lds2[i][r][cx] = C::enc(g[i], Ld.es[i]);
-    }
     int xl, xh, yl, yh, ncol, nrow;
     edge_count(x0 - 1, y0 - 1, T3_W2, TY + 2, xl, xh, yl, yh, ncol, nrow);
-    for (int e = tid; e < ncol + nrow; e += NT) {
+    for (int e = edge_lane((TY + 2) * T3_W2); e < ncol + nrow; e += NT) {
       int x, y;
       edge_node(e, xl, xh, yl, yh, ncol, x, y);
       const uint32_t unknown = tl_unknown(x, y, nx, ny);
@@ -478,6 +499,7 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
   __syncthreads();
 
   // ---- level t + 3 on the tile from lds2 (lattice node (x, y) at lds2[.][y - y0 + 1][x - x0 + 1])
+  level3(b, std::true_type{});
   {
     auto mom2 = [&](int xx, int yy, R m[3]) {
       R q[9];
@@ -486,25 +508,9 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
       for (int i = 0; i < 9; ++i) q[i] = C::dec(lds2[i][ly][lx], Ld.ds[i]);
       moments<R>(q, rho0, b, m[0], m[1], m[2]);
     };
-    auto store = [&](int x, int y, const R g[9]) {
-      const uint32_t off = (uint32_t)(y * pitch + x) * (uint32_t)sizeof(T);
-#pragma unroll
-      for (int i = 0; i < 9; ++i)
-        put<NTS>(reinterpret_cast<T*>(reinterpret_cast<char*>(B + i * plane) + off), C::enc(g[i], Ld.es[i]));
-    };
-    for (int k = tid; k < TY * TL_TX; k += NT) {
-      const int r = k / TL_TX, cx = k - r * TL_TX;
-      const int x = x0 + cx, y = y0 + r;
-      if (!interior_node(x, y)) continue;
-      R g[9];
-#pragma unroll
-      for (int i = 0; i < 9; ++i) g[i] = C::dec(lds2[i][r + 1 - kCy[i]][cx + 1 - kCx[i]], Ld.ds[i]);
-      collide<R, CM>(Ld, g, rho0, b, omega);
-      store(x, y, g);
-    }
     int xl, xh, yl, yh, ncol, nrow;
     edge_count(x0, y0, TL_TX, TY, xl, xh, yl, yh, ncol, nrow);
-    for (int e = tid; e < ncol + nrow; e += NT) {
+    for (int e = edge_lane(TY * TL_TX); e < ncol + nrow; e += NT) {
       int x, y;
       edge_node(e, xl, xh, yl, yh, ncol, x, y);
       const uint32_t unknown = tl_unknown(x, y, nx, ny);
