@@ -401,33 +401,12 @@ def run_c5(torch, W, steps, every=50, timing_steps=1000):
         lbm.lbm_set_tile(lat.ctx, k)
         return lbm.lbm_tile_describe(k)
 
-    def fastest(lat, reps=3, sustained=False):
-        """Tune the launch on `lat`; keep the multi-step sweep when it beats single steps per step.
-        The tuners time repeated launches on one unchanged input, which at 2048^2 (151 MB of state)
-        can stay in the 256 MB last-level cache; with `sustained` (a lattice whose state may
-        advance) the single-step winner and the best two- and three-step shapes are timed again over
-        60 consecutive steps, as the timed run steps, and the fastest is kept.  Returns the choice."""
+    def fastest(lat, reps=5):
+        """Tune the launch on `lat` (the library's tuners time consecutive steps from a saved state);
+        keep the multi-step sweep when it beats single steps per step.  Returns the choice."""
         best, times = lbm.lbm_autotune(lat.ctx, reps)
         b2, t2 = lbm.lbm_autotune_two_step(lat.ctx, reps)
-        if not sustained:
-            return ("multi", b2) if t2[b2] < times[best] else ("single", best)
-        cands = [("single", best)]
-        for k in (2, 3):
-            ids = [i for i, t in enumerate(t2) if t >= 0 and lbm.lbm_two_step_steps(i) == k]
-            if ids:
-                cands.append(("multi", min(ids, key=lambda i: t2[i])))
-        ms = {}
-        for c in cands:
-            use(lat, c)
-            lat.step(6)
-            torch.cuda.synchronize()
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record(lat.stream)
-            lat.step(60)
-            b.record(lat.stream)
-            torch.cuda.synchronize()
-            ms[c] = a.elapsed_time(b)
-        return min(cands, key=lambda c: ms[c])
+        return ("multi", b2) if t2[b2] < times[best] else ("single", best)
 
     def closure_overlap(lat, steps=100):
         """Time closure steps with the edge kernel on the lattice's stream and on a second stream
@@ -455,7 +434,7 @@ def run_c5(torch, W, steps, every=50, timing_steps=1000):
             launch = ("edge (closure) kernel on a second stream beside the bulk kernel" if overlap
                       else "separate edge (closure) and bulk launches")
         else:
-            choice = fastest(g, sustained=True)
+            choice = fastest(g)
             launch = use(g, choice)
         g.step(20)
         torch.cuda.synchronize()

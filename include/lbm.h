@@ -250,8 +250,13 @@ int lbm_energy_noalloc(lbm_ctx* test, const lbm_ctx* ref, int32_t x_off, int32_t
  * the lattice and storage).  lbm_autotune times every candidate on the
  * context's own lattice as the launch lbm_step uses (the fused step launch,
  * or the bulk kernel when fusion is off), `reps` timed launches each, median
- * of those, after one warm-up, leaving the state unchanged, and selects the
- * fastest; it writes the chosen id to *best and, if times_ms is not NULL,
+ * of those, after one warm-up, and selects the fastest.  The launches are
+ * consecutive steps, as stepping runs them (a launch repeated on one
+ * unchanged buffer can be served from the GPU's last-level cache, 256 MB on
+ * MI355X, where two buffers would not fit): the state is saved to a
+ * temporary device copy (one buffer's size, allocated and freed here) and
+ * restored afterwards, so it and t are left unchanged.  It writes the chosen
+ * id to *best and, if times_ms is not NULL,
  * the per-candidate median launch time in milliseconds (length
  * lbm_tile_count).  Synchronizes the stream. */
 int lbm_tile_count(void);
@@ -312,15 +317,12 @@ int lbm_set_fused(lbm_ctx* ctx, int on);
  * storage format), any other remainder single-step launches.  The closure,
  * the overlap option and periodic edges always use the single-step kernels.
  * lbm_autotune_two_step times every shape the lattice supports (`reps`
- * launches each, median; the state is left unchanged), selects the one with
+ * consecutive launches each, median, from a saved and restored state as
+ * lbm_autotune does; the state is left unchanged), selects the one with
  * the least time per step, writes its id to *best and, if times_ms is not
  * NULL, per shape the median launch time divided by its steps per launch
  * (ms per step; -1 for shapes the lattice cannot take).  Synchronizes the
- * stream.  Both autotuners repeat launches on one unchanged input: for a
- * state small enough to stay in the GPU's last-level cache (256 MB on
- * MI355X) those reads can hit the cache, which consecutive steps over two
- * buffers do not, so such lattices are better confirmed by timing a few
- * dozen consecutive steps per candidate.  lbm_two_step_times returns the summed elapsed milliseconds and
+ * stream.  lbm_two_step_times returns the summed elapsed milliseconds and
  * the count of multi-step launches timed while lbm_enable_timing is on, and
  * resets them. */
 int lbm_two_step_count(void);

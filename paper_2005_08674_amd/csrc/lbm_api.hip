@@ -763,16 +763,53 @@ int lbm_get_tile(const lbm_ctx* c, int32_t* id) {
   return LBM_OK;
 }
 
+namespace {
+
+// The tuners time launches that advance the state, as stepping does.  A
+// launch repeated on one unchanged input re-reads one buffer, which for a
+// lattice whose buffer fits in the GPU's last-level cache (256 MB on MI355X)
+// and whose two buffers do not is served partly from that cache, a speed no
+// run of consecutive steps sees.  The current buffer is saved to a temporary
+// device copy first and restored at the end, so tuning leaves the state (and
+// t) as it was.
+struct StateSnapshot {
+  lbm_ctx* c = nullptr;
+  void* copy = nullptr;
+  size_t bytes = 0;
+  int save(lbm_ctx* ctx) {
+    c = ctx;
+    bytes = 9 * (size_t)c->L.plane * c->lay.esize;
+    HIPCHK(hipMalloc(&copy, bytes));
+    HIPCHK(hipMemcpyAsync(copy, lbm::buf_of(c->L, c->parity), bytes, hipMemcpyDeviceToDevice, c->stream));
+    return LBM_OK;
+  }
+  int restore() {
+    HIPCHK(hipMemcpyAsync(lbm::buf_of(c->L, c->parity), copy, bytes, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return LBM_OK;
+  }
+  ~StateSnapshot() {
+    if (copy) (void)hipFree(copy);
+  }
+};
+
+}  // namespace
+
 int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* best, float* times_ms) {
   if (!c || !best) return fail(LBM_ERR_ARG, "NULL argument");
   if (reps < 1 || reps > 1000) return fail(LBM_ERR_ARG, "reps = %d outside [1, 1000]", reps);
   // The kernel timed is the one lbm_step launches: the fused step (edge
-  // segments + bulk tiles) or, without fusion, the bulk kernel.  Both read
-  // buffer `parity` and write only the other one, so relaunching them leaves
-  // the state untouched.
+  // segments + bulk tiles) or, without fusion, the bulk kernel, over
+  // consecutive steps from a saved state.
   const bool fused = use_fused(c);
+  StateSnapshot snap;
+  if (int rc = snap.save(c)) return rc;
+  int par = c->parity;
   auto launch = [&](int id) {
-    return fused ? lbm::launch_step(c->L, c->parity, id, c->stream) : lbm::launch_bulk(c->L, c->parity, id, c->stream);
+    const hipError_t e =
+        fused ? lbm::launch_step(c->L, par, id, c->stream) : lbm::launch_bulk(c->L, par, id, c->stream);
+    par ^= 1;
+    return e;
   };
   const int nt = lbm::num_tiles();
   std::vector<hipEvent_t> ev(2 * reps);
@@ -804,6 +841,7 @@ int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* best, float* times_ms) {
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
   if (rc) return rc;
+  if (int r = snap.restore()) return r;
   c->tile = best_id;
   *best = best_id;
   return LBM_OK;
@@ -860,9 +898,17 @@ int lbm_autotune_two_step(lbm_ctx* c, int32_t reps, int32_t* best, float* times_
   if (reps < 1 || reps > 1000) return fail(LBM_ERR_ARG, "reps = %d outside [1, 1000]", reps);
   if (!lbm::two_step_supported(c->L))
     return fail(LBM_ERR_ARG, "the multi-step sweeps need NSBC on all four edges");
-  // a sweep reads buffer `parity` and writes only the other one, so
-  // relaunching it leaves the state untouched; shapes are compared by time
-  // per step, and a shape the lattice cannot take reports a negative time
+  // consecutive launches from a saved state (as lbm_autotune); shapes are
+  // compared by time per step, and a shape the lattice cannot take reports a
+  // negative time
+  StateSnapshot snap;
+  if (int r = snap.save(c)) return r;
+  int par = c->parity;
+  auto launch = [&](int id) {
+    const hipError_t e = launch_multi(c->L, par, id, c->stream);
+    par ^= multi_steps(id) & 1;
+    return e;
+  };
   const int nt = multi_count();
   std::vector<hipEvent_t> ev(2 * reps);
   for (auto& e : ev) HIPCHK(hipEventCreate(&e));
@@ -874,10 +920,10 @@ int lbm_autotune_two_step(lbm_ctx* c, int32_t reps, int32_t* best, float* times_
       if (times_ms) times_ms[id] = -1.f;
       continue;
     }
-    hipError_t e = launch_multi(c->L, c->parity, id, c->stream);
+    hipError_t e = launch(id);
     for (int r = 0; r < reps && e == hipSuccess; ++r) {
       e = hipEventRecord(ev[2 * r], c->stream);
-      if (e == hipSuccess) e = launch_multi(c->L, c->parity, id, c->stream);
+      if (e == hipSuccess) e = launch(id);
       if (e == hipSuccess) e = hipEventRecord(ev[2 * r + 1], c->stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -902,6 +948,7 @@ int lbm_autotune_two_step(lbm_ctx* c, int32_t reps, int32_t* best, float* times_
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
   if (rc) return rc;
+  if (int r = snap.restore()) return r;
   c->two_step = best_id;
   for (int k = 2; k <= 4; ++k)
     if (best_k[k] >= 0) c->rem_best[k] = best_k[k];

@@ -117,6 +117,29 @@ def test_timing_counts_launches_and_odd_steps():
     assert g.t == 7
 
 
+@pytest.mark.parametrize("store", ["f32", "f16"])
+def test_autotuners_leave_the_state_and_time(store):
+    """Both tuners time consecutive steps from a saved state: afterwards the populations and t are
+    what they were, and stepping on gives the bits of an untuned twin."""
+    from paper_2005_08674_amd import lbm
+    from paper_2005_08674_amd.lattice import Lattice
+    f = W.gaussian_pulses(200, 150, [(1e-3, 9.0, 90.0, 70.0)], u0=(0.02, 0.01))
+    a = Lattice(200, 150, 0.58, f, store=store, m0=(1.0, 0.02, 0.01), beta=0.1)
+    b = Lattice(200, 150, 0.58, f, store=store, m0=(1.0, 0.02, 0.01), beta=0.1)
+    a.step(5)
+    b.step(5)
+    before = a.populations().cpu().numpy()
+    best, times = lbm.lbm_autotune(a.ctx, 2)
+    b2, t2 = lbm.lbm_autotune_two_step(a.ctx, 2)
+    assert a.t == 5 and np.array_equal(a.populations().cpu().numpy(), before)
+    assert times[best] > 0 and t2[b2] > 0 and lbm.lbm_get_two_step(a.ctx) == b2
+    a.step(7)
+    b.step(7)
+    assert np.array_equal(a.populations().cpu().numpy(), b.populations().cpu().numpy())
+    a.close()
+    b.close()
+
+
 def test_closure_falls_back_to_single_steps():
     """With the closure active the two-step shape is ignored: same bits as the closure alone."""
     from paper_2005_08674_amd import lbm
