@@ -314,8 +314,13 @@ int lbm_set_fused(lbm_ctx* ctx, int on);
  * selected, lbm_step advances groups of that many steps with it; after
  * three-step launches a remainder of two steps takes one two-step launch
  * (the best two-step shape lbm_autotune_two_step timed, else a default per
- * storage format), any other remainder single-step launches.  The closure,
- * the overlap option and periodic edges always use the single-step kernels.
+ * storage format), any other remainder single-step launches.  With the
+ * learned closure on (lbm_set_closure) the three-step shapes carry it: in
+ * their edge tiles the network corrects m_c of every single-normal edge
+ * node at each of the three levels, from the previous level, as the
+ * single-step edge kernel does (bit-identical to closure single steps);
+ * two-step shapes and remainders then run as closure single steps.  The
+ * overlap option and periodic edges always use the single-step kernels.
  * lbm_autotune_two_step times every shape the lattice supports (`reps`
  * consecutive launches each, median, from a saved and restored state as
  * lbm_autotune does; the state is left unchanged), selects the one with

@@ -419,13 +419,17 @@ int step_once(lbm_ctx* c) {
 // the next num_three_step() are three-step shapes.
 int multi_count() { return lbm::num_two_step() + lbm::num_three_step(); }
 int multi_steps(int id) { return id < lbm::num_two_step() ? 2 : 3; }
+// (with the learned closure only the three-step shapes: the two-step sweep has no closure path)
 bool multi_supported(const lbm::LatDesc& L, int id) {
   if (id < 0 || id >= multi_count()) return false;
-  return id < lbm::num_two_step() ? lbm::two_step_supported(L) : lbm::three_step_supported(L, id - lbm::num_two_step());
+  return id < lbm::num_two_step() ? lbm::two_step_supported(L) && !(L.closure && L.net)
+                                  : lbm::three_step_supported(L, id - lbm::num_two_step());
 }
-hipError_t launch_multi(const lbm::LatDesc& L, int parity, int id, hipStream_t s) {
-  return id < lbm::num_two_step() ? lbm::launch_two_step(L, parity, id, s)
-                                  : lbm::launch_three_step(L, parity, id - lbm::num_two_step(), s);
+// (a closure lattice's edge-tile kernel runs on the context's second stream)
+hipError_t launch_multi(const lbm_ctx* c, int parity, int id) {
+  return id < lbm::num_two_step()
+             ? lbm::launch_two_step(c->L, parity, id, c->stream)
+             : lbm::launch_three_step(c->L, parity, id - lbm::num_two_step(), c->stream, c->side, c->ev_bulk, c->ev_edge);
 }
 void multi_name(int id, char* buf, size_t len) {
   if (id < lbm::num_two_step())
@@ -450,7 +454,7 @@ int step_multi(lbm_ctx* c, int id) {
     c->ev_two.push_back(1);
   }
   if (t[0]) HIPCHK(hipEventRecord(t[0], c->stream));
-  HIPCHK(launch_multi(c->L, c->parity, id, c->stream));
+  HIPCHK(launch_multi(c, c->parity, id));
   if (t[1]) HIPCHK(hipEventRecord(t[1], c->stream));
   // the last level is in the other buffer: the launch wrote buffer parity ^ 1
   c->parity ^= 1;
@@ -476,7 +480,7 @@ int rem_shape(const lbm_ctx* c, int k) {
 }
 
 bool use_two_step(const lbm_ctx* c) {
-  return c->two_step >= 0 && !c->overlap && !(c->L.closure && c->L.net) && multi_supported(c->L, c->two_step);
+  return c->two_step >= 0 && !c->overlap && multi_supported(c->L, c->two_step);
 }
 
 }  // namespace
@@ -878,10 +882,14 @@ int lbm_set_two_step(lbm_ctx* c, int32_t id) {
   if (id < -1 || id >= multi_count()) return fail(LBM_ERR_ARG, "multi-step shape %d out of range", id);
   if (id >= 0 && !lbm::two_step_supported(c->L))
     return fail(LBM_ERR_ARG, "the multi-step sweeps need NSBC on all four edges");
-  if (id >= 0 && !multi_supported(c->L, id))
+  // the shape must suit the lattice; whether it carries the closure is
+  // decided per lbm_step (single steps where it does not)
+  lbm::LatDesc geom = c->L;
+  geom.closure = 0;
+  if (id >= 0 && !multi_supported(geom, id))
     return fail(LBM_ERR_ARG,
-                "multi-step shape %d: three-step shapes need whole tiles (nx >= 64, ny >= its tile rows), column-march "
-                "shapes nx >= their strip width and the first-order gradient, and both LDS for this format",
+                "multi-step shape %d: three-step shapes need whole tiles (nx >= 64, ny >= its tile rows) and "
+                "their LDS for this format",
                 id);
   c->two_step = id;
   return LBM_OK;
@@ -905,7 +913,7 @@ int lbm_autotune_two_step(lbm_ctx* c, int32_t reps, int32_t* best, float* times_
   if (int r = snap.save(c)) return r;
   int par = c->parity;
   auto launch = [&](int id) {
-    const hipError_t e = launch_multi(c->L, par, id, c->stream);
+    const hipError_t e = launch_multi(c, par, id);
     par ^= multi_steps(id) & 1;
     return e;
   };

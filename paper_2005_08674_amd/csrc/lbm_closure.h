@@ -79,48 +79,99 @@ __device__ inline void normal_frame_diff(const R a[3], const R b[3], int nx_, in
   out[2] = float(-dx * R(ny_) + dy * R(nx_));
 }
 
+// Strip amplitude of an input row,
+//   A = sqrt( (1/9) sum_j [c_s^2 (rho_j - rho_ref)^2 / rho0^2 + |u_j - u_ref|^2] ),
+// from the unscaled strip features feat(j, q) (strip node j, feature q).
+template <class F>
+__device__ inline float strip_amplitude(F feat, float rho0) {
+  constexpr float cs2 = 1.f / 3.f;
+  float s = 0.f;
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    const float r = feat(j, 0) / rho0, un = feat(j, 1), ut = feat(j, 2);
+    s += cs2 * r * r + un * un + ut * ut;
+  }
+  return sqrtf(s / 9.f);
+}
+
+__device__ inline float amplitude_inverse(float A) { return A > 0.f ? 1.f / A : 0.f; }
+
+// Input q of a finished row: the strip part scaled by 1/A (inv), omega,
+// (m_c - m0)/A, u_ref and zeros.  dmc: m_c - m0 and refn: m0, both as
+// (drho, u_n, u_t) in the edge frame.
+template <class F>
+__device__ inline float input_value(int q, F feat, float inv, float omega, const float dmc[3], const float refn[3]) {
+  if (q < F_STRIP) return feat(q / NODE_FEAT, q % NODE_FEAT) * inv;
+  if (q == F_OMEGA) return omega;
+  if (q < F_UREF) return dmc[q - F_MC] * inv;
+  if (q < mlp::NFEAT) return refn[1 + q - F_UREF];
+  return 0.f;
+}
+
+// Regime gate of a finished row, given as scaled(j, q) = feat(j, q) / A: true
+// when the strip's kinetic disturbance sum_j |u_j - u_ref|^2 exceeds kmin
+// times its acoustic part sum_j c_s^2 (rho_j - rho_ref)^2 / rho0^2.  A sound
+// wave carries the two in equal measure (ratio 1 at normal incidence), a
+// convected vortex almost only the first; kmin = 0 accepts every node.  The
+// ratio does not depend on the 1/A scaling of the row.
+template <class F>
+__device__ inline bool vortical_row(F scaled, float rho0, float kmin) {
+  constexpr float cs2 = 1.f / 3.f;
+  float su = 0.f, sr = 0.f;
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    const float r = scaled(j, 0) / rho0, un = scaled(j, 1), ut = scaled(j, 2);
+    su += un * un + ut * ut;
+    sr += cs2 * r * r;
+  }
+  return su > kmin * sr;
+}
+
 // Completes an input row x[0..86] whose strip part x[0..80] holds the
 // unscaled node features: appends omega, (m_c - m0)/A and u_ref, scales the
 // strip part by 1/A, zeroes 87..95 and returns A.  dmc: m_c - m0 and refn:
 // m0, both as (drho, u_n, u_t) in the edge frame.
 __device__ inline float finish_inputs(float* x, float rho0, float omega, const float dmc[3], const float refn[3]) {
-  constexpr float cs2 = 1.f / 3.f;
-  float s = 0.f;
+  auto unscaled = [&](int j, int q) { return x[NODE_FEAT * j + q]; };
+  const float A = strip_amplitude(unscaled, rho0);
+  const float inv = amplitude_inverse(A);
+  float row[mlp::IN];
 #pragma unroll
-  for (int j = 0; j < 9; ++j) {
-    const float r = x[NODE_FEAT * j] / rho0, un = x[NODE_FEAT * j + 1], ut = x[NODE_FEAT * j + 2];
-    s += cs2 * r * r + un * un + ut * ut;
-  }
-  const float A = sqrtf(s / 9.f);
-  const float inv = A > 0.f ? 1.f / A : 0.f;
+  for (int q = 0; q < mlp::IN; ++q) row[q] = input_value(q, unscaled, inv, omega, dmc, refn);
 #pragma unroll
-  for (int q = 0; q < F_STRIP; ++q) x[q] *= inv;
-  x[F_OMEGA] = omega;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) x[F_MC + c] = dmc[c] * inv;
-  x[F_UREF] = refn[1];
-  x[F_UREF + 1] = refn[2];
-#pragma unroll
-  for (int q = mlp::NFEAT; q < mlp::IN; ++q) x[q] = 0.f;
+  for (int q = 0; q < mlp::IN; ++q) x[q] = row[q];
   return A;
 }
 
-// Regime gate of a finished input row: true when the strip's kinetic
-// disturbance sum_j |u_j - u_ref|^2 exceeds kmin times its acoustic part
-// sum_j c_s^2 (rho_j - rho_ref)^2 / rho0^2.  A sound wave carries the two in
-// equal measure (ratio 1 at normal incidence), a convected vortex almost
-// only the first; kmin = 0 accepts every node.  The ratio does not depend
-// on the 1/A scaling of the row.
+// Regime gate of a finished row x (see vortical_row).
 __device__ inline bool vortical(const float* x, float rho0, float kmin) {
-  constexpr float cs2 = 1.f / 3.f;
-  float su = 0.f, sr = 0.f;
-#pragma unroll
-  for (int j = 0; j < 9; ++j) {
-    const float r = x[NODE_FEAT * j] / rho0, un = x[NODE_FEAT * j + 1], ut = x[NODE_FEAT * j + 2];
-    su += un * un + ut * ut;
-    sr += cs2 * r * r;
-  }
-  return su > kmin * sr;
+  return vortical_row([&](int j, int q) { return x[NODE_FEAT * j + q]; }, rho0, kmin);
+}
+
+// Normalised network input q of value v (BF16), as the network was trained.
+__device__ inline mlp::bf16 normalised_input(const float* mean, const float* inv_std, int q, float v) {
+  return (mlp::bf16)((v - mean[q]) * inv_std[q]);
+}
+__device__ inline mlp::bf16 normalised_input(const mlp::Net& net, int q, float v) {
+  return normalised_input(net.feat_mean, net.feat_inv_std, q, v);
+}
+
+// The closure's correction of m_c for network outputs o (normalised) and
+// strip amplitude amp > 0, in the lattice frame: false (NSBC's m_c stays)
+// when an output is not finite or leaves the trust bound (fmaxf would drop a
+// NaN operand, so finiteness is tested first).
+__device__ inline bool closure_delta(const mlp::Net& net, float o0, float o1, float o2, float amp, int enx, int eny,
+                                     float d[3]) {
+  const bool finite = isfinite(o0) && isfinite(o1) && isfinite(o2);
+  if (!(finite && fmaxf(fabsf(o0), fmaxf(fabsf(o1), fabsf(o2))) <= net.trust)) return false;
+  const float cr = amp * (o0 * net.out_scale[0]);
+  const float cn = amp * (o1 * net.out_scale[1]);
+  const float ct = amp * (o2 * net.out_scale[2]);
+  // back to the lattice frame: du = c_n n + c_t t, t = (-n_y, n_x)
+  d[0] = cr;
+  d[1] = cn * float(enx) - ct * float(eny);
+  d[2] = cn * float(eny) + ct * float(enx);
+  return true;
 }
 
 }  // namespace lbm

@@ -27,7 +27,9 @@ int two_step_min_rows();
 int num_three_step();
 void three_step_name(int id, char* buf, size_t len);
 bool three_step_supported(const LatDesc& L, int id);
-hipError_t launch_three_step(const LatDesc& L, int parity, int id, hipStream_t s);
+// (with the learned closure: edge tiles on `side` beside the inner tiles on s when side, fork and join are given)
+hipError_t launch_three_step(const LatDesc& L, int parity, int id, hipStream_t s, hipStream_t side = nullptr,
+                             hipEvent_t fork = nullptr, hipEvent_t join = nullptr);
 int three_step_tile_rows(int id);
 int three_step_min_rows();
 // ensemble two-step: one block per list entry (member, 64-column tile x, tile y); lat < 0 = padding

@@ -101,21 +101,68 @@ __device__ inline void bias_tanh_store(const f32x4 acc[NT], const float* bias, b
   }
 }
 
+// Where a forward pass reads the parameters: the Net itself, or a copy of
+// its weights and biases in LDS (same values, same instruction sequence).
+struct Params {
+  const bf16* W1;
+  const bf16* W2;
+  const bf16* W3;
+  const float* b1;
+  const float* b2;
+  const float* b3;
+  const float* mean;     // input normalisation (feat_mean, feat_inv_std)
+  const float* inv_std;
+};
+__device__ inline Params params_of(const Net& net) {
+  return {net.W1, net.W2, net.W3, net.b1, net.b2, net.b3, net.feat_mean, net.feat_inv_std};
+}
+
+// The biases and input normalisation as one block (b1, b2, b3, feat_mean,
+// feat_inv_std; fp32), for an LDS copy beside the weights in device memory.
+constexpr int PARAM_BYTES = (HID + HID + OUT_PAD + 2 * IN) * 4;
+
+// Copies the biases and the input normalisation into `dst` (16-byte aligned,
+// PARAM_BYTES) with the threads of a block (tid of nt) and returns the
+// parameters with those read from there; the caller synchronises before use.
+__device__ inline Params stage_params(const Net& net, char* dst, int tid, int nt) {
+  constexpr int ob2 = HID * 4, ob3 = ob2 + HID * 4, om = ob3 + OUT_PAD * 4, os = om + IN * 4;
+  auto copy = [&](const float* src, int off, int n) {
+    float* d = reinterpret_cast<float*>(dst + off);
+    for (int k = tid; k < n; k += nt) d[k] = src[k];
+  };
+  copy(net.b1, 0, HID);
+  copy(net.b2, ob2, HID);
+  copy(net.b3, ob3, OUT_PAD);
+  copy(net.feat_mean, om, IN);
+  copy(net.feat_inv_std, os, IN);
+  return {net.W1,
+          net.W2,
+          net.W3,
+          reinterpret_cast<const float*>(dst),
+          reinterpret_cast<const float*>(dst + ob2),
+          reinterpret_cast<const float*>(dst + ob3),
+          reinterpret_cast<const float*>(dst + om),
+          reinterpret_cast<const float*>(dst + os)};
+}
+
 // Forward pass of 16 rows (this wavefront): X (LDS, stride XS) -> H1, H2 (LDS,
 // stride HS) -> y (lane l, r: row 4 (l / 16) + r, output column l % 16).
-__device__ inline void forward16(const Net& net, const bf16* X, bf16* H1, bf16* H2, f32x4& y) {
+__device__ inline void forward16(const Params& p, const bf16* X, bf16* H1, bf16* H2, f32x4& y) {
   f32x4 a1[4], a2[4], a3[1];
-  layer<IN, 4>(X, XS, net.W1, a1);
-  bias_tanh_store<4>(a1, net.b1, H1, HS);
+  layer<IN, 4>(X, XS, p.W1, a1);
+  bias_tanh_store<4>(a1, p.b1, H1, HS);
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_s_waitcnt(0);
-  layer<HID, 4>(H1, HS, net.W2, a2);
-  bias_tanh_store<4>(a2, net.b2, H2, HS);
+  layer<HID, 4>(H1, HS, p.W2, a2);
+  bias_tanh_store<4>(a2, p.b2, H2, HS);
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_s_waitcnt(0);
-  layer<HID, 1>(H2, HS, net.W3, a3);
-  const float b = net.b3[lane() & 15];
+  layer<HID, 1>(H2, HS, p.W3, a3);
+  const float b = p.b3[lane() & 15];
   y = a3[0] + f32x4{b, b, b, b};
+}
+__device__ inline void forward16(const Net& net, const bf16* X, bf16* H1, bf16* H2, f32x4& y) {
+  forward16(params_of(net), X, H1, H2, y);
 }
 
 }  // namespace mlp

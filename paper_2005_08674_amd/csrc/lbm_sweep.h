@@ -130,6 +130,7 @@ struct ClosureLds {
   __attribute__((aligned(16))) mlp::bf16 H1[SEG * mlp::HS];
   __attribute__((aligned(16))) mlp::bf16 H2[SEG * mlp::HS];
   float Y[SEG][4];
+  int gate[SEG];  // 1 where the correction may apply (eligible node, amplitude > 0 after the gate)
 };
 
 // One 64-node segment `b` of edge `edge` of lattice L, computed by a block of
@@ -290,37 +291,31 @@ __device__ inline void edge_segment_body(const LatDesc& L, int parity, int edge,
       }
       mlp::bf16* row = cl->X + tid * mlp::XS;
 #pragma unroll
-      for (int q = 0; q < mlp::IN; ++q) {
-        const float v = eligible ? (xin[q] - net.feat_mean[q]) * net.feat_inv_std[q] : 0.f;
-        row[q] = (mlp::bf16)v;
-      }
+      for (int q = 0; q < mlp::IN; ++q) row[q] = eligible ? normalised_input(net, q, xin[q]) : (mlp::bf16)0.f;
+      cl->gate[tid] = eligible && amp > 0.f;
     }
     __syncthreads();
     {
       const int w = tid >> 6;  // wavefront w runs rows 16 w .. 16 w + 15
-      mlp::f32x4 yv;
-      mlp::forward16(net, cl->X + 16 * w * mlp::XS, cl->H1 + 16 * w * mlp::HS, cl->H2 + 16 * w * mlp::HS, yv);
-      const int l = tid & 63, col = l & 15;
-      if (col < 3) {
+      // (a group with no row the correction may apply to skips the network: its outputs are unused)
+      int any = 0;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) cl->Y[16 * w + 4 * (l >> 4) + r][col] = yv[r];
+      for (int r = 0; r < 16; ++r) any |= cl->gate[16 * w + r];
+      if (any) {
+        mlp::f32x4 yv;
+        mlp::forward16(net, cl->X + 16 * w * mlp::XS, cl->H1 + 16 * w * mlp::HS, cl->H2 + 16 * w * mlp::HS, yv);
+        const int l = tid & 63, col = l & 15;
+        if (col < 3) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) cl->Y[16 * w + 4 * (l >> 4) + r][col] = yv[r];
+        }
       }
     }
     __syncthreads();
-    if (eligible && amp > 0.f) {
-      const float o0 = cl->Y[tid][0], o1 = cl->Y[tid][1], o2 = cl->Y[tid][2];
-      // NSBC stays when an output is not finite or leaves the trust bound
-      // (fmaxf would drop a NaN operand, so finiteness is tested first)
-      const bool finite = isfinite(o0) && isfinite(o1) && isfinite(o2);
-      if (finite && fmaxf(fabsf(o0), fmaxf(fabsf(o1), fabsf(o2))) <= net.trust) {
-        const float cr = amp * (o0 * net.out_scale[0]);
-        const float cn = amp * (o1 * net.out_scale[1]);
-        const float ct = amp * (o2 * net.out_scale[2]);
-        // back to the lattice frame: du = c_n n + c_t t, t = (-n_y, n_x)
-        mc.v[0] += R(cr);
-        mc.v[1] += R(cn * float(enx) - ct * float(eny));
-        mc.v[2] += R(cn * float(eny) + ct * float(enx));
-      }
+    float dl[3];
+    if (eligible && amp > 0.f && closure_delta(net, cl->Y[tid][0], cl->Y[tid][1], cl->Y[tid][2], amp, enx, eny, dl)) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) mc.v[c] += R(dl[c]);
     }
   }
   if (!owner) return;

@@ -9,6 +9,7 @@
 
 #include "lbm_device.h"
 #include "lbm_launch.h"
+#include "lbm_threestep.h"
 #include "lbm_twostep_lds.h"
 
 namespace lbm {
@@ -41,15 +42,6 @@ namespace lbm {
   X(12, 384, true, 2)    \
   X(24, 768, true, 2)    \
   X(20, 768, true, 2)
-
-// Register budget: the 32-bit arithmetic formats are held to 80 VGPRs, which
-// lets 6 waves share a SIMD (the LDS of the larger tiles allows no more); the
-// boundary-tile path would otherwise take a few more and cost every tile that
-// occupancy.
-template <int S>
-constexpr int two_step_waves() {
-  return S == ST_F64 ? 1 : 6;
-}
 
 template <int S, int TY, int NT, bool NTS, int CM, int MAP>
 __global__ __launch_bounds__(NT, two_step_waves<S>()) void k_two_step(LatDesc L, int parity, int tiles_x,
@@ -128,7 +120,8 @@ static hipError_t launch_two_s(const LatDesc& L, int parity, int id, hipStream_t
 }
 
 hipError_t launch_two_step(const LatDesc& L, int parity, int id, hipStream_t s) {
-  if (!two_step_supported(L)) return hipErrorInvalidValue;
+  // the two-step sweep has no closure path
+  if (!two_step_supported(L) || (L.closure && L.net)) return hipErrorInvalidValue;
   switch (L.store) {
     case ST_F64: return launch_two_s<ST_F64>(L, parity, id, s);
     case ST_F32: return launch_two_s<ST_F32>(L, parity, id, s);
@@ -139,34 +132,7 @@ hipError_t launch_two_step(const LatDesc& L, int parity, int id, hipStream_t s) 
 }
 
 // ------------------------------------------------------------------ three-step kernel
-// Candidate shapes of the three-step sweep (three_step_tile): output tile
-// 64 x TY, NT threads, non-temporal stores (NTS); tiles in XCD bands (as MAP
-// 2 above).  A shape whose two LDS levels exceed a workgroup's 160 KiB for a
-// storage format is not built for it (FP64 at TY >= 16).
-#define LBM_THREE_STEP(X) \
-  X(8, 512, true)         \
-  X(12, 512, true)        \
-  X(12, 768, true)        \
-  X(16, 512, true)        \
-  X(16, 768, true)        \
-  X(20, 768, true)
-
-template <int S, int TY>
-constexpr bool three_step_fits() {
-  return three_step_lds_bytes<S, TY>() <= 160 * 1024;
-}
-
-template <int S, int TY, int NT, bool NTS, int CM>
-__global__ __launch_bounds__(NT, two_step_waves<S>()) void k_three_step(LatDesc L, int parity, int tiles_x,
-                                                                      int tiles_y) {
-  const int b = blockIdx.x, ntiles = tiles_x * tiles_y;
-  const int per = (ntiles + 7) >> 3;
-  const int tile = (b & 7) * per + (b >> 3);
-  if (tile >= ntiles) return;  // padding blocks: the whole block leaves before any barrier
-  const int tyi = tile / tiles_x, txi = tile - tyi * tiles_x;
-  three_step_tile<S, TY, NT, NTS, CM>(L, parity, txi, tyi);
-}
-
+// (shapes and kernel in lbm_threestep.h)
 struct ThreeStepShape {
   int ty, nt;
   bool nts;
@@ -188,64 +154,43 @@ void three_step_name(int id, char* buf, size_t len) {
   snprintf(buf, len, "3step:64x%d/%d+xcdband%s", kThree[id].ty, kThree[id].nt, kThree[id].nts ? "+nts" : "");
 }
 
-static bool three_step_fits_store(int store, int id) {
-  int k = 0;
-#define X(a, b, c)                                                                                   \
-  if (id == k) {                                                                                     \
-    switch (store) {                                                                                 \
-      case ST_F64: return three_step_fits<ST_F64, a>();                                              \
-      case ST_F32: return three_step_fits<ST_F32, a>();                                              \
-      case ST_F16: return three_step_fits<ST_F16, a>();                                              \
-      case ST_BF16: return three_step_fits<ST_BF16, a>();                                            \
-    }                                                                                                \
-    return false;                                                                                    \
-  }                                                                                                  \
-  ++k;
-  LBM_THREE_STEP(X)
-#undef X
-  return false;
-}
-
 bool three_step_supported(const LatDesc& L, int id) {
   return id >= 0 && id < kNumThree && two_step_supported(L) && L.nx >= TL_TX && L.ny >= kThree[id].ty &&
-         three_step_fits_store(L.store, id);
+         three_step_fits_store(L.store, id, L.closure && L.net);
 }
 
-template <int S, int TY, int NT, bool NTS>
-static hipError_t launch_three_t(const LatDesc& L, int parity, hipStream_t s) {
-  if constexpr (!three_step_fits<S, TY>()) {
-    return hipErrorInvalidValue;
-  } else {
-    const int tiles_x = (L.nx + TL_TX - 1) / TL_TX, tiles_y = (L.ny + TY - 1) / TY;
-    const dim3 grid(((tiles_x * tiles_y + 7) >> 3) * 8);
-    if (L.coll == COLL_MRT)
-      k_three_step<S, TY, NT, NTS, COLL_MRT><<<grid, dim3(NT), 0, s>>>(L, parity, tiles_x, tiles_y);
-    else
-      k_three_step<S, TY, NT, NTS, COLL_BGK><<<grid, dim3(NT), 0, s>>>(L, parity, tiles_x, tiles_y);
-    return hipGetLastError();
-  }
-}
-
-template <int S>
-static hipError_t launch_three_s(const LatDesc& L, int parity, int id, hipStream_t s) {
-  int k = 0;
-#define X(a, b, c)                                                 \
-  if (id == k) return launch_three_t<S, a, b, c>(L, parity, s);   \
-  ++k;
-  LBM_THREE_STEP(X)
-#undef X
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_three_step(const LatDesc& L, int parity, int id, hipStream_t s) {
+// A lattice on the learned closure takes two launches: its edge tiles with
+// the network and its inner tiles with the plain sweep (both read buffer
+// `parity` and write disjoint parts of the other).  With a second stream
+// `side` the edge-tile kernel runs there, forked from `s` after the work
+// already on it (event `fork`) and joined back before what follows (event
+// `join`), so the two kernels share the GPU; without one they run in turn
+// on `s`.
+hipError_t launch_three_step(const LatDesc& L, int parity, int id, hipStream_t s, hipStream_t side, hipEvent_t fork,
+                             hipEvent_t join) {
   if (!three_step_supported(L, id)) return hipErrorInvalidValue;
-  switch (L.store) {
-    case ST_F64: return launch_three_s<ST_F64>(L, parity, id, s);
-    case ST_F32: return launch_three_s<ST_F32>(L, parity, id, s);
-    case ST_F16: return launch_three_s<ST_F16>(L, parity, id, s);
-    case ST_BF16: return launch_three_s<ST_BF16>(L, parity, id, s);
+  int part = 0;
+  const bool forked = L.closure && L.net && side && fork && join;
+  if (L.closure && L.net) {
+    hipError_t e = hipSuccess;
+    if (forked) {
+      e = hipEventRecord(fork, s);
+      if (e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
+    }
+    if (e == hipSuccess) e = launch_three_step_closure(L, parity, id, forked ? side : s);
+    if (forked && e == hipSuccess) e = hipEventRecord(join, side);
+    if (e != hipSuccess) return e;
+    part = 1;
   }
-  return hipErrorInvalidValue;
+  hipError_t e = hipErrorInvalidValue;
+  switch (L.store) {
+    case ST_F64: e = launch_three_s<ST_F64, false>(L, parity, id, s, part); break;
+    case ST_F32: e = launch_three_s<ST_F32, false>(L, parity, id, s, part); break;
+    case ST_F16: e = launch_three_s<ST_F16, false>(L, parity, id, s, part); break;
+    case ST_BF16: e = launch_three_s<ST_BF16, false>(L, parity, id, s, part); break;
+  }
+  if (forked && e == hipSuccess) e = hipStreamWaitEvent(s, join, 0);
+  return e;
 }
 
 // ------------------------------------------------------------------ ensemble

@@ -52,14 +52,12 @@ __device__ inline uint32_t tl_unknown(int x, int y, int nx, int ny) {
   return u;
 }
 
-// NSBC of boundary node (x, y): unknown populations already zeroed and
-// flagged in `unknown`; `mom(xx, yy, m)` returns the previous level's moments
-// of any lattice node.  Same order as the edge kernel: the x normal first
-// (the vertical edges own the corners), then the y normal (eqs. nes_2,
-// nes_3), then assignment and correction (eqs. nes_0, nes_1, nes_4).
+// NSBC's vector m_c of boundary node (x, y) (eqs. nes_2, nes_3); `mom(xx,
+// yy, m)` returns the previous level's moments of any lattice node.  Same
+// order as the edge kernel: the x normal first (the vertical edges own the
+// corners), then the y normal.
 template <class R, class MomFn>
-__device__ inline void tl_nsbc(const LatDesc& Ld, R g[9], uint32_t unknown, int x, int y, R rho0, const Base<R>& b,
-                               MomFn mom) {
+__device__ inline M3<R> tl_predict(const LatDesc& Ld, int x, int y, const Base<R>& b, MomFn mom) {
   const int nx = Ld.nx, ny = Ld.ny;
   const bool onL = x == 0, onR = x == nx - 1, onB = y == 0, onT = y == ny - 1;
   R mb[3];
@@ -93,6 +91,16 @@ __device__ inline void tl_nsbc(const LatDesc& Ld, R g[9], uint32_t unknown, int 
     const R mp = mb[c] - fac * dsum[c];
     mc.v[c] = (R(1) - beta) * mp + beta * R(Ld.m0[c]);
   }
+  return mc;
+}
+
+// NSBC of boundary node (x, y): unknown populations already zeroed and
+// flagged in `unknown`; m_c as tl_predict, then assignment and correction
+// (eqs. nes_0, nes_1, nes_4).
+template <class R, class MomFn>
+__device__ inline void tl_nsbc(const LatDesc& Ld, R g[9], uint32_t unknown, int x, int y, R rho0, const Base<R>& b,
+                               MomFn mom) {
+  const M3<R> mc = tl_predict<R>(Ld, x, y, b, mom);
   nsbc_assign_correct<R>(g, unknown, mc, rho0, b, Ld.corr_mode);
 }
 
@@ -274,13 +282,219 @@ constexpr int three_step_lds_bytes() {
   return 9 * ((TY + 4) * T3_W1 + (TY + 2) * T3_W2) * (int)sizeof(typename Codec<S>::T);
 }
 
-template <int S, int TY, int NT, bool NTS, int CM>
-__device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, int tyi) {
+// LDS of the closure phases of an edge tile (CL), one edge segment at a
+// time: the segment's strip features [3][CL_STRIP][9] (fp32), then per
+// network wave its 16 input rows [16][XS] (reused for the second hidden
+// layer) and first hidden layer [16][HS] (bf16).  They reuse a level array
+// not in use at the time when at least two waves' worth fits in the
+// smaller one, else take LDS of their own; the outputs and amplitudes of a
+// level's edge nodes, [edge nodes][4] fp32, have LDS of their own.
+constexpr int CL_STRIP = TL_TX + 6;  // a segment's nodes plus one beyond each end, at most
+constexpr int CL_FEAT_BYTES = (3 * CL_STRIP * NODE_FEAT * 4 + 15) / 16 * 16;
+constexpr int CL_WAVE_BYTES = 16 * (mlp::XS + mlp::HS) * 2;
+
+template <int S, int TY, int NT>
+constexpr int cl_fit_waves() {
+  constexpr int w = (9 * (TY + 2) * T3_W2 * (int)sizeof(typename Codec<S>::T) - CL_FEAT_BYTES) / CL_WAVE_BYTES;
+  return w < 0 ? 0 : (w > 4 ? 4 : (w > NT / 64 ? NT / 64 : w));
+}
+template <int S, int TY, int NT>
+constexpr bool cl_own_lds() {
+  return cl_fit_waves<S, TY, NT>() < 2;
+}
+template <int S, int TY, int NT>
+constexpr int cl_waves() {
+  return cl_own_lds<S, TY, NT>() ? (NT / 64 < 4 ? NT / 64 : 4) : cl_fit_waves<S, TY, NT>();
+}
+// lattice-edge nodes of a level's region, at most (both columns and both rows of level t + 1's)
+template <int TY>
+constexpr int cl_max_edge() {
+  return 2 * (TY + 4) + 2 * T3_W1;
+}
+// (plus the network's biases and input normalisation, staged once per tile)
+template <int S, int TY, int NT, bool CL>
+constexpr int three_step_cl_lds_bytes() {
+  return !CL ? 0
+             : cl_max_edge<TY>() * 16 + mlp::PARAM_BYTES +
+                   (cl_own_lds<S, TY, NT>() ? CL_FEAT_BYTES + cl_waves<S, TY, NT>() * CL_WAVE_BYTES : 0);
+}
+
+// Lattice-edge node region of a level (rows ry0 .. ry0 + rh - 1, columns
+// rx0 .. rx0 + rw - 1, clipped to the lattice): bounds and the counts of
+// column nodes (x = 0 and x = nx - 1) and of the remaining row nodes.
+__device__ inline void tl_edge_count(int nx, int ny, int rx0, int ry0, int rw, int rh, int& xl, int& xh, int& yl,
+                                     int& yh, int& ncol, int& nrow) {
+  xl = max(rx0, 0);
+  xh = min(rx0 + rw - 1, nx - 1);
+  yl = max(ry0, 0);
+  yh = min(ry0 + rh - 1, ny - 1);
+  const int left = xl == 0, right = xh == nx - 1;
+  ncol = (left + right) * (yh - yl + 1);        // nodes of the x = 0 and x = nx - 1 columns
+  const int cx0 = xl + left, cx1 = xh - right;  // row nodes not already in those columns
+  nrow = ((yl == 0) + (yh == ny - 1)) * max(0, cx1 - cx0 + 1);
+}
+
+// The learned closure for one level of a multi-step edge tile: the
+// network's correction of m_c for every lattice-edge node of the level's
+// region with a single normal, from the previous level (the edge kernel's
+// closure applied per level: same inputs, same arithmetic).  The previous
+// level's population i of node (x, y) is prev[i ps_i + (y - oy) ps_y + (x -
+// ox)] (the state in HBM, or a level array in LDS).  One edge segment of the
+// region at a time (left column, right column, bottom row, top row, numbered
+// as the edge pass numbers its nodes): the strip features of the segment
+// (depth 0..2 along the inward normal, one node beyond each end) into LDS,
+// then waves 0..CLW-1 each build the input rows of 16 nodes and run the
+// network on them.  Outputs land in cl_y[4 e + 0..2] and the amplitude (0:
+// NSBC's m_c stays) in cl_y[4 e + 3] for edge node e.  Called by the whole
+// block.  An edge tile runs this code once per level and tile, not in a hot
+// loop, so it is kept compact (one copy for the three levels, loops rolled):
+// its instructions come from L2 on every tile, and their count, not the
+// arithmetic, sets its time.
+template <int S, int CLW>
+__device__ inline __attribute__((always_inline)) void closure_level(const LatDesc& Ld, int rx0, int ry0, int rw, int rh,
+                                           const typename Codec<S>::T* prev, int64_t ps_i, int ps_y, int ox, int oy,
+                                           char* scr, float* cl_y, int nt, const mlp::Params& par) {
+  using C = Codec<S>;
+  using R = typename C::R;
+  const int nx = Ld.nx, ny = Ld.ny;
+  const int tid = threadIdx.x;
+  const mlp::Net& net = *static_cast<const mlp::Net*>(Ld.net);
+  const Base<R> b(Ld);
+  const R rho0 = R(Ld.rho0);
+  const R ref[3] = {R(Ld.m0[0]), R(Ld.m0[1]), R(Ld.m0[2])};
+  const float rho0f = float(Ld.rho0), omegaf = float(Ld.omega);
+  auto pops = [&](int x, int y, R g[9]) {
+    const int64_t idx = (int64_t)(y - oy) * ps_y + (x - ox);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) g[i] = C::dec(prev[i * ps_i + idx], Ld.ds[i]);
+  };
+  int xl, xh, yl, yh, ncol, nrow;
+  tl_edge_count(nx, ny, rx0, ry0, rw, rh, xl, xh, yl, yh, ncol, nrow);
+  const int left = xl == 0, right = xh == nx - 1, hcol = yh - yl + 1;
+  const int cx0 = xl + left, cw = max(0, (xh - right) - cx0 + 1);
+  float* feat = reinterpret_cast<float*>(scr);
+  const int w = tid >> 6, l = tid & 63;
+  mlp::bf16* X = reinterpret_cast<mlp::bf16*>(scr + CL_FEAT_BYTES + w * CL_WAVE_BYTES);
+  mlp::bf16* H1 = X + 16 * mlp::XS;
+  for (int sg = 0; sg < 4; ++sg) {
+    // segment sg: left column, right column, bottom row, top row
+    const bool vert = sg < 2;
+    const bool present = sg == 0 ? left : (sg == 1 ? right : (sg == 2 ? yl == 0 && cw > 0 : yh == ny - 1 && cw > 0));
+    if (!present) continue;
+    const int base_e = sg == 0 ? 0 : (sg == 1 ? left * hcol : (sg == 2 ? ncol : ncol + (yl == 0) * cw));
+    const int len = vert ? hcol : cw, ta = vert ? yl : cx0, ntan = vert ? ny : nx;
+    const int enx = sg == 0 ? -1 : (sg == 1 ? 1 : 0), eny = sg == 2 ? -1 : (sg == 3 ? 1 : 0);
+    // node of the segment's strip at depth d and tangential coordinate tc
+    auto strip_xy = [&](int d, int tc, int& x, int& y) {
+      x = vert ? (enx < 0 ? d : nx - 1 - d) : tc;
+      y = vert ? tc : (eny < 0 ? d : ny - 1 - d);
+    };
+    // strip features: feat[(d CL_STRIP + j) 9 + q] at tangential coordinate ta - 1 + j
+    for (int i = tid; i < 3 * (len + 2); i += nt) {
+      const int d = i / (len + 2), j = i - d * (len + 2), tc = ta - 1 + j;
+      if (tc < 0 || tc >= ntan) continue;
+      int x, y;
+      strip_xy(d, tc, x, y);
+      R g[9];
+      pops(x, y, g);
+      float f[NODE_FEAT];
+      strip_node_features<R>(g, rho0, b, ref, enx, eny, f);
+#pragma unroll
+      for (int q = 0; q < NODE_FEAT; ++q) feat[(d * CL_STRIP + j) * NODE_FEAT + q] = f[q];
+    }
+    __syncthreads();
+    if (w < CLW) {
+      // lane l: node r = l % 16 of the group and inputs q = 4 qq + c of its row (c = l / 16), so
+      // that every lane takes the same path through the row; the node's amplitude and m_c are
+      // formed by each of its four lanes
+      const int r = l & 15, c = l >> 4;
+      // the tangent t = (-n_y, n_x) runs along increasing tc on the right and bottom edges
+      const int tsign = (sg == 1 || sg == 2) ? 1 : -1;
+      for (int g0 = 16 * w; g0 < len; g0 += 16 * CLW) {
+        const int i = g0 + r, tc = ta + i;
+        const bool valid = i < len;
+        const bool eligible = valid && (!vert || (tc >= 1 && tc <= ny - 2));
+        const int ic = min(i, len - 1);  // a strip position inside the segment for idle lanes
+        // unscaled features of strip node j = 3 d + k + 1, s(d, k) = b - d n + k t
+        auto fv = [&](int jj, int q) {
+          const int d = jj / 3, k = jj - 3 * d - 1;
+          return feat[(d * CL_STRIP + ic + 1 + tsign * k) * NODE_FEAT + q];
+        };
+        // amplitude and regime gate first: a group without a gated node keeps NSBC's m_c for all
+        // of its nodes (amplitude 0) and skips the network
+        float A = 0.f, inv = 0.f;
+        bool gated = false;
+        if (eligible) {
+          A = strip_amplitude(fv, rho0f);
+          inv = amplitude_inverse(A);
+          auto scaled = [&](int jj, int q) { return fv(jj, q) * inv; };
+          gated = vortical_row(scaled, rho0f, net.kmin);
+        }
+        if (c == 0 && valid) cl_y[4 * (base_e + i) + 3] = gated ? A : 0.f;
+        if (__ballot(gated) == 0) continue;              // wave-uniform
+        float dmc[3] = {0.f, 0.f, 0.f}, refn[3] = {0.f, 0.f, 0.f};
+        if (eligible) {
+          // inputs 82..86: m_c - m0 and m0 in the edge frame
+          int x, y;
+          strip_xy(0, tc, x, y);
+          auto mom = [&](int xx, int yy, R m[3]) {
+            R q[9];
+            pops(xx, yy, q);
+            moments<R>(q, rho0, b, m[0], m[1], m[2]);
+          };
+          const M3<R> mc = tl_predict<R>(Ld, x, y, b, mom);
+          normal_frame_diff<R>(mc.v, ref, enx, eny, dmc);
+          to_normal_frame<R>(ref, b, enx, eny, refn);
+        }
+        mlp::bf16* row = X + r * mlp::XS;
+#pragma unroll 4
+        for (int qq = 0; qq < mlp::IN / 4; ++qq) {
+          const int q = 4 * qq + c;
+          // input_value(q, ...) with the choice made by selects
+          const int qs = min(q, F_STRIP - 1);
+          const float strip = fv(qs / NODE_FEAT, qs % NODE_FEAT) * inv;
+          const int m = min(max(q - F_MC, 0), 2), u = min(max(q - F_UREF, 0), 1);
+          const float dm = (m == 0 ? dmc[0] : (m == 1 ? dmc[1] : dmc[2])) * inv;
+          const float ur = u == 0 ? refn[1] : refn[2];
+          const float v = q < F_STRIP ? strip : (q == F_OMEGA ? omegaf : (q < F_UREF ? dm : (q < mlp::NFEAT ? ur : 0.f)));
+          row[q] = eligible ? normalised_input(par.mean, par.inv_std, q, v) : (mlp::bf16)0.f;
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_s_waitcnt(0);
+        mlp::f32x4 yv;
+        mlp::forward16(par, X, H1, X, yv);
+        const int col = l & 15;
+        if (col < 3) {
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            const int node = g0 + 4 * (l >> 4) + rr;
+            if (node < len) cl_y[4 * (base_e + node) + col] = yv[rr];
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_s_waitcnt(0);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// `part` selects the tiles a launch updates: 0 every tile, 1 the inner tiles
+// only, 2 the edge tiles only (a tile of the other kind returns before any
+// barrier); a lattice on the learned closure runs its edge tiles with CL in
+// one launch and its inner tiles without in another.
+template <int S, int TY, int NT, bool NTS, int CM, bool CL = false>
+__device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, int tyi, int part = 0) {
   using C = Codec<S>;
   using T = typename C::T;
   using R = typename C::R;
-  __shared__ T lds1[9][TY + 4][T3_W1];
-  __shared__ T lds2[9][TY + 2][T3_W2];
+  __shared__ __attribute__((aligned(16))) T lds1[9][TY + 4][T3_W1];
+  __shared__ __attribute__((aligned(16))) T lds2[9][TY + 2][T3_W2];
+  constexpr int CLW = cl_waves<S, TY, NT>();
+  constexpr bool CL_OWN = CL && cl_own_lds<S, TY, NT>();
+  __shared__ __attribute__((aligned(16))) char cl_own[CL_OWN ? CL_FEAT_BYTES + CLW * CL_WAVE_BYTES : 16];
+  __shared__ float cl_y[CL ? cl_max_edge<TY>() : 1][4];
+  __shared__ __attribute__((aligned(16))) char cl_par[CL ? mlp::PARAM_BYTES : 16];
 
   const int nx = Ld.nx, ny = Ld.ny;
   const int x0 = min(txi * TL_TX, nx - TL_TX), y0 = min(tyi * TY, ny - TY);
@@ -295,6 +509,7 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
   // Inner tile: every level t + 1 node and its pull sources lie inside the
   // lattice and away from its edges: no clamps, no NSBC.
   const bool inner = x0 >= 3 && x0 + TL_TX + 3 <= nx && y0 >= 3 && y0 + TY + 3 <= ny;
+  if ((part == 1 && !inner) || (part == 2 && inner)) return;
   auto interior_node = [&](int x, int y) { return x >= 1 && x <= nx - 2 && y >= 1 && y <= ny - 2; };
 
   // One sweep per level over the level's whole region, its iterations
@@ -409,14 +624,7 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
   const Base<R>& b = base;
   // region of a level: lattice rows ry0 .. ry0 + rh - 1, columns rx0 .. rx0 + rw - 1
   auto edge_count = [&](int rx0, int ry0, int rw, int rh, int& xl, int& xh, int& yl, int& yh, int& ncol, int& nrow) {
-    xl = max(rx0, 0);
-    xh = min(rx0 + rw - 1, nx - 1);
-    yl = max(ry0, 0);
-    yh = min(ry0 + rh - 1, ny - 1);
-    const int left = xl == 0, right = xh == nx - 1;
-    ncol = (left + right) * (yh - yl + 1);                    // nodes of the x = 0 and x = nx - 1 columns
-    const int cx0 = xl + left, cx1 = xh - right;              // row nodes not already in those columns
-    nrow = ((yl == 0) + (yh == ny - 1)) * max(0, cx1 - cx0 + 1);
+    tl_edge_count(nx, ny, rx0, ry0, rw, rh, xl, xh, yl, yh, ncol, nrow);
   };
   // lattice-edge node number e of a region (left column, right column, then bottom row, top row)
   auto edge_node = [&](int e, int xl, int xh, int yl, int yh, int ncol, int& x, int& y) {
@@ -437,7 +645,39 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
   // edge-pass lane of this thread for a sweep over N nodes
   auto edge_lane = [&](int N) { return (tid + NT - light_waves_start(N, NT)) % NT; };
 
+  // m_c of edge node e at (x, y), with the closure's correction (CL)
+  auto edge_mc = [&](int e, int x, int y, auto mom) __attribute__((always_inline)) {
+    M3<R> mc = tl_predict<R>(Ld, x, y, b, mom);
+    if constexpr (CL) {
+      const float amp = cl_y[e][3];
+      float dl[3];
+      const int enx = x == 0 ? -1 : (x == nx - 1 ? 1 : 0), eny = y == 0 ? -1 : (y == ny - 1 ? 1 : 0);
+      if (amp > 0.f &&
+          closure_delta(*static_cast<const mlp::Net*>(Ld.net), cl_y[e][0], cl_y[e][1], cl_y[e][2], amp, enx, eny, dl)) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) mc.v[c] += R(dl[c]);
+      }
+    }
+    return mc;
+  };
+  // the network's parameters in LDS (CL; read after the first closure phase's barrier)
+  mlp::Params par{};
+  if constexpr (CL) par = mlp::stage_params(*static_cast<const mlp::Net*>(Ld.net), cl_par, tid, NT);
+  // the closure phases of a level (CL): region, previous level (base,
+  // strides, origin) and scratch (the level arrays not in use, or LDS of
+  // their own)
+  auto closure = [&](int rx0, int ry0, int rw, int rh, const T* prev, int64_t ps_i, int ps_y, int ox, int oy,
+                     int level) __attribute__((always_inline)) {
+    if constexpr (CL) {
+      char* scr = CL_OWN ? cl_own
+                         : (level == 3 ? reinterpret_cast<char*>(&lds1[0][0][0]) : reinterpret_cast<char*>(&lds2[0][0][0]));
+      closure_level<S, CLW>(Ld, rx0, ry0, rw, rh, prev, ps_i, ps_y, ox, oy, scr, &cl_y[0][0], NT, par);
+    }
+  };
+
   // ---- level t + 1 from HBM
+  auto mom0 = [&](int xx, int yy, R m[3]) { tl_moments_global<S>(Ld, A, xx, yy, b, m); };
+  closure(x0 - 2, y0 - 2, T3_W1, TY + 4, A, plane, pitch, 0, 0, 1);
   level1(b, std::true_type{});
   {
     int xl, xh, yl, yh, ncol, nrow;
@@ -457,8 +697,7 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
         const R v = C::dec(Ai[srow[1 + kCy[i]] + (uint32_t)sxs[1 + kCx[i]]], Ld.ds[i]);
         g[i] = (unknown >> i) & 1u ? R(0) : v;
       }
-      auto mom = [&](int xx, int yy, R m[3]) { tl_moments_global<S>(Ld, A, xx, yy, b, m); };
-      tl_nsbc<R>(Ld, g, unknown, x, y, rho0, b, mom);
+      nsbc_assign_correct<R>(g, unknown, edge_mc(e, x, y, mom0), rho0, b, Ld.corr_mode);
       collide<R, CM>(Ld, g, rho0, b, omega);
 #pragma unroll
       for (int i = 0; i < 9; ++i) lds1[i][y - y0 + 2][x - x0 + 2] = C::enc(g[i], Ld.es[i]);
@@ -467,15 +706,19 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
   __syncthreads();
 
   // ---- level t + 2 from lds1 (lattice node (x, y) at lds1[.][y - y0 + 2][x - x0 + 2])
-  level2(b, std::true_type{});
   {
-    auto mom1 = [&](int xx, int yy, R m[3]) {
-      R q[9];
+    auto pops1 = [&](int xx, int yy, R q[9]) {
       const int lx = xx - x0 + 2, ly = yy - y0 + 2;
 #pragma unroll
       for (int i = 0; i < 9; ++i) q[i] = C::dec(lds1[i][ly][lx], Ld.ds[i]);
+    };
+    auto mom1 = [&](int xx, int yy, R m[3]) {
+      R q[9];
+      pops1(xx, yy, q);
       moments<R>(q, rho0, b, m[0], m[1], m[2]);
     };
+    closure(x0 - 1, y0 - 1, T3_W2, TY + 2, &lds1[0][0][0], (TY + 4) * T3_W1, T3_W1, x0 - 2, y0 - 2, 2);
+    level2(b, std::true_type{});
     int xl, xh, yl, yh, ncol, nrow;
     edge_count(x0 - 1, y0 - 1, T3_W2, TY + 2, xl, xh, yl, yh, ncol, nrow);
     for (int e = edge_lane((TY + 2) * T3_W2); e < ncol + nrow; e += NT) {
@@ -490,7 +733,7 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
         const R v = C::dec(lds1[i][lys[1 + kCy[i]]][lxs[1 + kCx[i]]], Ld.ds[i]);
         g[i] = (unknown >> i) & 1u ? R(0) : v;
       }
-      tl_nsbc<R>(Ld, g, unknown, x, y, rho0, b, mom1);
+      nsbc_assign_correct<R>(g, unknown, edge_mc(e, x, y, mom1), rho0, b, Ld.corr_mode);
       collide<R, CM>(Ld, g, rho0, b, omega);
 #pragma unroll
       for (int i = 0; i < 9; ++i) lds2[i][y - y0 + 1][x - x0 + 1] = C::enc(g[i], Ld.es[i]);
@@ -499,15 +742,19 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
   __syncthreads();
 
   // ---- level t + 3 on the tile from lds2 (lattice node (x, y) at lds2[.][y - y0 + 1][x - x0 + 1])
-  level3(b, std::true_type{});
   {
-    auto mom2 = [&](int xx, int yy, R m[3]) {
-      R q[9];
+    auto pops2 = [&](int xx, int yy, R q[9]) {
       const int lx = xx - x0 + 1, ly = yy - y0 + 1;
 #pragma unroll
       for (int i = 0; i < 9; ++i) q[i] = C::dec(lds2[i][ly][lx], Ld.ds[i]);
+    };
+    auto mom2 = [&](int xx, int yy, R m[3]) {
+      R q[9];
+      pops2(xx, yy, q);
       moments<R>(q, rho0, b, m[0], m[1], m[2]);
     };
+    closure(x0, y0, TL_TX, TY, &lds2[0][0][0], (TY + 2) * T3_W2, T3_W2, x0 - 1, y0 - 1, 3);
+    level3(b, std::true_type{});
     int xl, xh, yl, yh, ncol, nrow;
     edge_count(x0, y0, TL_TX, TY, xl, xh, yl, yh, ncol, nrow);
     for (int e = edge_lane(TY * TL_TX); e < ncol + nrow; e += NT) {
@@ -522,7 +769,7 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
         const R v = C::dec(lds2[i][lys[1 + kCy[i]]][lxs[1 + kCx[i]]], Ld.ds[i]);
         g[i] = (unknown >> i) & 1u ? R(0) : v;
       }
-      tl_nsbc<R>(Ld, g, unknown, x, y, rho0, b, mom2);
+      nsbc_assign_correct<R>(g, unknown, edge_mc(e, x, y, mom2), rho0, b, Ld.corr_mode);
       collide<R, CM>(Ld, g, rho0, b, omega);
       store(x, y, g);
     }

@@ -478,3 +478,86 @@ def test_regime_gate_selects_vortical_nodes():
     print(f"\n[regime gate kmin={kmin}] corrected {n_on} vortical nodes, left {n_off} acoustic nodes on NSBC",
           flush=True)
     assert n_on > 10 and n_off > 10
+
+
+THREE_STEP_STORES = ["f64", "f32", "f16", "bf16"]
+
+
+@pytest.mark.parametrize("store", THREE_STEP_STORES)
+def test_closure_in_three_step_sweep_is_bit_identical(store):
+    """The three-step sweep with the closure in its edge tiles gives the bits of closure single steps,
+    for every three-step shape the lattice takes, on lattices one tile wide (both columns in a tile),
+    ragged in both directions and with u_b != 0; a remainder of two steps runs as closure single
+    steps.  The network (random weights, every single-normal edge node accepted) changes the result."""
+    from paper_2005_08674_amd import lbm
+    from paper_2005_08674_amd.lattice import Lattice
+    p = _oracle_params(47)
+    tr = _trainer(p)
+    tr.set_normalization(np.zeros(96, np.float32), np.full(96, 0.5, np.float32), np.full(3, 0.02, np.float32))
+    blob = tr.export(50.0, 1.0, 0.0)
+    names = [lbm.lbm_two_step_describe(i) for i in range(lbm.lbm_two_step_count())]
+    three = [i for i, n in enumerate(names) if n.startswith("3step")]
+    cases = [(64, 40, (0.04, 0.01)), (131, 77, (0.0, 0.0)), (200, 150, (-0.03, 0.05))]
+    for nx, ny, u0 in cases:
+        # a vortex on the right edge and a pulse at the bottom-left corner: disturbed edges from t = 0
+        dv, ux, uy = W.lamb_oseen(nx, ny, nx - 6.0, ny * 0.45, 5.0, 0.03, u0)
+        dp, _, _ = W.gaussian_pulses(nx, ny, [(1e-3, 6.0, 5.0, 4.0)])
+        f = (dv + dp, ux, uy)
+        kw = dict(store=store, m0=(1.0, u0[0], u0[1]), ubase=u0, beta=0.1)
+        ref = Lattice(nx, ny, 0.58, f, **kw)
+        lbm.lbm_set_closure(ref.ctx, blob.data_ptr(), 1)
+        ref.step(11)
+        want = ref.populations().cpu().numpy()
+        plain = Lattice(nx, ny, 0.58, f, **kw)
+        plain.step(11)
+        assert not np.array_equal(want, plain.populations().cpu().numpy())
+        plain.close()
+        ran = 0
+        for sid in three:
+            g = Lattice(nx, ny, 0.58, f, **kw)
+            lbm.lbm_set_closure(g.ctx, blob.data_ptr(), 1)
+            try:
+                lbm.lbm_set_two_step(g.ctx, sid)
+            except lbm.LbmError:
+                g.close()
+                continue
+            lbm.lbm_enable_timing(g.ctx, True)
+            g.step(11)
+            ms, launches = lbm.lbm_two_step_times(g.ctx)
+            got = g.populations().cpu().numpy()
+            g.close()
+            # every shape the lattice takes also fits the closure's LDS (the two levels, the edge
+            # nodes' outputs, the staged biases and normalisation, the phases' scratch)
+            assert launches == 3, (names[sid], launches)
+            ran += 1
+            assert np.array_equal(got, want), (nx, ny, names[sid])
+        ref.close()
+        assert ran > 0
+
+
+def test_closure_three_step_autotune_and_trained_network():
+    """With the committed network: the two-step shapes are refused for closure lattices by the tuner
+    (negative time), a three-step shape is chosen, and 2048 x 64 steps agree bit for bit with closure
+    single steps."""
+    import os
+    from paper_2005_08674_amd import lbm
+    from paper_2005_08674_amd.closure import Trainer
+    from paper_2005_08674_amd.lattice import Lattice
+    path = os.path.join(os.path.dirname(__file__), "..", "paper_2005_08674_amd", "data", "closure_c4.npz")
+    blob = Trainer.load(path).export()
+    nx, ny, u0 = 2048, 64, (0.1, 0.0)
+    f = W.lamb_oseen(nx, ny, 2030.0, 30.0, 8.0, 0.02, u0)
+    kw = dict(store="f32", m0=(1.0, 0.1, 0.0), ubase=u0)
+    a = Lattice(nx, ny, 0.55, f, **kw)
+    b = Lattice(nx, ny, 0.55, f, **kw)
+    for g in (a, b):
+        lbm.lbm_set_closure(g.ctx, blob.data_ptr(), 1)
+    best, t = lbm.lbm_autotune_two_step(b.ctx, 2)
+    names = [lbm.lbm_two_step_describe(i) for i in range(lbm.lbm_two_step_count())]
+    assert names[best].startswith("3step")
+    assert all(t[i] < 0 for i, n in enumerate(names) if n.startswith("2step"))
+    a.step(30)
+    b.step(30)
+    assert np.array_equal(a.populations().cpu().numpy(), b.populations().cpu().numpy())
+    a.close()
+    b.close()
