@@ -248,8 +248,9 @@ int lbm_energy_noalloc(lbm_ctx* test, const lbm_ctx* ref, int32_t x_off, int32_t
  * shapes; lbm_tile_describe writes a short text name of candidate `id` into
  * buf; lbm_set_tile selects one for this context (the default is chosen from
  * the lattice and storage).  lbm_autotune times every candidate on the
- * context's own lattice as the launch lbm_step uses (the fused step launch,
- * or the bulk kernel when fusion is off), `reps` timed launches each, median
+ * context's own lattice as lbm_step launches it (the fused step launch, or,
+ * with the closure or fusion off, the bulk kernel followed by the edge
+ * kernel: whole steps either way), `reps` timed steps each, median
  * of those, after one warm-up, and selects the fastest.  The launches are
  * consecutive steps, as stepping runs them (a launch repeated on one
  * unchanged buffer can be served from the GPU's last-level cache, 256 MB on
@@ -257,7 +258,7 @@ int lbm_energy_noalloc(lbm_ctx* test, const lbm_ctx* ref, int32_t x_off, int32_t
  * temporary device copy (one buffer's size, allocated and freed here) and
  * restored afterwards, so it and t are left unchanged.  It writes the chosen
  * id to *best and, if times_ms is not NULL,
- * the per-candidate median launch time in milliseconds (length
+ * the per-candidate median step time in milliseconds (length
  * lbm_tile_count).  Synchronizes the stream. */
 int lbm_tile_count(void);
 int lbm_tile_describe(int32_t id, char* buf, size_t len);

@@ -802,16 +802,18 @@ struct StateSnapshot {
 int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* best, float* times_ms) {
   if (!c || !best) return fail(LBM_ERR_ARG, "NULL argument");
   if (reps < 1 || reps > 1000) return fail(LBM_ERR_ARG, "reps = %d outside [1, 1000]", reps);
-  // The kernel timed is the one lbm_step launches: the fused step (edge
-  // segments + bulk tiles) or, without fusion, the bulk kernel, over
-  // consecutive steps from a saved state.
+  // The launches timed are those of an lbm_step: the fused step (edge
+  // segments + bulk tiles) or, without fusion (the closure, or fusion off),
+  // the bulk kernel and then the edge kernel, over consecutive steps from a
+  // saved state; the candidates differ in the bulk tile only, and their
+  // times are those of whole steps, comparable with the multi-step shapes'.
   const bool fused = use_fused(c);
   StateSnapshot snap;
   if (int rc = snap.save(c)) return rc;
   int par = c->parity;
   auto launch = [&](int id) {
-    const hipError_t e =
-        fused ? lbm::launch_step(c->L, par, id, c->stream) : lbm::launch_bulk(c->L, par, id, c->stream);
+    hipError_t e = fused ? lbm::launch_step(c->L, par, id, c->stream) : lbm::launch_bulk(c->L, par, id, c->stream);
+    if (!fused && e == hipSuccess) e = lbm::launch_edge(c->L, par, c->stream);
     par ^= 1;
     return e;
   };
