@@ -250,9 +250,9 @@ int lbm_energy_noalloc(lbm_ctx* test, const lbm_ctx* ref, int32_t x_off, int32_t
  * the lattice and storage).  lbm_autotune times every candidate on the
  * context's own lattice as lbm_step launches it (the fused step launch, or,
  * with the closure or fusion off, the bulk kernel followed by the edge
- * kernel: whole steps either way), `reps` timed steps each, median
- * of those, after one warm-up, and selects the fastest.  The launches are
- * consecutive steps, as stepping runs them (a launch repeated on one
+ * kernel: whole steps either way), `reps` timed runs of 24 consecutive
+ * steps each, median of those, after one warm-up, and selects the fastest.
+ * The launches are consecutive steps, as stepping runs them (a launch repeated on one
  * unchanged buffer can be served from the GPU's last-level cache, 256 MB on
  * MI355X, where two buffers would not fit): the state is saved to a
  * temporary device copy (one buffer's size, allocated and freed here) and
@@ -323,10 +323,11 @@ int lbm_set_fused(lbm_ctx* ctx, int on);
  * two-step shapes and remainders then run as closure single steps.  The
  * overlap option and periodic edges always use the single-step kernels.
  * lbm_autotune_two_step times every shape the lattice supports (`reps`
- * consecutive launches each, median, from a saved and restored state as
- * lbm_autotune does; the state is left unchanged), selects the one with
+ * runs of consecutive launches covering at least 24 steps each, median,
+ * from a saved and restored state as lbm_autotune does; the state is left
+ * unchanged), selects the one with
  * the least time per step, writes its id to *best and, if times_ms is not
- * NULL, per shape the median launch time divided by its steps per launch
+ * NULL, per shape the median run time divided by its steps
  * (ms per step; -1 for shapes the lattice cannot take).  Synchronizes the
  * stream.  lbm_two_step_times returns the summed elapsed milliseconds and
  * the count of multi-step launches timed while lbm_enable_timing is on, and

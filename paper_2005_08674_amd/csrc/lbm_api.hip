@@ -776,6 +776,11 @@ namespace {
 // run of consecutive steps sees.  The current buffer is saved to a temporary
 // device copy first and restored at the end, so tuning leaves the state (and
 // t) as it was.
+// Steps in one timed run of a tuner candidate (consecutive launches): short
+// runs of a lattice whose state partly fits in the last-level cache rank
+// shapes differently from long ones.
+constexpr int kTuneRunSteps = 24;
+
 struct StateSnapshot {
   lbm_ctx* c = nullptr;
   void* copy = nullptr;
@@ -827,7 +832,7 @@ int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* best, float* times_ms) {
     hipError_t e = launch(id);
     for (int r = 0; r < reps && e == hipSuccess; ++r) {
       e = hipEventRecord(ev[2 * r], c->stream);
-      if (e == hipSuccess) e = launch(id);
+      for (int k = 0; k < kTuneRunSteps && e == hipSuccess; ++k) e = launch(id);
       if (e == hipSuccess) e = hipEventRecord(ev[2 * r + 1], c->stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -838,7 +843,7 @@ int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* best, float* times_ms) {
       break;
     }
     std::sort(ts.begin(), ts.end());
-    const float med = ts[reps / 2];
+    const float med = ts[reps / 2] / (float)kTuneRunSteps;
     if (times_ms) times_ms[id] = med;
     if (med < best_t) {
       best_t = med;
@@ -916,7 +921,7 @@ int lbm_autotune_two_step(lbm_ctx* c, int32_t reps, int32_t* best, float* times_
   int par = c->parity;
   auto launch = [&](int id) {
     const hipError_t e = launch_multi(c, par, id);
-    par ^= multi_steps(id) & 1;
+    par ^= 1;  // a multi-step launch writes its last level to the other buffer
     return e;
   };
   const int nt = multi_count();
@@ -931,9 +936,10 @@ int lbm_autotune_two_step(lbm_ctx* c, int32_t reps, int32_t* best, float* times_
       continue;
     }
     hipError_t e = launch(id);
+    const int runs = (kTuneRunSteps + multi_steps(id) - 1) / multi_steps(id);  // launches per timed run
     for (int r = 0; r < reps && e == hipSuccess; ++r) {
       e = hipEventRecord(ev[2 * r], c->stream);
-      if (e == hipSuccess) e = launch(id);
+      for (int k = 0; k < runs && e == hipSuccess; ++k) e = launch(id);
       if (e == hipSuccess) e = hipEventRecord(ev[2 * r + 1], c->stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -944,7 +950,7 @@ int lbm_autotune_two_step(lbm_ctx* c, int32_t reps, int32_t* best, float* times_
       break;
     }
     std::sort(ts.begin(), ts.end());
-    const float med = ts[reps / 2] / (float)multi_steps(id);
+    const float med = ts[reps / 2] / (float)(runs * multi_steps(id));
     if (times_ms) times_ms[id] = med;
     if (med < best_t) {
       best_t = med;
