@@ -106,11 +106,16 @@ int lbm3d_check_finite(lbm3d_ctx* ctx, int* ok);
  * ("BXxBYxzZC", "+ntl" when the pulls are loaded non-temporally); the
  * blocks' columns are cut into eight contiguous stretches, one per XCD, so
  * that x-neighbouring blocks, which share the cache lines their shifted
- * pulls straddle, run on one L2.  All shapes give identical results.
+ * pulls straddle, run on one L2.  The "pair:BXxBYxzZC" shapes (ids after the
+ * others) give each thread two x-neighbouring nodes and move both nodes'
+ * value of a population with one 32-bit load or store; they take FP16 and
+ * BF16 storage with non-periodic x faces and an even nx only (lbm3d_set_shape
+ * fails otherwise).  All shapes give identical results.
  * lbm3d_shape_describe names candidate `id`; lbm3d_set_shape selects one
- * (default 128x1xz1); lbm3d_autotune times each (median of `reps` launches
- * after a warm-up; the state is not advanced), keeps the fastest and writes
- * its id to *best and, if times_ms is not NULL, one median per shape. */
+ * (default 128x1xz1); lbm3d_autotune times each shape the lattice takes
+ * (median of `reps` launches after a warm-up; the state is not advanced),
+ * keeps the fastest and writes its id to *best and, if times_ms is not NULL,
+ * one median per shape (-1 for shapes the lattice does not take). */
 int lbm3d_shape_count(void);
 int lbm3d_shape_describe(int32_t id, char* buf, size_t len);
 int lbm3d_set_shape(lbm3d_ctx* ctx, int32_t id);

@@ -407,6 +407,143 @@ __global__ __launch_bounds__(BX* BY, (k3_waves<S, NQ>())) void k3_step(Lat3 L, i
   }
 }
 
+// ------------------------------------------------------------------ pair sweep (16-bit formats)
+// The same step with two x-neighbouring nodes (x0, x0 + 1; x0 even) per lane,
+// for the 16-bit storage formats.  Each pull is one 32-bit load of the two
+// values the pair needs: at element x0 for c_x = 0, at x0 - 1 for c_x = +1
+// and at x0 + 1 for c_x = -1 (2-byte aligned: the GPU serves such loads),
+// and each store one 32-bit store of both results.  The one-node sweep
+// issues a load per 2 bytes; this one per 4, so every wave keeps twice the
+// bytes in flight.  Per node the pulls, the functions and their order are the
+// one-node sweep's (an x-face node takes its unknown pulls from itself, as
+// there), so the results are bit-identical.  Lattices with periodic x faces
+// or an odd nx take the one-node sweep.
+template <class T>
+__device__ inline T from_bits16(uint32_t h) {
+  return __builtin_bit_cast(T, (uint16_t)h);
+}
+template <class T>
+__device__ inline uint32_t to_bits16(T v) {
+  return (uint32_t)__builtin_bit_cast(uint16_t, v);
+}
+
+// (a wave per SIMD fewer than the one-node sweep: each holds two nodes' pulls)
+template <int NQ>
+constexpr int k3_pair_waves() {
+  return NQ == 19 ? 4 : 3;
+}
+
+template <int S, int NQ, int BX, int BY, int ZC>
+__global__ __launch_bounds__(BX* BY, (k3_pair_waves<NQ>())) void k3_pair(Lat3 L, int parity, int tiles_x, int tiles_y,
+                                                                int nitems, int per) {
+  using C = Codec<S>;
+  using T = typename C::T;
+  using R = typename C::R;
+  static_assert(sizeof(T) == 2, "the pair sweep is for the 16-bit formats");
+  const int b = blockIdx.x;
+  const int item = (b & 7) * per + (b >> 3);
+  if (item >= nitems) return;  // no barrier in this kernel
+  const int ntile = tiles_x * tiles_y;
+  const int zc = item / ntile, t = item - zc * ntile;
+  const int ty = t / tiles_x, tx = t - ty * tiles_x;
+  const int x0 = 2 * (tx * BX + threadIdx.x), y = ty * BY + threadIdx.y;
+  const int nx = L.nx, ny = L.ny, nz = L.nz;
+  if (x0 >= nx || y >= ny) return;  // nx is even: x0 + 1 < nx
+  const int xb = x0 + 1;
+  const T* __restrict__ A = static_cast<const T*>(parity ? L.buf[1] : L.buf[0]);
+  T* __restrict__ B = static_cast<T*>(parity ? L.buf[0] : L.buf[1]);
+  const R* __restrict__ MA = static_cast<const R*>(parity ? L.mx[1] : L.mx[0]);
+  R* __restrict__ MB = static_cast<R*>(parity ? L.mx[0] : L.mx[1]);
+  const R rho0 = R(L.rho0), omega = R(L.omega);
+  const bool y_inner = y >= 1 && y <= ny - 2;
+  const uint32_t mxs = (uint32_t)L.mxs;
+  // moments at time t + 1 of a node on or next to an x face, as its stored values decode (slot k of Lat3::mx)
+  auto write_slot = [&](const R g[NQ], int slot, uint32_t mo) {
+    R gs[NQ], m[4];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) gs[i] = C::dec(C::enc(g[i], L.es[i]), L.ds[i]);
+    moments3<NQ, R>(gs, rho0, m);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) MB[(4 * slot + c) * mxs + mo] = m[c];
+  };
+  // NSBC on an x face from the moments at time t of the face node and its inner neighbour
+  auto xface = [&](R g[NQ], int side, uint32_t mo) {
+    const R* Mb = MA + (side > 0 ? 0 : 8 * mxs);  // slots 0, 1 (x = 0) or 2, 3 (x = nx - 1)
+    R mb[4], mn[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      mb[c] = R(Mb[c * mxs + mo]);
+      mn[c] = R(Mb[(4 + c) * mxs + mo]);
+    }
+    xface_nsbc3<S, NQ>(L, mb, mn, side, g);
+  };
+  const int z1 = min(nz, (zc + 1) * ZC);
+  for (int z = zc * ZC; z < z1; ++z) {
+    const uint32_t idx = (uint32_t)((int64_t)z * L.slab + (int64_t)y * L.pitch + x0);
+    const uint32_t mo = (uint32_t)z * (uint32_t)ny + (uint32_t)y;
+    if (y_inner && z >= 1 && z <= nz - 2) {
+      // pulls: the low half of w[i] is node x0's, the high half node x0 + 1's.  Every load
+      // stays inside its source row (elements 0 .. nx - 1): on an x face the pair loads its
+      // own aligned word, whose halves hold what both nodes pull there (the face node pulls
+      // its unknown population from itself, as in the one-node sweep; the value is replaced)
+      const bool left_face = x0 == 0, right_face = xb == nx - 1;
+      uint32_t w[NQ];
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) {
+        const char* Ai = reinterpret_cast<const char*>(A + i * L.plane);
+        // element offset of (x0, y - c_y, z - c_z): >= 0 in an inner row
+        const uint32_t row = (idx - (uint32_t)(kC[i][2] * L.slab + kC[i][1] * L.pitch)) * 2u;
+        const int cx = kC[i][0];
+        const int sh = cx > 0 ? (left_face ? 0 : -2) : (cx < 0 ? (right_face ? 0 : 2) : 0);
+        const uint32_t v = *reinterpret_cast<const uint32_t*>(Ai + (int64_t)row + sh);
+        uint32_t lo = v & 0xffffu, hi = v >> 16;
+        if (cx > 0 && left_face) hi = lo;   // node 1 pulls element 0
+        if (cx < 0 && right_face) lo = hi;  // node nx - 2 pulls element nx - 1
+        w[i] = lo | (hi << 16);
+      }
+      {
+        R g[NQ];
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) g[i] = C::dec(from_bits16<T>(w[i]), L.ds[i]);
+        if (x0 == 0) xface(g, 1, mo);
+        bgk3<NQ, R>(g, rho0, omega);
+        if (x0 == 0) write_slot(g, 0, mo);
+        if (x0 == nx - 2) write_slot(g, 3, mo);
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) w[i] = (w[i] & 0xffff0000u) | to_bits16<T>(C::enc(g[i], L.es[i]));
+      }
+      {
+        R g[NQ];
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) g[i] = C::dec(from_bits16<T>(w[i] >> 16), L.ds[i]);
+        if (xb == nx - 1) xface(g, -1, mo);
+        bgk3<NQ, R>(g, rho0, omega);
+        if (xb == 1) write_slot(g, 1, mo);
+        if (xb == nx - 1) write_slot(g, 2, mo);
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) w[i] = (w[i] & 0xffffu) | (to_bits16<T>(C::enc(g[i], L.es[i])) << 16);
+      }
+      const uint32_t off = idx * 2u;
+#pragma unroll
+      for (int i = 0; i < NQ; ++i)
+        __builtin_nontemporal_store(w[i], reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(B + i * L.plane) + off));
+    } else {
+      // rows on a y or z face: node by node, as the one-node sweep
+#pragma unroll 1
+      for (int k = 0; k < 2; ++k) {
+        R g[NQ];
+        boundary_node3<S, NQ>(L, A, x0 + k, y, z, g);
+        bgk3<NQ, R>(g, rho0, omega);
+        const uint32_t off = (idx + (uint32_t)k) * 2u;
+#pragma unroll
+        for (int i = 0; i < NQ; ++i)
+          __builtin_nontemporal_store(C::enc(g[i], L.es[i]),
+                                      reinterpret_cast<T*>(reinterpret_cast<char*>(B + i * L.plane) + off));
+      }
+    }
+  }
+}
+
 // Launch shapes: block BX x BY, ZC z-planes per block, non-temporal pull
 // loads (NTL; every stored value is read once, so caching it only displaces
 // the lines that x-neighbouring blocks share).
@@ -432,6 +569,33 @@ static const Shape3 kShapes3[] = {
 };
 static constexpr int kNumShapes3 = sizeof(kShapes3) / sizeof(kShapes3[0]);
 
+// Pair-sweep shapes (ids from kNumShapes3 on): BX lanes (2 BX nodes) x BY rows, ZC z-planes.
+#define LBM3D_PAIR_SHAPES(X) \
+  X(64, 4, 1)                \
+  X(64, 2, 1)                \
+  X(64, 4, 2)                \
+  X(128, 1, 1)               \
+  X(128, 2, 2)               \
+  X(64, 1, 4)
+struct ShapePair {
+  int bx, by, zc;
+};
+static const ShapePair kPairs3[] = {
+#define X(a, b, c) {a, b, c},
+    LBM3D_PAIR_SHAPES(X)
+#undef X
+};
+static constexpr int kNumPairs3 = sizeof(kPairs3) / sizeof(kPairs3[0]);
+static constexpr int kNumAll3 = kNumShapes3 + kNumPairs3;
+
+// Whether launch shape `id` takes lattice L: the pair shapes need a 16-bit
+// format, non-periodic x faces and an even nx.
+static bool shape3_supported(const Lat3& L, int id) {
+  if (id < 0 || id >= kNumAll3) return false;
+  if (id < kNumShapes3) return true;
+  return (L.store == ST_F16 || L.store == ST_BF16) && L.bc[0] != BC_PERIODIC && L.nx % 2 == 0;
+}
+
 template <int S, int NQ, int BX, int BY, int ZC, bool NTL>
 static hipError_t launch3_t(const Lat3& L, int parity, hipStream_t s) {
   const int tiles_x = (L.nx + BX - 1) / BX, tiles_y = (L.ny + BY - 1) / BY, zch = (L.nz + ZC - 1) / ZC;
@@ -440,13 +604,31 @@ static hipError_t launch3_t(const Lat3& L, int parity, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int S, int NQ, int BX, int BY, int ZC>
+static hipError_t launch3_pair_t(const Lat3& L, int parity, hipStream_t s) {
+  if constexpr (S == ST_F16 || S == ST_BF16) {
+    const int tiles_x = (L.nx / 2 + BX - 1) / BX, tiles_y = (L.ny + BY - 1) / BY, zch = (L.nz + ZC - 1) / ZC;
+    const int nitems = tiles_x * tiles_y * zch, per = (nitems + 7) / 8;
+    k3_pair<S, NQ, BX, BY, ZC><<<dim3(8 * per), dim3(BX, BY), 0, s>>>(L, parity, tiles_x, tiles_y, nitems, per);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
 template <int S, int NQ>
 static hipError_t launch3_s(const Lat3& L, int parity, int shape, hipStream_t s) {
+  if (!shape3_supported(L, shape)) return hipErrorInvalidValue;
   int k = 0;
 #define X(a, b, c, d)                                                    \
   if (shape == k) return launch3_t<S, NQ, a, b, c, d>(L, parity, s);    \
   ++k;
   LBM3D_SHAPES(X)
+#undef X
+#define X(a, b, c)                                                       \
+  if (shape == k) return launch3_pair_t<S, NQ, a, b, c>(L, parity, s);  \
+  ++k;
+  LBM3D_PAIR_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;
 }
@@ -892,11 +1074,16 @@ int lbm3d_time(const lbm3d_ctx* c, int64_t* t) {
   return LBM_OK;
 }
 
-int lbm3d_shape_count(void) { return lbm::d3::kNumShapes3; }
+int lbm3d_shape_count(void) { return lbm::d3::kNumAll3; }
 
 int lbm3d_shape_describe(int32_t id, char* buf, size_t len) {
   if (!buf || len == 0) return fail(LBM_ERR_ARG, "NULL buffer");
-  if (id < 0 || id >= lbm::d3::kNumShapes3) return fail(LBM_ERR_ARG, "shape id %d out of range", id);
+  if (id < 0 || id >= lbm::d3::kNumAll3) return fail(LBM_ERR_ARG, "shape id %d out of range", id);
+  if (id >= lbm::d3::kNumShapes3) {
+    const lbm::d3::ShapePair& s = lbm::d3::kPairs3[id - lbm::d3::kNumShapes3];
+    snprintf(buf, len, "pair:%dx%dxz%d", s.bx, s.by, s.zc);
+    return LBM_OK;
+  }
   const lbm::d3::Shape3& s = lbm::d3::kShapes3[id];
   snprintf(buf, len, "%dx%dxz%d%s", s.bx, s.by, s.zc, s.ntl ? "+ntl" : "");
   return LBM_OK;
@@ -904,7 +1091,10 @@ int lbm3d_shape_describe(int32_t id, char* buf, size_t len) {
 
 int lbm3d_set_shape(lbm3d_ctx* c, int32_t id) {
   if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
-  if (id < 0 || id >= lbm::d3::kNumShapes3) return fail(LBM_ERR_ARG, "shape id %d out of range", id);
+  if (id < 0 || id >= lbm::d3::kNumAll3) return fail(LBM_ERR_ARG, "shape id %d out of range", id);
+  if (!lbm::d3::shape3_supported(c->L, id))
+    return fail(LBM_ERR_ARG, "shape %d: the pair shapes need FP16 or BF16 storage, non-periodic x faces and an even nx",
+                id);
   c->shape = id;
   return LBM_OK;
 }
@@ -916,7 +1106,11 @@ int lbm3d_autotune(lbm3d_ctx* c, int32_t reps, int32_t* best, float* times_ms) {
   for (auto& x : ev) HIPCHK3(hipEventCreate(&x));
   float best_t = 1e30f;
   int best_id = c->shape, rc = LBM_OK;
-  for (int id = 0; id < lbm::d3::kNumShapes3 && rc == LBM_OK; ++id) {
+  for (int id = 0; id < lbm::d3::kNumAll3 && rc == LBM_OK; ++id) {
+    if (!lbm::d3::shape3_supported(c->L, id)) {
+      if (times_ms) times_ms[id] = -1.f;
+      continue;
+    }
     // a step reads buffer `parity` and writes only the other: the state is not advanced
     hipError_t e = lbm::d3::launch3(c->L, c->parity, id, c->stream);
     for (int r = 0; r < reps && e == hipSuccess; ++r) {
