@@ -416,8 +416,9 @@ __global__ __launch_bounds__(BX* BY, (k3_waves<S, NQ>())) void k3_step(Lat3 L, i
 // issues a load per 2 bytes; this one per 4, so every wave keeps twice the
 // bytes in flight.  Per node the pulls, the functions and their order are the
 // one-node sweep's (an x-face node takes its unknown pulls from itself, as
-// there), so the results are bit-identical.  Lattices with periodic x faces
-// or an odd nx take the one-node sweep.
+// there), so the results are bit-identical.  The rows on a y or z face go to
+// a second, node-by-node launch (k3_faces).  Lattices with periodic x faces or
+// an odd nx take the one-node sweep.
 template <class T>
 __device__ inline T from_bits16(uint32_t h) {
   return __builtin_bit_cast(T, (uint16_t)h);
@@ -457,11 +458,12 @@ __global__ __launch_bounds__(BX* BY, (k3_pair_waves<NQ>())) void k3_pair(Lat3 L,
   const R rho0 = R(L.rho0), omega = R(L.omega);
   const bool y_inner = y >= 1 && y <= ny - 2;
   const uint32_t mxs = (uint32_t)L.mxs;
-  // moments at time t + 1 of a node on or next to an x face, as its stored values decode (slot k of Lat3::mx)
-  auto write_slot = [&](const R g[NQ], int slot, uint32_t mo) {
+  // moments at time t + 1 of a node on or next to an x face, as its stored values decode (slot k
+  // of Lat3::mx), from the encoded values in half `shift` (0 or 16) of w
+  auto write_slot = [&](const uint32_t w[NQ], int shift, int slot, uint32_t mo) {
     R gs[NQ], m[4];
 #pragma unroll
-    for (int i = 0; i < NQ; ++i) gs[i] = C::dec(C::enc(g[i], L.es[i]), L.ds[i]);
+    for (int i = 0; i < NQ; ++i) gs[i] = C::dec(from_bits16<T>(w[i] >> shift), L.ds[i]);
     moments3<NQ, R>(gs, rho0, m);
 #pragma unroll
     for (int c = 0; c < 4; ++c) MB[(4 * slot + c) * mxs + mo] = m[c];
@@ -507,41 +509,62 @@ __global__ __launch_bounds__(BX* BY, (k3_pair_waves<NQ>())) void k3_pair(Lat3 L,
         for (int i = 0; i < NQ; ++i) g[i] = C::dec(from_bits16<T>(w[i]), L.ds[i]);
         if (x0 == 0) xface(g, 1, mo);
         bgk3<NQ, R>(g, rho0, omega);
-        if (x0 == 0) write_slot(g, 0, mo);
-        if (x0 == nx - 2) write_slot(g, 3, mo);
 #pragma unroll
         for (int i = 0; i < NQ; ++i) w[i] = (w[i] & 0xffff0000u) | to_bits16<T>(C::enc(g[i], L.es[i]));
       }
+      if (x0 == 0) write_slot(w, 0, 0, mo);
+      if (x0 == nx - 2) write_slot(w, 0, 3, mo);
       {
         R g[NQ];
 #pragma unroll
         for (int i = 0; i < NQ; ++i) g[i] = C::dec(from_bits16<T>(w[i] >> 16), L.ds[i]);
         if (xb == nx - 1) xface(g, -1, mo);
         bgk3<NQ, R>(g, rho0, omega);
-        if (xb == 1) write_slot(g, 1, mo);
-        if (xb == nx - 1) write_slot(g, 2, mo);
 #pragma unroll
         for (int i = 0; i < NQ; ++i) w[i] = (w[i] & 0xffffu) | (to_bits16<T>(C::enc(g[i], L.es[i])) << 16);
       }
+      if (xb == 1) write_slot(w, 16, 1, mo);
+      if (xb == nx - 1) write_slot(w, 16, 2, mo);
       const uint32_t off = idx * 2u;
 #pragma unroll
       for (int i = 0; i < NQ; ++i)
         __builtin_nontemporal_store(w[i], reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(B + i * L.plane) + off));
-    } else {
-      // rows on a y or z face: node by node, as the one-node sweep
-#pragma unroll 1
-      for (int k = 0; k < 2; ++k) {
-        R g[NQ];
-        boundary_node3<S, NQ>(L, A, x0 + k, y, z, g);
-        bgk3<NQ, R>(g, rho0, omega);
-        const uint32_t off = (idx + (uint32_t)k) * 2u;
-#pragma unroll
-        for (int i = 0; i < NQ; ++i)
-          __builtin_nontemporal_store(C::enc(g[i], L.es[i]),
-                                      reinterpret_cast<T*>(reinterpret_cast<char*>(B + i * L.plane) + off));
-      }
     }
+    // (rows on a y or z face: k3_faces)
   }
+}
+
+// The rows on a y or z face (y = 0, ny - 1 for every z; z = 0, nz - 1 for the
+// other y), node by node as the one-node sweep takes them, one block per row
+// segment of 256 nodes; launched after k3_pair, which leaves them out so that
+// their registers do not weigh on it.
+template <int S, int NQ>
+__global__ __launch_bounds__(256) void k3_faces(Lat3 L, int parity) {
+  using C = Codec<S>;
+  using T = typename C::T;
+  using R = typename C::R;
+  const int nx = L.nx, ny = L.ny, nz = L.nz;
+  const int r = blockIdx.y;  // face row: 0 .. 2 nz - 1 on the y faces, then 2 (ny - 2) on the z faces
+  int y, z;
+  if (r < 2 * nz) {
+    z = r >> 1;
+    y = r & 1 ? ny - 1 : 0;
+  } else {
+    const int k = r - 2 * nz;
+    y = 1 + (k >> 1);
+    z = k & 1 ? nz - 1 : 0;
+  }
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  if (x >= nx) return;
+  const T* __restrict__ A = static_cast<const T*>(parity ? L.buf[1] : L.buf[0]);
+  T* __restrict__ B = static_cast<T*>(parity ? L.buf[0] : L.buf[1]);
+  R g[NQ];
+  boundary_node3<S, NQ>(L, A, x, y, z, g);
+  bgk3<NQ, R>(g, R(L.rho0), R(L.omega));
+  const uint32_t off = (uint32_t)((int64_t)z * L.slab + (int64_t)y * L.pitch + x) * (uint32_t)sizeof(T);
+#pragma unroll
+  for (int i = 0; i < NQ; ++i)
+    __builtin_nontemporal_store(C::enc(g[i], L.es[i]), reinterpret_cast<T*>(reinterpret_cast<char*>(B + i * L.plane) + off));
 }
 
 // Launch shapes: block BX x BY, ZC z-planes per block, non-temporal pull
@@ -610,6 +633,9 @@ static hipError_t launch3_pair_t(const Lat3& L, int parity, hipStream_t s) {
     const int tiles_x = (L.nx / 2 + BX - 1) / BX, tiles_y = (L.ny + BY - 1) / BY, zch = (L.nz + ZC - 1) / ZC;
     const int nitems = tiles_x * tiles_y * zch, per = (nitems + 7) / 8;
     k3_pair<S, NQ, BX, BY, ZC><<<dim3(8 * per), dim3(BX, BY), 0, s>>>(L, parity, tiles_x, tiles_y, nitems, per);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k3_faces<S, NQ><<<dim3((L.nx + 255) / 256, 2 * L.nz + 2 * (L.ny - 2)), dim3(256), 0, s>>>(L, parity);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
