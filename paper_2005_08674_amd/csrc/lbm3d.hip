@@ -320,8 +320,9 @@ __device__ __forceinline__ void pull_row3(const Lat3& L, const typename Codec<S>
 // list of (z chunk, tile row, tile column) in that order, so XCD k (blocks
 // b = k mod 8) works through the k-th contiguous stretch: x-neighbouring
 // tiles, which share the lines their shifted pulls straddle, run on one XCD.
-// Tile rows on a y or z face take boundary_node3 (whole wavefronts, as a
-// wavefront is a run of x).  In the other rows an x-face node is one lane of
+// Rows on a y or z face are left to a second launch (k3_faces, node by node
+// with boundary_node3), so that their registers do not weigh on this kernel.
+// In the other rows an x-face node is one lane of
 // a wavefront: it pulls with the others (the x shift adjusted), and on a NSBC
 // face it takes the moments at time t of itself and of its inner neighbour
 // from Lat3::mx instead of loading 2 q stored populations: the lanes of those
@@ -366,7 +367,8 @@ __global__ __launch_bounds__(BX* BY, (k3_waves<S, NQ>())) void k3_step(Lat3 L, i
     R g[NQ];
     const uint32_t idx = (uint32_t)((int64_t)z * L.slab + (int64_t)y * L.pitch + x);
     const bool inner_row = y_inner && z >= 1 && z <= nz - 2;
-    if (inner_row) {
+    if (!inner_row) continue;  // rows on a y or z face: k3_faces
+    {
       pull_row3<S, NQ, NTL>(L, A, idx, sxm, sxp, g);
       if (xside) {
         const uint32_t mo = (uint32_t)z * (uint32_t)ny + (uint32_t)y;
@@ -379,11 +381,9 @@ __global__ __launch_bounds__(BX* BY, (k3_waves<S, NQ>())) void k3_step(Lat3 L, i
         }
         xface_nsbc3<S, NQ>(L, mb, mn, xside, g);
       }
-    } else {
-      boundary_node3<S, NQ>(L, A, x, y, z, g);
     }
     bgk3<NQ, R>(g, rho0, omega);
-    if (inner_row && mwrite) {
+    if (mwrite) {
       // moments of the populations stored below, as they decode; slot 0:
       // x = 0, 1: x = 1, 2: x = nx - 1, 3: x = nx - 2 (both 1 and 3 when nx = 3)
       R gs[NQ], m[4];
@@ -535,9 +535,9 @@ __global__ __launch_bounds__(BX* BY, (k3_pair_waves<NQ>())) void k3_pair(Lat3 L,
 }
 
 // The rows on a y or z face (y = 0, ny - 1 for every z; z = 0, nz - 1 for the
-// other y), node by node as the one-node sweep takes them, one block per row
-// segment of 256 nodes; launched after k3_pair, which leaves them out so that
-// their registers do not weigh on it.
+// other y), node by node with boundary_node3, one block per row segment of
+// 256 nodes; launched after k3_step or k3_pair, which leave them out so that
+// their registers do not weigh on them.
 template <int S, int NQ>
 __global__ __launch_bounds__(256) void k3_faces(Lat3 L, int parity) {
   using C = Codec<S>;
@@ -624,6 +624,9 @@ static hipError_t launch3_t(const Lat3& L, int parity, hipStream_t s) {
   const int tiles_x = (L.nx + BX - 1) / BX, tiles_y = (L.ny + BY - 1) / BY, zch = (L.nz + ZC - 1) / ZC;
   const int nitems = tiles_x * tiles_y * zch, per = (nitems + 7) / 8;
   k3_step<S, NQ, BX, BY, ZC, NTL><<<dim3(8 * per), dim3(BX, BY), 0, s>>>(L, parity, tiles_x, tiles_y, nitems, per);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k3_faces<S, NQ><<<dim3((L.nx + 255) / 256, 2 * L.nz + 2 * (L.ny - 2)), dim3(256), 0, s>>>(L, parity);
   return hipGetLastError();
 }
 
