@@ -171,7 +171,7 @@ def run_store(torch, W, store, steps, warmup, tune_reps=5, size=4096, serial_che
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "multistep_pulses4096_f32_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2005_08674_amd", "csrc", f)
                   for f in ("lbm_kernels.hip", "lbm_twostep.hip", "lbm_device.h", "lbm_sweep.h", "lbm_twostep_lds.h",
-                            "lbm_threestep.h")]
+                            "lbm_threestep.h", "lbm_march.hip")]
 
 
 def kernel_source_sha() -> str:

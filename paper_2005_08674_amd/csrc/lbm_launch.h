@@ -27,6 +27,8 @@ int two_step_min_rows();
 int num_three_step();
 void three_step_name(int id, char* buf, size_t len);
 bool three_step_supported(const LatDesc& L, int id);
+// whether three-step shape id is a column march (single lattices only)
+bool three_step_is_march(int id);
 // (with the learned closure: edge tiles on `side` beside the inner tiles on s when side, fork and join are given)
 hipError_t launch_three_step(const LatDesc& L, int parity, int id, hipStream_t s, hipStream_t side = nullptr,
                              hipEvent_t fork = nullptr, hipEvent_t join = nullptr);

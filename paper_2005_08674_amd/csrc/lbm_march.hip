@@ -1,0 +1,33 @@
+// lbm_march.hip -- the marched three-step sweep's instances (kernel and
+// shapes in lbm_threestep.h): edge tiles and strips in one launch.
+#include <hip/hip_runtime.h>
+
+#include "lbm_device.h"
+#include "lbm_launch.h"
+#include "lbm_threestep.h"
+
+namespace lbm {
+
+// March shape `id` (among the march shapes) in format S.
+template <int S>
+static hipError_t launch_march_s(const LatDesc& L, int parity, int id, hipStream_t s) {
+  int k = 0;
+#define X(a, m, b, h, p)                                                     \
+  if (id == k) return launch_march_t<S, a, m, b, true, p>(L, parity, s, h);  \
+  ++k;
+  LBM_THREE_MARCH(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_three_march(const LatDesc& L, int parity, int id, hipStream_t s) {
+  switch (L.store) {
+    case ST_F64: return launch_march_s<ST_F64>(L, parity, id, s);
+    case ST_F32: return launch_march_s<ST_F32>(L, parity, id, s);
+    case ST_F16: return launch_march_s<ST_F16>(L, parity, id, s);
+    case ST_BF16: return launch_march_s<ST_BF16>(L, parity, id, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace lbm

@@ -33,6 +33,21 @@ constexpr int two_step_waves() {
   X(16, 768, true)        \
   X(20, 768, true)
 
+// ------------------------------------------------------------------ column march
+// Candidate shapes of the marched three-step sweep, one launch of NT-thread
+// blocks: the edge tiles (the ring around the inner tiles' rectangle) as
+// three-step tiles of 64 x TY, then the rectangle as 64-column strips cut
+// into chunks of about H rows, each walked down in rounds of MR rows
+// (three_step_march) with PF rounds of loads in flight; the march's level
+// rings take the tiles' level arrays.
+#define LBM_THREE_MARCH(X)  \
+  X(12, 11, 768, 128, 1)    \
+  X(12, 11, 768, 64, 1)     \
+  X(12, 11, 768, 96, 1)     \
+  X(12, 11, 768, 128, 2)    \
+  X(8, 7, 512, 128, 1)      \
+  X(8, 7, 512, 64, 1)
+
 template <int S, int TY>
 constexpr bool three_step_fits() {
   return three_step_lds_bytes<S, TY>() <= 160 * 1024;
@@ -154,8 +169,257 @@ inline bool three_step_fits_store(int store, int id, bool closure) {
   ++k;
   LBM_THREE_STEP(X)
 #undef X
+#define X(a, m, b, h, p)                                                                        \
+  if (id == k) {                                                                             \
+    if (closure) return false;                                                               \
+    switch (store) {                                                                         \
+      case ST_F64: return three_step_fits<ST_F64, a>();                                      \
+      case ST_F32: return three_step_fits<ST_F32, a>();                                      \
+      case ST_F16: return three_step_fits<ST_F16, a>();                                      \
+      case ST_BF16: return three_step_fits<ST_BF16, a>();                                    \
+    }                                                                                        \
+    return false;                                                                            \
+  }                                                                                          \
+  ++k;
+  LBM_THREE_MARCH(X)
+#undef X
   return false;
 }
+
+// Chunk rows of a march over an inner rectangle of `rows` rows in chunks of
+// about h: the count, and the height of all but the last.
+__host__ __device__ inline void march_chunks(int rows, int h, int& chunks, int& height) {
+  chunks = rows > 0 ? (rows + h - 1) / h : 0;
+  height = chunks > 0 ? (rows + chunks - 1) / chunks : 0;
+}
+
+// Column march (TY: the level arrays' tile rows): the block owns the 64 columns xs .. xs + 63 of output rows
+// ya .. yb - 1, all inside the inner tiles' rectangle (no clamp, no NSBC),
+// and walks down them in rounds of MR rows: round j computes level t + 1 on
+// rows ya - 2 + j MR + [0, MR) (68 columns, pulled from HBM), level t + 2
+// one row behind (66 columns) and level t + 3 one row behind that (the 64
+// output columns, stored).  Each level keeps its last MR + 2 rows in a ring
+// in the tile's level arrays (row y of level t + 1 in slot (y - ya + 2) mod
+// (MR + 2) of lds1, of level t + 2 in (y - ya + 1) mod (MR + 2) of lds2), so apart from the two ends of
+// the strip no row is computed twice.  The loads of level t + 1 run PF
+// rounds ahead of their use: those of round j + PF are issued before round
+// j's levels t + 2 and t + 3.  Per node the arithmetic and the codec
+// rounding are the tiles': bit-identical to single steps.
+template <int S, int TY, int MR, int NT, bool NTS, int CM, int PF>
+__device__ inline void three_step_march(const LatDesc& Ld, int parity, int xs, int ya, int yb) {
+  static_assert(MR >= 5 && MR <= TY && (PF == 1 || PF == 2), "march shape");
+  using C = Codec<S>;
+  using T = typename C::T;
+  using R = typename C::R;
+  constexpr int RR = MR + 2;
+  constexpr int NI = (MR * T3_W1 + NT - 1) / NT;
+  auto& r1 = three_lds1<S, TY>();
+  auto& r2 = three_lds2<S, TY>();
+  const int tid = threadIdx.x;
+  const T* __restrict__ A = static_cast<const T*>(buf_of(Ld, parity));
+  T* __restrict__ B = static_cast<T*>(buf_of(Ld, parity ^ 1));
+  const int pitch = Ld.pitch;
+  const int64_t plane = Ld.plane;
+  const R rho0 = R(Ld.rho0), omega = R(Ld.omega);
+  const int rounds = (yb - ya + 4 + MR - 1) / MR;
+  T raw[PF][NI][9];
+  // loads of level t + 1's rows of round j (ya - 2 + j MR + r, r < n) into raw[u]
+  auto fetch = [&](int j, int u) __attribute__((always_inline)) {
+    const int q = ya - 2 + j * MR, n = min(MR, yb + 2 - q);
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+      const int k = tid + it * NT;
+      if (k < n * T3_W1) {
+        const int r = k / T3_W1, cx = k - r * T3_W1;
+        const uint32_t idx = (uint32_t)((q + r) * pitch + (xs - 2 + cx));
+        const uint32_t ro[3] = {(idx + (uint32_t)pitch) * (uint32_t)sizeof(T), idx * (uint32_t)sizeof(T),
+                                (idx - (uint32_t)pitch) * (uint32_t)sizeof(T)};
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          const char* __restrict__ Ai = reinterpret_cast<const char*>(A + i * plane);
+          raw[u][it][i] = *reinterpret_cast<const T*>(Ai + ro[1 + kCy[i]] - kCx[i] * (int)sizeof(T));
+        }
+      }
+    }
+  };
+  // LDS as element offsets from the arrays' first element (32-bit
+  // arithmetic; population i's plane of a level array at a constant offset)
+  T* const l1 = &r1[0][0][0];
+  T* const l2 = &r2[0][0][0];
+  constexpr int P1 = (TY + 4) * T3_W1, P2 = (TY + 2) * T3_W2;
+  // per-plane output bases, held opaque in scalar registers so that each
+  // store is a scalar base plus the lane's 32-bit byte offset
+  using GC = __attribute__((address_space(1))) char;
+  using GT = __attribute__((address_space(1))) T;
+  GC* Bp[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    Bp[i] = (GC*)(reinterpret_cast<char*>(B + i * plane));
+    asm volatile("" : "+s"(Bp[i]));
+  }
+  // ring slot of a row: su (the round's first row's slot, uniform) + r, wrapped once
+  auto wrap = [](int v) { return v >= RR ? v - RR : v; };
+  auto level1 = [&](const Base<R>& b, int j, int u) __attribute__((always_inline)) {
+    const int q = ya - 2 + j * MR, n = min(MR, yb + 2 - q);
+    const int su = (j * MR) % RR;
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+      const int k = tid + it * NT;
+      if (k < n * T3_W1) {
+        const int r = k / T3_W1, cx = k - r * T3_W1;
+        R g[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) g[i] = C::dec(raw[u][it][i], Ld.ds[i]);
+        collide<R, CM>(Ld, g, rho0, b, omega);
+        const uint32_t o = (uint32_t)(wrap(su + r) * T3_W1 + cx);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) l1[o + i * P1] = C::enc(g[i], Ld.es[i]);
+      }
+    }
+  };
+  auto level2 = [&](const Base<R>& b, int j) __attribute__((always_inline)) {
+    const int lo = max(ya - 3 + j * MR, ya - 1), hi = min(ya - 3 + (j + 1) * MR, yb + 1);
+    const int su = (lo - ya + 2) % RR;
+    constexpr int N2 = MR * T3_W2;
+#pragma unroll
+    for (int it = 0; it < (N2 + NT - 1) / NT; ++it) {
+      const int k = tid + it * NT;
+      if (k < (hi - lo) * T3_W2) {
+        const int r = k / T3_W2, cx = k - r * T3_W2;
+        // level t + 1 slots of rows y - 1, y, y + 1 (y = lo + r); row y of level t + 2 goes to slot sm
+        const int s0 = wrap(su + r);
+        const int sm = s0 == 0 ? RR - 1 : s0 - 1, sp = s0 == RR - 1 ? 0 : s0 + 1;
+        const uint32_t om = (uint32_t)(sm * T3_W1 + cx + 1), o0 = (uint32_t)(s0 * T3_W1 + cx + 1),
+                       op = (uint32_t)(sp * T3_W1 + cx + 1);
+        R g[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+          g[i] = C::dec(l1[(kCy[i] > 0 ? om : (kCy[i] < 0 ? op : o0)) + i * P1 - kCx[i]], Ld.ds[i]);
+        collide<R, CM>(Ld, g, rho0, b, omega);
+        const uint32_t ow = (uint32_t)(sm * T3_W2 + cx);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) l2[ow + i * P2] = C::enc(g[i], Ld.es[i]);
+      }
+    }
+  };
+  auto level3 = [&](const Base<R>& b, int j) __attribute__((always_inline)) {
+    const int lo = max(ya - 4 + j * MR, ya), hi = min(ya - 4 + (j + 1) * MR, yb);
+    const int su = (lo - ya + 1) % RR;
+    constexpr int N3 = MR * TL_TX;
+#pragma unroll
+    for (int it = 0; it < (N3 + NT - 1) / NT; ++it) {
+      const int k = tid + it * NT;
+      if (k < (hi - lo) * TL_TX) {
+        const int r = k / TL_TX, cx = k - r * TL_TX;
+        const int s0 = wrap(su + r);
+        const int sm = s0 == 0 ? RR - 1 : s0 - 1, sp = s0 == RR - 1 ? 0 : s0 + 1;
+        const uint32_t om = (uint32_t)(sm * T3_W2 + cx + 1), o0 = (uint32_t)(s0 * T3_W2 + cx + 1),
+                       op = (uint32_t)(sp * T3_W2 + cx + 1);
+        R g[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+          g[i] = C::dec(l2[(kCy[i] > 0 ? om : (kCy[i] < 0 ? op : o0)) + i * P2 - kCx[i]], Ld.ds[i]);
+        collide<R, CM>(Ld, g, rho0, b, omega);
+        const uint32_t off = (uint32_t)((lo + r) * pitch + xs + cx) * (uint32_t)sizeof(T);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          GT* p = (GT*)(Bp[i] + off);
+          if constexpr (NTS)
+            __builtin_nontemporal_store(C::enc(g[i], Ld.es[i]), p);
+          else
+            *p = C::enc(g[i], Ld.es[i]);
+        }
+      }
+    }
+  };
+  // One round (its level t + 1 already in r1): round j + 1's level t + 1
+  // overwrites ring rows that round j's level t + 2 has read (a barrier lies
+  // between them), round j + 1's level t + 2 those that round j's level
+  // t + 3 has read (the barrier closing round j).  raw[u] holds round
+  // j + 1's loads; round j + PF's go to the buffer round j's level t + 1
+  // emptied.
+  auto round = [&](const Base<R>& b, int j, int u) __attribute__((always_inline)) {
+    if (PF == 2 && j + 2 < rounds) fetch(j + 2, u ^ 1);
+    if (PF == 1 && j + 1 < rounds) fetch(j + 1, 0);
+    level2(b, j);
+    __syncthreads();
+    level3(b, j);
+    if (j + 1 < rounds) level1(b, j + 1, PF == 2 ? u : 0);
+    __syncthreads();
+  };
+  auto run = [&](const Base<R>& b) __attribute__((always_inline)) {
+    fetch(0, 0);
+    if (PF == 2 && rounds > 1) fetch(1, 1);
+    level1(b, 0, 0);
+    __syncthreads();
+    // with PF = 2, round j's successor's loads sit in raw[(j + 1) & 1]; the
+    // loop is unrolled by two so that every register index is a constant
+    for (int j = 0; j < rounds; j += 2) {
+      round(b, j, 1);
+      if (j + 1 < rounds) round(b, j + 1, 0);
+    }
+  };
+  const Base<R> base(Ld);
+  Base<R> b = base;
+  if (base.zero) {
+    b.zero = true;
+    run(b);
+  } else {
+    b.zero = false;
+    run(b);
+  }
+}
+
+// Blocks below ring8 take the edge tiles (ring_tile order, padded to a
+// multiple of 8), the others the strips' chunks in XCD bands: XCD k takes
+// the k-th contiguous eighth of the chunk-major list, so neighbouring strips
+// share its L2.  The edge tiles come first: they are the slower blocks.
+template <int S, int TY, int MR, int NT, bool NTS, int CM, int PF>
+__global__ __launch_bounds__(NT, two_step_waves<S>()) void k_three_march(LatDesc L, int parity, int tiles_x,
+                                                                       int tiles_y, int ring8, int height,
+                                                                       int chunks) {
+  const int ix = inner_cols(L.nx), iy = inner_rows(L.ny, TY);
+  const int b = blockIdx.x;
+  if (b < ring8) {
+    int txi, tyi;
+    if (!ring_tile(b, tiles_x, tiles_y, ix, iy, txi, tyi)) return;  // padding: the block leaves before any barrier
+    three_step_tile<S, TY, NT, NTS, CM, false>(L, parity, txi, tyi, 2);
+    return;
+  }
+  // (ring8 is a multiple of 8, so m and b run on the same XCD)
+  const int m = b - ring8, items = ix * chunks, per = (items + 7) >> 3;
+  const int item = (m & 7) * per + (m >> 3);
+  if (item >= items) return;
+  const int c = item / ix, sx = item - c * ix;
+  const int ya = TY + c * height, yb = min(ya + height, TY * (iy + 1));
+  three_step_march<S, TY, MR, NT, NTS, CM, PF>(L, parity, TL_TX * (1 + sx), ya, yb);
+}
+
+// One launch: the edge tiles and the march over the inner rectangle in
+// chunks of about h rows.
+template <int S, int TY, int MR, int NT, bool NTS, int PF>
+inline hipError_t launch_march_t(const LatDesc& L, int parity, hipStream_t s, int h) {
+  if constexpr (!three_step_fits<S, TY>()) {
+    return hipErrorInvalidValue;
+  } else {
+    const int tiles_x = (L.nx + TL_TX - 1) / TL_TX, tiles_y = (L.ny + TY - 1) / TY;
+    const int ix = inner_cols(L.nx), iy = inner_rows(L.ny, TY);
+    const int ring = tiles_x * tiles_y - ix * iy, ring8 = (ring + 7) / 8 * 8;
+    int chunks, height;
+    march_chunks(ix > 0 ? TY * iy : 0, h, chunks, height);
+    const dim3 grid(ring8 + (ix * chunks + 7) / 8 * 8);
+    if (L.coll == COLL_MRT)
+      k_three_march<S, TY, MR, NT, NTS, COLL_MRT, PF>
+          <<<grid, dim3(NT), 0, s>>>(L, parity, tiles_x, tiles_y, ring8, height, chunks);
+    else
+      k_three_march<S, TY, MR, NT, NTS, COLL_BGK, PF>
+          <<<grid, dim3(NT), 0, s>>>(L, parity, tiles_x, tiles_y, ring8, height, chunks);
+    return hipGetLastError();
+  }
+}
+
+// march shape `id` (among the march shapes) on one lattice (lbm_march.hip)
+hipError_t launch_three_march(const LatDesc& L, int parity, int id, hipStream_t s);
 
 // three-step launch of a lattice with the learned closure (lbm_twostep_cl.hip)
 hipError_t launch_three_step_closure(const LatDesc& L, int parity, int id, hipStream_t s);

@@ -133,16 +133,29 @@ hipError_t launch_two_step(const LatDesc& L, int parity, int id, hipStream_t s) 
 
 // ------------------------------------------------------------------ three-step kernel
 // (shapes and kernel in lbm_threestep.h)
+// the tile shapes first, then the marched ones (mr > 0: rows per round, h:
+// chunk rows; non-temporal stores)
 struct ThreeStepShape {
   int ty, nt;
   bool nts;
+  int mr, h, pf;
 };
 static const ThreeStepShape kThree[] = {
-#define X(a, b, c) {a, b, c},
+#define X(a, b, c) {a, b, c, 0, 0, 0},
     LBM_THREE_STEP(X)
+#undef X
+#define X(a, m, b, h, p) {a, b, true, m, h, p},
+    LBM_THREE_MARCH(X)
 #undef X
 };
 static constexpr int kNumThree = sizeof(kThree) / sizeof(kThree[0]);
+static constexpr int kNumMarch = 0
+#define X(a, m, b, h, p) +1
+    LBM_THREE_MARCH(X)
+#undef X
+    ;
+
+bool three_step_is_march(int id) { return id >= 0 && id < kNumThree && kThree[id].mr > 0; }
 
 int num_three_step() { return kNumThree; }
 
@@ -151,12 +164,16 @@ void three_step_name(int id, char* buf, size_t len) {
     snprintf(buf, len, "invalid");
     return;
   }
-  snprintf(buf, len, "3step:64x%d/%d+xcdband%s", kThree[id].ty, kThree[id].nt, kThree[id].nts ? "+nts" : "");
+  const ThreeStepShape& t = kThree[id];
+  if (t.mr > 0)
+    snprintf(buf, len, "3step:64x%d/%d+march%dxh%d%s+xcdband+nts", t.ty, t.nt, t.mr, t.h, t.pf == 2 ? "+pf2" : "");
+  else
+    snprintf(buf, len, "3step:64x%d/%d+xcdband%s", t.ty, t.nt, t.nts ? "+nts" : "");
 }
 
 bool three_step_supported(const LatDesc& L, int id) {
   return id >= 0 && id < kNumThree && two_step_supported(L) && L.nx >= TL_TX && L.ny >= kThree[id].ty &&
-         three_step_fits_store(L.store, id, L.closure && L.net);
+         three_step_fits_store(L.store, id, L.closure && L.net) && !(kThree[id].mr > 0 && L.closure && L.net);
 }
 
 // A lattice on the learned closure takes two launches: its edge tiles with
@@ -169,6 +186,10 @@ bool three_step_supported(const LatDesc& L, int id) {
 hipError_t launch_three_step(const LatDesc& L, int parity, int id, hipStream_t s, hipStream_t side, hipEvent_t fork,
                              hipEvent_t join) {
   if (!three_step_supported(L, id)) return hipErrorInvalidValue;
+  if (kThree[id].mr > 0) {
+    const int mid = id - (kNumThree - kNumMarch);
+    return launch_three_march(L, parity, mid, s);
+  }
   int part = 0;
   const bool forked = L.closure && L.net && side && fork && join;
   if (L.closure && L.net) {

@@ -277,6 +277,19 @@ __host__ __device__ constexpr int light_waves_start(int n, int nt) {
   return n % nt == 0 ? 0 : ((n % nt + 63) / 64 * 64) % nt;
 }
 
+// The two level arrays of a three-step block, one allocation per kernel
+// whichever path (tile or column march) takes them.
+template <int S, int TY>
+__device__ inline auto three_lds1() -> typename Codec<S>::T (&)[9][TY + 4][T3_W1] {
+  __shared__ __attribute__((aligned(16))) typename Codec<S>::T a[9][TY + 4][T3_W1];
+  return a;
+}
+template <int S, int TY>
+__device__ inline auto three_lds2() -> typename Codec<S>::T (&)[9][TY + 2][T3_W2] {
+  __shared__ __attribute__((aligned(16))) typename Codec<S>::T a[9][TY + 2][T3_W2];
+  return a;
+}
+
 template <int S, int TY>
 constexpr int three_step_lds_bytes() {
   return 9 * ((TY + 4) * T3_W1 + (TY + 2) * T3_W2) * (int)sizeof(typename Codec<S>::T);
@@ -483,13 +496,14 @@ __device__ inline __attribute__((always_inline)) void closure_level(const LatDes
 // only, 2 the edge tiles only (a tile of the other kind returns before any
 // barrier); a lattice on the learned closure runs its edge tiles with CL in
 // one launch and its inner tiles without in another.
+// part: 0 the tile, 1 only an inner tile, 2 only an edge tile.
 template <int S, int TY, int NT, bool NTS, int CM, bool CL = false>
 __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, int tyi, int part = 0) {
   using C = Codec<S>;
   using T = typename C::T;
   using R = typename C::R;
-  __shared__ __attribute__((aligned(16))) T lds1[9][TY + 4][T3_W1];
-  __shared__ __attribute__((aligned(16))) T lds2[9][TY + 2][T3_W2];
+  auto& lds1 = three_lds1<S, TY>();
+  auto& lds2 = three_lds2<S, TY>();
   constexpr int CLW = cl_waves<S, TY, NT>();
   constexpr bool CL_OWN = CL && cl_own_lds<S, TY, NT>();
   __shared__ __attribute__((aligned(16))) char cl_own[CL_OWN ? CL_FEAT_BYTES + CLW * CL_WAVE_BYTES : 16];
