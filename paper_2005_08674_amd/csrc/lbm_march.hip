@@ -12,8 +12,8 @@ namespace lbm {
 template <int S>
 static hipError_t launch_march_s(const LatDesc& L, int parity, int id, hipStream_t s) {
   int k = 0;
-#define X(a, m, b, h, p)                                                     \
-  if (id == k) return launch_march_t<S, a, m, b, true, p>(L, parity, s, h);  \
+#define X(a, m, b, h, p, n)                                               \
+  if (id == k) return launch_march_t<S, a, m, b, n, p>(L, parity, s, h);   \
   ++k;
   LBM_THREE_MARCH(X)
 #undef X

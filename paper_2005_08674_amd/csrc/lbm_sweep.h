@@ -18,6 +18,43 @@ __device__ inline void put(T* p, T v) {
   else *p = v;
 }
 
+// Load of a population at byte offset `off` from plane base `base`, as a
+// global-memory access: a buffer pointer read from a descriptor in memory
+// (the ensemble's) is otherwise a generic one, whose FLAT loads also count
+// against the LDS counter and so wait on the LDS traffic around them.
+template <class T>
+__device__ inline T ldg(const T* base, uint32_t off) {
+  using GC = const __attribute__((address_space(1))) char;
+  using GT = const __attribute__((address_space(1))) T;
+  return *(GT*)((GC*)reinterpret_cast<const char*>(base) + off);
+}
+
+// The nine planes of an output buffer as global-memory bases, each held
+// opaque in scalar registers: a store is then a scalar base plus the lane's
+// 32-bit byte offset, instead of a 64-bit address formed per plane on every
+// lane.
+template <class T>
+struct OutPlanes {
+  using GC = __attribute__((address_space(1))) char;
+  using GT = __attribute__((address_space(1))) T;
+  GC* p[9];
+  __device__ inline OutPlanes(T* B, int64_t plane) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      p[i] = (GC*)(reinterpret_cast<char*>(B + i * plane));
+      asm volatile("" : "+s"(p[i]));
+    }
+  }
+  template <bool NTS>
+  __device__ inline void put(int i, uint32_t off, T v) const {
+    GT* q = (GT*)(p[i] + off);
+    if constexpr (NTS)
+      __builtin_nontemporal_store(v, q);
+    else
+      *q = v;
+  }
+};
+
 // Load of one population; NTL selects a non-temporal load, used only for the
 // populations with c_x = 0, whose cache lines no other wavefront reads.
 template <class T>

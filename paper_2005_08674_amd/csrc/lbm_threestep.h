@@ -39,14 +39,16 @@ constexpr int two_step_waves() {
 // three-step tiles of 64 x TY, then the rectangle as 64-column strips cut
 // into chunks of about H rows, each walked down in rounds of MR rows
 // (three_step_march) with PF rounds of loads in flight; the march's level
-// rings take the tiles' level arrays.
-#define LBM_THREE_MARCH(X)  \
-  X(12, 11, 768, 128, 1)    \
-  X(12, 11, 768, 64, 1)     \
-  X(12, 11, 768, 96, 1)     \
-  X(12, 11, 768, 128, 2)    \
-  X(8, 7, 512, 128, 1)      \
-  X(8, 7, 512, 64, 1)
+// rings take the tiles' level arrays.  NT threads cover a round's MR x 68
+// level-(t + 1) nodes in one pass; NTS: non-temporal stores (plain stores
+// and chunks of 160 rows measured slower at 4096^2 in every format).
+#define LBM_THREE_MARCH(X)       \
+  X(12, 11, 768, 128, 1, true)   \
+  X(12, 11, 768, 96, 1, true)    \
+  X(12, 11, 768, 64, 1, true)    \
+  X(12, 11, 768, 128, 2, true)   \
+  X(8, 7, 512, 128, 1, true)     \
+  X(8, 7, 512, 64, 1, true)
 
 template <int S, int TY>
 constexpr bool three_step_fits() {
@@ -169,7 +171,7 @@ inline bool three_step_fits_store(int store, int id, bool closure) {
   ++k;
   LBM_THREE_STEP(X)
 #undef X
-#define X(a, m, b, h, p)                                                                        \
+#define X(a, m, b, h, p, n)                                                                     \
   if (id == k) {                                                                             \
     if (closure) return false;                                                               \
     switch (store) {                                                                         \
@@ -235,10 +237,7 @@ __device__ inline void three_step_march(const LatDesc& Ld, int parity, int xs, i
         const uint32_t ro[3] = {(idx + (uint32_t)pitch) * (uint32_t)sizeof(T), idx * (uint32_t)sizeof(T),
                                 (idx - (uint32_t)pitch) * (uint32_t)sizeof(T)};
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-          const char* __restrict__ Ai = reinterpret_cast<const char*>(A + i * plane);
-          raw[u][it][i] = *reinterpret_cast<const T*>(Ai + ro[1 + kCy[i]] - kCx[i] * (int)sizeof(T));
-        }
+        for (int i = 0; i < 9; ++i) raw[u][it][i] = ldg(A + i * plane, ro[1 + kCy[i]] - kCx[i] * (int)sizeof(T));
       }
     }
   };
@@ -247,16 +246,7 @@ __device__ inline void three_step_march(const LatDesc& Ld, int parity, int xs, i
   T* const l1 = &r1[0][0][0];
   T* const l2 = &r2[0][0][0];
   constexpr int P1 = (TY + 4) * T3_W1, P2 = (TY + 2) * T3_W2;
-  // per-plane output bases, held opaque in scalar registers so that each
-  // store is a scalar base plus the lane's 32-bit byte offset
-  using GC = __attribute__((address_space(1))) char;
-  using GT = __attribute__((address_space(1))) T;
-  GC* Bp[9];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    Bp[i] = (GC*)(reinterpret_cast<char*>(B + i * plane));
-    asm volatile("" : "+s"(Bp[i]));
-  }
+  const OutPlanes<T> out(B, plane);
   // ring slot of a row: su (the round's first row's slot, uniform) + r, wrapped once
   auto wrap = [](int v) { return v >= RR ? v - RR : v; };
   auto level1 = [&](const Base<R>& b, int j, int u) __attribute__((always_inline)) {
@@ -322,13 +312,7 @@ __device__ inline void three_step_march(const LatDesc& Ld, int parity, int xs, i
         collide<R, CM>(Ld, g, rho0, b, omega);
         const uint32_t off = (uint32_t)((lo + r) * pitch + xs + cx) * (uint32_t)sizeof(T);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-          GT* p = (GT*)(Bp[i] + off);
-          if constexpr (NTS)
-            __builtin_nontemporal_store(C::enc(g[i], Ld.es[i]), p);
-          else
-            *p = C::enc(g[i], Ld.es[i]);
-        }
+        for (int i = 0; i < 9; ++i) out.template put<NTS>(i, off, C::enc(g[i], Ld.es[i]));
       }
     }
   };

@@ -144,13 +144,13 @@ static const ThreeStepShape kThree[] = {
 #define X(a, b, c) {a, b, c, 0, 0, 0},
     LBM_THREE_STEP(X)
 #undef X
-#define X(a, m, b, h, p) {a, b, true, m, h, p},
+#define X(a, m, b, h, p, n) {a, b, n, m, h, p},
     LBM_THREE_MARCH(X)
 #undef X
 };
 static constexpr int kNumThree = sizeof(kThree) / sizeof(kThree[0]);
 static constexpr int kNumMarch = 0
-#define X(a, m, b, h, p) +1
+#define X(a, m, b, h, p, n) +1
     LBM_THREE_MARCH(X)
 #undef X
     ;
@@ -166,7 +166,8 @@ void three_step_name(int id, char* buf, size_t len) {
   }
   const ThreeStepShape& t = kThree[id];
   if (t.mr > 0)
-    snprintf(buf, len, "3step:64x%d/%d+march%dxh%d%s+xcdband+nts", t.ty, t.nt, t.mr, t.h, t.pf == 2 ? "+pf2" : "");
+    snprintf(buf, len, "3step:64x%d/%d+march%dxh%d%s+xcdband%s", t.ty, t.nt, t.mr, t.h, t.pf == 2 ? "+pf2" : "",
+             t.nts ? "+nts" : "");
   else
     snprintf(buf, len, "3step:64x%d/%d+xcdband%s", t.ty, t.nt, t.nts ? "+nts" : "");
 }

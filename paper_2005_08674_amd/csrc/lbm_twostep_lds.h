@@ -34,7 +34,7 @@ __device__ inline void tl_moments_global(const LatDesc& Ld, const typename Codec
   R g[9];
   const int64_t idx = (int64_t)y * Ld.pitch + x;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) g[i] = C::dec(A[i * Ld.plane + idx], Ld.ds[i]);
+  for (int i = 0; i < 9; ++i) g[i] = C::dec(ldg(A + i * Ld.plane, (uint32_t)idx * (uint32_t)sizeof(typename C::T)), Ld.ds[i]);
   moments<R>(g, R(Ld.rho0), b, m[0], m[1], m[2]);
 }
 
@@ -129,6 +129,7 @@ __device__ inline void two_step_tile(const LatDesc& Ld, int parity, int txi, int
   const int64_t plane = Ld.plane;
   const R rho0 = R(Ld.rho0), omega = R(Ld.omega);
   const Base<R> base(Ld);
+  const OutPlanes<T> out(B, plane);
 
   // Inner tile: every level t + 1 node (rows y0 - 1 .. y0 + TY, columns
   // x0 - 2 .. x0 + 65) is an interior lattice node, so no pull leaves the
@@ -154,8 +155,7 @@ __device__ inline void two_step_tile(const LatDesc& Ld, int parity, int txi, int
         R g[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-          const char* __restrict__ Ai = reinterpret_cast<const char*>(A + i * plane);
-          g[i] = C::dec(*reinterpret_cast<const T*>(Ai + ro[1 + kCy[i]] - kCx[i] * (int)sizeof(T)), Ld.ds[i]);
+          g[i] = C::dec(ldg(A + i * plane, ro[1 + kCy[i]] - kCx[i] * (int)sizeof(T)), Ld.ds[i]);
         }
         collide<R, CM>(Ld, g, rho0, base, omega);
 #pragma unroll
@@ -175,7 +175,7 @@ __device__ inline void two_step_tile(const LatDesc& Ld, int parity, int txi, int
         const uint32_t off = (uint32_t)((y0 + r) * pitch + (x0 + cx)) * (uint32_t)sizeof(T);
 #pragma unroll
         for (int i = 0; i < 9; ++i)
-          put<NTS>(reinterpret_cast<T*>(reinterpret_cast<char*>(B + i * plane) + off), C::enc(g[i], Ld.es[i]));
+          out.template put<NTS>(i, off, C::enc(g[i], Ld.es[i]));
       }
     }
   };
@@ -208,8 +208,7 @@ __device__ inline void two_step_tile(const LatDesc& Ld, int parity, int txi, int
     R g[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      const T* __restrict__ Ai = A + i * plane;
-      const R v = C::dec(Ai[srow[1 + kCy[i]] + (uint32_t)sxs[1 + kCx[i]]], Ld.ds[i]);
+      const R v = C::dec(ldg(A + i * plane, (srow[1 + kCy[i]] + (uint32_t)sxs[1 + kCx[i]]) * (uint32_t)sizeof(T)), Ld.ds[i]);
       g[i] = (unknown >> i) & 1u ? R(0) : v;
     }
     if (unknown) {
@@ -249,7 +248,7 @@ __device__ inline void two_step_tile(const LatDesc& Ld, int parity, int txi, int
     const uint32_t off = (uint32_t)(y * pitch + x) * (uint32_t)sizeof(T);
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-      put<NTS>(reinterpret_cast<T*>(reinterpret_cast<char*>(B + i * plane) + off), C::enc(g[i], Ld.es[i]));
+      out.template put<NTS>(i, off, C::enc(g[i], Ld.es[i]));
   }
 }
 
@@ -555,8 +554,7 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
         R g[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-          const char* __restrict__ Ai = reinterpret_cast<const char*>(A + i * plane);
-          g[i] = C::dec(*reinterpret_cast<const T*>(Ai + ro[1 + kCy[i]] - kCx[i] * (int)sizeof(T)), Ld.ds[i]);
+          g[i] = C::dec(ldg(A + i * plane, ro[1 + kCy[i]] - kCx[i] * (int)sizeof(T)), Ld.ds[i]);
         }
         collide<R, CM>(Ld, g, rho0, b, omega);
         if (keep) {
@@ -586,11 +584,11 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
       }
     }
   };
+  const OutPlanes<T> out(B, plane);
   auto store = [&](int x, int y, const R g[9]) {
     const uint32_t off = (uint32_t)(y * pitch + x) * (uint32_t)sizeof(T);
 #pragma unroll
-    for (int i = 0; i < 9; ++i)
-      put<NTS>(reinterpret_cast<T*>(reinterpret_cast<char*>(B + i * plane) + off), C::enc(g[i], Ld.es[i]));
+    for (int i = 0; i < 9; ++i) out.template put<NTS>(i, off, C::enc(g[i], Ld.es[i]));
   };
   auto level3 = [&](const Base<R>& b, auto edge) __attribute__((always_inline)) {
     constexpr bool E = decltype(edge)::value;
@@ -707,8 +705,7 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
       R g[9];
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        const T* __restrict__ Ai = A + i * plane;
-        const R v = C::dec(Ai[srow[1 + kCy[i]] + (uint32_t)sxs[1 + kCx[i]]], Ld.ds[i]);
+        const R v = C::dec(ldg(A + i * plane, (srow[1 + kCy[i]] + (uint32_t)sxs[1 + kCx[i]]) * (uint32_t)sizeof(T)), Ld.ds[i]);
         g[i] = (unknown >> i) & 1u ? R(0) : v;
       }
       nsbc_assign_correct<R>(g, unknown, edge_mc(e, x, y, mom0), rho0, b, Ld.corr_mode);
