@@ -10,22 +10,22 @@ namespace lbm {
 
 // March shape `id` (among the march shapes) in format S.
 template <int S>
-static hipError_t launch_march_s(const LatDesc& L, int parity, int id, hipStream_t s) {
+static hipError_t launch_march_s(const LatDesc& L, int parity, int id, hipStream_t s, bool ring) {
   int k = 0;
 #define X(a, m, b, h, p, n)                                               \
-  if (id == k) return launch_march_t<S, a, m, b, n, p>(L, parity, s, h);   \
+  if (id == k) return launch_march_t<S, a, m, b, n, p>(L, parity, s, h, ring); \
   ++k;
   LBM_THREE_MARCH(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_three_march(const LatDesc& L, int parity, int id, hipStream_t s) {
+hipError_t launch_three_march(const LatDesc& L, int parity, int id, hipStream_t s, bool ring) {
   switch (L.store) {
-    case ST_F64: return launch_march_s<ST_F64>(L, parity, id, s);
-    case ST_F32: return launch_march_s<ST_F32>(L, parity, id, s);
-    case ST_F16: return launch_march_s<ST_F16>(L, parity, id, s);
-    case ST_BF16: return launch_march_s<ST_BF16>(L, parity, id, s);
+    case ST_F64: return launch_march_s<ST_F64>(L, parity, id, s, ring);
+    case ST_F32: return launch_march_s<ST_F32>(L, parity, id, s, ring);
+    case ST_F16: return launch_march_s<ST_F16>(L, parity, id, s, ring);
+    case ST_BF16: return launch_march_s<ST_BF16>(L, parity, id, s, ring);
   }
   return hipErrorInvalidValue;
 }

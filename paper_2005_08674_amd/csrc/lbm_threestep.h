@@ -171,17 +171,16 @@ inline bool three_step_fits_store(int store, int id, bool closure) {
   ++k;
   LBM_THREE_STEP(X)
 #undef X
-#define X(a, m, b, h, p, n)                                                                     \
-  if (id == k) {                                                                             \
-    if (closure) return false;                                                               \
-    switch (store) {                                                                         \
-      case ST_F64: return three_step_fits<ST_F64, a>();                                      \
-      case ST_F32: return three_step_fits<ST_F32, a>();                                      \
-      case ST_F16: return three_step_fits<ST_F16, a>();                                      \
-      case ST_BF16: return three_step_fits<ST_BF16, a>();                                    \
-    }                                                                                        \
-    return false;                                                                            \
-  }                                                                                          \
+#define X(a, m, b, h, p, n)                                                                                    \
+  if (id == k) {                                                                                            \
+    switch (store) {                                                                                        \
+      case ST_F64: return three_step_fits<ST_F64, a>() && (!closure || three_step_fits_closure<ST_F64, a>()); \
+      case ST_F32: return three_step_fits<ST_F32, a>() && (!closure || three_step_fits_closure<ST_F32, a>()); \
+      case ST_F16: return three_step_fits<ST_F16, a>() && (!closure || three_step_fits_closure<ST_F16, a>()); \
+      case ST_BF16: return three_step_fits<ST_BF16, a>() && (!closure || three_step_fits_closure<ST_BF16, a>()); \
+    }                                                                                                       \
+    return false;                                                                                           \
+  }                                                                                                         \
   ++k;
   LBM_THREE_MARCH(X)
 #undef X
@@ -379,18 +378,20 @@ __global__ __launch_bounds__(NT, two_step_waves<S>()) void k_three_march(LatDesc
   three_step_march<S, TY, MR, NT, NTS, CM, PF>(L, parity, TL_TX * (1 + sx), ya, yb);
 }
 
-// One launch: the edge tiles and the march over the inner rectangle in
-// chunks of about h rows.
+// One launch: the edge tiles (unless !ring: a closure lattice's run in the
+// closure kernel) and the march over the inner rectangle in chunks of about
+// h rows.
 template <int S, int TY, int MR, int NT, bool NTS, int PF>
-inline hipError_t launch_march_t(const LatDesc& L, int parity, hipStream_t s, int h) {
+inline hipError_t launch_march_t(const LatDesc& L, int parity, hipStream_t s, int h, bool ring) {
   if constexpr (!three_step_fits<S, TY>()) {
     return hipErrorInvalidValue;
   } else {
     const int tiles_x = (L.nx + TL_TX - 1) / TL_TX, tiles_y = (L.ny + TY - 1) / TY;
     const int ix = inner_cols(L.nx), iy = inner_rows(L.ny, TY);
-    const int ring = tiles_x * tiles_y - ix * iy, ring8 = (ring + 7) / 8 * 8;
+    const int ring8 = ring ? (tiles_x * tiles_y - ix * iy + 7) / 8 * 8 : 0;
     int chunks, height;
     march_chunks(ix > 0 ? TY * iy : 0, h, chunks, height);
+    if (ring8 + ix * chunks == 0) return hipSuccess;
     const dim3 grid(ring8 + (ix * chunks + 7) / 8 * 8);
     if (L.coll == COLL_MRT)
       k_three_march<S, TY, MR, NT, NTS, COLL_MRT, PF>
@@ -402,8 +403,9 @@ inline hipError_t launch_march_t(const LatDesc& L, int parity, hipStream_t s, in
   }
 }
 
-// march shape `id` (among the march shapes) on one lattice (lbm_march.hip)
-hipError_t launch_three_march(const LatDesc& L, int parity, int id, hipStream_t s);
+// march shape `id` (among the march shapes) on one lattice, with its edge
+// tiles when `ring` (lbm_march.hip)
+hipError_t launch_three_march(const LatDesc& L, int parity, int id, hipStream_t s, bool ring);
 
 // three-step launch of a lattice with the learned closure (lbm_twostep_cl.hip)
 hipError_t launch_three_step_closure(const LatDesc& L, int parity, int id, hipStream_t s);

@@ -174,7 +174,15 @@ void three_step_name(int id, char* buf, size_t len) {
 
 bool three_step_supported(const LatDesc& L, int id) {
   return id >= 0 && id < kNumThree && two_step_supported(L) && L.nx >= TL_TX && L.ny >= kThree[id].ty &&
-         three_step_fits_store(L.store, id, L.closure && L.net) && !(kThree[id].mr > 0 && L.closure && L.net);
+         three_step_fits_store(L.store, id, L.closure && L.net);
+}
+
+// The tile shape whose edge tiles a march shape's closure lattice runs in
+// the closure kernel: the first tile shape with the march's tile rows.
+static int closure_tile_of(int id) {
+  for (int k = 0; k < kNumThree; ++k)
+    if (kThree[k].mr == 0 && kThree[k].ty == kThree[id].ty) return k;
+  return -1;
 }
 
 // A lattice on the learned closure takes two launches: its edge tiles with
@@ -187,10 +195,9 @@ bool three_step_supported(const LatDesc& L, int id) {
 hipError_t launch_three_step(const LatDesc& L, int parity, int id, hipStream_t s, hipStream_t side, hipEvent_t fork,
                              hipEvent_t join) {
   if (!three_step_supported(L, id)) return hipErrorInvalidValue;
-  if (kThree[id].mr > 0) {
-    const int mid = id - (kNumThree - kNumMarch);
-    return launch_three_march(L, parity, mid, s);
-  }
+  const bool march = kThree[id].mr > 0;
+  const int mid = id - (kNumThree - kNumMarch);
+  if (march && !(L.closure && L.net)) return launch_three_march(L, parity, mid, s, true);
   int part = 0;
   const bool forked = L.closure && L.net && side && fork && join;
   if (L.closure && L.net) {
@@ -199,12 +206,19 @@ hipError_t launch_three_step(const LatDesc& L, int parity, int id, hipStream_t s
       e = hipEventRecord(fork, s);
       if (e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
     }
-    if (e == hipSuccess) e = launch_three_step_closure(L, parity, id, forked ? side : s);
+    const int cid = march ? closure_tile_of(id) : id;
+    if (e == hipSuccess) e = cid >= 0 ? launch_three_step_closure(L, parity, cid, forked ? side : s) : hipErrorInvalidValue;
     if (forked && e == hipSuccess) e = hipEventRecord(join, side);
     if (e != hipSuccess) return e;
     part = 1;
   }
   hipError_t e = hipErrorInvalidValue;
+  if (march) {
+    // the closure kernel took the edge tiles: the march covers the inner rectangle
+    e = launch_three_march(L, parity, mid, s, false);
+    if (forked && e == hipSuccess) e = hipStreamWaitEvent(s, join, 0);
+    return e;
+  }
   switch (L.store) {
     case ST_F64: e = launch_three_s<ST_F64, false>(L, parity, id, s, part); break;
     case ST_F32: e = launch_three_s<ST_F32, false>(L, parity, id, s, part); break;

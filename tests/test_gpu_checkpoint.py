@@ -168,7 +168,7 @@ def _poison_all_but_state(lat):
 @pytest.mark.parametrize("store", ["f64", "f32", "f16", "bf16"])
 def test_every_launch_writes_every_node(store):
     from paper_2005_08674_amd import lbm
-    cases = [(203, 77), (64, 12), (130, 3), (3, 3)]
+    cases = [(203, 77), (330, 300), (64, 12), (130, 3), (3, 3)]
     for nx, ny in cases:
         launches = [("tile", t) for t in range(lbm.lbm_tile_count())]
         launches += [("multi", k) for k in range(lbm.lbm_two_step_count())]
@@ -211,6 +211,13 @@ def test_every_3d_shape_writes_every_node(q):
         for shape in range(lbm.lbm3d_shape_count()):
             g = Lattice3D(nx, ny, nz, 0.6, f, store=store, q=q)
             r = Lattice3D(nx, ny, nz, 0.6, f, store=store, q=q)
+            if store == "f32" and lbm.lbm3d_shape_describe(shape).startswith("pair:"):
+                # the two-node pair sweep takes the 16-bit formats only
+                with pytest.raises(lbm.LbmError):
+                    lbm.lbm3d_set_shape(g.ctx, shape)
+                g.close()
+                r.close()
+                continue
             lbm.lbm3d_set_shape(g.ctx, shape)
             lbm.lbm3d_set_shape(r.ctx, shape)
             g.step(1)
