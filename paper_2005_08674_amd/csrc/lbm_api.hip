@@ -463,13 +463,16 @@ int step_multi(lbm_ctx* c, int id) {
 }
 
 // Shape that runs a remainder of k steps (2 <= k <= 4): the autotuner's best
-// supported shape with k steps per launch, else (k = 2) the band-mapped two-step
-// shape 64x12/512 for FP64 or 64x20/768 for the other formats; -1 if none.
+// supported shape with k steps per launch, else (k = 2) the two-step shape
+// measured fastest at 4096^2 for the format (tiles 64x12/512 for FP64,
+// 64x20/768 for FP32, the 64x8 march for the 16-bit formats); -1 if none.
 int rem_shape(const lbm_ctx* c, int k) {
   if (k < 2 || k > 4) return -1;
   if (c->rem_best[k] >= 0 && multi_supported(c->L, c->rem_best[k])) return c->rem_best[k];
   if (k == 2) {
-    const char* want = c->p.store == LBM_STORE_F64 ? "2step:64x12/512+xcdband+nts" : "2step:64x20/768+xcdband+nts";
+    const char* want = c->p.store == LBM_STORE_F64   ? "2step:64x12/512+xcdband+nts"
+                       : c->p.store == LBM_STORE_F32 ? "2step:64x20/768+xcdband+nts"
+                                                     : "2step:64x8/512+march7xh96+xcdband+nts";
     char buf[64];
     for (int id = 0; id < lbm::num_two_step(); ++id) {
       lbm::two_step_name(id, buf, sizeof(buf));

@@ -412,6 +412,7 @@ bool two_supported(const lbm_ens* e, int id = -1) {
   const int n2 = lbm::num_two_step();
   for (const auto& d : e->descs) {
     if (!lbm::two_step_supported(d)) return false;
+    if (id >= 0 && id < n2 && lbm::two_step_is_march(id)) return false;
     if (id >= n2 && (lbm::three_step_is_march(id - n2) || !lbm::three_step_supported(d, id - n2))) return false;
   }
   return true;

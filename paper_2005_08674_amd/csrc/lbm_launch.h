@@ -19,6 +19,8 @@ hipError_t launch_step(const LatDesc& L, int parity, int tile, hipStream_t s);
 int num_two_step();
 void two_step_name(int id, char* buf, size_t len);
 bool two_step_supported(const LatDesc& L);
+// whether two-step shape id is a column march (single lattices only)
+bool two_step_is_march(int id);
 hipError_t launch_two_step(const LatDesc& L, int parity, int id, hipStream_t s);
 // output tile rows of two-step shape id (0 if invalid), and the smallest over all shapes
 int two_step_tile_rows(int id);

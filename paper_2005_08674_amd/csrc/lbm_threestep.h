@@ -407,6 +407,170 @@ inline hipError_t launch_march_t(const LatDesc& L, int parity, hipStream_t s, in
 // tiles when `ring` (lbm_march.hip)
 hipError_t launch_three_march(const LatDesc& L, int parity, int id, hipStream_t s, bool ring);
 
+// ------------------------------------------------------------------ two-step column march
+// Candidate shapes of the marched two-step sweep (t -> t + 2), one launch of
+// NT-thread blocks: the edge tiles as two-step tiles of 64 x TY
+// (two_step_tile, part 2), then the inner rectangle of the two-step tiling
+// (tiles 1 .. (nx - 67) / 64 across, 1 .. (ny - TY - 2) / TY up) as
+// 64-column strips in chunks of about H rows, walked down in rounds of MR
+// rows (two_step_march) whose level ring takes the tile's level array.
+#define LBM_TWO_MARCH(X)      \
+  X(12, 11, 768, 96, true)    \
+  X(12, 11, 768, 128, true)   \
+  X(8, 7, 512, 96, true)
+
+__host__ __device__ inline int inner_rows2(int ny, int ty) { return ny >= ty + 2 ? (ny - ty - 2) / ty : 0; }
+
+// Two-step column march over output rows ya .. yb - 1 of the 64 columns xs
+// .. xs + 63 (all inside the two-step tiling's inner rectangle): round j
+// computes level t + 1 on rows ya - 1 + j MR + [0, MR) (66 columns, pulled
+// from HBM) into a ring of MR + 2 rows (row y in slot (y - ya + 1) mod
+// (MR + 2)) and level t + 2 one row behind, stored.  The loads of round
+// j + 1 are issued before round j's level t + 2.  Same per-node arithmetic
+// and codec rounding as the tiles: bit-identical to single steps.
+template <int S, int TY, int MR, int NT, bool NTS, int CM>
+__device__ inline void two_step_march(const LatDesc& Ld, int parity, int xs, int ya, int yb) {
+  static_assert(MR >= 3 && MR + 2 <= TY + 4, "march shape");
+  using C = Codec<S>;
+  using T = typename C::T;
+  using R = typename C::R;
+  constexpr int RR = MR + 2, W1 = TL_TX + 2;
+  constexpr int NI = (MR * W1 + NT - 1) / NT;
+  auto& r1 = two_lds<S, TY>();
+  T* const l1 = &r1[0][0][0];
+  constexpr int P1 = (TY + 4) * TL_W;
+  const int tid = threadIdx.x;
+  const T* __restrict__ A = static_cast<const T*>(buf_of(Ld, parity));
+  const OutPlanes<T> out(static_cast<T*>(buf_of(Ld, parity ^ 1)), Ld.plane);
+  const int pitch = Ld.pitch;
+  const int64_t plane = Ld.plane;
+  const R rho0 = R(Ld.rho0), omega = R(Ld.omega);
+  const int rounds = (yb - ya + 2 + MR - 1) / MR;
+  auto wrap = [](int v) { return v >= RR ? v - RR : v; };
+  T raw[NI][9];
+  auto fetch = [&](int j) __attribute__((always_inline)) {
+    const int q = ya - 1 + j * MR, n = min(MR, yb + 1 - q);
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+      const int k = tid + it * NT;
+      if (k < n * W1) {
+        const int r = k / W1, cx = k - r * W1;
+        const uint32_t idx = (uint32_t)((q + r) * pitch + (xs - 1 + cx));
+        const uint32_t ro[3] = {(idx + (uint32_t)pitch) * (uint32_t)sizeof(T), idx * (uint32_t)sizeof(T),
+                                (idx - (uint32_t)pitch) * (uint32_t)sizeof(T)};
+#pragma unroll
+        for (int i = 0; i < 9; ++i) raw[it][i] = ldg(A + i * plane, ro[1 + kCy[i]] - kCx[i] * (int)sizeof(T));
+      }
+    }
+  };
+  auto level1 = [&](const Base<R>& b, int j) __attribute__((always_inline)) {
+    const int q = ya - 1 + j * MR, n = min(MR, yb + 1 - q);
+    const int su = (j * MR) % RR;
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+      const int k = tid + it * NT;
+      if (k < n * W1) {
+        const int r = k / W1, cx = k - r * W1;
+        R g[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) g[i] = C::dec(raw[it][i], Ld.ds[i]);
+        collide<R, CM>(Ld, g, rho0, b, omega);
+        const uint32_t o = (uint32_t)(wrap(su + r) * TL_W + cx);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) l1[o + i * P1] = C::enc(g[i], Ld.es[i]);
+      }
+    }
+  };
+  auto level2 = [&](const Base<R>& b, int j) __attribute__((always_inline)) {
+    const int lo = max(ya - 2 + j * MR, ya), hi = min(ya - 2 + (j + 1) * MR, yb);
+    const int su = (lo - ya + 1) % RR;
+    constexpr int N2 = MR * TL_TX;
+#pragma unroll
+    for (int it = 0; it < (N2 + NT - 1) / NT; ++it) {
+      const int k = tid + it * NT;
+      if (k < (hi - lo) * TL_TX) {
+        const int r = k / TL_TX, cx = k - r * TL_TX;
+        const int s0 = wrap(su + r);
+        const int sm = s0 == 0 ? RR - 1 : s0 - 1, sp = s0 == RR - 1 ? 0 : s0 + 1;
+        const uint32_t om = (uint32_t)(sm * TL_W + cx + 1), o0 = (uint32_t)(s0 * TL_W + cx + 1),
+                       op = (uint32_t)(sp * TL_W + cx + 1);
+        R g[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+          g[i] = C::dec(l1[(kCy[i] > 0 ? om : (kCy[i] < 0 ? op : o0)) + i * P1 - kCx[i]], Ld.ds[i]);
+        collide<R, CM>(Ld, g, rho0, b, omega);
+        const uint32_t off = (uint32_t)((lo + r) * pitch + xs + cx) * (uint32_t)sizeof(T);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) out.template put<NTS>(i, off, C::enc(g[i], Ld.es[i]));
+      }
+    }
+  };
+  // round j + 1's level t + 1 overwrites ring rows round j's level t + 2 has
+  // read: a barrier between them, and one before the next level t + 2
+  auto run = [&](const Base<R>& b) __attribute__((always_inline)) {
+    fetch(0);
+    level1(b, 0);
+    __syncthreads();
+    for (int j = 0; j < rounds; ++j) {
+      const bool more = j + 1 < rounds;
+      if (more) fetch(j + 1);
+      level2(b, j);
+      __syncthreads();
+      if (more) level1(b, j + 1);
+      __syncthreads();
+    }
+  };
+  const Base<R> base(Ld);
+  Base<R> b = base;
+  if (base.zero) {
+    b.zero = true;
+    run(b);
+  } else {
+    b.zero = false;
+    run(b);
+  }
+}
+
+// Blocks below ring8 take the two-step tiling's edge tiles (ring_tile order,
+// padded to a multiple of 8), the others the strips' chunks in XCD bands.
+template <int S, int TY, int MR, int NT, bool NTS, int CM>
+__global__ __launch_bounds__(NT, two_step_waves<S>()) void k_two_march(LatDesc L, int parity, int tiles_x,
+                                                                     int tiles_y, int ring8, int height,
+                                                                     int chunks) {
+  const int ix = inner_cols(L.nx), iy = inner_rows2(L.ny, TY);
+  const int b = blockIdx.x;
+  if (b < ring8) {
+    int txi, tyi;
+    if (!ring_tile(b, tiles_x, tiles_y, ix, iy, txi, tyi)) return;  // padding: the block leaves before any barrier
+    two_step_tile<S, TY, NT, NTS, CM>(L, parity, txi, tyi, 2);
+    return;
+  }
+  const int m = b - ring8, items = ix * chunks, per = (items + 7) >> 3;
+  const int item = (m & 7) * per + (m >> 3);
+  if (item >= items) return;
+  const int c = item / ix, sx = item - c * ix;
+  const int ya = TY + c * height, yb = min(ya + height, TY * (iy + 1));
+  two_step_march<S, TY, MR, NT, NTS, CM>(L, parity, TL_TX * (1 + sx), ya, yb);
+}
+
+template <int S, int TY, int MR, int NT, bool NTS>
+inline hipError_t launch_two_march_t(const LatDesc& L, int parity, hipStream_t s, int h) {
+  const int tiles_x = (L.nx + TL_TX - 1) / TL_TX, tiles_y = (L.ny + TY - 1) / TY;
+  const int ix = inner_cols(L.nx), iy = inner_rows2(L.ny, TY);
+  const int ring8 = (tiles_x * tiles_y - ix * iy + 7) / 8 * 8;
+  int chunks, height;
+  march_chunks(ix > 0 ? TY * iy : 0, h, chunks, height);
+  const dim3 grid(ring8 + (ix * chunks + 7) / 8 * 8);
+  if (L.coll == COLL_MRT)
+    k_two_march<S, TY, MR, NT, NTS, COLL_MRT><<<grid, dim3(NT), 0, s>>>(L, parity, tiles_x, tiles_y, ring8, height, chunks);
+  else
+    k_two_march<S, TY, MR, NT, NTS, COLL_BGK><<<grid, dim3(NT), 0, s>>>(L, parity, tiles_x, tiles_y, ring8, height, chunks);
+  return hipGetLastError();
+}
+
+// two-step march shape `id` (among the two-step march shapes) on one lattice (lbm_march.hip)
+hipError_t launch_two_march(const LatDesc& L, int parity, int id, hipStream_t s);
+
 // three-step launch of a lattice with the learned closure (lbm_twostep_cl.hip)
 hipError_t launch_three_step_closure(const LatDesc& L, int parity, int id, hipStream_t s);
 

@@ -66,17 +66,29 @@ __global__ __launch_bounds__(NT, two_step_waves<S>()) void k_two_step(LatDesc L,
   two_step_tile<S, TY, NT, NTS, CM>(L, parity, txi, tyi);
 }
 
+// the tile shapes first, then the marched ones (mr > 0: rows per round, h:
+// chunk rows)
 struct TwoStepShape {
   int ty, nt;
   bool nts;
-  int map;
+  int map, mr, h;
 };
 static const TwoStepShape kTwo[] = {
-#define X(a, b, c, d) {a, b, c, d},
+#define X(a, b, c, d) {a, b, c, d, 0, 0},
     LBM_TWO_STEP(X)
+#undef X
+#define X(a, m, b, h, n) {a, b, n, 2, m, h},
+    LBM_TWO_MARCH(X)
 #undef X
 };
 static constexpr int kNumTwo = sizeof(kTwo) / sizeof(kTwo[0]);
+static constexpr int kNumTwoMarch = 0
+#define X(a, m, b, h, n) +1
+    LBM_TWO_MARCH(X)
+#undef X
+    ;
+
+bool two_step_is_march(int id) { return id >= 0 && id < kNumTwo && kTwo[id].mr > 0; }
 
 int num_two_step() { return kNumTwo; }
 
@@ -86,8 +98,11 @@ void two_step_name(int id, char* buf, size_t len) {
     return;
   }
   const TwoStepShape& t = kTwo[id];
-  snprintf(buf, len, "2step:64x%d/%d%s%s", t.ty, t.nt, t.map == 1 ? "+xcd8" : (t.map == 2 ? "+xcdband" : ""),
-           t.nts ? "+nts" : "");
+  if (t.mr > 0)
+    snprintf(buf, len, "2step:64x%d/%d+march%dxh%d+xcdband%s", t.ty, t.nt, t.mr, t.h, t.nts ? "+nts" : "");
+  else
+    snprintf(buf, len, "2step:64x%d/%d%s%s", t.ty, t.nt, t.map == 1 ? "+xcd8" : (t.map == 2 ? "+xcdband" : ""),
+             t.nts ? "+nts" : "");
 }
 
 bool two_step_supported(const LatDesc& L) {
@@ -122,6 +137,7 @@ static hipError_t launch_two_s(const LatDesc& L, int parity, int id, hipStream_t
 hipError_t launch_two_step(const LatDesc& L, int parity, int id, hipStream_t s) {
   // the two-step sweep has no closure path
   if (!two_step_supported(L) || (L.closure && L.net)) return hipErrorInvalidValue;
+  if (id >= 0 && id < kNumTwo && kTwo[id].mr > 0) return launch_two_march(L, parity, id - (kNumTwo - kNumTwoMarch), s);
   switch (L.store) {
     case ST_F64: return launch_two_s<ST_F64>(L, parity, id, s);
     case ST_F32: return launch_two_s<ST_F32>(L, parity, id, s);

@@ -108,13 +108,22 @@ __device__ inline void tl_nsbc(const LatDesc& Ld, R g[9], uint32_t unknown, int 
 // (encoded exactly as a store would write it, decoded on every read), which
 // halves the LDS of the 16-bit formats.  CM is the collision model, fixed at
 // compile time (COLL_BGK or COLL_MRT).
+// The level array of a two-step block, one allocation per kernel whichever
+// path (tile or column march) takes it.
+template <int S, int TY>
+__device__ inline auto two_lds() -> typename Codec<S>::T (&)[9][TY + 4][TL_W] {
+  __shared__ __attribute__((aligned(16))) typename Codec<S>::T a[9][TY + 4][TL_W];
+  return a;
+}
+
+// part 2: only an edge tile (an inner tile's block leaves at once).
 template <int S, int TY, int NT, bool NTS, int CM>
-__device__ inline void two_step_tile(const LatDesc& Ld, int parity, int txi, int tyi) {
+__device__ inline void two_step_tile(const LatDesc& Ld, int parity, int txi, int tyi, int part = 0) {
   using C = Codec<S>;
   using T = typename C::T;
   using R = typename C::R;
   constexpr int TH = TY + 4;  // LDS rows (margin of up to 2 each side)
-  __shared__ T lds[9][TH][TL_W];
+  auto& lds = two_lds<S, TY>();
 
   const int nx = Ld.nx, ny = Ld.ny;
   const int x0 = txi * TL_TX, y0 = tyi * TY;
@@ -136,6 +145,7 @@ __device__ inline void two_step_tile(const LatDesc& Ld, int parity, int txi, int
   // lattice and no NSBC node occurs: the loops drop those checks (same
   // arithmetic, same bits) and have trip counts known at compile time.
   const bool inner = x0 >= 3 && x0 + TL_TX + 3 <= nx && y0 >= 2 && y0 + TY + 2 <= ny;
+  if (part == 2 && inner) return;
   // Inlined twice, with the base state's u_b = 0 flag a known constant in
   // each copy (the per-node arithmetic keeps only the branch that runs).
   auto inner_sweep = [&](const Base<R>& base) __attribute__((always_inline)) {
