@@ -188,6 +188,26 @@ def test_remainder_of_two_after_three_step_launches():
         b.close()
 
 
+@pytest.mark.parametrize("store", ["f64", "f32", "f16", "bf16"])
+def test_march_shapes_on_many_strips_and_chunks(store):
+    """Every column-march shape (two- and three-step) on a 1000 x 999 lattice: 14 strips of 8 to 11
+    chunks each (a shorter last chunk) beside the edge tiles; 11 steps (three-step: 3 launches and a
+    two-step remainder; two-step: 5 launches and a single step) give the bits of 11 single steps."""
+    from paper_2005_08674_amd import lbm
+    march = [k for k in range(lbm.lbm_two_step_count()) if "+march" in lbm.lbm_two_step_describe(k)]
+    assert len(march) >= 4
+    for shape in march:
+        name = lbm.lbm_two_step_describe(shape)
+        print(f"[march] {store} {name} 1000x999", flush=True)
+        if lbm.lbm_two_step_steps(shape) == 3 and not _three_step_takes(name, store, 1000, 999):
+            with pytest.raises(lbm.LbmError):
+                _pair(1000, 999, store, shape, 11)
+            continue
+        pa, pb = _pair(1000, 999, store, shape, 11)
+        assert np.isfinite(pa).all()
+        assert np.array_equal(pa, pb), (store, name, np.argwhere(pa != pb)[:5])
+
+
 def test_full_size_4096_tuned_launch_against_single_and_oracle():
     """4096^2 FP32 (the HBM workload) in the launch the benchmark times (the autotuner's cached choice,
     three steps per launch): 99 steps (33 launches) bit-identical to the single-step path and within
