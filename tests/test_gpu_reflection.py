@@ -112,7 +112,8 @@ def test_pulse128_reflection_by_storage(store, bar):
 def test_vortex512x256_is_absorbed():
     """512x256 fp32 vortex convected out through the right edge over 5000 steps, measured
     against a 2048x1024 reference: the energy of the difference stays a small fraction of the
-    vortex's energy (the paper's "fully absorbed")."""
+    vortex's energy (the paper's "fully absorbed").  Bars a quarter above the measured values
+    (R_E 1.61e-2, final 7.9e-5), so that a change to NSBC that reflects more fails here."""
     from paper_2005_08674_amd.reflection import ReflectionRun
     w = W.vortex_512x256()
     ex = w.extra
@@ -124,8 +125,8 @@ def test_vortex512x256_is_absorbed():
     res = run.run(5000, every=50, respect_clean_time=False)
     s = res["series"]
     print(f"\n[vortex 512x256 fp32] R_E={res['R_E']:.4e} final={s[-1]:.4e} at t={res['horizon']}", flush=True)
-    assert s[-1] < 1e-2
-    assert res["R_E"] < 5e-2
+    assert s[-1] < 1e-4
+    assert res["R_E"] < 2e-2
 
 
 def test_committed_closure_closed_loop_against_nsbc():
