@@ -521,6 +521,9 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
 
   const int nx = Ld.nx, ny = Ld.ny;
   const int x0 = min(txi * TL_TX, nx - TL_TX), y0 = min(tyi * TY, ny - TY);
+  // a last tile moved back to end at the lattice edge stores only the nodes
+  // its neighbour does not (the overlap holds the same values in both)
+  const int xo = txi * TL_TX, yo = tyi * TY;
   const int tid = threadIdx.x;
   const T* __restrict__ A = static_cast<const T*>(buf_of(Ld, parity));
   T* __restrict__ B = static_cast<T*>(buf_of(Ld, parity ^ 1));
@@ -612,7 +615,7 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
 #pragma unroll
         for (int i = 0; i < 9; ++i) g[i] = C::dec(lds2[i][r + 1 - kCy[i]][cx + 1 - kCx[i]], Ld.ds[i]);
         collide<R, CM>(Ld, g, rho0, b, omega);
-        if (!E || interior_node(x0 + cx, y0 + r)) store(x0 + cx, y0 + r, g);
+        if (!E || (interior_node(x0 + cx, y0 + r) && x0 + cx >= xo && y0 + r >= yo)) store(x0 + cx, y0 + r, g);
       }
     }
   };
@@ -792,7 +795,7 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
       }
       nsbc_assign_correct<R>(g, unknown, edge_mc(e, x, y, mom2), rho0, b, Ld.corr_mode);
       collide<R, CM>(Ld, g, rho0, b, omega);
-      store(x, y, g);
+      if (x >= xo && y >= yo) store(x, y, g);
     }
   }
 }

@@ -217,8 +217,9 @@ def test_two_step_equals_single_steps_every_shape(store):
         e = Ensemble(members, fields)
         for m, fa in enumerate(far):
             e.set_farfield(m, *fa)
-        if lbm.lbm_two_step_steps(shape) == 3:
-            # these members include 3 x 3 and 130 x 3 lattices: three-step shapes are refused
+        if lbm.lbm_two_step_steps(shape) == 3 or "+march" in lbm.lbm_two_step_describe(shape):
+            # these members include 3 x 3 and 130 x 3 lattices: three-step shapes are refused, and
+            # the column marches take single lattices only
             with pytest.raises(lbm.LbmError):
                 e.set_two_step(shape)
             e.close()
@@ -246,7 +247,9 @@ def test_two_step_graph_replays_and_autotune():
         b.set_farfield(m, *fa)
     best, times = a.autotune_two_step(reps=3)
     assert 0 <= best < lbm.lbm_two_step_count() == len(times)
-    assert min(t for k, t in enumerate(times) if lbm.lbm_two_step_steps(k) == 2) > 0
+    march = ["+march" in lbm.lbm_two_step_describe(k) for k in range(len(times))]
+    assert min(t for k, t in enumerate(times) if lbm.lbm_two_step_steps(k) == 2 and not march[k]) > 0
+    assert all(t < 0 for k, t in enumerate(times) if march[k])  # single lattices only
     assert a.t == 0
     for rep in range(4):
         if rep == 2:
