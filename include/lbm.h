@@ -307,7 +307,14 @@ int lbm_set_fused(lbm_ctx* ctx, int on);
  * way the state crosses HBM about once per launch (2 x 9 x bytes per stored
  * population per node, plus margins re-read from L2), and results are
  * bit-identical to single steps: intermediate levels are held in the
- * storage format exactly as a store would write them.
+ * storage format exactly as a store would write them.  Column-march shapes
+ * ("...+march<MR>xh<H>..."): one launch runs the edge tiles (the ring of
+ * 64 x TY tiles around the inner tiles' rectangle) as tiles and the inner
+ * rectangle as 64-column strips cut into chunks of about H rows, each
+ * walked down in rounds of MR rows with every intermediate level's last
+ * MR + 2 rows in an LDS ring, so no row margin is recomputed; same
+ * conditions and results as the tile shapes of that TY.  They are single-
+ * lattice shapes (lbm_ens_set_two_step refuses them).
  * lbm_two_step_count / lbm_two_step_describe ("2step:..." or "3step:...")
  * list the candidate shapes and lbm_two_step_steps gives a shape's steps per
  * launch; lbm_set_two_step selects one (-1 turns the sweeps off, the
@@ -319,8 +326,10 @@ int lbm_set_fused(lbm_ctx* ctx, int on);
  * learned closure on (lbm_set_closure) the three-step shapes carry it: in
  * their edge tiles the network corrects m_c of every single-normal edge
  * node at each of the three levels, from the previous level, as the
- * single-step edge kernel does (bit-identical to closure single steps);
- * two-step shapes and remainders then run as closure single steps.  The
+ * single-step edge kernel does (bit-identical to closure single steps; the
+ * edge tiles then run in a kernel of their own on a second stream beside
+ * the inner tiles or strips); two-step shapes and remainders then run as
+ * closure single steps.  The
  * overlap option and periodic edges always use the single-step kernels.
  * lbm_autotune_two_step times every shape the lattice supports (`reps`
  * runs of consecutive launches covering at least 24 steps each, median,

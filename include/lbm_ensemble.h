@@ -135,9 +135,10 @@ int lbm_ens_autotune(lbm_ens* e, int32_t reps, int32_t* best, float* times_ms);
  * (lbm_two_step_steps); the ensemble lays every member's tiles out in one
  * list whose contiguous eighths run on the 8 XCDs (the shape's own block map
  * is not used).  lbm_ens_set_two_step selects a shape (-1, the default,
- * turns the sweeps off); LBM_ERR_UNSUPPORTED unless every member has NSBC on
- * all four edges and, for a three-step shape, is at least 64 x its tile rows
- * (FP64: tile rows <= 12).  While a member runs the learned closure the
+ * turns the sweeps off); LBM_ERR_UNSUPPORTED for the column-march shapes
+ * (single lattices only) and unless every member has NSBC on all four edges
+ * and, for a three-step shape, is at least 64 x its tile rows (FP64: tile
+ * rows <= 12).  While a member runs the learned closure the
  * ensemble steps singly.  lbm_ens_autotune_two_step times every shape the
  * members take (median of `reps` launches, after one warm-up; the state is
  * not advanced), selects the one with the least time per step and writes its
