@@ -194,18 +194,19 @@ __host__ __device__ inline void march_chunks(int rows, int h, int& chunks, int& 
   height = chunks > 0 ? (rows + chunks - 1) / chunks : 0;
 }
 
-// Column march (TY: the level arrays' tile rows): the block owns the 64 columns xs .. xs + 63 of output rows
-// ya .. yb - 1, all inside the inner tiles' rectangle (no clamp, no NSBC),
-// and walks down them in rounds of MR rows: round j computes level t + 1 on
-// rows ya - 2 + j MR + [0, MR) (68 columns, pulled from HBM), level t + 2
-// one row behind (66 columns) and level t + 3 one row behind that (the 64
-// output columns, stored).  Each level keeps its last MR + 2 rows in a ring
-// in the tile's level arrays (row y of level t + 1 in slot (y - ya + 2) mod
-// (MR + 2) of lds1, of level t + 2 in (y - ya + 1) mod (MR + 2) of lds2), so apart from the two ends of
-// the strip no row is computed twice.  The loads of level t + 1 run PF
-// rounds ahead of their use: those of round j + PF are issued before round
-// j's levels t + 2 and t + 3.  Per node the arithmetic and the codec
-// rounding are the tiles': bit-identical to single steps.
+// Column march (TY: the level arrays' tile rows): the block owns the 64
+// columns xs .. xs + 63 of output rows ya .. yb - 1, all inside the inner
+// tiles' rectangle (no clamp, no NSBC), and walks down them in rounds of MR
+// rows: round j computes level t + 1 on rows ya - 2 + j MR + [0, MR) (68
+// columns, pulled from HBM), level t + 2 one row behind (66 columns) and
+// level t + 3 one row behind that (the 64 output columns, stored).  Each
+// level keeps its last MR + 2 rows in a ring in the tile's level arrays (row
+// y of level t + 1 in slot (y - ya + 2) mod (MR + 2) of lds1, of level t + 2
+// in (y - ya + 1) mod (MR + 2) of lds2), so apart from the two ends of the
+// strip no row is computed twice.  The loads of level t + 1 run PF rounds
+// ahead of their use: those of round j + PF are issued before round j's
+// levels t + 2 and t + 3.  Per node the arithmetic and the codec rounding
+// are the tiles': bit-identical to single steps.
 template <int S, int TY, int MR, int NT, bool NTS, int CM, int PF>
 __device__ inline void three_step_march(const LatDesc& Ld, int parity, int xs, int ya, int yb) {
   static_assert(MR >= 5 && MR <= TY && (PF == 1 || PF == 2), "march shape");
