@@ -201,9 +201,10 @@ static int closure_tile_of(int id) {
   return -1;
 }
 
-// A lattice on the learned closure takes two launches: its edge tiles with
-// the network and its inner tiles with the plain sweep (both read buffer
-// `parity` and write disjoint parts of the other).  With a second stream
+// One launch of a tile or march shape, except on the learned closure, which
+// takes two: its edge tiles with the network and its inner tiles (tile
+// shapes) or inner strips (march shapes) with the plain sweep (both read
+// buffer `parity` and write disjoint parts of the other).  With a second stream
 // `side` the edge-tile kernel runs there, forked from `s` after the work
 // already on it (event `fork`) and joined back before what follows (event
 // `join`), so the two kernels share the GPU; without one they run in turn
