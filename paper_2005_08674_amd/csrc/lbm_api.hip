@@ -108,6 +108,7 @@ int check_params(const lbm_params* p) {
 }
 
 void set_scales(LatDesc& L, int store, int k) {
+  L.sc = (store == LBM_STORE_F64 || store == LBM_STORE_F32) ? 1.0f : (float)std::ldexp(1.0, k);
   for (int i = 0; i < 9; ++i) {
     if (store == LBM_STORE_F64 || store == LBM_STORE_F32) {
       L.ds[i] = 1.0f;

@@ -47,9 +47,15 @@ enum Coll : int { COLL_BGK = 0, COLL_MRT = 1 };
 // nearest even.
 template <int S> struct Codec;
 
+// dec(v, s) = raw(v) * s and enc(v, s) = raw_enc(v * s): raw and raw_enc
+// convert without the per-population scale (the stored value itself in the
+// arithmetic type); `scaled` marks the formats whose scale is not 1.
 template <> struct Codec<ST_F64> {
   using T = double;
   using R = double;
+  static constexpr bool scaled = false;
+  __device__ static inline R raw(T v) { return v; }
+  __device__ static inline T raw_enc(R v) { return v; }
   __device__ static inline R dec(T v, float) { return v; }
   __device__ static inline T enc(R v, float) { return v; }
 };
@@ -57,6 +63,9 @@ template <> struct Codec<ST_F64> {
 template <> struct Codec<ST_F32> {
   using T = float;
   using R = float;
+  static constexpr bool scaled = false;
+  __device__ static inline R raw(T v) { return v; }
+  __device__ static inline T raw_enc(R v) { return v; }
   __device__ static inline R dec(T v, float) { return v; }
   __device__ static inline T enc(R v, float) { return v; }
 };
@@ -64,20 +73,29 @@ template <> struct Codec<ST_F32> {
 template <> struct Codec<ST_F16> {
   using T = _Float16;
   using R = float;
-  __device__ static inline R dec(T v, float s) { return static_cast<float>(v) * s; }
-  __device__ static inline T enc(R v, float s) { return static_cast<_Float16>(v * s); }
+  static constexpr bool scaled = true;
+  __device__ static inline R raw(T v) { return static_cast<float>(v); }
+  // The value is rounded to f32 first and then to f16 in every kernel: the
+  // empty asm keeps the compiler from folding the operation that produced v
+  // into one mixed-precision FMA that rounds to f16 once (it does so at some
+  // sites and not at others, and the two roundings differ in rare ties).
+  __device__ static inline T raw_enc(R v) {
+    __asm__("" : "+v"(v));
+    return static_cast<_Float16>(v);
+  }
+  __device__ static inline R dec(T v, float s) { return raw(v) * s; }
+  __device__ static inline T enc(R v, float s) { return raw_enc(v * s); }
 };
 
 template <> struct Codec<ST_BF16> {
   using T = uint16_t;
   using R = float;
-  __device__ static inline R dec(T v, float s) {
-    return __uint_as_float(static_cast<uint32_t>(v) << 16) * s;
-  }
-  __device__ static inline T enc(R v, float s) {
-    // round to nearest, ties to even (one v_cvt_pk_bf16_f32 on gfx950)
-    return __builtin_bit_cast(T, static_cast<__bf16>(v * s));
-  }
+  static constexpr bool scaled = true;
+  __device__ static inline R raw(T v) { return __uint_as_float(static_cast<uint32_t>(v) << 16); }
+  // round to nearest, ties to even (one v_cvt_pk_bf16_f32 on gfx950)
+  __device__ static inline T raw_enc(R v) { return __builtin_bit_cast(T, static_cast<__bf16>(v)); }
+  __device__ static inline R dec(T v, float s) { return raw(v) * s; }
+  __device__ static inline T enc(R v, float s) { return raw_enc(v * s); }
 };
 
 // ------------------------------------------------------------------ lattice descriptor
@@ -99,6 +117,7 @@ struct LatDesc {
   double pb[9];     // P_i(u_b) = 1 + 3 c_i.u_b + 9/2 (c_i.u_b)^2 - 3/2 |u_b|^2
   float ds[9];      // decode scale per population
   float es[9];      // encode scale per population
+  float sc;         // 2^k: ds[i] = w_i / sc, es[i] = sc / w_i for the 16-bit formats; 1 otherwise
   const void* net;  // closure network (lbm::mlp::Net) or null
   int32_t closure;  // 1: the edge kernel replaces NSBC's m_c by the network's, NSBC as fallback
   int32_t ub_zero;  // 1 when u_b = (0, 0): the arithmetic drops the u_b terms
@@ -287,6 +306,75 @@ template <> __device__ inline const float* mrt_k<float>(const LatDesc& L) { retu
 // CM fixes the model at compile time (COLL_BGK or COLL_MRT); the default -1
 // reads it from the descriptor.
 template <class R, int CM = -1>
+__device__ inline void collide(const LatDesc& L, R g[9], R rho0, const Base<R>& b, R omega);
+
+// BGK on the stored values s_i = g_i / d_i of the 16-bit formats (d_i =
+// w_i / 2^k, three values: rest, axis, diagonal).  The moments are summed
+// from s by weight class, and with g^eq_i = w_i X_i (eq. feq_1) the update
+// g_i <- g_i + omega (g^eq_i - g_i) becomes s_i <- s_i + omega (2^k X_i - s_i):
+// the weights cancel, so no population is scaled on the way in or out.  For
+// u_b = 0 it is written per pair of opposite directions as in bgk.
+template <class R>
+__device__ inline void bgk_stored(R s[9], R rho0, const Base<R>& b, R omega, R d0, R d1, R d5, R sc) {
+  const R drho = fma(d0, s[0], fma(d1, (s[1] + s[2]) + (s[3] + s[4]), d5 * ((s[5] + s[6]) + (s[7] + s[8]))));
+  const R jx = fma(d1, s[1] - s[2], d5 * ((s[5] - s[6]) + (s[8] - s[7])));
+  const R jy = fma(d1, s[3] - s[4], d5 * ((s[5] - s[6]) + (s[7] - s[8])));
+  const R ir = recip(rho0 + drho);
+  const R rho = rho0 + drho;
+  if (b.zero) {
+    const R dux = jx * ir, duy = jy * ir;
+    const R e = fma(-rho, R(1.5) * fma(dux, dux, duy * duy), drho);
+    const R r45 = R(4.5) * rho, r3 = R(3) * rho;
+    const R om1 = R(1) - omega, osc = omega * sc;
+    s[0] = fma(osc, e, om1 * s[0]);
+    auto pair = [&](int i, int j, R a) {
+      const R even = fma(r45 * a, a, e), odd = r3 * a;
+      s[i] = fma(osc, even + odd, om1 * s[i]);
+      s[j] = fma(osc, even - odd, om1 * s[j]);
+    };
+    pair(1, 2, dux);
+    pair(3, 4, duy);
+    pair(5, 6, dux + duy);
+    pair(7, 8, duy - dux);
+    return;
+  }
+  const R dux = (jx - drho * b.ubx) * ir, duy = (jy - drho * b.uby) * ir;
+  const R q = R(1.5) * (dux * (dux + R(2) * b.ubx) + duy * (duy + R(2) * b.uby));
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const R a = R(kCx[i]) * dux + R(kCy[i]) * duy;
+    const R bi2 = R(2) * (R(kCx[i]) * b.ubx + R(kCy[i]) * b.uby);
+    const R x = fma(drho, b.pb[i], rho * fma(a, fma(R(4.5), a + bi2, R(3)), -q));
+    s[i] = fma(omega, fma(sc, x, -s[i]), s[i]);
+  }
+}
+
+// Collision of an interior node on its values as stored (Codec::raw, back
+// with Codec::raw_enc), the form every sweep uses for interior nodes; NSBC
+// and velocity-edge nodes decode, take collide and encode.  The 32/64-bit
+// formats store g itself; the 16-bit ones take bgk_stored for BGK and the
+// scaled round trip for MRT (the same operations as decode, collide,
+// encode).
+template <int S, int CM>
+__device__ inline void collide_stored(const LatDesc& L, typename Codec<S>::R s[9], typename Codec<S>::R rho0,
+                                      const Base<typename Codec<S>::R>& b, typename Codec<S>::R omega) {
+  using R = typename Codec<S>::R;
+  if constexpr (!Codec<S>::scaled) {
+    collide<R, CM>(L, s, rho0, b, omega);
+  } else {
+    if (CM == COLL_MRT || (CM < 0 && L.coll == COLL_MRT)) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) s[i] *= L.ds[i];
+      collide<R, COLL_MRT>(L, s, rho0, b, omega);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) s[i] *= L.es[i];
+    } else {
+      bgk_stored<R>(s, rho0, b, omega, R(L.ds[0]), R(L.ds[1]), R(L.ds[5]), R(L.sc));
+    }
+  }
+}
+
+template <class R, int CM>
 __device__ inline void collide(const LatDesc& L, R g[9], R rho0, const Base<R>& b, R omega) {
   if (CM == COLL_MRT || (CM < 0 && L.coll == COLL_MRT)) {
     const R* kp = mrt_k<R>(L);

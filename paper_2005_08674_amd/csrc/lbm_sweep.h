@@ -64,7 +64,8 @@ __device__ inline T get(const T* p, bool nt) {
 }
 
 // One bulk tile: BX x (BY * NYT) interior nodes starting at tile (txi, tyi)
-// of lattice L -- pull, BGK, store (eqs. lbe_0, lbe_1, feq_1).
+// of lattice L -- pull, collide on the values as stored (collide_stored),
+// store (eqs. lbe_0, lbe_1, feq_1).
 template <int S, int BX, int BY, int NYT, bool NTS, bool NTL>
 __device__ inline void bulk_tile_body(const LatDesc& L, int parity, int txi, int tyi) {
   using C = Codec<S>;
@@ -94,9 +95,8 @@ __device__ inline void bulk_tile_body(const LatDesc& L, int parity, int txi, int
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         const char* Ai = reinterpret_cast<const char*>(A + i * plane);
-        g[j][i] = C::dec(get(reinterpret_cast<const T*>(Ai + ro[1 + kCy[i]] - kCx[i] * (int)sizeof(T)),
-                             NTL && kCx[i] == 0),
-                         L.ds[i]);
+        g[j][i] = C::raw(get(reinterpret_cast<const T*>(Ai + ro[1 + kCy[i]] - kCx[i] * (int)sizeof(T)),
+                             NTL && kCx[i] == 0));
       }
     }
   }
@@ -104,11 +104,11 @@ __device__ inline void bulk_tile_body(const LatDesc& L, int parity, int txi, int
   for (int j = 0; j < NYT; ++j) {
     const int y = y0 + j * BY;
     if (y <= L.ny - 2) {
-      collide<R>(L, g[j], rho0, base, omega);
+      collide_stored<S, -1>(L, g[j], rho0, base, omega);
       const uint32_t off = (uint32_t)(y * pitch + x) * (uint32_t)sizeof(T);
 #pragma unroll
       for (int i = 0; i < 9; ++i)
-        put<NTS>(reinterpret_cast<T*>(reinterpret_cast<char*>(B + i * plane) + off), C::enc(g[j][i], L.es[i]));
+        put<NTS>(reinterpret_cast<T*>(reinterpret_cast<char*>(B + i * plane) + off), C::raw_enc(g[j][i]));
     }
   }
 }

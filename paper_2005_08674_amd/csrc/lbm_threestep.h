@@ -259,11 +259,11 @@ __device__ inline void three_step_march(const LatDesc& Ld, int parity, int xs, i
         const int r = k / T3_W1, cx = k - r * T3_W1;
         R g[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = C::dec(raw[u][it][i], Ld.ds[i]);
-        collide<R, CM>(Ld, g, rho0, b, omega);
+        for (int i = 0; i < 9; ++i) g[i] = C::raw(raw[u][it][i]);
+        collide_stored<S, CM>(Ld, g, rho0, b, omega);
         const uint32_t o = (uint32_t)(wrap(su + r) * T3_W1 + cx);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) l1[o + i * P1] = C::enc(g[i], Ld.es[i]);
+        for (int i = 0; i < 9; ++i) l1[o + i * P1] = C::raw_enc(g[i]);
       }
     }
   };
@@ -284,11 +284,11 @@ __device__ inline void three_step_march(const LatDesc& Ld, int parity, int xs, i
         R g[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i)
-          g[i] = C::dec(l1[(kCy[i] > 0 ? om : (kCy[i] < 0 ? op : o0)) + i * P1 - kCx[i]], Ld.ds[i]);
-        collide<R, CM>(Ld, g, rho0, b, omega);
+          g[i] = C::raw(l1[(kCy[i] > 0 ? om : (kCy[i] < 0 ? op : o0)) + i * P1 - kCx[i]]);
+        collide_stored<S, CM>(Ld, g, rho0, b, omega);
         const uint32_t ow = (uint32_t)(sm * T3_W2 + cx);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) l2[ow + i * P2] = C::enc(g[i], Ld.es[i]);
+        for (int i = 0; i < 9; ++i) l2[ow + i * P2] = C::raw_enc(g[i]);
       }
     }
   };
@@ -308,11 +308,11 @@ __device__ inline void three_step_march(const LatDesc& Ld, int parity, int xs, i
         R g[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i)
-          g[i] = C::dec(l2[(kCy[i] > 0 ? om : (kCy[i] < 0 ? op : o0)) + i * P2 - kCx[i]], Ld.ds[i]);
-        collide<R, CM>(Ld, g, rho0, b, omega);
+          g[i] = C::raw(l2[(kCy[i] > 0 ? om : (kCy[i] < 0 ? op : o0)) + i * P2 - kCx[i]]);
+        collide_stored<S, CM>(Ld, g, rho0, b, omega);
         const uint32_t off = (uint32_t)((lo + r) * pitch + xs + cx) * (uint32_t)sizeof(T);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) out.template put<NTS>(i, off, C::enc(g[i], Ld.es[i]));
+        for (int i = 0; i < 9; ++i) out.template put<NTS>(i, off, C::raw_enc(g[i]));
       }
     }
   };
@@ -474,11 +474,11 @@ __device__ inline void two_step_march(const LatDesc& Ld, int parity, int xs, int
         const int r = k / W1, cx = k - r * W1;
         R g[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = C::dec(raw[it][i], Ld.ds[i]);
-        collide<R, CM>(Ld, g, rho0, b, omega);
+        for (int i = 0; i < 9; ++i) g[i] = C::raw(raw[it][i]);
+        collide_stored<S, CM>(Ld, g, rho0, b, omega);
         const uint32_t o = (uint32_t)(wrap(su + r) * TL_W + cx);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) l1[o + i * P1] = C::enc(g[i], Ld.es[i]);
+        for (int i = 0; i < 9; ++i) l1[o + i * P1] = C::raw_enc(g[i]);
       }
     }
   };
@@ -498,11 +498,11 @@ __device__ inline void two_step_march(const LatDesc& Ld, int parity, int xs, int
         R g[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i)
-          g[i] = C::dec(l1[(kCy[i] > 0 ? om : (kCy[i] < 0 ? op : o0)) + i * P1 - kCx[i]], Ld.ds[i]);
-        collide<R, CM>(Ld, g, rho0, b, omega);
+          g[i] = C::raw(l1[(kCy[i] > 0 ? om : (kCy[i] < 0 ? op : o0)) + i * P1 - kCx[i]]);
+        collide_stored<S, CM>(Ld, g, rho0, b, omega);
         const uint32_t off = (uint32_t)((lo + r) * pitch + xs + cx) * (uint32_t)sizeof(T);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) out.template put<NTS>(i, off, C::enc(g[i], Ld.es[i]));
+        for (int i = 0; i < 9; ++i) out.template put<NTS>(i, off, C::raw_enc(g[i]));
       }
     }
   };

@@ -164,12 +164,10 @@ __device__ inline void two_step_tile(const LatDesc& Ld, int parity, int txi, int
                                 (idx - (uint32_t)pitch) * (uint32_t)sizeof(T)};
         R g[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-          g[i] = C::dec(ldg(A + i * plane, ro[1 + kCy[i]] - kCx[i] * (int)sizeof(T)), Ld.ds[i]);
-        }
-        collide<R, CM>(Ld, g, rho0, base, omega);
+        for (int i = 0; i < 9; ++i) g[i] = C::raw(ldg(A + i * plane, ro[1 + kCy[i]] - kCx[i] * (int)sizeof(T)));
+        collide_stored<S, CM>(Ld, g, rho0, base, omega);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) lds[i][1 + r][cx] = C::enc(g[i], Ld.es[i]);
+        for (int i = 0; i < 9; ++i) lds[i][1 + r][cx] = C::raw_enc(g[i]);
       }
     }
     __syncthreads();
@@ -180,12 +178,11 @@ __device__ inline void two_step_tile(const LatDesc& Ld, int parity, int txi, int
         const int r = k / TL_TX, cx = k - r * TL_TX;
         R g[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = C::dec(lds[i][r + 2 - kCy[i]][cx + 2 - kCx[i]], Ld.ds[i]);
-        collide<R, CM>(Ld, g, rho0, base, omega);
+        for (int i = 0; i < 9; ++i) g[i] = C::raw(lds[i][r + 2 - kCy[i]][cx + 2 - kCx[i]]);
+        collide_stored<S, CM>(Ld, g, rho0, base, omega);
         const uint32_t off = (uint32_t)((y0 + r) * pitch + (x0 + cx)) * (uint32_t)sizeof(T);
 #pragma unroll
-        for (int i = 0; i < 9; ++i)
-          out.template put<NTS>(i, off, C::enc(g[i], Ld.es[i]));
+        for (int i = 0; i < 9; ++i) out.template put<NTS>(i, off, C::raw_enc(g[i]));
       }
     }
   };
@@ -218,17 +215,30 @@ __device__ inline void two_step_tile(const LatDesc& Ld, int parity, int txi, int
     R g[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      const R v = C::dec(ldg(A + i * plane, (srow[1 + kCy[i]] + (uint32_t)sxs[1 + kCx[i]]) * (uint32_t)sizeof(T)), Ld.ds[i]);
+      const R v = C::raw(ldg(A + i * plane, (srow[1 + kCy[i]] + (uint32_t)sxs[1 + kCx[i]]) * (uint32_t)sizeof(T)));
       g[i] = (unknown >> i) & 1u ? R(0) : v;
     }
+    // a boundary node decodes, takes NSBC and collide, and encodes; an
+    // interior one collides on its values as stored (as the single-step
+    // edge and bulk kernels do)
     if (unknown) {
+      if constexpr (C::scaled) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) g[i] *= Ld.ds[i];
+      }
       auto mom = [&](int xx, int yy, R m[3]) { tl_moments_global<S>(Ld, A, xx, yy, base, m); };
       tl_nsbc<R>(Ld, g, unknown, x, y, rho0, base, mom);
+      collide<R, CM>(Ld, g, rho0, base, omega);
+      if constexpr (C::scaled) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) g[i] *= Ld.es[i];
+      }
+    } else {
+      collide_stored<S, CM>(Ld, g, rho0, base, omega);
     }
-    collide<R, CM>(Ld, g, rho0, base, omega);
     // encoded as the single-step path's store would write it
 #pragma unroll
-    for (int i = 0; i < 9; ++i) lds[i][ly0 + r][cx] = C::enc(g[i], Ld.es[i]);
+    for (int i = 0; i < 9; ++i) lds[i][ly0 + r][cx] = C::raw_enc(g[i]);
   }
   __syncthreads();
 
@@ -250,15 +260,26 @@ __device__ inline void two_step_tile(const LatDesc& Ld, int parity, int txi, int
     R g[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      const R v = C::dec(lds[i][lys[1 + kCy[i]]][lxs[1 + kCx[i]]], Ld.ds[i]);
+      const R v = C::raw(lds[i][lys[1 + kCy[i]]][lxs[1 + kCx[i]]]);
       g[i] = (unknown >> i) & 1u ? R(0) : v;
     }
-    if (unknown) tl_nsbc<R>(Ld, g, unknown, x, y, rho0, base, mom1);
-    collide<R, CM>(Ld, g, rho0, base, omega);
+    if (unknown) {
+      if constexpr (C::scaled) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) g[i] *= Ld.ds[i];
+      }
+      tl_nsbc<R>(Ld, g, unknown, x, y, rho0, base, mom1);
+      collide<R, CM>(Ld, g, rho0, base, omega);
+      if constexpr (C::scaled) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) g[i] *= Ld.es[i];
+      }
+    } else {
+      collide_stored<S, CM>(Ld, g, rho0, base, omega);
+    }
     const uint32_t off = (uint32_t)(y * pitch + x) * (uint32_t)sizeof(T);
 #pragma unroll
-    for (int i = 0; i < 9; ++i)
-      out.template put<NTS>(i, off, C::enc(g[i], Ld.es[i]));
+    for (int i = 0; i < 9; ++i) out.template put<NTS>(i, off, C::raw_enc(g[i]));
   }
 }
 
@@ -566,13 +587,11 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
                                 (idx - (uint32_t)pitch) * (uint32_t)sizeof(T)};
         R g[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-          g[i] = C::dec(ldg(A + i * plane, ro[1 + kCy[i]] - kCx[i] * (int)sizeof(T)), Ld.ds[i]);
-        }
-        collide<R, CM>(Ld, g, rho0, b, omega);
+        for (int i = 0; i < 9; ++i) g[i] = C::raw(ldg(A + i * plane, ro[1 + kCy[i]] - kCx[i] * (int)sizeof(T)));
+        collide_stored<S, CM>(Ld, g, rho0, b, omega);
         if (keep) {
 #pragma unroll
-          for (int i = 0; i < 9; ++i) lds1[i][r][cx] = C::enc(g[i], Ld.es[i]);
+          for (int i = 0; i < 9; ++i) lds1[i][r][cx] = C::raw_enc(g[i]);
         }
       }
     }
@@ -588,20 +607,26 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
         const int r = k / T3_W2, cx = k - r * T3_W2;
         R g[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = C::dec(lds1[i][r + 1 - kCy[i]][cx + 1 - kCx[i]], Ld.ds[i]);
-        collide<R, CM>(Ld, g, rho0, b, omega);
+        for (int i = 0; i < 9; ++i) g[i] = C::raw(lds1[i][r + 1 - kCy[i]][cx + 1 - kCx[i]]);
+        collide_stored<S, CM>(Ld, g, rho0, b, omega);
         if (!E || interior_node(x0 - 1 + cx, y0 - 1 + r)) {
 #pragma unroll
-          for (int i = 0; i < 9; ++i) lds2[i][r][cx] = C::enc(g[i], Ld.es[i]);
+          for (int i = 0; i < 9; ++i) lds2[i][r][cx] = C::raw_enc(g[i]);
         }
       }
     }
   };
   const OutPlanes<T> out(B, plane);
+  // store of decoded values (an edge node's) and of values as stored (an interior node's)
   auto store = [&](int x, int y, const R g[9]) {
     const uint32_t off = (uint32_t)(y * pitch + x) * (uint32_t)sizeof(T);
 #pragma unroll
     for (int i = 0; i < 9; ++i) out.template put<NTS>(i, off, C::enc(g[i], Ld.es[i]));
+  };
+  auto store_raw = [&](int x, int y, const R s[9]) {
+    const uint32_t off = (uint32_t)(y * pitch + x) * (uint32_t)sizeof(T);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) out.template put<NTS>(i, off, C::raw_enc(s[i]));
   };
   auto level3 = [&](const Base<R>& b, auto edge) __attribute__((always_inline)) {
     constexpr bool E = decltype(edge)::value;
@@ -613,9 +638,9 @@ __device__ inline void three_step_tile(const LatDesc& Ld, int parity, int txi, i
         const int r = k / TL_TX, cx = k - r * TL_TX;
         R g[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = C::dec(lds2[i][r + 1 - kCy[i]][cx + 1 - kCx[i]], Ld.ds[i]);
-        collide<R, CM>(Ld, g, rho0, b, omega);
-        if (!E || (interior_node(x0 + cx, y0 + r) && x0 + cx >= xo && y0 + r >= yo)) store(x0 + cx, y0 + r, g);
+        for (int i = 0; i < 9; ++i) g[i] = C::raw(lds2[i][r + 1 - kCy[i]][cx + 1 - kCx[i]]);
+        collide_stored<S, CM>(Ld, g, rho0, b, omega);
+        if (!E || (interior_node(x0 + cx, y0 + r) && x0 + cx >= xo && y0 + r >= yo)) store_raw(x0 + cx, y0 + r, g);
       }
     }
   };
