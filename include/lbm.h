@@ -328,8 +328,10 @@ int lbm_set_fused(lbm_ctx* ctx, int on);
  * node at each of the three levels, from the previous level, as the
  * single-step edge kernel does (bit-identical to closure single steps; the
  * edge tiles then run in a kernel of their own on a second stream beside
- * the inner tiles or strips); two-step shapes and remainders then run as
- * closure single steps.  The
+ * the inner tiles or strips; each launch's edge-tile kernel waits only for
+ * the previous launch's inner part, and before lbm_step returns the stream
+ * has waited for the last of them); two-step shapes and remainders then run
+ * as closure single steps.  The
  * overlap option and periodic edges always use the single-step kernels.
  * lbm_autotune_two_step times every shape the lattice supports (`reps`
  * runs of consecutive launches covering at least 24 steps each, median,

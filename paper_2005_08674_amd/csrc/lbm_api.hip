@@ -309,6 +309,9 @@ struct lbm_ctx {
   int64_t two_n = 0;
   // multi-step sweep shape (-1: off)
   int two_step = -1;
+  // a closure launch's wait of the stream for its edge-tile kernel (on the
+  // second stream) deferred to the next launch or to the end of lbm_step
+  bool join_pending = false;
   // shape per steps-per-launch k (2..4) that runs a remainder of k steps
   // after launches of the selected shape (the autotuner's best shape with
   // that many steps, else a default)
@@ -427,10 +430,37 @@ bool multi_supported(const lbm::LatDesc& L, int id) {
                                   : lbm::three_step_supported(L, id - lbm::num_two_step());
 }
 // (a closure lattice's edge-tile kernel runs on the context's second stream)
-hipError_t launch_multi(const lbm_ctx* c, int parity, int id) {
+hipError_t launch_multi(const lbm_ctx* c, int parity, int id, int flags = 0) {
   return id < lbm::num_two_step()
              ? lbm::launch_two_step(c->L, parity, id, c->stream)
-             : lbm::launch_three_step(c->L, parity, id - lbm::num_two_step(), c->stream, c->side, c->ev_bulk, c->ev_edge);
+             : lbm::launch_three_step(c->L, parity, id - lbm::num_two_step(), c->stream, c->side, c->ev_bulk,
+                                      c->ev_edge, flags);
+}
+// Whether launch `id` runs a closure lattice's edge tiles on the second stream.
+bool forks_closure(const lbm_ctx* c, int id) {
+  return id >= lbm::num_two_step() && c->L.closure && c->L.net && c->side && c->ev_bulk && c->ev_edge;
+}
+// One launch of a run of consecutive launches: a closure launch leaves the
+// stream's wait for its edge-tile kernel pending (the next launch issues it
+// before its own kernel on the stream, settle_join otherwise).
+hipError_t launch_multi_run(const lbm_ctx* c, int parity, int id, bool& pending) {
+  if (!forks_closure(c, id)) {
+    if (pending) {
+      pending = false;
+      const hipError_t e = hipStreamWaitEvent(c->stream, c->ev_edge, 0);
+      if (e != hipSuccess) return e;
+    }
+    return launch_multi(c, parity, id);
+  }
+  const hipError_t e = launch_multi(c, parity, id, lbm::kJoinDefer | (pending ? lbm::kJoinPrev : 0));
+  pending = true;  // (also after a failure: waiting for the last recorded edge-tile kernel is harmless)
+  return e;
+}
+// The stream waits for the last edge-tile kernel of the run, if one is pending.
+hipError_t settle_join(const lbm_ctx* c, bool& pending) {
+  if (!pending) return hipSuccess;
+  pending = false;
+  return hipStreamWaitEvent(c->stream, c->ev_edge, 0);
 }
 void multi_name(int id, char* buf, size_t len) {
   if (id < lbm::num_two_step())
@@ -454,8 +484,11 @@ int step_multi(lbm_ctx* c, int id) {
     }
     c->ev_two.push_back(1);
   }
+  if (t[0]) HIPCHK(settle_join(c, c->join_pending));
   if (t[0]) HIPCHK(hipEventRecord(t[0], c->stream));
-  HIPCHK(launch_multi(c, c->parity, id));
+  HIPCHK(launch_multi_run(c, c->parity, id, c->join_pending));
+  // (timed launches take the edge-tile kernel into their interval)
+  if (t[1]) HIPCHK(settle_join(c, c->join_pending));
   if (t[1]) HIPCHK(hipEventRecord(t[1], c->stream));
   // the last level is in the other buffer: the launch wrote buffer parity ^ 1
   c->parity ^= 1;
@@ -616,20 +649,21 @@ int lbm_step(lbm_ctx* c, int32_t n) {
   int32_t s = 0;
   if (use_two_step(c)) {
     const int k = multi_steps(c->two_step);
-    for (; s + k <= n; s += k) {
-      int rc = step_multi(c, c->two_step);
-      if (rc) return rc;
-    }
+    int rc = LBM_OK;
+    for (; s + k <= n && rc == LBM_OK; s += k) rc = step_multi(c, c->two_step);
     // a remainder of two or more steps: one launch of a shape with that
     // many steps instead of single steps (same results)
-    if (n - s >= 2) {
+    if (rc == LBM_OK && n - s >= 2) {
       const int r = rem_shape(c, n - s);
       if (r >= 0) {
-        int rc = step_multi(c, r);
-        if (rc) return rc;
+        rc = step_multi(c, r);
         s += multi_steps(r);
       }
     }
+    // nothing else runs on the stream before the last edge-tile kernel is done
+    const hipError_t e = settle_join(c, c->join_pending);
+    if (rc) return rc;
+    HIPCHK(e);
   }
   for (; s < n; ++s) {
     int rc = step_once(c);
@@ -923,8 +957,9 @@ int lbm_autotune_two_step(lbm_ctx* c, int32_t reps, int32_t* best, float* times_
   StateSnapshot snap;
   if (int r = snap.save(c)) return r;
   int par = c->parity;
+  bool pending = false;  // as in lbm_step: a closure launch's wait for its edge-tile kernel
   auto launch = [&](int id) {
-    const hipError_t e = launch_multi(c, par, id);
+    const hipError_t e = launch_multi_run(c, par, id, pending);
     par ^= 1;  // a multi-step launch writes its last level to the other buffer
     return e;
   };
@@ -942,9 +977,15 @@ int lbm_autotune_two_step(lbm_ctx* c, int32_t reps, int32_t* best, float* times_
     hipError_t e = launch(id);
     const int runs = (kTuneRunSteps + multi_steps(id) - 1) / multi_steps(id);  // launches per timed run
     for (int r = 0; r < reps && e == hipSuccess; ++r) {
-      e = hipEventRecord(ev[2 * r], c->stream);
+      e = settle_join(c, pending);
+      if (e == hipSuccess) e = hipEventRecord(ev[2 * r], c->stream);
       for (int k = 0; k < runs && e == hipSuccess; ++k) e = launch(id);
+      if (e == hipSuccess) e = settle_join(c, pending);
       if (e == hipSuccess) e = hipEventRecord(ev[2 * r + 1], c->stream);
+    }
+    {
+      const hipError_t e2 = settle_join(c, pending);
+      if (e == hipSuccess) e = e2;
     }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     std::vector<float> ts(reps);

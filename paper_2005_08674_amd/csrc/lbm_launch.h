@@ -32,8 +32,15 @@ bool three_step_supported(const LatDesc& L, int id);
 // whether three-step shape id is a column march (single lattices only)
 bool three_step_is_march(int id);
 // (with the learned closure: edge tiles on `side` beside the inner tiles on s when side, fork and join are given)
+// Flags of a closure launch on two streams.  kJoinPrev: s waits for the
+// previous launch's edge-tile kernel (the last record of join) before this
+// launch's kernel on s.  kJoinDefer: s does not wait for this launch's
+// edge-tile kernel on return; the caller issues that wait (the next launch
+// with kJoinPrev, or hipStreamWaitEvent(s, join)) before s runs anything else
+// that touches the lattice.
+constexpr int kJoinPrev = 1, kJoinDefer = 2;
 hipError_t launch_three_step(const LatDesc& L, int parity, int id, hipStream_t s, hipStream_t side = nullptr,
-                             hipEvent_t fork = nullptr, hipEvent_t join = nullptr);
+                             hipEvent_t fork = nullptr, hipEvent_t join = nullptr, int flags = 0);
 int three_step_tile_rows(int id);
 int three_step_min_rows();
 // ensemble two-step: one block per list entry (member, 64-column tile x, tile y); lat < 0 = padding

@@ -209,8 +209,17 @@ static int closure_tile_of(int id) {
 // already on it (event `fork`) and joined back before what follows (event
 // `join`), so the two kernels share the GPU; without one they run in turn
 // on `s`.
+// A closure launch on two streams: the edge-tile kernel on `side` after
+// everything already on s (the fork), the inner part on s.  Launch n's
+// edge-tile kernel needs launch n - 1's inner part done (it reads that
+// part's output and overwrites the buffer that part read) and launch n's
+// inner part needs launch n - 1's edge-tile kernel done (the same, the other
+// way); with kJoinDefer on every launch but the last and kJoinPrev on every
+// launch but the first, those are the only waits, so the edge-tile kernels,
+// the longer of the two, follow one another on `side` without a round trip
+// through s.
 hipError_t launch_three_step(const LatDesc& L, int parity, int id, hipStream_t s, hipStream_t side, hipEvent_t fork,
-                             hipEvent_t join) {
+                             hipEvent_t join, int flags) {
   if (!three_step_supported(L, id)) return hipErrorInvalidValue;
   const bool march = kThree[id].mr > 0;
   const int mid = id - (kNumThree - kNumMarch);
@@ -225,15 +234,18 @@ hipError_t launch_three_step(const LatDesc& L, int parity, int id, hipStream_t s
     }
     const int cid = march ? closure_tile_of(id) : id;
     if (e == hipSuccess) e = cid >= 0 ? launch_three_step_closure(L, parity, cid, forked ? side : s) : hipErrorInvalidValue;
+    // s waits for the previous launch's edge-tile kernel before join is recorded anew
+    if (forked && (flags & kJoinPrev) && e == hipSuccess) e = hipStreamWaitEvent(s, join, 0);
     if (forked && e == hipSuccess) e = hipEventRecord(join, side);
     if (e != hipSuccess) return e;
     part = 1;
   }
+  const bool wait_end = forked && !(flags & kJoinDefer);
   hipError_t e = hipErrorInvalidValue;
   if (march) {
     // the closure kernel took the edge tiles: the march covers the inner rectangle
     e = launch_three_march(L, parity, mid, s, false);
-    if (forked && e == hipSuccess) e = hipStreamWaitEvent(s, join, 0);
+    if (wait_end && e == hipSuccess) e = hipStreamWaitEvent(s, join, 0);
     return e;
   }
   switch (L.store) {
@@ -242,7 +254,7 @@ hipError_t launch_three_step(const LatDesc& L, int parity, int id, hipStream_t s
     case ST_F16: e = launch_three_s<ST_F16, false>(L, parity, id, s, part); break;
     case ST_BF16: e = launch_three_s<ST_BF16, false>(L, parity, id, s, part); break;
   }
-  if (forked && e == hipSuccess) e = hipStreamWaitEvent(s, join, 0);
+  if (wait_end && e == hipSuccess) e = hipStreamWaitEvent(s, join, 0);
   return e;
 }
 
