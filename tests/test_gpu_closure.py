@@ -535,6 +535,49 @@ def test_closure_in_three_step_sweep_is_bit_identical(store):
         assert ran > 0
 
 
+@pytest.mark.parametrize("store", ["f32", "f16"])
+def test_closure_launch_chain_is_bit_identical(store):
+    """Ten closure launches in one lbm_step (the edge-tile kernel on the second stream joined only
+    once, at the end) on a ragged square lattice whose inner strips border the edge tiles on all
+    four sides give the bits of closure single steps, for a march shape and a tile shape; the
+    same launches one lbm_step at a time agree too."""
+    from paper_2005_08674_amd import lbm
+    from paper_2005_08674_amd.lattice import Lattice
+    p = _oracle_params(53)
+    tr = _trainer(p)
+    tr.set_normalization(np.zeros(96, np.float32), np.full(96, 0.5, np.float32), np.full(3, 0.02, np.float32))
+    blob = tr.export(50.0, 1.0, 0.0)
+    names = [lbm.lbm_two_step_describe(i) for i in range(lbm.lbm_two_step_count())]
+    nx, ny, u0 = 520, 460, (0.05, -0.02)
+    dv, ux, uy = W.lamb_oseen(nx, ny, nx - 8.0, ny * 0.4, 6.0, 0.03, u0)
+    dp, _, _ = W.gaussian_pulses(nx, ny, [(1e-3, 6.0, 6.0, 5.0), (1e-3, 6.0, nx * 0.5, ny - 6.0)])
+    f = (dv + dp, ux, uy)
+    kw = dict(store=store, m0=(1.0, u0[0], u0[1]), ubase=u0, beta=0.1)
+    ref = Lattice(nx, ny, 0.58, f, **kw)
+    lbm.lbm_set_closure(ref.ctx, blob.data_ptr(), 1)
+    ref.step(30)
+    want = ref.populations().cpu().numpy()
+    ref.close()
+    shapes = ["3step:64x12/768+march11xh64+xcdband+nts", "3step:64x12/512+xcdband+nts", "3step:64x16/512+xcdband+nts"]
+    ran = []
+    for name in shapes:
+        for per_call in (30, 3):
+            g = Lattice(nx, ny, 0.58, f, **kw)
+            lbm.lbm_set_closure(g.ctx, blob.data_ptr(), 1)
+            try:
+                lbm.lbm_set_two_step(g.ctx, names.index(name))
+            except lbm.LbmError:  # a shape whose LDS cannot also hold the closure's
+                g.close()
+                continue
+            for _ in range(30 // per_call):
+                g.step(per_call)
+            got = g.populations().cpu().numpy()
+            g.close()
+            ran.append(name)
+            assert np.array_equal(got, want), (store, name, per_call)
+    assert shapes[0] in ran
+
+
 def test_closure_three_step_autotune_and_trained_network():
     """With the committed network: the two-step shapes are refused for closure lattices by the tuner
     (negative time), a three-step shape is chosen, and 2048 x 64 steps agree bit for bit with closure
