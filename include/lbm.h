@@ -139,7 +139,9 @@ int lbm_set_farfield(lbm_ctx* ctx, double beta, double rho_ref, double ux_ref, d
 int lbm_set_velocity_edge(lbm_ctx* ctx, double ux, double uy);
 
 /* Advance n >= 0 time steps (stream, NSBC, collide; eqs. lbe_0, nes_0..nes_4,
- * lbe_1).  Asynchronous; the context's time advances by n. */
+ * lbe_1).  Asynchronous; the context's time advances by n.  The call is a
+ * roctx range named "lbm_step" (as are the other stepping and tuning calls,
+ * each under its own name), visible to rocprofv3 --marker-trace. */
 int lbm_step(lbm_ctx* ctx, int32_t n);
 
 /* Moments of every node at the current time (eqs. cf_0, cf_1): writes

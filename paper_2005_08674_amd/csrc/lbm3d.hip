@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "lbm.h"
+#include "lbm_trace.h"
 #include "lbm3d.h"
 #include "lbm_device.h"
 #include "lbm_host.h"
@@ -1052,6 +1053,7 @@ int lbm3d_set_farfield(lbm3d_ctx* c, double beta, double rho, double ux, double 
 }
 
 int lbm3d_step(lbm3d_ctx* c, int32_t n) {
+  const lbm::TraceRange trace_range("lbm3d_step");
   if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
   if (n < 0) return fail(LBM_ERR_ARG, "n = %d < 0", n);
   for (int32_t s = 0; s < n; ++s) {
@@ -1129,6 +1131,7 @@ int lbm3d_set_shape(lbm3d_ctx* c, int32_t id) {
 }
 
 int lbm3d_autotune(lbm3d_ctx* c, int32_t reps, int32_t* best, float* times_ms) {
+  const lbm::TraceRange trace_range("lbm3d_autotune");
   if (!c || !best) return fail(LBM_ERR_ARG, "NULL argument");
   if (reps < 1 || reps > 1000) return fail(LBM_ERR_ARG, "reps = %d outside [1, 1000]", reps);
   std::vector<hipEvent_t> ev(2 * reps);

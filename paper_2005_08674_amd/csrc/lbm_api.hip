@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "lbm.h"
+#include "lbm_trace.h"
 #include "lbm_closure.h"
 #include "lbm_device.h"
 #include "lbm_host.h"
@@ -638,6 +639,7 @@ int lbm_set_velocity_edge(lbm_ctx* c, double ux, double uy) {
 }
 
 int lbm_step(lbm_ctx* c, int32_t n) {
+  const lbm::TraceRange trace_range("lbm_step");
   if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
   if (n < 0) return fail(LBM_ERR_ARG, "n = %d < 0", n);
   if (n == 0) return LBM_OK;
@@ -843,6 +845,7 @@ struct StateSnapshot {
 }  // namespace
 
 int lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* best, float* times_ms) {
+  const lbm::TraceRange trace_range("lbm_autotune");
   if (!c || !best) return fail(LBM_ERR_ARG, "NULL argument");
   if (reps < 1 || reps > 1000) return fail(LBM_ERR_ARG, "reps = %d outside [1, 1000]", reps);
   // The launches timed are those of an lbm_step: the fused step (edge
@@ -947,6 +950,7 @@ int lbm_get_two_step(const lbm_ctx* c, int32_t* id) {
 }
 
 int lbm_autotune_two_step(lbm_ctx* c, int32_t reps, int32_t* best, float* times_ms) {
+  const lbm::TraceRange trace_range("lbm_autotune_two_step");
   if (!c || !best) return fail(LBM_ERR_ARG, "NULL argument");
   if (reps < 1 || reps > 1000) return fail(LBM_ERR_ARG, "reps = %d outside [1, 1000]", reps);
   if (!lbm::two_step_supported(c->L))

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "lbm.h"
+#include "lbm_trace.h"
 #include "lbm_closure.h"
 #include "lbm_ensemble.h"
 #include "lbm_device.h"
@@ -576,6 +577,7 @@ int lbm_ens_set_velocity_edge(lbm_ens* e, int32_t member, double ux, double uy) 
 }
 
 int lbm_ens_step(lbm_ens* e, int32_t n) {
+  const lbm::TraceRange trace_range("lbm_ens_step");
   if (!e) return fail(LBM_ERR_ARG, "ensemble is NULL");
   if (n < 0) return fail(LBM_ERR_ARG, "n = %d < 0", n);
   const int k = use_two(e) ? ens_multi_steps(e->two) : 1;
@@ -611,6 +613,7 @@ int lbm_ens_log_bytes(const lbm_ens* e, int32_t n, int32_t log_every, size_t* by
 }
 
 int lbm_ens_step_graph(lbm_ens* e, int32_t n, void* log_buf, size_t log_bytes, int32_t log_every) {
+  const lbm::TraceRange trace_range("lbm_ens_step_graph");
   if (!e) return fail(LBM_ERR_ARG, "ensemble is NULL");
   if (n < 1 || n > 100000) return fail(LBM_ERR_ARG, "n = %d outside [1, 100000]", n);
   const bool logging = log_buf != nullptr;
@@ -807,6 +810,7 @@ int lbm_ens_set_shape(lbm_ens* e, int32_t id) {
 }
 
 int lbm_ens_autotune(lbm_ens* e, int32_t reps, int32_t* best, float* times_ms) {
+  const lbm::TraceRange trace_range("lbm_ens_autotune");
   if (!e || !best) return fail(LBM_ERR_ARG, "NULL argument");
   if (reps < 1 || reps > 1000) return fail(LBM_ERR_ARG, "reps = %d outside [1, 1000]", reps);
   std::vector<hipEvent_t> ev(2 * reps);
@@ -874,6 +878,7 @@ int lbm_ens_get_two_step(const lbm_ens* e, int32_t* id) {
 }
 
 int lbm_ens_autotune_two_step(lbm_ens* e, int32_t reps, int32_t* best, float* times_ms) {
+  const lbm::TraceRange trace_range("lbm_ens_autotune_two_step");
   if (!e || !best) return fail(LBM_ERR_ARG, "NULL argument");
   if (reps < 1 || reps > 1000) return fail(LBM_ERR_ARG, "reps = %d outside [1, 1000]", reps);
   if (!two_supported(e)) return fail(LBM_ERR_UNSUPPORTED, "the multi-step sweeps need NSBC on all four edges of every member");
