@@ -313,7 +313,9 @@ __device__ inline void collide(const LatDesc& L, R g[9], R rho0, const Base<R>& 
 // from s by weight class, and with g^eq_i = w_i X_i (eq. feq_1) the update
 // g_i <- g_i + omega (g^eq_i - g_i) becomes s_i <- s_i + omega (2^k X_i - s_i):
 // the weights cancel, so no population is scaled on the way in or out.  For
-// u_b = 0 it is written per pair of opposite directions as in bgk.
+// u_b = 0 it is written per pair of opposite directions as in bgk, with
+// omega 2^k taken into the pair's terms once per node (one factor for all
+// nine directions): s_i <- (1 - omega) s_i + (q_E + q_45 a^2 +- q_3 a).
 template <class R>
 __device__ inline void bgk_stored(R s[9], R rho0, const Base<R>& b, R omega, R d0, R d1, R d5, R sc) {
   const R drho = fma(d0, s[0], fma(d1, (s[1] + s[2]) + (s[3] + s[4]), d5 * ((s[5] + s[6]) + (s[7] + s[8]))));
@@ -324,13 +326,13 @@ __device__ inline void bgk_stored(R s[9], R rho0, const Base<R>& b, R omega, R d
   if (b.zero) {
     const R dux = jx * ir, duy = jy * ir;
     const R e = fma(-rho, R(1.5) * fma(dux, dux, duy * duy), drho);
-    const R r45 = R(4.5) * rho, r3 = R(3) * rho;
     const R om1 = R(1) - omega, osc = omega * sc;
-    s[0] = fma(osc, e, om1 * s[0]);
+    const R qe = osc * e, q45 = (R(4.5) * osc) * rho, q3 = (R(3) * osc) * rho;
+    s[0] = fma(om1, s[0], qe);
     auto pair = [&](int i, int j, R a) {
-      const R even = fma(r45 * a, a, e), odd = r3 * a;
-      s[i] = fma(osc, even + odd, om1 * s[i]);
-      s[j] = fma(osc, even - odd, om1 * s[j]);
+      const R even = fma(q45 * a, a, qe), odd = q3 * a;
+      s[i] = fma(om1, s[i], even + odd);
+      s[j] = fma(om1, s[j], even - odd);
     };
     pair(1, 2, dux);
     pair(3, 4, duy);
