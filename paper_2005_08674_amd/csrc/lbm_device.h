@@ -340,15 +340,28 @@ __device__ inline void bgk_stored(R s[9], R rho0, const Base<R>& b, R omega, R d
     pair(7, 8, duy - dux);
     return;
   }
+  // u_b != 0, per pair (i, j) of opposite directions, where a = c_i.du and
+  // b = c_i.u_b both change sign: with P_i(u_b) = pe + 3 b,
+  //   X_i = drho (pe +- 3 b) + rho (9/2 a (a + 2 b) +- 3 a - q),
+  // so the pair shares the even part; omega 2^k is taken into drho and rho
+  // once per node
   const R dux = (jx - drho * b.ubx) * ir, duy = (jy - drho * b.uby) * ir;
   const R q = R(1.5) * (dux * (dux + R(2) * b.ubx) + duy * (duy + R(2) * b.uby));
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    const R a = R(kCx[i]) * dux + R(kCy[i]) * duy;
-    const R bi2 = R(2) * (R(kCx[i]) * b.ubx + R(kCy[i]) * b.uby);
-    const R x = fma(drho, b.pb[i], rho * fma(a, fma(R(4.5), a + bi2, R(3)), -q));
-    s[i] = fma(omega, fma(sc, x, -s[i]), s[i]);
-  }
+  const R om1 = R(1) - omega, osc = omega * sc;
+  const R dro = osc * drho, rro = osc * rho, dro3 = R(3) * dro, rro3 = R(3) * rro;
+  s[0] = fma(om1, s[0], fma(dro, b.pb[0], -(rro * q)));
+  auto pair = [&](int i, int j, R a) {
+    const R bi = R(kCx[i]) * b.ubx + R(kCy[i]) * b.uby;
+    const R pe = R(0.5) * (b.pb[i] + b.pb[j]);
+    const R even = fma(dro, pe, rro * fma(a, R(4.5) * (a + R(2) * bi), -q));
+    const R odd = fma(rro3, a, dro3 * bi);
+    s[i] = fma(om1, s[i], even + odd);
+    s[j] = fma(om1, s[j], even - odd);
+  };
+  pair(1, 2, dux);
+  pair(3, 4, duy);
+  pair(5, 6, dux + duy);
+  pair(7, 8, duy - dux);
 }
 
 // Collision of an interior node on its values as stored (Codec::raw, back

@@ -92,6 +92,17 @@ def test_vortex512x256_fp32_1000_steps():
               ubase=(0.1, 0.0))
 
 
+@pytest.mark.parametrize("store,tol", [("f16", 2e-3), ("bf16", 2e-2)])
+def test_vortex_sixteen_bit_with_base_flow(store, tol):
+    """256x128 vortex on an inflow of 0.1 stored about the inflow equilibrium in FP16 and BF16:
+    interior nodes take the stored-form collision's u_b != 0 branch.  Within the storage formats'
+    rounding of the oracle (FP64) at every checkpoint to t = 300."""
+    w = W.vortex_512x256(nx=256, ny=128)
+    worst = _run_pair(256, 128, w.tau, w.fields, [1, 10, 100, 300], store, tol, w.u_ref, m0=w.m0,
+                      ubase=(0.1, 0.0))
+    print(f"  worst {store}: e_rho={worst[0]:.3e} e_u={worst[1]:.3e}", flush=True)
+
+
 def test_vortex512x256_fp32_rest_base_error_report():
     """Same run with deviations about the rest state (f_i - w_i rho0): the mean flow then sits in
     the stored values and fp32 rounding of it drifts coherently; reported, with a sanity bound."""
