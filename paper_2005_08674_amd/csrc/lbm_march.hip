@@ -11,22 +11,23 @@ namespace lbm {
 
 // March shape `id` (among the march shapes) in format S.
 template <int S>
-static hipError_t launch_march_s(const LatDesc& L, int parity, int id, hipStream_t s, bool ring) {
+static hipError_t launch_march_s(const LatDesc& L, int parity, int id, hipStream_t s, bool ring, int part) {
   int k = 0;
-#define X(a, m, b, h, p, n)                                               \
-  if (id == k) return launch_march_t<S, a, m, b, n, p>(L, parity, s, h, ring); \
+#define X(a, m, b, h, p, n)                                                     \
+  if (id == k) return launch_march_t<S, a, m, b, n, p>(L, parity, s, h, ring, part); \
   ++k;
   LBM_THREE_MARCH(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_three_march(const LatDesc& L, int parity, int id, hipStream_t s, bool ring) {
+hipError_t launch_three_march(const LatDesc& L, int parity, int id, hipStream_t s, bool ring, int part) {
+  if (part < 0 || part > 2) return hipErrorInvalidValue;
   switch (L.store) {
-    case ST_F64: return launch_march_s<ST_F64>(L, parity, id, s, ring);
-    case ST_F32: return launch_march_s<ST_F32>(L, parity, id, s, ring);
-    case ST_F16: return launch_march_s<ST_F16>(L, parity, id, s, ring);
-    case ST_BF16: return launch_march_s<ST_BF16>(L, parity, id, s, ring);
+    case ST_F64: return launch_march_s<ST_F64>(L, parity, id, s, ring, part);
+    case ST_F32: return launch_march_s<ST_F32>(L, parity, id, s, ring, part);
+    case ST_F16: return launch_march_s<ST_F16>(L, parity, id, s, ring, part);
+    case ST_BF16: return launch_march_s<ST_BF16>(L, parity, id, s, ring, part);
   }
   return hipErrorInvalidValue;
 }

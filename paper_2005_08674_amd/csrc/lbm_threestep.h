@@ -194,6 +194,43 @@ __host__ __device__ inline void march_chunks(int rows, int h, int& chunks, int& 
   height = chunks > 0 ? (rows + chunks - 1) / chunks : 0;
 }
 
+// The march items of a launch part (strip sx of ix, chunk c of chunks):
+// part 0 all of them, part 1 those whose neighbours are all march items
+// (1 <= sx <= ix - 2 and 1 <= c <= chunks - 2: a level-t read or a write of
+// theirs stays 3 nodes or more from every edge tile), part 2 the others (the
+// border of the rectangle).  Part 1 is chunk-major; part 2 is row c = 0, then
+// the two ends of each middle row, then row chunks - 1.  Block m takes item
+// (m mod 8) * per + m / 8 of its part, so each XCD works through a
+// contiguous stretch; false past the part's last item.
+__host__ __device__ inline int march_part_items(int ix, int chunks, int part) {
+  const int inner = ix > 2 && chunks > 2 ? (ix - 2) * (chunks - 2) : 0;
+  return part == 0 ? ix * chunks : (part == 1 ? inner : ix * chunks - inner);
+}
+__host__ __device__ inline bool march_item(int m, int ix, int chunks, int part, int& c, int& sx) {
+  const int items = march_part_items(ix, chunks, part), per = (items + 7) >> 3;
+  const int item = (m & 7) * per + (m >> 3);
+  if (item >= items) return false;
+  const int fx = ix - 2, fc = chunks - 2;
+  if (part == 1) {
+    c = 1 + item / fx;
+    sx = 1 + item % fx;
+  } else if (part == 0 || fx <= 0 || fc <= 0) {  // part 2 without inner items is every item
+    c = item / ix;
+    sx = item - c * ix;
+  } else if (item < ix) {
+    c = 0;
+    sx = item;
+  } else if (item < ix + 2 * fc) {
+    const int k = item - ix;
+    c = 1 + (k >> 1);
+    sx = (k & 1) ? ix - 1 : 0;
+  } else {
+    c = chunks - 1;
+    sx = item - ix - 2 * fc;
+  }
+  return true;
+}
+
 // Column march (TY: the level arrays' tile rows): the block owns the 64
 // columns xs .. xs + 63 of output rows ya .. yb - 1, all inside the inner
 // tiles' rectangle (no clamp, no NSBC), and walks down them in rounds of MR
@@ -361,7 +398,7 @@ __device__ inline void three_step_march(const LatDesc& Ld, int parity, int xs, i
 template <int S, int TY, int MR, int NT, bool NTS, int CM, int PF>
 __global__ __launch_bounds__(NT, two_step_waves<S>()) void k_three_march(LatDesc L, int parity, int tiles_x,
                                                                        int tiles_y, int ring8, int height,
-                                                                       int chunks) {
+                                                                       int chunks, int part) {
   const int ix = inner_cols(L.nx), iy = inner_rows(L.ny, TY);
   const int b = blockIdx.x;
   if (b < ring8) {
@@ -371,19 +408,17 @@ __global__ __launch_bounds__(NT, two_step_waves<S>()) void k_three_march(LatDesc
     return;
   }
   // (ring8 is a multiple of 8, so m and b run on the same XCD)
-  const int m = b - ring8, items = ix * chunks, per = (items + 7) >> 3;
-  const int item = (m & 7) * per + (m >> 3);
-  if (item >= items) return;
-  const int c = item / ix, sx = item - c * ix;
+  int c, sx;
+  if (!march_item(b - ring8, ix, chunks, part, c, sx)) return;
   const int ya = TY + c * height, yb = min(ya + height, TY * (iy + 1));
   three_step_march<S, TY, MR, NT, NTS, CM, PF>(L, parity, TL_TX * (1 + sx), ya, yb);
 }
 
 // One launch: the edge tiles (unless !ring: a closure lattice's run in the
-// closure kernel) and the march over the inner rectangle in chunks of about
-// h rows.
+// closure kernel) and part `part` of the march over the inner rectangle in
+// chunks of about h rows (march_item).
 template <int S, int TY, int MR, int NT, bool NTS, int PF>
-inline hipError_t launch_march_t(const LatDesc& L, int parity, hipStream_t s, int h, bool ring) {
+inline hipError_t launch_march_t(const LatDesc& L, int parity, hipStream_t s, int h, bool ring, int part) {
   if constexpr (!three_step_fits<S, TY>()) {
     return hipErrorInvalidValue;
   } else {
@@ -392,21 +427,22 @@ inline hipError_t launch_march_t(const LatDesc& L, int parity, hipStream_t s, in
     const int ring8 = ring ? (tiles_x * tiles_y - ix * iy + 7) / 8 * 8 : 0;
     int chunks, height;
     march_chunks(ix > 0 ? TY * iy : 0, h, chunks, height);
-    if (ring8 + ix * chunks == 0) return hipSuccess;
-    const dim3 grid(ring8 + (ix * chunks + 7) / 8 * 8);
+    const int items = march_part_items(ix, chunks, part);
+    if (ring8 + items == 0) return hipSuccess;
+    const dim3 grid(ring8 + (items + 7) / 8 * 8);
     if (L.coll == COLL_MRT)
       k_three_march<S, TY, MR, NT, NTS, COLL_MRT, PF>
-          <<<grid, dim3(NT), 0, s>>>(L, parity, tiles_x, tiles_y, ring8, height, chunks);
+          <<<grid, dim3(NT), 0, s>>>(L, parity, tiles_x, tiles_y, ring8, height, chunks, part);
     else
       k_three_march<S, TY, MR, NT, NTS, COLL_BGK, PF>
-          <<<grid, dim3(NT), 0, s>>>(L, parity, tiles_x, tiles_y, ring8, height, chunks);
+          <<<grid, dim3(NT), 0, s>>>(L, parity, tiles_x, tiles_y, ring8, height, chunks, part);
     return hipGetLastError();
   }
 }
 
 // march shape `id` (among the march shapes) on one lattice, with its edge
-// tiles when `ring` (lbm_march.hip)
-hipError_t launch_three_march(const LatDesc& L, int parity, int id, hipStream_t s, bool ring);
+// tiles when `ring`, over part `part` of the march items (lbm_march.hip)
+hipError_t launch_three_march(const LatDesc& L, int parity, int id, hipStream_t s, bool ring, int part = 0);
 
 // ------------------------------------------------------------------ two-step column march
 // Candidate shapes of the marched two-step sweep (t -> t + 2), one launch of
