@@ -102,7 +102,46 @@ __host__ __device__ inline bool ring_tile(int b, int tiles_x, int tiles_y, int i
 __host__ __device__ inline int inner_cols(int nx) { return nx >= 67 ? (nx - 67) / TL_TX : 0; }
 __host__ __device__ inline int inner_rows(int ny, int ty) { return ny >= ty + 3 ? (ny - ty - 3) / ty : 0; }
 
-// `part` as three_step_tile.  The closure kernel (CL) runs one block per
+// The march items of a launch part (strip sx of ix, chunk c of chunks):
+// part 0 all of them, part 1 those whose neighbours are all march items
+// (1 <= sx <= ix - 2 and 1 <= c <= chunks - 2: a level-t read or a write of
+// theirs stays 3 nodes or more from every edge tile), part 2 the others (the
+// border of the rectangle).  Part 1 is chunk-major; part 2 is row c = 0, then
+// the two ends of each middle row, then row chunks - 1.  Block m takes item
+// (m mod 8) * per + m / 8 of its part, so each XCD works through a
+// contiguous stretch; false past the part's last item.
+__host__ __device__ inline int march_part_items(int ix, int chunks, int part) {
+  const int inner = ix > 2 && chunks > 2 ? (ix - 2) * (chunks - 2) : 0;
+  return part == 0 ? ix * chunks : (part == 1 ? inner : ix * chunks - inner);
+}
+__host__ __device__ inline bool march_item(int m, int ix, int chunks, int part, int& c, int& sx) {
+  const int items = march_part_items(ix, chunks, part), per = (items + 7) >> 3;
+  const int item = (m & 7) * per + (m >> 3);
+  if (item >= items) return false;
+  const int fx = ix - 2, fc = chunks - 2;
+  if (part == 1) {
+    c = 1 + item / fx;
+    sx = 1 + item % fx;
+  } else if (part == 0 || fx <= 0 || fc <= 0) {  // part 2 without inner items is every item
+    c = item / ix;
+    sx = item - c * ix;
+  } else if (item < ix) {
+    c = 0;
+    sx = item;
+  } else if (item < ix + 2 * fc) {
+    const int k = item - ix;
+    c = 1 + (k >> 1);
+    sx = (k & 1) ? ix - 1 : 0;
+  } else {
+    c = chunks - 1;
+    sx = item - ix - 2 * fc;
+  }
+  return true;
+}
+
+// `part` as three_step_tile, or 3 and 4: the inner tiles away from the edge
+// tiles and the others (a closure lattice's two launches of its inner tiles).
+// The closure kernel (CL) runs one block per
 // edge tile (the ring); the others one block per tile in XCD bands.
 template <int S, int TY, int NT, bool NTS, int CM, bool CL>
 __global__ __launch_bounds__(NT, (three_step_waves<S, CL>())) void k_three_step(LatDesc L, int parity, int tiles_x,
@@ -110,6 +149,13 @@ __global__ __launch_bounds__(NT, (three_step_waves<S, CL>())) void k_three_step(
   int txi, tyi;
   if (CL) {
     if (!ring_tile(blockIdx.x, tiles_x, tiles_y, inner_cols(L.nx), inner_rows(L.ny, TY), txi, tyi)) return;
+  } else if (part >= 3) {
+    // part 3: the inner tiles whose neighbours are all inner tiles, part 4
+    // the other inner tiles (march_item over the inner rectangle)
+    int c, sx;
+    if (!march_item(blockIdx.x, inner_cols(L.nx), inner_rows(L.ny, TY), part - 2, c, sx)) return;
+    tyi = 1 + c;
+    txi = 1 + sx;
   } else {
     const int b = blockIdx.x, ntiles = tiles_x * tiles_y;
     const int per = (ntiles + 7) >> 3;
@@ -118,7 +164,7 @@ __global__ __launch_bounds__(NT, (three_step_waves<S, CL>())) void k_three_step(
     tyi = tile / tiles_x;
     txi = tile - tyi * tiles_x;
   }
-  three_step_tile<S, TY, NT, NTS, CM, CL>(L, parity, txi, tyi, CL ? 2 : part);
+  three_step_tile<S, TY, NT, NTS, CM, CL>(L, parity, txi, tyi, CL ? 2 : (part >= 3 ? 1 : part));
 }
 
 template <int S, int TY, int NT, bool NTS, bool CL>
@@ -128,8 +174,11 @@ inline hipError_t launch_three_t(const LatDesc& L, int parity, hipStream_t s, in
     return hipErrorInvalidValue;
   } else {
     const int tiles_x = (L.nx + TL_TX - 1) / TL_TX, tiles_y = (L.ny + TY - 1) / TY;
-    const dim3 grid(CL ? tiles_x * tiles_y - inner_cols(L.nx) * inner_rows(L.ny, TY)
-                       : ((tiles_x * tiles_y + 7) >> 3) * 8);
+    const int n = CL ? tiles_x * tiles_y - inner_cols(L.nx) * inner_rows(L.ny, TY)
+                     : (part >= 3 ? (march_part_items(inner_cols(L.nx), inner_rows(L.ny, TY), part - 2) + 7) >> 3 << 3
+                                  : ((tiles_x * tiles_y + 7) >> 3) * 8);
+    if (n == 0) return hipSuccess;
+    const dim3 grid(n);
     if (L.coll == COLL_MRT)
       k_three_step<S, TY, NT, NTS, COLL_MRT, CL><<<grid, dim3(NT), 0, s>>>(L, parity, tiles_x, tiles_y, part);
     else
@@ -192,43 +241,6 @@ inline bool three_step_fits_store(int store, int id, bool closure) {
 __host__ __device__ inline void march_chunks(int rows, int h, int& chunks, int& height) {
   chunks = rows > 0 ? (rows + h - 1) / h : 0;
   height = chunks > 0 ? (rows + chunks - 1) / chunks : 0;
-}
-
-// The march items of a launch part (strip sx of ix, chunk c of chunks):
-// part 0 all of them, part 1 those whose neighbours are all march items
-// (1 <= sx <= ix - 2 and 1 <= c <= chunks - 2: a level-t read or a write of
-// theirs stays 3 nodes or more from every edge tile), part 2 the others (the
-// border of the rectangle).  Part 1 is chunk-major; part 2 is row c = 0, then
-// the two ends of each middle row, then row chunks - 1.  Block m takes item
-// (m mod 8) * per + m / 8 of its part, so each XCD works through a
-// contiguous stretch; false past the part's last item.
-__host__ __device__ inline int march_part_items(int ix, int chunks, int part) {
-  const int inner = ix > 2 && chunks > 2 ? (ix - 2) * (chunks - 2) : 0;
-  return part == 0 ? ix * chunks : (part == 1 ? inner : ix * chunks - inner);
-}
-__host__ __device__ inline bool march_item(int m, int ix, int chunks, int part, int& c, int& sx) {
-  const int items = march_part_items(ix, chunks, part), per = (items + 7) >> 3;
-  const int item = (m & 7) * per + (m >> 3);
-  if (item >= items) return false;
-  const int fx = ix - 2, fc = chunks - 2;
-  if (part == 1) {
-    c = 1 + item / fx;
-    sx = 1 + item % fx;
-  } else if (part == 0 || fx <= 0 || fc <= 0) {  // part 2 without inner items is every item
-    c = item / ix;
-    sx = item - c * ix;
-  } else if (item < ix) {
-    c = 0;
-    sx = item;
-  } else if (item < ix + 2 * fc) {
-    const int k = item - ix;
-    c = 1 + (k >> 1);
-    sx = (k & 1) ? ix - 1 : 0;
-  } else {
-    c = chunks - 1;
-    sx = item - ix - 2 * fc;
-  }
-  return true;
 }
 
 // Column march (TY: the level arrays' tile rows): the block owns the 64

@@ -217,8 +217,9 @@ static int closure_tile_of(int id) {
 // way); with kJoinDefer on every launch but the last and kJoinPrev on every
 // launch but the first, those are the only waits, so the edge-tile kernels,
 // the longer of the two, follow one another on `side` without a round trip
-// through s.  A march's inner part splits further: its items away from the
-// edge tiles depend on neither edge-tile kernel and run before the wait.
+// through s.  The inner part splits further: its march items or inner tiles
+// away from the edge tiles depend on neither edge-tile kernel and run before
+// the wait.
 hipError_t launch_three_step(const LatDesc& L, int parity, int id, hipStream_t s, hipStream_t side, hipEvent_t fork,
                              hipEvent_t join, int flags) {
   if (!three_step_supported(L, id)) return hipErrorInvalidValue;
@@ -235,15 +236,24 @@ hipError_t launch_three_step(const LatDesc& L, int parity, int id, hipStream_t s
     }
     const int cid = march ? closure_tile_of(id) : id;
     if (e == hipSuccess) e = cid >= 0 ? launch_three_step_closure(L, parity, cid, forked ? side : s) : hipErrorInvalidValue;
-    // the march items whose reads and writes stay 3 nodes or more from every
-    // edge tile touch nothing an edge-tile kernel reads or writes: they go
-    // before the wait for the previous launch's edge-tile kernel
+    // the march items (inner tiles) whose reads and writes stay 3 nodes or
+    // more from every edge tile touch nothing an edge-tile kernel reads or
+    // writes: they go before the wait for the previous launch's edge-tile
+    // kernel
     if (forked && march && e == hipSuccess) e = launch_three_march(L, parity, mid, s, false, 1);
+    if (forked && !march && e == hipSuccess) {
+      switch (L.store) {
+        case ST_F64: e = launch_three_s<ST_F64, false>(L, parity, id, s, 3); break;
+        case ST_F32: e = launch_three_s<ST_F32, false>(L, parity, id, s, 3); break;
+        case ST_F16: e = launch_three_s<ST_F16, false>(L, parity, id, s, 3); break;
+        case ST_BF16: e = launch_three_s<ST_BF16, false>(L, parity, id, s, 3); break;
+      }
+    }
     // s waits for the previous launch's edge-tile kernel before join is recorded anew
     if (forked && (flags & kJoinPrev) && e == hipSuccess) e = hipStreamWaitEvent(s, join, 0);
     if (forked && e == hipSuccess) e = hipEventRecord(join, side);
     if (e != hipSuccess) return e;
-    part = 1;
+    part = forked ? 4 : 1;
   }
   const bool wait_end = forked && !(flags & kJoinDefer);
   hipError_t e = hipErrorInvalidValue;
